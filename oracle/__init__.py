@@ -1,0 +1,21 @@
+"""Plain FP64 CPU oracle for the ensemble gravitational-wave search hot path.
+
+THIS PACKAGE IS TEST INFRASTRUCTURE. Only the test suite, the smoke check and
+the CPU-baseline leg of the benchmark may import or call it. The product path
+(the HIP library and its Python binding) never imports it and shares no code
+with it: every function here is written from the paper and from the plain
+mathematical definition of each step, in float64 NumPy, with no blocking,
+fusion or reordering beyond what the definition states.
+
+Paper: "Inference-optimized AI and high performance computing for
+gravitational wave detection at scale" (arXiv 2201.11133).
+
+Modules
+  arch      architecture descriptors, parameter counts, receptive field,
+            canonical flat weight-blob layout
+  forward   per-window forward pass, per-layer forward, streaming forward
+  stream    sliding windows over a stream, owner-window stitching, ensemble
+  triggers  threshold + non-maximum-suppression trigger rule (+ brute force)
+  train     per-timestep BCE loss, manual reverse-mode gradient, Adam
+  quant     bfloat16 and FP8-E4M3 quantisers written from the formats
+"""

@@ -1,0 +1,139 @@
+"""Architecture descriptors and the canonical flat weight-blob layout (FP64 oracle).
+
+Test infrastructure only (see the package docstring).
+
+The paper describes its classifier as a modified WaveNet that reads the two
+detector strains sampled at 4096 Hz and emits a classification probability per
+time step (Materials and Methods, "AI architecture"; Fig. 1). It gives no
+widths, depths or kernel sizes, so this build fixes two concrete members:
+
+kind 0, "plain stack": four causal convolutions, kernel 2, dilations 1, 2, 4, 8,
+    16 channels, ReLU after each, then a 1x1 convolution to one channel; the
+    per-timestep probability is the sigmoid of that logit.
+kind 1, "gated residual WaveNet": a 1x1 input projection 2 -> C, then
+    n_stacks x layers_per_stack gated residual layers (kernel 2, dilation
+    2**(l mod layers_per_stack)), each with a tanh*sigmoid gate and residual
+    and skip 1x1 convolutions; the skip sum goes through ReLU, a 1x1 to H
+    channels, an optional ReLU, a 1x1 to one channel, then the sigmoid.
+
+Readings where the paper is silent (all listed in the design notes):
+  * the input layer is a 1x1 convolution with bias (input_kernel=1), so the
+    receptive field is 1 + (kernel-1) * sum of dilations;
+  * the last gated layer has no residual 1x1 (its output would be unused);
+  * kernel taps: W[..., 0] multiplies x[t - d], W[..., 1] multiplies x[t];
+  * gate split: channels [0, C) feed tanh, [C, 2C) feed the sigmoid;
+  * head_mid_relu=0: no nonlinearity between the two head 1x1s (the literal
+    configuration); 1 inserts a ReLU there (the usual WaveNet head).
+
+Blob layout (per member, float, in this order):
+  kind 0: for i = 1..4: conv_i.W[16][Cin][2], conv_i.b[16]  (Cin = 2, then 16)
+          out.W[1][16], out.b[1]
+  kind 1: in.W[C][2] (or [C][2][2] when input_kernel=2), in.b[C]
+          for l = 0..L-1: dil.W[2C][C][2], dil.b[2C],
+                          res.W[C][C], res.b[C]      (absent for l = L-1)
+                          skip.W[S][C], skip.b[S]
+          h1.W[H][S], h1.b[H], h2.W[1][H], h2.b[1]
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import Dict, List, Tuple
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class Arch:
+    kind: int = 1                 # 0 plain ReLU stack, 1 gated residual WaveNet
+    in_channels: int = 2          # Hanford, Livingston
+    channels: int = 128           # residual channels (kind 1) / conv channels (kind 0)
+    skip_channels: int = 128
+    head_channels: int = 128
+    n_stacks: int = 3
+    layers_per_stack: int = 10
+    kernel_size: int = 2
+    input_kernel: int = 1
+    head_mid_relu: int = 0
+
+    @property
+    def n_layers(self) -> int:
+        return self.n_stacks * self.layers_per_stack
+
+    def dilation(self, l: int) -> int:
+        return 2 ** (l % self.layers_per_stack)
+
+
+# The two members used throughout: the small parity model and the full-size member.
+TINY = Arch(kind=0, in_channels=2, channels=16, skip_channels=0, head_channels=0,
+            n_stacks=1, layers_per_stack=4, kernel_size=2, input_kernel=1, head_mid_relu=0)
+FULL = Arch()
+
+
+def layout(a: Arch) -> List[Tuple[str, Tuple[int, ...], int]]:
+    """Ordered list of (name, shape, fan_in) for every tensor of the blob.
+
+    fan_in is the He-normal fan-in (C_in * kernel) for weights and 0 for biases.
+    """
+    out: List[Tuple[str, Tuple[int, ...], int]] = []
+    k = a.kernel_size
+    if a.kind == 0:
+        cin = a.in_channels
+        for i in range(a.n_layers):
+            out.append((f"conv{i}.W", (a.channels, cin, k), cin * k))
+            out.append((f"conv{i}.b", (a.channels,), 0))
+            cin = a.channels
+        out.append(("out.W", (1, a.channels), a.channels))
+        out.append(("out.b", (1,), 0))
+        return out
+    C, S, H = a.channels, a.skip_channels, a.head_channels
+    if a.input_kernel == 1:
+        out.append(("in.W", (C, a.in_channels), a.in_channels))
+    else:
+        out.append(("in.W", (C, a.in_channels, a.input_kernel), a.in_channels * a.input_kernel))
+    out.append(("in.b", (C,), 0))
+    for l in range(a.n_layers):
+        out.append((f"dil{l}.W", (2 * C, C, k), C * k))
+        out.append((f"dil{l}.b", (2 * C,), 0))
+        if l < a.n_layers - 1:
+            out.append((f"res{l}.W", (C, C), C))
+            out.append((f"res{l}.b", (C,), 0))
+        out.append((f"skip{l}.W", (S, C), C))
+        out.append((f"skip{l}.b", (S,), 0))
+    out.append(("h1.W", (H, S), S))
+    out.append(("h1.b", (H,), 0))
+    out.append(("h2.W", (1, H), H))
+    out.append(("h2.b", (1,), 0))
+    return out
+
+
+def num_params(a: Arch) -> int:
+    return int(sum(int(np.prod(s)) for _, s, _ in layout(a)))
+
+
+def receptive_field(a: Arch) -> int:
+    """Number of input samples that influence one output sample (causal)."""
+    rf = 1 + (a.kernel_size - 1) * sum(a.dilation(l) for l in range(a.n_layers))
+    if a.kind == 1:
+        rf += a.input_kernel - 1
+    return rf
+
+
+def unpack(a: Arch, blob: np.ndarray) -> Dict[str, np.ndarray]:
+    """Split one member's flat blob into named float64 arrays (copies)."""
+    blob = np.asarray(blob, dtype=np.float64).reshape(-1)
+    n = num_params(a)
+    if blob.size != n:
+        raise ValueError(f"blob has {blob.size} values, architecture needs {n}")
+    p: Dict[str, np.ndarray] = {}
+    off = 0
+    for name, shape, _ in layout(a):
+        cnt = int(np.prod(shape))
+        p[name] = blob[off:off + cnt].reshape(shape).copy()
+        off += cnt
+    return p
+
+
+def pack(a: Arch, params: Dict[str, np.ndarray]) -> np.ndarray:
+    """Inverse of unpack: named arrays -> flat float64 blob in canonical order."""
+    return np.concatenate([np.asarray(params[name], dtype=np.float64).reshape(-1)
+                           for name, _, _ in layout(a)])
