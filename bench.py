@@ -1,0 +1,209 @@
+"""Benchmark of the ensemble gravitational-wave search hot path on one MI355X.
+
+One step = one pass of the whole path over one batch of synthetic two-detector strain:
+window gather + input projection, 30 gated dilated-conv layers, head, owner-window stitch,
+ensemble minimum over the members, threshold + clustering into triggers.
+
+Default workload: an ensemble of 4 members (3 stacks x 10 gated layers, 128 residual/skip
+channels, independent He-normal weights), BF16 operands with fp32 accumulation, over a
+21,600 s slice of a 86,400 s two-channel white-noise stream at 4096 Hz carrying leading-order
+chirps (200 per day, network SNR 8-20), window 4096, stride 256. Inputs are generated on the
+device before timing (HBM-resident when the timed region starts).
+
+Prints one JSON line. Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FS = 4096
+W, S = 4096, 256
+FLOP_PER_STEP_T = 5899008                 # flop per window time step per member
+FLOP_PER_LAYER_T = 196608                 # flop per time step of one gated layer (conv + res/skip)
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
+
+
+def make_stream_gpu(seconds: float, seed: int, chirps_per_day: float = 200.0):
+    """Device stream [L, 2]: N(0,1) noise from a seeded torch generator plus seeded chirps."""
+    import torch
+    from paper_2201_11133_amd import synth
+    L = int(round(seconds * FS))
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    x = torch.randn((L, 2), dtype=torch.float32, device="cuda", generator=gen)
+    rng = np.random.default_rng(seed)
+    n = int(round(chirps_per_day * seconds / 86400.0))
+    injs = [synth.draw_injection(rng, tc) for tc in synth.place_times(rng, n, seconds, 4.0, 10.0)]
+    for inj in injs:
+        lo = max(0, int(math.floor((inj.tc - inj.tau20 - 0.02) * FS)))
+        hi = min(L, int(math.ceil((inj.tc + 0.02) * FS)) + 1)
+        sig = synth.injection_signal(inj, lo / FS, hi - lo).astype(np.float32)
+        x[lo:hi] += torch.from_numpy(sig).cuda()
+    torch.cuda.synchronize()
+    return x, injs
+
+
+def n_windows(L: int) -> int:
+    return 1 if L <= W else -(-(L - W) // S) + 1
+
+
+def time_steps(fn, steps: int, warmup: int):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(steps):
+        fn()
+    ev1.record()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / steps, (time.perf_counter() - t0) * 1e3 / steps
+
+
+def layer_kernel_timing(model, prec: str, nb: int, reps: int = 10):
+    """Average duration of the dominant kernel (a middle gated layer) in the forward's launch
+    configuration (nb windows of 4096 steps per launch), timed with HIP events on its stream."""
+    import torch
+    C = 128
+    x = torch.randn((nb, W, C), dtype=torch.float32, device="cuda") * 3
+    xo = torch.empty_like(x)
+    sk = torch.randn((nb, W, C), dtype=torch.float32, device="cuda")
+    st = torch.cuda.current_stream()
+    for _ in range(2):
+        model.debug_layer(0, 15, x, nb, W, None, xo, sk, stream=st)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(st)
+    for _ in range(reps):
+        model.debug_layer(0, 15, x, nb, W, None, xo, sk, stream=st)
+    ev1.record(st)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    flop = nb * W * FLOP_PER_LAYER_T
+    achieved = flop / (ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[prec]
+    del x, xo, sk
+    return {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": None, "kernel": f"gated layer ({prec})",
+            "ms_per_launch": round(ms, 4), "flop_per_launch": flop}
+
+
+def cpu_baseline(n_members: int, n_windows_sample: int = 3):
+    """The FP64 oracle, windowed (the same algorithm and work as the GPU path), on a bounded sample:
+    n_windows_sample consecutive windows for every member; the strain they add is S samples each."""
+    import torch  # noqa: F401  (thread count report only)
+    from oracle.arch import FULL, unpack
+    from oracle.forward import forward_window
+    from oracle.stream import gather_windows
+    from paper_2201_11133_amd import synth
+    x, _ = synth.make_stream(102, (W + (n_windows_sample - 1) * S) / FS, 0)
+    win = gather_windows(x.astype(np.float64), W, S)[:n_windows_sample]
+    ps = [unpack(FULL, synth.full_weights(11 + i).astype(np.float64)) for i in range(n_members)]
+    t0 = time.perf_counter()
+    for p in ps:
+        forward_window(FULL, p, win)
+    dt = time.perf_counter() - t0
+    strain_s = n_windows_sample * S / FS
+    cores = os.cpu_count()
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        cores = max((i.get("num_threads", 0) for i in info), default=cores) or cores
+    except Exception:
+        pass
+    return {"value": round(strain_s / dt, 6), "unit": "strain-s/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{n_windows_sample} windows x {n_members} members, windowed FP64 NumPy ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp8"])
+    ap.add_argument("--seconds", type=float, default=21600.0)
+    ap.add_argument("--members", type=int, default=4)
+    ap.add_argument("--no-extra", action="store_true", help="skip the FP32/FP8 comparison lines")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(windows shard by time with no exchange; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2201_11133_amd import gwd, synth
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    x, injs = make_stream_gpu(args.seconds, 102)
+    L = x.shape[0]
+    blobs = np.stack([synth.full_weights(11 + i) for i in range(args.members)])
+    out = torch.empty(L, dtype=torch.float32, device="cuda")
+    result = {}
+
+    def run(prec, seconds=None):
+        xs = x if seconds is None else x[: int(round(seconds * FS))]
+        m = gwd.Model(gwd.full_arch(), blobs, prec)
+        n_trig = [0]
+
+        def step():
+            m.forward([xs], W, S, out_mode=0, out=out)
+            n_trig[0] = len(gwd.triggers(out[: xs.shape[0]], [0, xs.shape[0]], 0.9, 4096))
+
+        ms_ev, ms_wall = time_steps(step, args.steps, args.warmup)
+        secs = xs.shape[0] / FS
+        return m, {"strain_s_per_s": secs / (ms_wall / 1e3), "ms_per_step": ms_wall, "ms_events": ms_ev,
+                   "stream_s": secs, "triggers": n_trig[0],
+                   "tflops": args.members * n_windows(xs.shape[0]) * W * FLOP_PER_STEP_T / (ms_wall * 1e-3) / 1e12}
+
+    model, main_r = run(args.precision)
+    roof = layer_kernel_timing(model, args.precision, model_batch_windows(model))
+    model.close()
+    extra = {}
+    if not args.no_extra:
+        for prec, secs in (("fp8", None), ("fp32", min(args.seconds, 1024.0))):
+            if prec == args.precision:
+                continue
+            m2, r2 = run(prec, secs)
+            m2.close()
+            extra[prec] = {k: round(v, 3) if isinstance(v, float) else v for k, v in r2.items()}
+        extra[args.precision] = {k: round(v, 3) if isinstance(v, float) else v for k, v in main_r.items()}
+    cpu = None if args.no_cpu else cpu_baseline(args.members)
+    value = main_r["strain_s_per_s"]
+    line = {
+        "metric": "2-detector strain-sec/s per GPU, 4-model ensemble, FP32 vs BF16/FP8; train win/s",
+        "value": round(value, 3), "unit": "strain-s/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(main_r["ms_per_step"], 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.precision, "data": "synthetic",
+        "config": {"workload": (f"ensemble of {args.members} gated dilated-conv members (3x10 layers, 128 "
+                                f"channels), {args.precision} operands / fp32 accumulation, "
+                                f"{args.seconds:.0f} s two-channel 4096 Hz stream slice (white noise + "
+                                f"chirps), window 4096 stride 256, ensemble min + triggers (p>=0.9, +/-4096)"),
+                   "members": args.members, "stream_seconds": args.seconds, "window": W, "stride": S,
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "detail": {"triggers": main_r["triggers"], "tflops_step": round(main_r["tflops"], 2),
+                   "ms_events": round(main_r["ms_events"], 3), "precisions": extra},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def model_batch_windows(model) -> int:
+    return 512
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,246 @@
+/*
+ * gwd.h — C ABI of libgwd, the MI355X (gfx950) hot path of an ensemble
+ * gravitational-wave search over two-detector strain.
+ *
+ * Paper: "Inference-optimized AI and high performance computing for
+ * gravitational wave detection at scale" (arXiv 2201.11133).
+ *
+ * What the library computes (each entry point below names its passage):
+ *   - an ensemble of dilated causal 1-D convolutional classifiers (a modified
+ *     WaveNet, Materials and Methods "AI architecture", Fig. 1) applied to
+ *     sliding windows of two-channel (Hanford, Livingston) strain sampled at
+ *     4096 Hz, one logit per time step and window ("Optimization with
+ *     TensorRT": the engine maps (batch, 4096, 2) windows to (batch, 4096, 1));
+ *   - the per-sample ensemble score (minimum over members: a sample passes
+ *     the threshold only if every member passes it, Results "Event Detection");
+ *   - threshold + clustering of that score into a trigger list;
+ *   - a hand-written backward pass and Adam step for training one member
+ *     ("AI ensemble construction": per-timestep labels, random initialisation).
+ *
+ * Conventions
+ *   - Every function returns gwd_status (0 = OK, negative = error) unless its
+ *     return type says otherwise; gwd_last_error() gives a thread-local text.
+ *   - No C++ exception and no abort crosses this ABI.
+ *   - All argument checks run on the host before any HIP call, so invalid
+ *     arguments are reported even on a machine without a GPU.
+ *   - Device pointers are owned by the caller (for example torch CUDA/ROCm
+ *     tensors) and must stay valid until the enqueued work completes.
+ *   - The library owns only the opaque model handle: packed weights, scales,
+ *     workspace and launch plans. A model lives on the device that was current
+ *     when gwd_load_weights was called; call it with that device current.
+ *   - Every enqueueing call takes `hip_stream` (a hipStream_t; NULL = the
+ *     default stream) and is asynchronous with respect to the host, except
+ *     where stated (gwd_load_weights, gwd_triggers).
+ *   - Calls that share one model handle must not overlap in time (they share
+ *     its workspace); use one handle per host thread for concurrency.
+ */
+#ifndef GWD_H
+#define GWD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gwd_model gwd_model; /* opaque, library-owned */
+
+typedef enum {
+    GWD_FP32 = 0,     /* fp32 operands, fp32 MFMA, fp32 accumulation            */
+    GWD_BF16 = 1,     /* bf16 operands (RNE), fp32 accumulation, fp32 residual  */
+    GWD_FP8_E4M3 = 2  /* OCP E4M3FN operands, per-output-channel weight scales  */
+} gwd_precision;
+
+typedef enum {
+    GWD_OK = 0,
+    GWD_ERR_ARG = -1,         /* null/misaligned pointer, value out of range      */
+    GWD_ERR_SHAPE = -2,       /* window shorter than the receptive field, ...     */
+    GWD_ERR_CAPACITY = -3,    /* caller buffer too small (true size is reported)  */
+    GWD_ERR_HIP = -4,         /* a HIP runtime call failed                         */
+    GWD_ERR_UNSUPPORTED = -5, /* valid but not implemented combination            */
+    GWD_ERR_NONFINITE = -6,   /* NaN/Inf in a score stream                          */
+    GWD_ERR_NO_DEVICE = -7    /* no HIP device visible                              */
+} gwd_status;
+
+/* Architecture of one ensemble member (all members of a model share it).
+ * kind 0: plain stack — n_stacks*layers_per_stack causal convolutions of
+ *         `channels` channels, kernel `kernel_size`, dilation
+ *         2^(l mod layers_per_stack), ReLU after each, then a 1x1 to one logit.
+ * kind 1: gated residual WaveNet — 1x1 input projection in_channels ->
+ *         channels, then n_stacks*layers_per_stack layers
+ *           a = dilated causal conv (kernel 2) of x, 2*channels outputs
+ *           g = tanh(a[0:C]) * sigmoid(a[C:2C])
+ *           skip += W_s g + b_s ;  x += W_r g + b_r  (no residual in the last layer)
+ *         then logit = w_h2 . act(W_h1 ReLU(skip) + b_h1) + b_h2 with
+ *         act = identity (head_mid_relu = 0) or ReLU (head_mid_relu = 1).
+ * The paper (Fig. 1) does not give widths or depths; these are the build's
+ * members. Supported by the GPU path: kind 0 with channels 16, in_channels 2,
+ * kernel 2; kind 1 with channels = skip_channels = head_channels = 128,
+ * in_channels 2, kernel 2, input_kernel 1. */
+typedef struct {
+    int32_t kind;
+    int32_t in_channels;
+    int32_t channels;
+    int32_t skip_channels;
+    int32_t head_channels;
+    int32_t n_stacks;
+    int32_t layers_per_stack;
+    int32_t kernel_size;
+    int32_t input_kernel;
+    int32_t head_mid_relu;
+} gwd_arch;
+
+/* One two-channel strain stream in device memory: sample t of channel c is
+ * ch[c][t * elem_stride], t in [0, length). Planar (elem_stride 1, two
+ * pointers) and interleaved (elem_stride 2, ch[1] = ch[0] + 1) both work
+ * without a copy. */
+typedef struct {
+    const float* ch[2];
+    int64_t elem_stride;
+    int64_t length;
+} gwd_stream;
+
+/* One trigger: stream index, sample index within that stream, ensemble logit
+ * and its sigmoid. */
+typedef struct {
+    int32_t stream;
+    int32_t _pad;
+    int64_t sample;
+    float logit;
+    float prob;
+} gwd_trigger;
+
+/* Number of float parameters of one member in the canonical flat blob
+ * (kind 0 with 16 channels: 1,681; kind 1 with 128 channels, 3x10 layers:
+ * 2,964,993), or -1 for an invalid descriptor.
+ * Blob order (float32):
+ *   kind 0: for each layer i: W[channels][c_in][kernel], b[channels]
+ *           (c_in = in_channels for i = 0, else channels); out.W[1][channels], out.b[1]
+ *   kind 1: in.W[C][in_channels], in.b[C];
+ *           for layer l: dil.W[2C][C][2], dil.b[2C],
+ *                        res.W[C][C], res.b[C]   (absent in the last layer),
+ *                        skip.W[S][C], skip.b[S];
+ *           h1.W[H][S], h1.b[H], h2.W[1][H], h2.b[1]
+ *   Kernel tap 0 multiplies x[t - d], tap 1 multiplies x[t]. */
+int64_t gwd_num_params(const gwd_arch* arch);
+
+/* Input samples that influence one output sample: 1 + (kernel-1) * sum of
+ * dilations (16 and 3070 for the two members above), or -1 if invalid. */
+int32_t gwd_receptive_field(const gwd_arch* arch);
+
+/* Copy, pack and (for BF16 / FP8) quantise the weights of n_members members
+ * onto the current device. host_blob holds n_members consecutive blobs of
+ * n_params floats each (host memory, read during the call only). BF16 rounds
+ * to nearest even; FP8 E4M3 uses one scale per output channel of every
+ * weight matrix (max |w| over the channel / 448) and saturates at +/-448.
+ * Synchronous. On success *out owns device memory until gwd_free. */
+gwd_status gwd_load_weights(const gwd_arch* arch, int32_t n_members, const float* host_blob,
+                            int64_t n_params, gwd_precision precision, gwd_model** out);
+
+/* Release a model (waits for the device; NULL is ignored). */
+void gwd_free(gwd_model* model);
+
+/* Forward pass of every member over every window of every stream
+ * (windows: "Data preparation" — 1 s at 4096 Hz; the engine batch —
+ * "Optimization with TensorRT").
+ *
+ * Window k of a stream covers samples [k*stride, k*stride + window); samples
+ * at or past the stream length read as 0; each window starts from zero
+ * context. A stream of length L has n_win = 1 if L <= window, else
+ * ceil((L - window) / stride) + 1 windows. Each sample a is scored by its
+ * owner window: window 0 for a < window - stride, else
+ * k = floor((a - window + stride) / stride) at position a - k*stride.
+ * Ensemble score e[a] = minimum over members of the owner-window logits.
+ *
+ * out_mode and the layout of `out` (device, float32):
+ *   0: e for every stream, streams back to back:          [sum L]
+ *   1: as 0, followed by each member's stitched logits:   [sum L] + [M][sum L]
+ *   2: every member's full per-window logits:             [M][sum n_win][window]
+ * out_capacity_floats must be >= gwd_forward_out_floats(...).
+ * Requirements: 1 <= n_streams <= 65536, window a multiple of 64 and
+ * >= receptive field (else GWD_ERR_SHAPE), 0 < stride <= window,
+ * window - stride >= receptive field - 1 (so owner positions never see the
+ * zero left context of a later window, else GWD_ERR_SHAPE), stream pointers
+ * 4-byte aligned. Streams with length 0 are allowed and produce nothing.
+ * Asynchronous on hip_stream. */
+gwd_status gwd_forward(gwd_model* model, const gwd_stream* streams, int32_t n_streams,
+                       int32_t window, int32_t stride, int32_t out_mode,
+                       float* out, int64_t out_capacity_floats, void* hip_stream);
+
+/* Number of floats gwd_forward writes for these arguments (or -1 if invalid). */
+int64_t gwd_forward_out_floats(const gwd_model* model, const gwd_stream* streams, int32_t n_streams,
+                               int32_t window, int32_t stride, int32_t out_mode);
+
+/* Threshold + clustering of ensemble scores into triggers (the paper's
+ * post-processing keeps a candidate only if all members flag it, Results
+ * "Event Detection", and locates each merger with a peak search, "AI ensemble
+ * construction"). Rule, per stream (samples never interact across streams):
+ *   sample a triggers iff  e[a] >= ln(p / (1 - p))   (p = threshold_prob), and
+ *   e[a] >  e[b] for all b in [a - cluster_window, a), and
+ *   e[a] >= e[b] for all b in (a, a + cluster_window]
+ * i.e. non-maximum suppression over +/-cluster_window, ties to the earliest.
+ * The comparison with the threshold is done in double precision.
+ * ens_logit: device [stream_offsets[n_streams]] floats; stream s is
+ * ens_logit[stream_offsets[s] .. stream_offsets[s+1]) (host offsets,
+ * non-decreasing, starting at 0). Records are written to host memory `out`
+ * sorted by (stream, sample); *n_found receives the true count. If it
+ * exceeds `capacity`, the first `capacity` records are written and
+ * GWD_ERR_CAPACITY is returned. Any NaN or Inf in the scanned scores gives
+ * GWD_ERR_NONFINITE (and no records). 0 < threshold_prob < 1,
+ * 1 <= cluster_window <= 65536. Synchronises hip_stream before returning. */
+gwd_status gwd_triggers(const float* ens_logit, const int64_t* stream_offsets, int32_t n_streams,
+                        float threshold_prob, int32_t cluster_window, gwd_trigger* out,
+                        int64_t capacity, int64_t* n_found, void* hip_stream);
+
+/* ---- training (one member; "AI ensemble construction") ---------------------
+ * windows: device [B][W][2] float32 (interleaved channels), logits: device
+ * [B][W]. gwd_forward_train runs member `member` forward, writes the logits
+ * and keeps what the backward pass needs in `saved` (device, caller-owned,
+ * gwd_saved_bytes(model, B, W) bytes: the input of each stack of
+ * layers_per_stack layers plus the final skip sum; everything else is
+ * recomputed per stack). gwd_backward takes dL/dlogit [B][W] and writes
+ * dL/dparams (device float32 [n_params], overwritten, canonical blob order)
+ * and, if grad_input is not NULL, dL/dwindows [B][W][2].
+ * The arithmetic follows the model's precision (fp32 master weights are
+ * used for FP32; BF16 models run bf16 operands with fp32 accumulation);
+ * FP8 is not supported for training (GWD_ERR_UNSUPPORTED). */
+int64_t gwd_saved_bytes(const gwd_model* model, int32_t B, int32_t W);
+gwd_status gwd_forward_train(gwd_model* model, int32_t member, const float* windows, int32_t B, int32_t W,
+                             float* logits, void* saved, void* hip_stream);
+gwd_status gwd_backward(gwd_model* model, int32_t member, const float* windows, int32_t B, int32_t W,
+                        const void* saved, const float* grad_logit, float* grad_params,
+                        float* grad_input, void* hip_stream);
+
+/* Adam (Kingma & Ba) with bias correction on float32 master weights
+ * (device [n_params]), gradient, first and second moments (updated in
+ * place); step is 1-based. Also writes the global gradient 2-norm,
+ * accumulated in double, to *grad_norm_out (device, may be NULL), and
+ * refreshes member `member`'s packed working weights from the new master
+ * weights. No weight decay, no clipping. */
+gwd_status gwd_adam_step(gwd_model* model, int32_t member, float* master, const float* grad, float* m, float* v,
+                         int64_t step, float lr, float beta1, float beta2, float eps,
+                         double* grad_norm_out, void* hip_stream);
+
+/* Last error message of the calling thread ("" if none). */
+const char* gwd_last_error(void);
+
+/* ---- test support ------------------------------------------------------------
+ * gwd_debug_layer runs gated layer `layer` of member `member` (kind 1) with
+ * the same kernel the forward pass uses, on M = n_windows * window rows of
+ * device input x_in [n_windows][window][C] (each window zero-context), and
+ * writes the pre-activation a [M][2C] (may be NULL), x_out [M][C] (ignored in
+ * the last layer) and updates skip [M][S] in place (skip_inout; it is
+ * overwritten rather than accumulated when `layer` is 0).
+ * gwd_debug_export_weights copies the operands exactly as the kernels see
+ * them, unpacked to row-major float32: for every weight matrix of member
+ * `member` in blob order, the de-quantised values (bf16 / e4m3 value times
+ * scale), into host `out` of n_params floats (biases copied as stored). */
+gwd_status gwd_debug_layer(gwd_model* model, int32_t member, int32_t layer, const float* x_in,
+                           int32_t n_windows, int32_t window, float* pre_out, float* x_out,
+                           float* skip_inout, void* hip_stream);
+gwd_status gwd_debug_export_weights(const gwd_model* model, int32_t member, float* out, int64_t n_params);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GWD_H */

@@ -49,7 +49,8 @@ def causal_conv(x: np.ndarray, W: np.ndarray, b: np.ndarray, d: int) -> np.ndarr
     k = W.shape[2]
     y = np.broadcast_to(b, x.shape[:-1] + (W.shape[0],)).astype(np.float64).copy()
     for j in range(k):
-        y += shift_right(x, (k - 1 - j) * d) @ W[:, :, j].T
+        # contiguous copy of the tap so the product goes through BLAS (a strided view would not)
+        y += shift_right(x, (k - 1 - j) * d) @ np.ascontiguousarray(W[:, :, j]).T
     return y
 
 

@@ -55,6 +55,16 @@ def e4m3_channel_scales(W: np.ndarray) -> np.ndarray:
     return np.where(amax > 0, amax / E4M3_MAX, 1.0)
 
 
+def quantise_weight_e4m3_f32(W: np.ndarray):
+    """Same quantiser with the scale and the division taken in float32 (as a float32 kernel does):
+    s = float32(max |w|) / 448, code = e4m3(float32(w) / s). Returns (codes, scales as float32)."""
+    W32 = np.asarray(W, dtype=np.float32)
+    amax = np.max(np.abs(W32.reshape(W32.shape[0], -1)), axis=1)
+    s = np.where(amax > 0, amax / np.float32(E4M3_MAX), np.float32(1.0)).astype(np.float32)
+    shape = (W32.shape[0],) + (1,) * (W32.ndim - 1)
+    return to_e4m3((W32 / s.reshape(shape)).astype(np.float32).astype(np.float64)), s
+
+
 def quantise_weight_e4m3(W: np.ndarray):
     """(codes as float64 values, scales): W ~= codes * scale[:, None, ...]."""
     W = np.asarray(W, dtype=np.float64)

@@ -55,7 +55,7 @@ def _conv_backward(x: np.ndarray, W: np.ndarray, dy: np.ndarray, d: int):
         dyl = np.zeros_like(dy)
         if s < T:
             dyl[..., :T - s, :] = dy[..., s:, :]
-        dx += dyl @ W[:, :, j]
+        dx += dyl @ np.ascontiguousarray(W[:, :, j])
     db = flat_dy.sum(axis=0)
     return dx, dW, db
 

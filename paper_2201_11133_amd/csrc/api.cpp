@@ -1,0 +1,334 @@
+// C ABI of libgwd: argument validation, model lifetime, workspace and launch sequencing.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <math.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "gwd_internal.h"
+
+namespace gwd {
+
+static thread_local std::string g_err;
+
+void set_error(const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+}
+
+gwd_status hip_fail(hipError_t e, const char* what) {
+    set_error("%s failed: %s", what, hipGetErrorString(e));
+    return GWD_ERR_HIP;
+}
+
+static bool arch_valid(const gwd_arch* a) {
+    if (!a) return false;
+    if (a->kind != 0 && a->kind != 1) return false;
+    if (a->in_channels < 1 || a->channels < 1 || a->n_stacks < 1 || a->layers_per_stack < 1) return false;
+    if (a->layers_per_stack > 24 || a->n_stacks * a->layers_per_stack > 256) return false;
+    if (a->kernel_size < 1 || a->kernel_size > 8) return false;
+    if (a->kind == 1) {
+        if (a->skip_channels < 1 || a->head_channels < 1) return false;
+        if (a->kernel_size != 2) return false;
+        if (a->input_kernel < 1 || a->input_kernel > 2) return false;
+        if (a->head_mid_relu != 0 && a->head_mid_relu != 1) return false;
+    }
+    return true;
+}
+
+// The shapes the GPU kernels are specialised for.
+static bool arch_supported(const gwd_arch* a) {
+    if (a->kind == 0)
+        return a->in_channels == 2 && a->channels == 16 && a->n_stacks * a->layers_per_stack == 4 &&
+               a->layers_per_stack >= 4 && a->kernel_size == 2;
+    return a->in_channels == 2 && a->channels == kC && a->skip_channels == kC && a->head_channels == kC &&
+           a->kernel_size == 2 && a->input_kernel == 1;
+}
+
+static int64_t rf_of(const gwd_arch* a) {
+    int64_t s = 0;
+    for (int l = 0; l < a->n_stacks * a->layers_per_stack; ++l) s += (int64_t)1 << (l % a->layers_per_stack);
+    int64_t rf = 1 + (int64_t)(a->kernel_size - 1) * s;
+    if (a->kind == 1) rf += a->input_kernel - 1;
+    return rf;
+}
+
+static int64_t nwin_of(int64_t L, int W, int S) {
+    if (L <= 0) return 0;
+    if (L <= W) return 1;
+    return (L - W + S - 1) / S + 1;
+}
+
+}  // namespace gwd
+
+using namespace gwd;
+
+extern "C" {
+
+const char* gwd_last_error(void) { return g_err.c_str(); }
+
+int64_t gwd_num_params(const gwd_arch* a) {
+    if (!arch_valid(a)) return -1;
+    const int64_t C = a->channels, K = a->kernel_size;
+    const int L = a->n_stacks * a->layers_per_stack;
+    if (a->kind == 0) {
+        int64_t n = 0, cin = a->in_channels;
+        for (int l = 0; l < L; ++l) {
+            n += C * cin * K + C;
+            cin = C;
+        }
+        return n + C + 1;
+    }
+    const int64_t S = a->skip_channels, H = a->head_channels;
+    int64_t n = C * a->in_channels * a->input_kernel + C;
+    for (int l = 0; l < L; ++l) {
+        n += 2 * C * C * 2 + 2 * C;
+        if (l < L - 1) n += C * C + C;
+        n += S * C + S;
+    }
+    return n + H * S + H + H + 1;
+}
+
+int32_t gwd_receptive_field(const gwd_arch* a) {
+    if (!arch_valid(a)) return -1;
+    return (int32_t)rf_of(a);
+}
+
+gwd_status gwd_load_weights(const gwd_arch* arch, int32_t n_members, const float* host_blob, int64_t n_params,
+                            gwd_precision precision, gwd_model** out) {
+    if (!out) { set_error("gwd_load_weights: out is NULL"); return GWD_ERR_ARG; }
+    *out = nullptr;
+    if (!arch_valid(arch)) { set_error("gwd_load_weights: invalid architecture"); return GWD_ERR_ARG; }
+    if (n_members < 1 || n_members > 64) { set_error("gwd_load_weights: n_members %d not in [1, 64]", n_members); return GWD_ERR_ARG; }
+    if (!host_blob) { set_error("gwd_load_weights: host_blob is NULL"); return GWD_ERR_ARG; }
+    const int64_t np = gwd_num_params(arch);
+    if (n_params != np) { set_error("gwd_load_weights: n_params %lld, architecture needs %lld", (long long)n_params, (long long)np); return GWD_ERR_ARG; }
+    if (precision != GWD_FP32 && precision != GWD_BF16 && precision != GWD_FP8_E4M3) { set_error("gwd_load_weights: unknown precision %d", (int)precision); return GWD_ERR_ARG; }
+    if (!arch_supported(arch)) { set_error("gwd_load_weights: architecture not supported by the GPU kernels"); return GWD_ERR_UNSUPPORTED; }
+    if (arch->kind == 0 && precision != GWD_FP32) { set_error("gwd_load_weights: the plain member runs in FP32 only"); return GWD_ERR_UNSUPPORTED; }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) { set_error("gwd_load_weights: no HIP device"); return GWD_ERR_NO_DEVICE; }
+    gwd_model* m = new (std::nothrow) gwd_model();
+    if (!m) { set_error("gwd_load_weights: out of host memory"); return GWD_ERR_ARG; }
+    m->arch = *arch;
+    m->prec = precision;
+    m->n_members = n_members;
+    m->n_params = np;
+    m->batch_windows = 512;
+    hipError_t e = hipGetDevice(&m->device);
+    if (e != hipSuccess) { delete m; return hip_fail(e, "hipGetDevice"); }
+    m->host_blob.assign(host_blob, host_blob + (size_t)np * n_members);
+    m->members.resize(n_members);
+    for (int i = 0; i < n_members; ++i) {
+        gwd_status s = pack_member(m, i, host_blob + (size_t)np * i);
+        if (s != GWD_OK) { gwd_free(m); return s; }
+    }
+    *out = m;
+    return GWD_OK;
+}
+
+void gwd_free(gwd_model* m) {
+    if (!m) return;
+    (void)hipDeviceSynchronize();
+    for (auto& mw : m->members)
+        if (mw.base) (void)hipFree(mw.base);
+    if (m->ws.base) (void)hipFree(m->ws.base);
+    delete m;
+}
+
+// Shared validation of the forward arguments. Fills per-stream window counts and totals.
+static gwd_status check_forward(const gwd_model* m, const gwd_stream* streams, int32_t n_streams, int32_t window,
+                                int32_t stride, int32_t out_mode, std::vector<int64_t>& nwin, int64_t& sum_L,
+                                int64_t& total_win, int64_t& out_floats) {
+    if (!m) { set_error("gwd_forward: model is NULL"); return GWD_ERR_ARG; }
+    if (!streams) { set_error("gwd_forward: streams is NULL"); return GWD_ERR_ARG; }
+    if (n_streams < 1 || n_streams > 65536) { set_error("gwd_forward: n_streams %d not in [1, 65536]", n_streams); return GWD_ERR_ARG; }
+    if (out_mode < 0 || out_mode > 2) { set_error("gwd_forward: out_mode %d not in {0,1,2}", out_mode); return GWD_ERR_ARG; }
+    if (stride <= 0 || stride > window) { set_error("gwd_forward: stride %d not in (0, window]", stride); return GWD_ERR_ARG; }
+    const int64_t rf = rf_of(&m->arch);
+    const int tile = m->arch.kind == 0 ? 256 : kBM;
+    if (window <= 0 || window % tile != 0) { set_error("gwd_forward: window %d must be a positive multiple of %d", window, tile); return GWD_ERR_SHAPE; }
+    if (window < rf) { set_error("gwd_forward: window %d shorter than the receptive field %lld", window, (long long)rf); return GWD_ERR_SHAPE; }
+    if ((int64_t)(window - stride) < rf - 1) { set_error("gwd_forward: window - stride = %d < receptive field - 1 = %lld", window - stride, (long long)(rf - 1)); return GWD_ERR_SHAPE; }
+    nwin.assign(n_streams, 0);
+    sum_L = 0;
+    total_win = 0;
+    for (int s = 0; s < n_streams; ++s) {
+        const gwd_stream& st = streams[s];
+        if (st.length < 0) { set_error("gwd_forward: stream %d has negative length", s); return GWD_ERR_ARG; }
+        if (st.length > 0) {
+            if (!st.ch[0] || !st.ch[1]) { set_error("gwd_forward: stream %d has a NULL channel pointer", s); return GWD_ERR_ARG; }
+            if (((uintptr_t)st.ch[0] & 3) || ((uintptr_t)st.ch[1] & 3)) { set_error("gwd_forward: stream %d pointer not 4-byte aligned", s); return GWD_ERR_ARG; }
+            if (st.elem_stride < 1) { set_error("gwd_forward: stream %d elem_stride %lld < 1", s, (long long)st.elem_stride); return GWD_ERR_ARG; }
+        }
+        nwin[s] = nwin_of(st.length, window, stride);
+        sum_L += st.length;
+        total_win += nwin[s];
+    }
+    const int64_t M = m->n_members;
+    out_floats = out_mode == 0 ? sum_L : out_mode == 1 ? sum_L * (1 + M) : M * total_win * (int64_t)window;
+    return GWD_OK;
+}
+
+int64_t gwd_forward_out_floats(const gwd_model* m, const gwd_stream* streams, int32_t n_streams, int32_t window,
+                               int32_t stride, int32_t out_mode) {
+    std::vector<int64_t> nwin;
+    int64_t sum_L, total_win, out_floats;
+    if (check_forward(m, streams, n_streams, window, stride, out_mode, nwin, sum_L, total_win, out_floats) != GWD_OK)
+        return -1;
+    return out_floats;
+}
+
+static gwd_status ensure_workspace(gwd_model* m, int64_t bytes, hipStream_t st) {
+    if (m->ws.bytes >= bytes) return GWD_OK;
+    hipError_t e;
+    if (m->ws.base) {
+        e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+        (void)hipFree(m->ws.base);
+        m->ws.base = nullptr;
+        m->ws.bytes = 0;
+    }
+    e = hipMalloc(&m->ws.base, bytes);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(workspace)");
+    m->ws.bytes = bytes;
+    return GWD_OK;
+}
+
+gwd_status gwd_forward(gwd_model* m, const gwd_stream* streams, int32_t n_streams, int32_t window, int32_t stride,
+                       int32_t out_mode, float* out, int64_t out_capacity_floats, void* hip_stream) {
+    std::vector<int64_t> nwin;
+    int64_t sum_L, total_win, out_floats;
+    gwd_status s = check_forward(m, streams, n_streams, window, stride, out_mode, nwin, sum_L, total_win, out_floats);
+    if (s != GWD_OK) return s;
+    if (out_floats > 0 && !out) { set_error("gwd_forward: out is NULL"); return GWD_ERR_ARG; }
+    if (out_capacity_floats < out_floats) {
+        set_error("gwd_forward: out holds %lld floats, %lld needed", (long long)out_capacity_floats, (long long)out_floats);
+        return GWD_ERR_CAPACITY;
+    }
+    if (m->arch.kind == 1 && m->prec != GWD_FP32 && m->prec != GWD_BF16 && m->prec != GWD_FP8_E4M3) {
+        set_error("gwd_forward: precision not supported");
+        return GWD_ERR_UNSUPPORTED;
+    }
+    if (total_win == 0) return GWD_OK;
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipError_t e = hipSetDevice(m->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+
+    // stream table
+    std::vector<StreamDesc> tab(n_streams);
+    int64_t wb = 0, sb = 0;
+    for (int i = 0; i < n_streams; ++i) {
+        tab[i].ch0 = streams[i].ch[0];
+        tab[i].ch1 = streams[i].ch[1];
+        tab[i].stride = streams[i].elem_stride;
+        tab[i].length = streams[i].length;
+        tab[i].win_begin = wb;
+        tab[i].sample_begin = sb;
+        tab[i].n_win = nwin[i];
+        tab[i]._pad = 0;
+        wb += nwin[i];
+        sb += streams[i].length;
+    }
+    const int nb_max = (int)std::min<int64_t>(m->batch_windows, total_win);
+    const int64_t tab_bytes = ((int64_t)n_streams * (int64_t)sizeof(StreamDesc) + 255) & ~255LL;
+    const int64_t act = m->arch.kind == 1 ? (int64_t)nb_max * window * kC * 4 : 0;
+    s = ensure_workspace(m, tab_bytes + 3 * act, st);
+    if (s != GWD_OK) return s;
+    char* base = (char*)m->ws.base;
+    StreamDesc* d_tab = (StreamDesc*)base;
+    float* x_a = (float*)(base + tab_bytes);
+    float* x_b = (float*)(base + tab_bytes + act);
+    float* skip = (float*)(base + tab_bytes + 2 * act);
+    // pageable source: the copy is staged before the call returns, so tab may go out of scope
+    e = hipMemcpyAsync(d_tab, tab.data(), n_streams * sizeof(StreamDesc), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(stream table)");
+
+    FwdBatch fb;
+    fb.streams = d_tab;
+    fb.n_streams = n_streams;
+    fb.T = window;
+    fb.S = stride;
+    fb.out_mode = out_mode;
+    fb.n_members = m->n_members;
+    fb.out = out;
+    fb.sum_L = sum_L;
+    fb.total_win = total_win;
+    for (int64_t w0 = 0; w0 < total_win; w0 += nb_max) {
+        fb.win_base = w0;
+        fb.nb = (int)std::min<int64_t>(nb_max, total_win - w0);
+        for (int mem = 0; mem < m->n_members; ++mem) {
+            fb.member = mem;
+            e = m->arch.kind == 0 ? launch_tiny_forward(m, fb, st) : launch_wavenet_forward(m, fb, x_a, x_b, skip, st);
+            if (e != hipSuccess) return hip_fail(e, "forward kernel launch");
+        }
+    }
+    return GWD_OK;
+}
+
+gwd_status gwd_triggers(const float* ens_logit, const int64_t* offs, int32_t n_streams, float threshold_prob,
+                        int32_t cluster_window, gwd_trigger* out, int64_t capacity, int64_t* n_found,
+                        void* hip_stream) {
+    if (!n_found) { set_error("gwd_triggers: n_found is NULL"); return GWD_ERR_ARG; }
+    *n_found = 0;
+    if (!offs) { set_error("gwd_triggers: stream_offsets is NULL"); return GWD_ERR_ARG; }
+    if (n_streams < 1 || n_streams > 65536) { set_error("gwd_triggers: n_streams %d not in [1, 65536]", n_streams); return GWD_ERR_ARG; }
+    if (!(threshold_prob > 0.f && threshold_prob < 1.f)) { set_error("gwd_triggers: threshold_prob must be in (0, 1)"); return GWD_ERR_ARG; }
+    if (cluster_window < 1 || cluster_window > 65536) { set_error("gwd_triggers: cluster_window %d not in [1, 65536]", cluster_window); return GWD_ERR_ARG; }
+    if (capacity < 0) { set_error("gwd_triggers: negative capacity"); return GWD_ERR_ARG; }
+    if (capacity > 0 && !out) { set_error("gwd_triggers: out is NULL"); return GWD_ERR_ARG; }
+    if (offs[0] != 0) { set_error("gwd_triggers: stream_offsets[0] must be 0"); return GWD_ERR_ARG; }
+    for (int s = 0; s < n_streams; ++s)
+        if (offs[s + 1] < offs[s]) { set_error("gwd_triggers: stream_offsets decrease at %d", s); return GWD_ERR_ARG; }
+    if (offs[n_streams] > 0) {
+        if (!ens_logit) { set_error("gwd_triggers: ens_logit is NULL"); return GWD_ERR_ARG; }
+        if ((uintptr_t)ens_logit & 3) { set_error("gwd_triggers: ens_logit not 4-byte aligned"); return GWD_ERR_ARG; }
+    } else {
+        return GWD_OK;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) { set_error("gwd_triggers: no HIP device"); return GWD_ERR_NO_DEVICE; }
+    const double p = (double)threshold_prob;
+    const double thr = log(p / (1.0 - p));
+    return run_triggers(ens_logit, offs, n_streams, thr, cluster_window, out, capacity, n_found, (hipStream_t)hip_stream);
+}
+
+int64_t gwd_saved_bytes(const gwd_model* m, int32_t B, int32_t W) {
+    if (!m || B < 1 || W < 1) return -1;
+    if (m->arch.kind != 1) return (int64_t)B * W * 16 * 4 * 4;
+    return (int64_t)(m->arch.n_stacks + 1) * B * W * kC * 4;
+}
+
+gwd_status gwd_debug_layer(gwd_model* m, int32_t member, int32_t layer, const float* x_in, int32_t n_windows,
+                           int32_t window, float* pre_out, float* x_out, float* skip, void* hip_stream) {
+    if (!m) { set_error("gwd_debug_layer: model is NULL"); return GWD_ERR_ARG; }
+    if (m->arch.kind != 1) { set_error("gwd_debug_layer: needs the gated member"); return GWD_ERR_UNSUPPORTED; }
+    const int L = m->arch.n_stacks * m->arch.layers_per_stack;
+    if (member < 0 || member >= m->n_members) { set_error("gwd_debug_layer: member %d out of range", member); return GWD_ERR_ARG; }
+    if (layer < 0 || layer >= L) { set_error("gwd_debug_layer: layer %d out of range", layer); return GWD_ERR_ARG; }
+    if (n_windows < 1 || window < kBM || window % kBM) { set_error("gwd_debug_layer: bad shape"); return GWD_ERR_SHAPE; }
+    if (!x_in || !skip || (layer < L - 1 && !x_out)) { set_error("gwd_debug_layer: NULL buffer"); return GWD_ERR_ARG; }
+    hipError_t e = hipSetDevice(m->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    e = launch_layer_debug(m, member, layer, x_in, n_windows, window, pre_out, x_out, skip, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_fail(e, "layer kernel launch");
+    return GWD_OK;
+}
+
+gwd_status gwd_debug_export_weights(const gwd_model* m, int32_t member, float* out, int64_t n_params) {
+    if (!m || !out) { set_error("gwd_debug_export_weights: NULL argument"); return GWD_ERR_ARG; }
+    if (member < 0 || member >= m->n_members) { set_error("gwd_debug_export_weights: member out of range"); return GWD_ERR_ARG; }
+    if (n_params != m->n_params) { set_error("gwd_debug_export_weights: n_params mismatch"); return GWD_ERR_ARG; }
+    return export_member(m, member, out);
+}
+
+}  // extern "C"

@@ -1,0 +1,125 @@
+// Internal declarations shared by the libgwd translation units (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/gwd.h"
+
+namespace gwd {
+
+// Residual / skip / head width of the full-size member; the FP32/BF16/FP8 layer kernels are
+// specialised for it.
+constexpr int kC = 128;
+// Rows (time steps) of one layer-kernel tile.
+constexpr int kBM = 64;
+
+// One stream as the kernels see it; win_begin / sample_begin are prefix sums over streams.
+struct StreamDesc {
+    const float* ch0;
+    const float* ch1;
+    int64_t stride;
+    int64_t length;
+    int64_t win_begin;     // global index of this stream's first window
+    int64_t sample_begin;  // offset of this stream's first sample in the stitched output
+    int64_t n_win;
+    int64_t _pad;
+};
+
+// Device binary search: stream that owns global window gw (streams with no windows are skipped).
+__device__ inline int find_stream(const StreamDesc* s, int n, int64_t gw) {
+    int lo = 0, hi = n;  // first index with win_begin > gw
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (s[mid].win_begin <= gw) lo = mid + 1; else hi = mid;
+    }
+    return lo - 1;
+}
+
+// Blocks of a 1-D grid are dealt round-robin to the 8 XCDs of an MI355X. Renumber them so that
+// consecutive work items (tiles of one window, which share dilation halos) run on one XCD and
+// share its L2.
+__device__ inline int xcd_remap(int bid, int nblocks) {
+    const int nx = 8;
+    int per = nblocks / nx, rem = nblocks % nx;
+    int x = bid % nx, i = bid / nx;
+    // XCD x gets items [start(x), start(x) + per + (x < rem))
+    int start = x * per + (x < rem ? x : rem);
+    return start + i;
+}
+
+// Per-member packed weights (device), offsets in floats (or bytes for FP8) into one buffer.
+struct LayerOffsets {
+    int64_t wc, bc;    // conv weights (packed for the MFMA fragments), conv bias [2C]
+    int64_t wrs, brs;  // res|skip weights (packed), res|skip bias [2C] (skip only in the last layer: [C])
+    int64_t sc, srs;   // FP8 per-output-channel scales of conv [2C] and res|skip [2C] (floats)
+};
+
+struct MemberWeights {
+    void* base = nullptr;   // device buffer
+    int64_t bytes = 0;
+    std::vector<LayerOffsets> layers;
+    int64_t w_in = 0, b_in = 0, h1w = 0, h1b = 0, h2w = 0, h2b = 0;  // fp32 offsets (floats)
+    // kind 0 (tiny member): plain fp32 copy of the blob
+    int64_t blob = 0;
+};
+
+struct Workspace {
+    void* base = nullptr;
+    int64_t bytes = 0;
+};
+
+}  // namespace gwd
+
+struct gwd_model {
+    gwd_arch arch;
+    gwd_precision prec;
+    int32_t n_members;
+    int64_t n_params;
+    int device;
+    std::vector<float> host_blob;              // canonical fp32 weights (kept for export and repacking)
+    std::vector<gwd::MemberWeights> members;
+    gwd::Workspace ws;
+    int32_t batch_windows;                     // windows per layer-kernel batch
+};
+
+namespace gwd {
+
+void set_error(const char* fmt, ...);
+gwd_status hip_fail(hipError_t e, const char* what);
+
+// Packing (pack.cpp): build the device image of one member from its canonical blob.
+gwd_status pack_member(gwd_model* m, int member, const float* blob);
+gwd_status export_member(const gwd_model* m, int member, float* out);
+
+// Launchers (kernel translation units). All enqueue on `st`.
+struct FwdBatch {
+    const StreamDesc* streams;  // device
+    int n_streams;
+    int64_t win_base;   // global index of the batch's first window
+    int nb;             // windows in the batch
+    int T;              // window length
+    int S;              // stride
+    int out_mode;
+    int member;
+    int n_members;
+    float* out;
+    int64_t sum_L;      // total samples (stitched layout)
+    int64_t total_win;  // total windows (mode 2 layout)
+};
+
+hipError_t launch_tiny_forward(const gwd_model* m, const FwdBatch& fb, hipStream_t st);
+hipError_t launch_wavenet_forward(gwd_model* m, const FwdBatch& fb, float* x_a, float* x_b, float* skip,
+                                  hipStream_t st);
+hipError_t launch_layer_debug(gwd_model* m, int member, int layer, const float* x_in, int nb, int T,
+                              float* pre_out, float* x_out, float* skip, hipStream_t st);
+
+// Triggers (triggers.hip)
+struct TrigWork;
+gwd_status run_triggers(const float* e, const int64_t* offs, int n_streams, double thr, int wc,
+                        gwd_trigger* out, int64_t capacity, int64_t* n_found, hipStream_t st);
+
+}  // namespace gwd

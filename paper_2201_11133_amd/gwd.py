@@ -1,0 +1,210 @@
+"""Python binding of libgwd (ctypes): argument marshalling only.
+
+Every step of the hot path runs in the HIP kernels of libgwd.so; this module
+only converts torch tensors (device memory, streams) to the C ABI declared in
+include/gwd.h. There is no fallback: if the library is missing, importing the
+binding raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgwd.so")
+
+OK = 0
+ERR_ARG = -1
+ERR_SHAPE = -2
+ERR_CAPACITY = -3
+ERR_HIP = -4
+ERR_UNSUPPORTED = -5
+ERR_NONFINITE = -6
+ERR_NO_DEVICE = -7
+
+FP32, BF16, FP8_E4M3 = 0, 1, 2
+PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8_E4M3}
+
+
+class GwdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libgwd error {code}: {msg}")
+        self.code = code
+
+
+class Arch(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in
+                ("kind", "in_channels", "channels", "skip_channels", "head_channels",
+                 "n_stacks", "layers_per_stack", "kernel_size", "input_kernel", "head_mid_relu")]
+
+
+class Stream(ctypes.Structure):
+    _fields_ = [("ch", ctypes.c_void_p * 2), ("elem_stride", ctypes.c_int64), ("length", ctypes.c_int64)]
+
+
+class Trigger(ctypes.Structure):
+    _fields_ = [("stream", ctypes.c_int32), ("_pad", ctypes.c_int32), ("sample", ctypes.c_int64),
+                ("logit", ctypes.c_float), ("prob", ctypes.c_float)]
+
+
+def tiny_arch() -> Arch:
+    return Arch(0, 2, 16, 0, 0, 1, 4, 2, 1, 0)
+
+
+def full_arch(head_mid_relu: int = 0) -> Arch:
+    return Arch(1, 2, 128, 128, 128, 3, 10, 2, 1, head_mid_relu)
+
+
+def _load(path: str = LIB_PATH):
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with __graft_entry__.build() "
+                          "or python paper_2201_11133_amd/build.py")
+    lib = ctypes.CDLL(path)
+    P, I32, I64, F32, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_double
+    sig = {
+        "gwd_num_params": (I64, [ctypes.POINTER(Arch)]),
+        "gwd_receptive_field": (I32, [ctypes.POINTER(Arch)]),
+        "gwd_load_weights": (I32, [ctypes.POINTER(Arch), I32, P, I64, I32, ctypes.POINTER(P)]),
+        "gwd_free": (None, [P]),
+        "gwd_forward": (I32, [P, ctypes.POINTER(Stream), I32, I32, I32, I32, P, I64, P]),
+        "gwd_forward_out_floats": (I64, [P, ctypes.POINTER(Stream), I32, I32, I32, I32]),
+        "gwd_triggers": (I32, [P, P, I32, F32, I32, ctypes.POINTER(Trigger), I64, ctypes.POINTER(I64), P]),
+        "gwd_saved_bytes": (I64, [P, I32, I32]),
+        "gwd_forward_train": (I32, [P, I32, P, I32, I32, P, P, P]),
+        "gwd_backward": (I32, [P, I32, P, I32, I32, P, P, P, P, P]),
+        "gwd_adam_step": (I32, [P, I32, P, P, P, P, I64, F32, F32, F32, F32, P, P]),
+        "gwd_last_error": (ctypes.c_char_p, []),
+        "gwd_debug_layer": (I32, [P, I32, I32, P, I32, I32, P, P, P, P]),
+        "gwd_debug_export_weights": (I32, [P, I32, P, I64]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def last_error() -> str:
+    return lib.gwd_last_error().decode()
+
+
+def check(code: int) -> None:
+    if code != OK:
+        raise GwdError(code, last_error())
+
+
+def num_params(arch: Arch) -> int:
+    return int(lib.gwd_num_params(ctypes.byref(arch)))
+
+
+def receptive_field(arch: Arch) -> int:
+    return int(lib.gwd_receptive_field(ctypes.byref(arch)))
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+def _stream_handle(stream) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def make_streams(tensors: Sequence) -> Tuple[ctypes.Array, List[int]]:
+    """gwd_stream array for device tensors of shape [L, 2] (interleaved) or pairs (ch0, ch1) of [L]."""
+    arr = (Stream * len(tensors))()
+    lengths = []
+    for i, t in enumerate(tensors):
+        if isinstance(t, (tuple, list)):
+            c0, c1 = t
+            assert c0.dtype == c1.dtype and c0.shape == c1.shape and c0.dim() == 1
+            assert c0.stride(0) == c1.stride(0)
+            arr[i].ch[0], arr[i].ch[1] = c0.data_ptr(), c1.data_ptr()
+            arr[i].elem_stride = c0.stride(0)
+            arr[i].length = c0.shape[0]
+        else:
+            assert t.dim() == 2 and t.shape[1] == 2 and t.stride(1) == 1
+            arr[i].ch[0] = t.data_ptr()
+            arr[i].ch[1] = t.data_ptr() + 4
+            arr[i].elem_stride = t.stride(0)
+            arr[i].length = t.shape[0]
+        lengths.append(int(arr[i].length))
+    return arr, lengths
+
+
+class Model:
+    """Opaque libgwd model handle: n_members members of one architecture at one precision."""
+
+    def __init__(self, arch: Arch, blobs: np.ndarray, precision: str = "fp32"):
+        blobs = np.ascontiguousarray(np.asarray(blobs, dtype=np.float32))
+        if blobs.ndim == 1:
+            blobs = blobs[None]
+        self.arch = arch
+        self.n_members = blobs.shape[0]
+        self.n_params = blobs.shape[1]
+        self.precision = precision
+        h = ctypes.c_void_p()
+        check(lib.gwd_load_weights(ctypes.byref(arch), self.n_members, blobs.ctypes.data, self.n_params,
+                                   PRECISIONS[precision], ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.gwd_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def out_floats(self, streams, window: int, stride: int, out_mode: int) -> int:
+        arr, _ = make_streams(streams)
+        n = lib.gwd_forward_out_floats(self.h, arr, len(streams), window, stride, out_mode)
+        if n < 0:
+            raise GwdError(ERR_ARG, last_error())
+        return int(n)
+
+    def forward(self, streams, window: int = 4096, stride: int = 256, out_mode: int = 0, out=None, stream=None):
+        """Run gwd_forward; returns the float32 device output tensor (layout per out_mode)."""
+        import torch
+        arr, _ = make_streams(streams)
+        n = self.out_floats(streams, window, stride, out_mode)
+        if out is None:
+            out = torch.empty(max(n, 1), dtype=torch.float32, device="cuda")
+        check(lib.gwd_forward(self.h, arr, len(streams), window, stride, out_mode, _ptr(out), out.numel(),
+                              _stream_handle(stream)))
+        return out[:n]
+
+    def export_weights(self, member: int = 0) -> np.ndarray:
+        out = np.zeros(self.n_params, dtype=np.float32)
+        check(lib.gwd_debug_export_weights(self.h, member, out.ctypes.data, self.n_params))
+        return out
+
+    def debug_layer(self, member: int, layer: int, x_in, n_windows: int, window: int, pre_out, x_out, skip,
+                    stream=None):
+        check(lib.gwd_debug_layer(self.h, member, layer, _ptr(x_in), n_windows, window, _ptr(pre_out),
+                                  _ptr(x_out), _ptr(skip), _stream_handle(stream)))
+
+
+def triggers(e, offsets: Sequence[int], threshold_prob: float = 0.9, cluster_window: int = 4096,
+             capacity: Optional[int] = None, stream=None) -> List[Tuple[int, int, float, float]]:
+    """gwd_triggers on a device score tensor e; returns (stream, sample, logit, prob) records."""
+    offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    n_streams = offs.size - 1
+    if capacity is None:
+        capacity = int(sum(-(-(int(offs[i + 1] - offs[i])) // cluster_window) for i in range(n_streams)))
+    buf = (Trigger * max(capacity, 1))()
+    nf = ctypes.c_int64(0)
+    check(lib.gwd_triggers(_ptr(e), offs.ctypes.data, n_streams, threshold_prob, cluster_window, buf, capacity,
+                           ctypes.byref(nf), _stream_handle(stream)))
+    return [(buf[i].stream, buf[i].sample, buf[i].logit, buf[i].prob) for i in range(min(nf.value, capacity))]

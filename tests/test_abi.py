@@ -1,0 +1,131 @@
+"""C ABI host paths on a machine without a GPU: the library loads, exports every function the
+header declares, and rejects bad arguments with the documented codes before any HIP call."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gwd.h")
+
+
+@pytest.fixture(scope="module")
+def g():
+    from paper_2201_11133_amd import gwd
+    return gwd
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gwd_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ["gwd_load_weights", "gwd_forward", "gwd_triggers", "gwd_backward", "gwd_adam_step",
+              "gwd_forward_train", "gwd_num_params", "gwd_receptive_field", "gwd_free", "gwd_last_error"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(g):
+    lib = ctypes.CDLL(g.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert missing == []
+
+
+def test_counts(g):
+    assert g.num_params(g.tiny_arch()) == 1681
+    assert g.num_params(g.full_arch()) == 2964993
+    assert g.num_params(g.full_arch(1)) == 2964993
+    assert g.receptive_field(g.tiny_arch()) == 16
+    assert g.receptive_field(g.full_arch()) == 3070
+    a = g.full_arch()
+    a.input_kernel = 2
+    assert g.receptive_field(a) == 3071
+    assert g.num_params(a) == 2964993 + 256
+    bad = g.full_arch()
+    bad.kind = 7
+    assert g.num_params(bad) == -1 and g.receptive_field(bad) == -1
+
+
+def test_counts_match_oracle(g):
+    from oracle.arch import FULL, TINY, Arch, num_params, receptive_field
+    for ours, theirs in [(g.tiny_arch(), TINY), (g.full_arch(), FULL)]:
+        assert g.num_params(ours) == num_params(theirs)
+        assert g.receptive_field(ours) == receptive_field(theirs)
+    for ls, ns in [(2, 3), (5, 2), (10, 1)]:
+        a = g.full_arch()
+        a.layers_per_stack, a.n_stacks = ls, ns
+        o = Arch(n_stacks=ns, layers_per_stack=ls)
+        assert g.num_params(a) == num_params(o) and g.receptive_field(a) == receptive_field(o)
+
+
+def load(g, arch, blob, n_members, n_params, prec):
+    h = ctypes.c_void_p()
+    code = g.lib.gwd_load_weights(ctypes.byref(arch), n_members, blob.ctypes.data if blob is not None else None,
+                                  n_params, prec, ctypes.byref(h))
+    return code, h
+
+
+def test_load_weights_argument_errors(g):
+    a = g.full_arch()
+    n = g.num_params(a)
+    blob = np.zeros(n, np.float32)
+    assert load(g, a, blob, 1, n - 1, g.FP32)[0] == g.ERR_ARG          # wrong parameter count
+    assert load(g, a, None, 1, n, g.FP32)[0] == g.ERR_ARG               # null blob
+    assert load(g, a, blob, 0, n, g.FP32)[0] == g.ERR_ARG               # no members
+    assert load(g, a, blob, 1, n, 9)[0] == g.ERR_ARG                    # unknown precision
+    bad = g.full_arch()
+    bad.kernel_size = 3
+    assert load(g, bad, blob, 1, g.num_params(bad), g.FP32)[0] == g.ERR_ARG
+    unsup = g.full_arch()
+    unsup.channels = 64
+    assert load(g, unsup, np.zeros(g.num_params(unsup), np.float32), 1, g.num_params(unsup), g.FP32)[0] == g.ERR_UNSUPPORTED
+    t = g.tiny_arch()
+    assert load(g, t, np.zeros(1681, np.float32), 1, 1681, g.BF16)[0] == g.ERR_UNSUPPORTED
+    assert "only" in g.last_error()
+    code, h = load(g, a, blob, 1, n, g.FP32)
+    assert code == g.ERR_NO_DEVICE and not h.value          # valid arguments, but this host has no GPU
+    assert g.last_error() != ""
+
+
+def test_forward_and_debug_argument_errors(g):
+    arr = (g.Stream * 1)()
+    assert g.lib.gwd_forward(None, arr, 1, 4096, 256, 0, None, 0, None) == g.ERR_ARG
+    assert g.lib.gwd_forward_out_floats(None, arr, 1, 4096, 256, 0) == -1
+    assert g.lib.gwd_debug_layer(None, 0, 0, None, 1, 4096, None, None, None, None) == g.ERR_ARG
+    out = np.zeros(10, np.float32)
+    assert g.lib.gwd_debug_export_weights(None, 0, out.ctypes.data, 10) == g.ERR_ARG
+    g.lib.gwd_free(None)    # ignored
+
+
+def trig(g, offs, p=0.9, wc=4096, cap=4, e_ptr=8):
+    offs = np.asarray(offs, np.int64)
+    nf = ctypes.c_int64(-1)
+    buf = (g.Trigger * 4)()
+    code = g.lib.gwd_triggers(e_ptr, offs.ctypes.data, len(offs) - 1, p, wc, buf, cap, ctypes.byref(nf), None)
+    return code, nf.value
+
+
+def test_trigger_argument_errors(g):
+    assert trig(g, [0, 10], p=0.0)[0] == g.ERR_ARG
+    assert trig(g, [0, 10], p=1.0)[0] == g.ERR_ARG
+    assert trig(g, [0, 10], wc=0)[0] == g.ERR_ARG
+    assert trig(g, [0, 10], wc=70000)[0] == g.ERR_ARG
+    assert trig(g, [0, 10], cap=-1)[0] == g.ERR_ARG
+    assert trig(g, [1, 10])[0] == g.ERR_ARG              # offsets must start at 0
+    assert trig(g, [0, 10, 5])[0] == g.ERR_ARG           # and not decrease
+    assert trig(g, [0, 10], e_ptr=None)[0] == g.ERR_ARG  # scores needed when samples exist
+    assert trig(g, [0, 10], e_ptr=6)[0] == g.ERR_ARG     # misaligned
+    assert trig(g, [0, 0, 0]) == (g.OK, 0)               # nothing to scan: no device needed
+    assert trig(g, [0, 10])[0] == g.ERR_NO_DEVICE
+
+
+def test_training_argument_errors(g):
+    assert g.lib.gwd_saved_bytes(None, 1, 4096) == -1
+    assert g.lib.gwd_forward_train(None, 0, None, 1, 4096, None, None, None) in (g.ERR_ARG, g.ERR_UNSUPPORTED)
+    assert g.lib.gwd_backward(None, 0, None, 1, 4096, None, None, None, None, None) in (g.ERR_ARG, g.ERR_UNSUPPORTED)
+    assert g.lib.gwd_adam_step(None, 0, None, None, None, None, 1, 1e-3, 0.9, 0.999, 1e-8, None, None) in (g.ERR_ARG, g.ERR_UNSUPPORTED)

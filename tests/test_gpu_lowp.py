@@ -1,0 +1,139 @@
+"""GPU BF16 / FP8-E4M3 paths: quantised operands bit-equal to the oracle's quantisers, layer-local
+parity, and the end-to-end error against the FP64 oracle (stated, not gated)."""
+import numpy as np
+import pytest
+
+from tests.gpu_common import U32, sigmoid64, to_dev
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def g():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2201_11133_amd import gwd
+    return gwd
+
+
+@pytest.fixture(scope="module")
+def blob():
+    from paper_2201_11133_amd import synth
+    return synth.full_weights(1)
+
+
+@pytest.fixture(scope="module", params=["bf16", "fp8"])
+def model(request, g, blob):
+    m = g.Model(g.full_arch(), blob, request.param)
+    yield request.param, m
+    m.close()
+
+
+def quantised_layer_mats(prec, p, l, last):
+    """(conv codes [256(k), 256(n)] as float64, conv col scales, rs codes [128, N], rs scales) per the
+    oracle quantisers; for bf16 the scales are 1."""
+    from oracle.quant import quantise_weight_e4m3_f32, to_bf16
+    W = p[f"dil{l}.W"]
+    Bc = np.concatenate([W[:, :, 0].T, W[:, :, 1].T], axis=0)               # [k, n]
+    Brs = p[f"skip{l}.W"].T if last else np.concatenate([p[f"res{l}.W"].T, p[f"skip{l}.W"].T], axis=1)
+    if prec == "bf16":
+        return to_bf16(Bc), np.ones(Bc.shape[1]), to_bf16(Brs), np.ones(Brs.shape[1])
+    cq, cs = quantise_weight_e4m3_f32(Bc.T)        # per output column = per row of the transpose
+    rq, rs = quantise_weight_e4m3_f32(Brs.T)
+    return cq.T, cs.astype(np.float64), rq.T, rs.astype(np.float64)
+
+
+def test_exported_operands_match_oracle_quantiser(g, model, blob):
+    prec, m = model
+    print(f"case: export {prec}", flush=True)
+    from oracle.arch import FULL, unpack
+    p = unpack(FULL, blob.astype(np.float64))
+    pe = unpack(FULL, m.export_weights(0).astype(np.float64))
+    for l in [0, 7, 29]:
+        last = l == 29
+        Bc, sc, Brs, srs = quantised_layer_mats(prec, p, l, last)
+        We = pe[f"dil{l}.W"]
+        Bce = np.concatenate([We[:, :, 0].T, We[:, :, 1].T], axis=0)
+        # exported value = code * scale, rounded to float32 (exact for bf16)
+        assert np.array_equal(Bce, (Bc * sc[None, :]).astype(np.float32).astype(np.float64))
+        Brse = pe[f"skip{l}.W"].T if last else np.concatenate([pe[f"res{l}.W"].T, pe[f"skip{l}.W"].T], axis=1)
+        assert np.array_equal(Brse, (Brs * srs[None, :]).astype(np.float32).astype(np.float64))
+    # biases and head are kept in fp32
+    assert np.array_equal(pe["h1.W"], p["h1.W"]) and np.array_equal(pe["dil3.b"], p["dil3.b"])
+
+
+@pytest.mark.parametrize("layer", [0, 9, 18, 29])
+def test_layer_local_parity(g, model, blob, layer):
+    """GPU pre-activation vs the oracle applied to the same quantised operands: the only difference
+    allowed is fp32 accumulation of exact products (|d| <= K u |A||B| scale, Higham sec. 3.1). The
+    gate output is re-quantised before the second GEMM, where a rounding flip moves one operand by
+    one unit in the last place; the residual/skip bound allows for that."""
+    from oracle.arch import FULL, unpack
+    from oracle.forward import shift_right, sigmoid
+    from oracle.quant import to_bf16, to_e4m3
+    prec, m = model
+    print(f"case: {prec} layer {layer}", flush=True)
+    p = unpack(FULL, blob.astype(np.float64))
+    T, nw, C = 512, 2, 128
+    rng = np.random.default_rng(100 + layer)
+    x = (rng.standard_normal((nw, T, C)) * 3).astype(np.float32)
+    sk = (rng.standard_normal((nw, T, C)) * 4).astype(np.float32)
+    x_d, sk_d = to_dev(x), to_dev(sk.copy())
+    pre_d = torch.empty((nw, T, 2 * C), dtype=torch.float32, device="cuda")
+    xo_d = torch.zeros((nw, T, C), dtype=torch.float32, device="cuda")
+    m.debug_layer(0, layer, x_d, nw, T, pre_d, xo_d, sk_d)
+    torch.cuda.synchronize()
+    last = layer == 29
+    quant = to_bf16 if prec == "bf16" else to_e4m3
+    ulp_rel = 2.0 ** -7 if prec == "bf16" else 2.0 ** -3
+    Bc, sc, Brs, srs = quantised_layer_mats(prec, p, layer, last)
+    d = 2 ** (layer % 10)
+    x64 = x.astype(np.float64)
+    Aq = np.concatenate([quant(shift_right(x64, d)), quant(x64)], axis=-1)      # operands as the kernel rounds them
+    acc = Aq @ Bc
+    pre = acc * sc + p[f"dil{layer}.b"]
+    pre_g = pre_d.cpu().numpy().astype(np.float64)
+    bound = (2 * C) * U32 * (np.abs(Aq) @ np.abs(Bc)) * sc + 2 * U32 * np.abs(pre) + 1e-30
+    ratio = np.abs(pre_g - pre) / bound
+    print(f"{prec} layer {layer}: max |d pre| / bound = {ratio.max():.3g}", flush=True)
+    assert np.all(ratio <= 1.0)
+    # second GEMM on the gate of the GPU's own pre-activation, re-quantised like the kernel does
+    gq = quant(np.tanh(pre_g[..., :C]) * sigmoid(pre_g[..., C:]))
+    out = (gq @ Brs) * srs
+    gabs = np.abs(gq)
+    flip = (gabs * ulp_rel + 1e-7) @ np.abs(Brs * srs)             # one-ulp operand flips + fp32 gate
+    acc_b = C * U32 * (gabs @ np.abs(Brs)) * srs
+    if last:
+        sko = sk.astype(np.float64) + out + p[f"skip{layer}.b"]
+        assert np.all(np.abs(sk_d.cpu().numpy() - sko) <= flip + acc_b + 4 * U32 * (np.abs(sko) + 1))
+    else:
+        b_r, b_s = p[f"res{layer}.b"], p[f"skip{layer}.b"]
+        base = np.zeros_like(sk, dtype=np.float64) if layer == 0 else sk.astype(np.float64)
+        sko = base + out[..., C:] + b_s
+        xo = x64 + out[..., :C] + b_r
+        tol_s = flip[..., C:] + acc_b[..., C:] + 4 * U32 * (np.abs(sko) + 1)
+        tol_x = flip[..., :C] + acc_b[..., :C] + 4 * U32 * (np.abs(xo) + 1)
+        assert np.all(np.abs(sk_d.cpu().numpy() - sko) <= tol_s)
+        assert np.all(np.abs(xo_d.cpu().numpy() - xo) <= tol_x)
+
+
+def test_end_to_end_error_stated(g, model, blob):
+    """End-to-end probability error vs the FP64 oracle on 8 windows (reported; random He-normal
+    weights amplify reduced-precision rounding through 30 layers)."""
+    from oracle.arch import FULL, unpack
+    from oracle.forward import forward_window
+    from oracle.stream import gather_windows
+    from paper_2201_11133_amd import synth
+    prec, m = model
+    W, S = 4096, 256
+    L = W + 7 * S
+    x, _ = synth.make_stream(105, L / 4096, 0)
+    z64 = forward_window(FULL, unpack(FULL, blob.astype(np.float64)), gather_windows(x.astype(np.float64), W, S))
+    z = m.forward([to_dev(x)], W, S, out_mode=2).cpu().numpy().reshape(-1, W)
+    dp = np.abs(sigmoid64(z) - sigmoid64(z64))
+    print(f"{prec} end-to-end: max|dp| = {dp.max():.3g}, mean = {dp.mean():.3g}, "
+          f"decisions flipped at p=0.9: {np.count_nonzero((sigmoid64(z) >= 0.9) != (sigmoid64(z64) >= 0.9))} "
+          f"of {dp.size}", flush=True)
+    assert np.all(np.isfinite(z))
+    assert dp.mean() < 0.05
