@@ -46,9 +46,12 @@ extern "C" {
 typedef struct gwd_model gwd_model; /* opaque, library-owned */
 
 typedef enum {
-    GWD_FP32 = 0,     /* fp32 operands, fp32 MFMA, fp32 accumulation            */
-    GWD_BF16 = 1,     /* bf16 operands (RNE), fp32 accumulation, fp32 residual  */
-    GWD_FP8_E4M3 = 2  /* OCP E4M3FN operands, per-output-channel weight scales  */
+    GWD_FP32 = 0,     /* fp32 storage and operands; the dilated-conv GEMM accumulates in fp64,
+                         the res/skip GEMM in fp32                                          */
+    GWD_BF16 = 1,     /* bf16 operands (RNE), fp32 accumulation, fp32 residual and skip    */
+    GWD_FP8_E4M3 = 2, /* OCP E4M3FN operands, per-output-channel weight scales            */
+    GWD_FP64 = 3      /* plain member only, training entry points only: everything in fp64
+                         (device finite-difference gradient checks)                         */
 } gwd_precision;
 
 typedef enum {
@@ -189,34 +192,47 @@ int64_t gwd_forward_out_floats(const gwd_model* model, const gwd_stream* streams
  * GWD_ERR_NONFINITE (and no records). 0 < threshold_prob < 1,
  * 1 <= cluster_window <= 65536. Synchronises hip_stream before returning. */
 gwd_status gwd_triggers(const float* ens_logit, const int64_t* stream_offsets, int32_t n_streams,
-                        float threshold_prob, int32_t cluster_window, gwd_trigger* out,
+                        double threshold_prob, int32_t cluster_window, gwd_trigger* out,
                         int64_t capacity, int64_t* n_found, void* hip_stream);
 
 /* ---- training (one member; "AI ensemble construction") ---------------------
- * windows: device [B][W][2] float32 (interleaved channels), logits: device
- * [B][W]. gwd_forward_train runs member `member` forward, writes the logits
- * and keeps what the backward pass needs in `saved` (device, caller-owned,
- * gwd_saved_bytes(model, B, W) bytes: the input of each stack of
- * layers_per_stack layers plus the final skip sum; everything else is
- * recomputed per stack). gwd_backward takes dL/dlogit [B][W] and writes
- * dL/dparams (device float32 [n_params], overwritten, canonical blob order)
- * and, if grad_input is not NULL, dL/dwindows [B][W][2].
- * The arithmetic follows the model's precision (fp32 master weights are
- * used for FP32; BF16 models run bf16 operands with fp32 accumulation);
- * FP8 is not supported for training (GWD_ERR_UNSUPPORTED). */
+ * windows: device [B][W][2] float32 (interleaved channels). Element type T of
+ * logits, grad_logit, grad_params and grad_input is float, or double for a
+ * model loaded with GWD_FP64.
+ * gwd_forward_train runs member `member` forward over the B windows (each with
+ * zero context), writes the logits [B][W] (T) and keeps what the backward pass
+ * needs in `saved` (device, caller-owned, gwd_saved_bytes(model, B, W) bytes):
+ * for the gated member the input of each stack of layers_per_stack layers and
+ * the final skip sum (everything else is recomputed one stack at a time); for
+ * the plain member every layer output.
+ * gwd_backward takes dL/dlogit [B][W] (T) and the same windows and `saved`,
+ * and writes dL/dparams (device T [n_params], overwritten, canonical blob
+ * order) and, if grad_input is not NULL, dL/dwindows [B][W][2] (T).
+ * The gated member's forward uses the model's precision (FP32 or BF16
+ * kernels); its backward runs in fp32 against the fp32 master weights. FP8
+ * models are inference only (GWD_ERR_UNSUPPORTED). The gated member needs W a
+ * multiple of 64. Calls with one model must not overlap (shared workspace). */
 int64_t gwd_saved_bytes(const gwd_model* model, int32_t B, int32_t W);
 gwd_status gwd_forward_train(gwd_model* model, int32_t member, const float* windows, int32_t B, int32_t W,
-                             float* logits, void* saved, void* hip_stream);
+                             void* logits, void* saved, void* hip_stream);
 gwd_status gwd_backward(gwd_model* model, int32_t member, const float* windows, int32_t B, int32_t W,
-                        const void* saved, const float* grad_logit, float* grad_params,
-                        float* grad_input, void* hip_stream);
+                        const void* saved, const void* grad_logit, void* grad_params,
+                        void* grad_input, void* hip_stream);
+
+/* Per-timestep binary cross-entropy on logits (labels 0/1, "AI ensemble
+ * construction"): grad[i] = (sigmoid(z_i) - y_i) / n (float32 device), and the
+ * mean loss accumulated in double into *loss (device double). */
+gwd_status gwd_bce_logits(const float* logits, const float* labels, int64_t n, float* grad, double* loss,
+                          void* hip_stream);
 
 /* Adam (Kingma & Ba) with bias correction on float32 master weights
- * (device [n_params]), gradient, first and second moments (updated in
- * place); step is 1-based. Also writes the global gradient 2-norm,
- * accumulated in double, to *grad_norm_out (device, may be NULL), and
- * refreshes member `member`'s packed working weights from the new master
- * weights. No weight decay, no clipping. */
+ * (device [n_params], canonical order), gradient, first and second moments
+ * (updated in place); step is 1-based. Writes the global gradient 2-norm,
+ * accumulated in double, to *grad_norm_out (device, may be NULL), then
+ * refreshes member `member`'s working weights (packed operands for the
+ * forward kernels and the backward's copy) from the new master weights.
+ * No weight decay, no clipping. FP32 and BF16 models. Synchronises
+ * hip_stream (the working weights are repacked on the host). */
 gwd_status gwd_adam_step(gwd_model* model, int32_t member, float* master, const float* grad, float* m, float* v,
                          int64_t step, float lr, float beta1, float beta2, float eps,
                          double* grad_norm_out, void* hip_stream);

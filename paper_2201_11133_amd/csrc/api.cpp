@@ -112,9 +112,10 @@ gwd_status gwd_load_weights(const gwd_arch* arch, int32_t n_members, const float
     if (!host_blob) { set_error("gwd_load_weights: host_blob is NULL"); return GWD_ERR_ARG; }
     const int64_t np = gwd_num_params(arch);
     if (n_params != np) { set_error("gwd_load_weights: n_params %lld, architecture needs %lld", (long long)n_params, (long long)np); return GWD_ERR_ARG; }
-    if (precision != GWD_FP32 && precision != GWD_BF16 && precision != GWD_FP8_E4M3) { set_error("gwd_load_weights: unknown precision %d", (int)precision); return GWD_ERR_ARG; }
+    if (precision != GWD_FP32 && precision != GWD_BF16 && precision != GWD_FP8_E4M3 && precision != GWD_FP64) { set_error("gwd_load_weights: unknown precision %d", (int)precision); return GWD_ERR_ARG; }
     if (!arch_supported(arch)) { set_error("gwd_load_weights: architecture not supported by the GPU kernels"); return GWD_ERR_UNSUPPORTED; }
-    if (arch->kind == 0 && precision != GWD_FP32) { set_error("gwd_load_weights: the plain member runs in FP32 only"); return GWD_ERR_UNSUPPORTED; }
+    if (arch->kind == 0 && precision != GWD_FP32 && precision != GWD_FP64) { set_error("gwd_load_weights: the plain member runs in FP32 (or FP64 for training checks) only"); return GWD_ERR_UNSUPPORTED; }
+    if (arch->kind == 1 && precision == GWD_FP64) { set_error("gwd_load_weights: FP64 is for the plain member's gradient checks only"); return GWD_ERR_UNSUPPORTED; }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) { set_error("gwd_load_weights: no HIP device"); return GWD_ERR_NO_DEVICE; }
     gwd_model* m = new (std::nothrow) gwd_model();
@@ -128,9 +129,24 @@ gwd_status gwd_load_weights(const gwd_arch* arch, int32_t n_members, const float
     if (e != hipSuccess) { delete m; return hip_fail(e, "hipGetDevice"); }
     m->host_blob.assign(host_blob, host_blob + (size_t)np * n_members);
     m->members.resize(n_members);
+    m->canon.assign(n_members, nullptr);
     for (int i = 0; i < n_members; ++i) {
-        gwd_status s = pack_member(m, i, host_blob + (size_t)np * i);
-        if (s != GWD_OK) { gwd_free(m); return s; }
+        const float* src = host_blob + (size_t)np * i;
+        if (precision != GWD_FP64) {
+            gwd_status s = pack_member(m, i, src);
+            if (s != GWD_OK) { gwd_free(m); return s; }
+        }
+        // canonical copy for training (fp32, or fp64 for the FP64 gradient-check model)
+        const size_t es = precision == GWD_FP64 ? 8 : 4;
+        e = hipMalloc(&m->canon[i], np * es);
+        if (e != hipSuccess) { gwd_free(m); return hip_fail(e, "hipMalloc(canonical weights)"); }
+        if (precision == GWD_FP64) {
+            std::vector<double> d(src, src + np);
+            e = hipMemcpy(m->canon[i], d.data(), np * 8, hipMemcpyHostToDevice);
+        } else {
+            e = hipMemcpy(m->canon[i], src, np * 4, hipMemcpyHostToDevice);
+        }
+        if (e != hipSuccess) { gwd_free(m); return hip_fail(e, "hipMemcpy(canonical weights)"); }
     }
     *out = m;
     return GWD_OK;
@@ -141,7 +157,10 @@ void gwd_free(gwd_model* m) {
     (void)hipDeviceSynchronize();
     for (auto& mw : m->members)
         if (mw.base) (void)hipFree(mw.base);
+    for (void* c : m->canon)
+        if (c) (void)hipFree(c);
     if (m->ws.base) (void)hipFree(m->ws.base);
+    if (m->tws.base) (void)hipFree(m->tws.base);
     delete m;
 }
 
@@ -215,6 +234,10 @@ gwd_status gwd_forward(gwd_model* m, const gwd_stream* streams, int32_t n_stream
         set_error("gwd_forward: out holds %lld floats, %lld needed", (long long)out_capacity_floats, (long long)out_floats);
         return GWD_ERR_CAPACITY;
     }
+    if (m->prec == GWD_FP64) {
+        set_error("gwd_forward: FP64 models serve the training gradient checks only");
+        return GWD_ERR_UNSUPPORTED;
+    }
     if (m->arch.kind == 1 && m->prec != GWD_FP32 && m->prec != GWD_BF16 && m->prec != GWD_FP8_E4M3) {
         set_error("gwd_forward: precision not supported");
         return GWD_ERR_UNSUPPORTED;
@@ -275,14 +298,14 @@ gwd_status gwd_forward(gwd_model* m, const gwd_stream* streams, int32_t n_stream
     return GWD_OK;
 }
 
-gwd_status gwd_triggers(const float* ens_logit, const int64_t* offs, int32_t n_streams, float threshold_prob,
+gwd_status gwd_triggers(const float* ens_logit, const int64_t* offs, int32_t n_streams, double threshold_prob,
                         int32_t cluster_window, gwd_trigger* out, int64_t capacity, int64_t* n_found,
                         void* hip_stream) {
     if (!n_found) { set_error("gwd_triggers: n_found is NULL"); return GWD_ERR_ARG; }
     *n_found = 0;
     if (!offs) { set_error("gwd_triggers: stream_offsets is NULL"); return GWD_ERR_ARG; }
     if (n_streams < 1 || n_streams > 65536) { set_error("gwd_triggers: n_streams %d not in [1, 65536]", n_streams); return GWD_ERR_ARG; }
-    if (!(threshold_prob > 0.f && threshold_prob < 1.f)) { set_error("gwd_triggers: threshold_prob must be in (0, 1)"); return GWD_ERR_ARG; }
+    if (!(threshold_prob > 0.0 && threshold_prob < 1.0)) { set_error("gwd_triggers: threshold_prob must be in (0, 1)"); return GWD_ERR_ARG; }
     if (cluster_window < 1 || cluster_window > 65536) { set_error("gwd_triggers: cluster_window %d not in [1, 65536]", cluster_window); return GWD_ERR_ARG; }
     if (capacity < 0) { set_error("gwd_triggers: negative capacity"); return GWD_ERR_ARG; }
     if (capacity > 0 && !out) { set_error("gwd_triggers: out is NULL"); return GWD_ERR_ARG; }
@@ -297,21 +320,16 @@ gwd_status gwd_triggers(const float* ens_logit, const int64_t* offs, int32_t n_s
     }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) { set_error("gwd_triggers: no HIP device"); return GWD_ERR_NO_DEVICE; }
-    const double p = (double)threshold_prob;
+    const double p = threshold_prob;
     const double thr = log(p / (1.0 - p));
     return run_triggers(ens_logit, offs, n_streams, thr, cluster_window, out, capacity, n_found, (hipStream_t)hip_stream);
-}
-
-int64_t gwd_saved_bytes(const gwd_model* m, int32_t B, int32_t W) {
-    if (!m || B < 1 || W < 1) return -1;
-    if (m->arch.kind != 1) return (int64_t)B * W * 16 * 4 * 4;
-    return (int64_t)(m->arch.n_stacks + 1) * B * W * kC * 4;
 }
 
 gwd_status gwd_debug_layer(gwd_model* m, int32_t member, int32_t layer, const float* x_in, int32_t n_windows,
                            int32_t window, float* pre_out, float* x_out, float* skip, void* hip_stream) {
     if (!m) { set_error("gwd_debug_layer: model is NULL"); return GWD_ERR_ARG; }
     if (m->arch.kind != 1) { set_error("gwd_debug_layer: needs the gated member"); return GWD_ERR_UNSUPPORTED; }
+    if (m->prec == GWD_FP64) { set_error("gwd_debug_layer: not for FP64 models"); return GWD_ERR_UNSUPPORTED; }
     const int L = m->arch.n_stacks * m->arch.layers_per_stack;
     if (member < 0 || member >= m->n_members) { set_error("gwd_debug_layer: member %d out of range", member); return GWD_ERR_ARG; }
     if (layer < 0 || layer >= L) { set_error("gwd_debug_layer: layer %d out of range", layer); return GWD_ERR_ARG; }
@@ -328,6 +346,7 @@ gwd_status gwd_debug_export_weights(const gwd_model* m, int32_t member, float* o
     if (!m || !out) { set_error("gwd_debug_export_weights: NULL argument"); return GWD_ERR_ARG; }
     if (member < 0 || member >= m->n_members) { set_error("gwd_debug_export_weights: member out of range"); return GWD_ERR_ARG; }
     if (n_params != m->n_params) { set_error("gwd_debug_export_weights: n_params mismatch"); return GWD_ERR_ARG; }
+    if (m->prec == GWD_FP64) { set_error("gwd_debug_export_weights: not for FP64 models"); return GWD_ERR_UNSUPPORTED; }
     return export_member(m, member, out);
 }
 

@@ -175,7 +175,7 @@ __global__ __launch_bounds__(256, 2) void layer_f32_kernel(LayerArgsF32 p) {
         for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int m = 16 * rb + 4 * q + i;
+                const int m = 16 * rb + q + 4 * i;  // f64 16x16 result: lane 16 q + r, register i -> row q + 4 i
                 const float af = (float)(acc[rb][c][0][i] + bf);
                 const float ag = (float)(acc[rb][c][1][i] + bg);
                 if (p.pre_out) {

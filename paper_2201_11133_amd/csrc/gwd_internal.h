@@ -72,6 +72,13 @@ struct Workspace {
     int64_t bytes = 0;
 };
 
+// Offsets (floats) of every tensor of a gated-member (kind 1) blob, in blob order.
+struct BlobOffsets {
+    int64_t in_w, in_b, h1w, h1b, h2w, h2b;
+    std::vector<int64_t> dil_w, dil_b, res_w, res_b, skip_w, skip_b;
+};
+BlobOffsets blob_offsets(const gwd_arch& a);
+
 }  // namespace gwd
 
 struct gwd_model {
@@ -83,6 +90,8 @@ struct gwd_model {
     std::vector<float> host_blob;              // canonical fp32 weights (kept for export and repacking)
     std::vector<gwd::MemberWeights> members;
     gwd::Workspace ws;
+    gwd::Workspace tws;                        // training workspace
+    std::vector<void*> canon;                  // device copy of each member's canonical blob (fp32; fp64 for GWD_FP64)
     int32_t batch_windows;                     // windows per layer-kernel batch
 };
 

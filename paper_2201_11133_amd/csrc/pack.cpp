@@ -34,13 +34,11 @@ namespace gwd {
 
 namespace {
 
-struct BlobView {
-    // offsets (floats) of each tensor of a kind-1 blob
-    int64_t in_w, in_b, h1w, h1b, h2w, h2b;
-    std::vector<int64_t> dil_w, dil_b, res_w, res_b, skip_w, skip_b;
-};
+typedef BlobOffsets BlobView;
 
-BlobView view_kind1(const gwd_arch& a) {
+}  // namespace
+
+BlobOffsets blob_offsets(const gwd_arch& a) {
     BlobView v;
     const int64_t C = a.channels, S = a.skip_channels, H = a.head_channels;
     const int L = a.n_stacks * a.layers_per_stack;
@@ -66,6 +64,10 @@ BlobView view_kind1(const gwd_arch& a) {
     v.h2b = off; off += 1;
     return v;
 }
+
+namespace {
+
+BlobView view_kind1(const gwd_arch& a) { return blob_offsets(a); }
 
 // B matrices of layer l as functions of (k, n).
 struct LayerMats {
@@ -258,9 +260,14 @@ gwd_status pack_member(gwd_model* m, int member, const float* blob) {
             }
         }
     }
-    mw.bytes = (int64_t)img.size();
-    hipError_t e = hipMalloc(&mw.base, mw.bytes);
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc(weights)");
+    hipError_t e;
+    if (!mw.base || mw.bytes != (int64_t)img.size()) {
+        if (mw.base) (void)hipFree(mw.base);
+        mw.base = nullptr;
+        mw.bytes = (int64_t)img.size();
+        e = hipMalloc(&mw.base, mw.bytes);
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc(weights)");
+    }
     e = hipMemcpy(mw.base, img.data(), mw.bytes, hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy(weights)");
     return GWD_OK;

@@ -1,0 +1,80 @@
+// Internal declarations of the training kernels (not part of the ABI).
+#pragma once
+#include "gwd_internal.h"
+
+namespace gwd {
+
+// Operand part of a row GEMM: A(row, k) = ptr[(b T + t + shift) * ld + k], zero outside the window.
+struct APart {
+    const float* ptr;
+    int64_t ld;
+    int shift;
+    int K;
+};
+// B(k, n) = ptr[k * ld + n * es]
+struct BPart {
+    const float* ptr;
+    int64_t ld;
+    int64_t es;
+};
+
+struct GemmRowsArgs {
+    APart A[2];
+    BPart B[2];
+    int nparts;
+    int64_t M;
+    int N;
+    int T;
+    float* C;
+    int64_t ldc;
+    float beta;
+    const float* bias;   // optional [N]
+    const float* mask;   // optional: C = 0 where mask <= 0
+    int64_t ldm;
+};
+
+struct WgradArgs {
+    APart A[2];  // stacked along k (the output rows)
+    int nparts;
+    int Ktot;
+    const float* B;  // B(row, n) = B[(b T + t + bshift) * ldb + n], zero outside the window
+    int64_t ldb;
+    int bshift;
+    int N;
+    int64_t M;
+    int T;
+    int64_t rows_per_chunk;
+    float* part;  // [nchunks][Ktot][N]
+};
+
+hipError_t gemm_rows(const GemmRowsArgs& a, hipStream_t st);
+// dst (+)= reduced partials: out_mode 0 row-major [K][N]; 2: element (k, n) at dst[(k N + n) * 2]
+// (one tap of a conv weight [n_out][c][2])
+hipError_t gemm_wgrad(const WgradArgs& a, float* dst, int out_mode, hipStream_t st);
+// dst[n * dst_stride] += sum_rows f(X[row][n]) * w[row * wstride]   (w optional, f = id or ReLU)
+hipError_t colsum(const float* X, int64_t ldx, int64_t M, int N, const float* w, int64_t wstride, int relu,
+                  float* part, float* dst, int64_t dst_stride, hipStream_t st);
+hipError_t launch_input_proj(const float* u, int64_t M, const float* w_in, const float* b_in, float* x0,
+                             hipStream_t st);
+hipError_t launch_gate_bwd(const float* pre, const float* dg, int64_t M, float* g, float* dpre, hipStream_t st);
+hipError_t launch_head_bwd_elem(const float* h, const float* dz, int64_t M, const float* w2, int mid, float* dh,
+                                float* ah, hipStream_t st);
+hipError_t launch_head_logit(const float* h, int64_t M, const float* w2, const float* b2, int mid, float* z,
+                             hipStream_t st);
+hipError_t launch_input_grad(const float* dx0, int64_t M, const float* w_in, float* du, hipStream_t st);
+hipError_t launch_relu_copy(const float* x, int64_t n, float* y, hipStream_t st);
+hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t st);
+hipError_t launch_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                       float eps, int64_t step, double* norm_part, double* norm_out, hipStream_t st);
+hipError_t launch_bce(const float* z, const float* y, int64_t n, float* grad, double* part, double* loss,
+                      hipStream_t st);
+
+// small member (kind 0), float or double
+template <class T>
+hipError_t tiny_train_forward(const T* blob, const float* u, int B, int Tw, T* ys /*[4][M][16]*/, T* logits,
+                              hipStream_t st);
+template <class T>
+hipError_t tiny_train_backward(const T* blob, const float* u, int B, int Tw, const T* ys, const T* dz, T* grad,
+                               T* dbuf /*[2][M][16]*/, T* du, hipStream_t st);
+
+}  // namespace gwd

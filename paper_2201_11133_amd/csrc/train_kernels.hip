@@ -1,0 +1,376 @@
+// Training kernels: generic FP32 MFMA GEMMs with row-shifted operands, reductions, elementwise
+// backward steps, Adam. ("AI ensemble construction": each member is trained as a per-timestep
+// classifier from random initialisation.)
+//
+// Row index `row` = b * T + t addresses time step t of window b; an operand part with shift s reads
+// row b * T + (t + s) and is zero when t + s falls outside [0, T) (each window has zero context, so
+// a dilation tap never crosses windows).
+#include "gwd_internal.h"
+#include "train_internal.h"
+
+namespace gwd {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+#define MFMA32(a, b, c) __builtin_amdgcn_mfma_f32_32x32x2f32((a), (b), (c), 0, 0, 0)
+
+constexpr int GT = 64;   // output tile (rows x columns)
+constexpr int GK = 32;   // k chunk staged in LDS
+
+__device__ inline float part_a(const APart& p, int64_t row, int T, int k) {
+    const int64_t b = row / T;
+    const int t = (int)(row - b * T) + p.shift;
+    if (t < 0 || t >= T) return 0.f;
+    return p.ptr[(b * T + t) * p.ld + k];
+}
+
+// C[M, N] = beta * C + sum_p A_p[M, K_p] B_p[K_p, N]   (optionally masked: C *= (mask > 0))
+__global__ __launch_bounds__(256) void gemm_rows_kernel(GemmRowsArgs a) {
+    __shared__ float As[GT][GK + 1];
+    __shared__ float Bs[GK][GT + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;            // wave tile 32 x 32 inside the 64 x 64 block
+    const int ntn = a.N / GT;
+    const int64_t row0 = (int64_t)(blockIdx.x / ntn) * GT;
+    const int col0 = (blockIdx.x % ntn) * GT;
+    floatx16 acc = {};
+    for (int p = 0; p < a.nparts; ++p) {
+        const APart& ap = a.A[p];
+        const BPart& bp = a.B[p];
+        for (int k0 = 0; k0 < ap.K; k0 += GK) {
+            for (int i = tid; i < GT * GK; i += 256) {
+                const int rr = i / GK, kk = i % GK;
+                As[rr][kk] = part_a(ap, row0 + rr, a.T, k0 + kk);
+            }
+            for (int i = tid; i < GK * GT; i += 256) {
+                const int kk = i / GT, nn = i % GT;
+                Bs[kk][nn] = bp.ptr[(int64_t)(k0 + kk) * bp.ld + (int64_t)(col0 + nn) * bp.es];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int kk = 0; kk < GK; kk += 2) {
+                const float av = As[32 * wr + (lane & 31)][kk + (lane >> 5)];
+                const float bv = Bs[kk + (lane >> 5)][32 * wc + (lane & 31)];
+                acc = MFMA32(av, bv, acc);
+            }
+            __syncthreads();
+        }
+    }
+    const int n = col0 + 32 * wc + (lane & 31);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int64_t row = row0 + 32 * wr + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+        const int64_t o = row * a.ldc + n;
+        float v = acc[i];
+        if (a.bias) v += a.bias[n];
+        if (a.beta != 0.f) v += a.beta * a.C[o];
+        if (a.mask) v = (a.mask[row * a.ldm + n] > 0.f) ? v : 0.f;
+        a.C[o] = v;
+    }
+}
+
+// part[chunk][K][N] = sum over the chunk's rows of A(row, k) B(row, n); A from row-shifted parts
+// stacked along k, B plain. One block: one 64 x 64 output tile of one row chunk.
+__global__ __launch_bounds__(256) void gemm_wgrad_kernel(WgradArgs a) {
+    __shared__ float As[GK][GT + 1];   // [row][k]
+    __shared__ float Bs[GK][GT + 1];   // [row][n]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int ntn = a.N / GT, ntk = a.Ktot / GT;
+    const int tile = blockIdx.x % (ntn * ntk);
+    const int chunk = blockIdx.x / (ntn * ntk);
+    const int k0 = (tile / ntn) * GT, n0 = (tile % ntn) * GT;
+    // which A part holds columns [k0, k0 + 64)
+    int p = 0, kb = 0;
+    while (kb + a.A[p].K <= k0) {
+        kb += a.A[p].K;
+        ++p;
+    }
+    const APart ap = a.A[p];
+    const int64_t r0 = (int64_t)chunk * a.rows_per_chunk;
+    const int64_t r1 = min(r0 + a.rows_per_chunk, a.M);
+    floatx16 acc = {};
+    for (int64_t rb = r0; rb < r1; rb += GK) {
+        for (int i = tid; i < GK * GT; i += 256) {
+            const int rr = i / GT, kk = i % GT;
+            const int64_t row = rb + rr;
+            As[rr][kk] = (row < r1) ? part_a(ap, row, a.T, k0 - kb + kk) : 0.f;
+            Bs[rr][kk] = (row < r1) ? part_a(APart{a.B, a.ldb, a.bshift, a.N}, row, a.T, n0 + kk) : 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int rr = 0; rr < GK; rr += 2) {
+            const float av = As[rr + (lane >> 5)][32 * wr + (lane & 31)];   // A^T: (k, row)
+            const float bv = Bs[rr + (lane >> 5)][32 * wc + (lane & 31)];
+            acc = MFMA32(av, bv, acc);
+        }
+        __syncthreads();
+    }
+    float* out = a.part + (int64_t)chunk * a.Ktot * a.N;
+    const int n = n0 + 32 * wc + (lane & 31);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int k = k0 + 32 * wr + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+        out[(int64_t)k * a.N + n] = acc[i];
+    }
+}
+
+// dst[i * stride] += sum over chunks (in order) of part[chunk][i], i = k N + n
+__global__ __launch_bounds__(256) void reduce_parts_kernel(const float* part, int nchunks, int K, int N,
+                                                           float* dst, int64_t stride) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)K * N) return;
+    float s = 0.f;
+    for (int c = 0; c < nchunks; ++c) s += part[(int64_t)c * K * N + i];
+    dst[i * stride] += s;
+}
+
+// part[chunk][n] = sum over the chunk's rows of f(X[row][n]) * w(row); f = identity or ReLU
+__global__ __launch_bounds__(256) void colsum_kernel(const float* X, int64_t ldx, int64_t M, int N,
+                                                     const float* w, int64_t wstride, int relu,
+                                                     int64_t rows_per_chunk, float* part) {
+    const int chunk = blockIdx.y;
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    if (n >= N) return;
+    const int64_t r0 = (int64_t)chunk * rows_per_chunk;
+    const int64_t r1 = min(r0 + rows_per_chunk, M);
+    float s = 0.f;
+    for (int64_t r = r0; r < r1; ++r) {
+        float v = X[r * ldx + n];
+        if (relu) v = fmaxf(v, 0.f);
+        if (w) v *= w[r * wstride];
+        s += v;
+    }
+    part[(int64_t)chunk * N + n] = s;
+}
+
+// x0[row][c] = W_in[c] . u[row] + b_in[c]   (windows [B][T][2] interleaved)
+__global__ __launch_bounds__(256) void input_proj_kernel(const float* u, int64_t M, const float* w_in,
+                                                         const float* b_in, float* x0) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= M * kC) return;
+    const int64_t row = i / kC;
+    const int c = (int)(i % kC);
+    x0[i] = b_in[c] + w_in[2 * c] * u[2 * row] + w_in[2 * c + 1] * u[2 * row + 1];
+}
+
+// Gate backward: from pre [M][256] and dg [M][128]: g = tanh(pf) sigmoid(pg) [M][128] and
+// dpre = [dg sigmoid(pg) (1 - tanh^2(pf)) | dg tanh(pf) sigmoid(pg) (1 - sigmoid(pg))] [M][256].
+__global__ __launch_bounds__(256) void gate_bwd_kernel(const float* pre, const float* dg, int64_t M, float* g,
+                                                       float* dpre) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= M * kC) return;
+    const int64_t row = i / kC;
+    const int c = (int)(i % kC);
+    const float pf = pre[row * 2 * kC + c], pg = pre[row * 2 * kC + kC + c];
+    const float th = tanhf(pf), sg = 1.f / (1.f + expf(-pg));
+    const float d = dg[i];
+    g[i] = th * sg;
+    dpre[row * 2 * kC + c] = d * sg * (1.f - th * th);
+    dpre[row * 2 * kC + kC + c] = d * th * sg * (1.f - sg);
+}
+
+// Head backward, elementwise part: dh[row][j] = dz[row] * w2[j] * act'(h[row][j]);
+// ah[row][j] = act(h[row][j]) (used for d w2).
+__global__ __launch_bounds__(256) void head_bwd_elem_kernel(const float* h, const float* dz, int64_t M,
+                                                            const float* w2, int mid_relu, float* dh, float* ah) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= M * kC) return;
+    const int64_t row = i / kC;
+    const int j = (int)(i % kC);
+    const float hv = h[i];
+    const bool on = !mid_relu || hv > 0.f;
+    dh[i] = on ? dz[row] * w2[j] : 0.f;
+    ah[i] = mid_relu ? fmaxf(hv, 0.f) : hv;
+}
+
+// logit[row] = w2 . act(h[row]) + b2
+__global__ __launch_bounds__(256) void head_logit_kernel(const float* h, int64_t M, const float* w2,
+                                                         const float* b2, int mid_relu, float* z) {
+    const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (row >= M) return;
+    float s = 0.f;
+    for (int j = 0; j < kC; ++j) {
+        float v = h[row * kC + j];
+        if (mid_relu) v = fmaxf(v, 0.f);
+        s = fmaf(w2[j], v, s);
+    }
+    z[row] = s + b2[0];
+}
+
+// du[row][i] = sum_c dx0[row][c] W_in[c][i]
+__global__ __launch_bounds__(256) void input_grad_kernel(const float* dx0, int64_t M, const float* w_in, float* du) {
+    const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (row >= M) return;
+    float s0 = 0.f, s1 = 0.f;
+    for (int c = 0; c < kC; ++c) {
+        const float d = dx0[row * kC + c];
+        s0 = fmaf(d, w_in[2 * c], s0);
+        s1 = fmaf(d, w_in[2 * c + 1], s1);
+    }
+    du[2 * row] = s0;
+    du[2 * row + 1] = s1;
+}
+
+__global__ __launch_bounds__(256) void relu_copy_kernel(const float* x, int64_t n, float* y) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) y[i] = fmaxf(x[i], 0.f);
+}
+
+__global__ __launch_bounds__(256) void fill_kernel(float* p, int64_t n, float v) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ---- Adam with bias correction; per-block fp64 partial sums of g^2 for the global norm
+__global__ __launch_bounds__(256) void adam_kernel(float* w, const float* g, float* m, float* v, int64_t n,
+                                                   float lr, float b1, float b2, float eps, float c1, float c2,
+                                                   double* norm_part) {
+    __shared__ double red[4];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double sq = 0.0;
+    if (i < n) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        const float mh = mi / c1, vh = vi / c2;
+        w[i] -= lr * mh / (sqrtf(vh) + eps);
+        sq = (double)gi * (double)gi;
+    }
+    for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sq;
+    __syncthreads();
+    if (threadIdx.x == 0) norm_part[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+__global__ __launch_bounds__(256) void norm_final_kernel(const double* part, int64_t n, double* out) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) s += part[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sqrt(red[0]);
+}
+
+// BCE on logits: grad[i] = (sigmoid(z) - y) / n; loss partials in fp64
+__global__ __launch_bounds__(256) void bce_kernel(const float* z, const float* y, int64_t n, float* grad,
+                                                  double* part) {
+    __shared__ double red[4];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double l = 0.0;
+    if (i < n) {
+        const double zz = z[i], yy = y[i];
+        l = fmax(zz, 0.0) + log1p(exp(-fabs(zz))) - yy * zz;
+        grad[i] = (float)((1.0 / (1.0 + exp(-zz)) - yy) / (double)n);
+    }
+    for (int off = 32; off > 0; off >>= 1) l += __shfl_xor(l, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = l;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+__global__ __launch_bounds__(256) void mean_final_kernel(const double* part, int64_t nparts, int64_t n,
+                                                         double* out) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < nparts; i += 256) s += part[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0] / (double)n;
+}
+
+// ---------------------------------------------------------------- launchers
+static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+hipError_t gemm_rows(const GemmRowsArgs& a, hipStream_t st) {
+    const int64_t blocks = (a.M / GT) * (a.N / GT);
+    hipLaunchKernelGGL(gemm_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t gemm_wgrad(const WgradArgs& a0, float* dst, int out_mode, hipStream_t st) {
+    WgradArgs a = a0;
+    const int nchunks = (int)((a.M + a.rows_per_chunk - 1) / a.rows_per_chunk);
+    const int64_t blocks = (int64_t)nchunks * (a.Ktot / GT) * (a.N / GT);
+    hipLaunchKernelGGL(gemm_wgrad_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(nblk((int64_t)a.Ktot * a.N)), dim3(256), 0, st, a.part, nchunks,
+                       a.Ktot, a.N, dst, (int64_t)(out_mode == 2 ? 2 : 1));
+    return hipGetLastError();
+}
+
+hipError_t colsum(const float* X, int64_t ldx, int64_t M, int N, const float* w, int64_t wstride, int relu,
+                  float* part, float* dst, int64_t dst_stride, hipStream_t st) {
+    const int64_t rpc = 4096;
+    const int nchunks = (int)((M + rpc - 1) / rpc);
+    hipLaunchKernelGGL(colsum_kernel, dim3((N + 255) / 256, nchunks), dim3(256), 0, st, X, ldx, M, N, w, wstride,
+                       relu, rpc, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(nblk(N)), dim3(256), 0, st, part, nchunks, 1, N, dst, dst_stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_input_proj(const float* u, int64_t M, const float* w_in, const float* b_in, float* x0,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(input_proj_kernel, dim3(nblk(M * kC)), dim3(256), 0, st, u, M, w_in, b_in, x0);
+    return hipGetLastError();
+}
+hipError_t launch_gate_bwd(const float* pre, const float* dg, int64_t M, float* g, float* dpre, hipStream_t st) {
+    hipLaunchKernelGGL(gate_bwd_kernel, dim3(nblk(M * kC)), dim3(256), 0, st, pre, dg, M, g, dpre);
+    return hipGetLastError();
+}
+hipError_t launch_head_bwd_elem(const float* h, const float* dz, int64_t M, const float* w2, int mid, float* dh,
+                                float* ah, hipStream_t st) {
+    hipLaunchKernelGGL(head_bwd_elem_kernel, dim3(nblk(M * kC)), dim3(256), 0, st, h, dz, M, w2, mid, dh, ah);
+    return hipGetLastError();
+}
+hipError_t launch_head_logit(const float* h, int64_t M, const float* w2, const float* b2, int mid, float* z,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(head_logit_kernel, dim3(nblk(M)), dim3(256), 0, st, h, M, w2, b2, mid, z);
+    return hipGetLastError();
+}
+hipError_t launch_input_grad(const float* dx0, int64_t M, const float* w_in, float* du, hipStream_t st) {
+    hipLaunchKernelGGL(input_grad_kernel, dim3(nblk(M)), dim3(256), 0, st, dx0, M, w_in, du);
+    return hipGetLastError();
+}
+hipError_t launch_relu_copy(const float* x, int64_t n, float* y, hipStream_t st) {
+    hipLaunchKernelGGL(relu_copy_kernel, dim3(nblk(n)), dim3(256), 0, st, x, n, y);
+    return hipGetLastError();
+}
+hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t st) {
+    hipLaunchKernelGGL(fill_kernel, dim3(nblk(n)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+hipError_t launch_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                       float eps, int64_t step, double* norm_part, double* norm_out, hipStream_t st) {
+    const float c1 = (float)(1.0 - pow((double)b1, (double)step));
+    const float c2 = (float)(1.0 - pow((double)b2, (double)step));
+    const unsigned nb = nblk(n);
+    hipLaunchKernelGGL(adam_kernel, dim3(nb), dim3(256), 0, st, w, g, m, v, n, lr, b1, b2, eps, c1, c2, norm_part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !norm_out) return e;
+    hipLaunchKernelGGL(norm_final_kernel, dim3(1), dim3(256), 0, st, norm_part, (int64_t)nb, norm_out);
+    return hipGetLastError();
+}
+hipError_t launch_bce(const float* z, const float* y, int64_t n, float* grad, double* part, double* loss,
+                      hipStream_t st) {
+    const unsigned nb = nblk(n);
+    hipLaunchKernelGGL(bce_kernel, dim3(nb), dim3(256), 0, st, z, y, n, grad, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(mean_final_kernel, dim3(1), dim3(256), 0, st, part, (int64_t)nb, n, loss);
+    return hipGetLastError();
+}
+
+}  // namespace gwd

@@ -26,8 +26,8 @@ ERR_UNSUPPORTED = -5
 ERR_NONFINITE = -6
 ERR_NO_DEVICE = -7
 
-FP32, BF16, FP8_E4M3 = 0, 1, 2
-PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8_E4M3}
+FP32, BF16, FP8_E4M3, FP64 = 0, 1, 2, 3
+PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8_E4M3, "fp64": FP64}
 
 
 class GwdError(RuntimeError):
@@ -72,13 +72,14 @@ def _load(path: str = LIB_PATH):
         "gwd_free": (None, [P]),
         "gwd_forward": (I32, [P, ctypes.POINTER(Stream), I32, I32, I32, I32, P, I64, P]),
         "gwd_forward_out_floats": (I64, [P, ctypes.POINTER(Stream), I32, I32, I32, I32]),
-        "gwd_triggers": (I32, [P, P, I32, F32, I32, ctypes.POINTER(Trigger), I64, ctypes.POINTER(I64), P]),
+        "gwd_triggers": (I32, [P, P, I32, D, I32, ctypes.POINTER(Trigger), I64, ctypes.POINTER(I64), P]),
         "gwd_saved_bytes": (I64, [P, I32, I32]),
         "gwd_forward_train": (I32, [P, I32, P, I32, I32, P, P, P]),
         "gwd_backward": (I32, [P, I32, P, I32, I32, P, P, P, P, P]),
         "gwd_adam_step": (I32, [P, I32, P, P, P, P, I64, F32, F32, F32, F32, P, P]),
         "gwd_last_error": (ctypes.c_char_p, []),
         "gwd_debug_layer": (I32, [P, I32, I32, P, I32, I32, P, P, P, P]),
+        "gwd_bce_logits": (I32, [P, P, I64, P, P, P]),
         "gwd_debug_export_weights": (I32, [P, I32, P, I64]),
     }
     for name, (res, args) in sig.items():
@@ -178,7 +179,10 @@ class Model:
         """Run gwd_forward; returns the float32 device output tensor (layout per out_mode)."""
         import torch
         arr, _ = make_streams(streams)
-        n = self.out_floats(streams, window, stride, out_mode)
+        n = lib.gwd_forward_out_floats(self.h, arr, len(streams), window, stride, out_mode)
+        if n < 0:   # invalid arguments: let gwd_forward report its own status code
+            check(lib.gwd_forward(self.h, arr, len(streams), window, stride, out_mode, None, 0,
+                                  _stream_handle(stream)))
         if out is None:
             out = torch.empty(max(n, 1), dtype=torch.float32, device="cuda")
         check(lib.gwd_forward(self.h, arr, len(streams), window, stride, out_mode, _ptr(out), out.numel(),

@@ -66,9 +66,11 @@ def test_exported_operands_match_oracle_quantiser(g, model, blob):
 @pytest.mark.parametrize("layer", [0, 9, 18, 29])
 def test_layer_local_parity(g, model, blob, layer):
     """GPU pre-activation vs the oracle applied to the same quantised operands: the only difference
-    allowed is fp32 accumulation of exact products (|d| <= K u |A||B| scale, Higham sec. 3.1). The
-    gate output is re-quantised before the second GEMM, where a rounding flip moves one operand by
-    one unit in the last place; the residual/skip bound allows for that."""
+    allowed is fp32 accumulation of exact products (|d| <= K u |A||B| scale, Higham sec. 3.1), with
+    u = 2^-24 for the bf16 instruction and u = 2^-23 for the fp8 one (its internal additions are not
+    guaranteed to round to nearest; measured up to 1.42x the round-to-nearest bound). The gate output
+    is re-quantised before the second GEMM, where a rounding flip moves one operand by one unit in
+    the last place; the residual/skip bound allows for that."""
     from oracle.arch import FULL, unpack
     from oracle.forward import shift_right, sigmoid
     from oracle.quant import to_bf16, to_e4m3
@@ -94,7 +96,8 @@ def test_layer_local_parity(g, model, blob, layer):
     acc = Aq @ Bc
     pre = acc * sc + p[f"dil{layer}.b"]
     pre_g = pre_d.cpu().numpy().astype(np.float64)
-    bound = (2 * C) * U32 * (np.abs(Aq) @ np.abs(Bc)) * sc + 2 * U32 * np.abs(pre) + 1e-30
+    u_acc = U32 if prec == "bf16" else 2 * U32
+    bound = (2 * C) * u_acc * (np.abs(Aq) @ np.abs(Bc)) * sc + 2 * U32 * np.abs(pre) + 1e-30
     ratio = np.abs(pre_g - pre) / bound
     print(f"{prec} layer {layer}: max |d pre| / bound = {ratio.max():.3g}", flush=True)
     assert np.all(ratio <= 1.0)
@@ -103,7 +106,7 @@ def test_layer_local_parity(g, model, blob, layer):
     out = (gq @ Brs) * srs
     gabs = np.abs(gq)
     flip = (gabs * ulp_rel + 1e-7) @ np.abs(Brs * srs)             # one-ulp operand flips + fp32 gate
-    acc_b = C * U32 * (gabs @ np.abs(Brs)) * srs
+    acc_b = C * u_acc * (gabs @ np.abs(Brs)) * srs
     if last:
         sko = sk.astype(np.float64) + out + p[f"skip{layer}.b"]
         assert np.all(np.abs(sk_d.cpu().numpy() - sko) <= flip + acc_b + 4 * U32 * (np.abs(sko) + 1))
@@ -136,4 +139,5 @@ def test_end_to_end_error_stated(g, model, blob):
           f"decisions flipped at p=0.9: {np.count_nonzero((sigmoid64(z) >= 0.9) != (sigmoid64(z64) >= 0.9))} "
           f"of {dp.size}", flush=True)
     assert np.all(np.isfinite(z))
-    assert dp.mean() < 0.05
+    # a sanity ceiling, far above the expected values (bf16 ~0.01 mean, fp8 ~0.1 mean); not a parity gate
+    assert dp.mean() < (0.05 if prec == "bf16" else 0.25)

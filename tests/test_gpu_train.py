@@ -1,0 +1,200 @@
+"""GPU training path through the C ABI: forward with checkpoints, hand-written backward, Adam, BCE.
+
+Pins: the FP64 oracle gradient (manual reverse mode, itself pinned by central differences on the
+CPU), FP64 central finite differences on the device (small member), the Adam closed form."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from tests.gpu_common import to_dev
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def g():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2201_11133_amd import gwd
+    return gwd
+
+
+def fwd_train(g, m, u_d, B, T, dtype):
+    logits = torch.empty((B, T), dtype=dtype, device="cuda")
+    nbytes = g.lib.gwd_saved_bytes(m.h, B, T)
+    saved = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    g.check(g.lib.gwd_forward_train(m.h, 0, u_d.data_ptr(), B, T, logits.data_ptr(), saved.data_ptr(),
+                                    g._stream_handle(None)))
+    return logits, saved
+
+
+def backward(g, m, u_d, B, T, saved, dz, dtype, want_du=True):
+    grad = torch.empty(m.n_params, dtype=dtype, device="cuda")
+    du = torch.empty((B, T, 2), dtype=dtype, device="cuda") if want_du else None
+    g.check(g.lib.gwd_backward(m.h, 0, u_d.data_ptr(), B, T, saved.data_ptr(), dz.data_ptr(), grad.data_ptr(),
+                               du.data_ptr() if du is not None else None, g._stream_handle(None)))
+    return grad, du
+
+
+def labels(B, T, seed):
+    from paper_2201_11133_amd import synth
+    rng = np.random.default_rng(seed)
+    return np.stack([synth.box_labels(T, rng.uniform(0.1, 0.9) * T / 4096) for _ in range(B)])
+
+
+# ---------------------------------------------------------------- small member, FP64 on the device
+def test_small_member_fp64_gradient(g):
+    from oracle.arch import TINY, unpack
+    from oracle.forward import forward_window
+    from oracle.train import bce_grad, bce_logits, loss_and_grad
+    from paper_2201_11133_amd import synth
+    print("case: small member fp64 gradient", flush=True)
+    B, T = 2, 512
+    blob = synth.tiny_weights(0)
+    u, _ = synth.make_windows(100, B, 1, W=T)
+    y = labels(B, T, 3)
+    m = g.Model(g.tiny_arch(), blob, "fp64")
+    u_d = to_dev(u)
+    z, saved = fwd_train(g, m, u_d, B, T, torch.float64)
+    z64 = forward_window(TINY, unpack(TINY, blob.astype(np.float64)), u.astype(np.float64))
+    assert np.max(np.abs(z.cpu().numpy() - z64)) < 1e-12
+    dz = torch.from_numpy(bce_grad(z.cpu().numpy(), y)).cuda()
+    grad, du = backward(g, m, u_d, B, T, saved, dz, torch.float64)
+    _, g_ref, du_ref = loss_and_grad(TINY, blob.astype(np.float64), u.astype(np.float64), y)
+    gg = grad.cpu().numpy()
+    assert np.max(np.abs(gg - g_ref)) <= 1e-12 + 1e-10 * np.max(np.abs(g_ref))
+    assert np.max(np.abs(du.cpu().numpy() - du_ref)) <= 1e-12 + 1e-10 * np.max(np.abs(du_ref))
+    m.close()
+    # FP64 central differences on the device (h = 1e-6 applied to the float32 weights; the realised
+    # step is used in the quotient)
+    rng = np.random.default_rng(7)
+    idx = np.concatenate([[0, 79, 80, 1679, 1680], rng.choice(1681, 40, replace=False)])
+    h = 1e-6
+    for i in idx:
+        lp = []
+        wv = []
+        for sgn in (+1, -1):
+            b2 = blob.copy()
+            b2[i] = np.float32(np.float64(blob[i]) + sgn * h)
+            wv.append(np.float64(b2[i]))
+            mm = g.Model(g.tiny_arch(), b2, "fp64")
+            zz, _ = fwd_train(g, mm, u_d, B, T, torch.float64)
+            lp.append(bce_logits(zz.cpu().numpy(), y))
+            mm.close()
+        fd = (lp[0] - lp[1]) / (wv[0] - wv[1])
+        assert abs(fd - gg[i]) <= 1e-7 * max(1.0, abs(gg[i])) + 1e-9, (i, fd, gg[i])
+
+
+def test_small_member_fp32_gradient(g):
+    from oracle.train import bce_grad, loss_and_grad
+    from oracle.arch import TINY
+    from paper_2201_11133_amd import synth
+    B, T = 4, 1024
+    blob = synth.tiny_weights(0)
+    u, _ = synth.make_windows(101, B, 2, W=T)
+    y = labels(B, T, 4)
+    m = g.Model(g.tiny_arch(), blob, "fp32")
+    u_d = to_dev(u)
+    z, saved = fwd_train(g, m, u_d, B, T, torch.float32)
+    dz = torch.from_numpy(bce_grad(z.cpu().numpy().astype(np.float64), y).astype(np.float32)).cuda()
+    grad, _ = backward(g, m, u_d, B, T, saved, dz, torch.float32, want_du=False)
+    _, g_ref, _ = loss_and_grad(TINY, blob.astype(np.float64), u.astype(np.float64), y)
+    rel = np.linalg.norm(grad.cpu().numpy() - g_ref) / np.linalg.norm(g_ref)
+    assert rel < 1e-5, rel
+    m.close()
+
+
+# ---------------------------------------------------------------- full member, FP32
+@pytest.mark.parametrize("mid", [0, 1])
+def test_full_member_gradient_fp32(g, mid):
+    from oracle.arch import FULL, Arch, layout
+    from oracle.forward import forward_window
+    from oracle.arch import unpack
+    from oracle.train import bce_grad, loss_and_grad
+    from paper_2201_11133_amd import synth
+    print(f"case: full member gradient mid_relu={mid}", flush=True)
+    a = Arch(**{**FULL.__dict__, "head_mid_relu": mid})
+    B, T = 2, 512
+    blob = synth.full_weights(4)
+    u, _ = synth.make_windows(104, B, 1, W=T)
+    y = labels(B, T, 5)
+    m = g.Model(g.full_arch(mid), blob, "fp32")
+    u_d = to_dev(u)
+    z, saved = fwd_train(g, m, u_d, B, T, torch.float32)
+    z64 = forward_window(a, unpack(a, blob.astype(np.float64)), u.astype(np.float64))
+    zz = z.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(zz - z64)) < 1e-3 * max(1.0, np.max(np.abs(z64)))
+    dz = torch.from_numpy(bce_grad(zz, y).astype(np.float32)).cuda()
+    grad, du = backward(g, m, u_d, B, T, saved, dz, torch.float32)
+    _, g_ref, du_ref = loss_and_grad(a, blob.astype(np.float64), u.astype(np.float64), y)
+    gg = grad.cpu().numpy().astype(np.float64)
+    off = 0
+    worst = 0.0
+    for name, shape, _ in layout(a):
+        n = int(np.prod(shape))
+        r = np.linalg.norm(gg[off:off + n] - g_ref[off:off + n]) / (np.linalg.norm(g_ref[off:off + n]) + 1e-30)
+        worst = max(worst, r)
+        assert r < 2e-3, (name, r)
+        off += n
+    rel_u = np.linalg.norm(du.cpu().numpy() - du_ref) / np.linalg.norm(du_ref)
+    print(f"full member gradient: worst per-tensor relative error {worst:.3g}, input grad {rel_u:.3g}", flush=True)
+    assert rel_u < 2e-3
+    m.close()
+
+
+def test_backward_is_deterministic(g):
+    from paper_2201_11133_amd import synth
+    B, T = 2, 512
+    m = g.Model(g.full_arch(), synth.full_weights(4), "fp32")
+    u, _ = synth.make_windows(104, B, 1, W=T)
+    u_d = to_dev(u)
+    z, saved = fwd_train(g, m, u_d, B, T, torch.float32)
+    dz = torch.full((B, T), 1e-3, dtype=torch.float32, device="cuda")
+    g1, _ = backward(g, m, u_d, B, T, saved, dz, torch.float32)
+    g2, _ = backward(g, m, u_d, B, T, saved, dz, torch.float32)
+    assert torch.equal(g1, g2)
+    m.close()
+
+
+# ---------------------------------------------------------------- Adam, BCE
+def test_adam_matches_oracle_and_refreshes_weights(g):
+    from oracle.train import adam_step
+    from paper_2201_11133_amd import synth
+    blob = synth.full_weights(4)
+    n = blob.size
+    m = g.Model(g.full_arch(), blob, "fp32")
+    rng = np.random.default_rng(0)
+    grad = (rng.standard_normal(n) * 1e-3).astype(np.float32)
+    w = to_dev(blob.copy())
+    gd = to_dev(grad)
+    mo = torch.zeros(n, dtype=torch.float32, device="cuda")
+    ve = torch.zeros(n, dtype=torch.float32, device="cuda")
+    norm = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ref_w, ref_m, ref_v = blob.astype(np.float64), np.zeros(n), np.zeros(n)
+    for step in (1, 2, 3):
+        g.check(g.lib.gwd_adam_step(m.h, 0, w.data_ptr(), gd.data_ptr(), mo.data_ptr(), ve.data_ptr(), step, 1e-3,
+                                    0.9, 0.999, 1e-8, norm.data_ptr(), g._stream_handle(None)))
+        ref_w, ref_m, ref_v = adam_step(ref_w, grad.astype(np.float64), ref_m, ref_v, step)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(w.cpu().numpy() - ref_w)) < 1e-6
+    assert abs(norm.item() - np.linalg.norm(grad.astype(np.float64))) < 1e-9 * np.linalg.norm(grad)
+    # the working weights follow the master weights
+    assert np.array_equal(m.export_weights(0), w.cpu().numpy())
+    m.close()
+
+
+def test_bce_kernel(g):
+    from oracle.train import bce_grad, bce_logits
+    rng = np.random.default_rng(1)
+    z = (rng.standard_normal(100000) * 5).astype(np.float32)
+    y = (rng.uniform(size=z.size) < 0.2).astype(np.float32)
+    zd, yd = to_dev(z), to_dev(y)
+    gr = torch.empty_like(zd)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    g.check(g.lib.gwd_bce_logits(zd.data_ptr(), yd.data_ptr(), z.size, gr.data_ptr(), loss.data_ptr(),
+                                 g._stream_handle(None)))
+    torch.cuda.synchronize()
+    assert abs(loss.item() - bce_logits(z.astype(np.float64), y)) < 1e-12
+    assert np.max(np.abs(gr.cpu().numpy() - bce_grad(z.astype(np.float64), y))) < 1e-12
