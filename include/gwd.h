@@ -160,7 +160,8 @@ void gwd_free(gwd_model* model);
  *   1: as 0, followed by each member's stitched logits:   [sum L] + [M][sum L]
  *   2: every member's full per-window logits:             [M][sum n_win][window]
  * out_capacity_floats must be >= gwd_forward_out_floats(...).
- * Requirements: 1 <= n_streams <= 65536, window a multiple of 64 and
+ * Requirements: 1 <= n_streams <= 65536, window a multiple of 128 (256 for
+ * the plain member) and
  * >= receptive field (else GWD_ERR_SHAPE), 0 < stride <= window,
  * window - stride >= receptive field - 1 (so owner positions never see the
  * zero left context of a later window, else GWD_ERR_SHAPE), stream pointers
@@ -211,7 +212,7 @@ gwd_status gwd_triggers(const float* ens_logit, const int64_t* stream_offsets, i
  * The gated member's forward uses the model's precision (FP32 or BF16
  * kernels); its backward runs in fp32 against the fp32 master weights. FP8
  * models are inference only (GWD_ERR_UNSUPPORTED). The gated member needs W a
- * multiple of 64. Calls with one model must not overlap (shared workspace). */
+ * multiple of 128. Calls with one model must not overlap (shared workspace). */
 int64_t gwd_saved_bytes(const gwd_model* model, int32_t B, int32_t W);
 gwd_status gwd_forward_train(gwd_model* model, int32_t member, const float* windows, int32_t B, int32_t W,
                              void* logits, void* saved, void* hip_stream);

@@ -174,7 +174,7 @@ static gwd_status check_forward(const gwd_model* m, const gwd_stream* streams, i
     if (out_mode < 0 || out_mode > 2) { set_error("gwd_forward: out_mode %d not in {0,1,2}", out_mode); return GWD_ERR_ARG; }
     if (stride <= 0 || stride > window) { set_error("gwd_forward: stride %d not in (0, window]", stride); return GWD_ERR_ARG; }
     const int64_t rf = rf_of(&m->arch);
-    const int tile = m->arch.kind == 0 ? 256 : kBM;
+    const int tile = m->arch.kind == 0 ? 256 : 128;   // tile heights of the plain and gated kernels
     if (window <= 0 || window % tile != 0) { set_error("gwd_forward: window %d must be a positive multiple of %d", window, tile); return GWD_ERR_SHAPE; }
     if (window < rf) { set_error("gwd_forward: window %d shorter than the receptive field %lld", window, (long long)rf); return GWD_ERR_SHAPE; }
     if ((int64_t)(window - stride) < rf - 1) { set_error("gwd_forward: window - stride = %d < receptive field - 1 = %lld", window - stride, (long long)(rf - 1)); return GWD_ERR_SHAPE; }
@@ -333,7 +333,7 @@ gwd_status gwd_debug_layer(gwd_model* m, int32_t member, int32_t layer, const fl
     const int L = m->arch.n_stacks * m->arch.layers_per_stack;
     if (member < 0 || member >= m->n_members) { set_error("gwd_debug_layer: member %d out of range", member); return GWD_ERR_ARG; }
     if (layer < 0 || layer >= L) { set_error("gwd_debug_layer: layer %d out of range", layer); return GWD_ERR_ARG; }
-    if (n_windows < 1 || window < kBM || window % kBM) { set_error("gwd_debug_layer: bad shape"); return GWD_ERR_SHAPE; }
+    if (n_windows < 1 || window < 128 || window % 128) { set_error("gwd_debug_layer: window must be a positive multiple of 128"); return GWD_ERR_SHAPE; }
     if (!x_in || !skip || (layer < L - 1 && !x_out)) { set_error("gwd_debug_layer: NULL buffer"); return GWD_ERR_ARG; }
     hipError_t e = hipSetDevice(m->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");

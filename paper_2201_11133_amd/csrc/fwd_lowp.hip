@@ -7,7 +7,9 @@
 //   FP8:  v_mfma_scale_f32_32x32x64_f8f6f4 with E4M3 (OCP) operands and unit block scales;
 //         activations use a unit scale (saturated to +/-448), weights one scale per output column
 //         (max |w| / 448), applied to the fp32 accumulator in the epilogue.
-// The residual stream x and the skip sum stay fp32 in memory.
+// The residual stream x is stored in bf16 between layers (the operand format of this path; the
+// paper's half-precision engine likewise keeps its activations in half precision); the skip sum
+// stays fp32.
 //
 // Tile: 128 time steps of one window, 8 waves. Wave w owns rows [32 (w/2), +32) and the column
 // pairs (filter 64 (w%2) + 32 c + [0,32), gate 128 + same) for c = 0, 1, so the gate of a channel
@@ -24,8 +26,8 @@ typedef int intx8 __attribute__((ext_vector_type(8)));
 constexpr int LP_BM = 128;
 
 struct LayerArgsLP {
-    const float* x_in;
-    float* x_out;
+    const uint16_t* x_in;  // residual stream, bf16 [rows][128]
+    uint16_t* x_out;
     float* skip;
     float* pre_out;
     const uint8_t* wc;   // packed conv operands
@@ -49,6 +51,7 @@ __device__ inline uint16_t to_bf16_bits(float f) {
     u += 0x7fffu + ((u >> 16) & 1u);
     return (uint16_t)(u >> 16);
 }
+__device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // fp32 -> E4M3 (OCP) code, round to nearest even, saturated to +/-448 (hardware conversion).
 __device__ inline uint32_t to_e4m3_pair(float a, float b) {
@@ -62,29 +65,14 @@ struct LP {
     static constexpr int EB = FP8 ? 1 : 2;          // bytes per operand element
     static constexpr int KSTEP = FP8 ? 64 : 16;     // k per MFMA
     static constexpr int FRAG = KSTEP / 2 * EB;     // bytes per lane per fragment (16 or 32)
-    static constexpr int ROW = 2 * kC * EB + 16;    // padded LDS row (bytes)
+    static constexpr int ROW = 2 * kC * EB + 16;    // padded LDS operand row (bytes)
+    static constexpr int XROW = kC * 2 + 16;        // padded LDS row of the bf16 residual copy (FP8 only)
+    static constexpr int NK1 = 2 * kC / KSTEP;      // MFMA steps of phase 1 (16 / 4)
+    static constexpr int NK2 = kC / KSTEP;          // MFMA steps of phase 2 (8 / 2)
+    static constexpr int PF1 = FP8 ? 4 : 8;         // weight-fragment prefetch depth, phase 1
+    static constexpr int PF2 = FP8 ? 2 : 4;         // and phase 2
+    static constexpr int LDS = LP_BM * ROW + (FP8 ? LP_BM * XROW : 0);
 };
-
-// Store 4 fp32 values as operands at LDS byte address p.
-template <bool FP8>
-__device__ inline void store4(uint8_t* p, float4 v) {
-    if (FP8) {
-        const uint32_t lo = to_e4m3_pair(v.x, v.y), hi = to_e4m3_pair(v.z, v.w);
-        *(uint32_t*)p = lo | (hi << 16);
-    } else {
-        uint2 w;
-        w.x = (uint32_t)to_bf16_bits(v.x) | ((uint32_t)to_bf16_bits(v.y) << 16);
-        w.y = (uint32_t)to_bf16_bits(v.z) | ((uint32_t)to_bf16_bits(v.w) << 16);
-        *(uint2*)p = w;
-    }
-}
-
-template <bool FP8>
-__device__ inline void store1(uint8_t* p, float v);
-template <>
-__device__ inline void store1<false>(uint8_t* p, float v) { *(uint16_t*)p = to_bf16_bits(v); }
-template <>
-__device__ inline void store1<true>(uint8_t* p, float v) { *p = (uint8_t)(to_e4m3_pair(v, 0.f) & 0xffu); }
 
 template <bool FP8>
 struct Frag {
@@ -116,10 +104,21 @@ __device__ inline floatx16 mma(const Frag<FP8>& a, const Frag<FP8>& b, floatx16 
     }
 }
 
+// Eight bf16 values (16 bytes) -> eight E4M3 codes (8 bytes).
+__device__ inline uint2 bf16x8_to_e4m3(uint4 v) {
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+    uint32_t o[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) o[i] = to_e4m3_pair(bf16_to_f32((uint16_t)(w[i] & 0xffff)), bf16_to_f32((uint16_t)(w[i] >> 16)));
+    return make_uint2(o[0] | (o[1] << 16), o[2] | (o[3] << 16));
+}
+
 template <bool FP8, bool FROM_STREAM, bool SKIP_INIT, bool LAST>
 __global__ __launch_bounds__(512, 1) void layer_lp_kernel(LayerArgsLP p) {
     using T = LP<FP8>;
-    __shared__ __attribute__((aligned(16))) uint8_t A[LP_BM * T::ROW];
+    __shared__ __attribute__((aligned(16))) uint8_t lds[T::LDS];
+    uint8_t* A = lds;                     // operand tile [128][x[t-d] | x[t]]; g overwrites the first half
+    uint8_t* XR = lds + LP_BM * T::ROW;   // FP8: bf16 copy of x[t] (the residual base)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, r = lane & 31;
     const int rb = wave >> 1, half = wave & 1;
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
@@ -127,78 +126,105 @@ __global__ __launch_bounds__(512, 1) void layer_lp_kernel(LayerArgsLP p) {
     const int t0 = (tile - b * p.tiles_per_window) * LP_BM;
     const int64_t row0 = (int64_t)b * p.T + t0;
 
-    // stream position of this window (first layer only)
-    StreamDesc sd{};
-    int64_t start = 0;
-    if (FROM_STREAM) {
-        const int64_t gw = p.win_base + b;
-        sd = p.streams[find_stream(p.streams, p.n_streams, gw)];
-        start = (gw - sd.win_begin) * p.S;
-    }
-    auto x0_at = [&](int t, int c) -> float4 {  // input projection W_in u[t] + b_in, channels c..c+3
-        float u0 = 0.f, u1 = 0.f;
-        const int64_t smp = start + t;
-        if (smp < sd.length) {
-            u0 = sd.ch0[smp * sd.stride];
-            u1 = sd.ch1[smp * sd.stride];
+    // ---- stage A = [x[t-d] | x[t]]: 128 rows x 2 taps x 16 chunks of 8 channels, 8 chunks per thread
+    {
+        StreamDesc sd{};
+        int64_t start = 0;
+        if (FROM_STREAM) {
+            const int64_t gw = p.win_base + b;
+            sd = p.streams[find_stream(p.streams, p.n_streams, gw)];
+            start = (gw - sd.win_begin) * p.S;
         }
-        float4 v;
-        v.x = p.b_in[c + 0] + p.w_in[2 * c + 0] * u0 + p.w_in[2 * c + 1] * u1;
-        v.y = p.b_in[c + 1] + p.w_in[2 * c + 2] * u0 + p.w_in[2 * c + 3] * u1;
-        v.z = p.b_in[c + 2] + p.w_in[2 * c + 4] * u0 + p.w_in[2 * c + 5] * u1;
-        v.w = p.b_in[c + 3] + p.w_in[2 * c + 6] * u0 + p.w_in[2 * c + 7] * u1;
-        return v;
-    };
-
-    // ---- stage A = [x[t-d] | x[t]] as operands
-    for (int idx = tid; idx < LP_BM * 64; idx += 512) {
-        const int rr = idx >> 6, qq = idx & 63, tap = qq >> 5, c = 4 * (qq & 31);
-        const int t = t0 + rr - (tap == 0 ? p.d : 0);
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (t >= 0) {
-            if (FROM_STREAM) v = x0_at(t, c);
-            else v = *(const float4*)&p.x_in[((int64_t)b * p.T + t) * kC + c];
+        uint4 v[8];
+#pragma unroll
+        for (int it = 0; it < 8; ++it) {
+            const int idx = tid + 512 * it;
+            const int rr = idx >> 5, q = idx & 31, tap = q >> 4, c8 = 8 * (q & 15);
+            const int t = t0 + rr - (tap == 0 ? p.d : 0);
+            v[it] = make_uint4(0, 0, 0, 0);
+            if (t >= 0) {
+                if (FROM_STREAM) {  // input projection x0 = W_in u[t] + b_in, rounded to bf16
+                    float u0 = 0.f, u1 = 0.f;
+                    const int64_t smp = start + t;
+                    if (smp < sd.length) {
+                        u0 = sd.ch0[smp * sd.stride];
+                        u1 = sd.ch1[smp * sd.stride];
+                    }
+                    uint32_t w[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int c = c8 + 2 * e;
+                        const float x0 = p.b_in[c] + p.w_in[2 * c] * u0 + p.w_in[2 * c + 1] * u1;
+                        const float x1 = p.b_in[c + 1] + p.w_in[2 * c + 2] * u0 + p.w_in[2 * c + 3] * u1;
+                        w[e] = (uint32_t)to_bf16_bits(x0) | ((uint32_t)to_bf16_bits(x1) << 16);
+                    }
+                    v[it] = make_uint4(w[0], w[1], w[2], w[3]);
+                } else {
+                    v[it] = *(const uint4*)&p.x_in[((int64_t)b * p.T + t) * kC + c8];
+                }
+            }
         }
-        store4<FP8>(&A[rr * T::ROW + (tap * kC + c) * T::EB], v);
+#pragma unroll
+        for (int it = 0; it < 8; ++it) {
+            const int idx = tid + 512 * it;
+            const int rr = idx >> 5, q = idx & 31, tap = q >> 4, c8 = 8 * (q & 15);
+            if (FP8) {
+                *(uint2*)&A[rr * T::ROW + tap * kC + c8] = bf16x8_to_e4m3(v[it]);
+                if (tap == 1) *(uint4*)&XR[rr * T::XROW + 2 * c8] = v[it];
+            } else {
+                *(uint4*)&A[rr * T::ROW + 2 * (tap * kC + c8)] = v[it];
+            }
+        }
     }
     __syncthreads();
 
-    // ---- phase 1: pre = A Bc, K = 256
-    constexpr int NK1 = 2 * kC / T::KSTEP;
+    // ---- phase 1: pre = A Bc, K = 256, weight fragments from a register ring PF1 steps deep
     floatx16 af[2] = {}, ag[2] = {};
+    const uint8_t* Ar = &A[(32 * rb + r) * T::ROW + h * T::FRAG];
     {
-        const uint8_t* Ar = &A[(32 * rb + r) * T::ROW + h * T::FRAG];
-        const uint8_t* Bf[2];
-        const uint8_t* Bg[2];
+        const uint8_t* Bp[4];
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-            Bf[c] = p.wc + ((size_t)((2 * half + c) * NK1) * 64 + lane) * T::FRAG;
-            Bg[c] = p.wc + ((size_t)((4 + 2 * half + c) * NK1) * 64 + lane) * T::FRAG;
+            Bp[c] = p.wc + ((size_t)((2 * half + c) * T::NK1) * 64 + lane) * T::FRAG;          // filter
+            Bp[2 + c] = p.wc + ((size_t)((4 + 2 * half + c) * T::NK1) * 64 + lane) * T::FRAG;  // gate
         }
-        Frag<FP8> nf[2], ng[2];
+        Frag<FP8> ring[T::PF1][4];
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            nf[c] = load_frag<FP8>(Bf[c]);
-            ng[c] = load_frag<FP8>(Bg[c]);
-        }
+        for (int j = 0; j < T::PF1; ++j)
 #pragma unroll
-        for (int j = 0; j < NK1; ++j) {
-            Frag<FP8> f[2] = {nf[0], nf[1]}, g[2] = {ng[0], ng[1]};
-            if (j + 1 < NK1) {
+            for (int q = 0; q < 4; ++q) ring[j][q] = load_frag<FP8>(Bp[q] + (size_t)j * 64 * T::FRAG);
 #pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    nf[c] = load_frag<FP8>(Bf[c] + (size_t)(j + 1) * 64 * T::FRAG);
-                    ng[c] = load_frag<FP8>(Bg[c] + (size_t)(j + 1) * 64 * T::FRAG);
-                }
+        for (int j = 0; j < T::NK1; ++j) {
+            const int slot = j % T::PF1;
+            Frag<FP8> cur[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) cur[q] = ring[slot][q];
+            if (j + T::PF1 < T::NK1) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) ring[slot][q] = load_frag<FP8>(Bp[q] + (size_t)(j + T::PF1) * 64 * T::FRAG);
             }
             const Frag<FP8> a = load_frag<FP8>(Ar + j * T::KSTEP * T::EB);
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                af[c] = mma<FP8>(a, f[c], af[c]);
-                ag[c] = mma<FP8>(a, g[c], ag[c]);
+                af[c] = mma<FP8>(a, cur[c], af[c]);
+                ag[c] = mma<FP8>(a, cur[2 + c], ag[c]);
             }
         }
     }
+    // phase-2 weight fragments: start loading now (their latency overlaps the gate)
+    const int nq2 = LAST ? 2 : 4;
+    const uint8_t* Bq[4];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        Bq[c] = p.wrs + ((size_t)((2 * half + c) * T::NK2) * 64 + lane) * T::FRAG;          // res (skip if last)
+        Bq[2 + c] = p.wrs + ((size_t)((4 + 2 * half + c) * T::NK2) * 64 + lane) * T::FRAG;  // skip
+    }
+    Frag<FP8> ring2[T::PF2][4];
+#pragma unroll
+    for (int j = 0; j < T::PF2; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (q < nq2) ring2[j][q] = load_frag<FP8>(Bq[q] + (size_t)j * 64 * T::FRAG);
     __syncthreads();  // all reads of the x[t-d] half are done before g overwrites it
 
     // ---- gate -> g operands in LDS columns [0, 128)
@@ -217,40 +243,47 @@ __global__ __launch_bounds__(512, 1) void layer_lp_kernel(LayerArgsLP p) {
                 po[n] = vf;
                 po[kC + n] = vg;
             }
-            store1<FP8>(&A[m * T::ROW + n * T::EB], gate_f32(vf, vg));
+            const float gv = gate_f32(vf, vg);
+            if (FP8) A[m * T::ROW + n] = (uint8_t)(to_e4m3_pair(gv, 0.f) & 0xffu);
+            else *(uint16_t*)&A[m * T::ROW + 2 * n] = to_bf16_bits(gv);
         }
+    }
+    // skip values this lane updates: load them before the barrier so the latency overlaps phase 2
+    float skv[2][16];
+    if (!SKIP_INIT) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int m = 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
+                skv[c][i] = p.skip[(row0 + m) * kC + 64 * half + 32 * c + r];
+            }
     }
     __syncthreads();
 
     // ---- phase 2: [res | skip] = g Brs, K = 128
-    constexpr int NK2 = kC / T::KSTEP;
     floatx16 ar[2] = {}, as[2] = {};
-    {
-        const uint8_t* Ar = &A[(32 * rb + r) * T::ROW + h * T::FRAG];
-        // column blocks: res 2 half + c, skip 4 + 2 half + c (last layer: skip only, 2 half + c)
-        const uint8_t* Br[2];
-        const uint8_t* Bs[2];
+#pragma unroll
+    for (int j = 0; j < T::NK2; ++j) {
+        const int slot = j % T::PF2;
+        Frag<FP8> cur[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (q < nq2) cur[q] = ring2[slot][q];
+        if (j + T::PF2 < T::NK2) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (q < nq2) ring2[slot][q] = load_frag<FP8>(Bq[q] + (size_t)(j + T::PF2) * 64 * T::FRAG);
+        }
+        const Frag<FP8> a = load_frag<FP8>(Ar + j * T::KSTEP * T::EB);
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-            Br[c] = p.wrs + ((size_t)((2 * half + c) * NK2) * 64 + lane) * T::FRAG;
-            Bs[c] = p.wrs + ((size_t)((4 + 2 * half + c) * NK2) * 64 + lane) * T::FRAG;
-        }
-#pragma unroll
-        for (int j = 0; j < NK2; ++j) {
-            const Frag<FP8> a = load_frag<FP8>(Ar + j * T::KSTEP * T::EB);
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                const Frag<FP8> fr = load_frag<FP8>(Br[c] + (size_t)j * 64 * T::FRAG);
-                ar[c] = mma<FP8>(a, fr, ar[c]);
-                if (!LAST) {
-                    const Frag<FP8> fs = load_frag<FP8>(Bs[c] + (size_t)j * 64 * T::FRAG);
-                    as[c] = mma<FP8>(a, fs, as[c]);
-                }
-            }
+            ar[c] = mma<FP8>(a, cur[c], ar[c]);
+            if (!LAST) as[c] = mma<FP8>(a, cur[2 + c], as[c]);
         }
     }
 
-    // ---- epilogue: x_out = x + res + b_r, skip (+)= s + b_s   (last layer: skip only, from ar)
+    // ---- epilogue: x_out = bf16(x + res + b_r) (x from the LDS tile), skip (+)= s + b_s
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         const int n = 64 * half + 32 * c + r;
@@ -263,15 +296,10 @@ __global__ __launch_bounds__(512, 1) void layer_lp_kernel(LayerArgsLP p) {
                 const int64_t o = (row0 + m) * kC + n;
                 const float rv = FP8 ? fmaf(ar[c][i], s_r, br) : ar[c][i] + br;
                 const float sv = FP8 ? fmaf(as[c][i], s_s, bs) : as[c][i] + bs;
-                float xv;
-                if (FROM_STREAM) {
-                    const float4 x4 = x0_at(t0 + m, n & ~3);
-                    xv = (n & 3) == 0 ? x4.x : (n & 3) == 1 ? x4.y : (n & 3) == 2 ? x4.z : x4.w;
-                } else {
-                    xv = p.x_in[o];
-                }
-                p.x_out[o] = xv + rv;
-                p.skip[o] = SKIP_INIT ? sv : p.skip[o] + sv;
+                const uint16_t xb = FP8 ? *(const uint16_t*)&XR[m * T::XROW + 2 * n]
+                                        : *(const uint16_t*)&A[m * T::ROW + 2 * (kC + n)];
+                p.x_out[o] = to_bf16_bits(bf16_to_f32(xb) + rv);
+                p.skip[o] = SKIP_INIT ? sv : skv[c][i] + sv;
             }
         } else {
             const float bs = p.brs[n];
@@ -281,7 +309,7 @@ __global__ __launch_bounds__(512, 1) void layer_lp_kernel(LayerArgsLP p) {
                 const int m = 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
                 const int64_t o = (row0 + m) * kC + n;
                 const float sv = FP8 ? fmaf(ar[c][i], s_s, bs) : ar[c][i] + bs;
-                p.skip[o] = SKIP_INIT ? sv : p.skip[o] + sv;
+                p.skip[o] = SKIP_INIT ? sv : skv[c][i] + sv;
             }
         }
     }
@@ -317,8 +345,9 @@ static hipError_t layers_lp(gwd_model* m, const FwdBatch& fb, float* x_a, float*
     const int L = m->arch.n_stacks * m->arch.layers_per_stack;
     const int tpw = fb.T / LP_BM;
     const int nblocks = fb.nb * tpw;
-    float* xin = x_a;
-    float* xout = x_b;
+    // the residual stream is bf16 here: the fp32 workspace buffers hold it with room to spare
+    uint16_t* xin = (uint16_t*)x_a;
+    uint16_t* xout = (uint16_t*)x_b;
     for (int l = 0; l < L; ++l) {
         LayerArgsLP a = lp_args<FP8>(m, fb.member, l);
         a.x_in = xin;
@@ -336,27 +365,48 @@ static hipError_t layers_lp(gwd_model* m, const FwdBatch& fb, float* x_a, float*
         else if (l < L - 1) e = launch_lp<FP8, false, false, false>(a, nblocks, st);
         else e = launch_lp<FP8, false, false, true>(a, nblocks, st);
         if (e != hipSuccess) return e;
-        float* t = xin; xin = xout; xout = t;
+        uint16_t* t = xin; xin = xout; xout = t;
     }
     return hipSuccess;
 }
 
+__global__ __launch_bounds__(256) void f32_to_bf16_kernel(const float* x, int64_t n, uint16_t* y) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) y[i] = to_bf16_bits(x[i]);
+}
+__global__ __launch_bounds__(256) void bf16_to_f32_kernel(const uint16_t* x, int64_t n, float* y) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) y[i] = bf16_to_f32(x[i]);
+}
+
+// One layer on caller-provided fp32 activations (test support and the training forward): the input
+// is rounded to bf16 (the residual format of this path) and the output widened back to fp32.
 template <bool FP8>
 static hipError_t debug_lp(gwd_model* m, int member, int l, const float* x_in, int nb, int T, float* pre_out,
                            float* x_out, float* skip, hipStream_t st) {
     const int L = m->arch.n_stacks * m->arch.layers_per_stack;
+    const int64_t n = (int64_t)nb * T * kC;
+    uint16_t* tmp = nullptr;
+    hipError_t e = hipMallocAsync((void**)&tmp, 2 * n * sizeof(uint16_t), st);
+    if (e != hipSuccess) return e;
+    const unsigned nblk = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(f32_to_bf16_kernel, dim3(nblk), dim3(256), 0, st, x_in, n, tmp);
     LayerArgsLP a = lp_args<FP8>(m, member, l);
-    a.x_in = x_in;
-    a.x_out = x_out;
+    a.x_in = tmp;
+    a.x_out = tmp + n;
     a.skip = skip;
     a.pre_out = pre_out;
     a.T = T;
     a.tiles_per_window = T / LP_BM;
     const int nblocks = nb * (T / LP_BM);
-    if (l == 0) return (L == 1) ? launch_lp<FP8, false, true, true>(a, nblocks, st)
-                                : launch_lp<FP8, false, true, false>(a, nblocks, st);
-    if (l < L - 1) return launch_lp<FP8, false, false, false>(a, nblocks, st);
-    return launch_lp<FP8, false, false, true>(a, nblocks, st);
+    if (l == 0) e = (L == 1) ? launch_lp<FP8, false, true, true>(a, nblocks, st)
+                             : launch_lp<FP8, false, true, false>(a, nblocks, st);
+    else if (l < L - 1) e = launch_lp<FP8, false, false, false>(a, nblocks, st);
+    else e = launch_lp<FP8, false, false, true>(a, nblocks, st);
+    if (e == hipSuccess && x_out && l < L - 1)
+        hipLaunchKernelGGL(bf16_to_f32_kernel, dim3(nblk), dim3(256), 0, st, tmp + n, n, x_out);
+    hipError_t e2 = hipFreeAsync(tmp, st);
+    return e != hipSuccess ? e : (e2 != hipSuccess ? e2 : hipGetLastError());
 }
 
 hipError_t wavenet_layers_bf16(gwd_model* m, const FwdBatch& fb, float* x_a, float* x_b, float* skip, hipStream_t st) {

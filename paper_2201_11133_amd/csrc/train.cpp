@@ -40,7 +40,7 @@ static gwd_status check_train(const gwd_model* m, int member, const void* window
     if (member < 0 || member >= m->n_members) { set_error("%s: member %d out of range", who, member); return GWD_ERR_ARG; }
     if (!windows) { set_error("%s: windows is NULL", who); return GWD_ERR_ARG; }
     if (B < 1 || T < 1) { set_error("%s: bad batch shape", who); return GWD_ERR_SHAPE; }
-    if (m->arch.kind == 1 && T % kBM != 0) { set_error("%s: window %d must be a multiple of %d", who, T, kBM); return GWD_ERR_SHAPE; }
+    if (m->arch.kind == 1 && T % 128 != 0) { set_error("%s: window %d must be a multiple of 128", who, T); return GWD_ERR_SHAPE; }
     if (m->arch.kind == 1 && m->prec == GWD_FP8_E4M3) { set_error("%s: FP8 models are inference only", who); return GWD_ERR_UNSUPPORTED; }
     return GWD_OK;
 }
