@@ -39,6 +39,10 @@ def _compile(src: str) -> str:
 def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
+    keep = {os.path.basename(s) + ".o" for s in srcs}
+    for f in os.listdir(BUILD):          # objects of sources that no longer exist
+        if f.endswith(".o") and f not in keep:
+            os.remove(os.path.join(BUILD, f))
     with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = OUT + ".tmp"

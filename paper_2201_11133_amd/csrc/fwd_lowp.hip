@@ -11,9 +11,11 @@
 // paper's half-precision engine likewise keeps its activations in half precision); the skip sum
 // stays fp32.
 //
-// Tile: 128 time steps of one window, 8 waves. Wave w owns rows [32 (w/2), +32) and the column
-// pairs (filter 64 (w%2) + 32 c + [0,32), gate 128 + same) for c = 0, 1, so the gate of a channel
-// is formed in the lane that holds both halves.
+// Tile: 64 time steps of one window. Wave w owns 32 RB rows starting at 32 RB (w / 4) and one
+// column pair: filter [32 q, 32 q + 32) and gate 128 + the same, q = w % 4, so the gate of a
+// channel is formed in the lane that holds both halves and each weight fragment feeds RB MFMAs.
+// The second GEMM runs in two passes (residual columns, then skip columns) so only one set of
+// accumulators is live at a time.
 #include "gwd_internal.h"
 #include "layer_common.h"
 
@@ -23,7 +25,10 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef int intx8 __attribute__((ext_vector_type(8)));
 
-constexpr int LP_BM = 128;
+// Tile shape per precision (measured on MI355X, 4-member ensemble): BF16 4 waves x 2 row blocks,
+// FP8 8 waves x 1 row block; both 64-row tiles and 4 waves per SIMD (<= 128 VGPRs).
+constexpr int LP_BM = 64;                       // rows per tile
+constexpr int LP_OCC = 4;                       // waves per SIMD the register budget is sized for
 
 struct LayerArgsLP {
     const uint16_t* x_in;  // residual stream, bf16 [rows][128]
@@ -62,6 +67,9 @@ __device__ inline uint32_t to_e4m3_pair(float a, float b) {
 
 template <bool FP8>
 struct LP {
+    static constexpr int WAVES = FP8 ? 8 : 4;       // waves per block (groups of 4 column pairs)
+    static constexpr int RB = LP_BM * 4 / (32 * WAVES);  // 32-row blocks per wave (2 / 1)
+    static constexpr int THREADS = 64 * WAVES;
     static constexpr int EB = FP8 ? 1 : 2;          // bytes per operand element
     static constexpr int KSTEP = FP8 ? 64 : 16;     // k per MFMA
     static constexpr int FRAG = KSTEP / 2 * EB;     // bytes per lane per fragment (16 or 32)
@@ -69,7 +77,7 @@ struct LP {
     static constexpr int XROW = kC * 2 + 16;        // padded LDS row of the bf16 residual copy (FP8 only)
     static constexpr int NK1 = 2 * kC / KSTEP;      // MFMA steps of phase 1 (16 / 4)
     static constexpr int NK2 = kC / KSTEP;          // MFMA steps of phase 2 (8 / 2)
-    static constexpr int PF1 = FP8 ? 4 : 8;         // weight-fragment prefetch depth, phase 1
+    static constexpr int PF1 = FP8 ? 4 : 4;         // weight-fragment prefetch depth, phase 1
     static constexpr int PF2 = FP8 ? 2 : 4;         // and phase 2
     static constexpr int LDS = LP_BM * ROW + (FP8 ? LP_BM * XROW : 0);
 };
@@ -113,20 +121,46 @@ __device__ inline uint2 bf16x8_to_e4m3(uint4 v) {
     return make_uint2(o[0] | (o[1] << 16), o[2] | (o[3] << 16));
 }
 
-template <bool FP8, bool FROM_STREAM, bool SKIP_INIT, bool LAST>
-__global__ __launch_bounds__(512, 1) void layer_lp_kernel(LayerArgsLP p) {
+// One phase-2 pass: acc[i] = g rows of row block i times one 32-column block of Brs (K = 128).
+template <bool FP8>
+__device__ inline void phase2_pass(const uint8_t* Ar, const uint8_t* Bm, int lane, floatx16 (&acc)[LP<FP8>::RB]) {
     using T = LP<FP8>;
+    constexpr int LP_RB = T::RB;
+    Frag<FP8> ring[T::PF2];
+#pragma unroll
+    for (int j = 0; j < T::PF2; ++j) ring[j] = load_frag<FP8>(Bm + (size_t)j * 64 * T::FRAG);
+#pragma unroll
+    for (int i = 0; i < LP_RB; ++i) acc[i] = floatx16{};
+#pragma unroll
+    for (int j = 0; j < T::NK2; ++j) {
+        const int slot = j % T::PF2;
+        const Frag<FP8> cw = ring[slot];
+        if (j + T::PF2 < T::NK2) ring[slot] = load_frag<FP8>(Bm + (size_t)(j + T::PF2) * 64 * T::FRAG);
+#pragma unroll
+        for (int i = 0; i < LP_RB; ++i) {
+            const Frag<FP8> a = load_frag<FP8>(Ar + i * 32 * T::ROW + j * T::KSTEP * T::EB);
+            acc[i] = mma<FP8>(a, cw, acc[i]);
+        }
+    }
+}
+
+template <bool FP8, bool FROM_STREAM, bool SKIP_INIT, bool LAST>
+__global__ __launch_bounds__(LP<FP8>::THREADS) __attribute__((amdgpu_waves_per_eu(LP_OCC))) void layer_lp_kernel(LayerArgsLP p) {
+    using T = LP<FP8>;
+    constexpr int LP_RB = T::RB;
+    constexpr int LP_THREADS = T::THREADS;
     __shared__ __attribute__((aligned(16))) uint8_t lds[T::LDS];
-    uint8_t* A = lds;                     // operand tile [128][x[t-d] | x[t]]; g overwrites the first half
+    uint8_t* A = lds;                     // operand tile [256][x[t-d] | x[t]]; g overwrites the first half
     uint8_t* XR = lds + LP_BM * T::ROW;   // FP8: bf16 copy of x[t] (the residual base)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, r = lane & 31;
-    const int rb = wave >> 1, half = wave & 1;
+    const int rh = wave >> 2, q = wave & 3;  // rows [32 LP_RB rh, +32 LP_RB), column pair q
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     const int b = tile / p.tiles_per_window;
     const int t0 = (tile - b * p.tiles_per_window) * LP_BM;
     const int64_t row0 = (int64_t)b * p.T + t0;
+    constexpr int CH = LP_BM * 32 / LP_THREADS;  // 16-byte chunks staged per thread
 
-    // ---- stage A = [x[t-d] | x[t]]: 128 rows x 2 taps x 16 chunks of 8 channels, 8 chunks per thread
+    // ---- stage A = [x[t-d] | x[t]]: 256 rows x 2 taps x 16 chunks of 8 channels
     {
         StreamDesc sd{};
         int64_t start = 0;
@@ -135,11 +169,11 @@ __global__ __launch_bounds__(512, 1) void layer_lp_kernel(LayerArgsLP p) {
             sd = p.streams[find_stream(p.streams, p.n_streams, gw)];
             start = (gw - sd.win_begin) * p.S;
         }
-        uint4 v[8];
+        uint4 v[CH];
 #pragma unroll
-        for (int it = 0; it < 8; ++it) {
-            const int idx = tid + 512 * it;
-            const int rr = idx >> 5, q = idx & 31, tap = q >> 4, c8 = 8 * (q & 15);
+        for (int it = 0; it < CH; ++it) {
+            const int idx = tid + LP_THREADS * it;
+            const int rr = idx >> 5, qq = idx & 31, tap = qq >> 4, c8 = 8 * (qq & 15);
             const int t = t0 + rr - (tap == 0 ? p.d : 0);
             v[it] = make_uint4(0, 0, 0, 0);
             if (t >= 0) {
@@ -165,9 +199,9 @@ __global__ __launch_bounds__(512, 1) void layer_lp_kernel(LayerArgsLP p) {
             }
         }
 #pragma unroll
-        for (int it = 0; it < 8; ++it) {
-            const int idx = tid + 512 * it;
-            const int rr = idx >> 5, q = idx & 31, tap = q >> 4, c8 = 8 * (q & 15);
+        for (int it = 0; it < CH; ++it) {
+            const int idx = tid + LP_THREADS * it;
+            const int rr = idx >> 5, qq = idx & 31, tap = qq >> 4, c8 = 8 * (qq & 15);
             if (FP8) {
                 *(uint2*)&A[rr * T::ROW + tap * kC + c8] = bf16x8_to_e4m3(v[it]);
                 if (tap == 1) *(uint4*)&XR[rr * T::XROW + 2 * c8] = v[it];
@@ -178,138 +212,100 @@ __global__ __launch_bounds__(512, 1) void layer_lp_kernel(LayerArgsLP p) {
     }
     __syncthreads();
 
-    // ---- phase 1: pre = A Bc, K = 256, weight fragments from a register ring PF1 steps deep
-    floatx16 af[2] = {}, ag[2] = {};
-    const uint8_t* Ar = &A[(32 * rb + r) * T::ROW + h * T::FRAG];
+    // A fragment of row block i of this wave: row 128 rh + 32 i + r, k-half h
+    const uint8_t* Ar = &A[(32 * LP_RB * rh + r) * T::ROW + h * T::FRAG];
+
+    // ---- phase 1: pre = A Bc, K = 256; weight fragments from a register ring PF1 steps deep
+    floatx16 af[LP_RB] = {}, ag[LP_RB] = {};
     {
-        const uint8_t* Bp[4];
+        const uint8_t* Bf = p.wc + ((size_t)(q * T::NK1) * 64 + lane) * T::FRAG;        // filter block q
+        const uint8_t* Bg = p.wc + ((size_t)((4 + q) * T::NK1) * 64 + lane) * T::FRAG;  // gate block 4 + q
+        Frag<FP8> rf[T::PF1], rg[T::PF1];
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            Bp[c] = p.wc + ((size_t)((2 * half + c) * T::NK1) * 64 + lane) * T::FRAG;          // filter
-            Bp[2 + c] = p.wc + ((size_t)((4 + 2 * half + c) * T::NK1) * 64 + lane) * T::FRAG;  // gate
+        for (int j = 0; j < T::PF1; ++j) {
+            rf[j] = load_frag<FP8>(Bf + (size_t)j * 64 * T::FRAG);
+            rg[j] = load_frag<FP8>(Bg + (size_t)j * 64 * T::FRAG);
         }
-        Frag<FP8> ring[T::PF1][4];
-#pragma unroll
-        for (int j = 0; j < T::PF1; ++j)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) ring[j][q] = load_frag<FP8>(Bp[q] + (size_t)j * 64 * T::FRAG);
 #pragma unroll
         for (int j = 0; j < T::NK1; ++j) {
             const int slot = j % T::PF1;
-            Frag<FP8> cur[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) cur[q] = ring[slot][q];
+            const Frag<FP8> cf = rf[slot], cg = rg[slot];
             if (j + T::PF1 < T::NK1) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) ring[slot][q] = load_frag<FP8>(Bp[q] + (size_t)(j + T::PF1) * 64 * T::FRAG);
+                rf[slot] = load_frag<FP8>(Bf + (size_t)(j + T::PF1) * 64 * T::FRAG);
+                rg[slot] = load_frag<FP8>(Bg + (size_t)(j + T::PF1) * 64 * T::FRAG);
             }
-            const Frag<FP8> a = load_frag<FP8>(Ar + j * T::KSTEP * T::EB);
 #pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                af[c] = mma<FP8>(a, cur[c], af[c]);
-                ag[c] = mma<FP8>(a, cur[2 + c], ag[c]);
+            for (int i = 0; i < LP_RB; ++i) {
+                const Frag<FP8> a = load_frag<FP8>(Ar + i * 32 * T::ROW + j * T::KSTEP * T::EB);
+                af[i] = mma<FP8>(a, cf, af[i]);
+                ag[i] = mma<FP8>(a, cg, ag[i]);
             }
         }
     }
-    // phase-2 weight fragments: start loading now (their latency overlaps the gate)
-    const int nq2 = LAST ? 2 : 4;
-    const uint8_t* Bq[4];
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        Bq[c] = p.wrs + ((size_t)((2 * half + c) * T::NK2) * 64 + lane) * T::FRAG;          // res (skip if last)
-        Bq[2 + c] = p.wrs + ((size_t)((4 + 2 * half + c) * T::NK2) * 64 + lane) * T::FRAG;  // skip
-    }
-    Frag<FP8> ring2[T::PF2][4];
-#pragma unroll
-    for (int j = 0; j < T::PF2; ++j)
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (q < nq2) ring2[j][q] = load_frag<FP8>(Bq[q] + (size_t)j * 64 * T::FRAG);
     __syncthreads();  // all reads of the x[t-d] half are done before g overwrites it
 
     // ---- gate -> g operands in LDS columns [0, 128)
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const int n = 64 * half + 32 * c + r;
+    {
+        const int n = 32 * q + r;
         const float bf = p.bc[n], bg = p.bc[kC + n];
         const float sf = FP8 ? p.sc[n] : 1.f, sg = FP8 ? p.sc[kC + n] : 1.f;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int m = 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
-            const float vf = FP8 ? fmaf(af[c][i], sf, bf) : af[c][i] + bf;
-            const float vg = FP8 ? fmaf(ag[c][i], sg, bg) : ag[c][i] + bg;
-            if (p.pre_out) {
-                float* po = p.pre_out + (row0 + m) * (2 * kC);
-                po[n] = vf;
-                po[kC + n] = vg;
-            }
-            const float gv = gate_f32(vf, vg);
-            if (FP8) A[m * T::ROW + n] = (uint8_t)(to_e4m3_pair(gv, 0.f) & 0xffu);
-            else *(uint16_t*)&A[m * T::ROW + 2 * n] = to_bf16_bits(gv);
-        }
-    }
-    // skip values this lane updates: load them before the barrier so the latency overlaps phase 2
-    float skv[2][16];
-    if (!SKIP_INIT) {
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
+        for (int rb = 0; rb < LP_RB; ++rb)
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
-                const int m = 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
-                skv[c][i] = p.skip[(row0 + m) * kC + 64 * half + 32 * c + r];
+                const int m = 32 * LP_RB * rh + 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
+                const float vf = FP8 ? fmaf(af[rb][i], sf, bf) : af[rb][i] + bf;
+                const float vg = FP8 ? fmaf(ag[rb][i], sg, bg) : ag[rb][i] + bg;
+                if (p.pre_out) {
+                    float* po = p.pre_out + (row0 + m) * (2 * kC);
+                    po[n] = vf;
+                    po[kC + n] = vg;
+                }
+                const float gv = gate_fast(vf, vg);
+                if (FP8) A[m * T::ROW + n] = (uint8_t)(to_e4m3_pair(gv, 0.f) & 0xffu);
+                else *(uint16_t*)&A[m * T::ROW + 2 * n] = to_bf16_bits(gv);
+                if (i == 15) __builtin_amdgcn_sched_barrier(0);   // keep row blocks apart (register pressure)
             }
     }
     __syncthreads();
 
-    // ---- phase 2: [res | skip] = g Brs, K = 128
-    floatx16 ar[2] = {}, as[2] = {};
+    // ---- phase 2: [res | skip] = g Brs, K = 128, in two passes (res, then skip) so that only one
+    // set of accumulators is live at a time; each pass ends in its part of the epilogue.
+    const int n = 32 * q + r;
+    if (!LAST) {
+        floatx16 acc[LP_RB];
+        phase2_pass<FP8>(Ar, p.wrs + ((size_t)(q * T::NK2) * 64 + lane) * T::FRAG, lane, acc);
+        const float br = p.brs[n];
+        const float s_r = FP8 ? p.srs[n] : 1.f;
 #pragma unroll
-    for (int j = 0; j < T::NK2; ++j) {
-        const int slot = j % T::PF2;
-        Frag<FP8> cur[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (q < nq2) cur[q] = ring2[slot][q];
-        if (j + T::PF2 < T::NK2) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (q < nq2) ring2[slot][q] = load_frag<FP8>(Bq[q] + (size_t)(j + T::PF2) * 64 * T::FRAG);
-        }
-        const Frag<FP8> a = load_frag<FP8>(Ar + j * T::KSTEP * T::EB);
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            ar[c] = mma<FP8>(a, cur[c], ar[c]);
-            if (!LAST) as[c] = mma<FP8>(a, cur[2 + c], as[c]);
-        }
-    }
-
-    // ---- epilogue: x_out = bf16(x + res + b_r) (x from the LDS tile), skip (+)= s + b_s
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const int n = 64 * half + 32 * c + r;
-        if (!LAST) {
-            const float br = p.brs[n], bs = p.brs[kC + n];
-            const float s_r = FP8 ? p.srs[n] : 1.f, s_s = FP8 ? p.srs[kC + n] : 1.f;
+        for (int rb = 0; rb < LP_RB; ++rb) {
+            const int mb = 32 * LP_RB * rh + 32 * rb + 4 * h;        // first row of this lane in the block
+            uint16_t* xo = p.x_out + (row0 + mb) * kC + n;
+            const uint8_t* xr = FP8 ? &XR[mb * T::XROW + 2 * n] : &A[mb * T::ROW + 2 * (kC + n)];
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
-                const int m = 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
-                const int64_t o = (row0 + m) * kC + n;
-                const float rv = FP8 ? fmaf(ar[c][i], s_r, br) : ar[c][i] + br;
-                const float sv = FP8 ? fmaf(as[c][i], s_s, bs) : as[c][i] + bs;
-                const uint16_t xb = FP8 ? *(const uint16_t*)&XR[m * T::XROW + 2 * n]
-                                        : *(const uint16_t*)&A[m * T::ROW + 2 * (kC + n)];
-                p.x_out[o] = to_bf16_bits(bf16_to_f32(xb) + rv);
-                p.skip[o] = SKIP_INIT ? sv : skv[c][i] + sv;
+                const int dm = 8 * (i >> 2) + (i & 3);                  // compile-time row offset
+                const float rv = FP8 ? fmaf(acc[rb][i], s_r, br) : acc[rb][i] + br;
+                const uint16_t xb = *(const uint16_t*)(xr + dm * (FP8 ? T::XROW : T::ROW));
+                xo[dm * kC] = to_bf16_bits(bf16_to_f32(xb) + rv);
             }
-        } else {
-            const float bs = p.brs[n];
-            const float s_s = FP8 ? p.srs[n] : 1.f;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    {
+        floatx16 acc[LP_RB];
+        phase2_pass<FP8>(Ar, p.wrs + ((size_t)((LAST ? q : 4 + q) * T::NK2) * 64 + lane) * T::FRAG, lane, acc);
+        const int cs = LAST ? n : kC + n;
+        const float bs = p.brs[cs];
+        const float s_s = FP8 ? p.srs[cs] : 1.f;
+#pragma unroll
+        for (int rb = 0; rb < LP_RB; ++rb) {
+            float* sk = p.skip + (row0 + 32 * LP_RB * rh + 32 * rb + 4 * h) * kC + n;
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
-                const int m = 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
-                const int64_t o = (row0 + m) * kC + n;
-                const float sv = FP8 ? fmaf(ar[c][i], s_s, bs) : ar[c][i] + bs;
-                p.skip[o] = SKIP_INIT ? sv : skv[c][i] + sv;
+                const int dm = 8 * (i >> 2) + (i & 3);
+                const float sv = FP8 ? fmaf(acc[rb][i], s_s, bs) : acc[rb][i] + bs;
+                sk[dm * kC] = SKIP_INIT ? sv : sk[dm * kC] + sv;
             }
         }
     }
@@ -317,7 +313,7 @@ __global__ __launch_bounds__(512, 1) void layer_lp_kernel(LayerArgsLP p) {
 
 template <bool FP8, bool A_, bool B_, bool C_>
 static hipError_t launch_lp(const LayerArgsLP& a, int nblocks, hipStream_t st) {
-    hipLaunchKernelGGL((layer_lp_kernel<FP8, A_, B_, C_>), dim3(nblocks), dim3(512), 0, st, a);
+    hipLaunchKernelGGL((layer_lp_kernel<FP8, A_, B_, C_>), dim3(nblocks), dim3(LP<FP8>::THREADS), 0, st, a);
     return hipGetLastError();
 }
 
