@@ -32,6 +32,20 @@ W, S = 4096, 256
 FLOP_PER_STEP_T = 5899008                 # flop per window time step per member
 FLOP_PER_LAYER_T = 196608                 # flop per time step of one gated layer (conv + res/skip)
 PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
+# HBM bytes per launch of the middle BF16 gated layer (512 windows), from two rocprofv3 --pmc runs
+# (FETCH_SIZE, WRITE_SIZE) scaled by a 1 GiB copy; valid only for the kernel source they were taken on
+# (profiles/gated_layer_bf16_hbm_traffic_64s.md).
+MEASURED_TRAFFIC = {"bf16": {"source_sha256_16": "f33e883ba7a152e2", "bytes": 3181504337, "windows": 512}}
+
+
+def kernel_traffic(prec: str, windows: int):
+    import hashlib
+    t = MEASURED_TRAFFIC.get(prec)
+    if not t or t["windows"] != windows:
+        return None
+    src = os.path.join(ROOT, "paper_2201_11133_amd", "csrc", "fwd_lowp.hip")
+    sig = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    return t["bytes"] if sig == t["source_sha256_16"] else None
 
 
 def make_stream_gpu(seconds: float, seed: int, chirps_per_day: float = 200.0):
@@ -80,31 +94,20 @@ def time_steps(fn, steps: int, warmup: int, label: str = "", warm_fn=None):
     return ev0.elapsed_time(ev1) / steps, (time.perf_counter() - t0) * 1e3 / steps
 
 
-def layer_kernel_timing(model, prec: str, nb: int, reps: int = 10):
-    """Average duration of the dominant kernel (a middle gated layer) in the forward's launch
-    configuration (nb windows of 4096 steps per launch), timed with HIP events on its stream."""
-    import torch
-    C = 128
-    x = torch.randn((nb, W, C), dtype=torch.float32, device="cuda") * 3
-    xo = torch.empty_like(x)
-    sk = torch.randn((nb, W, C), dtype=torch.float32, device="cuda")
-    st = torch.cuda.current_stream()
-    for _ in range(2):
-        model.debug_layer(0, 15, x, nb, W, None, xo, sk, stream=st)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(st)
-    for _ in range(reps):
-        model.debug_layer(0, 15, x, nb, W, None, xo, sk, stream=st)
-    ev1.record(st)
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / reps
+def layer_kernel_timing(model, prec: str, reps: int = 10):
+    """Average duration of the dominant kernel (a middle gated layer) in the forward's own launch
+    configuration, timed by the library with HIP events on the stream it launches on."""
+    ms, nb = model.time_layer(0, 15, reps)
     flop = nb * W * FLOP_PER_LAYER_T
     achieved = flop / (ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[prec]
-    del x, xo, sk
-    return {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": None, "kernel": f"gated layer ({prec})",
-            "ms_per_launch": round(ms, 4), "flop_per_launch": flop}
+    traffic = kernel_traffic(prec, nb)
+    out = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+           "frac": round(achieved / peak, 4), "traffic": traffic, "kernel": f"gated layer ({prec})",
+           "ms_per_launch": round(ms, 4), "windows_per_launch": nb, "flop_per_launch": flop}
+    if traffic:
+        out["hbm_GBps"] = round(traffic / (ms * 1e-3) / 1e9, 1)
+    return out
 
 
 def cpu_baseline(n_members: int, n_windows_sample: int = 3):
@@ -144,6 +147,8 @@ def main():
     ap.add_argument("--members", type=int, default=4)
     ap.add_argument("--no-extra", action="store_true", help="skip the FP32/FP8 comparison lines")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one plain 1 GiB device-to-device copy (counter calibration for profiles)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -155,6 +160,13 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
 
+    if args.calib_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        progress("calibration copy of 1 GiB done")
     progress(f"generating a {args.seconds:.0f} s stream on the device")
     x, injs = make_stream_gpu(args.seconds, 102)
     L = x.shape[0]
@@ -181,7 +193,7 @@ def main():
 
     model, main_r = run(args.precision)
     progress("dominant-kernel timing")
-    roof = layer_kernel_timing(model, args.precision, model_batch_windows(model))
+    roof = layer_kernel_timing(model, args.precision)
     model.close()
     extra = {}
     if not args.no_extra:
@@ -213,9 +225,6 @@ def main():
     }
     print(json.dumps(line), flush=True)
 
-
-def model_batch_windows(model) -> int:
-    return 512
 
 
 if __name__ == "__main__":

@@ -238,6 +238,42 @@ gwd_status gwd_adam_step(gwd_model* model, int32_t member, float* master, const 
                          int64_t step, float lr, float beta1, float beta2, float eps,
                          double* grad_norm_out, void* hip_stream);
 
+/* ---- captured plans and tuning -------------------------------------------------
+ * A plan binds one request (streams, window, stride, out_mode, output buffer —
+ * exactly as for gwd_forward) to a hipGraph holding every kernel of the forward:
+ * all batches of windows packed across the (ragged) streams, all members, all
+ * layers, head, stitch and ensemble minimum, plus a device wall-clock stamp
+ * after every batch. gwd_plan_launch replays it with one graph launch; new data
+ * written into the same stream buffers is processed by the next launch. The
+ * plan owns its own workspace; free plans before their model. Creating a plan
+ * synchronises the device. (The paper serialises its engine once and replays
+ * it, "Optimization with TensorRT".)
+ * gwd_plan_completion_us (after a launch; synchronises the device) gives, per
+ * stream, the time from the plan's start to the end of the batch holding the
+ * stream's last window, and the total, in microseconds. */
+typedef struct gwd_plan gwd_plan;
+gwd_status gwd_plan_create(gwd_model* model, const gwd_stream* streams, int32_t n_streams, int32_t window,
+                           int32_t stride, int32_t out_mode, float* out, int64_t out_capacity_floats,
+                           gwd_plan** plan);
+gwd_status gwd_plan_launch(gwd_plan* plan, void* hip_stream);
+gwd_status gwd_plan_completion_us(gwd_plan* plan, double* per_stream_us, int32_t n_streams, double* total_us);
+void gwd_plan_free(gwd_plan* plan);
+
+/* Layer-kernel tiling of a model: waves per block of the BF16 layer kernel (4
+ * or 8; 0 = default; other precisions have one tiling) and windows per batch
+ * of layer launches (1..8192, default 512). Results do not depend on either. */
+gwd_status gwd_set_tiling(gwd_model* model, int32_t waves, int32_t batch_windows);
+
+/* Autotuner: times gwd_forward (out_mode 0) on the given request for every
+ * tiling candidate (BF16: waves 4 and 8; batch 256, 512, 1024 windows), keeps
+ * the fastest on the model and reports it. If the environment variable
+ * GWD_AUTOTUNE_CACHE names a file, a cached choice for the same (architecture,
+ * precision, members, window, stride) is used instead of timing, and new
+ * choices are appended to it. Synchronises hip_stream. */
+gwd_status gwd_autotune(gwd_model* model, const gwd_stream* streams, int32_t n_streams, int32_t window,
+                        int32_t stride, float* out, int64_t out_capacity_floats, int32_t* waves,
+                        int32_t* batch_windows, void* hip_stream);
+
 /* Last error message of the calling thread ("" if none). */
 const char* gwd_last_error(void);
 
@@ -256,6 +292,17 @@ gwd_status gwd_debug_layer(gwd_model* model, int32_t member, int32_t layer, cons
                            int32_t n_windows, int32_t window, float* pre_out, float* x_out,
                            float* skip_inout, void* hip_stream);
 gwd_status gwd_debug_export_weights(const gwd_model* model, int32_t member, float* out, int64_t n_params);
+
+/* Measurement support: launches middle gated layer `layer` (0 < layer < last) of
+ * member `member` reps + 1 times exactly as gwd_forward does (same kernel, same
+ * grid over the forward's batch of windows) on the activations the last
+ * gwd_forward left in the model's workspace, and times the last `reps`
+ * launches between two HIP events recorded on hip_stream. Writes the average
+ * milliseconds per launch and the windows per launch. Requires a prior
+ * gwd_forward on the model; synchronises hip_stream. The workspace contents
+ * are overwritten. */
+gwd_status gwd_debug_time_layer(gwd_model* model, int32_t member, int32_t layer, int32_t reps,
+                                float* ms_per_launch, int32_t* windows_per_launch, void* hip_stream);
 
 #ifdef __cplusplus
 }

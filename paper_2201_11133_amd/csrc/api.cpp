@@ -72,6 +72,151 @@ static int64_t nwin_of(int64_t L, int W, int S) {
 
 using namespace gwd;
 
+namespace gwd {
+
+// Shared validation of the forward arguments. Fills per-stream window counts and totals.
+gwd_status check_forward(const gwd_model* m, const gwd_stream* streams, int32_t n_streams, int32_t window,
+                                int32_t stride, int32_t out_mode, std::vector<int64_t>& nwin, int64_t& sum_L,
+                                int64_t& total_win, int64_t& out_floats) {
+    if (!m) { set_error("gwd_forward: model is NULL"); return GWD_ERR_ARG; }
+    if (!streams) { set_error("gwd_forward: streams is NULL"); return GWD_ERR_ARG; }
+    if (n_streams < 1 || n_streams > 65536) { set_error("gwd_forward: n_streams %d not in [1, 65536]", n_streams); return GWD_ERR_ARG; }
+    if (out_mode < 0 || out_mode > 2) { set_error("gwd_forward: out_mode %d not in {0,1,2}", out_mode); return GWD_ERR_ARG; }
+    if (stride <= 0 || stride > window) { set_error("gwd_forward: stride %d not in (0, window]", stride); return GWD_ERR_ARG; }
+    const int64_t rf = rf_of(&m->arch);
+    const int tile = m->arch.kind == 0 ? 256 : 128;   // tile heights of the plain and gated kernels
+    if (window <= 0 || window % tile != 0) { set_error("gwd_forward: window %d must be a positive multiple of %d", window, tile); return GWD_ERR_SHAPE; }
+    if (window < rf) { set_error("gwd_forward: window %d shorter than the receptive field %lld", window, (long long)rf); return GWD_ERR_SHAPE; }
+    if ((int64_t)(window - stride) < rf - 1) { set_error("gwd_forward: window - stride = %d < receptive field - 1 = %lld", window - stride, (long long)(rf - 1)); return GWD_ERR_SHAPE; }
+    nwin.assign(n_streams, 0);
+    sum_L = 0;
+    total_win = 0;
+    for (int s = 0; s < n_streams; ++s) {
+        const gwd_stream& st = streams[s];
+        if (st.length < 0) { set_error("gwd_forward: stream %d has negative length", s); return GWD_ERR_ARG; }
+        if (st.length > 0) {
+            if (!st.ch[0] || !st.ch[1]) { set_error("gwd_forward: stream %d has a NULL channel pointer", s); return GWD_ERR_ARG; }
+            if (((uintptr_t)st.ch[0] & 3) || ((uintptr_t)st.ch[1] & 3)) { set_error("gwd_forward: stream %d pointer not 4-byte aligned", s); return GWD_ERR_ARG; }
+            if (st.elem_stride < 1) { set_error("gwd_forward: stream %d elem_stride %lld < 1", s, (long long)st.elem_stride); return GWD_ERR_ARG; }
+        }
+        nwin[s] = nwin_of(st.length, window, stride);
+        sum_L += st.length;
+        total_win += nwin[s];
+    }
+    const int64_t M = m->n_members;
+    out_floats = out_mode == 0 ? sum_L : out_mode == 1 ? sum_L * (1 + M) : M * total_win * (int64_t)window;
+    return GWD_OK;
+}
+
+gwd_status ensure_workspace(gwd_model* m, int64_t bytes, hipStream_t st) {
+    if (m->ws.bytes >= bytes) return GWD_OK;
+    hipError_t e;
+    if (m->ws.base) {
+        e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+        (void)hipFree(m->ws.base);
+        m->ws.base = nullptr;
+        m->ws.bytes = 0;
+    }
+    e = hipMalloc(&m->ws.base, bytes);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(workspace)");
+    m->ws.bytes = bytes;
+    return GWD_OK;
+}
+
+// Validate, size the workspace, upload the stream table (synchronously when `sync_table`), and
+// fill `fb`; then enqueue every batch x member (kernels only, so it can be captured in a graph).
+// `after_batch` (optional) is called after each batch's last member, with the batch index.
+gwd_status forward_prepare(gwd_model* m, const gwd_stream* streams, int32_t n_streams, int32_t window, int32_t stride,
+                           int32_t out_mode, float* out, int64_t out_capacity_floats, hipStream_t st, bool sync_table,
+                           FwdBatch& fb, int64_t& total_win, int& nb_max, std::vector<int64_t>* nwin_out) {
+    std::vector<int64_t> nwin;
+    int64_t sum_L, out_floats;
+    gwd_status s = check_forward(m, streams, n_streams, window, stride, out_mode, nwin, sum_L, total_win, out_floats);
+    if (s != GWD_OK) return s;
+    if (out_floats > 0 && !out) { set_error("gwd_forward: out is NULL"); return GWD_ERR_ARG; }
+    if (out_capacity_floats < out_floats) {
+        set_error("gwd_forward: out holds %lld floats, %lld needed", (long long)out_capacity_floats, (long long)out_floats);
+        return GWD_ERR_CAPACITY;
+    }
+    if (m->prec == GWD_FP64) {
+        set_error("gwd_forward: FP64 models serve the training gradient checks only");
+        return GWD_ERR_UNSUPPORTED;
+    }
+    if (nwin_out) *nwin_out = nwin;
+    nb_max = 0;
+    if (total_win == 0) return GWD_OK;
+    hipError_t e = hipSetDevice(m->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    std::vector<StreamDesc> tab(n_streams);
+    int64_t wb = 0, sb = 0;
+    for (int i = 0; i < n_streams; ++i) {
+        tab[i].ch0 = streams[i].ch[0];
+        tab[i].ch1 = streams[i].ch[1];
+        tab[i].stride = streams[i].elem_stride;
+        tab[i].length = streams[i].length;
+        tab[i].win_begin = wb;
+        tab[i].sample_begin = sb;
+        tab[i].n_win = nwin[i];
+        tab[i]._pad = 0;
+        wb += nwin[i];
+        sb += streams[i].length;
+    }
+    nb_max = (int)std::min<int64_t>(m->batch_windows, total_win);
+    // workspace: stream table (sized for the largest table so far), then x ping-pong and skip
+    const int64_t tab_bytes = std::max<int64_t>(m->ws_tab_bytes,
+                                                ((int64_t)n_streams * (int64_t)sizeof(StreamDesc) + 255) & ~255LL);
+    const int64_t act = m->arch.kind == 1 ? (int64_t)nb_max * window * kC * 4 : 0;
+    s = ensure_workspace(m, tab_bytes + 3 * act, st);
+    if (s != GWD_OK) return s;
+    m->ws_tab_bytes = tab_bytes;
+    StreamDesc* d_tab = (StreamDesc*)m->ws.base;
+    if (sync_table) {
+        e = hipStreamSynchronize(st);
+        if (e == hipSuccess) e = hipMemcpy(d_tab, tab.data(), n_streams * sizeof(StreamDesc), hipMemcpyHostToDevice);
+    } else {
+        // pageable source: the copy is staged before the call returns, so tab may go out of scope
+        e = hipMemcpyAsync(d_tab, tab.data(), n_streams * sizeof(StreamDesc), hipMemcpyHostToDevice, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "stream table upload");
+    m->last_nb = nb_max;
+    m->last_T = window;
+    fb.streams = d_tab;
+    fb.n_streams = n_streams;
+    fb.T = window;
+    fb.S = stride;
+    fb.out_mode = out_mode;
+    fb.n_members = m->n_members;
+    fb.out = out;
+    fb.sum_L = sum_L;
+    fb.total_win = total_win;
+    return GWD_OK;
+}
+
+hipError_t forward_enqueue(gwd_model* m, FwdBatch fb, int64_t total_win, int nb_max, hipStream_t st,
+                           void (*after_batch)(void*, int64_t, hipStream_t), void* ctx) {
+    const int64_t tab_bytes = m->ws_tab_bytes;
+    const int64_t act = m->arch.kind == 1 ? (int64_t)nb_max * fb.T * kC * 4 : 0;
+    char* base = (char*)m->ws.base;
+    float* x_a = (float*)(base + tab_bytes);
+    float* x_b = (float*)(base + tab_bytes + act);
+    float* skip = (float*)(base + tab_bytes + 2 * act);
+    int64_t bi = 0;
+    for (int64_t w0 = 0; w0 < total_win; w0 += nb_max, ++bi) {
+        fb.win_base = w0;
+        fb.nb = (int)std::min<int64_t>(nb_max, total_win - w0);
+        for (int mem = 0; mem < m->n_members; ++mem) {
+            fb.member = mem;
+            hipError_t e = m->arch.kind == 0 ? launch_tiny_forward(m, fb, st)
+                                             : launch_wavenet_forward(m, fb, x_a, x_b, skip, st);
+            if (e != hipSuccess) return e;
+        }
+        if (after_batch) after_batch(ctx, bi, st);
+    }
+    return hipSuccess;
+}
+}  // namespace gwd
+
 extern "C" {
 
 const char* gwd_last_error(void) { return g_err.c_str(); }
@@ -164,40 +309,6 @@ void gwd_free(gwd_model* m) {
     delete m;
 }
 
-// Shared validation of the forward arguments. Fills per-stream window counts and totals.
-static gwd_status check_forward(const gwd_model* m, const gwd_stream* streams, int32_t n_streams, int32_t window,
-                                int32_t stride, int32_t out_mode, std::vector<int64_t>& nwin, int64_t& sum_L,
-                                int64_t& total_win, int64_t& out_floats) {
-    if (!m) { set_error("gwd_forward: model is NULL"); return GWD_ERR_ARG; }
-    if (!streams) { set_error("gwd_forward: streams is NULL"); return GWD_ERR_ARG; }
-    if (n_streams < 1 || n_streams > 65536) { set_error("gwd_forward: n_streams %d not in [1, 65536]", n_streams); return GWD_ERR_ARG; }
-    if (out_mode < 0 || out_mode > 2) { set_error("gwd_forward: out_mode %d not in {0,1,2}", out_mode); return GWD_ERR_ARG; }
-    if (stride <= 0 || stride > window) { set_error("gwd_forward: stride %d not in (0, window]", stride); return GWD_ERR_ARG; }
-    const int64_t rf = rf_of(&m->arch);
-    const int tile = m->arch.kind == 0 ? 256 : 128;   // tile heights of the plain and gated kernels
-    if (window <= 0 || window % tile != 0) { set_error("gwd_forward: window %d must be a positive multiple of %d", window, tile); return GWD_ERR_SHAPE; }
-    if (window < rf) { set_error("gwd_forward: window %d shorter than the receptive field %lld", window, (long long)rf); return GWD_ERR_SHAPE; }
-    if ((int64_t)(window - stride) < rf - 1) { set_error("gwd_forward: window - stride = %d < receptive field - 1 = %lld", window - stride, (long long)(rf - 1)); return GWD_ERR_SHAPE; }
-    nwin.assign(n_streams, 0);
-    sum_L = 0;
-    total_win = 0;
-    for (int s = 0; s < n_streams; ++s) {
-        const gwd_stream& st = streams[s];
-        if (st.length < 0) { set_error("gwd_forward: stream %d has negative length", s); return GWD_ERR_ARG; }
-        if (st.length > 0) {
-            if (!st.ch[0] || !st.ch[1]) { set_error("gwd_forward: stream %d has a NULL channel pointer", s); return GWD_ERR_ARG; }
-            if (((uintptr_t)st.ch[0] & 3) || ((uintptr_t)st.ch[1] & 3)) { set_error("gwd_forward: stream %d pointer not 4-byte aligned", s); return GWD_ERR_ARG; }
-            if (st.elem_stride < 1) { set_error("gwd_forward: stream %d elem_stride %lld < 1", s, (long long)st.elem_stride); return GWD_ERR_ARG; }
-        }
-        nwin[s] = nwin_of(st.length, window, stride);
-        sum_L += st.length;
-        total_win += nwin[s];
-    }
-    const int64_t M = m->n_members;
-    out_floats = out_mode == 0 ? sum_L : out_mode == 1 ? sum_L * (1 + M) : M * total_win * (int64_t)window;
-    return GWD_OK;
-}
-
 int64_t gwd_forward_out_floats(const gwd_model* m, const gwd_stream* streams, int32_t n_streams, int32_t window,
                                int32_t stride, int32_t out_mode) {
     std::vector<int64_t> nwin;
@@ -207,94 +318,18 @@ int64_t gwd_forward_out_floats(const gwd_model* m, const gwd_stream* streams, in
     return out_floats;
 }
 
-static gwd_status ensure_workspace(gwd_model* m, int64_t bytes, hipStream_t st) {
-    if (m->ws.bytes >= bytes) return GWD_OK;
-    hipError_t e;
-    if (m->ws.base) {
-        e = hipStreamSynchronize(st);
-        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-        (void)hipFree(m->ws.base);
-        m->ws.base = nullptr;
-        m->ws.bytes = 0;
-    }
-    e = hipMalloc(&m->ws.base, bytes);
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc(workspace)");
-    m->ws.bytes = bytes;
-    return GWD_OK;
-}
 
 gwd_status gwd_forward(gwd_model* m, const gwd_stream* streams, int32_t n_streams, int32_t window, int32_t stride,
                        int32_t out_mode, float* out, int64_t out_capacity_floats, void* hip_stream) {
-    std::vector<int64_t> nwin;
-    int64_t sum_L, total_win, out_floats;
-    gwd_status s = check_forward(m, streams, n_streams, window, stride, out_mode, nwin, sum_L, total_win, out_floats);
-    if (s != GWD_OK) return s;
-    if (out_floats > 0 && !out) { set_error("gwd_forward: out is NULL"); return GWD_ERR_ARG; }
-    if (out_capacity_floats < out_floats) {
-        set_error("gwd_forward: out holds %lld floats, %lld needed", (long long)out_capacity_floats, (long long)out_floats);
-        return GWD_ERR_CAPACITY;
-    }
-    if (m->prec == GWD_FP64) {
-        set_error("gwd_forward: FP64 models serve the training gradient checks only");
-        return GWD_ERR_UNSUPPORTED;
-    }
-    if (m->arch.kind == 1 && m->prec != GWD_FP32 && m->prec != GWD_BF16 && m->prec != GWD_FP8_E4M3) {
-        set_error("gwd_forward: precision not supported");
-        return GWD_ERR_UNSUPPORTED;
-    }
-    if (total_win == 0) return GWD_OK;
     hipStream_t st = (hipStream_t)hip_stream;
-    hipError_t e = hipSetDevice(m->device);
-    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-
-    // stream table
-    std::vector<StreamDesc> tab(n_streams);
-    int64_t wb = 0, sb = 0;
-    for (int i = 0; i < n_streams; ++i) {
-        tab[i].ch0 = streams[i].ch[0];
-        tab[i].ch1 = streams[i].ch[1];
-        tab[i].stride = streams[i].elem_stride;
-        tab[i].length = streams[i].length;
-        tab[i].win_begin = wb;
-        tab[i].sample_begin = sb;
-        tab[i].n_win = nwin[i];
-        tab[i]._pad = 0;
-        wb += nwin[i];
-        sb += streams[i].length;
-    }
-    const int nb_max = (int)std::min<int64_t>(m->batch_windows, total_win);
-    const int64_t tab_bytes = ((int64_t)n_streams * (int64_t)sizeof(StreamDesc) + 255) & ~255LL;
-    const int64_t act = m->arch.kind == 1 ? (int64_t)nb_max * window * kC * 4 : 0;
-    s = ensure_workspace(m, tab_bytes + 3 * act, st);
-    if (s != GWD_OK) return s;
-    char* base = (char*)m->ws.base;
-    StreamDesc* d_tab = (StreamDesc*)base;
-    float* x_a = (float*)(base + tab_bytes);
-    float* x_b = (float*)(base + tab_bytes + act);
-    float* skip = (float*)(base + tab_bytes + 2 * act);
-    // pageable source: the copy is staged before the call returns, so tab may go out of scope
-    e = hipMemcpyAsync(d_tab, tab.data(), n_streams * sizeof(StreamDesc), hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(stream table)");
-
-    FwdBatch fb;
-    fb.streams = d_tab;
-    fb.n_streams = n_streams;
-    fb.T = window;
-    fb.S = stride;
-    fb.out_mode = out_mode;
-    fb.n_members = m->n_members;
-    fb.out = out;
-    fb.sum_L = sum_L;
-    fb.total_win = total_win;
-    for (int64_t w0 = 0; w0 < total_win; w0 += nb_max) {
-        fb.win_base = w0;
-        fb.nb = (int)std::min<int64_t>(nb_max, total_win - w0);
-        for (int mem = 0; mem < m->n_members; ++mem) {
-            fb.member = mem;
-            e = m->arch.kind == 0 ? launch_tiny_forward(m, fb, st) : launch_wavenet_forward(m, fb, x_a, x_b, skip, st);
-            if (e != hipSuccess) return hip_fail(e, "forward kernel launch");
-        }
-    }
+    FwdBatch fb{};
+    int64_t total_win = 0;
+    int nb_max = 0;
+    gwd_status s = forward_prepare(m, streams, n_streams, window, stride, out_mode, out, out_capacity_floats, st, false,
+                                   fb, total_win, nb_max, nullptr);
+    if (s != GWD_OK || total_win == 0) return s;
+    hipError_t e = forward_enqueue(m, fb, total_win, nb_max, st, nullptr, nullptr);
+    if (e != hipSuccess) return hip_fail(e, "forward kernel launch");
     return GWD_OK;
 }
 
@@ -339,6 +374,43 @@ gwd_status gwd_debug_layer(gwd_model* m, int32_t member, int32_t layer, const fl
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     e = launch_layer_debug(m, member, layer, x_in, n_windows, window, pre_out, x_out, skip, (hipStream_t)hip_stream);
     if (e != hipSuccess) return hip_fail(e, "layer kernel launch");
+    return GWD_OK;
+}
+
+gwd_status gwd_debug_time_layer(gwd_model* m, int32_t member, int32_t layer, int32_t reps, float* ms_per_launch,
+                                int32_t* windows_per_launch, void* hip_stream) {
+    if (!m || !ms_per_launch || !windows_per_launch) { set_error("gwd_debug_time_layer: NULL argument"); return GWD_ERR_ARG; }
+    if (m->arch.kind != 1 || m->prec == GWD_FP64) { set_error("gwd_debug_time_layer: gated member, FP32/BF16/FP8 only"); return GWD_ERR_UNSUPPORTED; }
+    const int L = m->arch.n_stacks * m->arch.layers_per_stack;
+    if (member < 0 || member >= m->n_members || layer < 1 || layer >= L - 1) { set_error("gwd_debug_time_layer: member or layer out of range (middle layers only)"); return GWD_ERR_ARG; }
+    if (reps < 1 || reps > 1000) { set_error("gwd_debug_time_layer: reps not in [1, 1000]"); return GWD_ERR_ARG; }
+    if (m->last_nb == 0 || !m->ws.base) { set_error("gwd_debug_time_layer: run gwd_forward on this model first"); return GWD_ERR_ARG; }
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipError_t e = hipSetDevice(m->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    const int64_t tab_bytes = m->ws_tab_bytes;
+    const int64_t act = (int64_t)m->last_nb * m->last_T * kC * 4;
+    char* base = (char*)m->ws.base;
+    void* x_a = base + tab_bytes;
+    void* x_b = base + tab_bytes + act;
+    float* skip = (float*)(base + tab_bytes + 2 * act);
+    hipEvent_t e0, e1;
+    if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+    if ((e = hipEventCreate(&e1)) != hipSuccess) { (void)hipEventDestroy(e0); return hip_fail(e, "hipEventCreate"); }
+    e = launch_layer_production(m, member, layer, x_a, x_b, skip, m->last_nb, m->last_T, st);   // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    for (int i = 0; i < reps && e == hipSuccess; ++i)
+        e = launch_layer_production(m, member, layer, (i & 1) ? x_b : x_a, (i & 1) ? x_a : x_b, skip, m->last_nb,
+                                    m->last_T, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(e, "layer timing");
+    *ms_per_launch = ms / reps;
+    *windows_per_launch = m->last_nb;
     return GWD_OK;
 }
 

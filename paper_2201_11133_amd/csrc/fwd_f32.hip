@@ -313,6 +313,19 @@ hipError_t wavenet_layers_f32(gwd_model* m, const FwdBatch& fb, float* x_a, floa
     return hipSuccess;
 }
 
+// One launch of layer l exactly as the forward issues it for a middle layer (workspace buffers).
+hipError_t layer_production_f32(gwd_model* m, int member, int l, void* x_in, void* x_out, float* skip, int nb, int T,
+                                hipStream_t st) {
+    LayerArgsF32 a = layer_args(m, member, l);
+    a.x_in = (const float*)x_in;
+    a.x_out = (float*)x_out;
+    a.skip = skip;
+    a.pre_out = nullptr;
+    a.T = T;
+    a.tiles_per_window = T / kBM;
+    return launch_layer_f32<false, false, false>(a, nb * (T / kBM), st);
+}
+
 hipError_t layer_debug_f32(gwd_model* m, int member, int l, const float* x_in, int nb, int T, float* pre_out,
                            float* x_out, float* skip, hipStream_t st) {
     const int L = m->arch.n_stacks * m->arch.layers_per_stack;

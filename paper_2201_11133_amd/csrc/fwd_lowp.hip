@@ -25,8 +25,9 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef int intx8 __attribute__((ext_vector_type(8)));
 
-// Tile shape per precision (measured on MI355X, 4-member ensemble): BF16 4 waves x 2 row blocks,
-// FP8 8 waves x 1 row block; both 64-row tiles and 4 waves per SIMD (<= 128 VGPRs).
+// Tile shape: 64 rows, 4 or 8 waves (2 or 1 row blocks per wave), <= 128 VGPRs for 4 waves per SIMD.
+// The default per precision (BF16 4 waves, FP8 8 waves) is the faster one measured on MI355X; the
+// autotuner can choose either per model and request.
 constexpr int LP_BM = 64;                       // rows per tile
 constexpr int LP_OCC = 4;                       // waves per SIMD the register budget is sized for
 
@@ -65,9 +66,9 @@ __device__ inline uint32_t to_e4m3_pair(float a, float b) {
     return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false) & 0xffffu;
 }
 
-template <bool FP8>
+template <bool FP8, int W_>
 struct LP {
-    static constexpr int WAVES = FP8 ? 8 : 4;       // waves per block (groups of 4 column pairs)
+    static constexpr int WAVES = W_;                // waves per block (groups of 4 column pairs): 4 or 8
     static constexpr int RB = LP_BM * 4 / (32 * WAVES);  // 32-row blocks per wave (2 / 1)
     static constexpr int THREADS = 64 * WAVES;
     static constexpr int EB = FP8 ? 1 : 2;          // bytes per operand element
@@ -122,9 +123,9 @@ __device__ inline uint2 bf16x8_to_e4m3(uint4 v) {
 }
 
 // One phase-2 pass: acc[i] = g rows of row block i times one 32-column block of Brs (K = 128).
-template <bool FP8>
-__device__ inline void phase2_pass(const uint8_t* Ar, const uint8_t* Bm, int lane, floatx16 (&acc)[LP<FP8>::RB]) {
-    using T = LP<FP8>;
+template <bool FP8, int WV>
+__device__ inline void phase2_pass(const uint8_t* Ar, const uint8_t* Bm, int lane, floatx16 (&acc)[LP<FP8, WV>::RB]) {
+    using T = LP<FP8, WV>;
     constexpr int LP_RB = T::RB;
     Frag<FP8> ring[T::PF2];
 #pragma unroll
@@ -144,9 +145,9 @@ __device__ inline void phase2_pass(const uint8_t* Ar, const uint8_t* Bm, int lan
     }
 }
 
-template <bool FP8, bool FROM_STREAM, bool SKIP_INIT, bool LAST>
-__global__ __launch_bounds__(LP<FP8>::THREADS) __attribute__((amdgpu_waves_per_eu(LP_OCC))) void layer_lp_kernel(LayerArgsLP p) {
-    using T = LP<FP8>;
+template <bool FP8, int WV, bool FROM_STREAM, bool SKIP_INIT, bool LAST>
+__global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(LP_OCC))) void layer_lp_kernel(LayerArgsLP p) {
+    using T = LP<FP8, WV>;
     constexpr int LP_RB = T::RB;
     constexpr int LP_THREADS = T::THREADS;
     __shared__ __attribute__((aligned(16))) uint8_t lds[T::LDS];
@@ -274,7 +275,7 @@ __global__ __launch_bounds__(LP<FP8>::THREADS) __attribute__((amdgpu_waves_per_e
     const int n = 32 * q + r;
     if (!LAST) {
         floatx16 acc[LP_RB];
-        phase2_pass<FP8>(Ar, p.wrs + ((size_t)(q * T::NK2) * 64 + lane) * T::FRAG, lane, acc);
+        phase2_pass<FP8, WV>(Ar, p.wrs + ((size_t)(q * T::NK2) * 64 + lane) * T::FRAG, lane, acc);
         const float br = p.brs[n];
         const float s_r = FP8 ? p.srs[n] : 1.f;
 #pragma unroll
@@ -294,7 +295,7 @@ __global__ __launch_bounds__(LP<FP8>::THREADS) __attribute__((amdgpu_waves_per_e
     }
     {
         floatx16 acc[LP_RB];
-        phase2_pass<FP8>(Ar, p.wrs + ((size_t)((LAST ? q : 4 + q) * T::NK2) * 64 + lane) * T::FRAG, lane, acc);
+        phase2_pass<FP8, WV>(Ar, p.wrs + ((size_t)((LAST ? q : 4 + q) * T::NK2) * 64 + lane) * T::FRAG, lane, acc);
         const int cs = LAST ? n : kC + n;
         const float bs = p.brs[cs];
         const float s_s = FP8 ? p.srs[cs] : 1.f;
@@ -311,11 +312,25 @@ __global__ __launch_bounds__(LP<FP8>::THREADS) __attribute__((amdgpu_waves_per_e
     }
 }
 
-template <bool FP8, bool A_, bool B_, bool C_>
-static hipError_t launch_lp(const LayerArgsLP& a, int nblocks, hipStream_t st) {
-    hipLaunchKernelGGL((layer_lp_kernel<FP8, A_, B_, C_>), dim3(nblocks), dim3(LP<FP8>::THREADS), 0, st, a);
+template <bool FP8, int WV, bool A_, bool B_, bool C_>
+static hipError_t launch_lp_w(const LayerArgsLP& a, int nblocks, hipStream_t st) {
+    hipLaunchKernelGGL((layer_lp_kernel<FP8, WV, A_, B_, C_>), dim3(nblocks), dim3(LP<FP8, WV>::THREADS), 0, st, a);
     return hipGetLastError();
 }
+// waves per block: 4 or 8 (a per-model choice: default per precision, or the autotuner's pick)
+template <bool FP8, bool A_, bool B_, bool C_>
+static hipError_t launch_lp(const LayerArgsLP& a, int nblocks, int waves, hipStream_t st) {
+    // FP8 always uses 8 waves (its 4-wave tiling does not fit 128 registers)
+    if constexpr (FP8) {
+        (void)waves;
+        return launch_lp_w<true, 8, A_, B_, C_>(a, nblocks, st);
+    } else {
+        if (waves == 8) return launch_lp_w<false, 8, A_, B_, C_>(a, nblocks, st);
+        return launch_lp_w<false, 4, A_, B_, C_>(a, nblocks, st);
+    }
+}
+
+static int lp_waves(const gwd_model* m, bool fp8) { return m->lp_waves ? m->lp_waves : (fp8 ? 8 : 4); }
 
 template <bool FP8>
 static LayerArgsLP lp_args(gwd_model* m, int member, int l) {
@@ -357,9 +372,9 @@ static hipError_t layers_lp(gwd_model* m, const FwdBatch& fb, float* x_a, float*
         a.win_base = fb.win_base;
         a.S = fb.S;
         hipError_t e;
-        if (l == 0) e = launch_lp<FP8, true, true, false>(a, nblocks, st);
-        else if (l < L - 1) e = launch_lp<FP8, false, false, false>(a, nblocks, st);
-        else e = launch_lp<FP8, false, false, true>(a, nblocks, st);
+        if (l == 0) e = launch_lp<FP8, true, true, false>(a, nblocks, lp_waves(m, FP8), st);
+        else if (l < L - 1) e = launch_lp<FP8, false, false, false>(a, nblocks, lp_waves(m, FP8), st);
+        else e = launch_lp<FP8, false, false, true>(a, nblocks, lp_waves(m, FP8), st);
         if (e != hipSuccess) return e;
         uint16_t* t = xin; xin = xout; xout = t;
     }
@@ -395,14 +410,36 @@ static hipError_t debug_lp(gwd_model* m, int member, int l, const float* x_in, i
     a.T = T;
     a.tiles_per_window = T / LP_BM;
     const int nblocks = nb * (T / LP_BM);
-    if (l == 0) e = (L == 1) ? launch_lp<FP8, false, true, true>(a, nblocks, st)
-                             : launch_lp<FP8, false, true, false>(a, nblocks, st);
-    else if (l < L - 1) e = launch_lp<FP8, false, false, false>(a, nblocks, st);
-    else e = launch_lp<FP8, false, false, true>(a, nblocks, st);
+    if (l == 0) e = (L == 1) ? launch_lp<FP8, false, true, true>(a, nblocks, lp_waves(m, FP8), st)
+                             : launch_lp<FP8, false, true, false>(a, nblocks, lp_waves(m, FP8), st);
+    else if (l < L - 1) e = launch_lp<FP8, false, false, false>(a, nblocks, lp_waves(m, FP8), st);
+    else e = launch_lp<FP8, false, false, true>(a, nblocks, lp_waves(m, FP8), st);
     if (e == hipSuccess && x_out && l < L - 1)
         hipLaunchKernelGGL(bf16_to_f32_kernel, dim3(nblk), dim3(256), 0, st, tmp + n, n, x_out);
     hipError_t e2 = hipFreeAsync(tmp, st);
     return e != hipSuccess ? e : (e2 != hipSuccess ? e2 : hipGetLastError());
+}
+
+// One launch of layer l exactly as the forward issues it for a middle layer (workspace buffers).
+template <bool FP8>
+static hipError_t production_lp(gwd_model* m, int member, int l, void* x_in, void* x_out, float* skip, int nb, int T,
+                                hipStream_t st) {
+    LayerArgsLP a = lp_args<FP8>(m, member, l);
+    a.x_in = (const uint16_t*)x_in;
+    a.x_out = (uint16_t*)x_out;
+    a.skip = skip;
+    a.pre_out = nullptr;
+    a.T = T;
+    a.tiles_per_window = T / LP_BM;
+    return launch_lp<FP8, false, false, false>(a, nb * (T / LP_BM), lp_waves(m, FP8), st);
+}
+hipError_t layer_production_bf16(gwd_model* m, int member, int l, void* xi, void* xo, float* sk, int nb, int T,
+                                 hipStream_t st) {
+    return production_lp<false>(m, member, l, xi, xo, sk, nb, T, st);
+}
+hipError_t layer_production_fp8(gwd_model* m, int member, int l, void* xi, void* xo, float* sk, int nb, int T,
+                                hipStream_t st) {
+    return production_lp<true>(m, member, l, xi, xo, sk, nb, T, st);
 }
 
 hipError_t wavenet_layers_bf16(gwd_model* m, const FwdBatch& fb, float* x_a, float* x_b, float* skip, hipStream_t st) {

@@ -93,6 +93,9 @@ struct gwd_model {
     gwd::Workspace tws;                        // training workspace
     std::vector<void*> canon;                  // device copy of each member's canonical blob (fp32; fp64 for GWD_FP64)
     int32_t batch_windows;                     // windows per layer-kernel batch
+    int32_t last_nb = 0, last_T = 0;           // batch shape of the last gwd_forward (workspace contents)
+    int64_t ws_tab_bytes = 0;                  // bytes reserved for the stream table at the workspace start
+    int32_t lp_waves = 0;                      // BF16/FP8 layer tiling: waves per block (0 = default per precision)
 };
 
 namespace gwd {
@@ -125,6 +128,22 @@ hipError_t launch_wavenet_forward(gwd_model* m, const FwdBatch& fb, float* x_a, 
                                   hipStream_t st);
 hipError_t launch_layer_debug(gwd_model* m, int member, int layer, const float* x_in, int nb, int T,
                               float* pre_out, float* x_out, float* skip, hipStream_t st);
+
+// One production launch of a middle layer on the workspace buffers (timing support).
+hipError_t launch_layer_production(gwd_model* m, int member, int layer, void* x_in, void* x_out, float* skip, int nb,
+                                   int T, hipStream_t st);
+
+// Forward sequencing shared by gwd_forward and the captured plans (api.cpp).
+gwd_status check_forward(const gwd_model* m, const gwd_stream* streams, int32_t n_streams, int32_t window,
+                         int32_t stride, int32_t out_mode, std::vector<int64_t>& nwin, int64_t& sum_L,
+                         int64_t& total_win, int64_t& out_floats);
+gwd_status ensure_workspace(gwd_model* m, int64_t bytes, hipStream_t st);
+gwd_status forward_prepare(gwd_model* m, const gwd_stream* streams, int32_t n_streams, int32_t window, int32_t stride,
+                           int32_t out_mode, float* out, int64_t out_capacity_floats, hipStream_t st, bool sync_table,
+                           FwdBatch& fb, int64_t& total_win, int& nb_max, std::vector<int64_t>* nwin_out);
+hipError_t forward_enqueue(gwd_model* m, FwdBatch fb, int64_t total_win, int nb_max, hipStream_t st,
+                           void (*after_batch)(void*, int64_t, hipStream_t), void* ctx);
+hipError_t launch_stamp(unsigned long long* slot, hipStream_t st);
 
 // Triggers (triggers.hip)
 struct TrigWork;

@@ -223,6 +223,28 @@ hipError_t layer_debug_bf16(gwd_model* m, int member, int l, const float* x_in, 
 hipError_t layer_debug_fp8(gwd_model* m, int member, int l, const float* x_in, int nb, int T, float* pre_out,
                            float* x_out, float* skip, hipStream_t st);
 
+// Device completion stamp: the 64-bit wall clock (constant rate) when the stream reaches this point.
+__global__ void stamp_kernel(unsigned long long* slot) {
+    if (threadIdx.x == 0) *slot = wall_clock64();
+}
+hipError_t launch_stamp(unsigned long long* slot, hipStream_t st) {
+    hipLaunchKernelGGL(stamp_kernel, dim3(1), dim3(64), 0, st, slot);
+    return hipGetLastError();
+}
+
+hipError_t layer_production_f32(gwd_model*, int, int, void*, void*, float*, int, int, hipStream_t);
+hipError_t layer_production_bf16(gwd_model*, int, int, void*, void*, float*, int, int, hipStream_t);
+hipError_t layer_production_fp8(gwd_model*, int, int, void*, void*, float*, int, int, hipStream_t);
+
+hipError_t launch_layer_production(gwd_model* m, int member, int layer, void* x_in, void* x_out, float* skip, int nb,
+                                   int T, hipStream_t st) {
+    switch (m->prec) {
+        case GWD_FP32: return layer_production_f32(m, member, layer, x_in, x_out, skip, nb, T, st);
+        case GWD_BF16: return layer_production_bf16(m, member, layer, x_in, x_out, skip, nb, T, st);
+        default: return layer_production_fp8(m, member, layer, x_in, x_out, skip, nb, T, st);
+    }
+}
+
 hipError_t launch_layer_debug(gwd_model* m, int member, int layer, const float* x_in, int nb, int T, float* pre_out,
                               float* x_out, float* skip, hipStream_t st) {
     switch (m->prec) {

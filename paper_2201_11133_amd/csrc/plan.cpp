@@ -1,0 +1,229 @@
+// Captured forward plans (one hipGraph launch for all members x all ragged streams) and the
+// autotuner for the layer-kernel tiling and batch size.
+//
+// The paper serialises a TensorRT engine once and replays it for every batch ("Optimization with
+// TensorRT"; its builder also profiles candidate kernels). Here a plan binds one request shape and
+// its buffers (stream pointers, output) to a hipGraph that holds every kernel of the forward —
+// every batch of windows packed across streams, every member, every layer, head, stitch and
+// ensemble minimum — plus one completion stamp per batch; replaying it costs one launch.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "gwd_internal.h"
+
+struct gwd_plan {
+    gwd_model* model = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    unsigned long long* stamps = nullptr;  // device [n_batches + 1]: start, then after each batch
+    gwd::Workspace ws;                     // the plan's own activations and stream table (the graph points into it)
+    int64_t n_batches = 0;
+    std::vector<int64_t> last_batch;       // per stream: batch holding its last window (-1: no windows)
+};
+
+namespace gwd {
+
+struct StampCtx {
+    unsigned long long* stamps;
+};
+
+static void stamp_after_batch(void* ctx, int64_t bi, hipStream_t st) {
+    launch_stamp(((StampCtx*)ctx)->stamps + bi + 1, st);
+}
+
+}  // namespace gwd
+
+using namespace gwd;
+
+extern "C" {
+
+gwd_status gwd_plan_create(gwd_model* m, const gwd_stream* streams, int32_t n_streams, int32_t window,
+                           int32_t stride, int32_t out_mode, float* out, int64_t out_capacity_floats,
+                           gwd_plan** plan_out) {
+    if (!plan_out) { set_error("gwd_plan_create: plan is NULL"); return GWD_ERR_ARG; }
+    *plan_out = nullptr;
+    if (!m) { set_error("gwd_plan_create: model is NULL"); return GWD_ERR_ARG; }
+    hipStream_t cap = nullptr;
+    hipError_t e = hipSetDevice(m->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    FwdBatch fb{};
+    int64_t total_win = 0;
+    int nb_max = 0;
+    std::vector<int64_t> nwin;
+    // capture into a workspace of the plan's own: swap it into the model for the capture, then back
+    const Workspace saved_ws = m->ws;
+    const int64_t saved_tab = m->ws_tab_bytes;
+    const int32_t saved_nb = m->last_nb, saved_T = m->last_T;
+    m->ws = Workspace{};
+    m->ws_tab_bytes = 0;
+    auto restore = [&](gwd_plan* p) {
+        if (p) p->ws = m->ws;
+        else if (m->ws.base) (void)hipFree(m->ws.base);
+        m->ws = saved_ws;
+        m->ws_tab_bytes = saved_tab;
+        m->last_nb = saved_nb;
+        m->last_T = saved_T;
+    };
+    gwd_status s = forward_prepare(m, streams, n_streams, window, stride, out_mode, out, out_capacity_floats, nullptr,
+                                   true, fb, total_win, nb_max, &nwin);
+    if (s == GWD_OK && total_win == 0) { set_error("gwd_plan_create: the request has no windows"); s = GWD_ERR_SHAPE; }
+    gwd_plan* p = s == GWD_OK ? new (std::nothrow) gwd_plan() : nullptr;
+    if (s == GWD_OK && !p) { set_error("gwd_plan_create: out of host memory"); s = GWD_ERR_ARG; }
+    if (s != GWD_OK) {
+        restore(nullptr);
+        return s;
+    }
+    p->model = m;
+    p->n_batches = (total_win + nb_max - 1) / nb_max;
+    int64_t wb = 0;
+    p->last_batch.assign(n_streams, -1);
+    for (int i = 0; i < n_streams; ++i) {
+        if (nwin[i] > 0) p->last_batch[i] = (wb + nwin[i] - 1) / nb_max;
+        wb += nwin[i];
+    }
+    e = hipMalloc((void**)&p->stamps, (p->n_batches + 1) * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        StampCtx ctx{p->stamps};
+        hipError_t e1 = launch_stamp(p->stamps, cap);
+        if (e1 == hipSuccess) e1 = forward_enqueue(m, fb, total_win, nb_max, cap, stamp_after_batch, &ctx);
+        e = hipStreamEndCapture(cap, &p->graph);
+        if (e1 != hipSuccess) e = e1;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (cap) (void)hipStreamDestroy(cap);
+    restore(p);
+    if (e != hipSuccess) {
+        gwd_status r = hip_fail(e, "plan capture");
+        gwd_plan_free(p);
+        return r;
+    }
+    *plan_out = p;
+    return GWD_OK;
+}
+
+gwd_status gwd_plan_launch(gwd_plan* p, void* hip_stream) {
+    if (!p || !p->exec) { set_error("gwd_plan_launch: plan is NULL"); return GWD_ERR_ARG; }
+    hipError_t e = hipSetDevice(p->model->device);
+    if (e == hipSuccess) e = hipGraphLaunch(p->exec, (hipStream_t)hip_stream);
+    return e == hipSuccess ? GWD_OK : hip_fail(e, "hipGraphLaunch");
+}
+
+gwd_status gwd_plan_completion_us(gwd_plan* p, double* per_stream_us, int32_t n_streams, double* total_us) {
+    if (!p || !per_stream_us || !total_us) { set_error("gwd_plan_completion_us: NULL argument"); return GWD_ERR_ARG; }
+    if (n_streams != (int32_t)p->last_batch.size()) { set_error("gwd_plan_completion_us: n_streams mismatch"); return GWD_ERR_ARG; }
+    std::vector<unsigned long long> st(p->n_batches + 1);
+    hipError_t e = hipSetDevice(p->model->device);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(st.data(), p->stamps, st.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost);
+    int khz = 0;
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, p->model->device);
+    if (e != hipSuccess) return hip_fail(e, "plan stamps");
+    if (khz <= 0) { set_error("gwd_plan_completion_us: wall clock rate unknown"); return GWD_ERR_HIP; }
+    const double us_per_tick = 1e3 / (double)khz;
+    for (int i = 0; i < n_streams; ++i) {
+        const int64_t b = p->last_batch[i];
+        per_stream_us[i] = b < 0 ? 0.0 : (double)(st[b + 1] - st[0]) * us_per_tick;
+    }
+    *total_us = (double)(st[p->n_batches] - st[0]) * us_per_tick;
+    return GWD_OK;
+}
+
+void gwd_plan_free(gwd_plan* p) {
+    if (!p) return;
+    (void)hipDeviceSynchronize();
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->stamps) (void)hipFree(p->stamps);
+    if (p->ws.base) (void)hipFree(p->ws.base);
+    delete p;
+}
+
+gwd_status gwd_set_tiling(gwd_model* m, int32_t waves, int32_t batch_windows) {
+    if (!m) { set_error("gwd_set_tiling: model is NULL"); return GWD_ERR_ARG; }
+    if (waves != 0 && waves != 4 && waves != 8) { set_error("gwd_set_tiling: waves must be 0, 4 or 8"); return GWD_ERR_ARG; }
+    if (batch_windows < 1 || batch_windows > 8192) { set_error("gwd_set_tiling: batch_windows not in [1, 8192]"); return GWD_ERR_ARG; }
+    m->lp_waves = waves;
+    m->batch_windows = batch_windows;
+    return GWD_OK;
+}
+
+gwd_status gwd_autotune(gwd_model* m, const gwd_stream* streams, int32_t n_streams, int32_t window, int32_t stride,
+                        float* out, int64_t out_capacity_floats, int32_t* waves_out, int32_t* batch_out,
+                        void* hip_stream) {
+    if (!m || !waves_out || !batch_out) { set_error("gwd_autotune: NULL argument"); return GWD_ERR_ARG; }
+    hipStream_t st = (hipStream_t)hip_stream;
+    const char* cache = getenv("GWD_AUTOTUNE_CACHE");
+    char key[160];
+    snprintf(key, sizeof key, "gfx950 kind%d prec%d members%d W%d S%d", m->arch.kind, (int)m->prec, m->n_members,
+             window, stride);
+    if (cache) {  // "key waves batch" lines
+        if (FILE* f = fopen(cache, "r")) {
+            char line[256];
+            while (fgets(line, sizeof line, f)) {
+                int w = 0, b = 0;
+                const size_t kl = strlen(key);
+                if (strncmp(line, key, kl) == 0 && sscanf(line + kl, " %d %d", &w, &b) == 2) {
+                    fclose(f);
+                    gwd_status s = gwd_set_tiling(m, w, b);
+                    if (s == GWD_OK) { *waves_out = w; *batch_out = b; }
+                    return s;
+                }
+            }
+            fclose(f);
+        }
+    }
+    std::vector<int> wave_opts = {0};
+    if (m->arch.kind == 1 && m->prec == GWD_BF16) wave_opts = {4, 8};
+    const int batch_opts[] = {256, 512, 1024};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipSetDevice(m->device);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) return hip_fail(e, "autotune events");
+    float best = 1e30f;
+    int bw = m->lp_waves, bb = m->batch_windows;
+    gwd_status s = GWD_OK;
+    for (int w : wave_opts) {
+        for (int b : batch_opts) {
+            m->lp_waves = w;
+            m->batch_windows = b;
+            s = gwd_forward(m, streams, n_streams, window, stride, 0, out, out_capacity_floats, st);  // warm-up
+            if (s != GWD_OK) break;
+            e = hipEventRecord(e0, st);
+            if (e == hipSuccess) s = gwd_forward(m, streams, n_streams, window, stride, 0, out, out_capacity_floats, st);
+            if (e == hipSuccess && s == GWD_OK) e = hipEventRecord(e1, st);
+            if (e == hipSuccess && s == GWD_OK) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess && s == GWD_OK) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess || s != GWD_OK) break;
+            if (ms < best) { best = ms; bw = w; bb = b; }
+        }
+        if (e != hipSuccess || s != GWD_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(e, "autotune timing");
+    if (s != GWD_OK) return s;
+    m->lp_waves = bw;
+    m->batch_windows = bb;
+    *waves_out = bw;
+    *batch_out = bb;
+    if (cache) {
+        if (FILE* f = fopen(cache, "a")) {
+            fprintf(f, "%s %d %d\n", key, bw, bb);
+            fclose(f);
+        }
+    }
+    return GWD_OK;
+}
+
+}  // extern "C"

@@ -80,6 +80,14 @@ def _load(path: str = LIB_PATH):
         "gwd_last_error": (ctypes.c_char_p, []),
         "gwd_debug_layer": (I32, [P, I32, I32, P, I32, I32, P, P, P, P]),
         "gwd_bce_logits": (I32, [P, P, I64, P, P, P]),
+        "gwd_debug_time_layer": (I32, [P, I32, I32, I32, ctypes.POINTER(F32), ctypes.POINTER(I32), P]),
+        "gwd_plan_create": (I32, [P, ctypes.POINTER(Stream), I32, I32, I32, I32, P, I64, ctypes.POINTER(P)]),
+        "gwd_plan_launch": (I32, [P, P]),
+        "gwd_plan_completion_us": (I32, [P, P, I32, ctypes.POINTER(D)]),
+        "gwd_plan_free": (None, [P]),
+        "gwd_set_tiling": (I32, [P, I32, I32]),
+        "gwd_autotune": (I32, [P, ctypes.POINTER(Stream), I32, I32, I32, P, I64, ctypes.POINTER(I32),
+                               ctypes.POINTER(I32), P]),
         "gwd_debug_export_weights": (I32, [P, I32, P, I64]),
     }
     for name, (res, args) in sig.items():
@@ -189,6 +197,32 @@ class Model:
                               _stream_handle(stream)))
         return out[:n]
 
+    def time_layer(self, member: int = 0, layer: int = 15, reps: int = 10, stream=None):
+        """(ms per launch, windows per launch) of one production launch of a middle layer."""
+        ms, nw = ctypes.c_float(0), ctypes.c_int32(0)
+        check(lib.gwd_debug_time_layer(self.h, member, layer, reps, ctypes.byref(ms), ctypes.byref(nw),
+                                       _stream_handle(stream)))
+        return float(ms.value), int(nw.value)
+
+    def set_tiling(self, waves: int = 0, batch_windows: int = 512):
+        check(lib.gwd_set_tiling(self.h, waves, batch_windows))
+
+    def autotune(self, streams, window: int = 4096, stride: int = 256, out=None, stream=None):
+        """Pick the fastest tiling for this request; returns (waves, batch_windows)."""
+        import torch
+        arr, _ = make_streams(streams)
+        n = self.out_floats(streams, window, stride, 0)
+        if out is None:
+            out = torch.empty(max(n, 1), dtype=torch.float32, device="cuda")
+        w, b = ctypes.c_int32(0), ctypes.c_int32(0)
+        check(lib.gwd_autotune(self.h, arr, len(streams), window, stride, _ptr(out), out.numel(), ctypes.byref(w),
+                               ctypes.byref(b), _stream_handle(stream)))
+        return int(w.value), int(b.value)
+
+    def plan(self, streams, window: int = 4096, stride: int = 256, out_mode: int = 0, out=None):
+        """Capture the whole forward for this request into a replayable graph (see Plan)."""
+        return Plan(self, streams, window, stride, out_mode, out)
+
     def export_weights(self, member: int = 0) -> np.ndarray:
         out = np.zeros(self.n_params, dtype=np.float32)
         check(lib.gwd_debug_export_weights(self.h, member, out.ctypes.data, self.n_params))
@@ -198,6 +232,45 @@ class Model:
                     stream=None):
         check(lib.gwd_debug_layer(self.h, member, layer, _ptr(x_in), n_windows, window, _ptr(pre_out),
                                   _ptr(x_out), _ptr(skip), _stream_handle(stream)))
+
+
+class Plan:
+    """A captured forward: one graph launch per call, bound to the given stream buffers and output."""
+
+    def __init__(self, model: "Model", streams, window: int, stride: int, out_mode: int, out=None):
+        import torch
+        self.model = model
+        self.arr, self.lengths = make_streams(streams)
+        self.n_streams = len(streams)
+        n = model.out_floats(streams, window, stride, out_mode)
+        self.out = out if out is not None else torch.empty(max(n, 1), dtype=torch.float32, device="cuda")
+        h = ctypes.c_void_p()
+        check(lib.gwd_plan_create(model.h, self.arr, self.n_streams, window, stride, out_mode, _ptr(self.out),
+                                  self.out.numel(), ctypes.byref(h)))
+        self.h = h
+        self.n_out = n
+
+    def launch(self, stream=None):
+        check(lib.gwd_plan_launch(self.h, _stream_handle(stream)))
+        return self.out[: self.n_out]
+
+    def completion_us(self):
+        """(per-stream completion times, total) in microseconds for the last launch."""
+        per = np.zeros(self.n_streams, dtype=np.float64)
+        tot = ctypes.c_double(0)
+        check(lib.gwd_plan_completion_us(self.h, per.ctypes.data, self.n_streams, ctypes.byref(tot)))
+        return per, float(tot.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.gwd_plan_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def triggers(e, offsets: Sequence[int], threshold_prob: float = 0.9, cluster_window: int = 4096,

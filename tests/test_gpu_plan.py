@@ -1,0 +1,82 @@
+"""Captured plans (one graph launch for all members and ragged streams), tiling choices, autotuner."""
+import numpy as np
+import pytest
+
+from tests.gpu_common import to_dev
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def g():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2201_11133_amd import gwd
+    return gwd
+
+
+def ragged_streams(seed, n, max_s=40.0):
+    from paper_2201_11133_amd import synth
+    rng = np.random.default_rng(seed)
+    lens = [int(4096 * np.exp(rng.uniform(np.log(0.5), np.log(max_s)))) for _ in range(n)]
+    lens[1] = 0        # an empty stream
+    lens[2] = 3000     # shorter than one window
+    return [synth.make_stream(seed + i, max(L, 1) / 4096, 1 if L > 16 * 4096 else 0)[0][:L] for i, L in enumerate(lens)]
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_plan_replays_match_eager(g, prec):
+    from paper_2201_11133_amd import synth
+    print(f"case: plan replays {prec}", flush=True)
+    blobs = np.stack([synth.full_weights(11 + i) for i in range(2)])
+    m = g.Model(g.full_arch(), blobs, prec)
+    m.set_tiling(0, 96)          # several batches, streams split across batch boundaries
+    xs = ragged_streams(300, 6)
+    bufs = [to_dev(x) if len(x) else torch.zeros((0, 2), dtype=torch.float32, device="cuda") for x in xs]
+    plan = m.plan(bufs, 4096, 256, out_mode=1)
+    for rep in range(3):
+        # new data in the same buffers, then eager work between replays
+        for b in bufs:
+            if b.numel():
+                b.copy_(torch.randn_like(b))
+        eager = m.forward(bufs, 4096, 256, out_mode=1).clone()
+        torch.cuda.synchronize()
+        got = plan.launch().clone()
+        torch.cuda.synchronize()
+        assert torch.equal(got, eager), rep
+    per, tot = plan.completion_us()
+    lens = [len(x) for x in xs]
+    assert tot > 0 and np.all(per <= tot + 1e-6)
+    assert all((p > 0) == (L > 0) for p, L in zip(per, lens))
+    plan.close()
+    m.close()
+
+
+def test_tilings_and_batches_do_not_change_results(g):
+    from paper_2201_11133_amd import synth
+    m = g.Model(g.full_arch(), synth.full_weights(11), "bf16")
+    x = to_dev(synth.make_stream(310, 20.0, 1)[0])
+    ref = None
+    for waves in (4, 8):
+        for nb in (64, 300, 512):
+            m.set_tiling(waves, nb)
+            e = m.forward([x], 4096, 256, 0).clone()
+            if ref is None:
+                ref = e
+            assert torch.equal(e, ref), (waves, nb)
+    m.close()
+
+
+def test_autotune_picks_a_valid_tiling(g, tmp_path, monkeypatch):
+    from paper_2201_11133_amd import synth
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("GWD_AUTOTUNE_CACHE", str(cache))
+    m = g.Model(g.full_arch(), synth.full_weights(11), "bf16")
+    x = to_dev(synth.make_stream(311, 40.0, 1)[0])
+    w, b = m.autotune([x])
+    assert w in (4, 8) and b in (256, 512, 1024)
+    assert cache.read_text().strip().endswith(f"{w} {b}")
+    # second call reads the cache
+    assert m.autotune([x]) == (w, b)
+    m.close()
