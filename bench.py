@@ -110,6 +110,76 @@ def layer_kernel_timing(model, prec: str, reps: int = 10):
     return out
 
 
+def ragged_workload(gwd, blobs, prec: str):
+    """32 concurrent streams, lengths log-uniform in 8-4096 s, each with 0-5 chirps (>= 2.5 s apart),
+    all members and streams in one captured graph launch; tiling chosen by the autotuner on a
+    64 s sample of the first stream."""
+    import torch
+    from paper_2201_11133_amd import synth
+    lens = synth.ragged_lengths(103, 32)
+    rng = np.random.default_rng(103)
+    bufs = []
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(103)
+    for L in lens:
+        x = torch.randn((L, 2), dtype=torch.float32, device="cuda", generator=gen)
+        secs = L / FS
+        for inj in [synth.draw_injection(rng, tc) for tc in
+                    synth.place_times(rng, int(rng.integers(0, 6)), secs, 1.25, 2.5)]:
+            lo = max(0, int(math.floor((inj.tc - inj.tau20 - 0.02) * FS)))
+            hi = min(L, int(math.ceil((inj.tc + 0.02) * FS)) + 1)
+            if hi > lo:
+                x[lo:hi] += torch.from_numpy(synth.injection_signal(inj, lo / FS, hi - lo).astype(np.float32)).cuda()
+        bufs.append(x)
+    m = gwd.Model(gwd.full_arch(), blobs, prec)
+    waves, batch = m.autotune([bufs[0][: 64 * FS]])
+    plan = m.plan(bufs, W, S, out_mode=0)
+    plan.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = plan.launch()
+    offs = np.concatenate([[0], np.cumsum(lens)])
+    n_trig = len(gwd.triggers(out, offs, 0.9, 4096))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per, tot = plan.completion_us()
+    plan.close()
+    m.close()
+    total_s = sum(lens) / FS
+    return {"streams": 32, "stream_seconds_total": round(total_s, 1), "strain_s_per_s": round(total_s / wall, 2),
+            "completion_s_p50": round(float(np.percentile(per, 50)) / 1e6, 3),
+            "completion_s_p99": round(float(np.percentile(per, 99)) / 1e6, 3),
+            "graph_total_s": round(tot / 1e6, 3), "autotune": {"waves": waves, "batch_windows": batch},
+            "triggers": n_trig, "precision": prec}
+
+
+def train_workload(gwd, steps: int = 2, B: int = 256):
+    """Training of one full-size member: BF16 forward with per-stack checkpoints, BCE on logits,
+    fp32 hand-written backward, Adam on fp32 master weights; batches of 256 windows of 2 x 4096,
+    half of them chirped (SNR 8-20), labels 1 within 0.1 s of the coalescence time."""
+    import torch
+    from paper_2201_11133_amd import synth
+    blob = synth.full_weights(4)
+    m = gwd.Model(gwd.full_arch(), blob, "bf16")
+    tr = gwd.Trainer(m, blob, B, W)
+    x, injs = synth.make_windows(104, B, B // 2)
+    y = np.zeros((B, W), np.float32)
+    for i, inj in injs:
+        y[i] = synth.box_labels(W, inj.tc)
+    xd, yd = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    tr.step(xd, yd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        loss, norm = tr.step(xd, yd)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    m.close()
+    return {"train_windows_per_s": round(B / dt, 1), "s_per_step": round(dt, 3), "batch": B,
+            "loss": round(float(loss.item()), 5), "grad_norm": round(float(norm.item()), 5),
+            "precision": "bf16 forward, fp32 backward and master weights"}
+
+
 def cpu_baseline(n_members: int, n_windows_sample: int = 3):
     """The FP64 oracle, windowed (the same algorithm and work as the GPU path), on a bounded sample:
     n_windows_sample consecutive windows for every member; the strain they add is S samples each."""
@@ -147,6 +217,8 @@ def main():
     ap.add_argument("--members", type=int, default=4)
     ap.add_argument("--no-extra", action="store_true", help="skip the FP32/FP8 comparison lines")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-ragged", action="store_true", help="skip the 32-stream ragged graph workload")
+    ap.add_argument("--no-train", action="store_true", help="skip the training-throughput measurement")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device-to-device copy (counter calibration for profiles)")
     args = ap.parse_args()
@@ -204,6 +276,16 @@ def main():
             m2.close()
             extra[prec] = {k: round(v, 3) if isinstance(v, float) else v for k, v in r2.items()}
         extra[args.precision] = {k: round(v, 3) if isinstance(v, float) else v for k, v in main_r.items()}
+    ragged = None
+    if not args.no_ragged:
+        progress("ragged workload: 32 streams, one graph launch")
+        ragged = ragged_workload(gwd, blobs, args.precision)
+        progress(f"ragged: {ragged['strain_s_per_s']} strain-s/s over {ragged['stream_seconds_total']} s")
+    train = None
+    if not args.no_train:
+        progress("training throughput")
+        train = train_workload(gwd)
+        progress(f"training: {train['train_windows_per_s']} windows/s")
     progress("CPU oracle baseline")
     cpu = None if args.no_cpu else cpu_baseline(args.members)
     value = main_r["strain_s_per_s"]
@@ -221,7 +303,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "detail": {"triggers": main_r["triggers"], "tflops_step": round(main_r["tflops"], 2),
-                   "ms_events": round(main_r["ms_events"], 3), "precisions": extra},
+                   "ms_events": round(main_r["ms_events"], 3), "precisions": extra,
+                   "ragged_streams": ragged, "training": train},
     }
     print(json.dumps(line), flush=True)
 

@@ -63,6 +63,11 @@ def _load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with __graft_entry__.build() "
                           "or python paper_2201_11133_amd/build.py")
+    # torch carries its own HIP runtime (soname libamdhip64.so.7, loaded by file name). Importing it
+    # first makes libgwd's dependency resolve to that same runtime, so device pointers and streams
+    # from torch are valid in libgwd; opened the other way round the process would hold two HIP
+    # runtimes and torch would find no device.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     P, I32, I64, F32, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_double
     sig = {
@@ -232,6 +237,39 @@ class Model:
                     stream=None):
         check(lib.gwd_debug_layer(self.h, member, layer, _ptr(x_in), n_windows, window, _ptr(pre_out),
                                   _ptr(x_out), _ptr(skip), _stream_handle(stream)))
+
+
+class Trainer:
+    """Buffers and calls of one training step of member `member` (forward with checkpoints, BCE,
+    backward, Adam) through the C ABI; master weights, moments and gradients live on the device."""
+
+    def __init__(self, model: "Model", blob: np.ndarray, B: int, T: int, member: int = 0):
+        import torch
+        self.m, self.B, self.T, self.member = model, B, T, member
+        self.master = torch.from_numpy(np.ascontiguousarray(blob, dtype=np.float32)).cuda()
+        self.mom = torch.zeros_like(self.master)
+        self.vel = torch.zeros_like(self.master)
+        self.grad = torch.zeros_like(self.master)
+        self.logits = torch.empty((B, T), dtype=torch.float32, device="cuda")
+        self.dz = torch.empty_like(self.logits)
+        self.saved = torch.empty(int(lib.gwd_saved_bytes(model.h, B, T)), dtype=torch.uint8, device="cuda")
+        self.loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        self.norm = torch.zeros(1, dtype=torch.float64, device="cuda")
+        self.step_no = 0
+
+    def step(self, windows, labels, lr: float = 1e-3, stream=None):
+        s = _stream_handle(stream)
+        check(lib.gwd_forward_train(self.m.h, self.member, windows.data_ptr(), self.B, self.T,
+                                    self.logits.data_ptr(), self.saved.data_ptr(), s))
+        check(lib.gwd_bce_logits(self.logits.data_ptr(), labels.data_ptr(), self.B * self.T, self.dz.data_ptr(),
+                                 self.loss.data_ptr(), s))
+        check(lib.gwd_backward(self.m.h, self.member, windows.data_ptr(), self.B, self.T, self.saved.data_ptr(),
+                               self.dz.data_ptr(), self.grad.data_ptr(), None, s))
+        self.step_no += 1
+        check(lib.gwd_adam_step(self.m.h, self.member, self.master.data_ptr(), self.grad.data_ptr(),
+                                self.mom.data_ptr(), self.vel.data_ptr(), self.step_no, lr, 0.9, 0.999, 1e-8,
+                                self.norm.data_ptr(), s))
+        return self.loss, self.norm
 
 
 class Plan:

@@ -129,3 +129,14 @@ def test_training_argument_errors(g):
     assert g.lib.gwd_forward_train(None, 0, None, 1, 4096, None, None, None) in (g.ERR_ARG, g.ERR_UNSUPPORTED)
     assert g.lib.gwd_backward(None, 0, None, 1, 4096, None, None, None, None, None) in (g.ERR_ARG, g.ERR_UNSUPPORTED)
     assert g.lib.gwd_adam_step(None, 0, None, None, None, None, 1, 1e-3, 0.9, 0.999, 1e-8, None, None) in (g.ERR_ARG, g.ERR_UNSUPPORTED)
+
+
+def test_one_hip_runtime_in_process():
+    """libgwd shares torch's HIP runtime: a second copy would leave torch without devices."""
+    import subprocess
+    import sys
+    code = ("import paper_2201_11133_amd.gwd\n"
+            "print(sorted({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, check=True,
+                         cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__)))).stdout
+    assert out.count("libamdhip64") == 1, out
