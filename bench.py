@@ -29,7 +29,8 @@ sys.path.insert(0, ROOT)
 
 FS = 4096
 W, S = 4096, 256
-FLOP_PER_STEP_T = 5899008                 # flop per window time step per member
+FLOP_LAYERS_T = 5865984                   # flop per window time step per member: input conv + 30 gated layers
+FLOP_HEAD_T = 33024                       # flop per owned (output) sample per member: 128x128 + 128 -> 1
 FLOP_PER_LAYER_T = 196608                 # flop per time step of one gated layer (conv + res/skip)
 PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
 # HBM bytes per launch of the middle BF16 gated layer (512 windows), from two rocprofv3 --pmc runs
@@ -261,7 +262,8 @@ def main():
         secs = xs.shape[0] / FS
         return m, {"strain_s_per_s": secs / (ms_wall / 1e3), "ms_per_step": ms_wall, "ms_events": ms_ev,
                    "stream_s": secs, "triggers": n_trig[0],
-                   "tflops": args.members * n_windows(xs.shape[0]) * W * FLOP_PER_STEP_T / (ms_wall * 1e-3) / 1e12}
+                   "tflops": args.members * (n_windows(xs.shape[0]) * W * FLOP_LAYERS_T + xs.shape[0] * FLOP_HEAD_T)
+                   / (ms_wall * 1e-3) / 1e12}
 
     model, main_r = run(args.precision)
     progress("dominant-kernel timing")

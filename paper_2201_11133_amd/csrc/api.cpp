@@ -148,7 +148,10 @@ gwd_status forward_prepare(gwd_model* m, const gwd_stream* streams, int32_t n_st
     if (total_win == 0) return GWD_OK;
     hipError_t e = hipSetDevice(m->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    // device table: one StreamDesc per stream, then the global index of every stream's first window
     std::vector<StreamDesc> tab(n_streams);
+    std::vector<int64_t>& firsts = m->host_firsts;
+    firsts.clear();
     int64_t wb = 0, sb = 0;
     for (int i = 0; i < n_streams; ++i) {
         tab[i].ch0 = streams[i].ch[0];
@@ -159,29 +162,35 @@ gwd_status forward_prepare(gwd_model* m, const gwd_stream* streams, int32_t n_st
         tab[i].sample_begin = sb;
         tab[i].n_win = nwin[i];
         tab[i]._pad = 0;
+        if (nwin[i] > 0) firsts.push_back(wb);
         wb += nwin[i];
         sb += streams[i].length;
     }
     nb_max = (int)std::min<int64_t>(m->batch_windows, total_win);
     // workspace: stream table (sized for the largest table so far), then x ping-pong and skip
-    const int64_t tab_bytes = std::max<int64_t>(m->ws_tab_bytes,
-                                                ((int64_t)n_streams * (int64_t)sizeof(StreamDesc) + 255) & ~255LL);
+    const int64_t desc_bytes = (int64_t)n_streams * (int64_t)sizeof(StreamDesc);
+    const int64_t first_bytes = (int64_t)firsts.size() * (int64_t)sizeof(int64_t);
+    const int64_t tab_bytes = std::max<int64_t>(m->ws_tab_bytes, (desc_bytes + first_bytes + 255) & ~255LL);
     const int64_t act = m->arch.kind == 1 ? (int64_t)nb_max * window * kC * 4 : 0;
     s = ensure_workspace(m, tab_bytes + 3 * act, st);
     if (s != GWD_OK) return s;
     m->ws_tab_bytes = tab_bytes;
+    std::vector<char> host_tab(desc_bytes + first_bytes);
+    memcpy(host_tab.data(), tab.data(), desc_bytes);
+    memcpy(host_tab.data() + desc_bytes, firsts.data(), first_bytes);
     StreamDesc* d_tab = (StreamDesc*)m->ws.base;
     if (sync_table) {
         e = hipStreamSynchronize(st);
-        if (e == hipSuccess) e = hipMemcpy(d_tab, tab.data(), n_streams * sizeof(StreamDesc), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(d_tab, host_tab.data(), host_tab.size(), hipMemcpyHostToDevice);
     } else {
-        // pageable source: the copy is staged before the call returns, so tab may go out of scope
-        e = hipMemcpyAsync(d_tab, tab.data(), n_streams * sizeof(StreamDesc), hipMemcpyHostToDevice, st);
+        // pageable source: the copy is staged before the call returns, so host_tab may go out of scope
+        e = hipMemcpyAsync(d_tab, host_tab.data(), host_tab.size(), hipMemcpyHostToDevice, st);
     }
     if (e != hipSuccess) return hip_fail(e, "stream table upload");
     m->last_nb = nb_max;
     m->last_T = window;
     fb.streams = d_tab;
+    fb.firsts = (const int64_t*)((const char*)d_tab + desc_bytes);
     fb.n_streams = n_streams;
     fb.T = window;
     fb.S = stride;
@@ -194,7 +203,7 @@ gwd_status forward_prepare(gwd_model* m, const gwd_stream* streams, int32_t n_st
 }
 
 hipError_t forward_enqueue(gwd_model* m, FwdBatch fb, int64_t total_win, int nb_max, hipStream_t st,
-                           void (*after_batch)(void*, int64_t, hipStream_t), void* ctx) {
+                           hipError_t (*after_batch)(void*, int64_t, hipStream_t), void* ctx) {
     const int64_t tab_bytes = m->ws_tab_bytes;
     const int64_t act = m->arch.kind == 1 ? (int64_t)nb_max * fb.T * kC * 4 : 0;
     char* base = (char*)m->ws.base;
@@ -205,13 +214,22 @@ hipError_t forward_enqueue(gwd_model* m, FwdBatch fb, int64_t total_win, int nb_
     for (int64_t w0 = 0; w0 < total_win; w0 += nb_max, ++bi) {
         fb.win_base = w0;
         fb.nb = (int)std::min<int64_t>(nb_max, total_win - w0);
+        // stream starts inside [w0, w0 + nb): a contiguous run of the sorted first-window list
+        const std::vector<int64_t>& f = m->host_firsts;
+        const auto f0 = std::lower_bound(f.begin(), f.end(), w0);
+        const auto f1 = std::lower_bound(f0, f.end(), w0 + fb.nb);
+        fb.first_idx = f0 - f.begin();
+        fb.n_first = (int)(f1 - f0);
         for (int mem = 0; mem < m->n_members; ++mem) {
             fb.member = mem;
             hipError_t e = m->arch.kind == 0 ? launch_tiny_forward(m, fb, st)
                                              : launch_wavenet_forward(m, fb, x_a, x_b, skip, st);
             if (e != hipSuccess) return e;
         }
-        if (after_batch) after_batch(ctx, bi, st);
+        if (after_batch) {
+            hipError_t e = after_batch(ctx, bi, st);
+            if (e != hipSuccess) return e;
+        }
     }
     return hipSuccess;
 }

@@ -95,6 +95,7 @@ struct gwd_model {
     int32_t batch_windows;                     // windows per layer-kernel batch
     int32_t last_nb = 0, last_T = 0;           // batch shape of the last gwd_forward (workspace contents)
     int64_t ws_tab_bytes = 0;                  // bytes reserved for the stream table at the workspace start
+    std::vector<int64_t> host_firsts;          // host copy of FwdBatch::firsts for the current request
     int32_t lp_waves = 0;                      // BF16/FP8 layer tiling: waves per block (0 = default per precision)
 };
 
@@ -121,6 +122,9 @@ struct FwdBatch {
     float* out;
     int64_t sum_L;      // total samples (stitched layout)
     int64_t total_win;  // total windows (mode 2 layout)
+    const int64_t* firsts;  // device: global index of each stream's first window (streams with windows)
+    int64_t first_idx;      // first entry of `firsts` inside this batch
+    int n_first;            // entries of `firsts` inside this batch
 };
 
 hipError_t launch_tiny_forward(const gwd_model* m, const FwdBatch& fb, hipStream_t st);
@@ -142,7 +146,7 @@ gwd_status forward_prepare(gwd_model* m, const gwd_stream* streams, int32_t n_st
                            int32_t out_mode, float* out, int64_t out_capacity_floats, hipStream_t st, bool sync_table,
                            FwdBatch& fb, int64_t& total_win, int& nb_max, std::vector<int64_t>* nwin_out);
 hipError_t forward_enqueue(gwd_model* m, FwdBatch fb, int64_t total_win, int nb_max, hipStream_t st,
-                           void (*after_batch)(void*, int64_t, hipStream_t), void* ctx);
+                           hipError_t (*after_batch)(void*, int64_t, hipStream_t), void* ctx);
 hipError_t launch_stamp(unsigned long long* slot, hipStream_t st);
 
 // Triggers (triggers.hip)

@@ -34,8 +34,8 @@ struct StampCtx {
     unsigned long long* stamps;
 };
 
-static void stamp_after_batch(void* ctx, int64_t bi, hipStream_t st) {
-    launch_stamp(((StampCtx*)ctx)->stamps + bi + 1, st);
+static hipError_t stamp_after_batch(void* ctx, int64_t bi, hipStream_t st) {
+    return launch_stamp(((StampCtx*)ctx)->stamps + bi + 1, st);
 }
 
 }  // namespace gwd
