@@ -259,20 +259,29 @@ gwd_status gwd_plan_launch(gwd_plan* plan, void* hip_stream);
 gwd_status gwd_plan_completion_us(gwd_plan* plan, double* per_stream_us, int32_t n_streams, double* total_us);
 void gwd_plan_free(gwd_plan* plan);
 
-/* Layer-kernel tiling of a model: waves per block of the BF16 layer kernel (4
- * or 8; 0 = default; other precisions have one tiling) and windows per batch
- * of layer launches (1..8192, default 512). Results do not depend on either. */
-gwd_status gwd_set_tiling(gwd_model* model, int32_t waves, int32_t batch_windows);
+/* Layer-kernel schedule of a model:
+ *   tile_rows, waves: tiling of the single-layer BF16/FP8 kernel, (64, 4),
+ *     (64, 8) or (128, 4); (0, 0) = default per precision (BF16 (64, 4), FP8
+ *     (64, 8)); FP32 models have one tiling and accept only (0, 0);
+ *   layers_per_launch: BF16 only, 3 = layers with dilations d, 2d, 4d of a
+ *     stack run as one fused launch (the default), 1 = one launch per layer;
+ *     0 = default; other precisions accept 0 or 1;
+ *   batch_windows: windows per batch of layer launches (1..8192, default 512).
+ * Results do not depend on any of them. GWD_ERR_ARG for other values. */
+gwd_status gwd_set_tiling(gwd_model* model, int32_t tile_rows, int32_t waves, int32_t layers_per_launch,
+                          int32_t batch_windows);
 
 /* Autotuner: times gwd_forward (out_mode 0) on the given request for every
- * tiling candidate (BF16: waves 4 and 8; batch 256, 512, 1024 windows), keeps
+ * schedule candidate (BF16: fused triples with the default tiling, and the
+ * three tilings one layer per launch; FP8: the three tilings; all: batch 256,
+ * 512, 1024 windows), keeps
  * the fastest on the model and reports it. If the environment variable
  * GWD_AUTOTUNE_CACHE names a file, a cached choice for the same (architecture,
  * precision, members, window, stride) is used instead of timing, and new
  * choices are appended to it. Synchronises hip_stream. */
 gwd_status gwd_autotune(gwd_model* model, const gwd_stream* streams, int32_t n_streams, int32_t window,
-                        int32_t stride, float* out, int64_t out_capacity_floats, int32_t* waves,
-                        int32_t* batch_windows, void* hip_stream);
+                        int32_t stride, float* out, int64_t out_capacity_floats, int32_t* tile_rows,
+                        int32_t* waves, int32_t* layers_per_launch, int32_t* batch_windows, void* hip_stream);
 
 /* Last error message of the calling thread ("" if none). */
 const char* gwd_last_error(void);
@@ -293,16 +302,19 @@ gwd_status gwd_debug_layer(gwd_model* model, int32_t member, int32_t layer, cons
                            float* skip_inout, void* hip_stream);
 gwd_status gwd_debug_export_weights(const gwd_model* model, int32_t member, float* out, int64_t n_params);
 
-/* Measurement support: launches middle gated layer `layer` (0 < layer < last) of
- * member `member` reps + 1 times exactly as gwd_forward does (same kernel, same
- * grid over the forward's batch of windows) on the activations the last
- * gwd_forward left in the model's workspace, and times the last `reps`
- * launches between two HIP events recorded on hip_stream. Writes the average
- * milliseconds per launch and the windows per launch. Requires a prior
+/* Measurement support: issues the launch that gwd_forward makes at middle gated
+ * layer `layer` of member `member` (the single-layer kernel, or the fused
+ * three-layer kernel when a BF16 triple starts there; every layer it covers
+ * must be a middle one) reps + 1 times, with the forward's grid over its batch
+ * of windows, on the activations the last gwd_forward left in the model's
+ * workspace, and times the last `reps` launches between two HIP events
+ * recorded on hip_stream. Writes the average milliseconds per launch, the
+ * windows per launch and the layers per launch (1 or 3). Requires a prior
  * gwd_forward on the model; synchronises hip_stream. The workspace contents
  * are overwritten. */
 gwd_status gwd_debug_time_layer(gwd_model* model, int32_t member, int32_t layer, int32_t reps,
-                                float* ms_per_launch, int32_t* windows_per_launch, void* hip_stream);
+                                float* ms_per_launch, int32_t* windows_per_launch, int32_t* layers_per_launch,
+                                void* hip_stream);
 
 #ifdef __cplusplus
 }

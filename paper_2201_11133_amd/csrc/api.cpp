@@ -396,11 +396,11 @@ gwd_status gwd_debug_layer(gwd_model* m, int32_t member, int32_t layer, const fl
 }
 
 gwd_status gwd_debug_time_layer(gwd_model* m, int32_t member, int32_t layer, int32_t reps, float* ms_per_launch,
-                                int32_t* windows_per_launch, void* hip_stream) {
-    if (!m || !ms_per_launch || !windows_per_launch) { set_error("gwd_debug_time_layer: NULL argument"); return GWD_ERR_ARG; }
+                                int32_t* windows_per_launch, int32_t* layers_per_launch_out, void* hip_stream) {
+    if (!m || !ms_per_launch || !windows_per_launch || !layers_per_launch_out) { set_error("gwd_debug_time_layer: NULL argument"); return GWD_ERR_ARG; }
     if (m->arch.kind != 1 || m->prec == GWD_FP64) { set_error("gwd_debug_time_layer: gated member, FP32/BF16/FP8 only"); return GWD_ERR_UNSUPPORTED; }
     const int L = m->arch.n_stacks * m->arch.layers_per_stack;
-    if (member < 0 || member >= m->n_members || layer < 1 || layer >= L - 1) { set_error("gwd_debug_time_layer: member or layer out of range (middle layers only)"); return GWD_ERR_ARG; }
+    if (member < 0 || member >= m->n_members || layer < 1 || layer + layers_per_launch(m, layer) > L - 1) { set_error("gwd_debug_time_layer: member or layer out of range (middle layers only)"); return GWD_ERR_ARG; }
     if (reps < 1 || reps > 1000) { set_error("gwd_debug_time_layer: reps not in [1, 1000]"); return GWD_ERR_ARG; }
     if (m->last_nb == 0 || !m->ws.base) { set_error("gwd_debug_time_layer: run gwd_forward on this model first"); return GWD_ERR_ARG; }
     hipStream_t st = (hipStream_t)hip_stream;
@@ -429,6 +429,7 @@ gwd_status gwd_debug_time_layer(gwd_model* m, int32_t member, int32_t layer, int
     if (e != hipSuccess) return hip_fail(e, "layer timing");
     *ms_per_launch = ms / reps;
     *windows_per_launch = m->last_nb;
+    *layers_per_launch_out = layers_per_launch(m, layer);
     return GWD_OK;
 }
 

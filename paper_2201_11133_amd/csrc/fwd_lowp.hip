@@ -11,11 +11,15 @@
 // paper's half-precision engine likewise keeps its activations in half precision); the skip sum
 // stays fp32.
 //
-// Tile: 64 time steps of one window. Wave w owns 32 RB rows starting at 32 RB (w / 4) and one
-// column pair: filter [32 q, 32 q + 32) and gate 128 + the same, q = w % 4, so the gate of a
-// channel is formed in the lane that holds both halves and each weight fragment feeds RB MFMAs.
-// The second GEMM runs in two passes (residual columns, then skip columns) so only one set of
-// accumulators is live at a time.
+// Tile: BM time steps of one window, WV waves. Wave w owns RB blocks of 32 rows starting at
+// 32 RB (w / 4) and one column pair: filter [32 q, 32 q + 32) and gate 128 + the same, q = w % 4,
+// so the gate of a channel is formed in the lane that holds both halves and each weight fragment
+// feeds RB MFMAs. Weight fragments stream from L2 into registers (they are the bulk of the
+// vector-memory traffic, so RB sets how often each is fetched per row); operand rows sit in LDS.
+// Tilings (rows x waves, row blocks per wave, waves per SIMD the registers are sized for):
+//   64 x 4 (RB 2, 4 waves/SIMD, phase 2 in two passes: residual columns, then skip columns)
+//   64 x 8 (RB 1, 4 waves/SIMD, two passes)
+//   128 x 4 (RB 4, 2 waves/SIMD, one pass: each operand fragment feeds both column blocks)
 #include "gwd_internal.h"
 #include "layer_common.h"
 
@@ -24,12 +28,6 @@ namespace gwd {
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef int intx8 __attribute__((ext_vector_type(8)));
-
-// Tile shape: 64 rows, 4 or 8 waves (2 or 1 row blocks per wave), <= 128 VGPRs for 4 waves per SIMD.
-// The default per precision (BF16 4 waves, FP8 8 waves) is the faster one measured on MI355X; the
-// autotuner can choose either per model and request.
-constexpr int LP_BM = 64;                       // rows per tile
-constexpr int LP_OCC = 4;                       // waves per SIMD the register budget is sized for
 
 struct LayerArgsLP {
     const uint16_t* x_in;  // residual stream, bf16 [rows][128]
@@ -66,11 +64,14 @@ __device__ inline uint32_t to_e4m3_pair(float a, float b) {
     return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false) & 0xffffu;
 }
 
-template <bool FP8, int W_>
+template <bool FP8, int RB_, int WV_>
 struct LP {
-    static constexpr int WAVES = W_;                // waves per block (groups of 4 column pairs): 4 or 8
-    static constexpr int RB = LP_BM * 4 / (32 * WAVES);  // 32-row blocks per wave (2 / 1)
+    static constexpr int WAVES = WV_;               // waves per block: 4 column pairs x WV/4 row groups
+    static constexpr int RB = RB_;                  // 32-row blocks per wave
+    static constexpr int BM = 8 * RB * WV_;         // rows per tile
     static constexpr int THREADS = 64 * WAVES;
+    static constexpr int OCC = RB * (FP8 ? 2 : 1) >= 4 ? 2 : 4;  // waves per SIMD the registers allow
+    static constexpr bool ONE_PASS = OCC == 2;      // phase 2: both column blocks in one pass
     static constexpr int EB = FP8 ? 1 : 2;          // bytes per operand element
     static constexpr int KSTEP = FP8 ? 64 : 16;     // k per MFMA
     static constexpr int FRAG = KSTEP / 2 * EB;     // bytes per lane per fragment (16 or 32)
@@ -78,9 +79,10 @@ struct LP {
     static constexpr int XROW = kC * 2 + 16;        // padded LDS row of the bf16 residual copy (FP8 only)
     static constexpr int NK1 = 2 * kC / KSTEP;      // MFMA steps of phase 1 (16 / 4)
     static constexpr int NK2 = kC / KSTEP;          // MFMA steps of phase 2 (8 / 2)
-    static constexpr int PF1 = FP8 ? 4 : 4;         // weight-fragment prefetch depth, phase 1
-    static constexpr int PF2 = FP8 ? 2 : 4;         // and phase 2
-    static constexpr int LDS = LP_BM * ROW + (FP8 ? LP_BM * XROW : 0);
+    static constexpr int PF1 = 4;                   // weight-fragment prefetch depth, phase 1
+    static constexpr int PF2 = (FP8 || ONE_PASS) ? 2 : 4;  // and phase 2 (one pass: 2 fragments per step)
+    static constexpr int LDS = BM * ROW + (FP8 ? BM * XROW : 0);
+    static constexpr int CH = BM * 32 / THREADS;    // 16-byte chunks staged per thread
 };
 
 template <bool FP8>
@@ -122,46 +124,78 @@ __device__ inline uint2 bf16x8_to_e4m3(uint4 v) {
     return make_uint2(o[0] | (o[1] << 16), o[2] | (o[3] << 16));
 }
 
-// One phase-2 pass: acc[i] = g rows of row block i times one 32-column block of Brs (K = 128).
-template <bool FP8, int WV>
-__device__ inline void phase2_pass(const uint8_t* Ar, const uint8_t* Bm, int lane, floatx16 (&acc)[LP<FP8, WV>::RB]) {
-    using T = LP<FP8, WV>;
-    constexpr int LP_RB = T::RB;
-    Frag<FP8> ring[T::PF2];
+// One phase-2 pass over NB 32-column blocks of Brs (K = 128): acc[c][i] = g rows of row block i
+// times column block c; each operand fragment read from LDS feeds NB MFMAs.
+template <bool FP8, int RB, int WV, int NB, int ROWB = LP<FP8, RB, WV>::ROW>
+__device__ inline void phase2_pass(const uint8_t* Ar, const uint8_t* const (&Bm)[NB], floatx16 (&acc)[NB][RB]) {
+    using T = LP<FP8, RB, WV>;
+    Frag<FP8> ring[T::PF2][NB];
 #pragma unroll
-    for (int j = 0; j < T::PF2; ++j) ring[j] = load_frag<FP8>(Bm + (size_t)j * 64 * T::FRAG);
+    for (int j = 0; j < T::PF2; ++j)
 #pragma unroll
-    for (int i = 0; i < LP_RB; ++i) acc[i] = floatx16{};
+        for (int c = 0; c < NB; ++c) ring[j][c] = load_frag<FP8>(Bm[c] + (size_t)j * 64 * T::FRAG);
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+#pragma unroll
+        for (int i = 0; i < RB; ++i) acc[c][i] = floatx16{};
 #pragma unroll
     for (int j = 0; j < T::NK2; ++j) {
         const int slot = j % T::PF2;
-        const Frag<FP8> cw = ring[slot];
-        if (j + T::PF2 < T::NK2) ring[slot] = load_frag<FP8>(Bm + (size_t)(j + T::PF2) * 64 * T::FRAG);
+        Frag<FP8> cw[NB];
 #pragma unroll
-        for (int i = 0; i < LP_RB; ++i) {
-            const Frag<FP8> a = load_frag<FP8>(Ar + i * 32 * T::ROW + j * T::KSTEP * T::EB);
-            acc[i] = mma<FP8>(a, cw, acc[i]);
+        for (int c = 0; c < NB; ++c) {
+            cw[c] = ring[slot][c];
+            if (j + T::PF2 < T::NK2) ring[slot][c] = load_frag<FP8>(Bm[c] + (size_t)(j + T::PF2) * 64 * T::FRAG);
+        }
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+            const Frag<FP8> a = load_frag<FP8>(Ar + i * 32 * ROWB + j * T::KSTEP * T::EB);
+#pragma unroll
+            for (int c = 0; c < NB; ++c) acc[c][i] = mma<FP8>(a, cw[c], acc[c][i]);
         }
     }
 }
 
-template <bool FP8, int WV, bool FROM_STREAM, bool SKIP_INIT, bool LAST>
-__global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(LP_OCC))) void layer_lp_kernel(LayerArgsLP p) {
-    using T = LP<FP8, WV>;
-    constexpr int LP_RB = T::RB;
-    constexpr int LP_THREADS = T::THREADS;
+// Residual epilogue of row block rb: x_out = x + (acc + b_res) (scaled for FP8), rounded to bf16.
+template <bool FP8, int RB, int WV>
+__device__ inline void residual_out(const floatx16& acc, const uint8_t* xr, uint16_t* xo, float br, float s_r) {
+    using T = LP<FP8, RB, WV>;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int dm = 8 * (i >> 2) + (i & 3);  // compile-time row offset
+        const float rv = FP8 ? fmaf(acc[i], s_r, br) : acc[i] + br;
+        const uint16_t xb = *(const uint16_t*)(xr + dm * (FP8 ? T::XROW : T::ROW));
+        xo[dm * kC] = to_bf16_bits(bf16_to_f32(xb) + rv);
+    }
+}
+
+// Skip epilogue of row block rb: skip (+)= acc + b_skip (scaled for FP8).
+template <bool FP8, bool SKIP_INIT>
+__device__ inline void skip_out(const floatx16& acc, float* sk, float bs, float s_s) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int dm = 8 * (i >> 2) + (i & 3);
+        const float sv = FP8 ? fmaf(acc[i], s_s, bs) : acc[i] + bs;
+        sk[dm * kC] = SKIP_INIT ? sv : sk[dm * kC] + sv;
+    }
+}
+
+template <bool FP8, int RB, int WV, bool FROM_STREAM, bool SKIP_INIT, bool LAST>
+__global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(LP<FP8, RB, WV>::OCC)))
+void layer_lp_kernel(LayerArgsLP p) {
+    using T = LP<FP8, RB, WV>;
+    constexpr int BM = T::BM;
     __shared__ __attribute__((aligned(16))) uint8_t lds[T::LDS];
-    uint8_t* A = lds;                     // operand tile [256][x[t-d] | x[t]]; g overwrites the first half
-    uint8_t* XR = lds + LP_BM * T::ROW;   // FP8: bf16 copy of x[t] (the residual base)
+    uint8_t* A = lds;                // operand tile [BM][x[t-d] | x[t]]; g overwrites the first half
+    uint8_t* XR = lds + BM * T::ROW;  // FP8: bf16 copy of x[t] (the residual base)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, r = lane & 31;
-    const int rh = wave >> 2, q = wave & 3;  // rows [32 LP_RB rh, +32 LP_RB), column pair q
+    const int rh = wave >> 2, q = wave & 3;  // rows [32 RB rh, +32 RB), column pair q
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     const int b = tile / p.tiles_per_window;
-    const int t0 = (tile - b * p.tiles_per_window) * LP_BM;
+    const int t0 = (tile - b * p.tiles_per_window) * BM;
     const int64_t row0 = (int64_t)b * p.T + t0;
-    constexpr int CH = LP_BM * 32 / LP_THREADS;  // 16-byte chunks staged per thread
 
-    // ---- stage A = [x[t-d] | x[t]]: 256 rows x 2 taps x 16 chunks of 8 channels
+    // ---- stage A = [x[t-d] | x[t]]: BM rows x 2 taps x 16 chunks of 8 channels
     {
         StreamDesc sd{};
         int64_t start = 0;
@@ -170,10 +204,10 @@ __global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(LP_OCC)
             sd = p.streams[find_stream(p.streams, p.n_streams, gw)];
             start = (gw - sd.win_begin) * p.S;
         }
-        uint4 v[CH];
+        uint4 v[T::CH];
 #pragma unroll
-        for (int it = 0; it < CH; ++it) {
-            const int idx = tid + LP_THREADS * it;
+        for (int it = 0; it < T::CH; ++it) {
+            const int idx = tid + T::THREADS * it;
             const int rr = idx >> 5, qq = idx & 31, tap = qq >> 4, c8 = 8 * (qq & 15);
             const int t = t0 + rr - (tap == 0 ? p.d : 0);
             v[it] = make_uint4(0, 0, 0, 0);
@@ -200,8 +234,8 @@ __global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(LP_OCC)
             }
         }
 #pragma unroll
-        for (int it = 0; it < CH; ++it) {
-            const int idx = tid + LP_THREADS * it;
+        for (int it = 0; it < T::CH; ++it) {
+            const int idx = tid + T::THREADS * it;
             const int rr = idx >> 5, qq = idx & 31, tap = qq >> 4, c8 = 8 * (qq & 15);
             if (FP8) {
                 *(uint2*)&A[rr * T::ROW + tap * kC + c8] = bf16x8_to_e4m3(v[it]);
@@ -213,11 +247,11 @@ __global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(LP_OCC)
     }
     __syncthreads();
 
-    // A fragment of row block i of this wave: row 128 rh + 32 i + r, k-half h
-    const uint8_t* Ar = &A[(32 * LP_RB * rh + r) * T::ROW + h * T::FRAG];
+    // A fragment of row block i of this wave: row 32 RB rh + 32 i + r, k-half h
+    const uint8_t* Ar = &A[(32 * RB * rh + r) * T::ROW + h * T::FRAG];
 
     // ---- phase 1: pre = A Bc, K = 256; weight fragments from a register ring PF1 steps deep
-    floatx16 af[LP_RB] = {}, ag[LP_RB] = {};
+    floatx16 af[RB] = {}, ag[RB] = {};
     {
         const uint8_t* Bf = p.wc + ((size_t)(q * T::NK1) * 64 + lane) * T::FRAG;        // filter block q
         const uint8_t* Bg = p.wc + ((size_t)((4 + q) * T::NK1) * 64 + lane) * T::FRAG;  // gate block 4 + q
@@ -236,7 +270,7 @@ __global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(LP_OCC)
                 rg[slot] = load_frag<FP8>(Bg + (size_t)(j + T::PF1) * 64 * T::FRAG);
             }
 #pragma unroll
-            for (int i = 0; i < LP_RB; ++i) {
+            for (int i = 0; i < RB; ++i) {
                 const Frag<FP8> a = load_frag<FP8>(Ar + i * 32 * T::ROW + j * T::KSTEP * T::EB);
                 af[i] = mma<FP8>(a, cf, af[i]);
                 ag[i] = mma<FP8>(a, cg, ag[i]);
@@ -251,10 +285,10 @@ __global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(LP_OCC)
         const float bf = p.bc[n], bg = p.bc[kC + n];
         const float sf = FP8 ? p.sc[n] : 1.f, sg = FP8 ? p.sc[kC + n] : 1.f;
 #pragma unroll
-        for (int rb = 0; rb < LP_RB; ++rb)
+        for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
-                const int m = 32 * LP_RB * rh + 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
+                const int m = 32 * RB * rh + 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
                 const float vf = FP8 ? fmaf(af[rb][i], sf, bf) : af[rb][i] + bf;
                 const float vg = FP8 ? fmaf(ag[rb][i], sg, bg) : ag[rb][i] + bg;
                 if (p.pre_out) {
@@ -270,67 +304,349 @@ __global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(LP_OCC)
     }
     __syncthreads();
 
-    // ---- phase 2: [res | skip] = g Brs, K = 128, in two passes (res, then skip) so that only one
-    // set of accumulators is live at a time; each pass ends in its part of the epilogue.
+    // ---- phase 2: [res | skip] = g Brs, K = 128, each pass ending in its part of the epilogue
     const int n = 32 * q + r;
-    if (!LAST) {
-        floatx16 acc[LP_RB];
-        phase2_pass<FP8, WV>(Ar, p.wrs + ((size_t)(q * T::NK2) * 64 + lane) * T::FRAG, lane, acc);
-        const float br = p.brs[n];
-        const float s_r = FP8 ? p.srs[n] : 1.f;
+    const uint8_t* Wres = p.wrs + ((size_t)(q * T::NK2) * 64 + lane) * T::FRAG;
+    const uint8_t* Wskip = p.wrs + ((size_t)((LAST ? q : 4 + q) * T::NK2) * 64 + lane) * T::FRAG;
+    const int cs = LAST ? n : kC + n;
+    const float bs = p.brs[cs];
+    const float s_s = FP8 ? p.srs[cs] : 1.f;
+    const float br = p.brs[n];
+    const float s_r = FP8 ? p.srs[n] : 1.f;
+    if (!LAST && T::ONE_PASS) {
+        floatx16 acc[2][RB];
+        const uint8_t* const bm[2] = {Wres, Wskip};
+        phase2_pass<FP8, RB, WV, 2>(Ar, bm, acc);
+        __builtin_amdgcn_sched_barrier(0);  // epilogue loads stay after the MFMAs (register pressure)
 #pragma unroll
-        for (int rb = 0; rb < LP_RB; ++rb) {
-            const int mb = 32 * LP_RB * rh + 32 * rb + 4 * h;        // first row of this lane in the block
-            uint16_t* xo = p.x_out + (row0 + mb) * kC + n;
+        for (int rb = 0; rb < RB; ++rb) {
+            const int mb = 32 * RB * rh + 32 * rb + 4 * h;  // first row of this lane in the block
             const uint8_t* xr = FP8 ? &XR[mb * T::XROW + 2 * n] : &A[mb * T::ROW + 2 * (kC + n)];
+            residual_out<FP8, RB, WV>(acc[0][rb], xr, p.x_out + (row0 + mb) * kC + n, br, s_r);
+            skip_out<FP8, SKIP_INIT>(acc[1][rb], p.skip + (row0 + mb) * kC + n, bs, s_s);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        return;
+    }
+    if (!LAST) {
+        floatx16 acc[1][RB];
+        const uint8_t* const bm[1] = {Wres};
+        phase2_pass<FP8, RB, WV, 1>(Ar, bm, acc);
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int dm = 8 * (i >> 2) + (i & 3);                  // compile-time row offset
-                const float rv = FP8 ? fmaf(acc[rb][i], s_r, br) : acc[rb][i] + br;
-                const uint16_t xb = *(const uint16_t*)(xr + dm * (FP8 ? T::XROW : T::ROW));
-                xo[dm * kC] = to_bf16_bits(bf16_to_f32(xb) + rv);
-            }
+        for (int rb = 0; rb < RB; ++rb) {
+            const int mb = 32 * RB * rh + 32 * rb + 4 * h;
+            const uint8_t* xr = FP8 ? &XR[mb * T::XROW + 2 * n] : &A[mb * T::ROW + 2 * (kC + n)];
+            residual_out<FP8, RB, WV>(acc[0][rb], xr, p.x_out + (row0 + mb) * kC + n, br, s_r);
         }
         __builtin_amdgcn_sched_barrier(0);
     }
     {
-        floatx16 acc[LP_RB];
-        phase2_pass<FP8, WV>(Ar, p.wrs + ((size_t)((LAST ? q : 4 + q) * T::NK2) * 64 + lane) * T::FRAG, lane, acc);
-        const int cs = LAST ? n : kC + n;
-        const float bs = p.brs[cs];
-        const float s_s = FP8 ? p.srs[cs] : 1.f;
+        floatx16 acc[1][RB];
+        const uint8_t* const bm[1] = {Wskip};
+        phase2_pass<FP8, RB, WV, 1>(Ar, bm, acc);
 #pragma unroll
-        for (int rb = 0; rb < LP_RB; ++rb) {
-            float* sk = p.skip + (row0 + 32 * LP_RB * rh + 32 * rb + 4 * h) * kC + n;
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int dm = 8 * (i >> 2) + (i & 3);
-                const float sv = FP8 ? fmaf(acc[rb][i], s_s, bs) : acc[rb][i] + bs;
-                sk[dm * kC] = SKIP_INIT ? sv : sk[dm * kC] + sv;
-            }
+        for (int rb = 0; rb < RB; ++rb) {
+            const int mb = 32 * RB * rh + 32 * rb + 4 * h;
+            skip_out<FP8, SKIP_INIT>(acc[0][rb], p.skip + (row0 + mb) * kC + n, bs, s_s);
         }
     }
 }
 
-template <bool FP8, int WV, bool A_, bool B_, bool C_>
-static hipError_t launch_lp_w(const LayerArgsLP& a, int nblocks, hipStream_t st) {
-    hipLaunchKernelGGL((layer_lp_kernel<FP8, WV, A_, B_, C_>), dim3(nblocks), dim3(LP<FP8, WV>::THREADS), 0, st, a);
+// Layer-kernel tilings (rows per tile, waves per block); the first one of each precision is its
+// default.
+enum LpTile { LP_64x4 = 0, LP_64x8 = 1, LP_128x4 = 2 };
+
+template <bool FP8, int RB, int WV, bool A_, bool B_, bool C_>
+static hipError_t launch_lp_t(const LayerArgsLP& a, int nb, hipStream_t st) {
+    using T = LP<FP8, RB, WV>;
+    LayerArgsLP b = a;
+    b.tiles_per_window = a.T / T::BM;
+    hipLaunchKernelGGL((layer_lp_kernel<FP8, RB, WV, A_, B_, C_>), dim3(nb * b.tiles_per_window), dim3(T::THREADS),
+                       0, st, b);
     return hipGetLastError();
 }
-// waves per block: 4 or 8 (a per-model choice: default per precision, or the autotuner's pick)
 template <bool FP8, bool A_, bool B_, bool C_>
-static hipError_t launch_lp(const LayerArgsLP& a, int nblocks, int waves, hipStream_t st) {
-    // FP8 always uses 8 waves (its 4-wave tiling does not fit 128 registers)
-    if constexpr (FP8) {
-        (void)waves;
-        return launch_lp_w<true, 8, A_, B_, C_>(a, nblocks, st);
-    } else {
-        if (waves == 8) return launch_lp_w<false, 8, A_, B_, C_>(a, nblocks, st);
-        return launch_lp_w<false, 4, A_, B_, C_>(a, nblocks, st);
+static hipError_t launch_lp(const LayerArgsLP& a, int nb, int tiling, hipStream_t st) {
+    switch (tiling) {
+        case LP_64x8: return launch_lp_t<FP8, 1, 8, A_, B_, C_>(a, nb, st);
+        case LP_128x4: return launch_lp_t<FP8, 4, 4, A_, B_, C_>(a, nb, st);
+        default: return launch_lp_t<FP8, 2, 4, A_, B_, C_>(a, nb, st);
     }
 }
 
-static int lp_waves(const gwd_model* m, bool fp8) { return m->lp_waves ? m->lp_waves : (fp8 ? 8 : 4); }
+// The model's tiling choice: 0 = default per precision (BF16 64 x 4, FP8 64 x 8).
+static int lp_tiling(const gwd_model* m, bool fp8) {
+    if (m->lp_rows == 128) return LP_128x4;
+    if (m->lp_rows == 64) return m->lp_waves == 8 ? LP_64x8 : LP_64x4;
+    return fp8 ? LP_64x8 : LP_64x4;
+}
+
+// ---------------------------------------------------------------- fused layer triples (BF16)
+// Three consecutive layers of a stack, with dilations d0, 2 d0 and 4 d0, in one launch. Split a
+// window's rows by t mod d0 into d0 interleaved sub-sequences (t = p + d0 s): on each of them the
+// three layers are causal convolutions with dilations 1, 2 and 4 (the space-to-batch form of a
+// dilated convolution). A block walks 64-row chunks of one sub-sequence in time order and runs
+// the three layers on each chunk in LDS. Each layer's input buffer keeps the last 1 / 2 / 4 rows
+// of the previous chunk in front of the current one, so nothing is recomputed, and the skip sum of
+// the chunk stays in registers across the three layers: x and skip cross HBM once per three
+// layers instead of once per layer. Long sub-sequences (d0 = 1) are split into segments that
+// start with one warm-up chunk, computed only to rebuild those history rows; its outputs are not
+// stored. Every output is computed with the same operations, in the same order, as by three
+// launches of the single-layer kernel.
+constexpr int FU_ROWS = 64;                                // sub-rows per chunk (2 row blocks x 4 waves)
+constexpr int FU_HIST = 4;                                 // history rows in front of each input buffer
+constexpr int FU_XROW = 2 * kC + 16;                       // bf16 row + 16-byte pad
+constexpr int FU_XBUF = (FU_ROWS + FU_HIST) * FU_XROW;     // one input buffer with its history
+constexpr int FU_LDS = 3 * FU_XBUF + FU_ROWS * FU_XROW;    // three input buffers + the gate buffer
+
+struct FusedArgs {
+    const uint16_t* x_in;  // residual stream, bf16 [rows][128]
+    uint16_t* x_out;
+    float* skip;
+    const uint8_t* wc[3];
+    const float* bc[3];
+    const uint8_t* wrs[3];
+    const float* brs[3];
+    int d0, T;             // dilation of the first layer; window length
+    int n_seg, seg_chunks; // segments per sub-sequence, chunks per segment
+    const StreamDesc* streams;
+    int n_streams;
+    int64_t win_base;
+    int S;
+    const float* w_in;
+    const float* b_in;
+};
+
+__device__ inline uint8_t* fu_buf(uint8_t* lds, int j) { return lds + j * FU_XBUF + FU_HIST * FU_XROW; }
+
+template <bool FROM_STREAM, bool SKIP_INIT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void fused3_bf16_kernel(FusedArgs p) {
+    using T = LP<false, 2, 4>;  // bf16 fragments, 4 waves x 2 row blocks
+    __shared__ __attribute__((aligned(16))) uint8_t lds[FU_LDS];
+    uint8_t* G = lds + 3 * FU_XBUF;
+    const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6, h = lane >> 5, r = lane & 31;
+    const int seg = blockIdx.x % p.n_seg;
+    const int cls = (blockIdx.x / p.n_seg) % p.d0;
+    const int b = blockIdx.x / (p.n_seg * p.d0);
+    const int n_sub = (p.T - cls + p.d0 - 1) / p.d0;  // rows of this sub-sequence
+    const int n_ch = (n_sub + FU_ROWS - 1) / FU_ROWS;
+    const int c0 = seg * p.seg_chunks;
+    if (c0 >= n_ch) return;  // uniform over the block
+    const int c1 = min(c0 + p.seg_chunks, n_ch);
+    const int64_t wrow0 = (int64_t)b * p.T;
+    StreamDesc sd{};
+    int64_t start = 0;
+    if (FROM_STREAM) {
+        const int64_t gw = p.win_base + b;
+        sd = p.streams[find_stream(p.streams, p.n_streams, gw)];
+        start = (gw - sd.win_begin) * p.S;
+    }
+    // causal zero padding: the rows before the sub-sequence start are zero for every layer
+    for (int idx = tid; idx < 3 * FU_HIST * 16; idx += 256) {
+        const int j = idx / (FU_HIST * 16), rr = (idx >> 4) % FU_HIST, c = idx & 15;
+        *(uint4*)(fu_buf(lds, j) + (rr - FU_HIST) * FU_XROW + 16 * c) = make_uint4(0, 0, 0, 0);
+    }
+    const int n = 32 * q + r;
+    for (int c = (seg > 0 ? c0 - 1 : c0); c < c1; ++c) {
+        const bool store = c >= c0;
+        const int sb = c * FU_ROWS;
+        // ---- stage the first layer's input rows [0, 64) of the chunk; prefetch the skip rows
+        uint4 v[4];
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+            const int idx = tid + 256 * it, rr = idx >> 4, c8 = 8 * (idx & 15);
+            const int sr = sb + rr;
+            const int t = cls + p.d0 * sr;
+            v[it] = make_uint4(0, 0, 0, 0);
+            if (sr < n_sub) {
+                if (FROM_STREAM) {  // input projection x0 = W_in u[t] + b_in, rounded to bf16
+                    float u0 = 0.f, u1 = 0.f;
+                    const int64_t smp = start + t;
+                    if (smp < sd.length) {
+                        u0 = sd.ch0[smp * sd.stride];
+                        u1 = sd.ch1[smp * sd.stride];
+                    }
+                    uint32_t w[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int ch = c8 + 2 * e;
+                        const float x0 = p.b_in[ch] + p.w_in[2 * ch] * u0 + p.w_in[2 * ch + 1] * u1;
+                        const float x1 = p.b_in[ch + 1] + p.w_in[2 * ch + 2] * u0 + p.w_in[2 * ch + 3] * u1;
+                        w[e] = (uint32_t)to_bf16_bits(x0) | ((uint32_t)to_bf16_bits(x1) << 16);
+                    }
+                    v[it] = make_uint4(w[0], w[1], w[2], w[3]);
+                } else {
+                    v[it] = *(const uint4*)&p.x_in[(wrow0 + t) * kC + c8];
+                }
+            }
+        }
+        float sk[2][16];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int sr = sb + 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
+                sk[rb][i] = (!SKIP_INIT && store && sr < n_sub) ? p.skip[(wrow0 + cls + p.d0 * sr) * kC + n] : 0.f;
+            }
+        uint8_t* X0 = fu_buf(lds, 0);
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+            const int idx = tid + 256 * it, rr = idx >> 4, c8 = 8 * (idx & 15);
+            *(uint4*)(X0 + rr * FU_XROW + 2 * c8) = v[it];
+        }
+        __syncthreads();
+
+#pragma unroll 1
+        for (int j = 0; j < 3; ++j) {
+            const int dil = 1 << j;  // dilation in sub-rows
+            uint8_t* Xin = fu_buf(lds, j);
+            uint8_t* Xo = fu_buf(lds, j < 2 ? j + 1 : 0);  // the last layer's output goes to buffer 0
+            // biases first: their loads complete behind phase 1
+            const float bf = p.bc[j][n], bg = p.bc[j][kC + n], br = p.brs[j][n], bs = p.brs[j][kC + n];
+            // ---- phase 1: pre = [x[s - dil] | x[s]] Bc, K = 256 (k-steps 0-7: tap s - dil, 8-15: tap s);
+            // weight fragments from a register ring, operand fragments one step ahead
+            floatx16 af[2] = {}, ag[2] = {};
+            {
+                const uint8_t* A0 = Xin + r * FU_XROW + 16 * h;
+                const uint8_t* Bf = p.wc[j] + ((size_t)(q * T::NK1) * 64 + lane) * T::FRAG;
+                const uint8_t* Bg = p.wc[j] + ((size_t)((4 + q) * T::NK1) * 64 + lane) * T::FRAG;
+                Frag<false> rf[T::PF1], rg[T::PF1];
+#pragma unroll
+                for (int k = 0; k < T::PF1; ++k) {
+                    rf[k] = load_frag<false>(Bf + (size_t)k * 64 * T::FRAG);
+                    rg[k] = load_frag<false>(Bg + (size_t)k * 64 * T::FRAG);
+                }
+                Frag<false> acur[2], anxt[2];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) acur[i] = load_frag<false>(A0 + (32 * i - dil) * FU_XROW);
+#pragma unroll
+                for (int k = 0; k < T::NK1; ++k) {
+                    const int slot = k % T::PF1;
+                    const Frag<false> cf = rf[slot], cg = rg[slot];
+                    if (k + T::PF1 < T::NK1) {
+                        rf[slot] = load_frag<false>(Bf + (size_t)(k + T::PF1) * 64 * T::FRAG);
+                        rg[slot] = load_frag<false>(Bg + (size_t)(k + T::PF1) * 64 * T::FRAG);
+                    }
+                    if (k + 1 < T::NK1) {
+                        const int roff = k + 1 < T::NK1 / 2 ? -dil : 0;
+#pragma unroll
+                        for (int i = 0; i < 2; ++i)
+                            anxt[i] = load_frag<false>(A0 + (32 * i + roff) * FU_XROW + 32 * ((k + 1) & 7));
+                    }
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) {
+                        af[i] = mma<false>(acur[i], cf, af[i]);
+                        ag[i] = mma<false>(acur[i], cg, ag[i]);
+                    }
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) acur[i] = anxt[i];
+                }
+            }
+            // first weight fragments of the residual pass: in flight during the gate
+            const uint8_t* Wr = p.wrs[j] + ((size_t)(q * T::NK2) * 64 + lane) * T::FRAG;
+            const uint8_t* Ws = p.wrs[j] + ((size_t)((4 + q) * T::NK2) * 64 + lane) * T::FRAG;
+            Frag<false> ring[T::PF2];
+#pragma unroll
+            for (int k = 0; k < T::PF2; ++k) ring[k] = load_frag<false>(Wr + (size_t)k * 64 * T::FRAG);
+            __syncthreads();  // every wave is done with this layer's input rows
+            // this input's last dil rows become the history of the next chunk
+            if (tid < 16 * dil) {
+                const int rr = tid >> 4, cc = tid & 15;
+                *(uint4*)(Xin + (rr - dil) * FU_XROW + 16 * cc) = *(const uint4*)(Xin + (FU_ROWS - dil + rr) * FU_XROW + 16 * cc);
+            }
+            // ---- gate -> G
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int m = 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
+                    *(uint16_t*)&G[m * FU_XROW + 2 * n] = to_bf16_bits(gate_fast(af[rb][i] + bf, ag[rb][i] + bg));
+                    if (i == 15) __builtin_amdgcn_sched_barrier(0);
+                }
+            __syncthreads();
+            // ---- phase 2 over G (K = 128): residual columns, then skip columns
+            const uint8_t* Ag = G + r * FU_XROW + 16 * h;
+#pragma unroll
+            for (int pass = 0; pass < 2; ++pass) {
+                const uint8_t* Wm = pass == 0 ? Wr : Ws;
+                if (pass == 1) {
+#pragma unroll
+                    for (int k = 0; k < T::PF2; ++k) ring[k] = load_frag<false>(Ws + (size_t)k * 64 * T::FRAG);
+                }
+                // residual inputs of this lane, gathered before any output is written
+                uint32_t xold[2][8];
+                if (pass == 0) {
+#pragma unroll
+                    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                        for (int i = 0; i < 16; i += 2) {
+                            const int m = 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
+                            const uint32_t lo = *(const uint16_t*)(Xin + m * FU_XROW + 2 * n);
+                            const uint32_t hi = *(const uint16_t*)(Xin + (m + 1) * FU_XROW + 2 * n);
+                            xold[rb][i >> 1] = lo | (hi << 16);
+                        }
+                }
+                floatx16 acc[2] = {};
+                Frag<false> acur[2], anxt[2];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) acur[i] = load_frag<false>(Ag + 32 * i * FU_XROW);
+#pragma unroll
+                for (int k = 0; k < T::NK2; ++k) {
+                    const int slot = k % T::PF2;
+                    const Frag<false> cw = ring[slot];
+                    if (k + T::PF2 < T::NK2) ring[slot] = load_frag<false>(Wm + (size_t)(k + T::PF2) * 64 * T::FRAG);
+                    if (k + 1 < T::NK2) {
+#pragma unroll
+                        for (int i = 0; i < 2; ++i) anxt[i] = load_frag<false>(Ag + 32 * i * FU_XROW + 32 * (k + 1));
+                    }
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) acc[i] = mma<false>(acur[i], cw, acc[i]);
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) acur[i] = anxt[i];
+                }
+                if (pass == 0) {  // x_next = x + (g Brs_res + b_res), rounded to bf16
+#pragma unroll
+                    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                        for (int i = 0; i < 16; ++i) {
+                            const int m = 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
+                            const uint32_t w = xold[rb][i >> 1];
+                            const uint16_t xb = (uint16_t)((i & 1) ? (w >> 16) : (w & 0xffffu));
+                            *(uint16_t*)(Xo + m * FU_XROW + 2 * n) = to_bf16_bits(bf16_to_f32(xb) + (acc[rb][i] + br));
+                        }
+                    __builtin_amdgcn_sched_barrier(0);
+                } else {  // skip += g Brs_skip + b_skip
+#pragma unroll
+                    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                        for (int i = 0; i < 16; ++i) {
+                            const float sv = acc[rb][i] + bs;
+                            sk[rb][i] = (SKIP_INIT && j == 0) ? sv : sk[rb][i] + sv;
+                        }
+                }
+            }
+            __syncthreads();  // the next layer's input (or the chunk's output) is complete
+        }
+        // ---- chunk output: x rows from buffer 0 (16-byte stores), skip from registers
+        if (store) {
+#pragma unroll
+            for (int it = 0; it < 4; ++it) {
+                const int idx = tid + 256 * it, rr = idx >> 4, c8 = 8 * (idx & 15);
+                const int sr = sb + rr;
+                if (sr < n_sub)
+                    *(uint4*)&p.x_out[(wrow0 + cls + p.d0 * sr) * kC + c8] = *(const uint4*)(X0 + rr * FU_XROW + 2 * c8);
+            }
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int sr = sb + 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
+                    if (sr < n_sub) p.skip[(wrow0 + cls + p.d0 * sr) * kC + n] = sk[rb][i];
+                }
+        }
+        __syncthreads();  // buffer 0 is read above before the next chunk stages into it
+    }
+}
 
 template <bool FP8>
 static LayerArgsLP lp_args(gwd_model* m, int member, int l) {
@@ -351,30 +667,79 @@ static LayerArgsLP lp_args(gwd_model* m, int member, int l) {
     return a;
 }
 
+// Does layer l start a fused triple? Triples (i, i+1, i+2) with i % 3 == 0 inside a stack, never
+// holding the network's last layer (that one writes no residual).
+static bool fused_start(const gwd_model* m, int l) {
+    if (m->prec != GWD_BF16 || m->lp_fuse != 3) return false;
+    const int lps = m->arch.layers_per_stack, L = m->arch.n_stacks * lps, i = l % lps;
+    return i % 3 == 0 && i + 2 < lps && l + 2 < L - 1;
+}
+
+// One fused launch of layers l, l+1, l+2 over nb windows of length T.
+static hipError_t launch_fused3(gwd_model* m, int member, int l, const uint16_t* x_in, uint16_t* x_out, float* skip,
+                                int nb, int T, const FwdBatch* fb, hipStream_t st) {
+    FusedArgs a{};
+    for (int j = 0; j < 3; ++j) {
+        const LayerArgsLP la = lp_args<false>(m, member, l + j);
+        a.wc[j] = la.wc;
+        a.bc[j] = la.bc;
+        a.wrs[j] = la.wrs;
+        a.brs[j] = la.brs;
+        if (j == 0) { a.w_in = la.w_in; a.b_in = la.b_in; }
+    }
+    a.x_in = x_in;
+    a.x_out = x_out;
+    a.skip = skip;
+    a.d0 = 1 << (l % m->arch.layers_per_stack);
+    a.T = T;
+    const int n_ch = ((T + a.d0 - 1) / a.d0 + FU_ROWS - 1) / FU_ROWS;  // chunks of the longest sub-sequence
+    // enough blocks to fill the chip (>= 2048); a segment after the first costs one warm-up chunk
+    const int64_t per = (int64_t)nb * a.d0;
+    const int want = (int)std::min<int64_t>(n_ch, std::max<int64_t>(1, (2048 + per - 1) / per));
+    a.seg_chunks = (n_ch + want - 1) / want;
+    a.n_seg = (n_ch + a.seg_chunks - 1) / a.seg_chunks;
+    const bool first = l == 0;
+    if (first) {
+        a.streams = fb->streams;
+        a.n_streams = fb->n_streams;
+        a.win_base = fb->win_base;
+        a.S = fb->S;
+    }
+    const dim3 grid((unsigned)(per * a.n_seg));
+    if (first) hipLaunchKernelGGL((fused3_bf16_kernel<true, true>), grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((fused3_bf16_kernel<false, false>), grid, dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
 template <bool FP8>
 static hipError_t layers_lp(gwd_model* m, const FwdBatch& fb, float* x_a, float* x_b, float* skip, hipStream_t st) {
     const int L = m->arch.n_stacks * m->arch.layers_per_stack;
-    const int tpw = fb.T / LP_BM;
-    const int nblocks = fb.nb * tpw;
+    const int tiling = lp_tiling(m, FP8);
     // the residual stream is bf16 here: the fp32 workspace buffers hold it with room to spare
     uint16_t* xin = (uint16_t*)x_a;
     uint16_t* xout = (uint16_t*)x_b;
     for (int l = 0; l < L; ++l) {
+        if (!FP8 && fused_start(m, l)) {
+            hipError_t e = launch_fused3(m, fb.member, l, xin, xout, skip, fb.nb, fb.T, &fb, st);
+            if (e != hipSuccess) return e;
+            uint16_t* t = xin; xin = xout; xout = t;
+            l += 2;
+            continue;
+        }
         LayerArgsLP a = lp_args<FP8>(m, fb.member, l);
         a.x_in = xin;
         a.x_out = xout;
         a.skip = skip;
         a.pre_out = nullptr;
         a.T = fb.T;
-        a.tiles_per_window = tpw;
         a.streams = fb.streams;
         a.n_streams = fb.n_streams;
         a.win_base = fb.win_base;
         a.S = fb.S;
         hipError_t e;
-        if (l == 0) e = launch_lp<FP8, true, true, false>(a, nblocks, lp_waves(m, FP8), st);
-        else if (l < L - 1) e = launch_lp<FP8, false, false, false>(a, nblocks, lp_waves(m, FP8), st);
-        else e = launch_lp<FP8, false, false, true>(a, nblocks, lp_waves(m, FP8), st);
+        if (l == 0) e = launch_lp<FP8, true, true, false>(a, fb.nb, tiling, st);
+        else if (l < L - 1) e = launch_lp<FP8, false, false, false>(a, fb.nb, tiling, st);
+        else e = launch_lp<FP8, false, false, true>(a, fb.nb, tiling, st);
         if (e != hipSuccess) return e;
         uint16_t* t = xin; xin = xout; xout = t;
     }
@@ -408,12 +773,11 @@ static hipError_t debug_lp(gwd_model* m, int member, int l, const float* x_in, i
     a.skip = skip;
     a.pre_out = pre_out;
     a.T = T;
-    a.tiles_per_window = T / LP_BM;
-    const int nblocks = nb * (T / LP_BM);
-    if (l == 0) e = (L == 1) ? launch_lp<FP8, false, true, true>(a, nblocks, lp_waves(m, FP8), st)
-                             : launch_lp<FP8, false, true, false>(a, nblocks, lp_waves(m, FP8), st);
-    else if (l < L - 1) e = launch_lp<FP8, false, false, false>(a, nblocks, lp_waves(m, FP8), st);
-    else e = launch_lp<FP8, false, false, true>(a, nblocks, lp_waves(m, FP8), st);
+    const int tiling = lp_tiling(m, FP8);
+    if (l == 0) e = (L == 1) ? launch_lp<FP8, false, true, true>(a, nb, tiling, st)
+                             : launch_lp<FP8, false, true, false>(a, nb, tiling, st);
+    else if (l < L - 1) e = launch_lp<FP8, false, false, false>(a, nb, tiling, st);
+    else e = launch_lp<FP8, false, false, true>(a, nb, tiling, st);
     if (e == hipSuccess && x_out && l < L - 1)
         hipLaunchKernelGGL(bf16_to_f32_kernel, dim3(nblk), dim3(256), 0, st, tmp + n, n, x_out);
     hipError_t e2 = hipFreeAsync(tmp, st);
@@ -424,15 +788,17 @@ static hipError_t debug_lp(gwd_model* m, int member, int l, const float* x_in, i
 template <bool FP8>
 static hipError_t production_lp(gwd_model* m, int member, int l, void* x_in, void* x_out, float* skip, int nb, int T,
                                 hipStream_t st) {
+    if (!FP8 && fused_start(m, l) && l > 0)
+        return launch_fused3(m, member, l, (const uint16_t*)x_in, (uint16_t*)x_out, skip, nb, T, nullptr, st);
     LayerArgsLP a = lp_args<FP8>(m, member, l);
     a.x_in = (const uint16_t*)x_in;
     a.x_out = (uint16_t*)x_out;
     a.skip = skip;
     a.pre_out = nullptr;
     a.T = T;
-    a.tiles_per_window = T / LP_BM;
-    return launch_lp<FP8, false, false, false>(a, nb * (T / LP_BM), lp_waves(m, FP8), st);
+    return launch_lp<FP8, false, false, false>(a, nb, lp_tiling(m, FP8), st);
 }
+int layers_per_launch_bf16(const gwd_model* m, int l) { return fused_start(m, l) ? 3 : 1; }
 hipError_t layer_production_bf16(gwd_model* m, int member, int l, void* xi, void* xo, float* sk, int nb, int T,
                                  hipStream_t st) {
     return production_lp<false>(m, member, l, xi, xo, sk, nb, T, st);

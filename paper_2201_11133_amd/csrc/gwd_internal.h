@@ -96,7 +96,9 @@ struct gwd_model {
     int32_t last_nb = 0, last_T = 0;           // batch shape of the last gwd_forward (workspace contents)
     int64_t ws_tab_bytes = 0;                  // bytes reserved for the stream table at the workspace start
     std::vector<int64_t> host_firsts;          // host copy of FwdBatch::firsts for the current request
-    int32_t lp_waves = 0;                      // BF16/FP8 layer tiling: waves per block (0 = default per precision)
+    int32_t lp_rows = 0;                       // BF16/FP8 layer tiling: rows per tile (0 = default per precision)
+    int32_t lp_waves = 0;                      // and waves per block
+    int32_t lp_fuse = 3;                       // BF16: layers per launch (3 = fused triples, 1 = one per launch)
 };
 
 namespace gwd {
@@ -133,6 +135,8 @@ hipError_t launch_wavenet_forward(gwd_model* m, const FwdBatch& fb, float* x_a, 
 hipError_t launch_layer_debug(gwd_model* m, int member, int layer, const float* x_in, int nb, int T,
                               float* pre_out, float* x_out, float* skip, hipStream_t st);
 
+// Layers covered by the launch that starts at layer l (3 for a fused BF16 triple, else 1).
+int layers_per_launch(const gwd_model* m, int l);
 // One production launch of a middle layer on the workspace buffers (timing support).
 hipError_t launch_layer_production(gwd_model* m, int member, int layer, void* x_in, void* x_out, float* skip, int nb,
                                    int T, hipStream_t st);

@@ -297,6 +297,9 @@ hipError_t launch_layer_production(gwd_model* m, int member, int layer, void* x_
     }
 }
 
+int layers_per_launch_bf16(const gwd_model* m, int l);
+int layers_per_launch(const gwd_model* m, int l) { return m->prec == GWD_BF16 ? layers_per_launch_bf16(m, l) : 1; }
+
 hipError_t launch_layer_debug(gwd_model* m, int member, int layer, const float* x_in, int nb, int T, float* pre_out,
                               float* x_out, float* skip, hipStream_t st) {
     switch (m->prec) {

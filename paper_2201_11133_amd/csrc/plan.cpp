@@ -147,42 +147,64 @@ void gwd_plan_free(gwd_plan* p) {
     delete p;
 }
 
-gwd_status gwd_set_tiling(gwd_model* m, int32_t waves, int32_t batch_windows) {
+gwd_status gwd_set_tiling(gwd_model* m, int32_t tile_rows, int32_t waves, int32_t layers_per_launch,
+                          int32_t batch_windows) {
     if (!m) { set_error("gwd_set_tiling: model is NULL"); return GWD_ERR_ARG; }
-    if (waves != 0 && waves != 4 && waves != 8) { set_error("gwd_set_tiling: waves must be 0, 4 or 8"); return GWD_ERR_ARG; }
+    const bool lowp = m->arch.kind == 1 && (m->prec == GWD_BF16 || m->prec == GWD_FP8_E4M3);
+    const bool dflt = tile_rows == 0 && waves == 0;
+    const bool known = (tile_rows == 64 && (waves == 4 || waves == 8)) || (tile_rows == 128 && waves == 4);
+    if (!dflt && !(lowp && known)) {
+        set_error("gwd_set_tiling: (%d rows, %d waves) is not a tiling of this model", tile_rows, waves);
+        return GWD_ERR_ARG;
+    }
+    const bool fusable = m->arch.kind == 1 && m->prec == GWD_BF16;
+    if (!(layers_per_launch == 0 || layers_per_launch == 1 || (layers_per_launch == 3 && fusable))) {
+        set_error("gwd_set_tiling: %d layers per launch not available for this model", layers_per_launch);
+        return GWD_ERR_ARG;
+    }
     if (batch_windows < 1 || batch_windows > 8192) { set_error("gwd_set_tiling: batch_windows not in [1, 8192]"); return GWD_ERR_ARG; }
+    m->lp_rows = tile_rows;
     m->lp_waves = waves;
+    m->lp_fuse = layers_per_launch == 0 ? 3 : layers_per_launch;
     m->batch_windows = batch_windows;
     return GWD_OK;
 }
 
+namespace {
+struct Sched {
+    int rows, waves, fuse;
+};
+}  // namespace
+
 gwd_status gwd_autotune(gwd_model* m, const gwd_stream* streams, int32_t n_streams, int32_t window, int32_t stride,
-                        float* out, int64_t out_capacity_floats, int32_t* waves_out, int32_t* batch_out,
-                        void* hip_stream) {
-    if (!m || !waves_out || !batch_out) { set_error("gwd_autotune: NULL argument"); return GWD_ERR_ARG; }
+                        float* out, int64_t out_capacity_floats, int32_t* rows_out, int32_t* waves_out,
+                        int32_t* fuse_out, int32_t* batch_out, void* hip_stream) {
+    if (!m || !rows_out || !waves_out || !fuse_out || !batch_out) { set_error("gwd_autotune: NULL argument"); return GWD_ERR_ARG; }
     hipStream_t st = (hipStream_t)hip_stream;
     const char* cache = getenv("GWD_AUTOTUNE_CACHE");
     char key[160];
     snprintf(key, sizeof key, "gfx950 kind%d prec%d members%d W%d S%d", m->arch.kind, (int)m->prec, m->n_members,
              window, stride);
-    if (cache) {  // "key waves batch" lines
+    if (cache) {  // "key rows waves layers_per_launch batch" lines
         if (FILE* f = fopen(cache, "r")) {
             char line[256];
             while (fgets(line, sizeof line, f)) {
-                int w = 0, b = 0;
+                int rw = 0, w = 0, fu = 0, b = 0;
                 const size_t kl = strlen(key);
-                if (strncmp(line, key, kl) == 0 && sscanf(line + kl, " %d %d", &w, &b) == 2) {
+                if (strncmp(line, key, kl) == 0 && line[kl] == ' ' &&
+                    sscanf(line + kl, " %d %d %d %d", &rw, &w, &fu, &b) == 4) {
                     fclose(f);
-                    gwd_status s = gwd_set_tiling(m, w, b);
-                    if (s == GWD_OK) { *waves_out = w; *batch_out = b; }
+                    gwd_status s = gwd_set_tiling(m, rw, w, fu, b);
+                    if (s == GWD_OK) { *rows_out = rw; *waves_out = w; *fuse_out = fu; *batch_out = b; }
                     return s;
                 }
             }
             fclose(f);
         }
     }
-    std::vector<int> wave_opts = {0};
-    if (m->arch.kind == 1 && m->prec == GWD_BF16) wave_opts = {4, 8};
+    std::vector<Sched> cand = {{0, 0, 1}};
+    if (m->arch.kind == 1 && m->prec == GWD_BF16) cand = {{64, 4, 3}, {64, 4, 1}, {64, 8, 1}, {128, 4, 1}};
+    else if (m->arch.kind == 1 && m->prec == GWD_FP8_E4M3) cand = {{64, 4, 1}, {64, 8, 1}, {128, 4, 1}};
     const int batch_opts[] = {256, 512, 1024};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipSetDevice(m->device);
@@ -190,11 +212,14 @@ gwd_status gwd_autotune(gwd_model* m, const gwd_stream* streams, int32_t n_strea
     if (e == hipSuccess) e = hipEventCreate(&e1);
     if (e != hipSuccess) return hip_fail(e, "autotune events");
     float best = 1e30f;
-    int bw = m->lp_waves, bb = m->batch_windows;
+    Sched bs{m->lp_rows, m->lp_waves, m->lp_fuse};
+    int bb = m->batch_windows;
     gwd_status s = GWD_OK;
-    for (int w : wave_opts) {
+    for (const Sched& c : cand) {
         for (int b : batch_opts) {
-            m->lp_waves = w;
+            m->lp_rows = c.rows;
+            m->lp_waves = c.waves;
+            m->lp_fuse = c.fuse;
             m->batch_windows = b;
             s = gwd_forward(m, streams, n_streams, window, stride, 0, out, out_capacity_floats, st);  // warm-up
             if (s != GWD_OK) break;
@@ -205,7 +230,7 @@ gwd_status gwd_autotune(gwd_model* m, const gwd_stream* streams, int32_t n_strea
             float ms = 0.f;
             if (e == hipSuccess && s == GWD_OK) e = hipEventElapsedTime(&ms, e0, e1);
             if (e != hipSuccess || s != GWD_OK) break;
-            if (ms < best) { best = ms; bw = w; bb = b; }
+            if (ms < best) { best = ms; bs = c; bb = b; }
         }
         if (e != hipSuccess || s != GWD_OK) break;
     }
@@ -213,13 +238,17 @@ gwd_status gwd_autotune(gwd_model* m, const gwd_stream* streams, int32_t n_strea
     (void)hipEventDestroy(e1);
     if (e != hipSuccess) return hip_fail(e, "autotune timing");
     if (s != GWD_OK) return s;
-    m->lp_waves = bw;
+    m->lp_rows = bs.rows;
+    m->lp_waves = bs.waves;
+    m->lp_fuse = bs.fuse;
     m->batch_windows = bb;
-    *waves_out = bw;
+    *rows_out = bs.rows;
+    *waves_out = bs.waves;
+    *fuse_out = bs.fuse;
     *batch_out = bb;
     if (cache) {
         if (FILE* f = fopen(cache, "a")) {
-            fprintf(f, "%s %d %d\n", key, bw, bb);
+            fprintf(f, "%s %d %d %d %d\n", key, bs.rows, bs.waves, bs.fuse, bb);
             fclose(f);
         }
     }

@@ -85,14 +85,15 @@ def _load(path: str = LIB_PATH):
         "gwd_last_error": (ctypes.c_char_p, []),
         "gwd_debug_layer": (I32, [P, I32, I32, P, I32, I32, P, P, P, P]),
         "gwd_bce_logits": (I32, [P, P, I64, P, P, P]),
-        "gwd_debug_time_layer": (I32, [P, I32, I32, I32, ctypes.POINTER(F32), ctypes.POINTER(I32), P]),
+        "gwd_debug_time_layer": (I32, [P, I32, I32, I32, ctypes.POINTER(F32), ctypes.POINTER(I32),
+                                       ctypes.POINTER(I32), P]),
         "gwd_plan_create": (I32, [P, ctypes.POINTER(Stream), I32, I32, I32, I32, P, I64, ctypes.POINTER(P)]),
         "gwd_plan_launch": (I32, [P, P]),
         "gwd_plan_completion_us": (I32, [P, P, I32, ctypes.POINTER(D)]),
         "gwd_plan_free": (None, [P]),
-        "gwd_set_tiling": (I32, [P, I32, I32]),
+        "gwd_set_tiling": (I32, [P, I32, I32, I32, I32]),
         "gwd_autotune": (I32, [P, ctypes.POINTER(Stream), I32, I32, I32, P, I64, ctypes.POINTER(I32),
-                               ctypes.POINTER(I32), P]),
+                               ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32), P]),
         "gwd_debug_export_weights": (I32, [P, I32, P, I64]),
     }
     for name, (res, args) in sig.items():
@@ -203,26 +204,28 @@ class Model:
         return out[:n]
 
     def time_layer(self, member: int = 0, layer: int = 15, reps: int = 10, stream=None):
-        """(ms per launch, windows per launch) of one production launch of a middle layer."""
-        ms, nw = ctypes.c_float(0), ctypes.c_int32(0)
+        """(ms per launch, windows per launch, layers per launch) of the forward's launch at a middle
+        layer (a fused BF16 triple covers three layers)."""
+        ms, nw, nl = ctypes.c_float(0), ctypes.c_int32(0), ctypes.c_int32(0)
         check(lib.gwd_debug_time_layer(self.h, member, layer, reps, ctypes.byref(ms), ctypes.byref(nw),
-                                       _stream_handle(stream)))
-        return float(ms.value), int(nw.value)
+                                       ctypes.byref(nl), _stream_handle(stream)))
+        return float(ms.value), int(nw.value), int(nl.value)
 
-    def set_tiling(self, waves: int = 0, batch_windows: int = 512):
-        check(lib.gwd_set_tiling(self.h, waves, batch_windows))
+    def set_tiling(self, tile_rows: int = 0, waves: int = 0, batch_windows: int = 512, layers_per_launch: int = 0):
+        check(lib.gwd_set_tiling(self.h, tile_rows, waves, layers_per_launch, batch_windows))
 
     def autotune(self, streams, window: int = 4096, stride: int = 256, out=None, stream=None):
-        """Pick the fastest tiling for this request; returns (waves, batch_windows)."""
+        """Pick the fastest schedule for this request; returns (tile_rows, waves, layers_per_launch,
+        batch_windows)."""
         import torch
         arr, _ = make_streams(streams)
         n = self.out_floats(streams, window, stride, 0)
         if out is None:
             out = torch.empty(max(n, 1), dtype=torch.float32, device="cuda")
-        w, b = ctypes.c_int32(0), ctypes.c_int32(0)
-        check(lib.gwd_autotune(self.h, arr, len(streams), window, stride, _ptr(out), out.numel(), ctypes.byref(w),
-                               ctypes.byref(b), _stream_handle(stream)))
-        return int(w.value), int(b.value)
+        rw, w, fu, b = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+        check(lib.gwd_autotune(self.h, arr, len(streams), window, stride, _ptr(out), out.numel(), ctypes.byref(rw),
+                               ctypes.byref(w), ctypes.byref(fu), ctypes.byref(b), _stream_handle(stream)))
+        return int(rw.value), int(w.value), int(fu.value), int(b.value)
 
     def plan(self, streams, window: int = 4096, stride: int = 256, out_mode: int = 0, out=None):
         """Capture the whole forward for this request into a replayable graph (see Plan)."""

@@ -31,7 +31,7 @@ def test_plan_replays_match_eager(g, prec):
     print(f"case: plan replays {prec}", flush=True)
     blobs = np.stack([synth.full_weights(11 + i) for i in range(2)])
     m = g.Model(g.full_arch(), blobs, prec)
-    m.set_tiling(0, 96)          # several batches, streams split across batch boundaries
+    m.set_tiling(0, 0, 96)       # several batches, streams split across batch boundaries
     xs = ragged_streams(300, 6)
     bufs = [to_dev(x) if len(x) else torch.zeros((0, 2), dtype=torch.float32, device="cuda") for x in xs]
     plan = m.plan(bufs, 4096, 256, out_mode=1)
@@ -53,18 +53,29 @@ def test_plan_replays_match_eager(g, prec):
     m.close()
 
 
-def test_tilings_and_batches_do_not_change_results(g):
+TILINGS = [(64, 4), (64, 8), (128, 4)]
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_tilings_and_batches_do_not_change_results(g, prec):
+    """Every schedule (tiling, fused BF16 triples or one layer per launch, batch size) computes each
+    output with the same operations in the same order: results are bit-identical."""
     from paper_2201_11133_amd import synth
-    m = g.Model(g.full_arch(), synth.full_weights(11), "bf16")
-    x = to_dev(synth.make_stream(310, 20.0, 1)[0])
+    print(f"case: schedules {prec}", flush=True)
+    m = g.Model(g.full_arch(), synth.full_weights(11), prec)
+    # a long stream, one shorter than a window, one that ends inside its last window
+    xs = [to_dev(synth.make_stream(310, 20.0, 1)[0]), to_dev(synth.make_stream(311, 0.6, 0)[0]),
+          to_dev(synth.make_stream(312, 3.3, 0)[0][: 3 * 4096 + 1234])]
     ref = None
-    for waves in (4, 8):
-        for nb in (64, 300, 512):
-            m.set_tiling(waves, nb)
-            e = m.forward([x], 4096, 256, 0).clone()
-            if ref is None:
-                ref = e
-            assert torch.equal(e, ref), (waves, nb)
+    fuse_opts = (1, 3) if prec == "bf16" else (1,)
+    for fuse in fuse_opts:
+        for rows, waves in TILINGS:
+            for nb in (7, 64, 300, 512):
+                m.set_tiling(rows, waves, nb, fuse)
+                e = m.forward(xs, 4096, 256, 1).clone()
+                if ref is None:
+                    ref = e
+                assert torch.equal(e, ref), (fuse, rows, waves, nb)
     m.close()
 
 
@@ -74,9 +85,9 @@ def test_autotune_picks_a_valid_tiling(g, tmp_path, monkeypatch):
     monkeypatch.setenv("GWD_AUTOTUNE_CACHE", str(cache))
     m = g.Model(g.full_arch(), synth.full_weights(11), "bf16")
     x = to_dev(synth.make_stream(311, 40.0, 1)[0])
-    w, b = m.autotune([x])
-    assert w in (4, 8) and b in (256, 512, 1024)
-    assert cache.read_text().strip().endswith(f"{w} {b}")
+    rw, w, fu, b = m.autotune([x])
+    assert (rw, w) in TILINGS and fu in (1, 3) and b in (256, 512, 1024)
+    assert cache.read_text().strip().endswith(f"{rw} {w} {fu} {b}")
     # second call reads the cache
-    assert m.autotune([x]) == (w, b)
+    assert m.autotune([x]) == (rw, w, fu, b)
     m.close()
