@@ -7,7 +7,8 @@
 //   FP8:  v_mfma_scale_f32_32x32x64_f8f6f4 with E4M3 (OCP) operands and unit block scales;
 //         activations use a unit scale (saturated to +/-448), weights one scale per output column
 //         (max |w| / 448), applied to the fp32 accumulator in the epilogue.
-// The residual stream x is stored in bf16 between layers (the operand format of this path; the
+// BF16 accumulators start at the bias; FP8 adds it after the column scale. The residual stream x is
+// stored in bf16 between layers (the operand format of this path; the
 // paper's half-precision engine likewise keeps its activations in half precision); the skip sum
 // stays fp32.
 //
@@ -49,12 +50,8 @@ struct LayerArgsLP {
     const float* b_in;
 };
 
-// fp32 -> bf16 bits, round to nearest even (finite inputs).
-__device__ inline uint16_t to_bf16_bits(float f) {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
+// fp32 -> bf16 bits, round to nearest even (the gfx950 conversion instruction).
+__device__ inline uint16_t to_bf16_bits(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // fp32 -> E4M3 (OCP) code, round to nearest even, saturated to +/-448 (hardware conversion).
@@ -84,6 +81,13 @@ struct LP {
     static constexpr int LDS = BM * ROW + (FP8 ? BM * XROW : 0);
     static constexpr int CH = BM * 32 / THREADS;    // 16-byte chunks staged per thread
 };
+
+__device__ inline floatx16 splat16(float v) {
+    floatx16 r;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) r[i] = v;
+    return r;
+}
 
 template <bool FP8>
 struct Frag {
@@ -127,7 +131,8 @@ __device__ inline uint2 bf16x8_to_e4m3(uint4 v) {
 // One phase-2 pass over NB 32-column blocks of Brs (K = 128): acc[c][i] = g rows of row block i
 // times column block c; each operand fragment read from LDS feeds NB MFMAs.
 template <bool FP8, int RB, int WV, int NB, int ROWB = LP<FP8, RB, WV>::ROW>
-__device__ inline void phase2_pass(const uint8_t* Ar, const uint8_t* const (&Bm)[NB], floatx16 (&acc)[NB][RB]) {
+__device__ inline void phase2_pass(const uint8_t* Ar, const uint8_t* const (&Bm)[NB], const float (&init)[NB],
+                                   floatx16 (&acc)[NB][RB]) {
     using T = LP<FP8, RB, WV>;
     Frag<FP8> ring[T::PF2][NB];
 #pragma unroll
@@ -137,7 +142,7 @@ __device__ inline void phase2_pass(const uint8_t* Ar, const uint8_t* const (&Bm)
 #pragma unroll
     for (int c = 0; c < NB; ++c)
 #pragma unroll
-        for (int i = 0; i < RB; ++i) acc[c][i] = floatx16{};
+        for (int i = 0; i < RB; ++i) acc[c][i] = splat16(init[c]);
 #pragma unroll
     for (int j = 0; j < T::NK2; ++j) {
         const int slot = j % T::PF2;
@@ -163,7 +168,7 @@ __device__ inline void residual_out(const floatx16& acc, const uint8_t* xr, uint
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         const int dm = 8 * (i >> 2) + (i & 3);  // compile-time row offset
-        const float rv = FP8 ? fmaf(acc[i], s_r, br) : acc[i] + br;
+        const float rv = FP8 ? fmaf(acc[i], s_r, br) : acc[i];  // BF16: the bias started the accumulator
         const uint16_t xb = *(const uint16_t*)(xr + dm * (FP8 ? T::XROW : T::ROW));
         xo[dm * kC] = to_bf16_bits(bf16_to_f32(xb) + rv);
     }
@@ -175,7 +180,7 @@ __device__ inline void skip_out(const floatx16& acc, float* sk, float bs, float 
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         const int dm = 8 * (i >> 2) + (i & 3);
-        const float sv = FP8 ? fmaf(acc[i], s_s, bs) : acc[i] + bs;
+        const float sv = FP8 ? fmaf(acc[i], s_s, bs) : acc[i];
         sk[dm * kC] = SKIP_INIT ? sv : sk[dm * kC] + sv;
     }
 }
@@ -250,8 +255,14 @@ void layer_lp_kernel(LayerArgsLP p) {
     // A fragment of row block i of this wave: row 32 RB rh + 32 i + r, k-half h
     const uint8_t* Ar = &A[(32 * RB * rh + r) * T::ROW + h * T::FRAG];
 
-    // ---- phase 1: pre = A Bc, K = 256; weight fragments from a register ring PF1 steps deep
-    floatx16 af[RB] = {}, ag[RB] = {};
+    // ---- phase 1: pre = A Bc (+ bias, BF16), K = 256; weight fragments from a register ring PF1 steps deep
+    const int nc = 32 * q + r;
+    floatx16 af[RB], ag[RB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+        af[i] = splat16(FP8 ? 0.f : p.bc[nc]);
+        ag[i] = splat16(FP8 ? 0.f : p.bc[kC + nc]);
+    }
     {
         const uint8_t* Bf = p.wc + ((size_t)(q * T::NK1) * 64 + lane) * T::FRAG;        // filter block q
         const uint8_t* Bg = p.wc + ((size_t)((4 + q) * T::NK1) * 64 + lane) * T::FRAG;  // gate block 4 + q
@@ -289,8 +300,8 @@ void layer_lp_kernel(LayerArgsLP p) {
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int m = 32 * RB * rh + 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
-                const float vf = FP8 ? fmaf(af[rb][i], sf, bf) : af[rb][i] + bf;
-                const float vg = FP8 ? fmaf(ag[rb][i], sg, bg) : ag[rb][i] + bg;
+                const float vf = FP8 ? fmaf(af[rb][i], sf, bf) : af[rb][i];
+                const float vg = FP8 ? fmaf(ag[rb][i], sg, bg) : ag[rb][i];
                 if (p.pre_out) {
                     float* po = p.pre_out + (row0 + m) * (2 * kC);
                     po[n] = vf;
@@ -316,7 +327,8 @@ void layer_lp_kernel(LayerArgsLP p) {
     if (!LAST && T::ONE_PASS) {
         floatx16 acc[2][RB];
         const uint8_t* const bm[2] = {Wres, Wskip};
-        phase2_pass<FP8, RB, WV, 2>(Ar, bm, acc);
+        const float b0[2] = {FP8 ? 0.f : br, FP8 ? 0.f : bs};
+        phase2_pass<FP8, RB, WV, 2>(Ar, bm, b0, acc);
         __builtin_amdgcn_sched_barrier(0);  // epilogue loads stay after the MFMAs (register pressure)
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
@@ -331,7 +343,8 @@ void layer_lp_kernel(LayerArgsLP p) {
     if (!LAST) {
         floatx16 acc[1][RB];
         const uint8_t* const bm[1] = {Wres};
-        phase2_pass<FP8, RB, WV, 1>(Ar, bm, acc);
+        const float b0[1] = {FP8 ? 0.f : br};
+        phase2_pass<FP8, RB, WV, 1>(Ar, bm, b0, acc);
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
             const int mb = 32 * RB * rh + 32 * rb + 4 * h;
@@ -343,7 +356,8 @@ void layer_lp_kernel(LayerArgsLP p) {
     {
         floatx16 acc[1][RB];
         const uint8_t* const bm[1] = {Wskip};
-        phase2_pass<FP8, RB, WV, 1>(Ar, bm, acc);
+        const float b0[1] = {FP8 ? 0.f : bs};
+        phase2_pass<FP8, RB, WV, 1>(Ar, bm, b0, acc);
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
             const int mb = 32 * RB * rh + 32 * rb + 4 * h;
@@ -505,7 +519,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
             const float bf = p.bc[j][n], bg = p.bc[j][kC + n], br = p.brs[j][n], bs = p.brs[j][kC + n];
             // ---- phase 1: pre = [x[s - dil] | x[s]] Bc, K = 256 (k-steps 0-7: tap s - dil, 8-15: tap s);
             // weight fragments from a register ring, operand fragments one step ahead
-            floatx16 af[2] = {}, ag[2] = {};
+            floatx16 af[2] = {splat16(bf), splat16(bf)}, ag[2] = {splat16(bg), splat16(bg)};
             {
                 const uint8_t* A0 = Xin + r * FU_XROW + 16 * h;
                 const uint8_t* Bf = p.wc[j] + ((size_t)(q * T::NK1) * 64 + lane) * T::FRAG;
@@ -533,11 +547,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                         for (int i = 0; i < 2; ++i)
                             anxt[i] = load_frag<false>(A0 + (32 * i + roff) * FU_XROW + 32 * ((k + 1) & 7));
                     }
+                    __builtin_amdgcn_sched_barrier(0);  // the next step's loads issue before this step's MFMAs
 #pragma unroll
                     for (int i = 0; i < 2; ++i) {
                         af[i] = mma<false>(acur[i], cf, af[i]);
                         ag[i] = mma<false>(acur[i], cg, ag[i]);
                     }
+                    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                     for (int i = 0; i < 2; ++i) acur[i] = anxt[i];
                 }
@@ -560,7 +576,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
 #pragma unroll
                 for (int i = 0; i < 16; ++i) {
                     const int m = 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
-                    *(uint16_t*)&G[m * FU_XROW + 2 * n] = to_bf16_bits(gate_fast(af[rb][i] + bf, ag[rb][i] + bg));
+                    *(uint16_t*)&G[m * FU_XROW + 2 * n] = to_bf16_bits(gate_fast(af[rb][i], ag[rb][i]));
                     if (i == 15) __builtin_amdgcn_sched_barrier(0);
                 }
             __syncthreads();
@@ -586,7 +602,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                             xold[rb][i >> 1] = lo | (hi << 16);
                         }
                 }
-                floatx16 acc[2] = {};
+                floatx16 acc[2] = {splat16(pass == 0 ? br : bs), splat16(pass == 0 ? br : bs)};
                 Frag<false> acur[2], anxt[2];
 #pragma unroll
                 for (int i = 0; i < 2; ++i) acur[i] = load_frag<false>(Ag + 32 * i * FU_XROW);
@@ -599,8 +615,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
 #pragma unroll
                         for (int i = 0; i < 2; ++i) anxt[i] = load_frag<false>(Ag + 32 * i * FU_XROW + 32 * (k + 1));
                     }
+                    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                     for (int i = 0; i < 2; ++i) acc[i] = mma<false>(acur[i], cw, acc[i]);
+                    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                     for (int i = 0; i < 2; ++i) acur[i] = anxt[i];
                 }
@@ -612,7 +630,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                             const int m = 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
                             const uint32_t w = xold[rb][i >> 1];
                             const uint16_t xb = (uint16_t)((i & 1) ? (w >> 16) : (w & 0xffffu));
-                            *(uint16_t*)(Xo + m * FU_XROW + 2 * n) = to_bf16_bits(bf16_to_f32(xb) + (acc[rb][i] + br));
+                            *(uint16_t*)(Xo + m * FU_XROW + 2 * n) = to_bf16_bits(bf16_to_f32(xb) + acc[rb][i]);
                         }
                     __builtin_amdgcn_sched_barrier(0);
                 } else {  // skip += g Brs_skip + b_skip
@@ -620,7 +638,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                     for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
                         for (int i = 0; i < 16; ++i) {
-                            const float sv = acc[rb][i] + bs;
+                            const float sv = acc[rb][i];
                             sk[rb][i] = (SKIP_INIT && j == 0) ? sv : sk[rb][i] + sv;
                         }
                 }
