@@ -263,18 +263,18 @@ void gwd_plan_free(gwd_plan* plan);
  *   tile_rows, waves: tiling of the single-layer BF16/FP8 kernel, (64, 4),
  *     (64, 8) or (128, 4); (0, 0) = default per precision (BF16 (64, 4), FP8
  *     (64, 8)); FP32 models have one tiling and accept only (0, 0);
- *   layers_per_launch: BF16 only, 3 = layers with dilations d, 2d, 4d of a
- *     stack run as one fused launch (the default), 1 = one launch per layer;
- *     0 = default; other precisions accept 0 or 1;
+ *   layers_per_launch: BF16 and FP8, 3 = layers with dilations d, 2d, 4d of
+ *     a stack run as one fused launch (the default), 1 = one launch per
+ *     layer; 0 = default; FP32 models accept 0 or 1;
  *   batch_windows: windows per batch of layer launches (1..8192, default 512).
  * Results do not depend on any of them. GWD_ERR_ARG for other values. */
 gwd_status gwd_set_tiling(gwd_model* model, int32_t tile_rows, int32_t waves, int32_t layers_per_launch,
                           int32_t batch_windows);
 
 /* Autotuner: times gwd_forward (out_mode 0) on the given request for every
- * schedule candidate (BF16: fused triples with the default tiling, and the
- * three tilings one layer per launch; FP8: the three tilings; all: batch 256,
- * 512, 1024 windows), keeps
+ * schedule candidate (BF16/FP8: fused triples with the default tiling, and
+ * the three tilings one layer per launch; all: batch 256, 512, 1024 windows),
+ * keeps
  * the fastest on the model and reports it. If the environment variable
  * GWD_AUTOTUNE_CACHE names a file, a cached choice for the same (architecture,
  * precision, members, window, stride) is used instead of timing, and new
@@ -304,7 +304,7 @@ gwd_status gwd_debug_export_weights(const gwd_model* model, int32_t member, floa
 
 /* Measurement support: issues the launch that gwd_forward makes at middle gated
  * layer `layer` of member `member` (the single-layer kernel, or the fused
- * three-layer kernel when a BF16 triple starts there; every layer it covers
+ * three-layer kernel when a BF16/FP8 triple starts there; every layer it covers
  * must be a middle one) reps + 1 times, with the forward's grid over its batch
  * of windows, on the activations the last gwd_forward left in the model's
  * workspace, and times the last `reps` launches between two HIP events

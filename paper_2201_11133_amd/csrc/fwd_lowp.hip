@@ -388,11 +388,12 @@ static hipError_t launch_lp(const LayerArgsLP& a, int nb, int tiling, hipStream_
     }
 }
 
-// The model's tiling choice: 0 = default per precision (BF16 64 x 4, FP8 64 x 8).
+// The model's tiling choice: 0 = default (64 x 4 for both precisions, the fastest measured).
 static int lp_tiling(const gwd_model* m, bool fp8) {
+    (void)fp8;
     if (m->lp_rows == 128) return LP_128x4;
     if (m->lp_rows == 64) return m->lp_waves == 8 ? LP_64x8 : LP_64x4;
-    return fp8 ? LP_64x8 : LP_64x4;
+    return LP_64x4;
 }
 
 // ---------------------------------------------------------------- fused layer triples (BF16)
@@ -421,6 +422,8 @@ struct FusedArgs {
     const float* bc[3];
     const uint8_t* wrs[3];
     const float* brs[3];
+    const float* sc[3];    // FP8: conv column scales [256]
+    const float* srs[3];   // FP8: res|skip column scales [256]
     int d0, T;             // dilation of the first layer; window length
     int n_seg, seg_chunks; // segments per sub-sequence, chunks per segment
     const StreamDesc* streams;
@@ -685,24 +688,260 @@ static LayerArgsLP lp_args(gwd_model* m, int member, int l) {
     return a;
 }
 
+// FP8 form of the fused triple: the MFMA operands are E4M3, so each layer input is kept twice, as
+// E4M3 operand rows with their history (128 B + pad) and, for the rows of the chunk, as the bf16
+// residual base; the gate output is E4M3. Arithmetic as in the single-layer FP8 kernel: column
+// scale then bias on the accumulators, the residual added to the bf16 x, and the next layer's
+// operand converted from the bf16-rounded x. One 32-row block per wave (32-row chunks): E4M3
+// weights are half the bytes of bf16 ones, so the weight traffic per row matches the BF16 triple.
+constexpr int FE_RB = 1;                                         // row blocks per wave
+constexpr int FE_ROWS = 32 * FE_RB;                              // sub-rows per chunk
+constexpr int FE_ROW = kC + 16;                                  // E4M3 row + pad
+constexpr int FE_XBUF = (FE_ROWS + FU_HIST) * FE_ROW;            // one operand buffer with its history
+constexpr int FE_BBUF = FE_ROWS * FU_XROW;                       // one bf16 residual buffer
+constexpr int FE_LDS = 3 * FE_XBUF + 2 * FE_BBUF + FE_ROWS * FE_ROW;
+
+__device__ inline uint8_t* fe_xbuf(uint8_t* lds, int j) { return lds + j * FE_XBUF + FU_HIST * FE_ROW; }
+__device__ inline uint8_t* fe_bbuf(uint8_t* lds, int j) { return lds + 3 * FE_XBUF + j * FE_BBUF; }
+
+template <bool FROM_STREAM, bool SKIP_INIT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void fused3_fp8_kernel(FusedArgs p) {
+    using T = LP<true, FE_RB, 4>;  // E4M3 fragments (32 B per lane), 4 waves x FE_RB row blocks
+    constexpr int RB = FE_RB;
+    constexpr int PF = 2;          // weight-fragment ring depth
+    __shared__ __attribute__((aligned(16))) uint8_t lds[FE_LDS];
+    uint8_t* GE = lds + 3 * FE_XBUF + 2 * FE_BBUF;
+    const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6, h = lane >> 5, r = lane & 31;
+    const int seg = blockIdx.x % p.n_seg;
+    const int cls = (blockIdx.x / p.n_seg) % p.d0;
+    const int b = blockIdx.x / (p.n_seg * p.d0);
+    const int n_sub = (p.T - cls + p.d0 - 1) / p.d0;
+    const int n_ch = (n_sub + FE_ROWS - 1) / FE_ROWS;
+    const int c0 = seg * p.seg_chunks;
+    if (c0 >= n_ch) return;  // uniform over the block
+    const int c1 = min(c0 + p.seg_chunks, n_ch);
+    const int64_t wrow0 = (int64_t)b * p.T;
+    StreamDesc sd{};
+    int64_t start = 0;
+    if (FROM_STREAM) {
+        const int64_t gw = p.win_base + b;
+        sd = p.streams[find_stream(p.streams, p.n_streams, gw)];
+        start = (gw - sd.win_begin) * p.S;
+    }
+    // causal zero padding of the operand histories (E4M3 zero is 0x00)
+    for (int idx = tid; idx < 3 * FU_HIST * 8; idx += 256) {
+        const int j = idx / (FU_HIST * 8), rr = (idx >> 3) % FU_HIST, c = idx & 7;
+        *(uint4*)(fe_xbuf(lds, j) + (rr - FU_HIST) * FE_ROW + 16 * c) = make_uint4(0, 0, 0, 0);
+    }
+    const int n = 32 * q + r;
+    constexpr int SCH = FE_ROWS * 16 / 256;  // 16-byte chunks staged per thread
+    for (int c = (seg > 0 ? c0 - 1 : c0); c < c1; ++c) {
+        const bool store = c >= c0;
+        const int sb = c * FE_ROWS;
+        // ---- stage rows [0, FE_ROWS): bf16 residual base and E4M3 operand; prefetch the skip rows
+        uint4 v[SCH];
+#pragma unroll
+        for (int it = 0; it < SCH; ++it) {
+            const int idx = tid + 256 * it, rr = idx >> 4, c8 = 8 * (idx & 15);
+            const int sr = sb + rr;
+            const int t = cls + p.d0 * sr;
+            v[it] = make_uint4(0, 0, 0, 0);
+            if (sr < n_sub) {
+                if (FROM_STREAM) {
+                    float u0 = 0.f, u1 = 0.f;
+                    const int64_t smp = start + t;
+                    if (smp < sd.length) {
+                        u0 = sd.ch0[smp * sd.stride];
+                        u1 = sd.ch1[smp * sd.stride];
+                    }
+                    uint32_t w[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int ch = c8 + 2 * e;
+                        const float x0 = p.b_in[ch] + p.w_in[2 * ch] * u0 + p.w_in[2 * ch + 1] * u1;
+                        const float x1 = p.b_in[ch + 1] + p.w_in[2 * ch + 2] * u0 + p.w_in[2 * ch + 3] * u1;
+                        w[e] = (uint32_t)to_bf16_bits(x0) | ((uint32_t)to_bf16_bits(x1) << 16);
+                    }
+                    v[it] = make_uint4(w[0], w[1], w[2], w[3]);
+                } else {
+                    v[it] = *(const uint4*)&p.x_in[(wrow0 + t) * kC + c8];
+                }
+            }
+        }
+        float sk[RB][16];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int sr = sb + 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
+                sk[rb][i] = (!SKIP_INIT && store && sr < n_sub) ? p.skip[(wrow0 + cls + p.d0 * sr) * kC + n] : 0.f;
+            }
+#pragma unroll
+        for (int it = 0; it < SCH; ++it) {
+            const int idx = tid + 256 * it, rr = idx >> 4, c8 = 8 * (idx & 15);
+            *(uint4*)(fe_bbuf(lds, 0) + rr * FU_XROW + 2 * c8) = v[it];
+            *(uint2*)(fe_xbuf(lds, 0) + rr * FE_ROW + c8) = bf16x8_to_e4m3(v[it]);
+        }
+        __syncthreads();
+
+#pragma unroll 1
+        for (int j = 0; j < 3; ++j) {
+            const int dil = 1 << j;
+            uint8_t* XE = fe_xbuf(lds, j);
+            uint8_t* XEo = fe_xbuf(lds, j + 1 < 3 ? j + 1 : 0);
+            const uint8_t* XB = fe_bbuf(lds, j & 1);
+            uint8_t* XBo = fe_bbuf(lds, (j + 1) & 1);
+            const float bf = p.bc[j][n], bg = p.bc[j][kC + n], br = p.brs[j][n], bs = p.brs[j][kC + n];
+            const float sf = p.sc[j][n], sg = p.sc[j][kC + n], s_r = p.srs[j][n], s_s = p.srs[j][kC + n];
+            // ---- phase 1 (K = 256 in 4 steps: 0-1 tap s - dil, 2-3 tap s)
+            floatx16 af[RB] = {}, ag[RB] = {};
+            {
+                const uint8_t* A0 = XE + r * FE_ROW + 32 * h;
+                const uint8_t* Bf = p.wc[j] + ((size_t)(q * T::NK1) * 64 + lane) * T::FRAG;
+                const uint8_t* Bg = p.wc[j] + ((size_t)((4 + q) * T::NK1) * 64 + lane) * T::FRAG;
+                Frag<true> rf[PF], rg[PF];
+#pragma unroll
+                for (int k = 0; k < PF; ++k) {
+                    rf[k] = load_frag<true>(Bf + (size_t)k * 64 * T::FRAG);
+                    rg[k] = load_frag<true>(Bg + (size_t)k * 64 * T::FRAG);
+                }
+#pragma unroll
+                for (int k = 0; k < T::NK1; ++k) {
+                    const int slot = k % PF;
+                    const int roff = k < T::NK1 / 2 ? -dil : 0;
+                    Frag<true> a[RB];
+#pragma unroll
+                    for (int i = 0; i < RB; ++i) a[i] = load_frag<true>(A0 + (32 * i + roff) * FE_ROW + 64 * (k & 1));
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int i = 0; i < RB; ++i) {
+                        af[i] = mma<true>(a[i], rf[slot], af[i]);
+                        ag[i] = mma<true>(a[i], rg[slot], ag[i]);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (k + PF < T::NK1) {
+                        rf[slot] = load_frag<true>(Bf + (size_t)(k + PF) * 64 * T::FRAG);
+                        rg[slot] = load_frag<true>(Bg + (size_t)(k + PF) * 64 * T::FRAG);
+                    }
+                }
+            }
+            const uint8_t* Wr = p.wrs[j] + ((size_t)(q * T::NK2) * 64 + lane) * T::FRAG;
+            const uint8_t* Ws = p.wrs[j] + ((size_t)((4 + q) * T::NK2) * 64 + lane) * T::FRAG;
+            Frag<true> ring[T::NK2];  // phase 2 has two k-steps: both fragments up front
+#pragma unroll
+            for (int k = 0; k < T::NK2; ++k) ring[k] = load_frag<true>(Wr + (size_t)k * 64 * T::FRAG);
+            __syncthreads();
+            if (tid < 8 * dil) {  // operand history of the next chunk (128 B per row)
+                const int rr = tid >> 3, cc = tid & 7;
+                *(uint4*)(XE + (rr - dil) * FE_ROW + 16 * cc) = *(const uint4*)(XE + (FE_ROWS - dil + rr) * FE_ROW + 16 * cc);
+            }
+            // ---- gate -> E4M3 operand rows
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int m = 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
+                    const float gv = gate_fast(fmaf(af[rb][i], sf, bf), fmaf(ag[rb][i], sg, bg));
+                    GE[m * FE_ROW + n] = (uint8_t)(to_e4m3_pair(gv, 0.f) & 0xffu);
+                    if (i == 15) __builtin_amdgcn_sched_barrier(0);
+                }
+            __syncthreads();
+            const uint8_t* Ag = GE + r * FE_ROW + 32 * h;
+#pragma unroll
+            for (int pass = 0; pass < 2; ++pass) {
+                if (pass == 1) {
+#pragma unroll
+                    for (int k = 0; k < T::NK2; ++k) ring[k] = load_frag<true>(Ws + (size_t)k * 64 * T::FRAG);
+                }
+                uint32_t xold[RB][8];
+                if (pass == 0) {
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                        for (int i = 0; i < 16; i += 2) {
+                            const int m = 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
+                            const uint32_t lo = *(const uint16_t*)(XB + m * FU_XROW + 2 * n);
+                            const uint32_t hi = *(const uint16_t*)(XB + (m + 1) * FU_XROW + 2 * n);
+                            xold[rb][i >> 1] = lo | (hi << 16);
+                        }
+                }
+                floatx16 acc[RB] = {};
+#pragma unroll
+                for (int k = 0; k < T::NK2; ++k) {
+                    Frag<true> a[RB];
+#pragma unroll
+                    for (int i = 0; i < RB; ++i) a[i] = load_frag<true>(Ag + 32 * i * FE_ROW + 64 * k);
+#pragma unroll
+                    for (int i = 0; i < RB; ++i) acc[i] = mma<true>(a[i], ring[k], acc[i]);
+                }
+                if (pass == 0) {  // x_next = x + (scale * acc + b_res) in bf16; E4M3 operand of the next layer
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                        for (int i = 0; i < 16; ++i) {
+                            const int m = 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
+                            const uint32_t w = xold[rb][i >> 1];
+                            const uint16_t xb = (uint16_t)((i & 1) ? (w >> 16) : (w & 0xffffu));
+                            const uint16_t xn = to_bf16_bits(bf16_to_f32(xb) + fmaf(acc[rb][i], s_r, br));
+                            *(uint16_t*)(XBo + m * FU_XROW + 2 * n) = xn;
+                            if (j < 2) XEo[m * FE_ROW + n] = (uint8_t)(to_e4m3_pair(bf16_to_f32(xn), 0.f) & 0xffu);
+                        }
+                    __builtin_amdgcn_sched_barrier(0);
+                } else {
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                        for (int i = 0; i < 16; ++i) {
+                            const float sv = fmaf(acc[rb][i], s_s, bs);
+                            sk[rb][i] = (SKIP_INIT && j == 0) ? sv : sk[rb][i] + sv;
+                        }
+                }
+            }
+            __syncthreads();
+        }
+        // ---- chunk output: x rows from the last residual buffer, skip from registers
+        if (store) {
+            const uint8_t* XF = fe_bbuf(lds, 1);  // the third layer (j = 2) wrote buffer (2 + 1) & 1
+#pragma unroll
+            for (int it = 0; it < SCH; ++it) {
+                const int idx = tid + 256 * it, rr = idx >> 4, c8 = 8 * (idx & 15);
+                const int sr = sb + rr;
+                if (sr < n_sub)
+                    *(uint4*)&p.x_out[(wrow0 + cls + p.d0 * sr) * kC + c8] = *(const uint4*)(XF + rr * FU_XROW + 2 * c8);
+            }
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int sr = sb + 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
+                    if (sr < n_sub) p.skip[(wrow0 + cls + p.d0 * sr) * kC + n] = sk[rb][i];
+                }
+        }
+        __syncthreads();
+    }
+}
+
 // Does layer l start a fused triple? Triples (i, i+1, i+2) with i % 3 == 0 inside a stack, never
 // holding the network's last layer (that one writes no residual).
 static bool fused_start(const gwd_model* m, int l) {
-    if (m->prec != GWD_BF16 || m->lp_fuse != 3) return false;
+    if ((m->prec != GWD_BF16 && m->prec != GWD_FP8_E4M3) || m->lp_fuse != 3) return false;
     const int lps = m->arch.layers_per_stack, L = m->arch.n_stacks * lps, i = l % lps;
     return i % 3 == 0 && i + 2 < lps && l + 2 < L - 1;
 }
 
 // One fused launch of layers l, l+1, l+2 over nb windows of length T.
+template <bool FP8>
 static hipError_t launch_fused3(gwd_model* m, int member, int l, const uint16_t* x_in, uint16_t* x_out, float* skip,
                                 int nb, int T, const FwdBatch* fb, hipStream_t st) {
     FusedArgs a{};
     for (int j = 0; j < 3; ++j) {
-        const LayerArgsLP la = lp_args<false>(m, member, l + j);
+        const LayerArgsLP la = lp_args<FP8>(m, member, l + j);
         a.wc[j] = la.wc;
         a.bc[j] = la.bc;
         a.wrs[j] = la.wrs;
         a.brs[j] = la.brs;
+        a.sc[j] = la.sc;
+        a.srs[j] = la.srs;
         if (j == 0) { a.w_in = la.w_in; a.b_in = la.b_in; }
     }
     a.x_in = x_in;
@@ -710,7 +949,8 @@ static hipError_t launch_fused3(gwd_model* m, int member, int l, const uint16_t*
     a.skip = skip;
     a.d0 = 1 << (l % m->arch.layers_per_stack);
     a.T = T;
-    const int n_ch = ((T + a.d0 - 1) / a.d0 + FU_ROWS - 1) / FU_ROWS;  // chunks of the longest sub-sequence
+    const int rows = FP8 ? FE_ROWS : FU_ROWS;                           // sub-rows per chunk
+    const int n_ch = ((T + a.d0 - 1) / a.d0 + rows - 1) / rows;       // chunks of the longest sub-sequence
     // enough blocks to fill the chip (>= 2048); a segment after the first costs one warm-up chunk
     const int64_t per = (int64_t)nb * a.d0;
     const int want = (int)std::min<int64_t>(n_ch, std::max<int64_t>(1, (2048 + per - 1) / per));
@@ -724,8 +964,13 @@ static hipError_t launch_fused3(gwd_model* m, int member, int l, const uint16_t*
         a.S = fb->S;
     }
     const dim3 grid((unsigned)(per * a.n_seg));
-    if (first) hipLaunchKernelGGL((fused3_bf16_kernel<true, true>), grid, dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((fused3_bf16_kernel<false, false>), grid, dim3(256), 0, st, a);
+    if (FP8) {
+        if (first) hipLaunchKernelGGL((fused3_fp8_kernel<true, true>), grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((fused3_fp8_kernel<false, false>), grid, dim3(256), 0, st, a);
+    } else {
+        if (first) hipLaunchKernelGGL((fused3_bf16_kernel<true, true>), grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((fused3_bf16_kernel<false, false>), grid, dim3(256), 0, st, a);
+    }
     return hipGetLastError();
 }
 
@@ -737,8 +982,8 @@ static hipError_t layers_lp(gwd_model* m, const FwdBatch& fb, float* x_a, float*
     uint16_t* xin = (uint16_t*)x_a;
     uint16_t* xout = (uint16_t*)x_b;
     for (int l = 0; l < L; ++l) {
-        if (!FP8 && fused_start(m, l)) {
-            hipError_t e = launch_fused3(m, fb.member, l, xin, xout, skip, fb.nb, fb.T, &fb, st);
+        if (fused_start(m, l)) {
+            hipError_t e = launch_fused3<FP8>(m, fb.member, l, xin, xout, skip, fb.nb, fb.T, &fb, st);
             if (e != hipSuccess) return e;
             uint16_t* t = xin; xin = xout; xout = t;
             l += 2;
@@ -806,8 +1051,8 @@ static hipError_t debug_lp(gwd_model* m, int member, int l, const float* x_in, i
 template <bool FP8>
 static hipError_t production_lp(gwd_model* m, int member, int l, void* x_in, void* x_out, float* skip, int nb, int T,
                                 hipStream_t st) {
-    if (!FP8 && fused_start(m, l) && l > 0)
-        return launch_fused3(m, member, l, (const uint16_t*)x_in, (uint16_t*)x_out, skip, nb, T, nullptr, st);
+    if (fused_start(m, l) && l > 0)
+        return launch_fused3<FP8>(m, member, l, (const uint16_t*)x_in, (uint16_t*)x_out, skip, nb, T, nullptr, st);
     LayerArgsLP a = lp_args<FP8>(m, member, l);
     a.x_in = (const uint16_t*)x_in;
     a.x_out = (uint16_t*)x_out;
@@ -816,7 +1061,7 @@ static hipError_t production_lp(gwd_model* m, int member, int l, void* x_in, voi
     a.T = T;
     return launch_lp<FP8, false, false, false>(a, nb, lp_tiling(m, FP8), st);
 }
-int layers_per_launch_bf16(const gwd_model* m, int l) { return fused_start(m, l) ? 3 : 1; }
+int layers_per_launch_lp(const gwd_model* m, int l) { return fused_start(m, l) ? 3 : 1; }
 hipError_t layer_production_bf16(gwd_model* m, int member, int l, void* xi, void* xo, float* sk, int nb, int T,
                                  hipStream_t st) {
     return production_lp<false>(m, member, l, xi, xo, sk, nb, T, st);

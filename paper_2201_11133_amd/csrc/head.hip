@@ -297,8 +297,10 @@ hipError_t launch_layer_production(gwd_model* m, int member, int layer, void* x_
     }
 }
 
-int layers_per_launch_bf16(const gwd_model* m, int l);
-int layers_per_launch(const gwd_model* m, int l) { return m->prec == GWD_BF16 ? layers_per_launch_bf16(m, l) : 1; }
+int layers_per_launch_lp(const gwd_model* m, int l);
+int layers_per_launch(const gwd_model* m, int l) {
+    return (m->prec == GWD_BF16 || m->prec == GWD_FP8_E4M3) ? layers_per_launch_lp(m, l) : 1;
+}
 
 hipError_t launch_layer_debug(gwd_model* m, int member, int layer, const float* x_in, int nb, int T, float* pre_out,
                               float* x_out, float* skip, hipStream_t st) {

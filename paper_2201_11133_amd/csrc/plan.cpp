@@ -157,7 +157,7 @@ gwd_status gwd_set_tiling(gwd_model* m, int32_t tile_rows, int32_t waves, int32_
         set_error("gwd_set_tiling: (%d rows, %d waves) is not a tiling of this model", tile_rows, waves);
         return GWD_ERR_ARG;
     }
-    const bool fusable = m->arch.kind == 1 && m->prec == GWD_BF16;
+    const bool fusable = lowp;
     if (!(layers_per_launch == 0 || layers_per_launch == 1 || (layers_per_launch == 3 && fusable))) {
         set_error("gwd_set_tiling: %d layers per launch not available for this model", layers_per_launch);
         return GWD_ERR_ARG;
@@ -203,8 +203,8 @@ gwd_status gwd_autotune(gwd_model* m, const gwd_stream* streams, int32_t n_strea
         }
     }
     std::vector<Sched> cand = {{0, 0, 1}};
-    if (m->arch.kind == 1 && m->prec == GWD_BF16) cand = {{64, 4, 3}, {64, 4, 1}, {64, 8, 1}, {128, 4, 1}};
-    else if (m->arch.kind == 1 && m->prec == GWD_FP8_E4M3) cand = {{64, 4, 1}, {64, 8, 1}, {128, 4, 1}};
+    if (m->arch.kind == 1 && (m->prec == GWD_BF16 || m->prec == GWD_FP8_E4M3))
+        cand = {{64, 4, 3}, {64, 4, 1}, {64, 8, 1}, {128, 4, 1}};
     const int batch_opts[] = {256, 512, 1024};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipSetDevice(m->device);
