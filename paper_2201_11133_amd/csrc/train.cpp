@@ -109,6 +109,7 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
     float *G = fptr(b, f_g), *DG = fptr(b, f_dg), *DX = fptr(b, f_dx), *DS = fptr(b, f_ds), *SKS = fptr(b, f_sks);
     float *R = fptr(b, f_r), *H = fptr(b, f_h), *DH = fptr(b, f_dh), *AH = fptr(b, f_ah), *DPRE = fptr(b, f_dpre);
     float* PART = fptr(b, f_part);
+    const int64_t PART_CAP = total - f_part;  // floats
     hipError_t e;
 #define HIPCHK(x, what) do { e = (x); if (e != hipSuccess) return hip_fail(e, what); } while (0)
     HIPCHK(launch_fill(grad, m->n_params, 0.f, st), "zero grad");
@@ -123,15 +124,15 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
         HIPCHK(gemm_rows(g, st), "head gemm");
     }
     HIPCHK(launch_head_bwd_elem(H, dz, M, w + v.h2w, mid, DH, AH, st), "head bwd");
-    HIPCHK(colsum(AH, kC, M, kC, dz, 1, 0, PART, grad + v.h2w, 1, st), "d h2.W");
-    HIPCHK(colsum(dz, 1, M, 1, nullptr, 0, 0, PART, grad + v.h2b, 1, st), "d h2.b");
+    HIPCHK(colsum(AH, kC, M, kC, dz, 1, 0, PART, PART_CAP, grad + v.h2w, 1, st), "d h2.W");
+    HIPCHK(colsum(dz, 1, M, 1, nullptr, 0, 0, PART, PART_CAP, grad + v.h2b, 1, st), "d h2.b");
     {
         WgradArgs a{};
         a.A[0] = APart{DH, kC, 0, kC}; a.nparts = 1; a.Ktot = kC;
         a.B = R; a.ldb = kC; a.N = kC; a.M = M; a.T = T; a.rows_per_chunk = RPC; a.part = PART;
         HIPCHK(gemm_wgrad(a, grad + v.h1w, 0, st), "d h1.W");
     }
-    HIPCHK(colsum(DH, kC, M, kC, nullptr, 0, 0, PART, grad + v.h1b, 1, st), "d h1.b");
+    HIPCHK(colsum(DH, kC, M, kC, nullptr, 0, 0, PART, PART_CAP, grad + v.h1b, 1, st), "d h1.b");
     {
         GemmRowsArgs g{};
         g.A[0] = APart{DH, kC, 0, kC};
@@ -178,11 +179,11 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
                 a.A[0] = APart{DS, kC, 0, kC}; a.nparts = 1; a.Ktot = kC;
                 a.B = G; a.ldb = kC; a.N = kC; a.M = M; a.T = T; a.rows_per_chunk = RPC; a.part = PART;
                 HIPCHK(gemm_wgrad(a, grad + v.skip_w[l], 0, st), "d skip.W");
-                HIPCHK(colsum(DS, kC, M, kC, nullptr, 0, 0, PART, grad + v.skip_b[l], 1, st), "d skip.b");
+                HIPCHK(colsum(DS, kC, M, kC, nullptr, 0, 0, PART, PART_CAP, grad + v.skip_b[l], 1, st), "d skip.b");
                 if (!last) {
                     a.A[0] = APart{DX, kC, 0, kC};
                     HIPCHK(gemm_wgrad(a, grad + v.res_w[l], 0, st), "d res.W");
-                    HIPCHK(colsum(DX, kC, M, kC, nullptr, 0, 0, PART, grad + v.res_b[l], 1, st), "d res.b");
+                    HIPCHK(colsum(DX, kC, M, kC, nullptr, 0, 0, PART, PART_CAP, grad + v.res_b[l], 1, st), "d res.b");
                 }
             }
             // conv weight gradient: dW[n][c][tap] = sum_t dpre[t][n] x[t - d (1 - tap)][c]
@@ -194,7 +195,7 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
                 HIPCHK(gemm_wgrad(a, grad + v.dil_w[l] + 1, 2, st), "d dil.W tap1");
                 a.bshift = -d;
                 HIPCHK(gemm_wgrad(a, grad + v.dil_w[l], 2, st), "d dil.W tap0");
-                HIPCHK(colsum(DPRE, 2 * kC, M, 2 * kC, nullptr, 0, 0, PART, grad + v.dil_b[l], 1, st), "d dil.b");
+                HIPCHK(colsum(DPRE, 2 * kC, M, 2 * kC, nullptr, 0, 0, PART, PART_CAP, grad + v.dil_b[l], 1, st), "d dil.b");
             }
             // dx = dx' + dpre[t] W1 + dpre[t+d] W0   (W_tap as [n][c]: dil.W[(n C + c) 2 + tap])
             {
@@ -209,9 +210,9 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
         }
     }
     // ---- input projection: dW_in[c][i] = sum_rows dx0[row][c] u[row][i]; db_in = sum_rows dx0
-    HIPCHK(colsum(DX, kC, M, kC, u, 2, 0, PART, grad + v.in_w, 2, st), "d in.W ch0");
-    HIPCHK(colsum(DX, kC, M, kC, u + 1, 2, 0, PART, grad + v.in_w + 1, 2, st), "d in.W ch1");
-    HIPCHK(colsum(DX, kC, M, kC, nullptr, 0, 0, PART, grad + v.in_b, 1, st), "d in.b");
+    HIPCHK(colsum(DX, kC, M, kC, u, 2, 0, PART, PART_CAP, grad + v.in_w, 2, st), "d in.W ch0");
+    HIPCHK(colsum(DX, kC, M, kC, u + 1, 2, 0, PART, PART_CAP, grad + v.in_w + 1, 2, st), "d in.W ch1");
+    HIPCHK(colsum(DX, kC, M, kC, nullptr, 0, 0, PART, PART_CAP, grad + v.in_b, 1, st), "d in.b");
     if (du) HIPCHK(launch_input_grad(DX, M, w + v.in_w, du, st), "d input");
 #undef HIPCHK
     return GWD_OK;

@@ -53,7 +53,7 @@ hipError_t gemm_rows(const GemmRowsArgs& a, hipStream_t st);
 hipError_t gemm_wgrad(const WgradArgs& a, float* dst, int out_mode, hipStream_t st);
 // dst[n * dst_stride] += sum_rows f(X[row][n]) * w[row * wstride]   (w optional, f = id or ReLU)
 hipError_t colsum(const float* X, int64_t ldx, int64_t M, int N, const float* w, int64_t wstride, int relu,
-                  float* part, float* dst, int64_t dst_stride, hipStream_t st);
+                  float* part, int64_t part_capacity, float* dst, int64_t dst_stride, hipStream_t st);
 hipError_t launch_input_proj(const float* u, int64_t M, const float* w_in, const float* b_in, float* x0,
                              hipStream_t st);
 hipError_t launch_gate_bwd(const float* pre, const float* dg, int64_t M, float* g, float* dpre, hipStream_t st);

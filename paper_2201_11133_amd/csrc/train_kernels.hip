@@ -143,6 +143,40 @@ __global__ __launch_bounds__(256) void colsum_kernel(const float* X, int64_t ldx
     part[(int64_t)chunk * N + n] = s;
 }
 
+// The same column sums for 16-byte aligned rows of N = 4 c columns (N <= 1024): one block per chunk,
+// each thread a float4 of columns for every (256 / (N/4))-th row of the chunk, then the row groups
+// added in LDS in a fixed order (the result does not depend on scheduling).
+__global__ __launch_bounds__(256) void colsum4_kernel(const float* X, int64_t ldx, int64_t M, int N,
+                                                      const float* w, int64_t wstride, int relu,
+                                                      int64_t rows_per_chunk, float* part) {
+    __shared__ float4 red[256];
+    const int cpr = N >> 2;           // float4 columns per row
+    const int groups = 256 / cpr;     // rows in flight per block
+    const int tid = threadIdx.x, c4 = tid % cpr, g = tid / cpr;
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_chunk;
+    const int64_t r1 = min(r0 + rows_per_chunk, M);
+    float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (g < groups) {
+#pragma unroll 4
+        for (int64_t r = r0 + g; r < r1; r += groups) {
+            float4 v = *(const float4*)(X + r * ldx + 4 * c4);
+            if (relu) { v.x = fmaxf(v.x, 0.f); v.y = fmaxf(v.y, 0.f); v.z = fmaxf(v.z, 0.f); v.w = fmaxf(v.w, 0.f); }
+            if (w) { const float f = w[r * wstride]; v.x *= f; v.y *= f; v.z *= f; v.w *= f; }
+            s.x += v.x; s.y += v.y; s.z += v.z; s.w += v.w;
+        }
+    }
+    red[tid] = s;
+    __syncthreads();
+    if (tid < cpr) {
+        float4 t = red[tid];
+        for (int k = 1; k < groups; ++k) {
+            const float4 u = red[k * cpr + tid];
+            t.x += u.x; t.y += u.y; t.z += u.z; t.w += u.w;
+        }
+        *(float4*)(part + (int64_t)blockIdx.x * N + 4 * tid) = t;
+    }
+}
+
 // x0[row][c] = W_in[c] . u[row] + b_in[c]   (windows [B][T][2] interleaved)
 __global__ __launch_bounds__(256) void input_proj_kernel(const float* u, int64_t M, const float* w_in,
                                                          const float* b_in, float* x0) {
@@ -310,11 +344,18 @@ hipError_t gemm_wgrad(const WgradArgs& a0, float* dst, int out_mode, hipStream_t
 }
 
 hipError_t colsum(const float* X, int64_t ldx, int64_t M, int N, const float* w, int64_t wstride, int relu,
-                  float* part, float* dst, int64_t dst_stride, hipStream_t st) {
-    const int64_t rpc = 4096;
+                  float* part, int64_t part_capacity, float* dst, int64_t dst_stride, hipStream_t st) {
+    if (N < 1 || part_capacity < N) return hipErrorInvalidValue;
+    const bool vec = N % 4 == 0 && N <= 1024 && ldx % 4 == 0 && ((uintptr_t)X & 15) == 0;
+    // rows per chunk: enough chunks to fill the chip, partial sums within the buffer's capacity
+    int64_t rpc = vec ? 512 : 4096;
+    while (((M + rpc - 1) / rpc) * (int64_t)N > part_capacity) rpc *= 2;
     const int nchunks = (int)((M + rpc - 1) / rpc);
-    hipLaunchKernelGGL(colsum_kernel, dim3((N + 255) / 256, nchunks), dim3(256), 0, st, X, ldx, M, N, w, wstride,
-                       relu, rpc, part);
+    if (vec)
+        hipLaunchKernelGGL(colsum4_kernel, dim3(nchunks), dim3(256), 0, st, X, ldx, M, N, w, wstride, relu, rpc, part);
+    else
+        hipLaunchKernelGGL(colsum_kernel, dim3((N + 255) / 256, nchunks), dim3(256), 0, st, X, ldx, M, N, w, wstride,
+                           relu, rpc, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(reduce_parts_kernel, dim3(nblk(N)), dim3(256), 0, st, part, nchunks, 1, N, dst, dst_stride);

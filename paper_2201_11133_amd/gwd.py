@@ -242,6 +242,57 @@ class Model:
                                   _ptr(x_out), _ptr(skip), _stream_handle(stream)))
 
 
+def _member_function():
+    import torch
+
+    class MemberFunction(torch.autograd.Function):
+        """Per-timestep logits of one member over a batch of windows [B, T, 2], differentiable through
+        the library's hand-written backward (gwd_forward_train keeps the per-stack checkpoints,
+        gwd_backward recomputes each stack and returns the weight and input gradients).
+
+        `weights` is the member's fp32 (fp64 for FP64 models) master blob the model currently holds
+        (the one it was loaded from or gwd_adam_step last wrote); it is an argument so that autograd
+        routes the weight gradient to it. The forward itself uses the model's packed copy."""
+
+        @staticmethod
+        def forward(ctx, windows, weights, model, member):
+            B, T = windows.shape[0], windows.shape[1]
+            dt = torch.float64 if model.precision == "fp64" else torch.float32
+            logits = torch.empty((B, T), dtype=dt, device=windows.device)
+            saved = torch.empty(int(lib.gwd_saved_bytes(model.h, B, T)), dtype=torch.uint8, device=windows.device)
+            windows = windows.contiguous()
+            check(lib.gwd_forward_train(model.h, member, windows.data_ptr(), B, T, logits.data_ptr(),
+                                        saved.data_ptr(), _stream_handle(None)))
+            ctx.save_for_backward(windows)
+            ctx.saved_buf, ctx.model, ctx.member, ctx.wshape = saved, model, member, weights.shape
+            return logits
+
+        @staticmethod
+        def backward(ctx, grad_logits):
+            (windows,) = ctx.saved_tensors
+            B, T = windows.shape[0], windows.shape[1]
+            dz = grad_logits.contiguous()
+            grad = torch.empty(ctx.wshape, dtype=dz.dtype, device=dz.device)
+            du = torch.empty_like(windows) if ctx.needs_input_grad[0] else None
+            check(lib.gwd_backward(ctx.model.h, ctx.member, windows.data_ptr(), B, T, ctx.saved_buf.data_ptr(),
+                                   dz.data_ptr(), grad.data_ptr(), du.data_ptr() if du is not None else None,
+                                   _stream_handle(None)))
+            return du, grad, None, None
+
+    return MemberFunction
+
+
+_MEMBER_FN = None
+
+
+def member_logits(model: "Model", weights, windows, member: int = 0):
+    """Differentiable logits of one member (see MemberFunction)."""
+    global _MEMBER_FN
+    if _MEMBER_FN is None:
+        _MEMBER_FN = _member_function()
+    return _MEMBER_FN.apply(windows, weights, model, member)
+
+
 class Trainer:
     """Buffers and calls of one training step of member `member` (forward with checkpoints, BCE,
     backward, Adam) through the C ABI; master weights, moments and gradients live on the device."""

@@ -90,3 +90,20 @@ def test_autotune_picks_a_valid_tiling(g, tmp_path, monkeypatch):
     # second call reads the cache
     assert m.autotune([x]) == (rw, w, fu, b)
     m.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+def test_long_windows_give_the_same_scores(g, prec):
+    """Stitched scores depend only on each owned row's receptive field (W - S >= RF - 1), and every row
+    is computed with the same operations wherever it sits in a window: windows of 2^16 samples with
+    stride 2^16 - 3072 give bit-identical ensemble scores to windows of 4096 with stride 256."""
+    from paper_2201_11133_amd import synth
+    print(f"case: long windows {prec}", flush=True)
+    blobs = np.stack([synth.full_weights(11 + i) for i in range(2)])
+    m = g.Model(g.full_arch(), blobs, prec)
+    xs = [to_dev(synth.make_stream(320, 40.0, 2)[0]), to_dev(synth.make_stream(321, 3.7, 0)[0])]
+    a = m.forward(xs, 4096, 256, 1).clone()
+    W = 1 << 16
+    b = m.forward(xs, W, W - 3072, 1).clone()
+    assert torch.equal(a, b)
+    m.close()
