@@ -23,7 +23,17 @@ __device__ inline float part_a(const APart& p, int64_t row, int T, int k) {
     return p.ptr[(b * T + t) * p.ld + k];
 }
 
+// Source row of operand part p for output row `row`, or -1 when the shifted time step leaves its
+// window (zero operand): one division per row, done once.
+__device__ inline int64_t part_row(const APart& p, int64_t row, int T) {
+    const int64_t b = row / T;
+    const int t = (int)(row - b * T) + p.shift;
+    return (t < 0 || t >= T) ? -1 : b * T + t;
+}
+
 // C[M, N] = beta * C + sum_p A_p[M, K_p] B_p[K_p, N]   (optionally masked: C *= (mask > 0))
+// Staging: thread (row rr = tid / 4, k quarter q = tid % 4) loads 8 consecutive k of one row as two
+// 16-byte loads (operands are 16-byte aligned with row strides a multiple of 4 floats).
 __global__ __launch_bounds__(256) void gemm_rows_kernel(GemmRowsArgs a) {
     __shared__ float As[GT][GK + 1];
     __shared__ float Bs[GK][GT + 1];
@@ -32,19 +42,25 @@ __global__ __launch_bounds__(256) void gemm_rows_kernel(GemmRowsArgs a) {
     const int ntn = a.N / GT;
     const int64_t row0 = (int64_t)(blockIdx.x / ntn) * GT;
     const int col0 = (blockIdx.x % ntn) * GT;
+    const int rr = tid >> 2, kq = 8 * (tid & 3);
     floatx16 acc = {};
     for (int p = 0; p < a.nparts; ++p) {
         const APart& ap = a.A[p];
         const BPart& bp = a.B[p];
+        const int64_t src = part_row(ap, row0 + rr, a.T);
+        const float* arow = src < 0 ? nullptr : ap.ptr + src * ap.ld + kq;
         for (int k0 = 0; k0 < ap.K; k0 += GK) {
-            for (int i = tid; i < GT * GK; i += 256) {
-                const int rr = i / GK, kk = i % GK;
-                As[rr][kk] = part_a(ap, row0 + rr, a.T, k0 + kk);
+            float4 v0 = make_float4(0.f, 0.f, 0.f, 0.f), v1 = v0;
+            if (arow) {
+                v0 = *(const float4*)(arow + k0);
+                v1 = *(const float4*)(arow + k0 + 4);
             }
             for (int i = tid; i < GK * GT; i += 256) {
                 const int kk = i / GT, nn = i % GT;
                 Bs[kk][nn] = bp.ptr[(int64_t)(k0 + kk) * bp.ld + (int64_t)(col0 + nn) * bp.es];
             }
+            As[rr][kq + 0] = v0.x; As[rr][kq + 1] = v0.y; As[rr][kq + 2] = v0.z; As[rr][kq + 3] = v0.w;
+            As[rr][kq + 4] = v1.x; As[rr][kq + 5] = v1.y; As[rr][kq + 6] = v1.z; As[rr][kq + 7] = v1.w;
             __syncthreads();
 #pragma unroll
             for (int kk = 0; kk < GK; kk += 2) {
@@ -88,19 +104,36 @@ __global__ __launch_bounds__(256) void gemm_wgrad_kernel(WgradArgs a) {
     const APart ap = a.A[p];
     const int64_t r0 = (int64_t)chunk * a.rows_per_chunk;
     const int64_t r1 = min(r0 + a.rows_per_chunk, a.M);
+    // staging: thread (row rr = tid / 8, column group c8 = 8 (tid % 8)) loads 8 consecutive columns
+    // of A (columns k0 - kb + c8 ..) and of B (n0 + c8 ..) of one row, two 16-byte loads each
+    const int rr = tid >> 3, c8 = 8 * (tid & 7);
+    const APart bpart{a.B, a.ldb, a.bshift, a.N};
     floatx16 acc = {};
     for (int64_t rb = r0; rb < r1; rb += GK) {
-        for (int i = tid; i < GK * GT; i += 256) {
-            const int rr = i / GT, kk = i % GT;
-            const int64_t row = rb + rr;
-            As[rr][kk] = (row < r1) ? part_a(ap, row, a.T, k0 - kb + kk) : 0.f;
-            Bs[rr][kk] = (row < r1) ? part_a(APart{a.B, a.ldb, a.bshift, a.N}, row, a.T, n0 + kk) : 0.f;
+        const int64_t row = rb + rr;
+        float4 x0 = make_float4(0.f, 0.f, 0.f, 0.f), x1 = x0, y0 = x0, y1 = x0;
+        if (row < r1) {
+            const int64_t sa = part_row(ap, row, a.T), sb = part_row(bpart, row, a.T);
+            if (sa >= 0) {
+                const float* pa = ap.ptr + sa * ap.ld + (k0 - kb) + c8;
+                x0 = *(const float4*)pa;
+                x1 = *(const float4*)(pa + 4);
+            }
+            if (sb >= 0) {
+                const float* pb = a.B + sb * a.ldb + n0 + c8;
+                y0 = *(const float4*)pb;
+                y1 = *(const float4*)(pb + 4);
+            }
         }
+        As[rr][c8 + 0] = x0.x; As[rr][c8 + 1] = x0.y; As[rr][c8 + 2] = x0.z; As[rr][c8 + 3] = x0.w;
+        As[rr][c8 + 4] = x1.x; As[rr][c8 + 5] = x1.y; As[rr][c8 + 6] = x1.z; As[rr][c8 + 7] = x1.w;
+        Bs[rr][c8 + 0] = y0.x; Bs[rr][c8 + 1] = y0.y; Bs[rr][c8 + 2] = y0.z; Bs[rr][c8 + 3] = y0.w;
+        Bs[rr][c8 + 4] = y1.x; Bs[rr][c8 + 5] = y1.y; Bs[rr][c8 + 6] = y1.z; Bs[rr][c8 + 7] = y1.w;
         __syncthreads();
 #pragma unroll
-        for (int rr = 0; rr < GK; rr += 2) {
-            const float av = As[rr + (lane >> 5)][32 * wr + (lane & 31)];   // A^T: (k, row)
-            const float bv = Bs[rr + (lane >> 5)][32 * wc + (lane & 31)];
+        for (int r2 = 0; r2 < GK; r2 += 2) {
+            const float av = As[r2 + (lane >> 5)][32 * wr + (lane & 31)];   // A^T: (k, row)
+            const float bv = Bs[r2 + (lane >> 5)][32 * wc + (lane & 31)];
             acc = MFMA32(av, bv, acc);
         }
         __syncthreads();
