@@ -129,7 +129,7 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
     {
         WgradArgs a{};
         a.A[0] = APart{DH, kC, 0, kC}; a.nparts = 1; a.Ktot = kC;
-        a.B = R; a.ldb = kC; a.N = kC; a.M = M; a.T = T; a.rows_per_chunk = RPC; a.part = PART;
+        a.B = R; a.ldb = kC; a.N = kC; a.M = M; a.T = T; a.rows_per_chunk = RPC; a.part = PART; a.part_capacity = PART_CAP;
         HIPCHK(gemm_wgrad(a, grad + v.h1w, 0, st), "d h1.W");
     }
     HIPCHK(colsum(DH, kC, M, kC, nullptr, 0, 0, PART, PART_CAP, grad + v.h1b, 1, st), "d h1.b");
@@ -177,7 +177,7 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
             {
                 WgradArgs a{};
                 a.A[0] = APart{DS, kC, 0, kC}; a.nparts = 1; a.Ktot = kC;
-                a.B = G; a.ldb = kC; a.N = kC; a.M = M; a.T = T; a.rows_per_chunk = RPC; a.part = PART;
+                a.B = G; a.ldb = kC; a.N = kC; a.M = M; a.T = T; a.rows_per_chunk = RPC; a.part = PART; a.part_capacity = PART_CAP;
                 HIPCHK(gemm_wgrad(a, grad + v.skip_w[l], 0, st), "d skip.W");
                 HIPCHK(colsum(DS, kC, M, kC, nullptr, 0, 0, PART, PART_CAP, grad + v.skip_b[l], 1, st), "d skip.b");
                 if (!last) {
@@ -190,7 +190,7 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
             {
                 WgradArgs a{};
                 a.A[0] = APart{DPRE, 2 * kC, 0, 2 * kC}; a.nparts = 1; a.Ktot = 2 * kC;
-                a.B = xs_i; a.ldb = kC; a.N = kC; a.M = M; a.T = T; a.rows_per_chunk = RPC; a.part = PART;
+                a.B = xs_i; a.ldb = kC; a.N = kC; a.M = M; a.T = T; a.rows_per_chunk = RPC; a.part = PART; a.part_capacity = PART_CAP;
                 a.bshift = 0;
                 HIPCHK(gemm_wgrad(a, grad + v.dil_w[l] + 1, 2, st), "d dil.W tap1");
                 a.bshift = -d;

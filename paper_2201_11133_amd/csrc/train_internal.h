@@ -45,6 +45,7 @@ struct WgradArgs {
     int T;
     int64_t rows_per_chunk;
     float* part;  // [nchunks][Ktot][N]
+    int64_t part_capacity;  // floats available at part (partials, then the reduction's scratch)
 };
 
 hipError_t gemm_rows(const GemmRowsArgs& a, hipStream_t st);

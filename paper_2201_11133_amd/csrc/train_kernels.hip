@@ -147,7 +147,18 @@ __global__ __launch_bounds__(256) void gemm_wgrad_kernel(WgradArgs a) {
     }
 }
 
-// dst[i * stride] += sum over chunks (in order) of part[chunk][i], i = k N + n
+// dst[i * stride] += sum over chunks of part[chunk][i], i = k N + n, in two fixed-order stages:
+// stage 1 adds the chunks of each of G consecutive groups (in order) into tmp[g][i], stage 2 adds
+// the G group sums (in order) into dst. The result does not depend on scheduling.
+__global__ __launch_bounds__(256) void reduce_groups_kernel(const float* part, int nchunks, int per, int64_t KN,
+                                                            float* tmp) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= KN) return;
+    const int c0 = blockIdx.y * per, c1 = min(c0 + per, nchunks);
+    float s = 0.f;
+    for (int c = c0; c < c1; ++c) s += part[(int64_t)c * KN + i];
+    tmp[(int64_t)blockIdx.y * KN + i] = s;
+}
 __global__ __launch_bounds__(256) void reduce_parts_kernel(const float* part, int nchunks, int K, int N,
                                                            float* dst, int64_t stride) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -155,6 +166,28 @@ __global__ __launch_bounds__(256) void reduce_parts_kernel(const float* part, in
     float s = 0.f;
     for (int c = 0; c < nchunks; ++c) s += part[(int64_t)c * K * N + i];
     dst[i * stride] += s;
+}
+
+// Launch the reduction of nchunks partial sums of KN values each (part holds them; scratch for the
+// group sums follows them within part_capacity floats).
+static hipError_t reduce_parts(float* part, int64_t part_capacity, int nchunks, int64_t KN, float* dst,
+                               int64_t stride, hipStream_t st) {
+    int G = nchunks >= 128 ? 64 : 1;
+    while (G > 1 && (int64_t)(nchunks + G) * KN > part_capacity) G >>= 1;
+    if (G > 1) {
+        const int per = (nchunks + G - 1) / G;
+        G = (nchunks + per - 1) / per;
+        float* tmp = part + (int64_t)nchunks * KN;
+        hipLaunchKernelGGL(reduce_groups_kernel, dim3((unsigned)((KN + 255) / 256), (unsigned)G), dim3(256), 0, st,
+                           (const float*)part, nchunks, per, KN, tmp);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        part = tmp;
+        nchunks = G;
+    }
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3((unsigned)((KN + 255) / 256)), dim3(256), 0, st, (const float*)part,
+                       nchunks, 1, (int)KN, dst, stride);
+    return hipGetLastError();
 }
 
 // part[chunk][n] = sum over the chunk's rows of f(X[row][n]) * w(row); f = identity or ReLU
@@ -371,9 +404,8 @@ hipError_t gemm_wgrad(const WgradArgs& a0, float* dst, int out_mode, hipStream_t
     hipLaunchKernelGGL(gemm_wgrad_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(reduce_parts_kernel, dim3(nblk((int64_t)a.Ktot * a.N)), dim3(256), 0, st, a.part, nchunks,
-                       a.Ktot, a.N, dst, (int64_t)(out_mode == 2 ? 2 : 1));
-    return hipGetLastError();
+    return reduce_parts(a.part, a.part_capacity, nchunks, (int64_t)a.Ktot * a.N, dst, (int64_t)(out_mode == 2 ? 2 : 1),
+                        st);
 }
 
 hipError_t colsum(const float* X, int64_t ldx, int64_t M, int N, const float* w, int64_t wstride, int relu,
@@ -391,8 +423,7 @@ hipError_t colsum(const float* X, int64_t ldx, int64_t M, int N, const float* w,
                            relu, rpc, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(reduce_parts_kernel, dim3(nblk(N)), dim3(256), 0, st, part, nchunks, 1, N, dst, dst_stride);
-    return hipGetLastError();
+    return reduce_parts(part, part_capacity, nchunks, N, dst, dst_stride, st);
 }
 
 hipError_t launch_input_proj(const float* u, int64_t M, const float* w_in, const float* b_in, float* x0,
