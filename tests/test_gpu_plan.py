@@ -107,3 +107,22 @@ def test_long_windows_give_the_same_scores(g, prec):
     b = m.forward(xs, W, W - 3072, 1).clone()
     assert torch.equal(a, b)
     m.close()
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+@pytest.mark.parametrize("W,S", [(3200, 128), (3328, 200)])
+def test_fused_triples_with_partial_chunks(g, prec, W, S):
+    """Windows whose interleaved sub-sequences end inside a chunk (W = 3200: 50 rows at dilation 64,
+    400 at dilation 8; W = 3328: 52 and 416) and strides that are not multiples of a chunk: fused
+    triples give the same outputs as one layer per launch, per window (out_mode 2) and stitched."""
+    from paper_2201_11133_amd import synth
+    print(f"case: partial chunks {prec} W={W} S={S}", flush=True)
+    m = g.Model(g.full_arch(), synth.full_weights(12), prec)
+    xs = [to_dev(synth.make_stream(330, 6.0, 1)[0]), to_dev(synth.make_stream(331, 1.1, 0)[0][:4321])]
+    res = {}
+    for fuse in (1, 3):
+        m.set_tiling(0, 0, 64, fuse)
+        res[fuse] = (m.forward(xs, W, S, 2).clone(), m.forward(xs, W, S, 1).clone())
+    assert torch.equal(res[1][0], res[3][0])
+    assert torch.equal(res[1][1], res[3][1])
+    m.close()
