@@ -189,7 +189,8 @@ def ragged_workload(gwd, blobs, prec: str):
 
 def train_workload(gwd, steps: int = 2, B: int = 256):
     """Training of one full-size member: BF16 forward with per-stack checkpoints, BCE on logits,
-    fp32 hand-written backward, Adam on fp32 master weights; batches of 256 windows of 2 x 4096,
+    hand-written backward (bf16-operand row GEMMs, fp32 weight-gradient GEMMs), Adam on fp32 master
+    weights; batches of 256 windows of 2 x 4096,
     half of them chirped (SNR 8-20), labels 1 within 0.1 s of the coalescence time."""
     import torch
     from paper_2201_11133_amd import synth
@@ -211,7 +212,8 @@ def train_workload(gwd, steps: int = 2, B: int = 256):
     m.close()
     return {"train_windows_per_s": round(B / dt, 1), "s_per_step": round(dt, 3), "batch": B,
             "loss": round(float(loss.item()), 5), "grad_norm": round(float(norm.item()), 5),
-            "precision": "bf16 forward, fp32 backward and master weights"}
+            "precision": "bf16 forward and recompute, bf16-operand row GEMMs in the backward, fp32 "
+                         "weight-gradient GEMMs, fp32 master weights and Adam"}
 
 
 def cpu_baseline(n_members: int, n_windows_sample: int = 3):

@@ -101,7 +101,7 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
     const int64_t f_xs = 0, f_pre = f_xs + (int64_t)LPS * M * kC, f_g = f_pre + (int64_t)LPS * M * 2 * kC;
     const int64_t f_dg = f_g + M * kC, f_dx = f_dg + M * kC, f_ds = f_dx + M * kC, f_sks = f_ds + M * kC;
     const int64_t f_r = f_sks + M * kC, f_h = f_r + M * kC, f_dh = f_h + M * kC, f_ah = f_dh + M * kC;
-    const int64_t f_dpre = f_ah + M * kC, f_part = f_dpre + M * 2 * kC;
+    const int64_t f_dpre = f_ah + M * kC, f_bt = f_dpre + M * 2 * kC, f_part = f_bt + 2 * kC * 2 * kC;
     const int64_t total = f_part + nch * 2 * kC * 2 * kC;
     gwd_status s = ensure_tws(m, total * 4, st);
     if (s != GWD_OK) return s;
@@ -109,6 +109,8 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
     float *G = fptr(b, f_g), *DG = fptr(b, f_dg), *DX = fptr(b, f_dx), *DS = fptr(b, f_ds), *SKS = fptr(b, f_sks);
     float *R = fptr(b, f_r), *H = fptr(b, f_h), *DH = fptr(b, f_dh), *AH = fptr(b, f_ah), *DPRE = fptr(b, f_dpre);
     float* PART = fptr(b, f_part);
+    // BF16/FP8 members: the row GEMMs of the backward take bf16 operands (fp32 accumulation)
+    uint16_t* BT = (m->prec == GWD_BF16 || m->prec == GWD_FP8_E4M3) ? (uint16_t*)fptr(b, f_bt) : nullptr;
     const int64_t PART_CAP = total - f_part;  // floats
     hipError_t e;
 #define HIPCHK(x, what) do { e = (x); if (e != hipSuccess) return hip_fail(e, what); } while (0)
@@ -121,6 +123,7 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
         g.A[0] = APart{R, kC, 0, kC};
         g.B[0] = BPart{w + v.h1w, 1, kC};
         g.nparts = 1; g.M = M; g.N = kC; g.T = T; g.C = H; g.ldc = kC; g.bias = w + v.h1b;
+        g.bt = BT;
         HIPCHK(gemm_rows(g, st), "head gemm");
     }
     HIPCHK(launch_head_bwd_elem(H, dz, M, w + v.h2w, mid, DH, AH, st), "head bwd");
@@ -138,6 +141,7 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
         g.A[0] = APart{DH, kC, 0, kC};
         g.B[0] = BPart{w + v.h1w, kC, 1};      // B(k = j, n = c) = h1.W[j][c]
         g.nparts = 1; g.M = M; g.N = kC; g.T = T; g.C = DS; g.ldc = kC; g.mask = skip; g.ldm = kC;
+        g.bt = BT;
         HIPCHK(gemm_rows(g, st), "dskip");
     }
     HIPCHK(launch_fill(DX, M * kC, 0.f, st), "zero dx");
@@ -171,7 +175,8 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
                 g.nparts = 2;
             }
             g.M = M; g.N = kC; g.T = T; g.C = DG; g.ldc = kC;
-            HIPCHK(gemm_rows(g, st), "dg");
+            g.bt = BT;
+        HIPCHK(gemm_rows(g, st), "dg");
             HIPCHK(launch_gate_bwd(pre, DG, M, G, DPRE, st), "gate bwd");
             // skip / residual weight gradients
             {
@@ -205,6 +210,7 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
                 g2.A[1] = APart{DPRE, 2 * kC, d, 2 * kC};
                 g2.B[1] = BPart{w + v.dil_w[l], 2 * kC, 2};
                 g2.nparts = 2; g2.M = M; g2.N = kC; g2.T = T; g2.C = DX; g2.ldc = kC; g2.beta = 1.f;
+                g2.bt = BT;
                 HIPCHK(gemm_rows(g2, st), "dx");
             }
         }

@@ -31,6 +31,7 @@ struct GemmRowsArgs {
     const float* bias;   // optional [N]
     const float* mask;   // optional: C = 0 where mask <= 0
     int64_t ldm;
+    uint16_t* bt;        // optional scratch (N x sum K bf16): set = bf16 operands, fp32 accumulation
 };
 
 struct WgradArgs {

@@ -84,6 +84,89 @@ __global__ __launch_bounds__(256) void gemm_rows_kernel(GemmRowsArgs a) {
     }
 }
 
+// ---- the same row GEMM with bf16 operands (fp32 accumulation), for BF16/FP8 models: B is packed
+// once per call into bt[n][k] (parts stacked along k), so a lane's B fragment is one 16-byte load from
+// L2; A rows are read from HBM once per 64 x 128 output tile and rounded to bf16 as they are staged.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx8 __attribute__((ext_vector_type(8)));
+constexpr int BR = 64;        // rows per block
+constexpr int BN = 128;       // columns per block
+constexpr int BK = 64;        // k per staged chunk
+constexpr int AROW = BK + 8;  // bf16 per LDS row (144 B: conflict-free 16-byte fragment reads)
+
+__global__ __launch_bounds__(256) void pack_bt_kernel(GemmRowsArgs a, int Ktot) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;  // i = n Ktot + k
+    if (i >= (int64_t)a.N * Ktot) return;
+    const int n = (int)(i / Ktot);
+    int k = (int)(i - (int64_t)n * Ktot), p = 0;
+    while (p + 1 < a.nparts && k >= a.A[p].K) {
+        k -= a.A[p].K;
+        ++p;
+    }
+    const BPart& bp = a.B[p];
+    a.bt[i] = __builtin_bit_cast(uint16_t, (__bf16)bp.ptr[(int64_t)k * bp.ld + (int64_t)n * bp.es]);
+}
+
+__device__ inline uint4 bf16_pack8(float4 lo, float4 hi) {
+    const floatx8 f = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+    return __builtin_bit_cast(uint4, __builtin_convertvector(f, bf16x8));
+}
+
+__global__ __launch_bounds__(256) void gemm_rows_bf16_kernel(GemmRowsArgs a, int Ktot) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[BR * AROW];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave & 1, wc = wave >> 1;  // wave: rows 32 wr, columns 64 wc (two 32-column tiles)
+    const int r = lane & 31, h = lane >> 5;
+    const int ntn = a.N / BN;
+    const int64_t row0 = (int64_t)(blockIdx.x / ntn) * BR;
+    const int col0 = (blockIdx.x % ntn) * BN;
+    const int rr = tid >> 2, kq = 16 * (tid & 3);  // staging: 16 consecutive k of one row
+    const uint16_t* bcol0 = a.bt + (int64_t)(col0 + 64 * wc + r) * Ktot + 8 * h;
+    floatx16 acc[2] = {};
+    int kbase = 0;
+    for (int p = 0; p < a.nparts; ++p) {
+        const APart& ap = a.A[p];
+        const int64_t src = part_row(ap, row0 + rr, a.T);
+        const float* arow = src < 0 ? nullptr : ap.ptr + src * ap.ld + kq;
+        for (int k0 = 0; k0 < ap.K; k0 += BK) {
+            uint4 w0 = make_uint4(0, 0, 0, 0), w1 = w0;
+            if (arow) {
+                const float4* q4 = (const float4*)(arow + k0);
+                w0 = bf16_pack8(q4[0], q4[1]);
+                w1 = bf16_pack8(q4[2], q4[3]);
+            }
+            __syncthreads();  // the previous chunk's fragments are read
+            *(uint4*)&As[rr * AROW + kq] = w0;
+            *(uint4*)&As[rr * AROW + kq + 8] = w1;
+            __syncthreads();
+#pragma unroll
+            for (int s4 = 0; s4 < BK / 16; ++s4) {
+                const bf16x8 av = *(const bf16x8*)&As[(32 * wr + r) * AROW + 16 * s4 + 8 * h];
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const bf16x8 bv = *(const bf16x8*)(bcol0 + (int64_t)32 * c * Ktot + kbase + k0 + 16 * s4);
+                    acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[c], 0, 0, 0);
+                }
+            }
+        }
+        kbase += ap.K;
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int n = col0 + 64 * wc + 32 * c + r;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int64_t row = row0 + 32 * wr + 8 * (i >> 2) + 4 * h + (i & 3);
+            const int64_t o = row * a.ldc + n;
+            float v = acc[c][i];
+            if (a.bias) v += a.bias[n];
+            if (a.beta != 0.f) v += a.beta * a.C[o];
+            if (a.mask) v = (a.mask[row * a.ldm + n] > 0.f) ? v : 0.f;
+            a.C[o] = v;
+        }
+    }
+}
+
 // part[chunk][K][N] = sum over the chunk's rows of A(row, k) B(row, n); A from row-shifted parts
 // stacked along k, B plain. One block: one 64 x 64 output tile of one row chunk.
 __global__ __launch_bounds__(256) void gemm_wgrad_kernel(WgradArgs a) {
@@ -392,6 +475,21 @@ __global__ __launch_bounds__(256) void mean_final_kernel(const double* part, int
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 hipError_t gemm_rows(const GemmRowsArgs& a, hipStream_t st) {
+    bool bf16 = a.bt != nullptr && a.N % BN == 0 && a.M % BR == 0;
+    int Ktot = 0;
+    for (int p = 0; p < a.nparts; ++p) {
+        Ktot += a.A[p].K;
+        bf16 = bf16 && a.A[p].K % BK == 0 && a.A[p].ld % 4 == 0 && ((uintptr_t)a.A[p].ptr & 15) == 0;
+    }
+    if (bf16) {
+        hipLaunchKernelGGL(pack_bt_kernel, dim3((unsigned)(((int64_t)a.N * Ktot + 255) / 256)), dim3(256), 0, st, a,
+                           Ktot);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(gemm_rows_bf16_kernel, dim3((unsigned)((a.M / BR) * (a.N / BN))), dim3(256), 0, st, a,
+                           Ktot);
+        return hipGetLastError();
+    }
     const int64_t blocks = (a.M / GT) * (a.N / GT);
     hipLaunchKernelGGL(gemm_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
     return hipGetLastError();
