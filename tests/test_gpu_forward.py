@@ -179,6 +179,37 @@ def test_parity_slice_16s(g, full_model, full_blob):
     assert dp.max() <= FP32_P_TOL
 
 
+def test_full_size_stream_sampled_parity(g, full_model, full_blob):
+    """The single-member FP32 workload at its full size: 4096 s of two-channel strain (16,777,216
+    samples, 65,521 windows, 20 chirps), one forward in the batching the benchmark uses. Sampled
+    windows (the first, a middle one, one around each of three injections, the last two, whose tail
+    is zero-filled) are recomputed by the oracle window by window; every sample they own must match
+    within the FP32 tolerance."""
+    from oracle.forward import forward_window
+    from oracle.stream import gather_windows, n_windows, owner
+    from paper_2201_11133_amd import synth
+    print("case: full-size 4096 s stream, sampled windows", flush=True)
+    W, S = 4096, 256
+    x, injs = synth.make_stream(101, 4096.0, 20, spacing=10.0, margin=4.0)
+    L = x.shape[0]
+    nw = n_windows(L, W, S)
+    assert nw == 65521
+    e = full_model.forward([to_dev(x)], W, S, out_mode=0).cpu().numpy()
+    a, p = oracle_params(full_blob)
+    picks = {0, nw // 2, nw - 2, nw - 1}
+    for inj in injs[:3]:
+        picks.add(int(owner(np.array([int(inj.tc * 4096)]), W, S)[0][0]))
+    k_of, pos_of = owner(np.arange(L), W, S)
+    worst = 0.0
+    for k in sorted(picks):
+        z64 = forward_window(a, p, gather_windows(x[k * S: k * S + W + S].astype(np.float64), W, S)[:1])[0]
+        rows = np.nonzero(k_of == k)[0]
+        dp = np.abs(sigmoid64(e[rows]) - sigmoid64(z64[pos_of[rows]]))
+        worst = max(worst, float(dp.max()))
+    print(f"full-size sampled windows {sorted(picks)}: max|dp| = {worst:.3g}", flush=True)
+    assert worst <= FP32_P_TOL
+
+
 def test_arg_errors_on_device(g, full_model):
     xd = torch.zeros((5000, 2), dtype=torch.float32, device="cuda")
     with pytest.raises(g.GwdError) as ei:
