@@ -135,13 +135,31 @@ def streaming_line(gwd, blobs, x, out, ref_scores, args):
 
     ms_ev, ms_wall = time_steps(step, args.steps, args.warmup, "streaming", step)  # full stream: sizes the workspace
     same = bool(torch.equal(out[:L], ref_scores[:L]))
-    m.close()
     nw = 1 if L <= Wl else -(-(L - Wl) // Sl) + 1
     flop = args.members * (nw * Wl * FLOP_LAYERS_T + L * FLOP_HEAD_T)
-    return {"window": Wl, "stride": Sl, "strain_s_per_s": round(L / FS / (ms_wall / 1e3), 2),
-            "ms_per_step": round(ms_wall, 3), "tflop_per_step": round(flop / 1e12, 2),
-            "tflops": round(flop / (ms_wall * 1e-3) / 1e12, 2), "scores_identical_to_windowed": same,
-            "precision": args.precision}
+    res = {"window": Wl, "stride": Sl, "strain_s_per_s": round(L / FS / (ms_wall / 1e3), 2),
+           "ms_per_step": round(ms_wall, 3), "tflop_per_step": round(flop / 1e12, 2),
+           "tflops": round(flop / (ms_wall * 1e-3) / 1e12, 2), "scores_identical_to_windowed": same,
+           "precision": args.precision}
+    if args.stream_day:
+        # the same ensemble over a full day of strain (86400 s, 200 chirps): one pass, then triggers
+        progress("streaming variant over 86400 s")
+        xd, _ = make_stream_gpu(86400.0, 102)
+        od = torch.empty(xd.shape[0], dtype=torch.float32, device="cuda")
+        n_trig = [0]
+
+        def day():
+            m.forward([xd], Wl, Sl, out_mode=0, out=od)
+            n_trig[0] = len(gwd.triggers(od, [0, xd.shape[0]], 0.9, 4096))
+
+        _, ms_day = time_steps(day, 1, 1, "streaming day", lambda: m.forward([xd[: 64 * FS]], Wl, Sl, out_mode=0,
+                                                                            out=od))
+        res["day"] = {"stream_s": 86400.0, "s_per_day": round(ms_day / 1e3, 2),
+                      "strain_s_per_s": round(86400.0 / (ms_day / 1e3), 2), "triggers": n_trig[0],
+                      "scores_finite": bool(torch.isfinite(od).all().item())}
+        del xd, od
+    m.close()
+    return res
 
 
 def ragged_workload(gwd, blobs, prec: str):
@@ -256,6 +274,8 @@ def main():
     ap.add_argument("--no-ragged", action="store_true", help="skip the 32-stream ragged graph workload")
     ap.add_argument("--no-train", action="store_true", help="skip the training-throughput measurement")
     ap.add_argument("--no-streaming", action="store_true", help="skip the long-window (streaming) line")
+    ap.add_argument("--stream-day", action=argparse.BooleanOptionalAction, default=True,
+                    help="also run the streaming line over a full day (86400 s) of strain")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device-to-device copy (counter calibration for profiles)")
     args = ap.parse_args()

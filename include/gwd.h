@@ -266,7 +266,9 @@ void gwd_plan_free(gwd_plan* plan);
  *   layers_per_launch: BF16 and FP8, 3 = layers with dilations d, 2d, 4d of
  *     a stack run as one fused launch (the default), 1 = one launch per
  *     layer; 0 = default; FP32 models accept 0 or 1;
- *   batch_windows: windows per batch of layer launches (1..8192, default 512).
+ *   batch_windows: windows per batch of layer launches (1..8192, default 512;
+ *     gwd_forward lowers it for a call whose activations would not fit in 60 %
+ *     of the free device memory, e.g. windows of 2^20 samples).
  * Results do not depend on any of them. GWD_ERR_ARG for other values. */
 gwd_status gwd_set_tiling(gwd_model* model, int32_t tile_rows, int32_t waves, int32_t layers_per_launch,
                           int32_t batch_windows);

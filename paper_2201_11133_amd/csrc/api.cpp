@@ -167,6 +167,18 @@ gwd_status forward_prepare(gwd_model* m, const gwd_stream* streams, int32_t n_st
         sb += streams[i].length;
     }
     nb_max = (int)std::min<int64_t>(m->batch_windows, total_win);
+    if (m->arch.kind == 1) {
+        // long windows: cap the windows per batch so the activations (x ping-pong and skip, 3 x 512 B
+        // per time step) stay within 60 % of the device memory free now (plus what the model holds)
+        const int64_t per_window = (int64_t)window * kC * 4 * 3;
+        if ((int64_t)nb_max * per_window > m->ws.bytes) {
+            size_t free_b = 0, total_b = 0;
+            if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
+                const int64_t allowed = (int64_t)((double)(free_b + (size_t)m->ws.bytes) * 0.6);
+                nb_max = (int)std::max<int64_t>(1, std::min<int64_t>(nb_max, allowed / per_window));
+            }
+        }
+    }
     // workspace: stream table (sized for the largest table so far), then x ping-pong and skip
     const int64_t desc_bytes = (int64_t)n_streams * (int64_t)sizeof(StreamDesc);
     const int64_t first_bytes = (int64_t)firsts.size() * (int64_t)sizeof(int64_t);
