@@ -44,8 +44,10 @@ def kernel_traffic(prec: str, windows: int, layers: int):
     t = MEASURED_TRAFFIC.get(prec)
     if not t or t["windows"] != windows or t.get("layers", 1) != layers:
         return None
-    src = os.path.join(ROOT, "paper_2201_11133_amd", "csrc", "fwd_lowp.hip")
-    sig = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in ("fwd_lowp.hip", "layer_common.h"):   # the kernel source and its device helpers
+        h.update(open(os.path.join(ROOT, "paper_2201_11133_amd", "csrc", f), "rb").read())
+    sig = h.hexdigest()[:16]
     return t["bytes"] if sig == t["source_sha256_16"] else None
 
 
