@@ -54,11 +54,26 @@ struct LayerArgsLP {
 __device__ inline uint16_t to_bf16_bits(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-// fp32 -> E4M3 (OCP) code, round to nearest even, saturated to +/-448 (hardware conversion).
-__device__ inline uint32_t to_e4m3_pair(float a, float b) {
-    a = fminf(fmaxf(a, -448.f), 448.f);
-    b = fminf(fmaxf(b, -448.f), 448.f);
+// fp32 -> E4M3 (OCP) codes of two values already within +/-448 (gate outputs, |g| <= 1), round to
+// nearest even (hardware conversion): a in the low byte, b in the next.
+__device__ inline uint32_t e4m3_pair_in_range(float a, float b) {
     return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false) & 0xffffu;
+}
+
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+typedef short short2v __attribute__((ext_vector_type(2)));
+typedef unsigned short ushort2v __attribute__((ext_vector_type(2)));
+
+// Two bf16 values (one 32-bit word, first in the low half) -> two E4M3 codes in the low 16 bits,
+// round to nearest even, saturated to +/-448: bf16 is sign-magnitude, so the magnitudes are clamped
+// as 16-bit integers at 0x43e0 (448), then the gfx950 bf16 -> E4M3 conversion (unit scale) is exact.
+__device__ inline uint32_t bf16x2_to_e4m3(uint32_t w) {
+    const uint32_t sign = w & 0x80008000u;
+    ushort2v mag = __builtin_bit_cast(ushort2v, w & 0x7fff7fffu);
+    mag = __builtin_elementwise_min(mag, (ushort2v){0x43e0, 0x43e0});
+    const bf16x2v v = __builtin_bit_cast(bf16x2v, __builtin_bit_cast(uint32_t, mag) | sign);
+    const short2v r = __builtin_amdgcn_cvt_scalef32_pk_fp8_bf16((short2v){0, 0}, v, 1.0f, false);
+    return __builtin_bit_cast(uint32_t, r) & 0xffffu;
 }
 
 template <bool FP8, int RB_, int WV_>
@@ -121,11 +136,8 @@ __device__ inline floatx16 mma(const Frag<FP8>& a, const Frag<FP8>& b, floatx16 
 
 // Eight bf16 values (16 bytes) -> eight E4M3 codes (8 bytes).
 __device__ inline uint2 bf16x8_to_e4m3(uint4 v) {
-    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-    uint32_t o[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) o[i] = to_e4m3_pair(bf16_to_f32((uint16_t)(w[i] & 0xffff)), bf16_to_f32((uint16_t)(w[i] >> 16)));
-    return make_uint2(o[0] | (o[1] << 16), o[2] | (o[3] << 16));
+    return make_uint2(bf16x2_to_e4m3(v.x) | (bf16x2_to_e4m3(v.y) << 16),
+                      bf16x2_to_e4m3(v.z) | (bf16x2_to_e4m3(v.w) << 16));
 }
 
 // One phase-2 pass over NB 32-column blocks of Brs (K = 128): acc[c][i] = g rows of row block i
@@ -295,6 +307,7 @@ void layer_lp_kernel(LayerArgsLP p) {
         const int n = 32 * q + r;
         const float bf = p.bc[n], bg = p.bc[kC + n];
         const float sf = FP8 ? p.sc[n] : 1.f, sg = FP8 ? p.sc[kC + n] : 1.f;
+        float gprev = 0.f;
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
@@ -308,8 +321,17 @@ void layer_lp_kernel(LayerArgsLP p) {
                     po[kC + n] = vg;
                 }
                 const float gv = gate_fast(vf, vg);
-                if (FP8) A[m * T::ROW + n] = (uint8_t)(to_e4m3_pair(gv, 0.f) & 0xffu);
-                else *(uint16_t*)&A[m * T::ROW + 2 * n] = to_bf16_bits(gv);
+                if (FP8) {  // rows m (i even) and m + 1 (i odd) converted together
+                    if (i & 1) {
+                        const uint32_t c2 = e4m3_pair_in_range(gprev, gv);
+                        A[(m - 1) * T::ROW + n] = (uint8_t)(c2 & 0xffu);
+                        A[m * T::ROW + n] = (uint8_t)(c2 >> 8);
+                    } else {
+                        gprev = gv;
+                    }
+                } else {
+                    *(uint16_t*)&A[m * T::ROW + 2 * n] = to_bf16_bits(gv);
+                }
                 if (i == 15) __builtin_amdgcn_sched_barrier(0);   // keep row blocks apart (register pressure)
             }
     }
@@ -836,13 +858,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                 *(uint4*)(XE + (rr - dil) * FE_ROW + 16 * cc) = *(const uint4*)(XE + (FE_ROWS - dil + rr) * FE_ROW + 16 * cc);
             }
             // ---- gate -> E4M3 operand rows
+            float gprev = 0.f;
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                 for (int i = 0; i < 16; ++i) {
                     const int m = 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
                     const float gv = gate_fast(fmaf(af[rb][i], sf, bf), fmaf(ag[rb][i], sg, bg));
-                    GE[m * FE_ROW + n] = (uint8_t)(to_e4m3_pair(gv, 0.f) & 0xffu);
+                    if (i & 1) {  // rows m - 1 and m converted together
+                        const uint32_t c2 = e4m3_pair_in_range(gprev, gv);
+                        GE[(m - 1) * FE_ROW + n] = (uint8_t)(c2 & 0xffu);
+                        GE[m * FE_ROW + n] = (uint8_t)(c2 >> 8);
+                    } else {
+                        gprev = gv;
+                    }
                     if (i == 15) __builtin_amdgcn_sched_barrier(0);
                 }
             __syncthreads();
@@ -875,6 +904,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                     for (int i = 0; i < RB; ++i) acc[i] = mma<true>(a[i], ring[k], acc[i]);
                 }
                 if (pass == 0) {  // x_next = x + (scale * acc + b_res) in bf16; E4M3 operand of the next layer
+                    uint32_t xprev = 0;
 #pragma unroll
                     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
@@ -884,7 +914,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                             const uint16_t xb = (uint16_t)((i & 1) ? (w >> 16) : (w & 0xffffu));
                             const uint16_t xn = to_bf16_bits(bf16_to_f32(xb) + fmaf(acc[rb][i], s_r, br));
                             *(uint16_t*)(XBo + m * FU_XROW + 2 * n) = xn;
-                            if (j < 2) XEo[m * FE_ROW + n] = (uint8_t)(to_e4m3_pair(bf16_to_f32(xn), 0.f) & 0xffu);
+                            if (j < 2) {  // rows m - 1 and m of the next layer's operand, converted together
+                                if (i & 1) {
+                                    const uint32_t c2 = bf16x2_to_e4m3(xprev | ((uint32_t)xn << 16));
+                                    XEo[(m - 1) * FE_ROW + n] = (uint8_t)(c2 & 0xffu);
+                                    XEo[m * FE_ROW + n] = (uint8_t)(c2 >> 8);
+                                } else {
+                                    xprev = xn;
+                                }
+                            }
                         }
                     __builtin_amdgcn_sched_barrier(0);
                 } else {
