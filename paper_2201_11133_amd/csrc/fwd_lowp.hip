@@ -458,6 +458,39 @@ struct FusedArgs {
 
 __device__ inline uint8_t* fu_buf(uint8_t* lds, int j) { return lds + j * FU_XBUF + FU_HIST * FU_XROW; }
 
+// Sixteen fp32 values of one 32-channel block in the transposed accumulator layout (see
+// fused3_bf16_kernel): element 4 g + e is channel 8 g + e of b, where b already points at the
+// block's first channel + 4 h.
+__device__ inline floatx16 load_col16(const float* b) {
+    floatx16 v;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const float4 t = *(const float4*)(b + 8 * g);
+        v[4 * g] = t.x;
+        v[4 * g + 1] = t.y;
+        v[4 * g + 2] = t.z;
+        v[4 * g + 3] = t.w;
+    }
+    return v;
+}
+
+__device__ inline void store_col16(float* b, const floatx16& v) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g) *(float4*)(b + 8 * g) = make_float4(v[4 * g], v[4 * g + 1], v[4 * g + 2], v[4 * g + 3]);
+}
+
+// Two fp32 values rounded to bf16 (nearest even) in one conversion; a in the low half.
+typedef float float2v __attribute__((ext_vector_type(2)));
+__device__ inline uint32_t pack_bf16x2(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((float2v){a, b}, bf16x2v));
+}
+
+// x + v for four bf16 channels held in w, rounded back to bf16.
+__device__ inline uint2 residual4(uint2 w, float v0, float v1, float v2, float v3) {
+    return make_uint2(pack_bf16x2(__uint_as_float(w.x << 16) + v0, __uint_as_float(w.x & 0xffff0000u) + v1),
+                      pack_bf16x2(__uint_as_float(w.y << 16) + v2, __uint_as_float(w.y & 0xffff0000u) + v3));
+}
+
 template <bool FROM_STREAM, bool SKIP_INIT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void fused3_bf16_kernel(FusedArgs p) {
     using T = LP<false, 2, 4>;  // bf16 fragments, 4 waves x 2 row blocks
@@ -485,7 +518,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
         const int j = idx / (FU_HIST * 16), rr = (idx >> 4) % FU_HIST, c = idx & 15;
         *(uint4*)(fu_buf(lds, j) + (rr - FU_HIST) * FU_XROW + 16 * c) = make_uint4(0, 0, 0, 0);
     }
-    const int n = 32 * q + r;
+    // Products are taken transposed: weight fragments are the A operand and row fragments the B
+    // operand, so an accumulator holds rows along the lanes. Lane (h, r) holds row r of each
+    // 32-row block and, of its wave's 32-channel block, the channels 8 g + 4 h + e (g, e = 0..3):
+    // four runs of four consecutive channels, which move as 8- and 16-byte words.
+    const int cb = 32 * q + 4 * h;
     for (int c = (seg > 0 ? c0 - 1 : c0); c < c1; ++c) {
         const bool store = c >= c0;
         const int sb = c * FU_ROWS;
@@ -519,14 +556,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                 }
             }
         }
-        float sk[2][16];
+        floatx16 sk[2];
 #pragma unroll
-        for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int sr = sb + 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
-                sk[rb][i] = (!SKIP_INIT && store && sr < n_sub) ? p.skip[(wrow0 + cls + p.d0 * sr) * kC + n] : 0.f;
-            }
+        for (int rb = 0; rb < 2; ++rb) {
+            const int sr = sb + 32 * rb + r;
+            sk[rb] = splat16(0.f);
+            if (!SKIP_INIT && store && sr < n_sub) sk[rb] = load_col16(p.skip + (wrow0 + cls + (int64_t)p.d0 * sr) * kC + cb);
+        }
         uint8_t* X0 = fu_buf(lds, 0);
 #pragma unroll
         for (int it = 0; it < 4; ++it) {
@@ -540,11 +576,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
             const int dil = 1 << j;  // dilation in sub-rows
             uint8_t* Xin = fu_buf(lds, j);
             uint8_t* Xo = fu_buf(lds, j < 2 ? j + 1 : 0);  // the last layer's output goes to buffer 0
-            // biases first: their loads complete behind phase 1
-            const float bf = p.bc[j][n], bg = p.bc[j][kC + n], br = p.brs[j][n], bs = p.brs[j][kC + n];
+            // biases first: they are the first products' accumulator inputs
+            const floatx16 bf = load_col16(p.bc[j] + cb), bg = load_col16(p.bc[j] + kC + cb);
             // ---- phase 1: pre = [x[s - dil] | x[s]] Bc, K = 256 (k-steps 0-7: tap s - dil, 8-15: tap s);
             // weight fragments from a register ring, operand fragments one step ahead
-            floatx16 af[2] = {splat16(bf), splat16(bf)}, ag[2] = {splat16(bg), splat16(bg)};
+            floatx16 af[2], ag[2];
             {
                 const uint8_t* A0 = Xin + r * FU_XROW + 16 * h;
                 const uint8_t* Bf = p.wc[j] + ((size_t)(q * T::NK1) * 64 + lane) * T::FRAG;
@@ -575,15 +611,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                     __builtin_amdgcn_sched_barrier(0);  // the next step's loads issue before this step's MFMAs
 #pragma unroll
                     for (int i = 0; i < 2; ++i) {
-                        af[i] = mma<false>(acur[i], cf, af[i]);
-                        ag[i] = mma<false>(acur[i], cg, ag[i]);
+                        af[i] = mma<false>(cf, acur[i], k == 0 ? bf : af[i]);
+                        ag[i] = mma<false>(cg, acur[i], k == 0 ? bg : ag[i]);
                     }
                     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                     for (int i = 0; i < 2; ++i) acur[i] = anxt[i];
                 }
             }
-            // first weight fragments of the residual pass: in flight during the gate
+            // residual bias and the first weight fragments of the residual pass: in flight during the gate
+            const floatx16 br = load_col16(p.brs[j] + cb);
             const uint8_t* Wr = p.wrs[j] + ((size_t)(q * T::NK2) * 64 + lane) * T::FRAG;
             const uint8_t* Ws = p.wrs[j] + ((size_t)((4 + q) * T::NK2) * 64 + lane) * T::FRAG;
             Frag<false> ring[T::PF2];
@@ -595,18 +632,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                 const int rr = tid >> 4, cc = tid & 15;
                 *(uint4*)(Xin + (rr - dil) * FU_XROW + 16 * cc) = *(const uint4*)(Xin + (FU_ROWS - dil + rr) * FU_XROW + 16 * cc);
             }
-            // ---- gate -> G
+            // ---- gate -> G: per row block, four 8-byte writes of four channels
 #pragma unroll
-            for (int rb = 0; rb < 2; ++rb)
+            for (int rb = 0; rb < 2; ++rb) {
+                uint8_t* gr = G + (32 * rb + r) * FU_XROW + 2 * cb;
 #pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    const int m = 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
-                    *(uint16_t*)&G[m * FU_XROW + 2 * n] = to_bf16_bits(gate_fast(af[rb][i], ag[rb][i]));
-                    if (i == 15) __builtin_amdgcn_sched_barrier(0);
+                for (int g = 0; g < 4; ++g) {
+                    const int i = 4 * g;
+                    *(uint2*)(gr + 16 * g) =
+                        make_uint2(pack_bf16x2(gate_fast(af[rb][i], ag[rb][i]), gate_fast(af[rb][i + 1], ag[rb][i + 1])),
+                                   pack_bf16x2(gate_fast(af[rb][i + 2], ag[rb][i + 2]), gate_fast(af[rb][i + 3], ag[rb][i + 3])));
                 }
+                __builtin_amdgcn_sched_barrier(0);
+            }
             __syncthreads();
             // ---- phase 2 over G (K = 128): residual columns, then skip columns
             const uint8_t* Ag = G + r * FU_XROW + 16 * h;
+            floatx16 bs;
 #pragma unroll
             for (int pass = 0; pass < 2; ++pass) {
                 const uint8_t* Wm = pass == 0 ? Wr : Ws;
@@ -614,20 +656,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
 #pragma unroll
                     for (int k = 0; k < T::PF2; ++k) ring[k] = load_frag<false>(Ws + (size_t)k * 64 * T::FRAG);
                 }
-                // residual inputs of this lane, gathered before any output is written
-                uint32_t xold[2][8];
+                // residual inputs of this lane, gathered before any output is written; skip bias
+                uint2 xold[2][4];
                 if (pass == 0) {
+                    bs = load_col16(p.brs[j] + kC + cb);
 #pragma unroll
                     for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-                        for (int i = 0; i < 16; i += 2) {
-                            const int m = 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
-                            const uint32_t lo = *(const uint16_t*)(Xin + m * FU_XROW + 2 * n);
-                            const uint32_t hi = *(const uint16_t*)(Xin + (m + 1) * FU_XROW + 2 * n);
-                            xold[rb][i >> 1] = lo | (hi << 16);
-                        }
+                        for (int g = 0; g < 4; ++g) xold[rb][g] = *(const uint2*)(Xin + (32 * rb + r) * FU_XROW + 2 * cb + 16 * g);
                 }
-                floatx16 acc[2] = {splat16(pass == 0 ? br : bs), splat16(pass == 0 ? br : bs)};
+                floatx16 acc[2];
                 Frag<false> acur[2], anxt[2];
 #pragma unroll
                 for (int i = 0; i < 2; ++i) acur[i] = load_frag<false>(Ag + 32 * i * FU_XROW);
@@ -642,35 +680,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                     }
                     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                    for (int i = 0; i < 2; ++i) acc[i] = mma<false>(acur[i], cw, acc[i]);
+                    for (int i = 0; i < 2; ++i) acc[i] = mma<false>(cw, acur[i], k == 0 ? (pass == 0 ? br : bs) : acc[i]);
                     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                     for (int i = 0; i < 2; ++i) acur[i] = anxt[i];
                 }
                 if (pass == 0) {  // x_next = x + (g Brs_res + b_res), rounded to bf16
 #pragma unroll
-                    for (int rb = 0; rb < 2; ++rb)
+                    for (int rb = 0; rb < 2; ++rb) {
+                        uint8_t* xr = Xo + (32 * rb + r) * FU_XROW + 2 * cb;
 #pragma unroll
-                        for (int i = 0; i < 16; ++i) {
-                            const int m = 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
-                            const uint32_t w = xold[rb][i >> 1];
-                            const uint16_t xb = (uint16_t)((i & 1) ? (w >> 16) : (w & 0xffffu));
-                            *(uint16_t*)(Xo + m * FU_XROW + 2 * n) = to_bf16_bits(bf16_to_f32(xb) + acc[rb][i]);
+                        for (int g = 0; g < 4; ++g) {
+                            const int i = 4 * g;
+                            *(uint2*)(xr + 16 * g) = residual4(xold[rb][g], acc[rb][i], acc[rb][i + 1], acc[rb][i + 2], acc[rb][i + 3]);
                         }
+                    }
                     __builtin_amdgcn_sched_barrier(0);
                 } else {  // skip += g Brs_skip + b_skip
 #pragma unroll
                     for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-                        for (int i = 0; i < 16; ++i) {
-                            const float sv = acc[rb][i];
-                            sk[rb][i] = (SKIP_INIT && j == 0) ? sv : sk[rb][i] + sv;
-                        }
+                        for (int i = 0; i < 16; ++i) sk[rb][i] = (SKIP_INIT && j == 0) ? acc[rb][i] : sk[rb][i] + acc[rb][i];
                 }
             }
             __syncthreads();  // the next layer's input (or the chunk's output) is complete
         }
-        // ---- chunk output: x rows from buffer 0 (16-byte stores), skip from registers
+        // ---- chunk output: x rows from buffer 0 (16-byte stores), skip rows from registers
         if (store) {
 #pragma unroll
             for (int it = 0; it < 4; ++it) {
@@ -680,12 +715,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                     *(uint4*)&p.x_out[(wrow0 + cls + p.d0 * sr) * kC + c8] = *(const uint4*)(X0 + rr * FU_XROW + 2 * c8);
             }
 #pragma unroll
-            for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    const int sr = sb + 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
-                    if (sr < n_sub) p.skip[(wrow0 + cls + p.d0 * sr) * kC + n] = sk[rb][i];
-                }
+            for (int rb = 0; rb < 2; ++rb) {
+                const int sr = sb + 32 * rb + r;
+                if (sr < n_sub) store_col16(p.skip + (wrow0 + cls + (int64_t)p.d0 * sr) * kC + cb, sk[rb]);
+            }
         }
         __syncthreads();  // buffer 0 is read above before the next chunk stages into it
     }

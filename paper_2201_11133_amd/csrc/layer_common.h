@@ -10,17 +10,16 @@ __device__ inline float sigmoid_f32(float x) { return 1.f / (1.f + expf(-x)); }
 __device__ inline float gate_f32(float af, float ag) { return tanhf(af) * sigmoid_f32(ag); }
 
 // The same gate for the reduced-precision paths, whose result is rounded to bf16 / E4M3 right away:
-// with E_a = e^(-2a) and E_b = e^-b, tanh(a) sigmoid(b) = (1 - E_a) / ((1 + E_a)(1 + E_b)), from two
-// hardware exp2 and one reciprocal (a few ulp in fp32, far below the bf16 rounding step). a is
-// clamped below at -10 (tanh(-10) rounds to -1 in fp32), so E_a stays finite; a denominator that
-// overflows gives 0 where the true value is below 1e-30; a NaN from b propagates.
+// with E = e^(-2|a|) and E_b = e^-b, tanh(a) sigmoid(b) = sign(a) (1 - E) / ((1 + E)(1 + E_b)), from
+// two hardware exp2 and one reciprocal (a few ulp in fp32, far below the bf16 rounding step). E lies
+// in (0, 1] for every a, so nothing overflows on the tanh side; a denominator that overflows gives 0
+// where the true value is below 1e-30; a NaN from a or b propagates.
 __device__ inline float gate_fast(float af, float ag) {
     const float kLog2e = 1.4426950408889634f;
-    const float a = fmaxf(af, -10.f);
-    const float ea = __builtin_amdgcn_exp2f(-2.f * kLog2e * a);
+    const float ea = __builtin_amdgcn_exp2f(-2.f * kLog2e * fabsf(af));  // e^(-2|a|), in (0, 1]
     const float eb = __builtin_amdgcn_exp2f(-kLog2e * ag);
     const float ob = 1.f + eb;
-    return (1.f - ea) * __builtin_amdgcn_rcpf(fmaf(ea, ob, ob));
+    return copysignf((1.f - ea) * __builtin_amdgcn_rcpf(fmaf(ea, ob, ob)), af);
 }
 
 // Where the logits of one window go.
