@@ -491,11 +491,36 @@ __device__ inline uint2 residual4(uint2 w, float v0, float v1, float v2, float v
                       pack_bf16x2(__uint_as_float(w.y << 16) + v2, __uint_as_float(w.y & 0xffff0000u) + v3));
 }
 
+__device__ inline floatx16 lds_col16(const float* b) {
+    floatx16 v;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const float4 t = *(const float4*)(b + 8 * g);
+        v[4 * g] = t.x;
+        v[4 * g + 1] = t.y;
+        v[4 * g + 2] = t.z;
+        v[4 * g + 3] = t.w;
+    }
+    return v;
+}
+
+constexpr int FU_BIAS = 3 * 4 * kC * 4;  // biases of the three layers in LDS: [layer][conv 256 | res 128 | skip 128]
+
+// The input rows of one chunk as this thread stages them: four 16-byte pieces of bf16 x, or, for
+// the first triple, the two stream samples of each piece's row (the input projection is applied
+// when the rows are staged).
+template <bool FROM_STREAM>
+struct ChunkRows {
+    uint4 v[FROM_STREAM ? 1 : 4];
+    float u[FROM_STREAM ? 4 : 1][2];
+};
+
 template <bool FROM_STREAM, bool SKIP_INIT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void fused3_bf16_kernel(FusedArgs p) {
     using T = LP<false, 2, 4>;  // bf16 fragments, 4 waves x 2 row blocks
-    __shared__ __attribute__((aligned(16))) uint8_t lds[FU_LDS];
+    __shared__ __attribute__((aligned(16))) uint8_t lds[FU_LDS + FU_BIAS];
     uint8_t* G = lds + 3 * FU_XBUF;
+    float* BI = (float*)(lds + FU_LDS);
     const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6, h = lane >> 5, r = lane & 31;
     const int seg = blockIdx.x % p.n_seg;
     const int cls = (blockIdx.x / p.n_seg) % p.d0;
@@ -518,56 +543,76 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
         const int j = idx / (FU_HIST * 16), rr = (idx >> 4) % FU_HIST, c = idx & 15;
         *(uint4*)(fu_buf(lds, j) + (rr - FU_HIST) * FU_XROW + 16 * c) = make_uint4(0, 0, 0, 0);
     }
+    // the biases of the three layers, once per block
+    for (int idx = tid; idx < 3 * 4 * kC; idx += 256) {
+        const int j = idx / (4 * kC), e = idx % (4 * kC);
+        BI[idx] = e < 2 * kC ? p.bc[j][e] : p.brs[j][e - 2 * kC];
+    }
     // Products are taken transposed: weight fragments are the A operand and row fragments the B
     // operand, so an accumulator holds rows along the lanes. Lane (h, r) holds row r of each
     // 32-row block and, of its wave's 32-channel block, the channels 8 g + 4 h + e (g, e = 0..3):
     // four runs of four consecutive channels, which move as 8- and 16-byte words.
     const int cb = 32 * q + 4 * h;
-    for (int c = (seg > 0 ? c0 - 1 : c0); c < c1; ++c) {
-        const bool store = c >= c0;
+    // Global loads retire in issue order, so a load from HBM would hold up the next wait on a
+    // weight fragment. HBM rows are therefore requested right before a gate, which waits on no
+    // load for thousands of cycles: the skip rows of a chunk before its first layer's gate, the
+    // input rows of the next chunk before the last layer's gate. The weight fragments of each
+    // layer's first steps are requested during the previous layer's second phase.
+    auto fetch_rows = [&](int c, ChunkRows<FROM_STREAM>& cr) {
         const int sb = c * FU_ROWS;
-        // ---- stage the first layer's input rows [0, 64) of the chunk; prefetch the skip rows
-        uint4 v[4];
 #pragma unroll
         for (int it = 0; it < 4; ++it) {
             const int idx = tid + 256 * it, rr = idx >> 4, c8 = 8 * (idx & 15);
             const int sr = sb + rr;
             const int t = cls + p.d0 * sr;
-            v[it] = make_uint4(0, 0, 0, 0);
-            if (sr < n_sub) {
-                if (FROM_STREAM) {  // input projection x0 = W_in u[t] + b_in, rounded to bf16
-                    float u0 = 0.f, u1 = 0.f;
-                    const int64_t smp = start + t;
-                    if (smp < sd.length) {
-                        u0 = sd.ch0[smp * sd.stride];
-                        u1 = sd.ch1[smp * sd.stride];
-                    }
-                    uint32_t w[4];
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int ch = c8 + 2 * e;
-                        const float x0 = p.b_in[ch] + p.w_in[2 * ch] * u0 + p.w_in[2 * ch + 1] * u1;
-                        const float x1 = p.b_in[ch + 1] + p.w_in[2 * ch + 2] * u0 + p.w_in[2 * ch + 3] * u1;
-                        w[e] = (uint32_t)to_bf16_bits(x0) | ((uint32_t)to_bf16_bits(x1) << 16);
-                    }
-                    v[it] = make_uint4(w[0], w[1], w[2], w[3]);
-                } else {
-                    v[it] = *(const uint4*)&p.x_in[(wrow0 + t) * kC + c8];
+            if (FROM_STREAM) {
+                cr.u[it][0] = 0.f;
+                cr.u[it][1] = 0.f;
+                const int64_t smp = start + t;
+                if (sr < n_sub && smp < sd.length) {
+                    cr.u[it][0] = sd.ch0[smp * sd.stride];
+                    cr.u[it][1] = sd.ch1[smp * sd.stride];
                 }
+            } else {
+                cr.v[it] = sr < n_sub ? *(const uint4*)&p.x_in[(wrow0 + t) * kC + c8] : make_uint4(0, 0, 0, 0);
             }
         }
-        floatx16 sk[2];
+    };
+    ChunkRows<FROM_STREAM> nrows;
+    fetch_rows(seg > 0 ? c0 - 1 : c0, nrows);
+    // the weight-fragment ring of the first phase; its first FU_PRE slots are loaded ahead of each layer
+    constexpr int FU_PRE = 2;
+    Frag<false> rf[T::PF1], rg[T::PF1];
 #pragma unroll
-        for (int rb = 0; rb < 2; ++rb) {
-            const int sr = sb + 32 * rb + r;
-            sk[rb] = splat16(0.f);
-            if (!SKIP_INIT && store && sr < n_sub) sk[rb] = load_col16(p.skip + (wrow0 + cls + (int64_t)p.d0 * sr) * kC + cb);
-        }
+    for (int k = 0; k < FU_PRE; ++k) {
+        rf[k] = load_frag<false>(p.wc[0] + ((size_t)(q * T::NK1 + k) * 64 + lane) * T::FRAG);
+        rg[k] = load_frag<false>(p.wc[0] + ((size_t)((4 + q) * T::NK1 + k) * 64 + lane) * T::FRAG);
+    }
+    for (int c = (seg > 0 ? c0 - 1 : c0); c < c1; ++c) {
+        const bool store = c >= c0;
+        const int sb = c * FU_ROWS;
+        floatx16 sk[2];
+        // ---- stage the first layer's input rows [0, 64) of the chunk
         uint8_t* X0 = fu_buf(lds, 0);
 #pragma unroll
         for (int it = 0; it < 4; ++it) {
             const int idx = tid + 256 * it, rr = idx >> 4, c8 = 8 * (idx & 15);
-            *(uint4*)(X0 + rr * FU_XROW + 2 * c8) = v[it];
+            uint4 v;
+            if (FROM_STREAM) {  // input projection x0 = W_in u[t] + b_in, rounded to bf16 (zero past the sub-sequence end)
+                const float u0 = nrows.u[it][0], u1 = nrows.u[it][1];
+                uint32_t w[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int ch = c8 + 2 * e;
+                    const float x0 = p.b_in[ch] + p.w_in[2 * ch] * u0 + p.w_in[2 * ch + 1] * u1;
+                    const float x1 = p.b_in[ch + 1] + p.w_in[2 * ch + 2] * u0 + p.w_in[2 * ch + 3] * u1;
+                    w[e] = (uint32_t)to_bf16_bits(x0) | ((uint32_t)to_bf16_bits(x1) << 16);
+                }
+                v = sb + rr < n_sub ? make_uint4(w[0], w[1], w[2], w[3]) : make_uint4(0, 0, 0, 0);
+            } else {
+                v = nrows.v[it];
+            }
+            *(uint4*)(X0 + rr * FU_XROW + 2 * c8) = v;
         }
         __syncthreads();
 
@@ -576,18 +621,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
             const int dil = 1 << j;  // dilation in sub-rows
             uint8_t* Xin = fu_buf(lds, j);
             uint8_t* Xo = fu_buf(lds, j < 2 ? j + 1 : 0);  // the last layer's output goes to buffer 0
-            // biases first: they are the first products' accumulator inputs
-            const floatx16 bf = load_col16(p.bc[j] + cb), bg = load_col16(p.bc[j] + kC + cb);
+            const float* bj = BI + j * 4 * kC;
+            // biases are the first products' accumulator inputs
+            const floatx16 bf = lds_col16(bj + cb), bg = lds_col16(bj + kC + cb);
             // ---- phase 1: pre = [x[s - dil] | x[s]] Bc, K = 256 (k-steps 0-7: tap s - dil, 8-15: tap s);
-            // weight fragments from a register ring, operand fragments one step ahead
+            // weight fragments from the register ring, operand fragments one step ahead
             floatx16 af[2], ag[2];
             {
                 const uint8_t* A0 = Xin + r * FU_XROW + 16 * h;
                 const uint8_t* Bf = p.wc[j] + ((size_t)(q * T::NK1) * 64 + lane) * T::FRAG;
                 const uint8_t* Bg = p.wc[j] + ((size_t)((4 + q) * T::NK1) * 64 + lane) * T::FRAG;
-                Frag<false> rf[T::PF1], rg[T::PF1];
 #pragma unroll
-                for (int k = 0; k < T::PF1; ++k) {
+                for (int k = FU_PRE; k < T::PF1; ++k) {
                     rf[k] = load_frag<false>(Bf + (size_t)k * 64 * T::FRAG);
                     rg[k] = load_frag<false>(Bg + (size_t)k * 64 * T::FRAG);
                 }
@@ -619,13 +664,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                     for (int i = 0; i < 2; ++i) acur[i] = anxt[i];
                 }
             }
-            // residual bias and the first weight fragments of the residual pass: in flight during the gate
-            const floatx16 br = load_col16(p.brs[j] + cb);
+            // the weight fragments of the second phase: one stream of 2 NK2 steps, residual columns
+            // then skip columns; its first PF2 are in flight during the gate
             const uint8_t* Wr = p.wrs[j] + ((size_t)(q * T::NK2) * 64 + lane) * T::FRAG;
             const uint8_t* Ws = p.wrs[j] + ((size_t)((4 + q) * T::NK2) * 64 + lane) * T::FRAG;
             Frag<false> ring[T::PF2];
 #pragma unroll
             for (int k = 0; k < T::PF2; ++k) ring[k] = load_frag<false>(Wr + (size_t)k * 64 * T::FRAG);
+            const bool more = j < 2 || c + 1 < c1;
+            if (j == 2 && c + 1 < c1) fetch_rows(c + 1, nrows);  // next chunk's rows, in flight during the gate
+            if (j == 0) {  // this chunk's skip rows, first needed in this layer's skip pass
+#pragma unroll
+                for (int rb = 0; rb < 2; ++rb) {
+                    const int sr = sb + 32 * rb + r;
+                    sk[rb] = splat16(0.f);
+                    if (!SKIP_INIT && store && sr < n_sub) sk[rb] = load_col16(p.skip + (wrow0 + cls + (int64_t)p.d0 * sr) * kC + cb);
+                }
+            }
+            const floatx16 br = lds_col16(bj + 2 * kC + cb);
             __syncthreads();  // every wave is done with this layer's input rows
             // this input's last dil rows become the history of the next chunk
             if (tid < 16 * dil) {
@@ -648,39 +704,44 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
             __syncthreads();
             // ---- phase 2 over G (K = 128): residual columns, then skip columns
             const uint8_t* Ag = G + r * FU_XROW + 16 * h;
-            floatx16 bs;
+            const int jn = j < 2 ? j + 1 : 0;  // the next layer (the first of the next chunk after the last)
+            const uint8_t* Nf = p.wc[jn] + ((size_t)(q * T::NK1) * 64 + lane) * T::FRAG;
+            const uint8_t* Ng = p.wc[jn] + ((size_t)((4 + q) * T::NK1) * 64 + lane) * T::FRAG;
 #pragma unroll
             for (int pass = 0; pass < 2; ++pass) {
-                const uint8_t* Wm = pass == 0 ? Wr : Ws;
-                if (pass == 1) {
-#pragma unroll
-                    for (int k = 0; k < T::PF2; ++k) ring[k] = load_frag<false>(Ws + (size_t)k * 64 * T::FRAG);
-                }
-                // residual inputs of this lane, gathered before any output is written; skip bias
+                // residual inputs of this lane, gathered before any output is written
                 uint2 xold[2][4];
                 if (pass == 0) {
-                    bs = load_col16(p.brs[j] + kC + cb);
 #pragma unroll
                     for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
                         for (int g = 0; g < 4; ++g) xold[rb][g] = *(const uint2*)(Xin + (32 * rb + r) * FU_XROW + 2 * cb + 16 * g);
                 }
+                const floatx16 bias = pass == 0 ? br : lds_col16(bj + 3 * kC + cb);
                 floatx16 acc[2];
                 Frag<false> acur[2], anxt[2];
 #pragma unroll
                 for (int i = 0; i < 2; ++i) acur[i] = load_frag<false>(Ag + 32 * i * FU_XROW);
 #pragma unroll
                 for (int k = 0; k < T::NK2; ++k) {
-                    const int slot = k % T::PF2;
+                    const int st = pass * T::NK2 + k, slot = st % T::PF2;
                     const Frag<false> cw = ring[slot];
-                    if (k + T::PF2 < T::NK2) ring[slot] = load_frag<false>(Wm + (size_t)(k + T::PF2) * 64 * T::FRAG);
+                    if (st + T::PF2 < 2 * T::NK2) {
+                        const int kn = st + T::PF2;
+                        ring[slot] = load_frag<false>((kn < T::NK2 ? Wr : Ws) + (size_t)(kn % T::NK2) * 64 * T::FRAG);
+                    }
+                    // the next layer's first-phase ring, in the skip pass (its registers are free)
+                    if (pass == 1 && k < FU_PRE && more) {
+                        rf[k] = load_frag<false>(Nf + (size_t)k * 64 * T::FRAG);
+                        rg[k] = load_frag<false>(Ng + (size_t)k * 64 * T::FRAG);
+                    }
                     if (k + 1 < T::NK2) {
 #pragma unroll
                         for (int i = 0; i < 2; ++i) anxt[i] = load_frag<false>(Ag + 32 * i * FU_XROW + 32 * (k + 1));
                     }
                     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                    for (int i = 0; i < 2; ++i) acc[i] = mma<false>(cw, acur[i], k == 0 ? (pass == 0 ? br : bs) : acc[i]);
+                    for (int i = 0; i < 2; ++i) acc[i] = mma<false>(cw, acur[i], k == 0 ? bias : acc[i]);
                     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                     for (int i = 0; i < 2; ++i) acur[i] = anxt[i];
