@@ -582,6 +582,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
     fetch_rows(seg > 0 ? c0 - 1 : c0, nrows);
     // the weight-fragment ring of the first phase; its first FU_PRE slots are loaded ahead of each layer
     constexpr int FU_PRE = 2;
+    constexpr int FU_PF2 = 2;  // second-phase ring depth in fragment pairs (four MFMAs per step)
     Frag<false> rf[T::PF1], rg[T::PF1];
 #pragma unroll
     for (int k = 0; k < FU_PRE; ++k) {
@@ -664,16 +665,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                     for (int i = 0; i < 2; ++i) acur[i] = anxt[i];
                 }
             }
-            // the weight fragments of the second phase: one stream of 2 NK2 steps, residual columns
-            // then skip columns; its first PF2 are in flight during the gate
+            // the weight fragments of the second phase, residual and skip columns side by side; the
+            // first PF2 pairs are in flight during the gate
             const uint8_t* Wr = p.wrs[j] + ((size_t)(q * T::NK2) * 64 + lane) * T::FRAG;
             const uint8_t* Ws = p.wrs[j] + ((size_t)((4 + q) * T::NK2) * 64 + lane) * T::FRAG;
-            Frag<false> ring[T::PF2];
+            Frag<false> ringr[FU_PF2], rings[FU_PF2];
 #pragma unroll
-            for (int k = 0; k < T::PF2; ++k) ring[k] = load_frag<false>(Wr + (size_t)k * 64 * T::FRAG);
+            for (int k = 0; k < FU_PF2; ++k) {
+                ringr[k] = load_frag<false>(Wr + (size_t)k * 64 * T::FRAG);
+                rings[k] = load_frag<false>(Ws + (size_t)k * 64 * T::FRAG);
+            }
             const bool more = j < 2 || c + 1 < c1;
             if (j == 2 && c + 1 < c1) fetch_rows(c + 1, nrows);  // next chunk's rows, in flight during the gate
-            if (j == 0) {  // this chunk's skip rows, first needed in this layer's skip pass
+            if (j == 0) {  // this chunk's skip rows, first needed at the end of this layer
 #pragma unroll
                 for (int rb = 0; rb < 2; ++rb) {
                     const int sr = sb + 32 * rb + r;
@@ -681,7 +685,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                     if (!SKIP_INIT && store && sr < n_sub) sk[rb] = load_col16(p.skip + (wrow0 + cls + (int64_t)p.d0 * sr) * kC + cb);
                 }
             }
-            const floatx16 br = lds_col16(bj + 2 * kC + cb);
             __syncthreads();  // every wave is done with this layer's input rows
             // this input's last dil rows become the history of the next chunk
             if (tid < 16 * dil) {
@@ -701,39 +704,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
+            // residual inputs of this lane, gathered before any output is written
+            uint2 xold[2][4];
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int g = 0; g < 4; ++g) xold[rb][g] = *(const uint2*)(Xin + (32 * rb + r) * FU_XROW + 2 * cb + 16 * g);
+            const floatx16 br = lds_col16(bj + 2 * kC + cb), bs = lds_col16(bj + 3 * kC + cb);
             __syncthreads();
-            // ---- phase 2 over G (K = 128): residual columns, then skip columns
+            // ---- phase 2 over G (K = 128): each g fragment feeds the residual and the skip columns
             const uint8_t* Ag = G + r * FU_XROW + 16 * h;
             const int jn = j < 2 ? j + 1 : 0;  // the next layer (the first of the next chunk after the last)
             const uint8_t* Nf = p.wc[jn] + ((size_t)(q * T::NK1) * 64 + lane) * T::FRAG;
             const uint8_t* Ng = p.wc[jn] + ((size_t)((4 + q) * T::NK1) * 64 + lane) * T::FRAG;
-#pragma unroll
-            for (int pass = 0; pass < 2; ++pass) {
-                // residual inputs of this lane, gathered before any output is written
-                uint2 xold[2][4];
-                if (pass == 0) {
-#pragma unroll
-                    for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-                        for (int g = 0; g < 4; ++g) xold[rb][g] = *(const uint2*)(Xin + (32 * rb + r) * FU_XROW + 2 * cb + 16 * g);
-                }
-                const floatx16 bias = pass == 0 ? br : lds_col16(bj + 3 * kC + cb);
-                floatx16 acc[2];
+            floatx16 ar[2], as[2];
+            {
                 Frag<false> acur[2], anxt[2];
 #pragma unroll
                 for (int i = 0; i < 2; ++i) acur[i] = load_frag<false>(Ag + 32 * i * FU_XROW);
 #pragma unroll
                 for (int k = 0; k < T::NK2; ++k) {
-                    const int st = pass * T::NK2 + k, slot = st % T::PF2;
-                    const Frag<false> cw = ring[slot];
-                    if (st + T::PF2 < 2 * T::NK2) {
-                        const int kn = st + T::PF2;
-                        ring[slot] = load_frag<false>((kn < T::NK2 ? Wr : Ws) + (size_t)(kn % T::NK2) * 64 * T::FRAG);
-                    }
-                    // the next layer's first-phase ring, in the skip pass (its registers are free)
-                    if (pass == 1 && k < FU_PRE && more) {
-                        rf[k] = load_frag<false>(Nf + (size_t)k * 64 * T::FRAG);
-                        rg[k] = load_frag<false>(Ng + (size_t)k * 64 * T::FRAG);
+                    const int slot = k % FU_PF2;
+                    const Frag<false> cwr = ringr[slot], cws = rings[slot];
+                    if (k + FU_PF2 < T::NK2) {
+                        ringr[slot] = load_frag<false>(Wr + (size_t)(k + FU_PF2) * 64 * T::FRAG);
+                        rings[slot] = load_frag<false>(Ws + (size_t)(k + FU_PF2) * 64 * T::FRAG);
+                    } else if (k - (T::NK2 - FU_PF2) < FU_PRE && more) {
+                        // the next layer's first-phase ring, in registers this phase leaves free
+                        const int kk = k - (T::NK2 - FU_PF2);
+                        rf[kk] = load_frag<false>(Nf + (size_t)kk * 64 * T::FRAG);
+                        rg[kk] = load_frag<false>(Ng + (size_t)kk * 64 * T::FRAG);
                     }
                     if (k + 1 < T::NK2) {
 #pragma unroll
@@ -741,29 +741,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                     }
                     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                    for (int i = 0; i < 2; ++i) acc[i] = mma<false>(cw, acur[i], k == 0 ? bias : acc[i]);
+                    for (int i = 0; i < 2; ++i) {
+                        ar[i] = mma<false>(cwr, acur[i], k == 0 ? br : ar[i]);
+                        as[i] = mma<false>(cws, acur[i], k == 0 ? bs : as[i]);
+                    }
                     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                     for (int i = 0; i < 2; ++i) acur[i] = anxt[i];
                 }
-                if (pass == 0) {  // x_next = x + (g Brs_res + b_res), rounded to bf16
+            }
+            // x_next = x + (g Brs_res + b_res), rounded to bf16; skip += g Brs_skip + b_skip
 #pragma unroll
-                    for (int rb = 0; rb < 2; ++rb) {
-                        uint8_t* xr = Xo + (32 * rb + r) * FU_XROW + 2 * cb;
+            for (int rb = 0; rb < 2; ++rb) {
+                uint8_t* xr = Xo + (32 * rb + r) * FU_XROW + 2 * cb;
 #pragma unroll
-                        for (int g = 0; g < 4; ++g) {
-                            const int i = 4 * g;
-                            *(uint2*)(xr + 16 * g) = residual4(xold[rb][g], acc[rb][i], acc[rb][i + 1], acc[rb][i + 2], acc[rb][i + 3]);
-                        }
-                    }
-                    __builtin_amdgcn_sched_barrier(0);
-                } else {  // skip += g Brs_skip + b_skip
-#pragma unroll
-                    for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-                        for (int i = 0; i < 16; ++i) sk[rb][i] = (SKIP_INIT && j == 0) ? acc[rb][i] : sk[rb][i] + acc[rb][i];
+                for (int g = 0; g < 4; ++g) {
+                    const int i = 4 * g;
+                    *(uint2*)(xr + 16 * g) = residual4(xold[rb][g], ar[rb][i], ar[rb][i + 1], ar[rb][i + 2], ar[rb][i + 3]);
                 }
             }
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) sk[rb][i] = (SKIP_INIT && j == 0) ? as[rb][i] : sk[rb][i] + as[rb][i];
             __syncthreads();  // the next layer's input (or the chunk's output) is complete
         }
         // ---- chunk output: x rows from buffer 0 (16-byte stores), skip rows from registers
