@@ -18,4 +18,6 @@ Modules
   triggers  threshold + non-maximum-suppression trigger rule (+ brute force)
   train     per-timestep BCE loss, manual reverse-mode gradient, Adam
   quant     bfloat16 and FP8-E4M3 quantisers written from the formats
+  background  time-slid copies of a two-channel stream and the false-alarm
+            count per threshold ("Statistical Analysis")
 """
