@@ -207,6 +207,37 @@ def ragged_workload(gwd, blobs, prec: str):
             "triggers": n_trig, "precision": prec}
 
 
+def background_workload(gwd, blobs, x, prec: str, seconds: float = 900.0, n_slides: int = 4,
+                        step_s: float = 64.0):
+    """Time-slide background ("Statistical Analysis"): n_slides copies of a stream slice with channel 1
+    shifted by k * step_s seconds (circularly), scored in one forward call as ragged streams; the
+    false-alarm curve of their triggers."""
+    import torch
+    xs = x[: int(round(seconds * FS))]
+    L = xs.shape[0]
+    shifts = [k * int(step_s * FS) for k in range(1, n_slides + 1)]
+    m = gwd.Model(gwd.full_arch(), blobs, prec)
+    warm = gwd.time_slide(xs[: 64 * FS], shifts)
+    m.forward([warm[k] for k in range(n_slides)], W, S, out_mode=0)
+    del warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    slid = gwd.time_slide(xs, shifts)
+    e = m.forward([slid[k] for k in range(n_slides)], W, S, out_mode=0)
+    recs = gwd.triggers(e, [k * L for k in range(n_slides + 1)], 0.9, 4096)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    m.close()
+    live = n_slides * L / FS
+    probs = [0.9, 0.99, 0.999, 0.9998]
+    counts, far = gwd.far_curve(recs, [math.log(p / (1 - p)) for p in probs], live)
+    return {"slides": n_slides, "slide_step_s": step_s, "slice_s": round(L / FS, 1), "background_s": round(live, 1),
+            "strain_s_per_s": round(live / wall, 2), "triggers": len(recs),
+            "false_alarms_per_hour": {str(p): round(float(f) * 3600.0, 2) for p, f in zip(probs, far)},
+            "counts": {str(p): int(c) for p, c in zip(probs, counts)}, "precision": prec,
+            "note": "random-weight members: the rates show the mechanism, not a trained model's background"}
+
+
 def train_workload(gwd, steps: int = 2, B: int = 256):
     """Training of one full-size member: BF16 forward with per-stack checkpoints, BCE on logits,
     hand-written backward (bf16-operand row GEMMs, fp32 weight-gradient GEMMs), Adam on fp32 master
@@ -276,6 +307,7 @@ def main():
     ap.add_argument("--no-ragged", action="store_true", help="skip the 32-stream ragged graph workload")
     ap.add_argument("--no-train", action="store_true", help="skip the training-throughput measurement")
     ap.add_argument("--no-streaming", action="store_true", help="skip the long-window (streaming) line")
+    ap.add_argument("--no-background", action="store_true", help="skip the time-slide background line")
     ap.add_argument("--stream-day", action=argparse.BooleanOptionalAction, default=True,
                     help="also run the streaming line over a full day (86400 s) of strain")
     ap.add_argument("--calib-copy", action="store_true",
@@ -347,6 +379,11 @@ def main():
         progress("ragged workload: 32 streams, one graph launch")
         ragged = ragged_workload(gwd, blobs, args.precision)
         progress(f"ragged: {ragged['strain_s_per_s']} strain-s/s over {ragged['stream_seconds_total']} s")
+    background = None
+    if not args.no_background:
+        progress("time-slide background")
+        background = background_workload(gwd, blobs, x, args.precision, min(900.0, args.seconds))
+        progress(f"background: {background['strain_s_per_s']} strain-s/s over {background['background_s']} s")
     train = None
     if not args.no_train:
         progress("training throughput")
@@ -370,7 +407,8 @@ def main():
         "cpu_baseline": cpu,
         "detail": {"triggers": main_r["triggers"], "tflops_step": round(main_r["tflops"], 2),
                    "ms_events": round(main_r["ms_events"], 3), "precisions": extra,
-                   "ragged_streams": ragged, "training": train, "streaming_variant": streaming},
+                   "ragged_streams": ragged, "time_slide_background": background, "training": train,
+                   "streaming_variant": streaming},
     }
     print(json.dumps(line), flush=True)
 

@@ -196,6 +196,37 @@ gwd_status gwd_triggers(const float* ens_logit, const int64_t* stream_offsets, i
                         double threshold_prob, int32_t cluster_window, gwd_trigger* out,
                         int64_t capacity, int64_t* n_found, void* hip_stream);
 
+/* ---- time-slide background ("Statistical Analysis") -------------------------
+ * The paper measures how often the ensemble fires on noise with years of
+ * background built from one month of two-detector data by time slides: one
+ * detector's strain is shifted against the other's by far more than the
+ * light travel time between the sites, so no astrophysical coincidence
+ * survives and every trigger in slid data is a false positive.
+ *
+ * gwd_time_slide writes, for each shift k, the slid copy of `src` as an
+ * interleaved device stream at dst + 2 * length * k (feed it to gwd_forward
+ * with elem_stride 2):
+ *   dst[k][t][0] = ch0[t],   dst[k][t][1] = ch1[(t + shifts[k]) mod length]
+ * for t in [0, length): channel 0 stays, channel 1 is read shifts[k] samples
+ * later, circularly over the stream. shifts: host array of n_shifts values of
+ * any sign and size (taken modulo length). The copies are plain fp32 moves.
+ * dst: device, 2 * length * n_shifts floats, 8-byte aligned, not overlapping
+ * the source. length 0 writes nothing. GWD_ERR_ARG for NULL pointers, n_shifts
+ * < 1, elem_stride < 1, length < 0 or misaligned pointers. Asynchronous on
+ * hip_stream. */
+gwd_status gwd_time_slide(const gwd_stream* src, const int64_t* shifts, int32_t n_shifts, float* dst,
+                          void* hip_stream);
+
+/* False-alarm counts of a background trigger list (host memory, no device
+ * work): counts[i] = number of records with logit >= thresholds[i] (compared in
+ * double), far_per_s[i] = counts[i] / livetime_s. The clustering rule of
+ * gwd_triggers does not involve the threshold, so the records found at the
+ * lowest threshold give the whole curve above it; thresholds below that one
+ * are undercounted. GWD_ERR_ARG for NULL pointers (n > 0 needs trig), n < 0,
+ * n_thr < 1 or livetime_s <= 0. */
+gwd_status gwd_far_curve(const gwd_trigger* trig, int64_t n, const double* thresholds, int32_t n_thr,
+                         double livetime_s, int64_t* counts, double* far_per_s);
+
 /* ---- training (one member; "AI ensemble construction") ---------------------
  * windows: device [B][W][2] float32 (interleaved channels). Element type T of
  * logits, grad_logit, grad_params and grad_input is float, or double for a

@@ -78,6 +78,8 @@ def _load(path: str = LIB_PATH):
         "gwd_forward": (I32, [P, ctypes.POINTER(Stream), I32, I32, I32, I32, P, I64, P]),
         "gwd_forward_out_floats": (I64, [P, ctypes.POINTER(Stream), I32, I32, I32, I32]),
         "gwd_triggers": (I32, [P, P, I32, D, I32, ctypes.POINTER(Trigger), I64, ctypes.POINTER(I64), P]),
+        "gwd_time_slide": (I32, [ctypes.POINTER(Stream), P, I32, P, P]),
+        "gwd_far_curve": (I32, [ctypes.POINTER(Trigger), I64, P, I32, D, P, P]),
         "gwd_saved_bytes": (I64, [P, I32, I32]),
         "gwd_forward_train": (I32, [P, I32, P, I32, I32, P, P, P]),
         "gwd_backward": (I32, [P, I32, P, I32, I32, P, P, P, P, P]),
@@ -377,3 +379,34 @@ def triggers(e, offsets: Sequence[int], threshold_prob: float = 0.9, cluster_win
     check(lib.gwd_triggers(_ptr(e), offs.ctypes.data, n_streams, threshold_prob, cluster_window, buf, capacity,
                            ctypes.byref(nf), _stream_handle(stream)))
     return [(buf[i].stream, buf[i].sample, buf[i].logit, buf[i].prob) for i in range(min(nf.value, capacity))]
+
+
+def time_slide(src, shifts: Sequence[int], out=None, stream=None):
+    """gwd_time_slide: slid copies of one device stream ([L, 2] tensor or (ch0, ch1) pair) as a
+    [len(shifts), L, 2] float32 device tensor; channel 1 of copy k is read shifts[k] samples later,
+    circularly."""
+    import torch
+    arr, lengths = make_streams([src])
+    L = lengths[0]
+    sh = np.ascontiguousarray(np.asarray(shifts, dtype=np.int64))
+    if out is None:
+        dev = src[0].device if isinstance(src, (tuple, list)) else src.device
+        out = torch.empty((sh.size, L, 2), dtype=torch.float32, device=dev)
+    assert out.dtype == torch.float32 and out.is_contiguous() and tuple(out.shape) == (sh.size, L, 2)
+    check(lib.gwd_time_slide(arr, sh.ctypes.data, int(sh.size), _ptr(out), _stream_handle(stream)))
+    return out
+
+
+def far_curve(records: Sequence[Tuple[int, int, float, float]], logit_thresholds: Sequence[float],
+              livetime_s: float) -> Tuple[np.ndarray, np.ndarray]:
+    """gwd_far_curve on (stream, sample, logit, prob) trigger records: (counts, false alarms per second)."""
+    n = len(records)
+    buf = (Trigger * max(n, 1))()
+    for i, (st, a, z, pr) in enumerate(records):
+        buf[i].stream, buf[i].sample, buf[i].logit, buf[i].prob = int(st), int(a), float(z), float(pr)
+    thr = np.ascontiguousarray(np.asarray(logit_thresholds, dtype=np.float64))
+    counts = np.zeros(thr.size, dtype=np.int64)
+    far = np.zeros(thr.size, dtype=np.float64)
+    check(lib.gwd_far_curve(buf, n, thr.ctypes.data, int(thr.size), float(livetime_s), counts.ctypes.data,
+                            far.ctypes.data))
+    return counts, far
