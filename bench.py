@@ -99,12 +99,16 @@ def time_steps(fn, steps: int, warmup: int, label: str = "", warm_fn=None):
 
 def layer_kernel_timing(model, prec: str, reps: int = 10):
     """Average duration of the dominant kernel in the forward's own launch configuration, timed by
-    the library with HIP events on the stream it launches on. With fused BF16 triples that is the
-    three-layer kernel, timed at the three triples of the middle stack (dilations 1-4, 8-32,
-    64-256); otherwise the single-layer kernel at a middle layer."""
-    launches = [model.time_layer(0, l, reps) for l in (10, 13, 16)]
-    if any(nl != 3 for _, _, nl in launches):
-        launches = [model.time_layer(0, 15, reps)]
+    the library with HIP events on the stream it launches on. With fused launches that is the
+    three-layer kernel, timed at the triples of the middle stack (dilations 1-4, 8-32, and 64-256
+    where that one is a triple); a launch at layer 16 that also takes the stack's last layer (a
+    quad, dilations 64-512) is reported beside it. Otherwise the single-layer kernel at a middle
+    layer."""
+    timed = [model.time_layer(0, l, reps) for l in (10, 13, 16)]
+    launches = [t for t in timed if t[2] == 3]
+    quads = [t for t in timed if t[2] == 4]
+    if not launches:
+        launches, quads = [model.time_layer(0, 15, reps)], []
     ms = sum(x[0] for x in launches) / len(launches)
     nb, nl = launches[0][1], launches[0][2]
     flop = nb * W * FLOP_PER_LAYER_T * nl
@@ -118,6 +122,11 @@ def layer_kernel_timing(model, prec: str, reps: int = 10):
            "windows_per_launch": nb, "layers_per_launch": nl, "flop_per_launch": flop}
     if traffic:
         out["hbm_GBps"] = round(traffic / (ms * 1e-3) / 1e9, 1)
+    if quads:
+        qms, qnb = quads[0][0], quads[0][1]
+        qflop = qnb * W * FLOP_PER_LAYER_T * 4
+        out["quad"] = {"ms_per_launch": round(qms, 4), "layers_per_launch": 4, "flop_per_launch": qflop,
+                       "achieved": round(qflop / (qms * 1e-3) / 1e12, 2)}
     return out
 
 

@@ -294,9 +294,12 @@ void gwd_plan_free(gwd_plan* plan);
  *   tile_rows, waves: tiling of the single-layer BF16/FP8 kernel, (64, 4),
  *     (64, 8) or (128, 4); (0, 0) = default per precision (BF16 (64, 4), FP8
  *     (64, 8)); FP32 models have one tiling and accept only (0, 0);
- *   layers_per_launch: BF16 and FP8, 3 = layers with dilations d, 2d, 4d of
- *     a stack run as one fused launch (the default), 1 = one launch per
- *     layer; 0 = default; FP32 models accept 0 or 1;
+ *   layers_per_launch: BF16 and FP8, 3 = fused launches (the default): the
+ *     layers with dilations d, 2d, 4d of a stack run as one launch, and in
+ *     BF16 the triple at stack position 6 also takes the stack's last layer
+ *     (four layers) when the sub-sequences at its dilation fit one 64-row
+ *     chunk (window <= 64 x that dilation, e.g. 4096 at 64); 1 = one launch
+ *     per layer; 0 = default; FP32 models accept 0 or 1;
  *   batch_windows: windows per batch of layer launches (1..8192, default 512;
  *     gwd_forward lowers it for a call whose activations would not fit in 60 %
  *     of the free device memory, e.g. windows of 2^20 samples).
@@ -337,12 +340,12 @@ gwd_status gwd_debug_export_weights(const gwd_model* model, int32_t member, floa
 
 /* Measurement support: issues the launch that gwd_forward makes at middle gated
  * layer `layer` of member `member` (the single-layer kernel, or the fused
- * three-layer kernel when a BF16/FP8 triple starts there; every layer it covers
- * must be a middle one) reps + 1 times, with the forward's grid over its batch
+ * kernel when a fused launch starts there; every layer it covers must be a
+ * middle one) reps + 1 times, with the forward's grid over its batch
  * of windows, on the activations the last gwd_forward left in the model's
  * workspace, and times the last `reps` launches between two HIP events
  * recorded on hip_stream. Writes the average milliseconds per launch, the
- * windows per launch and the layers per launch (1 or 3). Requires a prior
+ * windows per launch and the layers per launch (1, 3 or 4). Requires a prior
  * gwd_forward on the model; synchronises hip_stream. The workspace contents
  * are overwritten. */
 gwd_status gwd_debug_time_layer(gwd_model* model, int32_t member, int32_t layer, int32_t reps,

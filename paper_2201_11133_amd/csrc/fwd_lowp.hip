@@ -433,19 +433,29 @@ static int lp_tiling(const gwd_model* m, bool fp8) {
 constexpr int FU_ROWS = 64;                                // sub-rows per chunk (2 row blocks x 4 waves)
 constexpr int FU_HIST = 4;                                 // history rows in front of each input buffer
 constexpr int FU_XROW = 2 * kC + 16;                       // bf16 row + 16-byte pad
-constexpr int FU_XBUF = (FU_ROWS + FU_HIST) * FU_XROW;     // one input buffer with its history
-constexpr int FU_LDS = 3 * FU_XBUF + FU_ROWS * FU_XROW;    // three input buffers + the gate buffer
+constexpr int FU_XBUF = (FU_ROWS + FU_HIST) * FU_XROW;     // one input buffer with its history (FP8 form)
+// BF16 form: layer j reads buffer j % 3 and writes buffer (j + 1) % 3. Each buffer keeps in front of
+// its rows as many history rows as the largest dilation read from it: 8 for buffer 0 (dilation 1,
+// and 8 for the fourth layer of a quad), 2 for buffer 1, 4 for buffer 2. Then the gate buffer and
+// the biases of up to four layers.
+constexpr int FU_B0 = 8 * FU_XROW;
+constexpr int FU_B1 = FU_B0 + (FU_ROWS + 2) * FU_XROW;
+constexpr int FU_B2 = FU_B1 + (FU_ROWS + 4) * FU_XROW;
+constexpr int FU_GB = FU_B2 + FU_ROWS * FU_XROW;
+constexpr int FU_BI = FU_GB + FU_ROWS * FU_XROW;
+constexpr int FU_LDS = FU_BI + 4 * 4 * kC * 4;             // 81,632 bytes: two blocks per CU
+static_assert(2 * FU_LDS <= 160 * 1024, "two fused blocks per CU");
 
 struct FusedArgs {
     const uint16_t* x_in;  // residual stream, bf16 [rows][128]
     uint16_t* x_out;
     float* skip;
-    const uint8_t* wc[3];
-    const float* bc[3];
-    const uint8_t* wrs[3];
-    const float* brs[3];
-    const float* sc[3];    // FP8: conv column scales [256]
-    const float* srs[3];   // FP8: res|skip column scales [256]
+    const uint8_t* wc[4];  // layers of the launch (three, or four for a quad)
+    const float* bc[4];
+    const uint8_t* wrs[4];
+    const float* brs[4];
+    const float* sc[4];    // FP8: conv column scales [256]
+    const float* srs[4];   // FP8: res|skip column scales [256]
     int d0, T;             // dilation of the first layer; window length
     int n_seg, seg_chunks; // segments per sub-sequence, chunks per segment
     const StreamDesc* streams;
@@ -456,10 +466,10 @@ struct FusedArgs {
     const float* b_in;
 };
 
-__device__ inline uint8_t* fu_buf(uint8_t* lds, int j) { return lds + j * FU_XBUF + FU_HIST * FU_XROW; }
+__device__ inline uint8_t* fu_buf(uint8_t* lds, int j) { return lds + (j == 0 ? FU_B0 : j == 1 ? FU_B1 : FU_B2); }
 
 // Sixteen fp32 values of one 32-channel block in the transposed accumulator layout (see
-// fused3_bf16_kernel): element 4 g + e is channel 8 g + e of b, where b already points at the
+// fused_bf16_kernel): element 4 g + e is channel 8 g + e of b, where b already points at the
 // block's first channel + 4 h.
 __device__ inline floatx16 load_col16(const float* b) {
     floatx16 v;
@@ -504,8 +514,6 @@ __device__ inline floatx16 lds_col16(const float* b) {
     return v;
 }
 
-constexpr int FU_BIAS = 3 * 4 * kC * 4;  // biases of the three layers in LDS: [layer][conv 256 | res 128 | skip 128]
-
 // The input rows of one chunk as this thread stages them: four 16-byte pieces of bf16 x, or, for
 // the first triple, the two stream samples of each piece's row (the input projection is applied
 // when the rows are staged).
@@ -515,12 +523,17 @@ struct ChunkRows {
     float u[FROM_STREAM ? 4 : 1][2];
 };
 
-template <bool FROM_STREAM, bool SKIP_INIT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void fused3_bf16_kernel(FusedArgs p) {
+// NL consecutive layers of one stack in one launch (NL = 3, or 4 when the sub-sequences are one chunk
+// long, so that the fourth layer's history rows are the causal zeros). LAST: the fourth layer is the
+// network's last, which writes the skip sum only (its residual projection is not part of the model).
+template <bool FROM_STREAM, bool SKIP_INIT, int NL, bool LAST>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void fused_bf16_kernel(FusedArgs p) {
+    static_assert(NL == 3 || NL == 4, "three or four layers");
+    static_assert(!LAST || NL == 4, "the network's last layer ends a quad");
     using T = LP<false, 2, 4>;  // bf16 fragments, 4 waves x 2 row blocks
-    __shared__ __attribute__((aligned(16))) uint8_t lds[FU_LDS + FU_BIAS];
-    uint8_t* G = lds + 3 * FU_XBUF;
-    float* BI = (float*)(lds + FU_LDS);
+    __shared__ __attribute__((aligned(16))) uint8_t lds[FU_LDS];
+    uint8_t* G = lds + FU_GB;
+    float* BI = (float*)(lds + FU_BI);
     const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6, h = lane >> 5, r = lane & 31;
     const int seg = blockIdx.x % p.n_seg;
     const int cls = (blockIdx.x / p.n_seg) % p.d0;
@@ -539,14 +552,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
         start = (gw - sd.win_begin) * p.S;
     }
     // causal zero padding: the rows before the sub-sequence start are zero for every layer
-    for (int idx = tid; idx < 3 * FU_HIST * 16; idx += 256) {
-        const int j = idx / (FU_HIST * 16), rr = (idx >> 4) % FU_HIST, c = idx & 15;
-        *(uint4*)(fu_buf(lds, j) + (rr - FU_HIST) * FU_XROW + 16 * c) = make_uint4(0, 0, 0, 0);
+    for (int idx = tid; idx < (8 + 2 + 4) * 16; idx += 256) {
+        const int rr = idx >> 4, c = idx & 15;  // rows 0-7: buffer 0, 8-9: buffer 1, 10-13: buffer 2
+        uint8_t* row = rr < 8 ? fu_buf(lds, 0) - (8 - rr) * FU_XROW
+                     : rr < 10 ? fu_buf(lds, 1) - (10 - rr) * FU_XROW : fu_buf(lds, 2) - (14 - rr) * FU_XROW;
+        *(uint4*)(row + 16 * c) = make_uint4(0, 0, 0, 0);
     }
-    // the biases of the three layers, once per block
-    for (int idx = tid; idx < 3 * 4 * kC; idx += 256) {
+    // the biases of the layers, once per block: [layer][conv 256 | res 128 | skip 128]
+    for (int idx = tid; idx < NL * 4 * kC; idx += 256) {
         const int j = idx / (4 * kC), e = idx % (4 * kC);
-        BI[idx] = e < 2 * kC ? p.bc[j][e] : p.brs[j][e - 2 * kC];
+        float v;
+        if (e < 2 * kC) v = p.bc[j][e];
+        else if (LAST && j == NL - 1) v = e < 3 * kC ? 0.f : p.brs[j][e - 3 * kC];  // skip columns only
+        else v = p.brs[j][e - 2 * kC];
+        BI[idx] = v;
     }
     // Products are taken transposed: weight fragments are the A operand and row fragments the B
     // operand, so an accumulator holds rows along the lanes. Lane (h, r) holds row r of each
@@ -618,10 +637,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
         __syncthreads();
 
 #pragma unroll 1
-        for (int j = 0; j < 3; ++j) {
+        for (int j = 0; j < NL; ++j) {
             const int dil = 1 << j;  // dilation in sub-rows
-            uint8_t* Xin = fu_buf(lds, j);
-            uint8_t* Xo = fu_buf(lds, j < 2 ? j + 1 : 0);  // the last layer's output goes to buffer 0
+            uint8_t* Xin = fu_buf(lds, j % 3);
+            uint8_t* Xo = fu_buf(lds, (j + 1) % 3);
+            const bool resid = !LAST || j < NL - 1;  // the network's last layer has no residual output
             const float* bj = BI + j * 4 * kC;
             // biases are the first products' accumulator inputs
             const floatx16 bf = lds_col16(bj + cb), bg = lds_col16(bj + kC + cb);
@@ -667,16 +687,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
             }
             // the weight fragments of the second phase, residual and skip columns side by side; the
             // first PF2 pairs are in flight during the gate
+            // (the network's last layer packs its skip columns only, as column blocks 0-3; its residual
+            // products are then computed from those same fragments and not used)
             const uint8_t* Wr = p.wrs[j] + ((size_t)(q * T::NK2) * 64 + lane) * T::FRAG;
-            const uint8_t* Ws = p.wrs[j] + ((size_t)((4 + q) * T::NK2) * 64 + lane) * T::FRAG;
+            const uint8_t* Ws = p.wrs[j] + ((size_t)((resid ? 4 + q : q) * T::NK2) * 64 + lane) * T::FRAG;
             Frag<false> ringr[FU_PF2], rings[FU_PF2];
 #pragma unroll
             for (int k = 0; k < FU_PF2; ++k) {
                 ringr[k] = load_frag<false>(Wr + (size_t)k * 64 * T::FRAG);
                 rings[k] = load_frag<false>(Ws + (size_t)k * 64 * T::FRAG);
             }
-            const bool more = j < 2 || c + 1 < c1;
-            if (j == 2 && c + 1 < c1) fetch_rows(c + 1, nrows);  // next chunk's rows, in flight during the gate
+            const bool more = j < NL - 1 || c + 1 < c1;
+            if (j == NL - 1 && c + 1 < c1) fetch_rows(c + 1, nrows);  // next chunk's rows, in flight during the gate
             if (j == 0) {  // this chunk's skip rows, first needed at the end of this layer
 #pragma unroll
                 for (int rb = 0; rb < 2; ++rb) {
@@ -687,7 +709,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
             }
             __syncthreads();  // every wave is done with this layer's input rows
             // this input's last dil rows become the history of the next chunk
-            if (tid < 16 * dil) {
+            if (c + 1 < c1 && tid < 16 * dil) {
                 const int rr = tid >> 4, cc = tid & 15;
                 *(uint4*)(Xin + (rr - dil) * FU_XROW + 16 * cc) = *(const uint4*)(Xin + (FU_ROWS - dil + rr) * FU_XROW + 16 * cc);
             }
@@ -714,7 +736,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
             __syncthreads();
             // ---- phase 2 over G (K = 128): each g fragment feeds the residual and the skip columns
             const uint8_t* Ag = G + r * FU_XROW + 16 * h;
-            const int jn = j < 2 ? j + 1 : 0;  // the next layer (the first of the next chunk after the last)
+            const int jn = j < NL - 1 ? j + 1 : 0;  // the next layer (the first of the next chunk after the last)
             const uint8_t* Nf = p.wc[jn] + ((size_t)(q * T::NK1) * 64 + lane) * T::FRAG;
             const uint8_t* Ng = p.wc[jn] + ((size_t)((4 + q) * T::NK1) * 64 + lane) * T::FRAG;
             floatx16 ar[2], as[2];
@@ -752,7 +774,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
             }
             // x_next = x + (g Brs_res + b_res), rounded to bf16; skip += g Brs_skip + b_skip
 #pragma unroll
-            for (int rb = 0; rb < 2; ++rb) {
+            for (int rb = 0; rb < 2 && resid; ++rb) {
                 uint8_t* xr = Xo + (32 * rb + r) * FU_XROW + 2 * cb;
 #pragma unroll
                 for (int g = 0; g < 4; ++g) {
@@ -766,14 +788,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                 for (int i = 0; i < 16; ++i) sk[rb][i] = (SKIP_INIT && j == 0) ? as[rb][i] : sk[rb][i] + as[rb][i];
             __syncthreads();  // the next layer's input (or the chunk's output) is complete
         }
-        // ---- chunk output: x rows from buffer 0 (16-byte stores), skip rows from registers
+        // ---- chunk output: x rows from the last layer's output buffer (16-byte stores), skip rows
+        // from registers
         if (store) {
+            const uint8_t* XL = fu_buf(lds, NL % 3);
 #pragma unroll
-            for (int it = 0; it < 4; ++it) {
+            for (int it = 0; it < 4 && !LAST; ++it) {
                 const int idx = tid + 256 * it, rr = idx >> 4, c8 = 8 * (idx & 15);
                 const int sr = sb + rr;
                 if (sr < n_sub)
-                    *(uint4*)&p.x_out[(wrow0 + cls + p.d0 * sr) * kC + c8] = *(const uint4*)(X0 + rr * FU_XROW + 2 * c8);
+                    *(uint4*)&p.x_out[(wrow0 + cls + p.d0 * sr) * kC + c8] = *(const uint4*)(XL + rr * FU_XROW + 2 * c8);
             }
 #pragma unroll
             for (int rb = 0; rb < 2; ++rb) {
@@ -781,7 +805,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                 if (sr < n_sub) store_col16(p.skip + (wrow0 + cls + (int64_t)p.d0 * sr) * kC + cb, sk[rb]);
             }
         }
-        __syncthreads();  // buffer 0 is read above before the next chunk stages into it
+        __syncthreads();  // the output buffer is read above before the next chunk stages into buffer 0
     }
 }
 
@@ -1055,18 +1079,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
 
 // Does layer l start a fused triple? Triples (i, i+1, i+2) with i % 3 == 0 inside a stack, never
 // holding the network's last layer (that one writes no residual).
-static bool fused_start(const gwd_model* m, int l) {
-    if ((m->prec != GWD_BF16 && m->prec != GWD_FP8_E4M3) || m->lp_fuse != 3) return false;
+// Layers covered by the fused launch that starts at layer l for windows of length T: 0 (l is not a
+// start), 3, or 4. Triples start at stack positions 0, 3, 6; the triple at 6 also takes the stack's
+// last layer (a quad, BF16) when the sub-sequences at its dilation are one chunk long. A triple never
+// includes the network's last layer.
+static int fused_layers(const gwd_model* m, int l, int T) {
+    if ((m->prec != GWD_BF16 && m->prec != GWD_FP8_E4M3) || m->lp_fuse != 3) return 0;
     const int lps = m->arch.layers_per_stack, L = m->arch.n_stacks * lps, i = l % lps;
-    return i % 3 == 0 && i + 2 < lps && l + 2 < L - 1;
+    if (i % 3 != 0 || i + 2 >= lps) return 0;
+    const int d0 = 1 << i;
+    if (m->prec == GWD_BF16 && i + 4 == lps && T > 0 && (T + d0 - 1) / d0 <= FU_ROWS) return 4;
+    return l + 2 < L - 1 ? 3 : 0;
 }
 
-// One fused launch of layers l, l+1, l+2 over nb windows of length T.
+// One fused launch of layers l .. l + nl - 1 over nb windows of length T.
 template <bool FP8>
-static hipError_t launch_fused3(gwd_model* m, int member, int l, const uint16_t* x_in, uint16_t* x_out, float* skip,
-                                int nb, int T, const FwdBatch* fb, hipStream_t st) {
+static hipError_t launch_fused(gwd_model* m, int member, int l, int nl, const uint16_t* x_in, uint16_t* x_out,
+                               float* skip, int nb, int T, const FwdBatch* fb, hipStream_t st) {
+    const int L = m->arch.n_stacks * m->arch.layers_per_stack;
     FusedArgs a{};
-    for (int j = 0; j < 3; ++j) {
+    for (int j = 0; j < nl; ++j) {
         const LayerArgsLP la = lp_args<FP8>(m, member, l + j);
         a.wc[j] = la.wc;
         a.bc[j] = la.bc;
@@ -1083,6 +1115,7 @@ static hipError_t launch_fused3(gwd_model* m, int member, int l, const uint16_t*
     a.T = T;
     const int rows = FP8 ? FE_ROWS : FU_ROWS;                           // sub-rows per chunk
     const int n_ch = ((T + a.d0 - 1) / a.d0 + rows - 1) / rows;       // chunks of the longest sub-sequence
+    if (nl == 4 && n_ch != 1) return hipErrorInvalidValue;              // a quad needs one-chunk sub-sequences
     // enough blocks to fill the chip (>= 2048); a segment after the first costs one warm-up chunk
     const int64_t per = (int64_t)nb * a.d0;
     const int want = (int)std::min<int64_t>(n_ch, std::max<int64_t>(1, (2048 + per - 1) / per));
@@ -1097,11 +1130,16 @@ static hipError_t launch_fused3(gwd_model* m, int member, int l, const uint16_t*
     }
     const dim3 grid((unsigned)(per * a.n_seg));
     if (FP8) {
+        if (nl != 3) return hipErrorInvalidValue;
         if (first) hipLaunchKernelGGL((fused3_fp8_kernel<true, true>), grid, dim3(256), 0, st, a);
         else hipLaunchKernelGGL((fused3_fp8_kernel<false, false>), grid, dim3(256), 0, st, a);
+    } else if (nl == 3) {
+        if (first) hipLaunchKernelGGL((fused_bf16_kernel<true, true, 3, false>), grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((fused_bf16_kernel<false, false, 3, false>), grid, dim3(256), 0, st, a);
     } else {
-        if (first) hipLaunchKernelGGL((fused3_bf16_kernel<true, true>), grid, dim3(256), 0, st, a);
-        else hipLaunchKernelGGL((fused3_bf16_kernel<false, false>), grid, dim3(256), 0, st, a);
+        if (first) return hipErrorInvalidValue;                          // stacks of at least 10 layers
+        if (l + 3 == L - 1) hipLaunchKernelGGL((fused_bf16_kernel<false, false, 4, true>), grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((fused_bf16_kernel<false, false, 4, false>), grid, dim3(256), 0, st, a);
     }
     return hipGetLastError();
 }
@@ -1114,11 +1152,11 @@ static hipError_t layers_lp(gwd_model* m, const FwdBatch& fb, float* x_a, float*
     uint16_t* xin = (uint16_t*)x_a;
     uint16_t* xout = (uint16_t*)x_b;
     for (int l = 0; l < L; ++l) {
-        if (fused_start(m, l)) {
-            hipError_t e = launch_fused3<FP8>(m, fb.member, l, xin, xout, skip, fb.nb, fb.T, &fb, st);
+        if (const int nl = fused_layers(m, l, fb.T)) {
+            hipError_t e = launch_fused<FP8>(m, fb.member, l, nl, xin, xout, skip, fb.nb, fb.T, &fb, st);
             if (e != hipSuccess) return e;
             uint16_t* t = xin; xin = xout; xout = t;
-            l += 2;
+            l += nl - 1;
             continue;
         }
         LayerArgsLP a = lp_args<FP8>(m, fb.member, l);
@@ -1183,8 +1221,8 @@ static hipError_t debug_lp(gwd_model* m, int member, int l, const float* x_in, i
 template <bool FP8>
 static hipError_t production_lp(gwd_model* m, int member, int l, void* x_in, void* x_out, float* skip, int nb, int T,
                                 hipStream_t st) {
-    if (fused_start(m, l) && l > 0)
-        return launch_fused3<FP8>(m, member, l, (const uint16_t*)x_in, (uint16_t*)x_out, skip, nb, T, nullptr, st);
+    if (const int nl = l > 0 ? fused_layers(m, l, T) : 0)
+        return launch_fused<FP8>(m, member, l, nl, (const uint16_t*)x_in, (uint16_t*)x_out, skip, nb, T, nullptr, st);
     LayerArgsLP a = lp_args<FP8>(m, member, l);
     a.x_in = (const uint16_t*)x_in;
     a.x_out = (uint16_t*)x_out;
@@ -1193,7 +1231,11 @@ static hipError_t production_lp(gwd_model* m, int member, int l, void* x_in, voi
     a.T = T;
     return launch_lp<FP8, false, false, false>(a, nb, lp_tiling(m, FP8), st);
 }
-int layers_per_launch_lp(const gwd_model* m, int l) { return fused_start(m, l) ? 3 : 1; }
+// Layers of the launch that starts at layer l, for the window length of the last forward.
+int layers_per_launch_lp(const gwd_model* m, int l) {
+    const int nl = fused_layers(m, l, m->last_T);
+    return nl ? nl : 1;
+}
 hipError_t layer_production_bf16(gwd_model* m, int member, int l, void* xi, void* xo, float* sk, int nb, int T,
                                  hipStream_t st) {
     return production_lp<false>(m, member, l, xi, xo, sk, nb, T, st);
