@@ -433,7 +433,6 @@ static int lp_tiling(const gwd_model* m, bool fp8) {
 constexpr int FU_ROWS = 64;                                // sub-rows per chunk (2 row blocks x 4 waves)
 constexpr int FU_HIST = 4;                                 // history rows in front of each input buffer
 constexpr int FU_XROW = 2 * kC + 16;                       // bf16 row + 16-byte pad
-constexpr int FU_XBUF = (FU_ROWS + FU_HIST) * FU_XROW;     // one input buffer with its history (FP8 form)
 // BF16 form: layer j reads buffer j % 3 and writes buffer (j + 1) % 3. Each buffer keeps in front of
 // its rows as many history rows as the largest dilation read from it: 8 for buffer 0 (dilation 1,
 // and 8 for the fourth layer of a quad), 2 for buffer 1, 4 for buffer 2. Then the gate buffer and
@@ -1116,9 +1115,10 @@ static hipError_t launch_fused(gwd_model* m, int member, int l, int nl, const ui
     const int rows = FP8 ? FE_ROWS : FU_ROWS;                           // sub-rows per chunk
     const int n_ch = ((T + a.d0 - 1) / a.d0 + rows - 1) / rows;       // chunks of the longest sub-sequence
     if (nl == 4 && n_ch != 1) return hipErrorInvalidValue;              // a quad needs one-chunk sub-sequences
-    // enough blocks to fill the chip (>= 2048); a segment after the first costs one warm-up chunk
+    // enough blocks for every resident slot (two per CU on 256 CUs); a segment after the first costs
+    // one warm-up chunk, so no more segments than that (more, shorter blocks measured slower)
     const int64_t per = (int64_t)nb * a.d0;
-    const int want = (int)std::min<int64_t>(n_ch, std::max<int64_t>(1, (2048 + per - 1) / per));
+    const int want = (int)std::min<int64_t>(n_ch, std::max<int64_t>(1, (512 + per - 1) / per));
     a.seg_chunks = (n_ch + want - 1) / want;
     a.n_seg = (n_ch + a.seg_chunks - 1) / a.seg_chunks;
     const bool first = l == 0;
