@@ -249,7 +249,7 @@ def background_workload(gwd, blobs, x, prec: str, seconds: float = 900.0, n_slid
 
 def train_workload(gwd, steps: int = 2, B: int = 256):
     """Training of one full-size member: BF16 forward with per-stack checkpoints, BCE on logits,
-    hand-written backward (bf16-operand row GEMMs, fp32 weight-gradient GEMMs), Adam on fp32 master
+    hand-written backward (bf16-operand row and weight-gradient GEMMs, fp32 accumulation), Adam on fp32 master
     weights; batches of 256 windows of 2 x 4096,
     half of them chirped (SNR 8-20), labels 1 within 0.1 s of the coalescence time."""
     import torch
@@ -272,8 +272,8 @@ def train_workload(gwd, steps: int = 2, B: int = 256):
     m.close()
     return {"train_windows_per_s": round(B / dt, 1), "s_per_step": round(dt, 3), "batch": B,
             "loss": round(float(loss.item()), 5), "grad_norm": round(float(norm.item()), 5),
-            "precision": "bf16 forward and recompute, bf16-operand row GEMMs in the backward, fp32 "
-                         "weight-gradient GEMMs, fp32 master weights and Adam"}
+            "precision": "bf16 forward and recompute, bf16-operand row and weight-gradient GEMMs in the "
+                         "backward (fp32 accumulation), fp32 master weights and Adam"}
 
 
 def cpu_baseline(n_members: int, n_windows_sample: int = 3):

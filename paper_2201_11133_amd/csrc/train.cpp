@@ -109,7 +109,8 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
     float *G = fptr(b, f_g), *DG = fptr(b, f_dg), *DX = fptr(b, f_dx), *DS = fptr(b, f_ds), *SKS = fptr(b, f_sks);
     float *R = fptr(b, f_r), *H = fptr(b, f_h), *DH = fptr(b, f_dh), *AH = fptr(b, f_ah), *DPRE = fptr(b, f_dpre);
     float* PART = fptr(b, f_part);
-    // BF16/FP8 members: the row GEMMs of the backward take bf16 operands (fp32 accumulation)
+    // BF16/FP8 members: the row and weight-gradient GEMMs of the backward take bf16 operands (fp32
+    // accumulation)
     uint16_t* BT = (m->prec == GWD_BF16 || m->prec == GWD_FP8_E4M3) ? (uint16_t*)fptr(b, f_bt) : nullptr;
     const int64_t PART_CAP = total - f_part;  // floats
     hipError_t e;
@@ -132,7 +133,7 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
     {
         WgradArgs a{};
         a.A[0] = APart{DH, kC, 0, kC}; a.nparts = 1; a.Ktot = kC;
-        a.B = R; a.ldb = kC; a.N = kC; a.M = M; a.T = T; a.rows_per_chunk = RPC; a.part = PART; a.part_capacity = PART_CAP;
+        a.B = R; a.ldb = kC; a.N = kC; a.M = M; a.T = T; a.rows_per_chunk = RPC; a.part = PART; a.part_capacity = PART_CAP; a.bf16 = BT != nullptr;
         HIPCHK(gemm_wgrad(a, grad + v.h1w, 0, st), "d h1.W");
     }
     HIPCHK(colsum(DH, kC, M, kC, nullptr, 0, 0, PART, PART_CAP, grad + v.h1b, 1, st), "d h1.b");
@@ -182,7 +183,7 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
             {
                 WgradArgs a{};
                 a.A[0] = APart{DS, kC, 0, kC}; a.nparts = 1; a.Ktot = kC;
-                a.B = G; a.ldb = kC; a.N = kC; a.M = M; a.T = T; a.rows_per_chunk = RPC; a.part = PART; a.part_capacity = PART_CAP;
+                a.B = G; a.ldb = kC; a.N = kC; a.M = M; a.T = T; a.rows_per_chunk = RPC; a.part = PART; a.part_capacity = PART_CAP; a.bf16 = BT != nullptr;
                 HIPCHK(gemm_wgrad(a, grad + v.skip_w[l], 0, st), "d skip.W");
                 HIPCHK(colsum(DS, kC, M, kC, nullptr, 0, 0, PART, PART_CAP, grad + v.skip_b[l], 1, st), "d skip.b");
                 if (!last) {
@@ -195,7 +196,7 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
             {
                 WgradArgs a{};
                 a.A[0] = APart{DPRE, 2 * kC, 0, 2 * kC}; a.nparts = 1; a.Ktot = 2 * kC;
-                a.B = xs_i; a.ldb = kC; a.N = kC; a.M = M; a.T = T; a.rows_per_chunk = RPC; a.part = PART; a.part_capacity = PART_CAP;
+                a.B = xs_i; a.ldb = kC; a.N = kC; a.M = M; a.T = T; a.rows_per_chunk = RPC; a.part = PART; a.part_capacity = PART_CAP; a.bf16 = BT != nullptr;
                 a.bshift = 0;
                 HIPCHK(gemm_wgrad(a, grad + v.dil_w[l] + 1, 2, st), "d dil.W tap1");
                 a.bshift = -d;

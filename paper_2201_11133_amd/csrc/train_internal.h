@@ -47,6 +47,7 @@ struct WgradArgs {
     int64_t rows_per_chunk;
     float* part;  // [nchunks][Ktot][N]
     int64_t part_capacity;  // floats available at part (partials, then the reduction's scratch)
+    bool bf16 = false;      // operands rounded to bf16 (fp32 accumulation): BF16/FP8 members
 };
 
 hipError_t gemm_rows(const GemmRowsArgs& a, hipStream_t st);

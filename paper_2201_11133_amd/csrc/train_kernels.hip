@@ -167,6 +167,16 @@ __global__ __launch_bounds__(256) void gemm_rows_bf16_kernel(GemmRowsArgs a, int
     }
 }
 
+// Block -> (output tile, row chunk) of the weight-gradient GEMMs. Blocks are dispatched round-robin
+// over the 8 XCDs, each with its own L2; the tiles of one chunk read the same rows, so they are put
+// on one XCD as consecutive dispatches there and their re-reads hit that L2. The grid is padded to
+// a multiple of 8 chunks; blocks of chunks past the end return.
+__device__ inline void wgrad_block(int ntiles, int& tile, int& chunk) {
+    const int xcd = blockIdx.x & 7, idx = blockIdx.x >> 3;
+    tile = idx % ntiles;
+    chunk = (idx / ntiles) * 8 + xcd;
+}
+
 // part[chunk][K][N] = sum over the chunk's rows of A(row, k) B(row, n); A from row-shifted parts
 // stacked along k, B plain. One block: one 64 x 64 output tile of one row chunk.
 __global__ __launch_bounds__(256) void gemm_wgrad_kernel(WgradArgs a) {
@@ -175,8 +185,9 @@ __global__ __launch_bounds__(256) void gemm_wgrad_kernel(WgradArgs a) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
     const int ntn = a.N / GT, ntk = a.Ktot / GT;
-    const int tile = blockIdx.x % (ntn * ntk);
-    const int chunk = blockIdx.x / (ntn * ntk);
+    int tile, chunk;
+    wgrad_block(ntn * ntk, tile, chunk);
+    if ((int64_t)chunk * a.rows_per_chunk >= a.M) return;  // padding of the grid (uniform per block)
     const int k0 = (tile / ntn) * GT, n0 = (tile % ntn) * GT;
     // which A part holds columns [k0, k0 + 64)
     int p = 0, kb = 0;
@@ -226,6 +237,92 @@ __global__ __launch_bounds__(256) void gemm_wgrad_kernel(WgradArgs a) {
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         const int k = k0 + 32 * wr + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+        out[(int64_t)k * a.N + n] = acc[i];
+    }
+}
+
+// The same partial sums with bf16 operands (rounded to nearest even) and fp32 accumulation, for
+// BF16/FP8 members: v_mfma_f32_32x32x16_bf16 with the data rows as the contraction. Each step
+// stages 64 rows of A and B, converts them to bf16 and stores them transposed in LDS ([column][row],
+// 144-byte rows), so that a lane reads the 8 consecutive rows of its fragment as one 16-byte word;
+// the next step's rows are loaded during this step's products. Same tiles, chunks and partials as
+// gemm_wgrad_kernel.
+constexpr int WB_ROWS = 64;                // rows per step
+constexpr int WB_LD = WB_ROWS * 2 + 16;    // bytes per transposed LDS row
+__global__ __launch_bounds__(256) void gemm_wgrad_bf16_kernel(WgradArgs a) {
+    __shared__ __attribute__((aligned(16))) uint8_t At[GT * WB_LD];   // [k][row] bf16
+    __shared__ __attribute__((aligned(16))) uint8_t Bt[GT * WB_LD];   // [n][row] bf16
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1, h = lane >> 5, r = lane & 31;
+    const int ntn = a.N / GT, ntk = a.Ktot / GT;
+    int tile, chunk;
+    wgrad_block(ntn * ntk, tile, chunk);
+    if ((int64_t)chunk * a.rows_per_chunk >= a.M) return;  // padding of the grid (uniform per block)
+    const int k0 = (tile / ntn) * GT, n0 = (tile % ntn) * GT;
+    int p = 0, kb = 0;
+    while (kb + a.A[p].K <= k0) {
+        kb += a.A[p].K;
+        ++p;
+    }
+    const APart ap = a.A[p];
+    const APart bpart{a.B, a.ldb, a.bshift, a.N};
+    const int64_t r0 = (int64_t)chunk * a.rows_per_chunk;
+    const int64_t r1 = min(r0 + a.rows_per_chunk, a.M);
+    // staging: thread (row pair rp = tid / 8, column group c8 = 8 (tid % 8)) loads 8 consecutive
+    // columns of rows 2 rp and 2 rp + 1, of A and of B
+    const int rp = tid >> 3, c8 = 8 * (tid & 7);
+    float4 ra[2][2], rbv[2][2];
+    auto load = [&](int64_t rb) {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int64_t row = rb + 2 * rp + e;
+            ra[e][0] = ra[e][1] = rbv[e][0] = rbv[e][1] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (row < r1) {
+                const int64_t sa = part_row(ap, row, a.T), sb = part_row(bpart, row, a.T);
+                if (sa >= 0) {
+                    const float* pa = ap.ptr + sa * ap.ld + (k0 - kb) + c8;
+                    ra[e][0] = *(const float4*)pa;
+                    ra[e][1] = *(const float4*)(pa + 4);
+                }
+                if (sb >= 0) {
+                    const float* pb = a.B + sb * a.ldb + n0 + c8;
+                    rbv[e][0] = *(const float4*)pb;
+                    rbv[e][1] = *(const float4*)(pb + 4);
+                }
+            }
+        }
+    };
+    // column c of rows (2 rp, 2 rp + 1) as one bf16 pair at [c][2 rp]
+    auto put = [&](uint8_t* dst, const float4 (&v)[2][2]) {
+        const float c0[8] = {v[0][0].x, v[0][0].y, v[0][0].z, v[0][0].w, v[0][1].x, v[0][1].y, v[0][1].z, v[0][1].w};
+        const float c1[8] = {v[1][0].x, v[1][0].y, v[1][0].z, v[1][0].w, v[1][1].x, v[1][1].y, v[1][1].z, v[1][1].w};
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const uint32_t w = (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)c0[j]) |
+                               ((uint32_t)__builtin_bit_cast(uint16_t, (__bf16)c1[j]) << 16);
+            *(uint32_t*)(dst + (c8 + j) * WB_LD + 4 * rp) = w;
+        }
+    };
+    floatx16 acc = {};
+    load(r0);
+    for (int64_t rb = r0; rb < r1; rb += WB_ROWS) {
+        put(At, ra);
+        put(Bt, rbv);
+        __syncthreads();
+        if (rb + WB_ROWS < r1) load(rb + WB_ROWS);  // in flight during the products
+#pragma unroll
+        for (int s16 = 0; s16 < WB_ROWS / 16; ++s16) {
+            const bf16x8 av = *(const bf16x8*)(At + (32 * wr + r) * WB_LD + 2 * (16 * s16 + 8 * h));
+            const bf16x8 bv = *(const bf16x8*)(Bt + (32 * wc + r) * WB_LD + 2 * (16 * s16 + 8 * h));
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    float* out = a.part + (int64_t)chunk * a.Ktot * a.N;
+    const int n = n0 + 32 * wc + r;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int k = k0 + 32 * wr + 8 * (i >> 2) + 4 * h + (i & 3);
         out[(int64_t)k * a.N + n] = acc[i];
     }
 }
@@ -498,8 +595,9 @@ hipError_t gemm_rows(const GemmRowsArgs& a, hipStream_t st) {
 hipError_t gemm_wgrad(const WgradArgs& a0, float* dst, int out_mode, hipStream_t st) {
     WgradArgs a = a0;
     const int nchunks = (int)((a.M + a.rows_per_chunk - 1) / a.rows_per_chunk);
-    const int64_t blocks = (int64_t)nchunks * (a.Ktot / GT) * (a.N / GT);
-    hipLaunchKernelGGL(gemm_wgrad_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
+    const int64_t blocks = (int64_t)((nchunks + 7) / 8) * 8 * (a.Ktot / GT) * (a.N / GT);
+    if (a.bf16) hipLaunchKernelGGL(gemm_wgrad_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(gemm_wgrad_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return reduce_parts(a.part, a.part_capacity, nchunks, (int64_t)a.Ktot * a.N, dst, (int64_t)(out_mode == 2 ? 2 : 1),

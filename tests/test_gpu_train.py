@@ -232,8 +232,8 @@ def test_autograd_function_matches_direct_calls(g, prec):
 
 # ---------------------------------------------------------------- full member, BF16 compute
 def test_full_member_gradient_bf16_stated(g):
-    """BF16 member: bf16 forward (with per-stack recompute) and bf16-operand row GEMMs in the
-    backward, fp32 accumulation and fp32 weight gradients. Against the FP64 oracle gradient the
+    """BF16 member: bf16 forward (with per-stack recompute) and bf16-operand row and weight-gradient
+    GEMMs in the backward, fp32 accumulation. Against the FP64 oracle gradient the
     error is stated per tensor (relative and cosine); the gate is loose: the direction of every
     tensor's gradient must be kept."""
     from oracle.arch import FULL, layout
