@@ -1217,6 +1217,35 @@ static hipError_t debug_lp(gwd_model* m, int member, int l, const float* x_in, i
     return e != hipSuccess ? e : (e2 != hipSuccess ? e2 : hipGetLastError());
 }
 
+// One gated layer on bf16 activations, for the training forward and its recompute: x_in and x_out
+// bf16 [nb][T][128] (x_out unused for the network's last layer), skip fp32, pre-activations fp32
+// when pre_out is set. The same launches as the debug path without its fp32 <-> bf16 conversions.
+template <bool FP8>
+static hipError_t train_lp(gwd_model* m, int member, int l, const uint16_t* x_in, int nb, int T, float* pre_out,
+                           uint16_t* x_out, float* skip, hipStream_t st) {
+    const int L = m->arch.n_stacks * m->arch.layers_per_stack;
+    LayerArgsLP a = lp_args<FP8>(m, member, l);
+    a.x_in = x_in;
+    a.x_out = x_out;
+    a.skip = skip;
+    a.pre_out = pre_out;
+    a.T = T;
+    const int tiling = lp_tiling(m, FP8);
+    if (l == 0) return (L == 1) ? launch_lp<FP8, false, true, true>(a, nb, tiling, st)
+                                : launch_lp<FP8, false, true, false>(a, nb, tiling, st);
+    if (l < L - 1) return launch_lp<FP8, false, false, false>(a, nb, tiling, st);
+    return launch_lp<FP8, false, false, true>(a, nb, tiling, st);
+}
+hipError_t launch_layer_train_bf16io(gwd_model* m, int member, int l, const uint16_t* x_in, int nb, int T,
+                                     float* pre_out, uint16_t* x_out, float* skip, hipStream_t st) {
+    return m->prec == GWD_FP8_E4M3 ? train_lp<true>(m, member, l, x_in, nb, T, pre_out, x_out, skip, st)
+                                   : train_lp<false>(m, member, l, x_in, nb, T, pre_out, x_out, skip, st);
+}
+hipError_t launch_f32_to_bf16(const float* x, int64_t n, uint16_t* y, hipStream_t st) {
+    hipLaunchKernelGGL(f32_to_bf16_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, n, y);
+    return hipGetLastError();
+}
+
 // One launch of layer l exactly as the forward issues it for a middle layer (workspace buffers).
 template <bool FP8>
 static hipError_t production_lp(gwd_model* m, int member, int l, void* x_in, void* x_out, float* skip, int nb, int T,

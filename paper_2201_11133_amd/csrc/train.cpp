@@ -62,16 +62,36 @@ static gwd_status fwd_train_kind1(gwd_model* m, int member, const float* u, int 
     float* R = fptr(m->tws.base, 2 * M * kC);
     float* H = fptr(m->tws.base, 3 * M * kC);
     float* skip = saved + (int64_t)m->arch.n_stacks * M * kC;
-    hipError_t e = launch_input_proj(u, M, w + v.in_w, w + v.in_b, saved, st);
-    if (e != hipSuccess) return hip_fail(e, "input projection");
-    const float* xin = saved;
-    for (int l = 0; l < L; ++l) {
-        float* xout;
-        if ((l + 1) % LPS == 0 && l + 1 < L) xout = saved + (int64_t)((l + 1) / LPS) * M * kC;  // next stack input
-        else xout = (xin == xa) ? xb : xa;
-        e = launch_layer_debug(m, member, l, xin, B, T, nullptr, xout, skip, st);
-        if (e != hipSuccess) return hip_fail(e, "layer kernel");
-        xin = xout;
+    hipError_t e;
+    if (m->prec == GWD_BF16 || m->prec == GWD_FP8_E4M3) {
+        // bf16 residual stream, as in the inference forward: the saved stack inputs are bf16 (each
+        // in the first half of its slot), the input projection is rounded to bf16 once
+        e = launch_input_proj(u, M, w + v.in_w, w + v.in_b, xa, st);
+        if (e != hipSuccess) return hip_fail(e, "input projection");
+        e = launch_f32_to_bf16(xa, M * kC, (uint16_t*)saved, st);
+        if (e != hipSuccess) return hip_fail(e, "bf16 rounding");
+        const uint16_t* xin = (const uint16_t*)saved;
+        uint16_t *ya = (uint16_t*)xa, *yb = (uint16_t*)xb;
+        for (int l = 0; l < L; ++l) {
+            uint16_t* xout;
+            if ((l + 1) % LPS == 0 && l + 1 < L) xout = (uint16_t*)(saved + (int64_t)((l + 1) / LPS) * M * kC);
+            else xout = (xin == ya) ? yb : ya;
+            e = launch_layer_train_bf16io(m, member, l, xin, B, T, nullptr, l < L - 1 ? xout : nullptr, skip, st);
+            if (e != hipSuccess) return hip_fail(e, "layer kernel");
+            xin = xout;
+        }
+    } else {
+        e = launch_input_proj(u, M, w + v.in_w, w + v.in_b, saved, st);
+        if (e != hipSuccess) return hip_fail(e, "input projection");
+        const float* xin = saved;
+        for (int l = 0; l < L; ++l) {
+            float* xout;
+            if ((l + 1) % LPS == 0 && l + 1 < L) xout = saved + (int64_t)((l + 1) / LPS) * M * kC;  // next stack input
+            else xout = (xin == xa) ? xb : xa;
+            e = launch_layer_debug(m, member, l, xin, B, T, nullptr, xout, skip, st);
+            if (e != hipSuccess) return hip_fail(e, "layer kernel");
+            xin = xout;
+        }
     }
     // head: h = W_h1 ReLU(skip) + b_h1; logit = w_h2 . act(h) + b_h2
     e = launch_relu_copy(skip, M * kC, R, st);
@@ -149,15 +169,22 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
     // ---- stacks, last to first
     for (int sidx = m->arch.n_stacks - 1; sidx >= 0; --sidx) {
         // recompute the stack, keeping each layer's input and pre-activation
+        // (BF16/FP8 members: the layer inputs XS are bf16, in the first half of each slot)
         const float* xin = saved + (int64_t)sidx * M * kC;
         for (int i = 0; i < LPS; ++i) {
             const int l = sidx * LPS + i;
             float* xs_i = fptr(b, f_xs + (int64_t)i * M * kC);
-            if (i == 0) HIPCHK(hipMemcpyAsync(xs_i, xin, M * kC * 4, hipMemcpyDeviceToDevice, st), "copy stack input");
+            if (i == 0)
+                HIPCHK(hipMemcpyAsync(xs_i, xin, M * kC * (BT ? 2 : 4), hipMemcpyDeviceToDevice, st), "copy stack input");
             // the stack's last output and the recomputed skip sum are not needed: scratch buffers
             float* xnext = (i + 1 < LPS) ? fptr(b, f_xs + (int64_t)(i + 1) * M * kC) : G;
-            HIPCHK(launch_layer_debug(m, member, l, xs_i, B, T, fptr(b, f_pre + (int64_t)i * M * 2 * kC),
-                                      (l < L - 1) ? xnext : nullptr, SKS, st), "recompute");
+            float* pre_i = fptr(b, f_pre + (int64_t)i * M * 2 * kC);
+            if (BT)
+                HIPCHK(launch_layer_train_bf16io(m, member, l, (const uint16_t*)xs_i, B, T, pre_i,
+                                                 (l < L - 1) ? (uint16_t*)xnext : nullptr, SKS, st), "recompute");
+            else
+                HIPCHK(launch_layer_debug(m, member, l, xs_i, B, T, pre_i, (l < L - 1) ? xnext : nullptr, SKS, st),
+                       "recompute");
         }
         for (int i = LPS - 1; i >= 0; --i) {
             const int l = sidx * LPS + i;
@@ -197,6 +224,7 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
                 WgradArgs a{};
                 a.A[0] = APart{DPRE, 2 * kC, 0, 2 * kC}; a.nparts = 1; a.Ktot = 2 * kC;
                 a.B = xs_i; a.ldb = kC; a.N = kC; a.M = M; a.T = T; a.rows_per_chunk = RPC; a.part = PART; a.part_capacity = PART_CAP; a.bf16 = BT != nullptr;
+                if (BT) a.B16 = (const uint16_t*)xs_i;
                 a.bshift = 0;
                 HIPCHK(gemm_wgrad(a, grad + v.dil_w[l] + 1, 2, st), "d dil.W tap1");
                 a.bshift = -d;

@@ -48,6 +48,7 @@ struct WgradArgs {
     float* part;  // [nchunks][Ktot][N]
     int64_t part_capacity;  // floats available at part (partials, then the reduction's scratch)
     bool bf16 = false;      // operands rounded to bf16 (fp32 accumulation): BF16/FP8 members
+    const uint16_t* B16 = nullptr;  // with bf16: B already in bf16 (same layout as B, which is unused)
 };
 
 hipError_t gemm_rows(const GemmRowsArgs& a, hipStream_t st);

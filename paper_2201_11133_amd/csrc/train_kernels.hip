@@ -272,11 +272,13 @@ __global__ __launch_bounds__(256) void gemm_wgrad_bf16_kernel(WgradArgs a) {
     // columns of rows 2 rp and 2 rp + 1, of A and of B
     const int rp = tid >> 3, c8 = 8 * (tid & 7);
     float4 ra[2][2], rbv[2][2];
+    uint4 rb16[2];  // B rows already in bf16
     auto load = [&](int64_t rb) {
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             const int64_t row = rb + 2 * rp + e;
             ra[e][0] = ra[e][1] = rbv[e][0] = rbv[e][1] = make_float4(0.f, 0.f, 0.f, 0.f);
+            rb16[e] = make_uint4(0, 0, 0, 0);
             if (row < r1) {
                 const int64_t sa = part_row(ap, row, a.T), sb = part_row(bpart, row, a.T);
                 if (sa >= 0) {
@@ -285,11 +287,25 @@ __global__ __launch_bounds__(256) void gemm_wgrad_bf16_kernel(WgradArgs a) {
                     ra[e][1] = *(const float4*)(pa + 4);
                 }
                 if (sb >= 0) {
-                    const float* pb = a.B + sb * a.ldb + n0 + c8;
-                    rbv[e][0] = *(const float4*)pb;
-                    rbv[e][1] = *(const float4*)(pb + 4);
+                    if (a.B16) {
+                        rb16[e] = *(const uint4*)(a.B16 + sb * a.ldb + n0 + c8);
+                    } else {
+                        const float* pb = a.B + sb * a.ldb + n0 + c8;
+                        rbv[e][0] = *(const float4*)pb;
+                        rbv[e][1] = *(const float4*)(pb + 4);
+                    }
                 }
             }
+        }
+    };
+    // the same for B given in bf16: column c of the two rows as one pair
+    auto put16 = [&](uint8_t* dst) {
+        const uint32_t w0[4] = {rb16[0].x, rb16[0].y, rb16[0].z, rb16[0].w};
+        const uint32_t w1[4] = {rb16[1].x, rb16[1].y, rb16[1].z, rb16[1].w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            *(uint32_t*)(dst + (c8 + 2 * j) * WB_LD + 4 * rp) = (w0[j] & 0xffffu) | (w1[j] << 16);
+            *(uint32_t*)(dst + (c8 + 2 * j + 1) * WB_LD + 4 * rp) = (w0[j] >> 16) | (w1[j] & 0xffff0000u);
         }
     };
     // column c of rows (2 rp, 2 rp + 1) as one bf16 pair at [c][2 rp]
@@ -307,7 +323,8 @@ __global__ __launch_bounds__(256) void gemm_wgrad_bf16_kernel(WgradArgs a) {
     load(r0);
     for (int64_t rb = r0; rb < r1; rb += WB_ROWS) {
         put(At, ra);
-        put(Bt, rbv);
+        if (a.B16) put16(Bt);
+        else put(Bt, rbv);
         __syncthreads();
         if (rb + WB_ROWS < r1) load(rb + WB_ROWS);  // in flight during the products
 #pragma unroll
@@ -596,6 +613,7 @@ hipError_t gemm_wgrad(const WgradArgs& a0, float* dst, int out_mode, hipStream_t
     WgradArgs a = a0;
     const int nchunks = (int)((a.M + a.rows_per_chunk - 1) / a.rows_per_chunk);
     const int64_t blocks = (int64_t)((nchunks + 7) / 8) * 8 * (a.Ktot / GT) * (a.N / GT);
+    if (a.B16 && !a.bf16) return hipErrorInvalidValue;
     if (a.bf16) hipLaunchKernelGGL(gemm_wgrad_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
     else hipLaunchKernelGGL(gemm_wgrad_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
     hipError_t e = hipGetLastError();
