@@ -1121,8 +1121,9 @@ static hipError_t launch_fused(gwd_model* m, int member, int l, int nl, const ui
     const int want = (int)std::min<int64_t>(n_ch, std::max<int64_t>(1, (512 + per - 1) / per));
     a.seg_chunks = (n_ch + want - 1) / want;
     a.n_seg = (n_ch + a.seg_chunks - 1) / a.seg_chunks;
-    const bool first = l == 0;
-    if (first) {
+    // the network's first layers take the stream (inference) or a bf16 x0 (training: fb == nullptr)
+    const bool first = l == 0, stream_in = first && fb != nullptr;
+    if (stream_in) {
         a.streams = fb->streams;
         a.n_streams = fb->n_streams;
         a.win_base = fb->win_base;
@@ -1131,10 +1132,12 @@ static hipError_t launch_fused(gwd_model* m, int member, int l, int nl, const ui
     const dim3 grid((unsigned)(per * a.n_seg));
     if (FP8) {
         if (nl != 3) return hipErrorInvalidValue;
-        if (first) hipLaunchKernelGGL((fused3_fp8_kernel<true, true>), grid, dim3(256), 0, st, a);
+        if (stream_in) hipLaunchKernelGGL((fused3_fp8_kernel<true, true>), grid, dim3(256), 0, st, a);
+        else if (first) hipLaunchKernelGGL((fused3_fp8_kernel<false, true>), grid, dim3(256), 0, st, a);
         else hipLaunchKernelGGL((fused3_fp8_kernel<false, false>), grid, dim3(256), 0, st, a);
     } else if (nl == 3) {
-        if (first) hipLaunchKernelGGL((fused_bf16_kernel<true, true, 3, false>), grid, dim3(256), 0, st, a);
+        if (stream_in) hipLaunchKernelGGL((fused_bf16_kernel<true, true, 3, false>), grid, dim3(256), 0, st, a);
+        else if (first) hipLaunchKernelGGL((fused_bf16_kernel<false, true, 3, false>), grid, dim3(256), 0, st, a);
         else hipLaunchKernelGGL((fused_bf16_kernel<false, false, 3, false>), grid, dim3(256), 0, st, a);
     } else {
         if (first) return hipErrorInvalidValue;                          // stacks of at least 10 layers
@@ -1240,6 +1243,17 @@ hipError_t launch_layer_train_bf16io(gwd_model* m, int member, int l, const uint
                                      float* pre_out, uint16_t* x_out, float* skip, hipStream_t st) {
     return m->prec == GWD_FP8_E4M3 ? train_lp<true>(m, member, l, x_in, nb, T, pre_out, x_out, skip, st)
                                    : train_lp<false>(m, member, l, x_in, nb, T, pre_out, x_out, skip, st);
+}
+// Training forward of BF16/FP8 members (no pre-activations kept): the fused launches of the
+// inference forward where they apply. Layers covered by the launch at layer l (1 = a single layer).
+int train_layers_per_launch(const gwd_model* m, int l, int T) {
+    const int nl = fused_layers(m, l, T);
+    return nl ? nl : 1;
+}
+hipError_t launch_fused_train(gwd_model* m, int member, int l, int nl, const uint16_t* x_in, uint16_t* x_out,
+                              float* skip, int nb, int T, hipStream_t st) {
+    return m->prec == GWD_FP8_E4M3 ? launch_fused<true>(m, member, l, nl, x_in, x_out, skip, nb, T, nullptr, st)
+                                   : launch_fused<false>(m, member, l, nl, x_in, x_out, skip, nb, T, nullptr, st);
 }
 hipError_t launch_f32_to_bf16(const float* x, int64_t n, uint16_t* y, hipStream_t st) {
     hipLaunchKernelGGL(f32_to_bf16_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, n, y);

@@ -138,6 +138,9 @@ hipError_t launch_layer_debug(gwd_model* m, int member, int layer, const float* 
 hipError_t launch_layer_train_bf16io(gwd_model* m, int member, int l, const uint16_t* x_in, int nb, int T,
                                      float* pre_out, uint16_t* x_out, float* skip, hipStream_t st);
 hipError_t launch_f32_to_bf16(const float* x, int64_t n, uint16_t* y, hipStream_t st);
+int train_layers_per_launch(const gwd_model* m, int l, int T);
+hipError_t launch_fused_train(gwd_model* m, int member, int l, int nl, const uint16_t* x_in, uint16_t* x_out,
+                              float* skip, int nb, int T, hipStream_t st);
 
 // Layers covered by the launch that starts at layer l (3 for a fused BF16 triple, else 1).
 int layers_per_launch(const gwd_model* m, int l);

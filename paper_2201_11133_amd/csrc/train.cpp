@@ -70,15 +70,20 @@ static gwd_status fwd_train_kind1(gwd_model* m, int member, const float* u, int 
         if (e != hipSuccess) return hip_fail(e, "input projection");
         e = launch_f32_to_bf16(xa, M * kC, (uint16_t*)saved, st);
         if (e != hipSuccess) return hip_fail(e, "bf16 rounding");
+        // fused launches as in the inference forward (a stack ends on a launch boundary)
         const uint16_t* xin = (const uint16_t*)saved;
         uint16_t *ya = (uint16_t*)xa, *yb = (uint16_t*)xb;
-        for (int l = 0; l < L; ++l) {
+        for (int l = 0; l < L;) {
+            const int nl = train_layers_per_launch(m, l, T);
+            const int le = l + nl;  // first layer after this launch
             uint16_t* xout;
-            if ((l + 1) % LPS == 0 && l + 1 < L) xout = (uint16_t*)(saved + (int64_t)((l + 1) / LPS) * M * kC);
+            if (le % LPS == 0 && le < L) xout = (uint16_t*)(saved + (int64_t)(le / LPS) * M * kC);
             else xout = (xin == ya) ? yb : ya;
-            e = launch_layer_train_bf16io(m, member, l, xin, B, T, nullptr, l < L - 1 ? xout : nullptr, skip, st);
+            if (nl > 1) e = launch_fused_train(m, member, l, nl, xin, xout, skip, B, T, st);
+            else e = launch_layer_train_bf16io(m, member, l, xin, B, T, nullptr, le < L ? xout : nullptr, skip, st);
             if (e != hipSuccess) return hip_fail(e, "layer kernel");
             xin = xout;
+            l = le;
         }
     } else {
         e = launch_input_proj(u, M, w + v.in_w, w + v.in_b, saved, st);
