@@ -557,15 +557,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                      : rr < 10 ? fu_buf(lds, 1) - (10 - rr) * FU_XROW : fu_buf(lds, 2) - (14 - rr) * FU_XROW;
         *(uint4*)(row + 16 * c) = make_uint4(0, 0, 0, 0);
     }
-    // the biases of the layers, once per block: [layer][conv 256 | res 128 | skip 128]
-    for (int idx = tid; idx < NL * 4 * kC; idx += 256) {
-        const int j = idx / (4 * kC), e = idx % (4 * kC);
-        float v;
-        if (e < 2 * kC) v = p.bc[j][e];
-        else if (LAST && j == NL - 1) v = e < 3 * kC ? 0.f : p.brs[j][e - 3 * kC];  // skip columns only
-        else v = p.brs[j][e - 2 * kC];
-        BI[idx] = v;
-    }
     // Products are taken transposed: weight fragments are the A operand and row fragments the B
     // operand, so an accumulator holds rows along the lanes. Lane (h, r) holds row r of each
     // 32-row block and, of its wave's 32-channel block, the channels 8 g + 4 h + e (g, e = 0..3):
@@ -606,6 +597,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
     for (int k = 0; k < FU_PRE; ++k) {
         rf[k] = load_frag<false>(p.wc[0] + ((size_t)(q * T::NK1 + k) * 64 + lane) * T::FRAG);
         rg[k] = load_frag<false>(p.wc[0] + ((size_t)((4 + q) * T::NK1 + k) * 64 + lane) * T::FRAG);
+    }
+    // the biases of the layers, once per block (requested after the first rows and
+    // weights, so the latencies overlap): [layer][conv 256 | res 128 | skip 128]
+    for (int idx = tid; idx < NL * 4 * kC; idx += 256) {
+        const int j = idx / (4 * kC), e = idx % (4 * kC);
+        float v;
+        if (e < 2 * kC) v = p.bc[j][e];
+        else if (LAST && j == NL - 1) v = e < 3 * kC ? 0.f : p.brs[j][e - 3 * kC];  // skip columns only
+        else v = p.brs[j][e - 2 * kC];
+        BI[idx] = v;
     }
     for (int c = (seg > 0 ? c0 - 1 : c0); c < c1; ++c) {
         const bool store = c >= c0;
@@ -1076,8 +1077,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
     }
 }
 
-// Does layer l start a fused triple? Triples (i, i+1, i+2) with i % 3 == 0 inside a stack, never
-// holding the network's last layer (that one writes no residual).
 // Layers covered by the fused launch that starts at layer l for windows of length T: 0 (l is not a
 // start), 3, or 4. Triples start at stack positions 0, 3, 6; the triple at 6 also takes the stack's
 // last layer (a quad, BF16) when the sub-sequences at its dilation are one chunk long. A triple never
