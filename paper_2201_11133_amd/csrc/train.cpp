@@ -210,12 +210,17 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
             g.M = M; g.N = kC; g.T = T; g.C = DG; g.ldc = kC;
             g.bt = BT;
         HIPCHK(gemm_rows(g, st), "dg");
-            HIPCHK(launch_gate_bwd(pre, DG, M, G, DPRE, st), "gate bwd");
+            // BF16/FP8 members: g and dpre in bf16 (the GEMMs that read them round to bf16 anyway)
+            uint16_t* G16 = BT ? (uint16_t*)G : nullptr;
+            uint16_t* DPRE16 = BT ? (uint16_t*)DPRE : nullptr;
+            if (BT) HIPCHK(launch_gate_bwd16(pre, DG, M, G16, DPRE16, st), "gate bwd");
+            else HIPCHK(launch_gate_bwd(pre, DG, M, G, DPRE, st), "gate bwd");
             // skip / residual weight gradients
             {
                 WgradArgs a{};
                 a.A[0] = APart{DS, kC, 0, kC}; a.nparts = 1; a.Ktot = kC;
                 a.B = G; a.ldb = kC; a.N = kC; a.M = M; a.T = T; a.rows_per_chunk = RPC; a.part = PART; a.part_capacity = PART_CAP; a.bf16 = BT != nullptr;
+                a.B16 = G16;
                 HIPCHK(gemm_wgrad(a, grad + v.skip_w[l], 0, st), "d skip.W");
                 HIPCHK(colsum(DS, kC, M, kC, nullptr, 0, 0, PART, PART_CAP, grad + v.skip_b[l], 1, st), "d skip.b");
                 if (!last) {
@@ -227,21 +232,22 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
             // conv weight gradient: dW[n][c][tap] = sum_t dpre[t][n] x[t - d (1 - tap)][c]
             {
                 WgradArgs a{};
-                a.A[0] = APart{DPRE, 2 * kC, 0, 2 * kC}; a.nparts = 1; a.Ktot = 2 * kC;
+                a.A[0] = APart{DPRE, 2 * kC, 0, 2 * kC, DPRE16}; a.nparts = 1; a.Ktot = 2 * kC;
                 a.B = xs_i; a.ldb = kC; a.N = kC; a.M = M; a.T = T; a.rows_per_chunk = RPC; a.part = PART; a.part_capacity = PART_CAP; a.bf16 = BT != nullptr;
                 if (BT) a.B16 = (const uint16_t*)xs_i;
                 a.bshift = 0;
                 HIPCHK(gemm_wgrad(a, grad + v.dil_w[l] + 1, 2, st), "d dil.W tap1");
                 a.bshift = -d;
                 HIPCHK(gemm_wgrad(a, grad + v.dil_w[l], 2, st), "d dil.W tap0");
-                HIPCHK(colsum(DPRE, 2 * kC, M, 2 * kC, nullptr, 0, 0, PART, PART_CAP, grad + v.dil_b[l], 1, st), "d dil.b");
+                if (BT) HIPCHK(colsum16(DPRE16, 2 * kC, M, 2 * kC, PART, PART_CAP, grad + v.dil_b[l], 1, st), "d dil.b");
+                else HIPCHK(colsum(DPRE, 2 * kC, M, 2 * kC, nullptr, 0, 0, PART, PART_CAP, grad + v.dil_b[l], 1, st), "d dil.b");
             }
             // dx = dx' + dpre[t] W1 + dpre[t+d] W0   (W_tap as [n][c]: dil.W[(n C + c) 2 + tap])
             {
                 GemmRowsArgs g2{};
-                g2.A[0] = APart{DPRE, 2 * kC, 0, 2 * kC};
+                g2.A[0] = APart{DPRE, 2 * kC, 0, 2 * kC, DPRE16};
                 g2.B[0] = BPart{w + v.dil_w[l] + 1, 2 * kC, 2};
-                g2.A[1] = APart{DPRE, 2 * kC, d, 2 * kC};
+                g2.A[1] = APart{DPRE, 2 * kC, d, 2 * kC, DPRE16};
                 g2.B[1] = BPart{w + v.dil_w[l], 2 * kC, 2};
                 g2.nparts = 2; g2.M = M; g2.N = kC; g2.T = T; g2.C = DX; g2.ldc = kC; g2.beta = 1.f;
                 g2.bt = BT;

@@ -10,6 +10,7 @@ struct APart {
     int64_t ld;
     int shift;
     int K;
+    const uint16_t* p16 = nullptr;  // set: the part is bf16 (ptr unused); bf16-operand kernels only
 };
 // B(k, n) = ptr[k * ld + n * es]
 struct BPart {
@@ -61,6 +62,11 @@ hipError_t colsum(const float* X, int64_t ldx, int64_t M, int N, const float* w,
 hipError_t launch_input_proj(const float* u, int64_t M, const float* w_in, const float* b_in, float* x0,
                              hipStream_t st);
 hipError_t launch_gate_bwd(const float* pre, const float* dg, int64_t M, float* g, float* dpre, hipStream_t st);
+// the same with g and dpre rounded to bf16 (round to nearest even), for the bf16-operand backward
+hipError_t launch_gate_bwd16(const float* pre, const float* dg, int64_t M, uint16_t* g, uint16_t* dpre, hipStream_t st);
+// dst[n * dst_stride] += sum_rows X[row][n] for bf16 X (N % 4 == 0, N <= 1024, ldx % 4 == 0)
+hipError_t colsum16(const uint16_t* X, int64_t ldx, int64_t M, int N, float* part, int64_t part_capacity, float* dst,
+                    int64_t dst_stride, hipStream_t st);
 hipError_t launch_head_bwd_elem(const float* h, const float* dz, int64_t M, const float* w2, int mid, float* dh,
                                 float* ah, hipStream_t st);
 hipError_t launch_head_logit(const float* h, int64_t M, const float* w2, const float* b2, int mid, float* z,

@@ -127,13 +127,17 @@ __global__ __launch_bounds__(256) void gemm_rows_bf16_kernel(GemmRowsArgs a, int
     for (int p = 0; p < a.nparts; ++p) {
         const APart& ap = a.A[p];
         const int64_t src = part_row(ap, row0 + rr, a.T);
-        const float* arow = src < 0 ? nullptr : ap.ptr + src * ap.ld + kq;
+        const float* arow = src < 0 || ap.p16 ? nullptr : ap.ptr + src * ap.ld + kq;
+        const uint16_t* arow16 = src < 0 || !ap.p16 ? nullptr : ap.p16 + src * ap.ld + kq;
         for (int k0 = 0; k0 < ap.K; k0 += BK) {
             uint4 w0 = make_uint4(0, 0, 0, 0), w1 = w0;
             if (arow) {
                 const float4* q4 = (const float4*)(arow + k0);
                 w0 = bf16_pack8(q4[0], q4[1]);
                 w1 = bf16_pack8(q4[2], q4[3]);
+            } else if (arow16) {  // already bf16
+                w0 = *(const uint4*)(arow16 + k0);
+                w1 = *(const uint4*)(arow16 + k0 + 8);
             }
             __syncthreads();  // the previous chunk's fragments are read
             *(uint4*)&As[rr * AROW + kq] = w0;
@@ -272,19 +276,23 @@ __global__ __launch_bounds__(256) void gemm_wgrad_bf16_kernel(WgradArgs a) {
     // columns of rows 2 rp and 2 rp + 1, of A and of B
     const int rp = tid >> 3, c8 = 8 * (tid & 7);
     float4 ra[2][2], rbv[2][2];
-    uint4 rb16[2];  // B rows already in bf16
+    uint4 ra16[2], rb16[2];  // A / B rows already in bf16
     auto load = [&](int64_t rb) {
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             const int64_t row = rb + 2 * rp + e;
             ra[e][0] = ra[e][1] = rbv[e][0] = rbv[e][1] = make_float4(0.f, 0.f, 0.f, 0.f);
-            rb16[e] = make_uint4(0, 0, 0, 0);
+            ra16[e] = rb16[e] = make_uint4(0, 0, 0, 0);
             if (row < r1) {
                 const int64_t sa = part_row(ap, row, a.T), sb = part_row(bpart, row, a.T);
                 if (sa >= 0) {
-                    const float* pa = ap.ptr + sa * ap.ld + (k0 - kb) + c8;
-                    ra[e][0] = *(const float4*)pa;
-                    ra[e][1] = *(const float4*)(pa + 4);
+                    if (ap.p16) {
+                        ra16[e] = *(const uint4*)(ap.p16 + sa * ap.ld + (k0 - kb) + c8);
+                    } else {
+                        const float* pa = ap.ptr + sa * ap.ld + (k0 - kb) + c8;
+                        ra[e][0] = *(const float4*)pa;
+                        ra[e][1] = *(const float4*)(pa + 4);
+                    }
                 }
                 if (sb >= 0) {
                     if (a.B16) {
@@ -298,10 +306,10 @@ __global__ __launch_bounds__(256) void gemm_wgrad_bf16_kernel(WgradArgs a) {
             }
         }
     };
-    // the same for B given in bf16: column c of the two rows as one pair
-    auto put16 = [&](uint8_t* dst) {
-        const uint32_t w0[4] = {rb16[0].x, rb16[0].y, rb16[0].z, rb16[0].w};
-        const uint32_t w1[4] = {rb16[1].x, rb16[1].y, rb16[1].z, rb16[1].w};
+    // the same for rows given in bf16: column c of the two rows as one pair
+    auto put16 = [&](uint8_t* dst, const uint4 (&v)[2]) {
+        const uint32_t w0[4] = {v[0].x, v[0].y, v[0].z, v[0].w};
+        const uint32_t w1[4] = {v[1].x, v[1].y, v[1].z, v[1].w};
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             *(uint32_t*)(dst + (c8 + 2 * j) * WB_LD + 4 * rp) = (w0[j] & 0xffffu) | (w1[j] << 16);
@@ -322,8 +330,9 @@ __global__ __launch_bounds__(256) void gemm_wgrad_bf16_kernel(WgradArgs a) {
     floatx16 acc = {};
     load(r0);
     for (int64_t rb = r0; rb < r1; rb += WB_ROWS) {
-        put(At, ra);
-        if (a.B16) put16(Bt);
+        if (ap.p16) put16(At, ra16);
+        else put(At, ra);
+        if (a.B16) put16(Bt, rb16);
         else put(Bt, rbv);
         __syncthreads();
         if (rb + WB_ROWS < r1) load(rb + WB_ROWS);  // in flight during the products
@@ -440,6 +449,38 @@ __global__ __launch_bounds__(256) void colsum4_kernel(const float* X, int64_t ld
     }
 }
 
+// colsum4_kernel for bf16 X (four columns as one 8-byte load)
+__global__ __launch_bounds__(256) void colsum16_kernel(const uint16_t* X, int64_t ldx, int64_t M, int N,
+                                                       int64_t rows_per_chunk, float* part) {
+    __shared__ float4 red[256];
+    const int cpr = N >> 2;
+    const int groups = 256 / cpr;
+    const int tid = threadIdx.x, c4 = tid % cpr, g = tid / cpr;
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_chunk;
+    const int64_t r1 = min(r0 + rows_per_chunk, M);
+    float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (g < groups) {
+#pragma unroll 4
+        for (int64_t r = r0 + g; r < r1; r += groups) {
+            const uint2 w = *(const uint2*)(X + r * ldx + 4 * c4);
+            s.x += __uint_as_float(w.x << 16);
+            s.y += __uint_as_float(w.x & 0xffff0000u);
+            s.z += __uint_as_float(w.y << 16);
+            s.w += __uint_as_float(w.y & 0xffff0000u);
+        }
+    }
+    red[tid] = s;
+    __syncthreads();
+    if (tid < cpr) {
+        float4 t = red[tid];
+        for (int k = 1; k < groups; ++k) {
+            const float4 u = red[k * cpr + tid];
+            t.x += u.x; t.y += u.y; t.z += u.z; t.w += u.w;
+        }
+        *(float4*)(part + (int64_t)blockIdx.x * N + 4 * tid) = t;
+    }
+}
+
 // x0[row][c] = W_in[c] . u[row] + b_in[c]   (windows [B][T][2] interleaved)
 __global__ __launch_bounds__(256) void input_proj_kernel(const float* u, int64_t M, const float* w_in,
                                                          const float* b_in, float* x0) {
@@ -464,6 +505,20 @@ __global__ __launch_bounds__(256) void gate_bwd_kernel(const float* pre, const f
     g[i] = th * sg;
     dpre[row * 2 * kC + c] = d * sg * (1.f - th * th);
     dpre[row * 2 * kC + kC + c] = d * th * sg * (1.f - sg);
+}
+
+__global__ __launch_bounds__(256) void gate_bwd16_kernel(const float* pre, const float* dg, int64_t M, uint16_t* g,
+                                                         uint16_t* dpre) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= M * kC) return;
+    const int64_t row = i / kC;
+    const int c = (int)(i % kC);
+    const float pf = pre[row * 2 * kC + c], pg = pre[row * 2 * kC + kC + c];
+    const float th = tanhf(pf), sg = 1.f / (1.f + expf(-pg));
+    const float d = dg[i];
+    g[i] = __builtin_bit_cast(uint16_t, (__bf16)(th * sg));
+    dpre[row * 2 * kC + c] = __builtin_bit_cast(uint16_t, (__bf16)(d * sg * (1.f - th * th)));
+    dpre[row * 2 * kC + kC + c] = __builtin_bit_cast(uint16_t, (__bf16)(d * th * sg * (1.f - sg)));
 }
 
 // Head backward, elementwise part: dh[row][j] = dz[row] * w2[j] * act'(h[row][j]);
@@ -590,11 +645,16 @@ static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 hipError_t gemm_rows(const GemmRowsArgs& a, hipStream_t st) {
     bool bf16 = a.bt != nullptr && a.N % BN == 0 && a.M % BR == 0;
+    bool any16 = false;
     int Ktot = 0;
     for (int p = 0; p < a.nparts; ++p) {
         Ktot += a.A[p].K;
-        bf16 = bf16 && a.A[p].K % BK == 0 && a.A[p].ld % 4 == 0 && ((uintptr_t)a.A[p].ptr & 15) == 0;
+        const APart& q = a.A[p];
+        any16 = any16 || q.p16;
+        bf16 = bf16 && q.K % BK == 0 &&
+               (q.p16 ? q.ld % 8 == 0 && ((uintptr_t)q.p16 & 15) == 0 : q.ld % 4 == 0 && ((uintptr_t)q.ptr & 15) == 0);
     }
+    if (any16 && !bf16) return hipErrorInvalidValue;  // bf16 parts need the bf16-operand kernel
     if (bf16) {
         hipLaunchKernelGGL(pack_bt_kernel, dim3((unsigned)(((int64_t)a.N * Ktot + 255) / 256)), dim3(256), 0, st, a,
                            Ktot);
@@ -613,7 +673,7 @@ hipError_t gemm_wgrad(const WgradArgs& a0, float* dst, int out_mode, hipStream_t
     WgradArgs a = a0;
     const int nchunks = (int)((a.M + a.rows_per_chunk - 1) / a.rows_per_chunk);
     const int64_t blocks = (int64_t)((nchunks + 7) / 8) * 8 * (a.Ktot / GT) * (a.N / GT);
-    if (a.B16 && !a.bf16) return hipErrorInvalidValue;
+    if ((a.B16 || a.A[0].p16 || (a.nparts > 1 && a.A[1].p16)) && !a.bf16) return hipErrorInvalidValue;
     if (a.bf16) hipLaunchKernelGGL(gemm_wgrad_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
     else hipLaunchKernelGGL(gemm_wgrad_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
     hipError_t e = hipGetLastError();
@@ -645,6 +705,23 @@ hipError_t launch_input_proj(const float* u, int64_t M, const float* w_in, const
     hipLaunchKernelGGL(input_proj_kernel, dim3(nblk(M * kC)), dim3(256), 0, st, u, M, w_in, b_in, x0);
     return hipGetLastError();
 }
+hipError_t launch_gate_bwd16(const float* pre, const float* dg, int64_t M, uint16_t* g, uint16_t* dpre, hipStream_t st) {
+    hipLaunchKernelGGL(gate_bwd16_kernel, dim3((unsigned)((M * kC + 255) / 256)), dim3(256), 0, st, pre, dg, M, g, dpre);
+    return hipGetLastError();
+}
+
+hipError_t colsum16(const uint16_t* X, int64_t ldx, int64_t M, int N, float* part, int64_t part_capacity, float* dst,
+                    int64_t dst_stride, hipStream_t st) {
+    if (N < 4 || N % 4 || N > 1024 || ldx % 4 || ((uintptr_t)X & 7) || part_capacity < N) return hipErrorInvalidValue;
+    int64_t rpc = 512;
+    while (((M + rpc - 1) / rpc) * (int64_t)N > part_capacity) rpc *= 2;
+    const int nchunks = (int)((M + rpc - 1) / rpc);
+    hipLaunchKernelGGL(colsum16_kernel, dim3(nchunks), dim3(256), 0, st, X, ldx, M, N, rpc, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return reduce_parts(part, part_capacity, nchunks, N, dst, dst_stride, st);
+}
+
 hipError_t launch_gate_bwd(const float* pre, const float* dg, int64_t M, float* g, float* dpre, hipStream_t st) {
     hipLaunchKernelGGL(gate_bwd_kernel, dim3(nblk(M * kC)), dim3(256), 0, st, pre, dg, M, g, dpre);
     return hipGetLastError();
