@@ -600,13 +600,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
     }
     // the biases of the layers, once per block (requested after the first rows and
     // weights, so the latencies overlap): [layer][conv 256 | res 128 | skip 128]
-    for (int idx = tid; idx < NL * 4 * kC; idx += 256) {
-        const int j = idx / (4 * kC), e = idx % (4 * kC);
-        float v;
-        if (e < 2 * kC) v = p.bc[j][e];
-        else if (LAST && j == NL - 1) v = e < 3 * kC ? 0.f : p.brs[j][e - 3 * kC];  // skip columns only
-        else v = p.brs[j][e - 2 * kC];
-        BI[idx] = v;
+    for (int idx = tid; idx < NL * kC; idx += 256) {  // four floats per thread and step
+        const int j = idx / kC, e = 4 * (idx % kC);
+        float4 v;
+        if (e < 2 * kC) v = *(const float4*)(p.bc[j] + e);
+        else if (LAST && j == NL - 1)  // skip columns only
+            v = e < 3 * kC ? make_float4(0.f, 0.f, 0.f, 0.f) : *(const float4*)(p.brs[j] + e - 3 * kC);
+        else v = *(const float4*)(p.brs[j] + e - 2 * kC);
+        *(float4*)(BI + 4 * idx) = v;
     }
     for (int c = (seg > 0 ? c0 - 1 : c0); c < c1; ++c) {
         const bool store = c >= c0;
