@@ -20,4 +20,6 @@ Modules
   quant     bfloat16 and FP8-E4M3 quantisers written from the formats
   background  time-slid copies of a two-channel stream and the false-alarm
             count per threshold ("Statistical Analysis")
+  postproc  the paper's peak finding (SciPy find_peaks: height, width >= 0.5 s)
+            and all-member coincidence within 0.5 s
 """
