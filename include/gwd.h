@@ -227,6 +227,44 @@ gwd_status gwd_time_slide(const gwd_stream* src, const int64_t* shifts, int32_t 
 gwd_status gwd_far_curve(const gwd_trigger* trig, int64_t n, const double* thresholds, int32_t n_thr,
                          double livetime_s, int64_t* counts, double* far_per_s);
 
+/* ---- the paper's post-processing ("AI ensemble construction", "Statistical Analysis",
+ * "Event Detection") ---------------------------------------------------------
+ * The paper locates mergers with SciPy's find_peaks on each model's output,
+ * keeps peaks at least 0.5 s wide above a height threshold, and flags an event
+ * when all models report it within 0.5 s.
+ *
+ * gwd_prob64 writes p[i] = 1 / (1 + e^-z[i]) in float64 for float32 logits z
+ * (device arrays of n elements); asynchronous on hip_stream.
+ *
+ * gwd_find_peaks finds the peaks of a float64 device signal x[0, n) with the
+ * semantics of scipy.signal.find_peaks(x, height=height, width=min_width):
+ *   - a peak is a sample, or the middle (rounded down) of a run of equal
+ *     samples, with a strictly lower neighbour on each side; the first and
+ *     last samples are never peaks; x[peak] >= height;
+ *   - prominence: the peak's height above the higher of the lowest points
+ *     reached walking left and right up to a strictly higher sample (or the
+ *     end), which are also the bases;
+ *   - width: between the crossings of the level x[peak] - prominence / 2
+ *     inside the bases, linearly interpolated, in samples; kept if >= min_width.
+ * Peak indices (ascending) and widths go to host arrays `peaks` and `widths`;
+ * *n_found receives the true count, and if it exceeds `capacity` the first
+ * `capacity` are written and GWD_ERR_CAPACITY is returned. NaN or Inf in x
+ * gives GWD_ERR_NONFINITE. n < 3 finds nothing (no device work). The
+ * prominence and width arithmetic is float64 in the order above, so results
+ * equal SciPy's exactly. Synchronises hip_stream before returning.
+ *
+ * gwd_coincidence (host memory, no device work): peak_lists[m] holds counts[m]
+ * ascending peak indices of member m; a peak t of member 0 is an event when
+ * every other member has a peak within |t' - t| <= window. Events (ascending)
+ * go to `events`, up to `capacity` (GWD_ERR_CAPACITY beyond, *n_events gets the
+ * true count). GWD_ERR_ARG for NULL pointers, n_members < 1, negative counts
+ * or window. */
+gwd_status gwd_prob64(const float* z, int64_t n, double* p, void* hip_stream);
+gwd_status gwd_find_peaks(const double* x, int64_t n, double height, double min_width, int64_t* peaks,
+                          double* widths, int64_t capacity, int64_t* n_found, void* hip_stream);
+gwd_status gwd_coincidence(const int64_t* const* peak_lists, const int64_t* counts, int32_t n_members,
+                           int64_t window, int64_t* events, int64_t capacity, int64_t* n_events);
+
 /* ---- training (one member; "AI ensemble construction") ---------------------
  * windows: device [B][W][2] float32 (interleaved channels). Element type T of
  * logits, grad_logit, grad_params and grad_input is float, or double for a

@@ -80,6 +80,9 @@ def _load(path: str = LIB_PATH):
         "gwd_triggers": (I32, [P, P, I32, D, I32, ctypes.POINTER(Trigger), I64, ctypes.POINTER(I64), P]),
         "gwd_time_slide": (I32, [ctypes.POINTER(Stream), P, I32, P, P]),
         "gwd_far_curve": (I32, [ctypes.POINTER(Trigger), I64, P, I32, D, P, P]),
+        "gwd_prob64": (I32, [P, I64, P, P]),
+        "gwd_find_peaks": (I32, [P, I64, D, D, P, P, I64, ctypes.POINTER(I64), P]),
+        "gwd_coincidence": (I32, [P, P, I32, I64, P, I64, ctypes.POINTER(I64)]),
         "gwd_saved_bytes": (I64, [P, I32, I32]),
         "gwd_forward_train": (I32, [P, I32, P, I32, I32, P, P, P]),
         "gwd_backward": (I32, [P, I32, P, I32, I32, P, P, P, P, P]),
@@ -410,3 +413,37 @@ def far_curve(records: Sequence[Tuple[int, int, float, float]], logit_thresholds
     check(lib.gwd_far_curve(buf, n, thr.ctypes.data, int(thr.size), float(livetime_s), counts.ctypes.data,
                             far.ctypes.data))
     return counts, far
+
+
+def prob64(z, out=None, stream=None):
+    """gwd_prob64: float64 probabilities 1 / (1 + e^-z) of a float32 device logit tensor."""
+    import torch
+    z = z.contiguous()
+    if out is None:
+        out = torch.empty(z.shape, dtype=torch.float64, device=z.device)
+    check(lib.gwd_prob64(_ptr(z), z.numel(), _ptr(out), _stream_handle(stream)))
+    return out
+
+
+def find_peaks(x, height: float, min_width: float, capacity: Optional[int] = None, stream=None):
+    """gwd_find_peaks on a float64 device signal: (peak indices int64, widths float64) as numpy arrays."""
+    n = x.numel()
+    cap = (n // 2 + 1) if capacity is None else int(capacity)
+    peaks = np.empty(max(cap, 1), dtype=np.int64)
+    widths = np.empty(max(cap, 1), dtype=np.float64)
+    nf = ctypes.c_int64(0)
+    check(lib.gwd_find_peaks(_ptr(x), n, float(height), float(min_width), peaks.ctypes.data, widths.ctypes.data, cap,
+                             ctypes.byref(nf), _stream_handle(stream)))
+    return peaks[:nf.value].copy(), widths[:nf.value].copy()
+
+
+def coincidence(peak_lists: Sequence, window: int) -> List[int]:
+    """gwd_coincidence: peaks of member 0 matched by every other member within +/- window samples."""
+    arrs = [np.ascontiguousarray(np.asarray(p, dtype=np.int64)) for p in peak_lists]
+    ptrs = (ctypes.c_void_p * max(len(arrs), 1))(*[a.ctypes.data for a in arrs])
+    counts = np.array([a.size for a in arrs], dtype=np.int64)
+    cap = int(arrs[0].size) if arrs else 0
+    ev = np.empty(max(cap, 1), dtype=np.int64)
+    nf = ctypes.c_int64(0)
+    check(lib.gwd_coincidence(ptrs, counts.ctypes.data, len(arrs), int(window), ev.ctypes.data, cap, ctypes.byref(nf)))
+    return [int(v) for v in ev[:nf.value]]

@@ -187,3 +187,30 @@ def test_far_curve_matches_oracle(g):
             g.far_curve(recs, thr, **bad)
     assert g.lib.gwd_far_curve(None, 3, thr.ctypes.data, 1, 1.0, np.zeros(1, np.int64).ctypes.data,
                                np.zeros(1).ctypes.data) == g.ERR_ARG
+
+
+def test_coincidence_matches_oracle(g):
+    from oracle.postproc import coincident_events
+    rng = np.random.default_rng(8)
+    for _ in range(40):
+        lists = [np.sort(rng.choice(50000, int(rng.integers(0, 40)), replace=False)) for _ in range(int(rng.integers(1, 5)))]
+        wnd = int(rng.integers(0, 4000))
+        assert g.coincidence(lists, wnd) == coincident_events(lists, wnd)
+
+
+def test_postproc_argument_errors(g):
+    nf = ctypes.c_int64(-1)
+    out = np.zeros(4, np.int64)
+    assert g.lib.gwd_coincidence(None, None, 1, 10, None, 0, ctypes.byref(nf)) == g.ERR_ARG
+    cnt = np.array([1], np.int64)
+    lst = (ctypes.c_void_p * 1)(out.ctypes.data)
+    assert g.lib.gwd_coincidence(lst, cnt.ctypes.data, 1, -1, out.ctypes.data, 4, ctypes.byref(nf)) == g.ERR_ARG
+    assert g.lib.gwd_coincidence(lst, cnt.ctypes.data, 0, 10, out.ctypes.data, 4, ctypes.byref(nf)) == g.ERR_ARG
+    pk, wd = np.zeros(4, np.int64), np.zeros(4)
+    assert g.lib.gwd_find_peaks(8, 2, 0.5, 1.0, pk.ctypes.data, wd.ctypes.data, 4, ctypes.byref(nf), None) == g.OK
+    assert nf.value == 0                                  # fewer than 3 samples: nothing, no device needed
+    assert g.lib.gwd_find_peaks(8, 100, float("nan"), 1.0, pk.ctypes.data, wd.ctypes.data, 4, ctypes.byref(nf), None) == g.ERR_ARG
+    assert g.lib.gwd_find_peaks(12, 100, 0.5, 1.0, pk.ctypes.data, wd.ctypes.data, 4, ctypes.byref(nf), None) == g.ERR_ARG  # misaligned
+    assert g.lib.gwd_find_peaks(8, 100, 0.5, 1.0, None, None, 4, ctypes.byref(nf), None) == g.ERR_ARG
+    assert g.lib.gwd_prob64(None, 10, None, None) == g.ERR_ARG
+    assert g.lib.gwd_prob64(None, 0, None, None) == g.OK
