@@ -247,6 +247,39 @@ def background_workload(gwd, blobs, x, prec: str, seconds: float = 900.0, n_slid
             "note": "random-weight members: the rates show the mechanism, not a trained model's background"}
 
 
+def postproc_workload(gwd, blobs, x, prec: str, seconds: float = 900.0, height: float = 0.9,
+                      width_s: float = 0.5):
+    """The paper's post-processing: each member's stitched logits (one forward call, out_mode 1) to
+    float64 probabilities, peaks of height >= 0.9 and width >= 0.5 s per member, and the events all
+    members report within 0.5 s. Timed apart from the forward."""
+    import torch
+    xs = x[: int(round(seconds * FS))]
+    L = xs.shape[0]
+    M = blobs.shape[0]
+    m = gwd.Model(gwd.full_arch(), blobs, prec)
+    out = m.forward([xs], W, S, out_mode=1)
+    torch.cuda.synchronize()
+    p = torch.empty(L, dtype=torch.float64, device="cuda")
+    gwd.find_peaks(gwd.prob64(out[L: 2 * L], out=p), height, width_s * FS)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lists = []
+    for k in range(M):
+        gwd.prob64(out[(k + 1) * L: (k + 2) * L], out=p)
+        lists.append(gwd.find_peaks(p, height, width_s * FS)[0])
+    events = gwd.coincidence(lists, int(width_s * FS))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # context, untimed: member 0's peaks above the height at any width (random-weight members give
+    # narrow peaks, so few or none reach 0.5 s)
+    any_width = len(gwd.find_peaks(gwd.prob64(out[L: 2 * L], out=p), height, 0.0)[0])
+    m.close()
+    return {"slice_s": round(L / FS, 1), "members": M, "height": height, "min_width_s": width_s,
+            "peaks_per_member": [int(len(q)) for q in lists], "member0_peaks_any_width": any_width,
+            "coincident_events": len(events),
+            "postproc_s": round(wall, 4), "strain_s_per_s": round(L / FS / wall, 1), "precision": prec}
+
+
 def train_workload(gwd, steps: int = 2, B: int = 256):
     """Training of one full-size member: BF16 forward with per-stack checkpoints, BCE on logits,
     hand-written backward (bf16-operand row and weight-gradient GEMMs, fp32 accumulation), Adam on fp32 master
@@ -317,6 +350,7 @@ def main():
     ap.add_argument("--no-train", action="store_true", help="skip the training-throughput measurement")
     ap.add_argument("--no-streaming", action="store_true", help="skip the long-window (streaming) line")
     ap.add_argument("--no-background", action="store_true", help="skip the time-slide background line")
+    ap.add_argument("--no-postproc", action="store_true", help="skip the peak-finding post-processing line")
     ap.add_argument("--stream-day", action=argparse.BooleanOptionalAction, default=True,
                     help="also run the streaming line over a full day (86400 s) of strain")
     ap.add_argument("--calib-copy", action="store_true",
@@ -393,6 +427,11 @@ def main():
         progress("time-slide background")
         background = background_workload(gwd, blobs, x, args.precision, min(900.0, args.seconds))
         progress(f"background: {background['strain_s_per_s']} strain-s/s over {background['background_s']} s")
+    postproc = None
+    if not args.no_postproc:
+        progress("post-processing: peaks and coincidence")
+        postproc = postproc_workload(gwd, blobs, x, args.precision, min(900.0, args.seconds))
+        progress(f"post-processing: {postproc['strain_s_per_s']} strain-s/s")
     train = None
     if not args.no_train:
         progress("training throughput")
@@ -416,7 +455,8 @@ def main():
         "cpu_baseline": cpu,
         "detail": {"triggers": main_r["triggers"], "tflops_step": round(main_r["tflops"], 2),
                    "ms_events": round(main_r["ms_events"], 3), "precisions": extra,
-                   "ragged_streams": ragged, "time_slide_background": background, "training": train,
+                   "ragged_streams": ragged, "time_slide_background": background, "postprocessing": postproc,
+                   "training": train,
                    "streaming_variant": streaming},
     }
     print(json.dumps(line), flush=True)

@@ -2,7 +2,8 @@
 // Analysis", "Event Detection"): peak finding with a height threshold and a minimum width at half
 // prominence (the semantics of SciPy's find_peaks), and all-member coincidence.
 //
-// Device steps over a float64 signal x[0, n):
+// Device steps over a float64 signal x[0, n) (with block summaries so that walks across long
+// stretches take whole blocks):
 //   1. flags: sample i is the rising edge of a qualifying peak (x[i-1] < x[i], the run of samples
 //      equal to x[i] ends below it before the last sample, and x >= height); one thread per i, the
 //      rising-edge thread scans the run;
@@ -102,28 +103,117 @@ __global__ __launch_bounds__(256) void pk_scatter_kernel(const double* x, int64_
     }
 }
 
+// Block summaries for the walks: for each block of PK_B1 samples (level 1) and of PK_B1 * PK_B1
+// samples (level 2), the maximum, the minimum, and the first and last index holding the minimum.
+constexpr int PK_B1 = 256;
+constexpr int64_t PK_B2 = (int64_t)PK_B1 * PK_B1;
+struct PkSum {
+    double mx, mn;
+    int64_t first, last;
+};
+
+__device__ inline PkSum pk_merge(PkSum a, PkSum b) {  // a covers lower indices than b
+    PkSum r;
+    r.mx = a.mx > b.mx ? a.mx : b.mx;
+    if (a.mn < b.mn) { r.mn = a.mn; r.first = a.first; r.last = a.last; }
+    else if (b.mn < a.mn) { r.mn = b.mn; r.first = b.first; r.last = b.last; }
+    else { r.mn = a.mn; r.first = a.first; r.last = b.last; }
+    return r;
+}
+
+__device__ inline PkSum pk_shfl_down(PkSum v, int o) {
+    PkSum r;
+    r.mx = __shfl_down(v.mx, o);
+    r.mn = __shfl_down(v.mn, o);
+    r.first = __shfl_down(v.first, o);
+    r.last = __shfl_down(v.last, o);
+    return r;
+}
+
+// level 1 from x (src == nullptr) or level 2 from level 1: one block per output summary; block g
+// covers inputs [g * PK_B1, (g + 1) * PK_B1) of the level below (only those below n_in)
+__global__ __launch_bounds__(256) void pk_sum_kernel(const double* x, const PkSum* src, int64_t n_in, PkSum* dst) {
+    __shared__ PkSum part[4];
+    const int64_t k = (int64_t)blockIdx.x * PK_B1 + threadIdx.x;
+    PkSum v;
+    if (k < n_in) {
+        if (src) v = src[k];
+        else { v.mx = x[k]; v.mn = x[k]; v.first = k; v.last = k; }
+    } else {
+        v.mx = -INFINITY; v.mn = INFINITY; v.first = INT64_MAX; v.last = -1;
+    }
+    for (int o = 1; o < 64; o <<= 1) {  // lane l merges l + o (lower lanes cover lower indices)
+        const PkSum w = pk_shfl_down(v, o);
+        if ((threadIdx.x & 63) + o < 64 && ((threadIdx.x & 63) & (2 * o - 1)) == 0) v = pk_merge(v, w);
+    }
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) dst[blockIdx.x] = pk_merge(pk_merge(part[0], part[1]), pk_merge(part[2], part[3]));
+}
+
 // prominence bases and the width at half prominence of each peak (float64, the order of the
-// definition)
+// definition). The walks step over whole blocks that cannot stop them: a block whose maximum does
+// not exceed the peak (prominence walks, which take the block's minimum, nearest occurrence first)
+// or whose minimum lies above the level and which sits inside the bases (width walks).
 __global__ __launch_bounds__(256) void pk_width_kernel(const double* x, int64_t n, const int64_t* cand, int64_t k,
-                                                       double* width) {
+                                                       const PkSum* s1, const PkSum* s2, double* width) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= k) return;
     const int64_t p = cand[c];
     const double xp = x[p];
-    double lmin = xp, rmin = xp;
-    int64_t lb = p, rb = p;
-    for (int64_t j = p; j >= 0 && x[j] <= xp; --j)
-        if (x[j] < lmin) { lmin = x[j]; lb = j; }
-    for (int64_t j = p; j <= n - 1 && x[j] <= xp; ++j)
-        if (x[j] < rmin) { rmin = x[j]; rb = j; }
+    // left walk to the first strictly higher sample: the minimum nearest to the peak wins ties
+    double lmin = xp;
+    int64_t lb = p, j = p;
+    while (j >= 0) {
+        if (j % PK_B2 == PK_B2 - 1 && s2[j / PK_B2].mx <= xp) {
+            const PkSum& b2 = s2[j / PK_B2];
+            if (b2.mn < lmin) { lmin = b2.mn; lb = b2.last; }
+            j -= PK_B2;
+        } else if (j % PK_B1 == PK_B1 - 1 && s1[j / PK_B1].mx <= xp) {
+            const PkSum& b1 = s1[j / PK_B1];
+            if (b1.mn < lmin) { lmin = b1.mn; lb = b1.last; }
+            j -= PK_B1;
+        } else {
+            if (x[j] > xp) break;
+            if (x[j] < lmin) { lmin = x[j]; lb = j; }
+            --j;
+        }
+    }
+    double rmin = xp;
+    int64_t rb = p;
+    j = p;
+    while (j <= n - 1) {
+        if (j % PK_B2 == 0 && j + PK_B2 - 1 <= n - 1 && s2[j / PK_B2].mx <= xp) {
+            const PkSum& b2 = s2[j / PK_B2];
+            if (b2.mn < rmin) { rmin = b2.mn; rb = b2.first; }
+            j += PK_B2;
+        } else if (j % PK_B1 == 0 && j + PK_B1 - 1 <= n - 1 && s1[j / PK_B1].mx <= xp) {
+            const PkSum& b1 = s1[j / PK_B1];
+            if (b1.mn < rmin) { rmin = b1.mn; rb = b1.first; }
+            j += PK_B1;
+        } else {
+            if (x[j] > xp) break;
+            if (x[j] < rmin) { rmin = x[j]; rb = j; }
+            ++j;
+        }
+    }
     const double prom = xp - (lmin > rmin ? lmin : rmin);
     const double level = xp - prom * 0.5;
+    // width walks: step down while above the level, strictly inside the bases
     int64_t i = p;
-    while (lb < i && level < x[i]) --i;
+    while (lb < i && level < x[i]) {
+        if (i % PK_B2 == PK_B2 - 1 && i - PK_B2 >= lb && s2[i / PK_B2].mn > level) i -= PK_B2;
+        else if (i % PK_B1 == PK_B1 - 1 && i - PK_B1 >= lb && s1[i / PK_B1].mn > level) i -= PK_B1;
+        else --i;
+    }
     double left = (double)i;
     if (x[i] < level) left += (level - x[i]) / (x[i + 1] - x[i]);
     i = p;
-    while (i < rb && level < x[i]) ++i;
+    while (i < rb && level < x[i]) {
+        if (i % PK_B2 == 0 && i + PK_B2 <= rb && s2[i / PK_B2].mn > level) i += PK_B2;
+        else if (i % PK_B1 == 0 && i + PK_B1 <= rb && s1[i / PK_B1].mn > level) i += PK_B1;
+        else ++i;
+    }
     double right = (double)i;
     if (x[i] < level) right -= (level - x[i]) / (x[i - 1] - x[i]);
     width[c] = right - left;
@@ -181,7 +271,10 @@ gwd_status gwd_find_peaks(const double* x, int64_t n, double height, double min_
     const int64_t off_cnt = (n + 15) / 16 * 16;
     const int64_t off_cand = off_cnt + (nt + 1) * 8;
     const int64_t off_w = off_cand + kmax * 8;
-    const int64_t off_err = off_w + kmax * 8;
+    const int64_t n1 = (n + PK_B1 - 1) / PK_B1, n2 = (n1 + PK_B1 - 1) / PK_B1;
+    const int64_t off_s1 = off_w + kmax * 8;
+    const int64_t off_s2 = off_s1 + n1 * (int64_t)sizeof(PkSum);
+    const int64_t off_err = off_s2 + n2 * (int64_t)sizeof(PkSum);
     const int64_t need = off_err + 16;
     std::lock_guard<std::mutex> lock(g_pk.mu);
     if (g_pk.bytes < need || g_pk.device != dev) {
@@ -201,6 +294,8 @@ gwd_status gwd_find_peaks(const double* x, int64_t n, double height, double min_
     int64_t* counts = (int64_t*)(b + off_cnt);
     int64_t* cand = (int64_t*)(b + off_cand);
     double* wd = (double*)(b + off_w);
+    PkSum* s1 = (PkSum*)(b + off_s1);
+    PkSum* s2 = (PkSum*)(b + off_s2);
     int* err = (int*)(b + off_err);
     e = hipMemsetAsync(err, 0, sizeof(int), st);
     if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
@@ -219,7 +314,9 @@ gwd_status gwd_find_peaks(const double* x, int64_t n, double height, double min_
     if (e != hipSuccess) return hip_fail(e, "peak count copy");
     if (bad) { set_error("gwd_find_peaks: NaN or Inf in the signal"); return GWD_ERR_NONFINITE; }
     if (k == 0) return GWD_OK;
-    hipLaunchKernelGGL(pk_width_kernel, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, st, x, n, cand, k, wd);
+    hipLaunchKernelGGL(pk_sum_kernel, dim3((unsigned)n1), dim3(256), 0, st, x, (const PkSum*)nullptr, n, s1);
+    hipLaunchKernelGGL(pk_sum_kernel, dim3((unsigned)n2), dim3(256), 0, st, (const double*)nullptr, s1, n1, s2);
+    hipLaunchKernelGGL(pk_width_kernel, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, st, x, n, cand, k, s1, s2, wd);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "width kernel launch");
     std::vector<int64_t> hc((size_t)k);
