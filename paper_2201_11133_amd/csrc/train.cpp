@@ -222,7 +222,13 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
                 a.B = G; a.ldb = kC; a.N = kC; a.M = M; a.T = T; a.rows_per_chunk = RPC; a.part = PART; a.part_capacity = PART_CAP; a.bf16 = BT != nullptr;
                 a.B16 = G16;
                 HIPCHK(gemm_wgrad(a, grad + v.skip_w[l], 0, st), "d skip.W");
-                HIPCHK(colsum(DS, kC, M, kC, nullptr, 0, 0, PART, PART_CAP, grad + v.skip_b[l], 1, st), "d skip.b");
+                // dskip is the same for every layer, and so is its column sum: computed once (for the
+                // last layer, the first one here), then copied (the gradient starts at zero)
+                if (l == L - 1)
+                    HIPCHK(colsum(DS, kC, M, kC, nullptr, 0, 0, PART, PART_CAP, grad + v.skip_b[l], 1, st), "d skip.b");
+                else
+                    HIPCHK(hipMemcpyAsync(grad + v.skip_b[l], grad + v.skip_b[L - 1], kC * sizeof(float),
+                                          hipMemcpyDeviceToDevice, st), "d skip.b");
                 if (!last) {
                     a.A[0] = APart{DX, kC, 0, kC};
                     HIPCHK(gemm_wgrad(a, grad + v.res_w[l], 0, st), "d res.W");
