@@ -171,6 +171,10 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
         HIPCHK(gemm_rows(g, st), "dskip");
     }
     HIPCHK(launch_fill(DX, M * kC, 0.f, st), "zero dx");
+    // BF16/FP8 members: dskip rounded to bf16 once, in R (free after the head); its GEMMs would
+    // round it on every read
+    uint16_t* DS16 = BT ? (uint16_t*)R : nullptr;
+    if (BT) HIPCHK(launch_f32_to_bf16(DS, M * kC, DS16, st), "dskip bf16");
     // ---- stacks, last to first
     for (int sidx = m->arch.n_stacks - 1; sidx >= 0; --sidx) {
         // recompute the stack, keeping each layer's input and pre-activation
@@ -199,7 +203,7 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
             const float* pre = fptr(b, f_pre + (int64_t)i * M * 2 * kC);
             // dg = dskip W_s + dx' W_r
             GemmRowsArgs g{};
-            g.A[0] = APart{DS, kC, 0, kC};
+            g.A[0] = APart{DS, kC, 0, kC, DS16};
             g.B[0] = BPart{w + v.skip_w[l], kC, 1};
             g.nparts = 1;
             if (!last) {
@@ -209,7 +213,7 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
             }
             g.M = M; g.N = kC; g.T = T; g.C = DG; g.ldc = kC;
             g.bt = BT;
-        HIPCHK(gemm_rows(g, st), "dg");
+            HIPCHK(gemm_rows(g, st), "dg");
             // BF16/FP8 members: g and dpre in bf16 (the GEMMs that read them round to bf16 anyway)
             uint16_t* G16 = BT ? (uint16_t*)G : nullptr;
             uint16_t* DPRE16 = BT ? (uint16_t*)DPRE : nullptr;
@@ -218,7 +222,7 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
             // skip / residual weight gradients
             {
                 WgradArgs a{};
-                a.A[0] = APart{DS, kC, 0, kC}; a.nparts = 1; a.Ktot = kC;
+                a.A[0] = APart{DS, kC, 0, kC, DS16}; a.nparts = 1; a.Ktot = kC;
                 a.B = G; a.ldb = kC; a.N = kC; a.M = M; a.T = T; a.rows_per_chunk = RPC; a.part = PART; a.part_capacity = PART_CAP; a.bf16 = BT != nullptr;
                 a.B16 = G16;
                 HIPCHK(gemm_wgrad(a, grad + v.skip_w[l], 0, st), "d skip.W");
