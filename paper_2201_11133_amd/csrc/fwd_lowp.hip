@@ -357,7 +357,7 @@ void layer_lp_kernel(LayerArgsLP p) {
             const int mb = 32 * RB * rh + 32 * rb + 4 * h;  // first row of this lane in the block
             const uint8_t* xr = FP8 ? &XR[mb * T::XROW + 2 * n] : &A[mb * T::ROW + 2 * (kC + n)];
             residual_out<FP8, RB, WV>(acc[0][rb], xr, p.x_out + (row0 + mb) * kC + n, br, s_r);
-            skip_out<FP8, SKIP_INIT>(acc[1][rb], p.skip + (row0 + mb) * kC + n, bs, s_s);
+            if (p.skip) skip_out<FP8, SKIP_INIT>(acc[1][rb], p.skip + (row0 + mb) * kC + n, bs, s_s);
             __builtin_amdgcn_sched_barrier(0);
         }
         return;
@@ -383,7 +383,7 @@ void layer_lp_kernel(LayerArgsLP p) {
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
             const int mb = 32 * RB * rh + 32 * rb + 4 * h;
-            skip_out<FP8, SKIP_INIT>(acc[0][rb], p.skip + (row0 + mb) * kC + n, bs, s_s);
+            if (p.skip) skip_out<FP8, SKIP_INIT>(acc[0][rb], p.skip + (row0 + mb) * kC + n, bs, s_s);
         }
     }
 }

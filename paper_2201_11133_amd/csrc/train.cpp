@@ -188,9 +188,9 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
             // the stack's last output and the recomputed skip sum are not needed: scratch buffers
             float* xnext = (i + 1 < LPS) ? fptr(b, f_xs + (int64_t)(i + 1) * M * kC) : G;
             float* pre_i = fptr(b, f_pre + (int64_t)i * M * 2 * kC);
-            if (BT)
+            if (BT)  // (no skip sum: the recompute needs layer inputs and pre-activations only)
                 HIPCHK(launch_layer_train_bf16io(m, member, l, (const uint16_t*)xs_i, B, T, pre_i,
-                                                 (l < L - 1) ? (uint16_t*)xnext : nullptr, SKS, st), "recompute");
+                                                 (l < L - 1) ? (uint16_t*)xnext : nullptr, nullptr, st), "recompute");
             else
                 HIPCHK(launch_layer_debug(m, member, l, xs_i, B, T, pre_i, (l < L - 1) ? xnext : nullptr, SKS, st),
                        "recompute");
