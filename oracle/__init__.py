@@ -22,4 +22,6 @@ Modules
             count per threshold ("Statistical Analysis")
   postproc  the paper's peak finding (SciPy find_peaks: height, width >= 0.5 s)
             and all-member coincidence within 0.5 s
+  whiten    the front end ("Data preparation"): Welch PSD, whitening of the
+            stream by it, unit standard deviation
 """

@@ -129,6 +129,24 @@ def noise_stream(rng: np.random.Generator, L: int, dtype=np.float32) -> np.ndarr
     return rng.standard_normal((L, 2), dtype=np.float32 if dtype == np.float32 else np.float64).astype(dtype, copy=False)
 
 
+def coloured_stream(seed: int, L: int, scale: float = 1.0, dtype=np.float32) -> np.ndarray:
+    """Two-channel coloured noise [L, 2], a stand-in for unwhitened detector strain: per channel a
+    red component (white noise through a one-pole low-pass, pole 0.99, gain 0.1), a white floor of
+    unit variance, and power-line-like sinusoids (channel 0: 60 Hz amplitude 3 and 120 Hz amplitude
+    1; channel 1: 60 Hz amplitude 2 and 180 Hz amplitude 1) with random phases, all times `scale`."""
+    from scipy.signal import lfilter
+    rng = np.random.default_rng(seed)
+    t = np.arange(L, dtype=np.float64) / FS
+    lines = (((60.0, 3.0), (120.0, 1.0)), ((60.0, 2.0), (180.0, 1.0)))
+    x = np.empty((L, 2), dtype=np.float64)
+    for c in range(2):
+        red = lfilter([0.1], [1.0, -0.99], rng.standard_normal(L))
+        x[:, c] = red + rng.standard_normal(L)
+        for f, a in lines[c]:
+            x[:, c] += a * np.cos(2.0 * np.pi * f * t + rng.uniform(0.0, 2.0 * np.pi))
+    return (x * scale).astype(dtype)
+
+
 def make_stream(seed: int, seconds: float, n_chirps: int, spacing: float = 10.0, margin: float = 4.0,
                 dtype=np.float32) -> Tuple[np.ndarray, List[Injection]]:
     """One two-channel stream [L, 2] of white noise with n_chirps leading-order chirps."""
