@@ -280,6 +280,45 @@ def postproc_workload(gwd, blobs, x, prec: str, seconds: float = 900.0, height: 
             "postproc_s": round(wall, 4), "strain_s_per_s": round(L / FS / wall, 1), "precision": prec}
 
 
+def whitening_workload(gwd, seconds: float = 4096.0, nperseg: int = 16384, reps: int = 5):
+    """The front end before the networks ("Data preparation"): the Welch PSD of a coloured
+    two-channel stream (4 s Hann segments, half overlap) and the whitening of the whole stream by it,
+    scaled to unit deviation. The paper's data segments are 4096 s at 4096 Hz: 2^24 samples per
+    detector. Algorithmic HBM bytes per time step: 8 read by the PSD, 8 read and 8 written by the
+    whitening (both channels, fp32), 24 in all."""
+    import torch
+    from paper_2201_11133_amd import synth
+    L = int(round(seconds * FS))
+    x = torch.from_numpy(synth.coloured_stream(2024, L)).cuda()
+    psd = torch.empty((2, nperseg // 2 + 1), dtype=torch.float64, device="cuda")
+    y = torch.empty((L, 2), dtype=torch.float32, device="cuda")
+    gwd.whiten(x, gwd.welch_psd(x, nperseg, FS, out=psd), nperseg, FS, True, out=y)   # warm-up (workspace)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    t_psd, t_wh = [], []
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ev[0].record()
+        gwd.welch_psd(x, nperseg, FS, out=psd)
+        ev[1].record()
+        gwd.whiten(x, psd, nperseg, FS, True, out=y)
+        ev[2].record()
+        ev[2].synchronize()
+        t_psd.append(ev[0].elapsed_time(ev[1]))
+        t_wh.append(ev[1].elapsed_time(ev[2]))
+    wall = (time.perf_counter() - t0) / reps
+    ms_psd, ms_wh = float(np.median(t_psd)), float(np.median(t_wh))
+    gbs = 24.0 * L / ((ms_psd + ms_wh) * 1e-3) / 1e9
+    sd = [round(float(v), 6) for v in torch.std(y, dim=0, unbiased=False).tolist()]
+    del x, y
+    return {"stream_s": seconds, "samples_per_channel": L, "nperseg": nperseg,
+            "ms_psd": round(ms_psd, 3), "ms_whiten": round(ms_wh, 3), "ms_wall": round(wall * 1e3, 3),
+            "strain_s_per_s": round(seconds / wall, 1),
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s",
+                         "frac": round(gbs / 8000.0, 4), "algorithmic_bytes_per_step": 24},
+            "output_std": sd}
+
+
 def train_workload(gwd, steps: int = 2, B: int = 256):
     """Training of one full-size member: BF16 forward with per-stack checkpoints, BCE on logits,
     hand-written backward (bf16-operand row and weight-gradient GEMMs, fp32 accumulation), Adam on fp32 master
@@ -351,6 +390,7 @@ def main():
     ap.add_argument("--no-streaming", action="store_true", help="skip the long-window (streaming) line")
     ap.add_argument("--no-background", action="store_true", help="skip the time-slide background line")
     ap.add_argument("--no-postproc", action="store_true", help="skip the peak-finding post-processing line")
+    ap.add_argument("--no-whiten", action="store_true", help="skip the whitening front-end line")
     ap.add_argument("--stream-day", action=argparse.BooleanOptionalAction, default=True,
                     help="also run the streaming line over a full day (86400 s) of strain")
     ap.add_argument("--calib-copy", action="store_true",
@@ -432,6 +472,11 @@ def main():
         progress("post-processing: peaks and coincidence")
         postproc = postproc_workload(gwd, blobs, x, args.precision, min(900.0, args.seconds))
         progress(f"post-processing: {postproc['strain_s_per_s']} strain-s/s")
+    whitening = None
+    if not args.no_whiten:
+        progress("whitening front end: Welch PSD and whitening of a 4096 s stream")
+        whitening = whitening_workload(gwd)
+        progress(f"whitening: {whitening['strain_s_per_s']} strain-s/s")
     train = None
     if not args.no_train:
         progress("training throughput")
@@ -456,7 +501,7 @@ def main():
         "detail": {"triggers": main_r["triggers"], "tflops_step": round(main_r["tflops"], 2),
                    "ms_events": round(main_r["ms_events"], 3), "precisions": extra,
                    "ragged_streams": ragged, "time_slide_background": background, "postprocessing": postproc,
-                   "training": train,
+                   "whitening_front_end": whitening, "training": train,
                    "streaming_variant": streaming},
     }
     print(json.dumps(line), flush=True)

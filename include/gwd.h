@@ -265,6 +265,46 @@ gwd_status gwd_find_peaks(const double* x, int64_t n, double height, double min_
 gwd_status gwd_coincidence(const int64_t* const* peak_lists, const int64_t* counts, int32_t n_members,
                            int64_t window, int64_t* events, int64_t capacity, int64_t* n_events);
 
+/* ---- whitening front end ("Data preparation") -------------------------------
+ * Before the networks see strain, the paper estimates the detector noise's
+ * power spectral density (PSD), whitens the strain with it and scales the
+ * network input to unit standard deviation. Both functions take one
+ * two-channel device stream (gwd_stream above) and treat the channels alike.
+ *
+ * gwd_welch_psd writes the one-sided Welch PSD of each channel to
+ * psd[c * (nperseg/2 + 1) + k] (device, float64, k = 0 .. nperseg/2, bin k at
+ * k fs / nperseg Hz): segments of nperseg samples at step nperseg/2 (only
+ * full segments, K = (length - nperseg) / (nperseg/2) + 1), periodic Hann
+ * window w[j] = 1/2 - 1/2 cos(2 pi j / nperseg), no detrending, mean of
+ * |FFT|^2 over the segments, scaled by c_k / (K fs sum w^2) with c_k = 1 at
+ * k = 0 and nperseg/2 and 2 elsewhere (scipy.signal.welch with window "hann",
+ * noverlap nperseg/2, detrend False). The transforms run in float32; the
+ * squared magnitudes and the mean in float64.
+ *
+ * gwd_whiten writes the whitened stream, interleaved, to dst[t * 2 + c]
+ * (device float32 [length][2], 8-byte aligned; dst may be the source's own
+ * interleaved buffer): X = DFT of the whole channel (length L), divided bin by
+ * bin by sqrt(P(f) fs / 2) with P linearly interpolated at f = m fs / L from
+ * the psd grid (same layout as above), inverse DFT; white noise of variance
+ * s^2 thus comes out with unit variance. With normalize = 1 each channel is
+ * then divided by its population standard deviation (mean not removed). The
+ * transforms are float32 (both channels in one complex transform); the
+ * coefficients and the deviation float64. The psd must be positive: a zero
+ * bin gives non-finite output, as the definition does.
+ *
+ * Limits and errors: nperseg a power of two in [16, 16384]; fs > 0 and
+ * finite; gwd_whiten needs length a power of two in [16, 2^28] and
+ * nperseg <= length (GWD_ERR_SHAPE otherwise; a 4096 s segment at 4096 Hz is
+ * 2^24 samples); gwd_welch_psd needs length >= nperseg (GWD_ERR_SHAPE).
+ * GWD_ERR_ARG for NULL or misaligned pointers, elem_stride < 1 or normalize
+ * not 0 or 1. Both use a library-owned workspace (2 L complex float32 for
+ * gwd_whiten, 2 (K + 64) (nperseg/2 + 1) float64 for gwd_welch_psd) that grows on
+ * demand and is shared by the calls of the process: calls must not overlap
+ * in time. Asynchronous on hip_stream (except when the workspace grows). */
+gwd_status gwd_welch_psd(const gwd_stream* src, int32_t nperseg, double fs, double* psd, void* hip_stream);
+gwd_status gwd_whiten(const gwd_stream* src, const double* psd, int32_t nperseg, double fs, int32_t normalize,
+                      float* dst, void* hip_stream);
+
 /* ---- training (one member; "AI ensemble construction") ---------------------
  * windows: device [B][W][2] float32 (interleaved channels). Element type T of
  * logits, grad_logit, grad_params and grad_input is float, or double for a

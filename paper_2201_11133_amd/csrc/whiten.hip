@@ -1,0 +1,430 @@
+// Whitening front end ("Data preparation"): the Welch PSD of each channel of a two-detector
+// stream, whitening of the stream by that PSD as one transform over the whole stream, and scaling
+// of each channel to unit standard deviation.
+//
+// Both channels travel in one complex sequence z[t] = x0[t] + i x1[t]; the spectra of the two real
+// channels separate as X0[k] = (Z[k] + conj Z[N-k]) / 2 and X1[k] = (Z[k] - conj Z[N-k]) / 2i.
+// Transforms are radix-2 decimation-in-time in LDS, one workgroup per transform, up to 16384
+// points. A stream of L = N1 N2 samples takes the four-step route: N2 transforms of length N1 down
+// the columns t = n1 N2 + n2, a twiddle e^(-2 pi i n2 k1 / L), N1 transforms of length N2 along
+// the rows; the spectrum is kept transposed (bin k1 + N1 k2 at k1 N2 + k2), which is the order
+// the inverse reads back.
+#include <algorithm>
+#include <cmath>
+#include <mutex>
+
+#include "gwd_internal.h"
+
+namespace gwd {
+
+constexpr int WH_THREADS = 512;
+constexpr int WH_MAXLOG = 14;                 // largest transform in one workgroup: 16384 points
+constexpr int WH_TW = 1 << (WH_MAXLOG - 1);   // twiddle table tw[t] = e^(-2 pi i t / 16384), t < 8192
+
+__device__ inline float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+__device__ inline int bitrev(int j, int logn) { return (int)(__brev((unsigned)j) >> (32 - logn)); }
+
+// Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous range of transforms so
+// that the neighbouring columns that share cache lines in the strided passes meet in one L2.
+__device__ inline int64_t xcd_block(int64_t nblk) {
+    const int64_t b = blockIdx.x;
+    return (nblk & 7) ? b : (b & 7) * (nblk >> 3) + (b >> 3);
+}
+
+// e^(sign 2 pi i e / L) for an exact integer e < L (L a power of two), through float64
+__device__ inline float2 twiddle_l(int64_t e, int logl, bool inverse) {
+    double s, c;
+    sincospi((inverse ? 2.0 : -2.0) * ldexp((double)e, -logl), &s, &c);
+    return make_float2((float)c, (float)s);
+}
+
+__global__ void wh_twiddle_kernel(float2* tw) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < WH_TW) {
+        double s, c;
+        sincospi(-2.0 * ldexp((double)t, -WH_MAXLOG), &s, &c);
+        tw[t] = make_float2((float)c, (float)s);
+    }
+}
+
+// In-place radix-2 DIT transform of s[0, 2^logn) (input already in bit-reversed order, output in
+// natural order); the inverse uses the conjugate twiddles and does not scale.
+__device__ void lds_fft(float2* s, int logn, const float2* __restrict__ tw, bool inverse) {
+    const int half_n = 1 << (logn - 1);
+    for (int lh = 0; lh < logn; ++lh) {
+        const int half = 1 << lh;
+        const int tsh = WH_MAXLOG - 1 - lh;   // W_(2 half)^j = tw[j * 16384 / (2 half)]
+        __syncthreads();
+        for (int b = threadIdx.x; b < half_n; b += blockDim.x) {
+            const int j = b & (half - 1);
+            const int i0 = ((b - j) << 1) + j;
+            const int i1 = i0 + half;
+            float2 w = tw[j << tsh];
+            if (inverse) w.y = -w.y;
+            const float2 a = s[i0];
+            const float2 c = cmul(s[i1], w);
+            s[i0] = make_float2(a.x + c.x, a.y + c.y);
+            s[i1] = make_float2(a.x - c.x, a.y - c.y);
+        }
+    }
+    __syncthreads();
+}
+
+// One Welch segment per workgroup: both channels windowed into one complex sequence, transformed,
+// separated, and |X_c[k]|^2 written in float64 to pseg[(seg * 2 + c) * h + k], h = n/2 + 1.
+template <int LOGMAX>
+__global__ __launch_bounds__(WH_THREADS) void wh_welch_kernel(const float* x0, const float* x1, int64_t es,
+                                                             int logn, const float2* tw, double* pseg) {
+    __shared__ float2 s[1 << LOGMAX];
+    const int n = 1 << logn;
+    const int h = n / 2 + 1;
+    const int64_t seg = blockIdx.x;
+    const int64_t t0 = seg * (n / 2);
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const float w = (float)(0.5 - 0.5 * cospi(ldexp((double)j, 1 - logn)));
+        const int64_t t = (t0 + j) * es;
+        s[bitrev(j, logn)] = make_float2(w * x0[t], w * x1[t]);
+    }
+    lds_fft(s, logn, tw, false);
+    double* out = pseg + seg * 2 * h;
+    for (int k = threadIdx.x; k < h; k += blockDim.x) {
+        const float2 z = s[k], zp = s[(n - k) & (n - 1)];
+        const double a0 = 0.5 * ((double)z.x + zp.x), b0 = 0.5 * ((double)z.y - zp.y);
+        const double a1 = 0.5 * ((double)z.y + zp.y), b1 = -0.5 * ((double)z.x - zp.x);
+        out[k] = a0 * a0 + b0 * b0;
+        out[h + k] = a1 * a1 + b1 * b1;
+    }
+}
+
+// Mean over segments and one-sided density scaling in two fixed-order levels: group g of
+// WH_GROUPS sums its contiguous run of segments, then the groups are summed in order.
+constexpr int WH_GROUPS = 64;
+
+__global__ void wh_welch_part_kernel(const double* pseg, int64_t nseg, int h, double* part) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 2 * h) return;
+    const int64_t g = blockIdx.y;
+    const int64_t s0 = nseg * g / WH_GROUPS, s1 = nseg * (g + 1) / WH_GROUPS;
+    double acc = 0.0;
+    for (int64_t sg = s0; sg < s1; ++sg) acc += pseg[sg * 2 * h + i];
+    part[g * 2 * h + i] = acc;
+}
+
+__global__ void wh_welch_reduce_kernel(const double* part, int h, double scale, double* psd) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 2 * h) return;
+    const int k = i % h;
+    double acc = 0.0;
+    for (int g = 0; g < WH_GROUPS; ++g) acc += part[(int64_t)g * 2 * h + i];
+    psd[i] = acc * scale * ((k == 0 || k == h - 1) ? 1.0 : 2.0);
+}
+
+// Forward column pass: workgroup n2 transforms z[n1 N2 + n2] over n1 and writes
+// A[n2 N1 + k1] = Z_n2[k1] e^(-2 pi i n2 k1 / L).
+template <int LOGMAX>
+__global__ __launch_bounds__(WH_THREADS) void wh_cols_fwd_kernel(const float* x0, const float* x1, int64_t es,
+                                                                int logn1, int logn2, const float2* tw, float2* A) {
+    __shared__ float2 s[1 << LOGMAX];
+    const int n1c = 1 << logn1;
+    const int64_t n2 = xcd_block(1ll << logn2);
+    for (int j = threadIdx.x; j < n1c; j += blockDim.x) {
+        const int64_t t = (((int64_t)j << logn2) + n2) * es;
+        s[bitrev(j, logn1)] = make_float2(x0[t], x1[t]);
+    }
+    lds_fft(s, logn1, tw, false);
+    const int logl = logn1 + logn2;
+    float2* out = A + (n2 << logn1);
+    for (int k1 = threadIdx.x; k1 < n1c; k1 += blockDim.x)
+        out[k1] = cmul(s[k1], twiddle_l(n2 * k1, logl, false));
+}
+
+// Forward row pass: workgroup k1 transforms A[n2 N1 + k1] over n2 and writes T[k1 N2 + k2].
+template <int LOGMAX>
+__global__ __launch_bounds__(WH_THREADS) void wh_rows_fwd_kernel(const float2* A, int logn1, int logn2,
+                                                                const float2* tw, float2* T) {
+    __shared__ float2 s[1 << LOGMAX];
+    const int n2c = 1 << logn2;
+    const int64_t k1 = xcd_block(1ll << logn1);
+    for (int j = threadIdx.x; j < n2c; j += blockDim.x) s[bitrev(j, logn2)] = A[((int64_t)j << logn1) + k1];
+    lds_fft(s, logn2, tw, false);
+    float2* out = T + (k1 << logn2);
+    for (int k2 = threadIdx.x; k2 < n2c; k2 += blockDim.x) out[k2] = s[k2];
+}
+
+// 1 / (L sqrt(P_c(f_k) fs / 2)): the PSD linearly interpolated at bin k of L (grid position
+// k n / L), with the inverse transform's 1/L folded in.
+__device__ inline float wh_coef(const double* psd, int h, int c, int64_t k, int sh, int logl, double fs) {
+    const int64_t j = k >> sh;
+    const double fr = ldexp((double)(k & ((1ll << sh) - 1)), -sh);
+    const double* p = psd + (int64_t)c * h;
+    const double pk = fr == 0.0 ? p[j] : p[j] * (1.0 - fr) + p[j + 1] * fr;
+    return (float)(1.0 / (ldexp(1.0, logl) * sqrt(pk * fs * 0.5)));
+}
+
+// Spectrum division on the transposed spectrum, in place. The thread of bin k <= L - k handles the
+// pair (k, L - k): separate the channels, scale each by its coefficient, recombine.
+__global__ void wh_spectrum_kernel(float2* T, int logn1, int logn2, const double* psd, int logn, double fs) {
+    const int logl = logn1 + logn2;
+    const int64_t L = 1ll << logl;
+    const int h = (1 << logn) / 2 + 1;
+    const int sh = logl - logn;
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < L; p += step) {
+        const int64_t k = (p >> logn2) + ((p & ((1ll << logn2) - 1)) << logn1);
+        const int64_t kp = (L - k) & (L - 1);
+        if (k > kp) continue;
+        const int64_t pp = ((kp & ((1ll << logn1) - 1)) << logn2) + (kp >> logn1);
+        const float2 z = T[p], zp = T[pp];
+        const float2 X0 = make_float2(0.5f * (z.x + zp.x), 0.5f * (z.y - zp.y));
+        const float2 X1 = make_float2(0.5f * (z.y + zp.y), -0.5f * (z.x - zp.x));
+        const float a0 = wh_coef(psd, h, 0, k, sh, logl, fs);
+        const float a1 = wh_coef(psd, h, 1, k, sh, logl, fs);
+        T[p] = make_float2(a0 * X0.x - a1 * X1.y, a0 * X0.y + a1 * X1.x);
+        if (pp != p) T[pp] = make_float2(a0 * X0.x + a1 * X1.y, a1 * X1.x - a0 * X0.y);
+    }
+}
+
+// Inverse row pass: workgroup k1 inverse-transforms T[k1 N2 + k2] over k2 and writes
+// C[k1 N2 + n2] = c_k1[n2] e^(+2 pi i n2 k1 / L).
+template <int LOGMAX>
+__global__ __launch_bounds__(WH_THREADS) void wh_rows_inv_kernel(const float2* T, int logn1, int logn2,
+                                                                const float2* tw, float2* C) {
+    __shared__ float2 s[1 << LOGMAX];
+    const int n2c = 1 << logn2;
+    const int64_t k1 = blockIdx.x;
+    const float2* in = T + (k1 << logn2);
+    for (int j = threadIdx.x; j < n2c; j += blockDim.x) s[bitrev(j, logn2)] = in[j];
+    lds_fft(s, logn2, tw, true);
+    const int logl = logn1 + logn2;
+    float2* out = C + (k1 << logn2);
+    for (int n2 = threadIdx.x; n2 < n2c; n2 += blockDim.x)
+        out[n2] = cmul(s[n2], twiddle_l(n2 * k1, logl, true));
+}
+
+// Inverse column pass: workgroup n2 inverse-transforms C[k1 N2 + n2] over k1 into
+// y[n1 N2 + n2] (channel 0 real part, channel 1 imaginary part), written interleaved, and leaves
+// its float64 sums of y and y^2 per channel in part[n2 * 4 + {0..3}].
+template <int LOGMAX>
+__global__ __launch_bounds__(WH_THREADS) void wh_cols_inv_kernel(const float2* C, int logn1, int logn2,
+                                                                const float2* tw, float* out, double* part) {
+    __shared__ float2 s[1 << LOGMAX];
+    __shared__ double red[4][WH_THREADS];
+    const int n1c = 1 << logn1;
+    const int64_t n2 = xcd_block(1ll << logn2);
+    for (int j = threadIdx.x; j < n1c; j += blockDim.x) s[bitrev(j, logn1)] = C[((int64_t)j << logn2) + n2];
+    lds_fft(s, logn1, tw, true);
+    double a0 = 0.0, q0 = 0.0, a1 = 0.0, q1 = 0.0;
+    for (int j = threadIdx.x; j < n1c; j += blockDim.x) {
+        const float2 y = s[j];
+        const int64_t t = ((int64_t)j << logn2) + n2;
+        *reinterpret_cast<float2*>(out + 2 * t) = y;
+        a0 += y.x;
+        q0 += (double)y.x * y.x;
+        a1 += y.y;
+        q1 += (double)y.y * y.y;
+    }
+    red[0][threadIdx.x] = a0;
+    red[1][threadIdx.x] = q0;
+    red[2][threadIdx.x] = a1;
+    red[3][threadIdx.x] = q1;
+    for (int w = WH_THREADS / 2; w > 0; w >>= 1) {
+        __syncthreads();
+        if ((int)threadIdx.x < w)
+            for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) part[n2 * 4 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// 1 / sigma per channel from the per-workgroup sums (fixed summation order).
+__global__ void wh_sigma_kernel(const double* part, int64_t nblk, int logl, float* inv_sigma) {
+    __shared__ double red[4][256];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t b = threadIdx.x; b < nblk; b += blockDim.x)
+        for (int q = 0; q < 4; ++q) acc[q] += part[b * 4 + q];
+    for (int q = 0; q < 4; ++q) red[q][threadIdx.x] = acc[q];
+    for (int w = 128; w > 0; w >>= 1) {
+        __syncthreads();
+        if ((int)threadIdx.x < w)
+            for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        const double inv_l = ldexp(1.0, -logl);
+        const double mean = red[2 * threadIdx.x][0] * inv_l;
+        const double var = red[2 * threadIdx.x + 1][0] * inv_l - mean * mean;
+        inv_sigma[threadIdx.x] = (float)(1.0 / sqrt(var));
+    }
+}
+
+__global__ void wh_scale_kernel(float2* out, int64_t L, const float* inv_sigma) {
+    const float s0 = inv_sigma[0], s1 = inv_sigma[1];
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < L; t += step) {
+        const float2 y = out[t];
+        out[t] = make_float2(y.x * s0, y.y * s1);
+    }
+}
+
+// grow-only device workspace (twiddle table first), shared by the calls of the process
+struct WhitenWs {
+    std::mutex mu;
+    void* buf = nullptr;
+    int64_t bytes = 0;
+    int device = -1;
+};
+static WhitenWs g_wh;
+
+constexpr int64_t WH_TW_BYTES = (int64_t)WH_TW * 8;
+
+static gwd_status wh_workspace(int64_t need, hipStream_t st, char** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    need += WH_TW_BYTES;
+    if (g_wh.bytes < need || g_wh.device != dev) {
+        if (g_wh.buf) {
+            (void)hipDeviceSynchronize();
+            (void)hipFree(g_wh.buf);
+            g_wh.buf = nullptr;
+            g_wh.bytes = 0;
+        }
+        e = hipMalloc(&g_wh.buf, need);
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc(whitening workspace)");
+        g_wh.bytes = need;
+        g_wh.device = dev;
+        hipLaunchKernelGGL(wh_twiddle_kernel, dim3(WH_TW / 256), dim3(256), 0, st, (float2*)g_wh.buf);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(st);   // the table serves calls on any stream
+        if (e != hipSuccess) return hip_fail(e, "twiddle table");
+    }
+    *out = (char*)g_wh.buf;
+    return GWD_OK;
+}
+
+static int log2_exact(int64_t v) {
+    if (v <= 0 || (v & (v - 1))) return -1;
+    int l = 0;
+    while ((1ll << l) < v) ++l;
+    return l;
+}
+
+static gwd_status check_stream(const gwd_stream* src, const char* who) {
+    if (!src || !src->ch[0] || !src->ch[1]) { set_error("%s: NULL stream or channel pointer", who); return GWD_ERR_ARG; }
+    if (src->elem_stride < 1 || src->length < 0) { set_error("%s: elem_stride < 1 or negative length", who); return GWD_ERR_ARG; }
+    if (((uintptr_t)src->ch[0] & 3) || ((uintptr_t)src->ch[1] & 3)) { set_error("%s: misaligned channel pointer", who); return GWD_ERR_ARG; }
+    return GWD_OK;
+}
+
+static gwd_status check_fs_n(int32_t nperseg, double fs, const char* who, int* logn) {
+    *logn = log2_exact(nperseg);
+    if (*logn < 4 || *logn > WH_MAXLOG) { set_error("%s: nperseg must be a power of two in [16, 16384]", who); return GWD_ERR_ARG; }
+    if (!(fs > 0.0) || !std::isfinite(fs)) { set_error("%s: fs must be positive and finite", who); return GWD_ERR_ARG; }
+    return GWD_OK;
+}
+
+}  // namespace gwd
+
+using namespace gwd;
+
+gwd_status gwd_welch_psd(const gwd_stream* src, int32_t nperseg, double fs, double* psd, void* hip_stream) {
+    gwd_status r = check_stream(src, "gwd_welch_psd");
+    if (r != GWD_OK) return r;
+    int logn = 0;
+    r = check_fs_n(nperseg, fs, "gwd_welch_psd", &logn);
+    if (r != GWD_OK) return r;
+    if (!psd || ((uintptr_t)psd & 7)) { set_error("gwd_welch_psd: NULL or misaligned psd"); return GWD_ERR_ARG; }
+    if (src->length < nperseg) { set_error("gwd_welch_psd: stream shorter than one segment"); return GWD_ERR_SHAPE; }
+    const int64_t nseg = (src->length - nperseg) / (nperseg / 2) + 1;
+    if (nseg > 0x7fffffff) { set_error("gwd_welch_psd: too many segments"); return GWD_ERR_SHAPE; }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) { set_error("gwd_welch_psd: no HIP device"); return GWD_ERR_NO_DEVICE; }
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int h = nperseg / 2 + 1;
+    std::lock_guard<std::mutex> lock(g_wh.mu);
+    char* ws = nullptr;
+    r = wh_workspace((nseg + WH_GROUPS) * 2 * h * 8, st, &ws);
+    if (r != GWD_OK) return r;
+    const float2* tw = (const float2*)ws;
+    double* pseg = (double*)(ws + WH_TW_BYTES);
+    double* part = pseg + nseg * 2 * h;
+    if (logn <= 12)
+        hipLaunchKernelGGL(wh_welch_kernel<12>, dim3((unsigned)nseg), dim3(WH_THREADS), 0, st, src->ch[0], src->ch[1],
+                           src->elem_stride, logn, tw, pseg);
+    else
+        hipLaunchKernelGGL(wh_welch_kernel<WH_MAXLOG>, dim3((unsigned)nseg), dim3(WH_THREADS), 0, st, src->ch[0],
+                           src->ch[1], src->elem_stride, logn, tw, pseg);
+    // sum of the squared periodic Hann window: 3n/8
+    const double scale = 1.0 / ((double)nseg * fs * (3.0 * nperseg / 8.0));
+    hipLaunchKernelGGL(wh_welch_part_kernel, dim3((2 * h + 255) / 256, WH_GROUPS), dim3(256), 0, st, (const double*)pseg,
+                       nseg, h, part);
+    hipLaunchKernelGGL(wh_welch_reduce_kernel, dim3((2 * h + 255) / 256), dim3(256), 0, st, (const double*)part, h, scale,
+                       psd);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? GWD_OK : hip_fail(e, "Welch kernel launch");
+}
+
+gwd_status gwd_whiten(const gwd_stream* src, const double* psd, int32_t nperseg, double fs, int32_t normalize,
+                      float* dst, void* hip_stream) {
+    gwd_status r = check_stream(src, "gwd_whiten");
+    if (r != GWD_OK) return r;
+    int logn = 0;
+    r = check_fs_n(nperseg, fs, "gwd_whiten", &logn);
+    if (r != GWD_OK) return r;
+    if (!psd || ((uintptr_t)psd & 7)) { set_error("gwd_whiten: NULL or misaligned psd"); return GWD_ERR_ARG; }
+    if (!dst || ((uintptr_t)dst & 7)) { set_error("gwd_whiten: NULL or misaligned output"); return GWD_ERR_ARG; }
+    if (normalize != 0 && normalize != 1) { set_error("gwd_whiten: normalize must be 0 or 1"); return GWD_ERR_ARG; }
+    const int logl = log2_exact(src->length);
+    if (logl < 4 || logl > 2 * WH_MAXLOG) { set_error("gwd_whiten: length must be a power of two in [16, 2^28]"); return GWD_ERR_SHAPE; }
+    if (logn > logl) { set_error("gwd_whiten: nperseg longer than the stream"); return GWD_ERR_SHAPE; }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) { set_error("gwd_whiten: no HIP device"); return GWD_ERR_NO_DEVICE; }
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int logn1 = (logl + 1) / 2, logn2 = logl / 2;
+    const int64_t L = 1ll << logl, n1c = 1ll << logn1, n2c = 1ll << logn2;
+    std::lock_guard<std::mutex> lock(g_wh.mu);
+    char* ws = nullptr;
+    r = wh_workspace(2 * L * 8 + n2c * 32 + 16, st, &ws);
+    if (r != GWD_OK) return r;
+    const float2* tw = (const float2*)ws;
+    float2* A = (float2*)(ws + WH_TW_BYTES);
+    float2* T = A + L;
+    double* part = (double*)(T + L);
+    float* inv_sigma = (float*)(part + 4 * n2c);
+    const bool big = logn1 > 12;
+    if (big)
+        hipLaunchKernelGGL(wh_cols_fwd_kernel<WH_MAXLOG>, dim3((unsigned)n2c), dim3(WH_THREADS), 0, st, src->ch[0],
+                           src->ch[1], src->elem_stride, logn1, logn2, tw, A);
+    else
+        hipLaunchKernelGGL(wh_cols_fwd_kernel<12>, dim3((unsigned)n2c), dim3(WH_THREADS), 0, st, src->ch[0], src->ch[1],
+                           src->elem_stride, logn1, logn2, tw, A);
+    if (logn2 > 12)
+        hipLaunchKernelGGL(wh_rows_fwd_kernel<WH_MAXLOG>, dim3((unsigned)n1c), dim3(WH_THREADS), 0, st, (const float2*)A,
+                           logn1, logn2, tw, T);
+    else
+        hipLaunchKernelGGL(wh_rows_fwd_kernel<12>, dim3((unsigned)n1c), dim3(WH_THREADS), 0, st, (const float2*)A, logn1,
+                           logn2, tw, T);
+    const unsigned sblocks = (unsigned)std::min<int64_t>((L + 255) / 256, 16384);
+    hipLaunchKernelGGL(wh_spectrum_kernel, dim3(sblocks), dim3(256), 0, st, T, logn1, logn2, psd, logn, fs);
+    if (logn2 > 12)
+        hipLaunchKernelGGL(wh_rows_inv_kernel<WH_MAXLOG>, dim3((unsigned)n1c), dim3(WH_THREADS), 0, st, (const float2*)T,
+                           logn1, logn2, tw, A);
+    else
+        hipLaunchKernelGGL(wh_rows_inv_kernel<12>, dim3((unsigned)n1c), dim3(WH_THREADS), 0, st, (const float2*)T, logn1,
+                           logn2, tw, A);
+    if (big)
+        hipLaunchKernelGGL(wh_cols_inv_kernel<WH_MAXLOG>, dim3((unsigned)n2c), dim3(WH_THREADS), 0, st, (const float2*)A,
+                           logn1, logn2, tw, dst, part);
+    else
+        hipLaunchKernelGGL(wh_cols_inv_kernel<12>, dim3((unsigned)n2c), dim3(WH_THREADS), 0, st, (const float2*)A, logn1,
+                           logn2, tw, dst, part);
+    if (normalize) {
+        hipLaunchKernelGGL(wh_sigma_kernel, dim3(1), dim3(256), 0, st, (const double*)part, n2c, logl, inv_sigma);
+        hipLaunchKernelGGL(wh_scale_kernel, dim3(sblocks), dim3(256), 0, st, (float2*)dst, L, (const float*)inv_sigma);
+    }
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? GWD_OK : hip_fail(e, "whitening kernel launch");
+}

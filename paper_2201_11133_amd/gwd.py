@@ -83,6 +83,8 @@ def _load(path: str = LIB_PATH):
         "gwd_prob64": (I32, [P, I64, P, P]),
         "gwd_find_peaks": (I32, [P, I64, D, D, P, P, I64, ctypes.POINTER(I64), P]),
         "gwd_coincidence": (I32, [P, P, I32, I64, P, I64, ctypes.POINTER(I64)]),
+        "gwd_welch_psd": (I32, [ctypes.POINTER(Stream), I32, D, P, P]),
+        "gwd_whiten": (I32, [ctypes.POINTER(Stream), P, I32, D, I32, P, P]),
         "gwd_saved_bytes": (I64, [P, I32, I32]),
         "gwd_forward_train": (I32, [P, I32, P, I32, I32, P, P, P]),
         "gwd_backward": (I32, [P, I32, P, I32, I32, P, P, P, P, P]),
@@ -447,3 +449,31 @@ def coincidence(peak_lists: Sequence, window: int) -> List[int]:
     nf = ctypes.c_int64(0)
     check(lib.gwd_coincidence(ptrs, counts.ctypes.data, len(arrs), int(window), ev.ctypes.data, cap, ctypes.byref(nf)))
     return [int(v) for v in ev[:nf.value]]
+
+
+def welch_psd(src, nperseg: int = 16384, fs: float = 4096.0, out=None, stream=None):
+    """gwd_welch_psd: one-sided Welch PSD of both channels of one device stream ([L, 2] tensor or
+    (ch0, ch1) pair) as a float64 device tensor [2, nperseg // 2 + 1]."""
+    import torch
+    arr, _ = make_streams([src])
+    if out is None:
+        dev = src[0].device if isinstance(src, (tuple, list)) else src.device
+        out = torch.empty((2, nperseg // 2 + 1), dtype=torch.float64, device=dev)
+    assert out.dtype == torch.float64 and out.is_contiguous() and tuple(out.shape) == (2, nperseg // 2 + 1)
+    check(lib.gwd_welch_psd(arr, int(nperseg), float(fs), _ptr(out), _stream_handle(stream)))
+    return out
+
+
+def whiten(src, psd, nperseg: int = 16384, fs: float = 4096.0, normalize: bool = True, out=None, stream=None):
+    """gwd_whiten: the stream whitened by psd (float64 device [2, nperseg // 2 + 1]) and, if normalize,
+    scaled to unit deviation per channel, as a float32 device tensor [L, 2]."""
+    import torch
+    arr, lengths = make_streams([src])
+    if out is None:
+        dev = src[0].device if isinstance(src, (tuple, list)) else src.device
+        out = torch.empty((lengths[0], 2), dtype=torch.float32, device=dev)
+    assert out.dtype == torch.float32 and out.is_contiguous() and tuple(out.shape) == (lengths[0], 2)
+    assert psd.dtype == torch.float64 and psd.is_contiguous() and tuple(psd.shape) == (2, nperseg // 2 + 1)
+    check(lib.gwd_whiten(arr, _ptr(psd), int(nperseg), float(fs), int(bool(normalize)), _ptr(out),
+                         _stream_handle(stream)))
+    return out

@@ -214,3 +214,41 @@ def test_postproc_argument_errors(g):
     assert g.lib.gwd_find_peaks(8, 100, 0.5, 1.0, None, None, 4, ctypes.byref(nf), None) == g.ERR_ARG
     assert g.lib.gwd_prob64(None, 10, None, None) == g.ERR_ARG
     assert g.lib.gwd_prob64(None, 0, None, None) == g.OK
+
+
+def whiten_call(g, length=4096, stride=2, n=256, fs=4096.0, normalize=1, psd=8, dst=8, ch0=16, ch1=20):
+    src = g.Stream()
+    src.ch[0], src.ch[1], src.elem_stride, src.length = ch0, ch1, stride, length
+    return g.lib.gwd_whiten(ctypes.byref(src), psd, n, fs, normalize, dst, None)
+
+
+def welch_call(g, length=4096, stride=2, n=256, fs=4096.0, psd=8, ch0=16, ch1=20):
+    src = g.Stream()
+    src.ch[0], src.ch[1], src.elem_stride, src.length = ch0, ch1, stride, length
+    return g.lib.gwd_welch_psd(ctypes.byref(src), n, fs, psd, None)
+
+
+def test_whitening_argument_errors(g):
+    assert g.lib.gwd_whiten(None, 8, 256, 4096.0, 1, 8, None) == g.ERR_ARG
+    assert g.lib.gwd_welch_psd(None, 256, 4096.0, 8, None) == g.ERR_ARG
+    for f in (whiten_call, welch_call):
+        assert f(g, n=100) == g.ERR_ARG                   # not a power of two
+        assert f(g, n=8) == g.ERR_ARG                     # below 16
+        assert f(g, n=32768) == g.ERR_ARG                 # above 16384
+        assert f(g, fs=0.0) == g.ERR_ARG
+        assert f(g, fs=float("inf")) == g.ERR_ARG
+        assert f(g, psd=None) == g.ERR_ARG
+        assert f(g, psd=12) == g.ERR_ARG                  # float64 PSD, misaligned
+        assert f(g, ch0=18) == g.ERR_ARG
+        assert f(g, ch1=None) == g.ERR_ARG
+        assert f(g, stride=0) == g.ERR_ARG
+    assert whiten_call(g, dst=12) == g.ERR_ARG
+    assert whiten_call(g, normalize=2) == g.ERR_ARG
+    assert whiten_call(g, length=5000) == g.ERR_SHAPE     # whole-stream transform: a power of two
+    assert whiten_call(g, length=8) == g.ERR_SHAPE
+    assert whiten_call(g, length=1 << 29) == g.ERR_SHAPE
+    assert whiten_call(g, length=128, n=256) == g.ERR_SHAPE
+    assert welch_call(g, length=255, n=256) == g.ERR_SHAPE
+    if not host_has_gpu():                                # (the pointers are not real buffers)
+        assert whiten_call(g) == g.ERR_NO_DEVICE
+        assert welch_call(g, length=5000) == g.ERR_NO_DEVICE
