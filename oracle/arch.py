@@ -16,6 +16,13 @@ kind 1, "gated residual WaveNet": a 1x1 input projection 2 -> C, then
     and skip 1x1 convolutions; the skip sum goes through ReLU, a 1x1 to H
     channels, an optional ReLU, a 1x1 to one channel, then the sigmoid.
 
+kind 2, "two-branch" (the paper's Fig. 1): one gated residual WaveNet per
+    detector (Hanford, Livingston), each reading its own channel through a
+    1x1 input projection 1 -> C, with its own n_stacks x layers_per_stack
+    gated layers and its own skip sum of S channels; the two skip sums are
+    concatenated (2S channels, Hanford first) and go through the same head as
+    kind 1 (ReLU, 1x1 to H, optional ReLU, 1x1 to one channel).
+
 Readings where the paper is silent (all listed in the design notes):
   * the input layer is a 1x1 convolution with bias (input_kernel=1), so the
     receptive field is 1 + (kernel-1) * sum of dilations;
@@ -33,6 +40,9 @@ Blob layout (per member, float, in this order):
                           res.W[C][C], res.b[C]      (absent for l = L-1)
                           skip.W[S][C], skip.b[S]
           h1.W[H][S], h1.b[H], h2.W[1][H], h2.b[1]
+  kind 2: for branch b = 0 (Hanford), 1 (Livingston): the kind-1 tensors from
+          in.W[C][1] through the last skip.b[S], prefixed "b<b>."
+          h1.W[H][2S], h1.b[H], h2.W[1][H], h2.b[1]
 """
 from __future__ import annotations
 
@@ -44,7 +54,7 @@ import numpy as np
 
 @dataclass(frozen=True)
 class Arch:
-    kind: int = 1                 # 0 plain ReLU stack, 1 gated residual WaveNet
+    kind: int = 1                 # 0 plain ReLU stack, 1 gated residual WaveNet, 2 two-branch
     in_channels: int = 2          # Hanford, Livingston
     channels: int = 128           # residual channels (kind 1) / conv channels (kind 0)
     skip_channels: int = 128
@@ -67,6 +77,16 @@ class Arch:
 TINY = Arch(kind=0, in_channels=2, channels=16, skip_channels=0, head_channels=0,
             n_stacks=1, layers_per_stack=4, kernel_size=2, input_kernel=1, head_mid_relu=0)
 FULL = Arch()
+# The paper's two-branch topology at the same total width: two 64-channel branches whose skip sums
+# concatenate to the 128 channels the head reads.
+TWO_BRANCH = Arch(kind=2, in_channels=2, channels=64, skip_channels=64, head_channels=128)
+
+
+def branch_arch(a: Arch) -> Arch:
+    """The single-detector gated member one branch of a kind-2 member is."""
+    return Arch(kind=1, in_channels=1, channels=a.channels, skip_channels=a.skip_channels,
+                head_channels=a.head_channels, n_stacks=a.n_stacks, layers_per_stack=a.layers_per_stack,
+                kernel_size=a.kernel_size, input_kernel=a.input_kernel, head_mid_relu=a.head_mid_relu)
 
 
 def layout(a: Arch) -> List[Tuple[str, Tuple[int, ...], int]]:
@@ -85,6 +105,12 @@ def layout(a: Arch) -> List[Tuple[str, Tuple[int, ...], int]]:
         out.append(("out.W", (1, a.channels), a.channels))
         out.append(("out.b", (1,), 0))
         return out
+    if a.kind == 2:
+        trunk = [t for t in layout(branch_arch(a)) if not t[0].startswith("h")]
+        for br in range(2):
+            out += [(f"b{br}.{name}", shape, fan) for name, shape, fan in trunk]
+        S2, H = 2 * a.skip_channels, a.head_channels
+        return out + [("h1.W", (H, S2), S2), ("h1.b", (H,), 0), ("h2.W", (1, H), H), ("h2.b", (1,), 0)]
     C, S, H = a.channels, a.skip_channels, a.head_channels
     if a.input_kernel == 1:
         out.append(("in.W", (C, a.in_channels), a.in_channels))
@@ -113,7 +139,7 @@ def num_params(a: Arch) -> int:
 def receptive_field(a: Arch) -> int:
     """Number of input samples that influence one output sample (causal)."""
     rf = 1 + (a.kernel_size - 1) * sum(a.dilation(l) for l in range(a.n_layers))
-    if a.kind == 1:
+    if a.kind in (1, 2):
         rf += a.input_kernel - 1
     return rf
 

@@ -17,7 +17,7 @@ from typing import Dict, List, Optional
 
 import numpy as np
 
-from .arch import Arch
+from .arch import Arch, branch_arch
 
 
 def sigmoid(z: np.ndarray) -> np.ndarray:
@@ -105,6 +105,8 @@ def forward_window(a: Arch, p: Dict[str, np.ndarray], u: np.ndarray,
             if capture is not None:
                 capture.append({"y": y})
         return (y @ p["out.W"].T + p["out.b"])[..., 0]
+    if a.kind == 2:
+        return forward_two_branch(a, p, u, capture)
     x = input_projection(a, p, u)
     skip = np.zeros(x.shape[:-1] + (a.skip_channels,))
     for l in range(a.n_layers):
@@ -113,6 +115,30 @@ def forward_window(a: Arch, p: Dict[str, np.ndarray], u: np.ndarray,
         if capture is not None:
             capture.append({"x_in": x_in, "pre": pre, "g": g, "x_out": x, "skip": skip})
     return head(a, p, skip)
+
+
+def branch_skip(a: Arch, p: Dict[str, np.ndarray], u: np.ndarray, br: int,
+                capture: Optional[List[dict]] = None) -> np.ndarray:
+    """Skip sum [..., T, S] of branch br of a kind-2 member, which reads detector channel br only."""
+    ab = branch_arch(a)
+    pre = f"b{br}."
+    pb = {k[len(pre):]: v for k, v in p.items() if k.startswith(pre)}
+    x = input_projection(ab, pb, u[..., br:br + 1])
+    skip = np.zeros(x.shape[:-1] + (ab.skip_channels,))
+    for l in range(ab.n_layers):
+        x_in = x
+        pre_act, g, x, skip = gated_layer(ab, pb, l, x, skip)
+        if capture is not None:
+            capture.append({"branch": br, "x_in": x_in, "pre": pre_act, "g": g, "x_out": x, "skip": skip})
+    return skip
+
+
+def forward_two_branch(a: Arch, p: Dict[str, np.ndarray], u: np.ndarray,
+                       capture: Optional[List[dict]] = None) -> np.ndarray:
+    """Kind-2 member: each detector through its own branch, the two skip sums concatenated
+    (Hanford first), then the head."""
+    s = np.concatenate([branch_skip(a, p, u, br, capture) for br in range(2)], axis=-1)
+    return head(a, p, s)
 
 
 def forward_stream(a: Arch, p: Dict[str, np.ndarray], u_stream: np.ndarray) -> np.ndarray:

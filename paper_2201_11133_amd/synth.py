@@ -204,6 +204,10 @@ def weight_layout(kind: int, channels: int, skip_channels: int = 128, head_chann
             out += [((channels, cin, kernel), cin * kernel), ((channels,), 0)]
             cin = channels
         return out + [((1, channels), channels), ((1,), 0)]
+    if kind == 2:       # one single-channel gated branch per detector, then the head on both skip sums
+        branch = weight_layout(1, channels, skip_channels, head_channels, n_layers, 1, kernel, input_kernel)[:-4]
+        return branch + branch + [((head_channels, 2 * skip_channels), 2 * skip_channels), ((head_channels,), 0),
+                                  ((1, head_channels), head_channels), ((1,), 0)]
     C, S, H = channels, skip_channels, head_channels
     if input_kernel == 1:
         out.append(((C, in_channels), in_channels))
@@ -238,6 +242,7 @@ def he_normal_blob(seed: int, layout: Sequence[Tuple[Tuple[int, ...], int]]) -> 
 
 TINY_LAYOUT = dict(kind=0, channels=16, n_layers=4)
 FULL_LAYOUT = dict(kind=1, channels=128, skip_channels=128, head_channels=128, n_layers=30)
+TWO_BRANCH_LAYOUT = dict(kind=2, channels=64, skip_channels=64, head_channels=128, n_layers=30)
 
 
 def tiny_weights(seed: int = 0) -> np.ndarray:
@@ -248,3 +253,9 @@ def full_weights(seed: int = 1, **kw) -> np.ndarray:
     lay = dict(FULL_LAYOUT)
     lay.update(kw)
     return he_normal_blob(seed, weight_layout(**lay))
+
+
+def two_branch_weights(seed: int = 21) -> np.ndarray:
+    """He-normal blob of the two-branch member (two 64-channel branches, 128-channel head)."""
+    return he_normal_blob(seed, weight_layout(**TWO_BRANCH_LAYOUT))
+
