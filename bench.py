@@ -32,6 +32,9 @@ W, S = 4096, 256
 FLOP_LAYERS_T = 5865984                   # flop per window time step per member: input conv + 30 gated layers
 FLOP_HEAD_T = 33024                       # flop per owned (output) sample per member: 128x128 + 128 -> 1
 FLOP_PER_LAYER_T = 196608                 # flop per time step of one gated layer (conv + res/skip)
+# the two-branch member's own work per window time step: two 64-channel branches (input 1x1, 30 gated
+# layers with 64 -> 128 dilated convs and 64 x 64 res/skip), i.e. the nonzero blocks of the trunk image
+FLOP_LAYERS_T_2B = 2 * (64 * 2 + 30 * 2 * 128 * 64 * 2 + 29 * 2 * 64 * 64 + 30 * 2 * 64 * 64)
 PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
 # HBM bytes per launch of the middle BF16 gated layer (512 windows), from two rocprofv3 --pmc runs
 # (FETCH_SIZE, WRITE_SIZE) scaled by a 1 GiB copy; valid only for the kernel source they were taken on
@@ -280,6 +283,35 @@ def postproc_workload(gwd, blobs, x, prec: str, seconds: float = 900.0, height: 
             "postproc_s": round(wall, 4), "strain_s_per_s": round(L / FS / wall, 1), "precision": prec}
 
 
+def two_branch_workload(gwd, x, prec: str, seconds: float = 256.0, members: int = 4):
+    """The paper's two-branch topology (Fig. 1: one gated branch of 64 channels per detector, skip sums
+    concatenated into the 128-channel head): a 4-member ensemble scored and thresholded like the main
+    line. It runs as the block-diagonal 128-channel trunk on the same kernels, so the executed work is
+    the trunk's and the useful work (nonzero blocks) about half of it."""
+    import torch
+    from paper_2201_11133_amd import synth
+    xs = x[: int(round(seconds * FS))]
+    L = xs.shape[0]
+    blobs = np.stack([synth.two_branch_weights(21 + i) for i in range(members)])
+    m = gwd.Model(gwd.two_branch_arch(), blobs, prec)
+    out = torch.empty(L, dtype=torch.float32, device="cuda")
+    m.forward([xs[: 64 * FS]], W, S, out_mode=0, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m.forward([xs], W, S, out_mode=0, out=out)
+    n_trig = len(gwd.triggers(out, [0, L], 0.9, 4096))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    m.close()
+    nw = n_windows(L)
+    executed = members * (nw * W * FLOP_LAYERS_T + L * FLOP_HEAD_T) / wall / 1e12
+    useful = members * (nw * W * FLOP_LAYERS_T_2B + L * FLOP_HEAD_T) / wall / 1e12
+    return {"slice_s": round(L / FS, 1), "members": members, "precision": prec, "triggers": n_trig,
+            "strain_s_per_s": round(L / FS / wall, 2), "executed_tflops": round(executed, 1),
+            "useful_tflops": round(useful, 1),
+            "note": "block-diagonal image on the trunk kernels; skipping the zero blocks is the next step"}
+
+
 def whitening_workload(gwd, seconds: float = 4096.0, nperseg: int = 16384, reps: int = 5):
     """The front end before the networks ("Data preparation"): the Welch PSD of a coloured
     two-channel stream (4 s Hann segments, half overlap) and the whitening of the whole stream by it,
@@ -391,6 +423,7 @@ def main():
     ap.add_argument("--no-background", action="store_true", help="skip the time-slide background line")
     ap.add_argument("--no-postproc", action="store_true", help="skip the peak-finding post-processing line")
     ap.add_argument("--no-whiten", action="store_true", help="skip the whitening front-end line")
+    ap.add_argument("--no-two-branch", action="store_true", help="skip the two-branch topology line")
     ap.add_argument("--stream-day", action=argparse.BooleanOptionalAction, default=True,
                     help="also run the streaming line over a full day (86400 s) of strain")
     ap.add_argument("--calib-copy", action="store_true",
@@ -472,6 +505,11 @@ def main():
         progress("post-processing: peaks and coincidence")
         postproc = postproc_workload(gwd, blobs, x, args.precision, min(900.0, args.seconds))
         progress(f"post-processing: {postproc['strain_s_per_s']} strain-s/s")
+    two_branch = None
+    if not args.no_two_branch:
+        progress("two-branch topology: 4 members")
+        two_branch = two_branch_workload(gwd, x, args.precision, min(256.0, args.seconds))
+        progress(f"two-branch: {two_branch['strain_s_per_s']} strain-s/s")
     whitening = None
     if not args.no_whiten:
         progress("whitening front end: Welch PSD and whitening of a 4096 s stream")
@@ -501,7 +539,7 @@ def main():
         "detail": {"triggers": main_r["triggers"], "tflops_step": round(main_r["tflops"], 2),
                    "ms_events": round(main_r["ms_events"], 3), "precisions": extra,
                    "ragged_streams": ragged, "time_slide_background": background, "postprocessing": postproc,
-                   "whitening_front_end": whitening, "training": train,
+                   "whitening_front_end": whitening, "two_branch": two_branch, "training": train,
                    "streaming_variant": streaming},
     }
     print(json.dumps(line), flush=True)

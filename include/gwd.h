@@ -76,10 +76,22 @@ typedef enum {
  *           skip += W_s g + b_s ;  x += W_r g + b_r  (no residual in the last layer)
  *         then logit = w_h2 . act(W_h1 ReLU(skip) + b_h1) + b_h2 with
  *         act = identity (head_mid_relu = 0) or ReLU (head_mid_relu = 1).
+ * kind 2: two-branch (the paper's Fig. 1) — one kind-1 trunk per detector,
+ *         each reading its own input channel (in_channels must be 2: branch b
+ *         reads channel b) with `channels` residual and `skip_channels` skip
+ *         channels; the two skip sums are concatenated (detector 0 first) and
+ *         go through the kind-1 head with W_h1 of [head_channels][2 *
+ *         skip_channels]. Blob: branch 0's trunk tensors (in.W[C][1] .. the
+ *         last skip.b), branch 1's, then h1.W, h1.b, h2.W, h2.b.
  * The paper (Fig. 1) does not give widths or depths; these are the build's
  * members. Supported by the GPU path: kind 0 with channels 16, in_channels 2,
  * kernel 2; kind 1 with channels = skip_channels = head_channels = 128,
- * in_channels 2, kernel 2, input_kernel 1. */
+ * in_channels 2, kernel 2, input_kernel 1; kind 2 with channels =
+ * skip_channels = 64, head_channels = 128, kernel 2, input_kernel 1, which
+ * gwd_load_weights expands into the block-diagonal kind-1 member of 128
+ * channels and runs on the same kernels (inference only: the training entry
+ * points return GWD_ERR_UNSUPPORTED; gwd_debug_export_weights returns the
+ * expanded kind-1 blob). */
 typedef struct {
     int32_t kind;
     int32_t in_channels;
@@ -115,7 +127,8 @@ typedef struct {
 
 /* Number of float parameters of one member in the canonical flat blob
  * (kind 0 with 16 channels: 1,681; kind 1 with 128 channels, 3x10 layers:
- * 2,964,993), or -1 for an invalid descriptor.
+ * 2,964,993; kind 2 with two 64-channel branches and a 128-channel head:
+ * 1,498,497), or -1 for an invalid descriptor.
  * Blob order (float32):
  *   kind 0: for each layer i: W[channels][c_in][kernel], b[channels]
  *           (c_in = in_channels for i = 0, else channels); out.W[1][channels], out.b[1]
@@ -124,11 +137,14 @@ typedef struct {
  *                        res.W[C][C], res.b[C]   (absent in the last layer),
  *                        skip.W[S][C], skip.b[S];
  *           h1.W[H][S], h1.b[H], h2.W[1][H], h2.b[1]
+ *   kind 2: for branch b = 0, 1: the kind-1 tensors from in.W[C][1] to the
+ *           last skip.b[S]; then h1.W[H][2S], h1.b[H], h2.W[1][H], h2.b[1]
  *   Kernel tap 0 multiplies x[t - d], tap 1 multiplies x[t]. */
 int64_t gwd_num_params(const gwd_arch* arch);
 
 /* Input samples that influence one output sample: 1 + (kernel-1) * sum of
- * dilations (16 and 3070 for the two members above), or -1 if invalid. */
+ * dilations (16 for the plain member, 3070 for the gated and two-branch
+ * members), or -1 if invalid. */
 int32_t gwd_receptive_field(const gwd_arch* arch);
 
 /* Copy, pack and (for BF16 / FP8) quantise the weights of n_members members

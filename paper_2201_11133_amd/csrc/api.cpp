@@ -32,11 +32,12 @@ gwd_status hip_fail(hipError_t e, const char* what) {
 
 static bool arch_valid(const gwd_arch* a) {
     if (!a) return false;
-    if (a->kind != 0 && a->kind != 1) return false;
+    if (a->kind < 0 || a->kind > 2) return false;
     if (a->in_channels < 1 || a->channels < 1 || a->n_stacks < 1 || a->layers_per_stack < 1) return false;
     if (a->layers_per_stack > 24 || a->n_stacks * a->layers_per_stack > 256) return false;
     if (a->kernel_size < 1 || a->kernel_size > 8) return false;
-    if (a->kind == 1) {
+    if (a->kind == 2 && a->in_channels != 2) return false;   // one branch per detector
+    if (a->kind >= 1) {
         if (a->skip_channels < 1 || a->head_channels < 1) return false;
         if (a->kernel_size != 2) return false;
         if (a->input_kernel < 1 || a->input_kernel > 2) return false;
@@ -50,15 +51,81 @@ static bool arch_supported(const gwd_arch* a) {
     if (a->kind == 0)
         return a->in_channels == 2 && a->channels == 16 && a->n_stacks * a->layers_per_stack == 4 &&
                a->layers_per_stack >= 4 && a->kernel_size == 2;
+    if (a->kind == 2)   // two branches of kC/2 channels: the block-diagonal image of one kC-channel trunk
+        return a->channels == kC / 2 && a->skip_channels == kC / 2 && a->head_channels == kC &&
+               a->kernel_size == 2 && a->input_kernel == 1;
     return a->in_channels == 2 && a->channels == kC && a->skip_channels == kC && a->head_channels == kC &&
            a->kernel_size == 2 && a->input_kernel == 1;
+}
+
+// The two-branch member (one gated WaveNet per detector, skip sums concatenated, one head) equals the
+// single trunk of twice the width whose weights are block-diagonal: branch b owns residual and skip
+// channels [bC, (b+1)C), dilated outputs [bC, (b+1)C) of the tanh half and 2C + [bC, (b+1)C) of the
+// sigmoid half, and reads input channel b only. Writes the trunk blob (kind-1 order) of one member.
+static void expand_two_branch(const gwd_arch* a, const float* src, std::vector<float>& dst) {
+    const int64_t C = a->channels, S = a->skip_channels, H = a->head_channels;
+    const int64_t C2 = 2 * C, S2 = 2 * S;
+    const int L = a->n_stacks * a->layers_per_stack;
+    // trunk offsets
+    std::vector<int64_t> t_dil(L), t_res(L), t_skip(L);
+    int64_t o = 0;
+    const int64_t t_inw = o; o += C2 * 2;
+    const int64_t t_inb = o; o += C2;
+    for (int l = 0; l < L; ++l) {
+        t_dil[l] = o; o += 2 * C2 * C2 * 2 + 2 * C2;
+        t_res[l] = o; if (l < L - 1) o += C2 * C2 + C2;
+        t_skip[l] = o; o += S2 * C2 + S2;
+    }
+    const int64_t t_head = o;
+    o += H * S2 + H + H + 1;
+    dst.assign((size_t)o, 0.0f);
+    // branch blobs: in.W[C][1], in.b[C], then per layer dil.W[2C][C][2], dil.b[2C], res.W[C][C], res.b[C]
+    // (not in the last layer), skip.W[S][C], skip.b[S]
+    const float* q = src;
+    for (int b = 0; b < 2; ++b) {
+        for (int64_t c = 0; c < C; ++c) dst[t_inw + (b * C + c) * 2 + b] = q[c];
+        q += C;
+        for (int64_t c = 0; c < C; ++c) dst[t_inb + b * C + c] = q[c];
+        q += C;
+        for (int l = 0; l < L; ++l) {
+            float* dw = &dst[t_dil[l]];
+            float* db = dw + 2 * C2 * C2 * 2;
+            for (int half = 0; half < 2; ++half)
+                for (int64_t oo = 0; oo < C; ++oo) {
+                    const int64_t to = half * C2 + b * C + oo;     // trunk output channel
+                    const int64_t bo = half * C + oo;              // branch output channel
+                    for (int64_t i = 0; i < C; ++i)
+                        for (int k = 0; k < 2; ++k) dw[(to * C2 + b * C + i) * 2 + k] = q[(bo * C + i) * 2 + k];
+                }
+            q += 2 * C * C * 2;
+            for (int half = 0; half < 2; ++half)
+                for (int64_t oo = 0; oo < C; ++oo) db[half * C2 + b * C + oo] = q[half * C + oo];
+            q += 2 * C;
+            if (l < L - 1) {
+                float* rw = &dst[t_res[l]];
+                for (int64_t r = 0; r < C; ++r)
+                    for (int64_t i = 0; i < C; ++i) rw[(b * C + r) * C2 + b * C + i] = q[r * C + i];
+                q += C * C;
+                for (int64_t r = 0; r < C; ++r) rw[C2 * C2 + b * C + r] = q[r];
+                q += C;
+            }
+            float* sw = &dst[t_skip[l]];
+            for (int64_t r = 0; r < S; ++r)
+                for (int64_t i = 0; i < C; ++i) sw[(b * S + r) * C2 + b * C + i] = q[r * C + i];
+            q += S * C;
+            for (int64_t r = 0; r < S; ++r) sw[S2 * C2 + b * S + r] = q[r];
+            q += S;
+        }
+    }
+    // the head reads the concatenated skip sums: the same tensors in the same order
+    std::copy(q, q + (H * S2 + H + H + 1), dst.begin() + t_head);
 }
 
 static int64_t rf_of(const gwd_arch* a) {
     int64_t s = 0;
     for (int l = 0; l < a->n_stacks * a->layers_per_stack; ++l) s += (int64_t)1 << (l % a->layers_per_stack);
     int64_t rf = 1 + (int64_t)(a->kernel_size - 1) * s;
-    if (a->kind == 1) rf += a->input_kernel - 1;
+    if (a->kind >= 1) rf += a->input_kernel - 1;
     return rf;
 }
 
@@ -264,13 +331,15 @@ int64_t gwd_num_params(const gwd_arch* a) {
         return n + C + 1;
     }
     const int64_t S = a->skip_channels, H = a->head_channels;
-    int64_t n = C * a->in_channels * a->input_kernel + C;
+    const int64_t branches = a->kind == 2 ? 2 : 1;            // kind 2: one single-channel trunk per detector
+    const int64_t cin = a->kind == 2 ? 1 : a->in_channels;
+    int64_t n = C * cin * a->input_kernel + C;
     for (int l = 0; l < L; ++l) {
         n += 2 * C * C * 2 + 2 * C;
         if (l < L - 1) n += C * C + C;
         n += S * C + S;
     }
-    return n + H * S + H + H + 1;
+    return branches * n + H * S * branches + H + H + 1;
 }
 
 int32_t gwd_receptive_field(const gwd_arch* a) {
@@ -290,7 +359,7 @@ gwd_status gwd_load_weights(const gwd_arch* arch, int32_t n_members, const float
     if (precision != GWD_FP32 && precision != GWD_BF16 && precision != GWD_FP8_E4M3 && precision != GWD_FP64) { set_error("gwd_load_weights: unknown precision %d", (int)precision); return GWD_ERR_ARG; }
     if (!arch_supported(arch)) { set_error("gwd_load_weights: architecture not supported by the GPU kernels"); return GWD_ERR_UNSUPPORTED; }
     if (arch->kind == 0 && precision != GWD_FP32 && precision != GWD_FP64) { set_error("gwd_load_weights: the plain member runs in FP32 (or FP64 for training checks) only"); return GWD_ERR_UNSUPPORTED; }
-    if (arch->kind == 1 && precision == GWD_FP64) { set_error("gwd_load_weights: FP64 is for the plain member's gradient checks only"); return GWD_ERR_UNSUPPORTED; }
+    if (arch->kind >= 1 && precision == GWD_FP64) { set_error("gwd_load_weights: FP64 is for the plain member's gradient checks only"); return GWD_ERR_UNSUPPORTED; }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) { set_error("gwd_load_weights: no HIP device"); return GWD_ERR_NO_DEVICE; }
     gwd_model* m = new (std::nothrow) gwd_model();
@@ -302,24 +371,46 @@ gwd_status gwd_load_weights(const gwd_arch* arch, int32_t n_members, const float
     m->batch_windows = 512;
     hipError_t e = hipGetDevice(&m->device);
     if (e != hipSuccess) { delete m; return hip_fail(e, "hipGetDevice"); }
-    m->host_blob.assign(host_blob, host_blob + (size_t)np * n_members);
+    if (arch->kind == 2) {
+        // run as the block-diagonal trunk of twice the width: the same kernels, zero off-diagonal blocks
+        gwd_arch t = *arch;
+        t.kind = 1;
+        t.channels = 2 * arch->channels;
+        t.skip_channels = 2 * arch->skip_channels;
+        const int64_t tnp = gwd_num_params(&t);
+        std::vector<float> all;
+        all.reserve((size_t)tnp * n_members);
+        std::vector<float> one;
+        for (int i = 0; i < n_members; ++i) {
+            expand_two_branch(arch, host_blob + (size_t)np * i, one);
+            if ((int64_t)one.size() != tnp) { delete m; set_error("gwd_load_weights: internal two-branch size mismatch"); return GWD_ERR_ARG; }
+            all.insert(all.end(), one.begin(), one.end());
+        }
+        m->arch = t;
+        m->n_params = tnp;
+        m->two_branch = true;
+        m->host_blob.swap(all);
+    } else {
+        m->host_blob.assign(host_blob, host_blob + (size_t)np * n_members);
+    }
+    const int64_t npk = m->n_params;
     m->members.resize(n_members);
     m->canon.assign(n_members, nullptr);
     for (int i = 0; i < n_members; ++i) {
-        const float* src = host_blob + (size_t)np * i;
+        const float* src = m->host_blob.data() + (size_t)npk * i;
         if (precision != GWD_FP64) {
             gwd_status s = pack_member(m, i, src);
             if (s != GWD_OK) { gwd_free(m); return s; }
         }
         // canonical copy for training (fp32, or fp64 for the FP64 gradient-check model)
         const size_t es = precision == GWD_FP64 ? 8 : 4;
-        e = hipMalloc(&m->canon[i], np * es);
+        e = hipMalloc(&m->canon[i], npk * es);
         if (e != hipSuccess) { gwd_free(m); return hip_fail(e, "hipMalloc(canonical weights)"); }
         if (precision == GWD_FP64) {
-            std::vector<double> d(src, src + np);
-            e = hipMemcpy(m->canon[i], d.data(), np * 8, hipMemcpyHostToDevice);
+            std::vector<double> d(src, src + npk);
+            e = hipMemcpy(m->canon[i], d.data(), npk * 8, hipMemcpyHostToDevice);
         } else {
-            e = hipMemcpy(m->canon[i], src, np * 4, hipMemcpyHostToDevice);
+            e = hipMemcpy(m->canon[i], src, npk * 4, hipMemcpyHostToDevice);
         }
         if (e != hipSuccess) { gwd_free(m); return hip_fail(e, "hipMemcpy(canonical weights)"); }
     }

@@ -99,6 +99,7 @@ struct gwd_model {
     int32_t lp_rows = 0;                       // BF16/FP8 layer tiling: rows per tile (0 = default per precision)
     int32_t lp_waves = 0;                      // and waves per block
     int32_t lp_fuse = 3;                       // BF16: layers per launch (3 = fused triples, 1 = one per launch)
+    bool two_branch = false;                   // loaded as kind 2 and expanded to the block-diagonal kind-1 image
 };
 
 namespace gwd {

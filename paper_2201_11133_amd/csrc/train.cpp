@@ -42,6 +42,7 @@ static gwd_status check_train(const gwd_model* m, int member, const void* window
     if (B < 1 || T < 1) { set_error("%s: bad batch shape", who); return GWD_ERR_SHAPE; }
     if (m->arch.kind == 1 && T % 128 != 0) { set_error("%s: window %d must be a multiple of 128", who, T); return GWD_ERR_SHAPE; }
     if (m->arch.kind == 1 && m->prec == GWD_FP8_E4M3) { set_error("%s: FP8 models are inference only", who); return GWD_ERR_UNSUPPORTED; }
+    if (m->two_branch) { set_error("%s: the two-branch member is inference only", who); return GWD_ERR_UNSUPPORTED; }
     return GWD_OK;
 }
 
@@ -348,6 +349,7 @@ gwd_status gwd_adam_step(gwd_model* m, int32_t member, float* master, const floa
         return GWD_ERR_ARG;
     }
     if (m->prec == GWD_FP64 || m->prec == GWD_FP8_E4M3) { set_error("gwd_adam_step: FP32/BF16 models only"); return GWD_ERR_UNSUPPORTED; }
+    if (m->two_branch) { set_error("gwd_adam_step: the two-branch member is inference only"); return GWD_ERR_UNSUPPORTED; }
     hipStream_t st = (hipStream_t)hip_stream;
     hipError_t e = hipSetDevice(m->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");

@@ -59,6 +59,11 @@ def full_arch(head_mid_relu: int = 0) -> Arch:
     return Arch(1, 2, 128, 128, 128, 3, 10, 2, 1, head_mid_relu)
 
 
+def two_branch_arch(head_mid_relu: int = 0) -> Arch:
+    """One 64-channel gated branch per detector, skip sums concatenated into a 128-channel head."""
+    return Arch(2, 2, 64, 64, 128, 3, 10, 2, 1, head_mid_relu)
+
+
 def _load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with __graft_entry__.build() "
@@ -172,6 +177,10 @@ class Model:
         self.arch = arch
         self.n_members = blobs.shape[0]
         self.n_params = blobs.shape[1]
+        # a two-branch model runs (and exports) as the block-diagonal trunk of twice the width
+        self.export_params = self.n_params if arch.kind != 2 else num_params(
+            Arch(1, 2, 2 * arch.channels, 2 * arch.skip_channels, arch.head_channels, arch.n_stacks,
+                 arch.layers_per_stack, arch.kernel_size, arch.input_kernel, arch.head_mid_relu))
         self.precision = precision
         h = ctypes.c_void_p()
         check(lib.gwd_load_weights(ctypes.byref(arch), self.n_members, blobs.ctypes.data, self.n_params,
@@ -239,8 +248,8 @@ class Model:
         return Plan(self, streams, window, stride, out_mode, out)
 
     def export_weights(self, member: int = 0) -> np.ndarray:
-        out = np.zeros(self.n_params, dtype=np.float32)
-        check(lib.gwd_debug_export_weights(self.h, member, out.ctypes.data, self.n_params))
+        out = np.zeros(self.export_params, dtype=np.float32)
+        check(lib.gwd_debug_export_weights(self.h, member, out.ctypes.data, self.export_params))
         return out
 
     def debug_layer(self, member: int, layer: int, x_in, n_windows: int, window: int, pre_out, x_out, skip,

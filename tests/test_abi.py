@@ -252,3 +252,22 @@ def test_whitening_argument_errors(g):
     if not host_has_gpu():                                # (the pointers are not real buffers)
         assert whiten_call(g) == g.ERR_NO_DEVICE
         assert welch_call(g, length=5000) == g.ERR_NO_DEVICE
+
+
+def test_two_branch_counts_and_load_errors(g):
+    from oracle.arch import TWO_BRANCH, num_params, receptive_field
+    a = g.two_branch_arch()
+    assert g.num_params(a) == num_params(TWO_BRANCH) == 1_498_497
+    assert g.receptive_field(a) == receptive_field(TWO_BRANCH) == 3070
+    bad = g.two_branch_arch()
+    bad.in_channels = 3                                   # one branch per detector: exactly 2
+    assert g.num_params(bad) == -1
+    blob = np.zeros(g.num_params(a), np.float32)
+    h = ctypes.c_void_p()
+    assert g.lib.gwd_load_weights(ctypes.byref(a), 1, blob.ctypes.data, blob.size, g.FP64, ctypes.byref(h)) == g.ERR_UNSUPPORTED
+    wide = g.two_branch_arch()
+    wide.channels = wide.skip_channels = 128              # valid, but not what the kernels take
+    wb = np.zeros(g.num_params(wide), np.float32)
+    assert g.lib.gwd_load_weights(ctypes.byref(wide), 1, wb.ctypes.data, wb.size, g.FP32, ctypes.byref(h)) == g.ERR_UNSUPPORTED
+    if not host_has_gpu():
+        assert g.lib.gwd_load_weights(ctypes.byref(a), 1, blob.ctypes.data, blob.size, g.BF16, ctypes.byref(h)) == g.ERR_NO_DEVICE
