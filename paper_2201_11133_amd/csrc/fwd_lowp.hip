@@ -525,7 +525,9 @@ struct ChunkRows {
 // NL consecutive layers of one stack in one launch (NL = 3, or 4 when the sub-sequences are one chunk
 // long, so that the fourth layer's history rows are the causal zeros). LAST: the fourth layer is the
 // network's last, which writes the skip sum only (its residual projection is not part of the model).
-template <bool FROM_STREAM, bool SKIP_INIT, int NL, bool LAST>
+// G2: the weights are block-diagonal over two 64-channel groups (the two-branch member); each wave
+// then takes only the k-steps of its own group's input channels, since the others multiply zeros.
+template <bool FROM_STREAM, bool SKIP_INIT, int NL, bool LAST, bool G2>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void fused_bf16_kernel(FusedArgs p) {
     static_assert(NL == 3 || NL == 4, "three or four layers");
     static_assert(!LAST || NL == 4, "the network's last layer ends a quad");
@@ -562,6 +564,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
     // 32-row block and, of its wave's 32-channel block, the channels 8 g + 4 h + e (g, e = 0..3):
     // four runs of four consecutive channels, which move as 8- and 16-byte words.
     const int cb = 32 * q + 4 * h;
+    // The k-steps this wave takes. Wave q owns output channels [32 q, 32 q + 32) of each column half,
+    // which for G2 lie in group q / 2; that group's input channels are k-steps gk .. gk + 3 of each
+    // tap (phase 1: step s is k = 8 (s / 4) + gk + s % 4) and of the gate output (phase 2: k = gk + s),
+    // gk = 4 (q / 2). The weight, row and gate pointers are shifted by gk once, so the unrolled
+    // offsets stay constants. Skipped steps would add exact zero products, so the accumulators, and
+    // every result, are those of the full loop.
+    const int gk = G2 ? 4 * (q >> 1) : 0;
+    constexpr auto k1 = [](int s) { return G2 ? ((s & 4) << 1) + (s & 3) : s; };
+    constexpr int NS1 = G2 ? T::NK1 / 2 : T::NK1, NS2 = G2 ? T::NK2 / 2 : T::NK2;
+    const size_t wsh = (size_t)gk * 64 * T::FRAG;   // weight-fragment shift
     // Global loads retire in issue order, so a load from HBM would hold up the next wait on a
     // weight fragment. HBM rows are therefore requested right before a gate, which waits on no
     // load for thousands of cycles: the skip rows of a chunk before its first layer's gate, the
@@ -595,8 +607,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
     Frag<false> rf[T::PF1], rg[T::PF1];
 #pragma unroll
     for (int k = 0; k < FU_PRE; ++k) {
-        rf[k] = load_frag<false>(p.wc[0] + ((size_t)(q * T::NK1 + k) * 64 + lane) * T::FRAG);
-        rg[k] = load_frag<false>(p.wc[0] + ((size_t)((4 + q) * T::NK1 + k) * 64 + lane) * T::FRAG);
+        if constexpr (G2) {
+            rf[k] = load_frag<false>(p.wc[0] + ((size_t)(q * T::NK1 + gk + k1(k)) * 64 + lane) * T::FRAG);
+            rg[k] = load_frag<false>(p.wc[0] + ((size_t)((4 + q) * T::NK1 + gk + k1(k)) * 64 + lane) * T::FRAG);
+        } else {
+            rf[k] = load_frag<false>(p.wc[0] + ((size_t)(q * T::NK1 + k) * 64 + lane) * T::FRAG);
+            rg[k] = load_frag<false>(p.wc[0] + ((size_t)((4 + q) * T::NK1 + k) * 64 + lane) * T::FRAG);
+        }
     }
     // the biases of the layers, once per block (requested after the first rows and
     // weights, so the latencies overlap): [layer][conv 256 | res 128 | skip 128]
@@ -653,27 +670,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                 const uint8_t* A0 = Xin + r * FU_XROW + 16 * h;
                 const uint8_t* Bf = p.wc[j] + ((size_t)(q * T::NK1) * 64 + lane) * T::FRAG;
                 const uint8_t* Bg = p.wc[j] + ((size_t)((4 + q) * T::NK1) * 64 + lane) * T::FRAG;
+                if constexpr (G2) {
+                    A0 += 32 * gk;
+                    Bf += wsh;
+                    Bg += wsh;
+                }
 #pragma unroll
                 for (int k = FU_PRE; k < T::PF1; ++k) {
-                    rf[k] = load_frag<false>(Bf + (size_t)k * 64 * T::FRAG);
-                    rg[k] = load_frag<false>(Bg + (size_t)k * 64 * T::FRAG);
+                    rf[k] = load_frag<false>(Bf + (size_t)k1(k) * 64 * T::FRAG);
+                    rg[k] = load_frag<false>(Bg + (size_t)k1(k) * 64 * T::FRAG);
                 }
                 Frag<false> acur[2], anxt[2];
 #pragma unroll
                 for (int i = 0; i < 2; ++i) acur[i] = load_frag<false>(A0 + (32 * i - dil) * FU_XROW);
 #pragma unroll
-                for (int k = 0; k < T::NK1; ++k) {
+                for (int k = 0; k < NS1; ++k) {
                     const int slot = k % T::PF1;
                     const Frag<false> cf = rf[slot], cg = rg[slot];
-                    if (k + T::PF1 < T::NK1) {
-                        rf[slot] = load_frag<false>(Bf + (size_t)(k + T::PF1) * 64 * T::FRAG);
-                        rg[slot] = load_frag<false>(Bg + (size_t)(k + T::PF1) * 64 * T::FRAG);
+                    if (k + T::PF1 < NS1) {
+                        rf[slot] = load_frag<false>(Bf + (size_t)k1(k + T::PF1) * 64 * T::FRAG);
+                        rg[slot] = load_frag<false>(Bg + (size_t)k1(k + T::PF1) * 64 * T::FRAG);
                     }
-                    if (k + 1 < T::NK1) {
-                        const int roff = k + 1 < T::NK1 / 2 ? -dil : 0;
+                    if (k + 1 < NS1) {
+                        const int roff = k1(k + 1) < T::NK1 / 2 ? -dil : 0;
 #pragma unroll
                         for (int i = 0; i < 2; ++i)
-                            anxt[i] = load_frag<false>(A0 + (32 * i + roff) * FU_XROW + 32 * ((k + 1) & 7));
+                            anxt[i] = load_frag<false>(A0 + (32 * i + roff) * FU_XROW + 32 * (k1(k + 1) & 7));   // gk in A0
                     }
                     __builtin_amdgcn_sched_barrier(0);  // the next step's loads issue before this step's MFMAs
 #pragma unroll
@@ -692,6 +714,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
             // products are then computed from those same fragments and not used)
             const uint8_t* Wr = p.wrs[j] + ((size_t)(q * T::NK2) * 64 + lane) * T::FRAG;
             const uint8_t* Ws = p.wrs[j] + ((size_t)((resid ? 4 + q : q) * T::NK2) * 64 + lane) * T::FRAG;
+            if constexpr (G2) {
+                Wr += wsh;
+                Ws += wsh;
+            }
             Frag<false> ringr[FU_PF2], rings[FU_PF2];
 #pragma unroll
             for (int k = 0; k < FU_PF2; ++k) {
@@ -737,28 +763,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
             __syncthreads();
             // ---- phase 2 over G (K = 128): each g fragment feeds the residual and the skip columns
             const uint8_t* Ag = G + r * FU_XROW + 16 * h;
+            if constexpr (G2) Ag += 32 * gk;
             const int jn = j < NL - 1 ? j + 1 : 0;  // the next layer (the first of the next chunk after the last)
             const uint8_t* Nf = p.wc[jn] + ((size_t)(q * T::NK1) * 64 + lane) * T::FRAG;
             const uint8_t* Ng = p.wc[jn] + ((size_t)((4 + q) * T::NK1) * 64 + lane) * T::FRAG;
+            if constexpr (G2) {
+                Nf += wsh;
+                Ng += wsh;
+            }
             floatx16 ar[2], as[2];
             {
                 Frag<false> acur[2], anxt[2];
 #pragma unroll
                 for (int i = 0; i < 2; ++i) acur[i] = load_frag<false>(Ag + 32 * i * FU_XROW);
 #pragma unroll
-                for (int k = 0; k < T::NK2; ++k) {
+                for (int k = 0; k < NS2; ++k) {
                     const int slot = k % FU_PF2;
                     const Frag<false> cwr = ringr[slot], cws = rings[slot];
-                    if (k + FU_PF2 < T::NK2) {
+                    if (k + FU_PF2 < NS2) {
                         ringr[slot] = load_frag<false>(Wr + (size_t)(k + FU_PF2) * 64 * T::FRAG);
                         rings[slot] = load_frag<false>(Ws + (size_t)(k + FU_PF2) * 64 * T::FRAG);
-                    } else if (k - (T::NK2 - FU_PF2) < FU_PRE && more) {
+                    } else if (k - (NS2 - FU_PF2) < FU_PRE && more) {
                         // the next layer's first-phase ring, in registers this phase leaves free
-                        const int kk = k - (T::NK2 - FU_PF2);
-                        rf[kk] = load_frag<false>(Nf + (size_t)kk * 64 * T::FRAG);
-                        rg[kk] = load_frag<false>(Ng + (size_t)kk * 64 * T::FRAG);
+                        const int kk = k - (NS2 - FU_PF2);
+                        rf[kk] = load_frag<false>(Nf + (size_t)k1(kk) * 64 * T::FRAG);
+                        rg[kk] = load_frag<false>(Ng + (size_t)k1(kk) * 64 * T::FRAG);
                     }
-                    if (k + 1 < T::NK2) {
+                    if (k + 1 < NS2) {
 #pragma unroll
                         for (int i = 0; i < 2; ++i) anxt[i] = load_frag<false>(Ag + 32 * i * FU_XROW + 32 * (k + 1));
                     }
@@ -1092,6 +1123,12 @@ static int fused_layers(const gwd_model* m, int l, int T) {
 }
 
 // One fused launch of layers l .. l + nl - 1 over nb windows of length T.
+template <bool FROM_STREAM, bool SKIP_INIT, int NL, bool LAST>
+static void launch_fused_bf16(bool g2, dim3 grid, hipStream_t st, const FusedArgs& a) {
+    if (g2) hipLaunchKernelGGL((fused_bf16_kernel<FROM_STREAM, SKIP_INIT, NL, LAST, true>), grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((fused_bf16_kernel<FROM_STREAM, SKIP_INIT, NL, LAST, false>), grid, dim3(256), 0, st, a);
+}
+
 template <bool FP8>
 static hipError_t launch_fused(gwd_model* m, int member, int l, int nl, const uint16_t* x_in, uint16_t* x_out,
                                float* skip, int nb, int T, const FwdBatch* fb, hipStream_t st) {
@@ -1136,13 +1173,14 @@ static hipError_t launch_fused(gwd_model* m, int member, int l, int nl, const ui
         else if (first) hipLaunchKernelGGL((fused3_fp8_kernel<false, true>), grid, dim3(256), 0, st, a);
         else hipLaunchKernelGGL((fused3_fp8_kernel<false, false>), grid, dim3(256), 0, st, a);
     } else if (nl == 3) {
-        if (stream_in) hipLaunchKernelGGL((fused_bf16_kernel<true, true, 3, false>), grid, dim3(256), 0, st, a);
-        else if (first) hipLaunchKernelGGL((fused_bf16_kernel<false, true, 3, false>), grid, dim3(256), 0, st, a);
-        else hipLaunchKernelGGL((fused_bf16_kernel<false, false, 3, false>), grid, dim3(256), 0, st, a);
+        const bool g2 = m->two_branch;   // block-diagonal weights: skip the zero blocks
+        if (stream_in) launch_fused_bf16<true, true, 3, false>(g2, grid, st, a);
+        else if (first) launch_fused_bf16<false, true, 3, false>(g2, grid, st, a);
+        else launch_fused_bf16<false, false, 3, false>(g2, grid, st, a);
     } else {
         if (first) return hipErrorInvalidValue;                          // stacks of at least 10 layers
-        if (l + 3 == L - 1) hipLaunchKernelGGL((fused_bf16_kernel<false, false, 4, true>), grid, dim3(256), 0, st, a);
-        else hipLaunchKernelGGL((fused_bf16_kernel<false, false, 4, false>), grid, dim3(256), 0, st, a);
+        if (l + 3 == L - 1) launch_fused_bf16<false, false, 4, true>(m->two_branch, grid, st, a);
+        else launch_fused_bf16<false, false, 4, false>(m->two_branch, grid, st, a);
     }
     return hipGetLastError();
 }
