@@ -163,3 +163,46 @@ def pack(a: Arch, params: Dict[str, np.ndarray]) -> np.ndarray:
     """Inverse of unpack: named arrays -> flat float64 blob in canonical order."""
     return np.concatenate([np.asarray(params[name], dtype=np.float64).reshape(-1)
                            for name, _, _ in layout(a)])
+
+
+def two_branch_blocks(a: Arch):
+    """(branch tensor name, its index, trunk tensor name, trunk index) for every tensor of a kind-2
+    member: where it sits in the single trunk of twice the width that the member equals when that
+    trunk's weights are block-diagonal (branch b owns residual and skip channels [bC, (b+1)C), the
+    same slice of each half of the dilated output, and input channel b). The head is shared."""
+    C, S = a.channels, a.skip_channels
+    out = []
+    for b in range(2):
+        r, sk = slice(b * C, (b + 1) * C), slice(b * S, (b + 1) * S)
+        out.append((f"b{b}.in.W", (slice(None), 0), "in.W", (r, b)))
+        out.append((f"b{b}.in.b", (slice(None),), "in.b", (r,)))
+        for l in range(a.n_layers):
+            for half in range(2):
+                hs = slice(half * C, (half + 1) * C)
+                o = slice(half * 2 * C + b * C, half * 2 * C + (b + 1) * C)
+                out.append((f"b{b}.dil{l}.W", (hs,), f"dil{l}.W", (o, r)))
+                out.append((f"b{b}.dil{l}.b", (hs,), f"dil{l}.b", (o,)))
+            if l < a.n_layers - 1:
+                out.append((f"b{b}.res{l}.W", (slice(None),), f"res{l}.W", (r, r)))
+                out.append((f"b{b}.res{l}.b", (slice(None),), f"res{l}.b", (r,)))
+            out.append((f"b{b}.skip{l}.W", (slice(None),), f"skip{l}.W", (sk, r)))
+            out.append((f"b{b}.skip{l}.b", (slice(None),), f"skip{l}.b", (sk,)))
+    for n in ("h1.W", "h1.b", "h2.W", "h2.b"):
+        out.append((n, (slice(None),), n, (slice(None),)))
+    return out
+
+
+def two_branch_trunk_arch(a: Arch) -> Arch:
+    return Arch(kind=1, in_channels=2, channels=2 * a.channels, skip_channels=2 * a.skip_channels,
+                head_channels=a.head_channels, n_stacks=a.n_stacks, layers_per_stack=a.layers_per_stack,
+                kernel_size=a.kernel_size, input_kernel=a.input_kernel, head_mid_relu=a.head_mid_relu)
+
+
+def two_branch_as_trunk(a: Arch, p: Dict[str, np.ndarray]):
+    """(trunk arch, trunk params) of the block-diagonal trunk a kind-2 member equals."""
+    t = two_branch_trunk_arch(a)
+    q = {n: np.zeros(s) for n, s, _ in layout(t)}
+    for bn, bi, tn, ti in two_branch_blocks(a):
+        q[tn][ti] = p[bn][bi]
+    return t, q
+

@@ -20,7 +20,7 @@ from typing import Dict, Tuple
 
 import numpy as np
 
-from .arch import Arch, layout, unpack
+from .arch import Arch, layout, pack, two_branch_as_trunk, two_branch_blocks, unpack
 from .forward import causal_conv, gated_layer, input_projection, relu, shift_right, sigmoid
 
 
@@ -63,6 +63,17 @@ def _conv_backward(x: np.ndarray, W: np.ndarray, dy: np.ndarray, d: int):
 def loss_and_grad(a: Arch, blob: np.ndarray, u: np.ndarray, y: np.ndarray
                   ) -> Tuple[float, np.ndarray, np.ndarray]:
     """(loss, d loss / d blob [n_params], d loss / d u) for windows u [B, T, 2] and labels y [B, T]."""
+    if a.kind == 2:
+        # the member equals its block-diagonal trunk, whose weights are a linear (selection) image of
+        # the branch tensors: the branch gradient is the trunk gradient read back at those positions
+        p2 = unpack(a, blob)
+        t, q = two_branch_as_trunk(a, p2)
+        loss, gt, du = loss_and_grad(t, pack(t, q), u, y)
+        gq = unpack(t, gt)
+        gb = {n: np.zeros(s) for n, s, _ in layout(a)}
+        for bn, bi, tn, ti in two_branch_blocks(a):
+            gb[bn][bi] = gq[tn][ti]
+        return loss, pack(a, gb), du
     p = unpack(a, blob)
     u = np.asarray(u, dtype=np.float64)
     g: Dict[str, np.ndarray] = {}

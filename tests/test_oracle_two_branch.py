@@ -80,8 +80,8 @@ def test_tiny_brute_force(seed):
 
 def block_diagonal(a, p):
     """The single-trunk member (kind 1, channels 2C) whose weights are block-diagonal copies of the
-    two branches: branch b owns residual and skip channels [bC, (b+1)C) and, in each half of the
-    dilated output, the same slice."""
+    two branches, written out here slice by slice: branch b owns residual and skip channels
+    [bC, (b+1)C) and, in each half of the dilated output, the same slice."""
     C, S = a.channels, a.skip_channels
     t = Arch(kind=1, in_channels=2, channels=2 * C, skip_channels=2 * S, head_channels=a.head_channels,
              n_stacks=a.n_stacks, layers_per_stack=a.layers_per_stack)
@@ -155,3 +155,44 @@ def test_receptive_field_and_causality():
         v[t + 1:, ch] += 3.0                           # the future does not matter either
         assert np.array_equal(last_skip(v, ch), last_skip(u, ch))
         assert forward_window(a, p, v)[t] == z[t]
+
+
+def test_oracle_trunk_image_matches_slices():
+    """The oracle's own block map gives the same trunk as the slice-by-slice statement above."""
+    from oracle.arch import two_branch_as_trunk
+    a = Arch(kind=2, in_channels=2, channels=3, skip_channels=2, head_channels=4, n_stacks=1, layers_per_stack=3)
+    p = rand_params(a, 12)
+    t1, q1 = block_diagonal(a, p)
+    t2, q2 = two_branch_as_trunk(a, p)
+    assert t1 == t2
+    assert all(np.array_equal(q1[n], q2[n]) for n in q1)
+
+
+def test_gradient_by_central_differences():
+    """The two-branch gradient (the trunk's reverse mode read back through the block map) against
+    central differences of the two-branch forward itself, every parameter of a tiny member."""
+    from oracle.arch import pack
+    from oracle.train import loss_and_grad, loss_only
+    a = Arch(kind=2, in_channels=2, channels=2, skip_channels=2, head_channels=3, n_stacks=1, layers_per_stack=3,
+             head_mid_relu=1)
+    rng = np.random.default_rng(3)
+    blob = pack(a, rand_params(a, 13, 0.6))
+    u = rng.standard_normal((2, 20, 2))
+    y = (rng.uniform(size=(2, 20)) < 0.3).astype(float)
+    loss, g, du = loss_and_grad(a, blob, u, y)
+    assert abs(loss - loss_only(a, blob, u, y)) < 1e-14
+    h = 1e-6
+    fd = np.empty_like(blob)
+    for i in range(blob.size):
+        e = np.zeros_like(blob)
+        e[i] = h
+        fd[i] = (loss_only(a, blob + e, u, y) - loss_only(a, blob - e, u, y)) / (2 * h)
+    assert np.max(np.abs(fd - g)) < 1e-7 * max(1.0, np.max(np.abs(g)))
+    # the input gradient as well (two channels, each through its own branch)
+    fdu = np.empty_like(u)
+    for idx in np.ndindex(u.shape):
+        e = np.zeros_like(u)
+        e[idx] = h
+        fdu[idx] = (loss_only(a, blob, u + e, y) - loss_only(a, blob, u - e, y)) / (2 * h)
+    assert np.max(np.abs(fdu - du)) < 1e-7 * max(1.0, np.max(np.abs(du)))
+
