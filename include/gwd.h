@@ -89,9 +89,12 @@ typedef enum {
  * in_channels 2, kernel 2, input_kernel 1; kind 2 with channels =
  * skip_channels = 64, head_channels = 128, kernel 2, input_kernel 1, which
  * gwd_load_weights expands into the block-diagonal kind-1 member of 128
- * channels and runs on the same kernels (inference only: the training entry
- * points return GWD_ERR_UNSUPPORTED; gwd_debug_export_weights returns the
- * expanded kind-1 blob). */
+ * channels and runs on the same kernels; its BF16 fused kernels skip the
+ * zero blocks. Training (FP32 and BF16 models) takes and returns the kind-2
+ * blob layout: gwd_backward writes dL/dparams of the branch blob (the trunk
+ * image's gradient read back at each branch parameter's place) and
+ * gwd_adam_step updates the branch blob, then re-expands the working weights.
+ * gwd_debug_export_weights returns the expanded kind-1 blob. */
 typedef struct {
     int32_t kind;
     int32_t in_channels;

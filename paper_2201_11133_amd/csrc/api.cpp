@@ -62,7 +62,7 @@ static bool arch_supported(const gwd_arch* a) {
 // single trunk of twice the width whose weights are block-diagonal: branch b owns residual and skip
 // channels [bC, (b+1)C), dilated outputs [bC, (b+1)C) of the tanh half and 2C + [bC, (b+1)C) of the
 // sigmoid half, and reads input channel b only. Writes the trunk blob (kind-1 order) of one member.
-static void expand_two_branch(const gwd_arch* a, const float* src, std::vector<float>& dst) {
+void expand_two_branch(const gwd_arch* a, const float* src, std::vector<float>& dst) {
     const int64_t C = a->channels, S = a->skip_channels, H = a->head_channels;
     const int64_t C2 = 2 * C, S2 = 2 * S;
     const int L = a->n_stacks * a->layers_per_stack;
@@ -386,6 +386,23 @@ gwd_status gwd_load_weights(const gwd_arch* arch, int32_t n_members, const float
             if ((int64_t)one.size() != tnp) { delete m; set_error("gwd_load_weights: internal two-branch size mismatch"); return GWD_ERR_ARG; }
             all.insert(all.end(), one.begin(), one.end());
         }
+        // where each branch parameter sits in the trunk blob (for the gradient read-back): expand the
+        // indices themselves (1-based, exact in float below 2^24)
+        if (np >= (1 << 24)) { delete m; set_error("gwd_load_weights: two-branch blob too large"); return GWD_ERR_ARG; }
+        std::vector<float> ids((size_t)np);
+        for (int64_t i = 0; i < np; ++i) ids[i] = (float)(i + 1);
+        expand_two_branch(arch, ids.data(), one);
+        std::vector<int64_t> map((size_t)np, -1);
+        for (int64_t d = 0; d < tnp; ++d)
+            if (one[d] != 0.0f) map[(int64_t)one[d] - 1] = d;
+        for (int64_t i = 0; i < np; ++i)
+            if (map[i] < 0) { delete m; set_error("gwd_load_weights: internal two-branch map incomplete"); return GWD_ERR_ARG; }
+        e = hipMalloc((void**)&m->branch_map, np * 8);
+        if (e != hipSuccess) { delete m; return hip_fail(e, "hipMalloc(branch map)"); }
+        e = hipMemcpy(m->branch_map, map.data(), np * 8, hipMemcpyHostToDevice);
+        if (e != hipSuccess) { (void)hipFree(m->branch_map); delete m; return hip_fail(e, "hipMemcpy(branch map)"); }
+        m->branch_arch = *arch;
+        m->branch_params = np;
         m->arch = t;
         m->n_params = tnp;
         m->two_branch = true;
@@ -427,6 +444,8 @@ void gwd_free(gwd_model* m) {
         if (c) (void)hipFree(c);
     if (m->ws.base) (void)hipFree(m->ws.base);
     if (m->tws.base) (void)hipFree(m->tws.base);
+    if (m->branch_map) (void)hipFree(m->branch_map);
+    if (m->dense_grad) (void)hipFree(m->dense_grad);
     delete m;
 }
 

@@ -100,7 +100,16 @@ struct gwd_model {
     int32_t lp_waves = 0;                      // and waves per block
     int32_t lp_fuse = 3;                       // BF16: layers per launch (3 = fused triples, 1 = one per launch)
     bool two_branch = false;                   // loaded as kind 2 and expanded to the block-diagonal kind-1 image
+    gwd_arch branch_arch{};                    // kind 2: the architecture as loaded
+    int64_t branch_params = 0;                 // kind 2: parameters of one member in its own (branch) blob
+    int64_t* branch_map = nullptr;             // kind 2: device [branch_params], trunk index of each branch parameter
+    float* dense_grad = nullptr;               // kind 2: device [n_params], the trunk gradient before read-back
 };
+
+namespace gwd {
+// The trunk blob (kind-1 order) of one kind-2 member: its block-diagonal image.
+void expand_two_branch(const gwd_arch* a, const float* src, std::vector<float>& dst);
+}
 
 namespace gwd {
 

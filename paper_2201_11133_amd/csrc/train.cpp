@@ -42,7 +42,6 @@ static gwd_status check_train(const gwd_model* m, int member, const void* window
     if (B < 1 || T < 1) { set_error("%s: bad batch shape", who); return GWD_ERR_SHAPE; }
     if (m->arch.kind == 1 && T % 128 != 0) { set_error("%s: window %d must be a multiple of 128", who, T); return GWD_ERR_SHAPE; }
     if (m->arch.kind == 1 && m->prec == GWD_FP8_E4M3) { set_error("%s: FP8 models are inference only", who); return GWD_ERR_UNSUPPORTED; }
-    if (m->two_branch) { set_error("%s: the two-branch member is inference only", who); return GWD_ERR_UNSUPPORTED; }
     return GWD_OK;
 }
 
@@ -333,6 +332,18 @@ gwd_status gwd_backward(gwd_model* m, int32_t member, const float* windows, int3
         }
         return e == hipSuccess ? GWD_OK : hip_fail(e, "small member backward");
     }
+    if (m->two_branch) {
+        // the trunk gradient of the block-diagonal image, read back at the branch parameters' places
+        if (!m->dense_grad) {
+            hipError_t e = hipMalloc((void**)&m->dense_grad, m->n_params * 4);
+            if (e != hipSuccess) return hip_fail(e, "hipMalloc(two-branch trunk gradient)");
+        }
+        gwd_status s = bwd_kind1(m, member, windows, B, W, (const float*)saved, (const float*)grad_logit, m->dense_grad,
+                                 (float*)grad_input, st);
+        if (s != GWD_OK) return s;
+        hipError_t e = launch_gather(m->dense_grad, m->branch_map, m->branch_params, (float*)grad_params, st);
+        return e == hipSuccess ? GWD_OK : hip_fail(e, "gradient read-back");
+    }
     return bwd_kind1(m, member, windows, B, W, (const float*)saved, (const float*)grad_logit, (float*)grad_params,
                      (float*)grad_input, st);
 }
@@ -349,11 +360,10 @@ gwd_status gwd_adam_step(gwd_model* m, int32_t member, float* master, const floa
         return GWD_ERR_ARG;
     }
     if (m->prec == GWD_FP64 || m->prec == GWD_FP8_E4M3) { set_error("gwd_adam_step: FP32/BF16 models only"); return GWD_ERR_UNSUPPORTED; }
-    if (m->two_branch) { set_error("gwd_adam_step: the two-branch member is inference only"); return GWD_ERR_UNSUPPORTED; }
     hipStream_t st = (hipStream_t)hip_stream;
     hipError_t e = hipSetDevice(m->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-    const int64_t n = m->n_params;
+    const int64_t n = m->two_branch ? m->branch_params : m->n_params;   // the caller's blob layout
     const int64_t nb = (n + 255) / 256;
     double* part = nullptr;
     e = hipMallocAsync((void**)&part, nb * sizeof(double), st);
@@ -362,6 +372,18 @@ gwd_status gwd_adam_step(gwd_model* m, int32_t member, float* master, const floa
     if (e != hipSuccess) return hip_fail(e, "adam kernel");
     (void)hipFreeAsync(part, st);
     // refresh the member's working weights from the new master weights
+    if (m->two_branch) {   // expand to the block-diagonal trunk, then as below
+        std::vector<float> hb2((size_t)n), dense;
+        e = hipMemcpyAsync(hb2.data(), master, n * 4, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy(master to host)");
+        expand_two_branch(&m->branch_arch, hb2.data(), dense);
+        float* hb = m->host_blob.data() + (size_t)member * m->n_params;
+        std::copy(dense.begin(), dense.end(), hb);
+        e = hipMemcpy(m->canon[member], hb, m->n_params * 4, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy(trunk weights)");
+        return pack_member(m, member, hb);
+    }
     e = hipMemcpyAsync(m->canon[member], master, n * 4, hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(master)");
     float* hb = m->host_blob.data() + (size_t)member * n;

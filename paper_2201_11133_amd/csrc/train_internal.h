@@ -74,6 +74,7 @@ hipError_t launch_head_logit(const float* h, int64_t M, const float* w2, const f
 hipError_t launch_input_grad(const float* dx0, int64_t M, const float* w_in, float* du, hipStream_t st);
 hipError_t launch_relu_copy(const float* x, int64_t n, float* y, hipStream_t st);
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t st);
+hipError_t launch_gather(const float* src, const int64_t* idx, int64_t n, float* dst, hipStream_t st);
 hipError_t launch_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
                        float eps, int64_t step, double* norm_part, double* norm_out, hipStream_t st);
 hipError_t launch_bce(const float* z, const float* y, int64_t n, float* grad, double* part, double* loss,

@@ -744,6 +744,17 @@ hipError_t launch_relu_copy(const float* x, int64_t n, float* y, hipStream_t st)
     hipLaunchKernelGGL(relu_copy_kernel, dim3(nblk(n)), dim3(256), 0, st, x, n, y);
     return hipGetLastError();
 }
+// dst[i] = src[idx[i]]: the two-branch member's gradient read back from its block-diagonal trunk's
+__global__ void gather_kernel(const float* src, const int64_t* idx, int64_t n, float* dst) {
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) dst[i] = src[idx[i]];
+}
+
+hipError_t launch_gather(const float* src, const int64_t* idx, int64_t n, float* dst, hipStream_t st) {
+    hipLaunchKernelGGL(gather_kernel, dim3(nblk(n)), dim3(256), 0, st, src, idx, n, dst);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t st) {
     hipLaunchKernelGGL(fill_kernel, dim3(nblk(n)), dim3(256), 0, st, p, n, v);
     return hipGetLastError();

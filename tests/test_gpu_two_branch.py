@@ -115,13 +115,82 @@ def test_low_precision_error_stated(g, blob, dense, prec):
     m.close()
 
 
-def test_training_is_refused(g, blob):
-    m = g.Model(g.two_branch_arch(), blob, "bf16")
+def test_fp8_training_is_refused(g, blob):
+    m = g.Model(g.two_branch_arch(), blob, "fp8")
     B, W = 2, 4096
     w = torch.zeros((B, W, 2), dtype=torch.float32, device="cuda")
     z = torch.zeros((B, W), dtype=torch.float32, device="cuda")
     rc = g.lib.gwd_forward_train(m.h, 0, w.data_ptr(), B, W, z.data_ptr(), z.data_ptr(), None)
     assert rc == g.ERR_UNSUPPORTED
+    m.close()
+
+
+def test_gradient_fp32(g, blob):
+    """FP32 training pass of the two-branch member: the gradient in its own blob layout (read back from
+    the trunk image's) and the input gradient, per tensor against the oracle."""
+    from oracle.arch import TWO_BRANCH, layout
+    from oracle.train import bce_grad, loss_and_grad
+    from paper_2201_11133_amd import synth
+    from tests.test_gpu_train import backward, fwd_train, labels
+    print("case: two-branch fp32 gradient", flush=True)
+    B, T = 2, 512
+    u, _ = synth.make_windows(310, B, 1, W=T)
+    y = labels(B, T, 7)
+    m = g.Model(g.two_branch_arch(), blob, "fp32")
+    u_d = to_dev(u)
+    z, saved = fwd_train(g, m, u_d, B, T, torch.float32)
+    zz = z.cpu().numpy().astype(np.float64)
+    dz = torch.from_numpy(bce_grad(zz, y).astype(np.float32)).cuda()
+    grad, du = backward(g, m, u_d, B, T, saved, dz, torch.float32)   # m.n_params: the branch blob
+    _, g_ref, du_ref = loss_and_grad(TWO_BRANCH, blob.astype(np.float64), u.astype(np.float64), y)
+    gg = grad.cpu().numpy().astype(np.float64)
+    assert gg.size == g_ref.size == blob.size
+    off, worst = 0, 0.0
+    for name, shape, _ in layout(TWO_BRANCH):
+        n = int(np.prod(shape))
+        r = np.linalg.norm(gg[off:off + n] - g_ref[off:off + n]) / (np.linalg.norm(g_ref[off:off + n]) + 1e-30)
+        worst = max(worst, r)
+        assert r < 2e-3, (name, r)
+        off += n
+    rel_u = np.linalg.norm(du.cpu().numpy() - du_ref) / np.linalg.norm(du_ref)
+    print(f"  two-branch gradient: worst per-tensor relative error {worst:.3g}, input grad {rel_u:.3g}", flush=True)
+    assert rel_u < 2e-3
+    m.close()
+
+
+def test_adam_and_weight_refresh(g, blob):
+    """Adam on the two-branch blob; the working weights follow as the block-diagonal image of the new
+    master weights, and the next forward uses them."""
+    from oracle.arch import TWO_BRANCH, pack, two_branch_as_trunk, unpack
+    from oracle.train import adam_step
+    print("case: two-branch adam", flush=True)
+    n = blob.size
+    m = g.Model(g.two_branch_arch(), blob, "bf16")
+    rng = np.random.default_rng(2)
+    grad = (rng.standard_normal(n) * 1e-3).astype(np.float32)
+    w, gd = to_dev(blob.copy()), to_dev(grad)
+    mo = torch.zeros(n, dtype=torch.float32, device="cuda")
+    ve = torch.zeros(n, dtype=torch.float32, device="cuda")
+    norm = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ref_w, ref_m, ref_v = blob.astype(np.float64), np.zeros(n), np.zeros(n)
+    for step in (1, 2):
+        g.check(g.lib.gwd_adam_step(m.h, 0, w.data_ptr(), gd.data_ptr(), mo.data_ptr(), ve.data_ptr(), step, 1e-3,
+                                    0.9, 0.999, 1e-8, norm.data_ptr(), g._stream_handle(None)))
+        ref_w, ref_m, ref_v = adam_step(ref_w, grad.astype(np.float64), ref_m, ref_v, step)
+    torch.cuda.synchronize()
+    wn = w.cpu().numpy()
+    assert np.max(np.abs(wn - ref_w)) < 1e-6
+    t, q = two_branch_as_trunk(TWO_BRANCH, unpack(TWO_BRANCH, wn.astype(np.float64)))
+    from tests.test_gpu_lowp import quantised_layer_mats
+    pe = unpack(t, m.export_weights(0).astype(np.float64))
+    Bc, sc, _, _ = quantised_layer_mats("bf16", q, 5, False)
+    We = pe["dil5.W"]
+    assert np.array_equal(np.concatenate([We[:, :, 0].T, We[:, :, 1].T], axis=0), Bc)
+    # a fresh model loaded with the new weights scores the same
+    x = torch.randn((4096 + 256 * 3, 2), dtype=torch.float32, device="cuda")
+    m2 = g.Model(g.two_branch_arch(), wn, "bf16")
+    assert torch.equal(m.forward([x], 4096, 256, 0), m2.forward([x], 4096, 256, 0))
+    m2.close()
     m.close()
 
 
