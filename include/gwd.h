@@ -317,7 +317,8 @@ gwd_status gwd_coincidence(const int64_t* const* peak_lists, const int64_t* coun
  * 2^24 samples); gwd_welch_psd needs length >= nperseg (GWD_ERR_SHAPE).
  * GWD_ERR_ARG for NULL or misaligned pointers, elem_stride < 1 or normalize
  * not 0 or 1. Both use a library-owned workspace (2 L complex float32 for
- * gwd_whiten, 2 (K + 64) (nperseg/2 + 1) float64 for gwd_welch_psd) that grows on
+ * gwd_whiten, 2 G (nperseg/2 + 1) float64 for gwd_welch_psd, G = min(K, 256)
+ * for nperseg > 4096, else min(K, 1024)) that grows on
  * demand and is shared by the calls of the process: calls must not overlap
  * in time. Asynchronous on hip_stream (except when the workspace grows). */
 gwd_status gwd_welch_psd(const gwd_stream* src, int32_t nperseg, double fs, double* psd, void* hip_stream);

@@ -4,8 +4,8 @@
 //
 // Both channels travel in one complex sequence z[t] = x0[t] + i x1[t]; the spectra of the two real
 // channels separate as X0[k] = (Z[k] + conj Z[N-k]) / 2 and X1[k] = (Z[k] - conj Z[N-k]) / 2i.
-// Transforms are radix-2 decimation-in-time in LDS, one workgroup per transform, up to 16384
-// points. A stream of L = N1 N2 samples takes the four-step route: N2 transforms of length N1 down
+// Transforms are decimation-in-time in LDS (radix-2 stages taken two at a time), one workgroup per
+// transform, up to 16384 points. A stream of L = N1 N2 samples takes the four-step route: N2 transforms of length N1 down
 // the columns t = n1 N2 + n2, a twiddle e^(-2 pi i n2 k1 / L), N1 transforms of length N2 along
 // the rows; the spectrum is kept transposed (bin k1 + N1 k2 at k1 N2 + k2), which is the order
 // the inverse reads back.
@@ -51,74 +51,113 @@ __global__ void wh_twiddle_kernel(float2* tw) {
 }
 
 // In-place radix-2 DIT transform of s[0, 2^logn) (input already in bit-reversed order, output in
-// natural order); the inverse uses the conjugate twiddles and does not scale.
+// natural order); the inverse uses the conjugate twiddles and does not scale. Stages go in pairs
+// (radix 2^2): a thread takes four points base + j + {0, 1, 2, 3} * half through both stages in
+// registers, so LDS is read and written once per pair; an odd last stage runs alone.
+__device__ inline float2 tw_at(const float2* __restrict__ tw, int i, bool inverse) {
+    float2 w = tw[i];
+    if (inverse) w.y = -w.y;
+    return w;
+}
+
+__device__ inline void bfly(float2& a, float2& b, float2 w) {
+    const float2 c = cmul(b, w);
+    b = make_float2(a.x - c.x, a.y - c.y);
+    a = make_float2(a.x + c.x, a.y + c.y);
+}
+
 __device__ void lds_fft(float2* s, int logn, const float2* __restrict__ tw, bool inverse) {
-    const int half_n = 1 << (logn - 1);
-    for (int lh = 0; lh < logn; ++lh) {
+    const int n = 1 << logn;
+    int lh = 0;
+    for (; lh + 1 < logn; lh += 2) {
         const int half = 1 << lh;
-        const int tsh = WH_MAXLOG - 1 - lh;   // W_(2 half)^j = tw[j * 16384 / (2 half)]
         __syncthreads();
-        for (int b = threadIdx.x; b < half_n; b += blockDim.x) {
+        for (int b = threadIdx.x; b < (n >> 2); b += blockDim.x) {
+            const int j = b & (half - 1);
+            const int base = ((b - j) << 2) + j;
+            float2 a0 = s[base], a1 = s[base + half], a2 = s[base + 2 * half], a3 = s[base + 3 * half];
+            const float2 w1 = tw_at(tw, j << (WH_MAXLOG - 1 - lh), inverse);           // W_(2 half)^j
+            bfly(a0, a1, w1);
+            bfly(a2, a3, w1);
+            bfly(a0, a2, tw_at(tw, j << (WH_MAXLOG - 2 - lh), inverse));               // W_(4 half)^j
+            bfly(a1, a3, tw_at(tw, (j + half) << (WH_MAXLOG - 2 - lh), inverse));      // W_(4 half)^(j + half)
+            s[base] = a0;
+            s[base + half] = a1;
+            s[base + 2 * half] = a2;
+            s[base + 3 * half] = a3;
+        }
+    }
+    if (lh < logn) {   // odd number of stages: the last one on its own
+        const int half = 1 << lh;
+        __syncthreads();
+        for (int b = threadIdx.x; b < (n >> 1); b += blockDim.x) {
             const int j = b & (half - 1);
             const int i0 = ((b - j) << 1) + j;
-            const int i1 = i0 + half;
-            float2 w = tw[j << tsh];
-            if (inverse) w.y = -w.y;
-            const float2 a = s[i0];
-            const float2 c = cmul(s[i1], w);
-            s[i0] = make_float2(a.x + c.x, a.y + c.y);
-            s[i1] = make_float2(a.x - c.x, a.y - c.y);
+            float2 a0 = s[i0], a1 = s[i0 + half];
+            bfly(a0, a1, tw_at(tw, j << (WH_MAXLOG - 1 - lh), inverse));
+            s[i0] = a0;
+            s[i0 + half] = a1;
         }
     }
     __syncthreads();
 }
 
-// One Welch segment per workgroup: both channels windowed into one complex sequence, transformed,
-// separated, and |X_c[k]|^2 written in float64 to pseg[(seg * 2 + c) * h + k], h = n/2 + 1.
+// Welch: workgroup g takes the contiguous run of segments [nseg g / G, nseg (g + 1) / G) in order.
+// Each segment: both channels windowed into one complex sequence, transformed, separated; every
+// thread keeps |X_c[k]|^2 summed in float64 registers for its bins k = tid + 512 i, and the run's sums
+// go to part[(g * 2 + c) * h + k], h = n/2 + 1.
 template <int LOGMAX>
 __global__ __launch_bounds__(WH_THREADS) void wh_welch_kernel(const float* x0, const float* x1, int64_t es,
-                                                             int logn, const float2* tw, double* pseg) {
+                                                             int logn, int64_t nseg, const float2* tw,
+                                                             double* part) {
     __shared__ float2 s[1 << LOGMAX];
+    constexpr int NB = ((1 << LOGMAX) / 2 + 1 + WH_THREADS - 1) / WH_THREADS;   // bins per thread
     const int n = 1 << logn;
     const int h = n / 2 + 1;
-    const int64_t seg = blockIdx.x;
-    const int64_t t0 = seg * (n / 2);
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
-        const float w = (float)(0.5 - 0.5 * cospi(ldexp((double)j, 1 - logn)));
-        const int64_t t = (t0 + j) * es;
-        s[bitrev(j, logn)] = make_float2(w * x0[t], w * x1[t]);
+    const int64_t g = blockIdx.x, G = gridDim.x;
+    const int64_t s0 = nseg * g / G, s1 = nseg * (g + 1) / G;
+    double acc0[NB], acc1[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) acc0[i] = acc1[i] = 0.0;
+    for (int64_t seg = s0; seg < s1; ++seg) {
+        const int64_t t0 = seg * (n / 2);
+        __syncthreads();   // the previous segment's spectrum has been read
+        for (int j = threadIdx.x; j < n; j += blockDim.x) {
+            const float w = (float)(0.5 - 0.5 * cospi(ldexp((double)j, 1 - logn)));
+            const int64_t t = (t0 + j) * es;
+            s[bitrev(j, logn)] = make_float2(w * x0[t], w * x1[t]);
+        }
+        lds_fft(s, logn, tw, false);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int k = threadIdx.x + WH_THREADS * i;
+            if (k < h) {
+                const float2 z = s[k], zp = s[(n - k) & (n - 1)];
+                const double a0 = 0.5 * ((double)z.x + zp.x), b0 = 0.5 * ((double)z.y - zp.y);
+                const double a1 = 0.5 * ((double)z.y + zp.y), b1 = -0.5 * ((double)z.x - zp.x);
+                acc0[i] += a0 * a0 + b0 * b0;
+                acc1[i] += a1 * a1 + b1 * b1;
+            }
+        }
     }
-    lds_fft(s, logn, tw, false);
-    double* out = pseg + seg * 2 * h;
-    for (int k = threadIdx.x; k < h; k += blockDim.x) {
-        const float2 z = s[k], zp = s[(n - k) & (n - 1)];
-        const double a0 = 0.5 * ((double)z.x + zp.x), b0 = 0.5 * ((double)z.y - zp.y);
-        const double a1 = 0.5 * ((double)z.y + zp.y), b1 = -0.5 * ((double)z.x - zp.x);
-        out[k] = a0 * a0 + b0 * b0;
-        out[h + k] = a1 * a1 + b1 * b1;
+    double* out = part + g * 2 * h;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int k = threadIdx.x + WH_THREADS * i;
+        if (k < h) {
+            out[k] = acc0[i];
+            out[h + k] = acc1[i];
+        }
     }
 }
 
-// Mean over segments and one-sided density scaling in two fixed-order levels: group g of
-// WH_GROUPS sums its contiguous run of segments, then the groups are summed in order.
-constexpr int WH_GROUPS = 64;
-
-__global__ void wh_welch_part_kernel(const double* pseg, int64_t nseg, int h, double* part) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= 2 * h) return;
-    const int64_t g = blockIdx.y;
-    const int64_t s0 = nseg * g / WH_GROUPS, s1 = nseg * (g + 1) / WH_GROUPS;
-    double acc = 0.0;
-    for (int64_t sg = s0; sg < s1; ++sg) acc += pseg[sg * 2 * h + i];
-    part[g * 2 * h + i] = acc;
-}
-
-__global__ void wh_welch_reduce_kernel(const double* part, int h, double scale, double* psd) {
+// The workgroups' sums added in workgroup order, scaled to the one-sided density.
+__global__ void wh_welch_reduce_kernel(const double* part, int64_t groups, int h, double scale, double* psd) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= 2 * h) return;
     const int k = i % h;
     double acc = 0.0;
-    for (int g = 0; g < WH_GROUPS; ++g) acc += part[(int64_t)g * 2 * h + i];
+    for (int64_t g = 0; g < groups; ++g) acc += part[g * 2 * h + i];
     psd[i] = acc * scale * ((k == 0 || k == h - 1) ? 1.0 : 2.0);
 }
 
@@ -344,25 +383,24 @@ gwd_status gwd_welch_psd(const gwd_stream* src, int32_t nperseg, double fs, doub
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) { set_error("gwd_welch_psd: no HIP device"); return GWD_ERR_NO_DEVICE; }
     hipStream_t st = (hipStream_t)hip_stream;
     const int h = nperseg / 2 + 1;
+    // one workgroup per CU for the 128 KB transforms, four for the 32 KB ones, none without a segment
+    const int64_t groups = std::min<int64_t>(nseg, logn > 12 ? 256 : 1024);
     std::lock_guard<std::mutex> lock(g_wh.mu);
     char* ws = nullptr;
-    r = wh_workspace((nseg + WH_GROUPS) * 2 * h * 8, st, &ws);
+    r = wh_workspace(groups * 2 * h * 8, st, &ws);
     if (r != GWD_OK) return r;
     const float2* tw = (const float2*)ws;
-    double* pseg = (double*)(ws + WH_TW_BYTES);
-    double* part = pseg + nseg * 2 * h;
+    double* part = (double*)(ws + WH_TW_BYTES);
     if (logn <= 12)
-        hipLaunchKernelGGL(wh_welch_kernel<12>, dim3((unsigned)nseg), dim3(WH_THREADS), 0, st, src->ch[0], src->ch[1],
-                           src->elem_stride, logn, tw, pseg);
+        hipLaunchKernelGGL(wh_welch_kernel<12>, dim3((unsigned)groups), dim3(WH_THREADS), 0, st, src->ch[0], src->ch[1],
+                           src->elem_stride, logn, nseg, tw, part);
     else
-        hipLaunchKernelGGL(wh_welch_kernel<WH_MAXLOG>, dim3((unsigned)nseg), dim3(WH_THREADS), 0, st, src->ch[0],
-                           src->ch[1], src->elem_stride, logn, tw, pseg);
+        hipLaunchKernelGGL(wh_welch_kernel<WH_MAXLOG>, dim3((unsigned)groups), dim3(WH_THREADS), 0, st, src->ch[0],
+                           src->ch[1], src->elem_stride, logn, nseg, tw, part);
     // sum of the squared periodic Hann window: 3n/8
     const double scale = 1.0 / ((double)nseg * fs * (3.0 * nperseg / 8.0));
-    hipLaunchKernelGGL(wh_welch_part_kernel, dim3((2 * h + 255) / 256, WH_GROUPS), dim3(256), 0, st, (const double*)pseg,
-                       nseg, h, part);
-    hipLaunchKernelGGL(wh_welch_reduce_kernel, dim3((2 * h + 255) / 256), dim3(256), 0, st, (const double*)part, h, scale,
-                       psd);
+    hipLaunchKernelGGL(wh_welch_reduce_kernel, dim3((2 * h + 255) / 256), dim3(256), 0, st, (const double*)part, groups, h,
+                       scale, psd);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? GWD_OK : hip_fail(e, "Welch kernel launch");
 }
