@@ -876,11 +876,15 @@ constexpr int FE_LDS = 3 * FE_XBUF + 2 * FE_BBUF + FE_ROWS * FE_ROW;
 __device__ inline uint8_t* fe_xbuf(uint8_t* lds, int j) { return lds + j * FE_XBUF + FU_HIST * FE_ROW; }
 __device__ inline uint8_t* fe_bbuf(uint8_t* lds, int j) { return lds + 3 * FE_XBUF + j * FE_BBUF; }
 
-template <bool FROM_STREAM, bool SKIP_INIT>
+// G2 as in the BF16 kernel: one k-step covers 64 input channels, i.e. one group, so a wave of group
+// q / 2 takes steps q / 2 and 2 + q / 2 of phase 1 and step q / 2 of phase 2.
+template <bool FROM_STREAM, bool SKIP_INIT, bool G2>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void fused3_fp8_kernel(FusedArgs p) {
     using T = LP<true, FE_RB, 4>;  // E4M3 fragments (32 B per lane), 4 waves x FE_RB row blocks
     constexpr int RB = FE_RB;
     constexpr int PF = 2;          // weight-fragment ring depth
+    constexpr int NS1 = G2 ? T::NK1 / 2 : T::NK1, NS2 = G2 ? T::NK2 / 2 : T::NK2;
+    constexpr auto k1 = [](int s) { return G2 ? 2 * s : s; };   // phase-1 step s -> k, after the group shift
     __shared__ __attribute__((aligned(16))) uint8_t lds[FE_LDS];
     uint8_t* GE = lds + 3 * FE_XBUF + 2 * FE_BBUF;
     const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6, h = lane >> 5, r = lane & 31;
@@ -971,19 +975,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                 const uint8_t* A0 = XE + r * FE_ROW + 32 * h;
                 const uint8_t* Bf = p.wc[j] + ((size_t)(q * T::NK1) * 64 + lane) * T::FRAG;
                 const uint8_t* Bg = p.wc[j] + ((size_t)((4 + q) * T::NK1) * 64 + lane) * T::FRAG;
+                if constexpr (G2) {   // this wave's group: input channels [64 (q / 2), + 64)
+                    A0 += 64 * (q >> 1);
+                    Bf += (size_t)(q >> 1) * 64 * T::FRAG;
+                    Bg += (size_t)(q >> 1) * 64 * T::FRAG;
+                }
                 Frag<true> rf[PF], rg[PF];
 #pragma unroll
-                for (int k = 0; k < PF; ++k) {
-                    rf[k] = load_frag<true>(Bf + (size_t)k * 64 * T::FRAG);
-                    rg[k] = load_frag<true>(Bg + (size_t)k * 64 * T::FRAG);
+                for (int k = 0; k < PF && k < NS1; ++k) {
+                    rf[k] = load_frag<true>(Bf + (size_t)k1(k) * 64 * T::FRAG);
+                    rg[k] = load_frag<true>(Bg + (size_t)k1(k) * 64 * T::FRAG);
                 }
 #pragma unroll
-                for (int k = 0; k < T::NK1; ++k) {
+                for (int k = 0; k < NS1; ++k) {
                     const int slot = k % PF;
-                    const int roff = k < T::NK1 / 2 ? -dil : 0;
+                    const int roff = k1(k) < T::NK1 / 2 ? -dil : 0;
                     Frag<true> a[RB];
 #pragma unroll
-                    for (int i = 0; i < RB; ++i) a[i] = load_frag<true>(A0 + (32 * i + roff) * FE_ROW + 64 * (k & 1));
+                    for (int i = 0; i < RB; ++i) a[i] = load_frag<true>(A0 + (32 * i + roff) * FE_ROW + 64 * (k1(k) & 1));
                     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                     for (int i = 0; i < RB; ++i) {
@@ -991,17 +1000,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                         ag[i] = mma<true>(a[i], rg[slot], ag[i]);
                     }
                     __builtin_amdgcn_sched_barrier(0);
-                    if (k + PF < T::NK1) {
-                        rf[slot] = load_frag<true>(Bf + (size_t)(k + PF) * 64 * T::FRAG);
-                        rg[slot] = load_frag<true>(Bg + (size_t)(k + PF) * 64 * T::FRAG);
+                    if (k + PF < NS1) {
+                        rf[slot] = load_frag<true>(Bf + (size_t)k1(k + PF) * 64 * T::FRAG);
+                        rg[slot] = load_frag<true>(Bg + (size_t)k1(k + PF) * 64 * T::FRAG);
                     }
                 }
             }
             const uint8_t* Wr = p.wrs[j] + ((size_t)(q * T::NK2) * 64 + lane) * T::FRAG;
             const uint8_t* Ws = p.wrs[j] + ((size_t)((4 + q) * T::NK2) * 64 + lane) * T::FRAG;
+            if constexpr (G2) {
+                Wr += (size_t)(q >> 1) * 64 * T::FRAG;
+                Ws += (size_t)(q >> 1) * 64 * T::FRAG;
+            }
             Frag<true> ring[T::NK2];  // phase 2 has two k-steps: both fragments up front
 #pragma unroll
-            for (int k = 0; k < T::NK2; ++k) ring[k] = load_frag<true>(Wr + (size_t)k * 64 * T::FRAG);
+            for (int k = 0; k < NS2; ++k) ring[k] = load_frag<true>(Wr + (size_t)k * 64 * T::FRAG);
             __syncthreads();
             if (tid < 8 * dil) {  // operand history of the next chunk (128 B per row)
                 const int rr = tid >> 3, cc = tid & 7;
@@ -1026,11 +1039,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                 }
             __syncthreads();
             const uint8_t* Ag = GE + r * FE_ROW + 32 * h;
+            if constexpr (G2) Ag += 64 * (q >> 1);
 #pragma unroll
             for (int pass = 0; pass < 2; ++pass) {
                 if (pass == 1) {
 #pragma unroll
-                    for (int k = 0; k < T::NK2; ++k) ring[k] = load_frag<true>(Ws + (size_t)k * 64 * T::FRAG);
+                    for (int k = 0; k < NS2; ++k) ring[k] = load_frag<true>(Ws + (size_t)k * 64 * T::FRAG);
                 }
                 uint32_t xold[RB][8];
                 if (pass == 0) {
@@ -1046,7 +1060,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                 }
                 floatx16 acc[RB] = {};
 #pragma unroll
-                for (int k = 0; k < T::NK2; ++k) {
+                for (int k = 0; k < NS2; ++k) {
                     Frag<true> a[RB];
 #pragma unroll
                     for (int i = 0; i < RB; ++i) a[i] = load_frag<true>(Ag + 32 * i * FE_ROW + 64 * k);
@@ -1169,9 +1183,15 @@ static hipError_t launch_fused(gwd_model* m, int member, int l, int nl, const ui
     const dim3 grid((unsigned)(per * a.n_seg));
     if (FP8) {
         if (nl != 3) return hipErrorInvalidValue;
-        if (stream_in) hipLaunchKernelGGL((fused3_fp8_kernel<true, true>), grid, dim3(256), 0, st, a);
-        else if (first) hipLaunchKernelGGL((fused3_fp8_kernel<false, true>), grid, dim3(256), 0, st, a);
-        else hipLaunchKernelGGL((fused3_fp8_kernel<false, false>), grid, dim3(256), 0, st, a);
+        if (m->two_branch) {   // block-diagonal weights: skip the zero blocks
+            if (stream_in) hipLaunchKernelGGL((fused3_fp8_kernel<true, true, true>), grid, dim3(256), 0, st, a);
+            else if (first) hipLaunchKernelGGL((fused3_fp8_kernel<false, true, true>), grid, dim3(256), 0, st, a);
+            else hipLaunchKernelGGL((fused3_fp8_kernel<false, false, true>), grid, dim3(256), 0, st, a);
+        } else {
+            if (stream_in) hipLaunchKernelGGL((fused3_fp8_kernel<true, true, false>), grid, dim3(256), 0, st, a);
+            else if (first) hipLaunchKernelGGL((fused3_fp8_kernel<false, true, false>), grid, dim3(256), 0, st, a);
+            else hipLaunchKernelGGL((fused3_fp8_kernel<false, false, false>), grid, dim3(256), 0, st, a);
+        }
     } else if (nl == 3) {
         const bool g2 = m->two_branch;   // block-diagonal weights: skip the zero blocks
         if (stream_in) launch_fused_bf16<true, true, 3, false>(g2, grid, st, a);

@@ -194,22 +194,23 @@ def test_adam_and_weight_refresh(g, blob):
     m.close()
 
 
-def test_zero_block_skipping_is_exact(g, dense):
-    """BF16: the two-branch model's fused kernels take only each wave's own group of k-steps; a kind-1
-    model loaded with the same block-diagonal weights runs every step. The skipped steps add exact
-    zero products, so the scores (ensemble and per member) are identical."""
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_zero_block_skipping_is_exact(g, dense, prec):
+    """BF16 / FP8: the two-branch model's fused kernels take only each wave's own group of k-steps; a
+    kind-1 model loaded with the same block-diagonal weights runs every step. The skipped steps add
+    exact zero products, so the scores (ensemble and per member) are identical."""
     from oracle.arch import pack
     from paper_2201_11133_amd import synth
     from oracle.arch import TWO_BRANCH, unpack
     from tests.test_oracle_two_branch import block_diagonal
-    print("case: two-branch zero-block skipping vs dense trunk", flush=True)
+    print(f"case: two-branch zero-block skipping vs dense trunk, {prec}", flush=True)
     blobs = np.stack([synth.two_branch_weights(40 + i) for i in range(2)])
     trunk = np.stack([pack(*block_diagonal(TWO_BRANCH, unpack(TWO_BRANCH, b.astype(np.float64)))).astype(np.float32)
                       for b in blobs])
     x, _ = synth.make_stream(308, 64.0, 2)
     xd = to_dev(x)
-    m2 = g.Model(g.two_branch_arch(), blobs, "bf16")
-    m1 = g.Model(g.full_arch(), trunk, "bf16")
+    m2 = g.Model(g.two_branch_arch(), blobs, prec)
+    m1 = g.Model(g.full_arch(), trunk, prec)
     a = m2.forward([xd], 4096, 256, out_mode=1).cpu().numpy()
     b = m1.forward([xd], 4096, 256, out_mode=1).cpu().numpy()
     assert np.array_equal(a, b)
