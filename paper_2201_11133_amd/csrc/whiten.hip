@@ -151,46 +151,90 @@ __global__ __launch_bounds__(WH_THREADS) void wh_welch_kernel(const float* x0, c
     }
 }
 
-// The workgroups' sums added in workgroup order, scaled to the one-sided density.
-__global__ void wh_welch_reduce_kernel(const double* part, int64_t groups, int h, double scale, double* psd) {
+// The workgroups' sums added in workgroup order, in two fixed levels: WH_RG contiguous runs of
+// workgroups, then the runs; scaled to the one-sided density.
+constexpr int WH_RG = 16;
+
+__global__ void wh_welch_runs_kernel(const double* part, int64_t groups, int h, double* runs) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 2 * h) return;
+    const int64_t y = blockIdx.y;
+    const int64_t g0 = groups * y / WH_RG, g1 = groups * (y + 1) / WH_RG;
+    double acc = 0.0;
+    for (int64_t g = g0; g < g1; ++g) acc += part[g * 2 * h + i];
+    runs[y * 2 * h + i] = acc;
+}
+
+__global__ void wh_welch_reduce_kernel(const double* runs, int h, double scale, double* psd) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= 2 * h) return;
     const int k = i % h;
     double acc = 0.0;
-    for (int64_t g = 0; g < groups; ++g) acc += part[g * 2 * h + i];
+    for (int y = 0; y < WH_RG; ++y) acc += runs[(int64_t)y * 2 * h + i];
     psd[i] = acc * scale * ((k == 0 || k == h - 1) ? 1.0 : 2.0);
 }
 
-// Forward column pass: workgroup n2 transforms z[n1 N2 + n2] over n1 and writes
-// A[n2 N1 + k1] = Z_n2[k1] e^(-2 pi i n2 k1 / L).
-template <int LOGMAX>
-__global__ __launch_bounds__(WH_THREADS) void wh_cols_fwd_kernel(const float* x0, const float* x1, int64_t es,
+// The strided passes take CPB adjacent columns per workgroup (CPB transforms in LDS one after the
+// other), so each gathered row is CPB complex values in one 8 CPB-byte access.
+
+// Forward column pass: workgroup b transforms z[n1 N2 + n2] over n1 for n2 = CPB b .. CPB b + CPB - 1
+// and writes A[n2 N1 + k1] = Z_n2[k1] e^(-2 pi i n2 k1 / L). vec: the channels are interleaved
+// (x1 = x0 + 1, element stride 2) and 16-byte aligned, so a row's two columns are one 16-byte load.
+template <int LOGMAX, int CPB>
+__global__ __launch_bounds__(WH_THREADS) void wh_cols_fwd_kernel(const float* x0, const float* x1, int64_t es, int vec,
                                                                 int logn1, int logn2, const float2* tw, float2* A) {
-    __shared__ float2 s[1 << LOGMAX];
+    __shared__ float2 s[CPB << LOGMAX];
     const int n1c = 1 << logn1;
-    const int64_t n2 = xcd_block(1ll << logn2);
+    const int64_t n2b = xcd_block((1ll << logn2) / CPB) * CPB;
     for (int j = threadIdx.x; j < n1c; j += blockDim.x) {
-        const int64_t t = (((int64_t)j << logn2) + n2) * es;
-        s[bitrev(j, logn1)] = make_float2(x0[t], x1[t]);
+        const int64_t t = ((int64_t)j << logn2) + n2b;
+        const int rj = bitrev(j, logn1);
+        if (CPB == 2 && vec) {
+            const float4 v = *reinterpret_cast<const float4*>(x0 + 2 * t);
+            s[rj] = make_float2(v.x, v.y);
+            s[(1 << LOGMAX) + rj] = make_float2(v.z, v.w);
+        } else {
+#pragma unroll
+            for (int c = 0; c < CPB; ++c) s[(c << LOGMAX) + rj] = make_float2(x0[(t + c) * es], x1[(t + c) * es]);
+        }
     }
-    lds_fft(s, logn1, tw, false);
+#pragma unroll
+    for (int c = 0; c < CPB; ++c) lds_fft(s + (c << LOGMAX), logn1, tw, false);
     const int logl = logn1 + logn2;
-    float2* out = A + (n2 << logn1);
-    for (int k1 = threadIdx.x; k1 < n1c; k1 += blockDim.x)
-        out[k1] = cmul(s[k1], twiddle_l(n2 * k1, logl, false));
+#pragma unroll
+    for (int c = 0; c < CPB; ++c) {
+        float2* out = A + ((n2b + c) << logn1);
+        for (int k1 = threadIdx.x; k1 < n1c; k1 += blockDim.x)
+            out[k1] = cmul(s[(c << LOGMAX) + k1], twiddle_l((n2b + c) * k1, logl, false));
+    }
 }
 
-// Forward row pass: workgroup k1 transforms A[n2 N1 + k1] over n2 and writes T[k1 N2 + k2].
-template <int LOGMAX>
+// Forward row pass: workgroup b transforms A[n2 N1 + k1] over n2 for k1 = CPB b .. CPB b + CPB - 1
+// and writes T[k1 N2 + k2].
+template <int LOGMAX, int CPB>
 __global__ __launch_bounds__(WH_THREADS) void wh_rows_fwd_kernel(const float2* A, int logn1, int logn2,
                                                                 const float2* tw, float2* T) {
-    __shared__ float2 s[1 << LOGMAX];
+    __shared__ float2 s[CPB << LOGMAX];
     const int n2c = 1 << logn2;
-    const int64_t k1 = xcd_block(1ll << logn1);
-    for (int j = threadIdx.x; j < n2c; j += blockDim.x) s[bitrev(j, logn2)] = A[((int64_t)j << logn1) + k1];
-    lds_fft(s, logn2, tw, false);
-    float2* out = T + (k1 << logn2);
-    for (int k2 = threadIdx.x; k2 < n2c; k2 += blockDim.x) out[k2] = s[k2];
+    const int64_t k1b = xcd_block((1ll << logn1) / CPB) * CPB;
+    for (int j = threadIdx.x; j < n2c; j += blockDim.x) {
+        const float2* src = A + ((int64_t)j << logn1) + k1b;
+        const int rj = bitrev(j, logn2);
+        if (CPB == 2) {
+            const float4 v = *reinterpret_cast<const float4*>(src);
+            s[rj] = make_float2(v.x, v.y);
+            s[(1 << LOGMAX) + rj] = make_float2(v.z, v.w);
+        } else {
+            s[rj] = src[0];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < CPB; ++c) lds_fft(s + (c << LOGMAX), logn2, tw, false);
+#pragma unroll
+    for (int c = 0; c < CPB; ++c) {
+        float2* out = T + ((k1b + c) << logn2);
+        for (int k2 = threadIdx.x; k2 < n2c; k2 += blockDim.x) out[k2] = s[(c << LOGMAX) + k2];
+    }
 }
 
 // 1 / (L sqrt(P_c(f_k) fs / 2)): the PSD linearly interpolated at bin k of L (grid position
@@ -243,27 +287,50 @@ __global__ __launch_bounds__(WH_THREADS) void wh_rows_inv_kernel(const float2* T
         out[n2] = cmul(s[n2], twiddle_l(n2 * k1, logl, true));
 }
 
-// Inverse column pass: workgroup n2 inverse-transforms C[k1 N2 + n2] over k1 into
-// y[n1 N2 + n2] (channel 0 real part, channel 1 imaginary part), written interleaved, and leaves
-// its float64 sums of y and y^2 per channel in part[n2 * 4 + {0..3}].
-template <int LOGMAX>
-__global__ __launch_bounds__(WH_THREADS) void wh_cols_inv_kernel(const float2* C, int logn1, int logn2,
+// Inverse column pass: workgroup b inverse-transforms C[k1 N2 + n2] over k1 for n2 = CPB b ..
+// CPB b + CPB - 1 into y[n1 N2 + n2] (channel 0 real part, channel 1 imaginary part), written
+// interleaved (one 16-byte store per row for CPB = 2 when vec), and leaves its float64 sums of y and
+// y^2 per channel in part[b * 4 + {0..3}].
+template <int LOGMAX, int CPB>
+__global__ __launch_bounds__(WH_THREADS) void wh_cols_inv_kernel(const float2* C, int logn1, int logn2, int vec,
                                                                 const float2* tw, float* out, double* part) {
-    __shared__ float2 s[1 << LOGMAX];
+    __shared__ float2 s[CPB << LOGMAX];
     __shared__ double red[4][WH_THREADS];
     const int n1c = 1 << logn1;
-    const int64_t n2 = xcd_block(1ll << logn2);
-    for (int j = threadIdx.x; j < n1c; j += blockDim.x) s[bitrev(j, logn1)] = C[((int64_t)j << logn2) + n2];
-    lds_fft(s, logn1, tw, true);
+    const int64_t blk = xcd_block((1ll << logn2) / CPB);
+    const int64_t n2b = blk * CPB;
+    for (int j = threadIdx.x; j < n1c; j += blockDim.x) {
+        const float2* src = C + ((int64_t)j << logn2) + n2b;
+        const int rj = bitrev(j, logn1);
+        if (CPB == 2) {
+            const float4 v = *reinterpret_cast<const float4*>(src);
+            s[rj] = make_float2(v.x, v.y);
+            s[(1 << LOGMAX) + rj] = make_float2(v.z, v.w);
+        } else {
+            s[rj] = src[0];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < CPB; ++c) lds_fft(s + (c << LOGMAX), logn1, tw, true);
     double a0 = 0.0, q0 = 0.0, a1 = 0.0, q1 = 0.0;
     for (int j = threadIdx.x; j < n1c; j += blockDim.x) {
-        const float2 y = s[j];
-        const int64_t t = ((int64_t)j << logn2) + n2;
-        *reinterpret_cast<float2*>(out + 2 * t) = y;
-        a0 += y.x;
-        q0 += (double)y.x * y.x;
-        a1 += y.y;
-        q1 += (double)y.y * y.y;
+        const int64_t t = ((int64_t)j << logn2) + n2b;
+        float2 y[CPB];
+#pragma unroll
+        for (int c = 0; c < CPB; ++c) y[c] = s[(c << LOGMAX) + j];
+        if (CPB == 2 && vec) {
+            *reinterpret_cast<float4*>(out + 2 * t) = make_float4(y[0].x, y[0].y, y[CPB - 1].x, y[CPB - 1].y);
+        } else {
+#pragma unroll
+            for (int c = 0; c < CPB; ++c) *reinterpret_cast<float2*>(out + 2 * (t + c)) = y[c];
+        }
+#pragma unroll
+        for (int c = 0; c < CPB; ++c) {
+            a0 += y[c].x;
+            q0 += (double)y[c].x * y[c].x;
+            a1 += y[c].y;
+            q1 += (double)y[c].y * y[c].y;
+        }
     }
     red[0][threadIdx.x] = a0;
     red[1][threadIdx.x] = q0;
@@ -275,7 +342,7 @@ __global__ __launch_bounds__(WH_THREADS) void wh_cols_inv_kernel(const float2* C
             for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
     }
     __syncthreads();
-    if (threadIdx.x < 4) part[n2 * 4 + threadIdx.x] = red[threadIdx.x][0];
+    if (threadIdx.x < 4) part[blk * 4 + threadIdx.x] = red[threadIdx.x][0];
 }
 
 // 1 / sigma per channel from the per-workgroup sums (fixed summation order).
@@ -387,10 +454,11 @@ gwd_status gwd_welch_psd(const gwd_stream* src, int32_t nperseg, double fs, doub
     const int64_t groups = std::min<int64_t>(nseg, logn > 12 ? 256 : 1024);
     std::lock_guard<std::mutex> lock(g_wh.mu);
     char* ws = nullptr;
-    r = wh_workspace(groups * 2 * h * 8, st, &ws);
+    r = wh_workspace((groups + WH_RG) * 2 * h * 8, st, &ws);
     if (r != GWD_OK) return r;
     const float2* tw = (const float2*)ws;
     double* part = (double*)(ws + WH_TW_BYTES);
+    double* runs = part + groups * 2 * h;
     if (logn <= 12)
         hipLaunchKernelGGL(wh_welch_kernel<12>, dim3((unsigned)groups), dim3(WH_THREADS), 0, st, src->ch[0], src->ch[1],
                            src->elem_stride, logn, nseg, tw, part);
@@ -399,8 +467,10 @@ gwd_status gwd_welch_psd(const gwd_stream* src, int32_t nperseg, double fs, doub
                            src->ch[1], src->elem_stride, logn, nseg, tw, part);
     // sum of the squared periodic Hann window: 3n/8
     const double scale = 1.0 / ((double)nseg * fs * (3.0 * nperseg / 8.0));
-    hipLaunchKernelGGL(wh_welch_reduce_kernel, dim3((2 * h + 255) / 256), dim3(256), 0, st, (const double*)part, groups, h,
-                       scale, psd);
+    hipLaunchKernelGGL(wh_welch_runs_kernel, dim3((2 * h + 255) / 256, WH_RG), dim3(256), 0, st, (const double*)part, groups,
+                       h, runs);
+    hipLaunchKernelGGL(wh_welch_reduce_kernel, dim3((2 * h + 255) / 256), dim3(256), 0, st, (const double*)runs, h, scale,
+                       psd);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? GWD_OK : hip_fail(e, "Welch kernel launch");
 }
@@ -432,19 +502,24 @@ gwd_status gwd_whiten(const gwd_stream* src, const double* psd, int32_t nperseg,
     float2* T = A + L;
     double* part = (double*)(T + L);
     float* inv_sigma = (float*)(part + 4 * n2c);
-    const bool big = logn1 > 12;
-    if (big)
-        hipLaunchKernelGGL(wh_cols_fwd_kernel<WH_MAXLOG>, dim3((unsigned)n2c), dim3(WH_THREADS), 0, st, src->ch[0],
-                           src->ch[1], src->elem_stride, logn1, logn2, tw, A);
+    // columns per workgroup in the strided passes: two for transforms of up to 4096 points (2 x 32 KB
+    // of LDS), one for the 128 KB transforms
+    const int cpb_c = logn1 <= 12 ? 2 : 1, cpb_r = logn2 <= 12 ? 2 : 1;
+    const int vec_in = src->elem_stride == 2 && src->ch[1] == src->ch[0] + 1 && ((uintptr_t)src->ch[0] & 15) == 0;
+    const int vec_out = ((uintptr_t)dst & 15) == 0;
+    const int64_t nblk_c = n2c / cpb_c, nblk_r = n1c / cpb_r;
+    if (cpb_c == 2)
+        hipLaunchKernelGGL((wh_cols_fwd_kernel<12, 2>), dim3((unsigned)nblk_c), dim3(WH_THREADS), 0, st, src->ch[0],
+                           src->ch[1], src->elem_stride, vec_in, logn1, logn2, tw, A);
     else
-        hipLaunchKernelGGL(wh_cols_fwd_kernel<12>, dim3((unsigned)n2c), dim3(WH_THREADS), 0, st, src->ch[0], src->ch[1],
-                           src->elem_stride, logn1, logn2, tw, A);
-    if (logn2 > 12)
-        hipLaunchKernelGGL(wh_rows_fwd_kernel<WH_MAXLOG>, dim3((unsigned)n1c), dim3(WH_THREADS), 0, st, (const float2*)A,
+        hipLaunchKernelGGL((wh_cols_fwd_kernel<WH_MAXLOG, 1>), dim3((unsigned)nblk_c), dim3(WH_THREADS), 0, st, src->ch[0],
+                           src->ch[1], src->elem_stride, vec_in, logn1, logn2, tw, A);
+    if (cpb_r == 2)
+        hipLaunchKernelGGL((wh_rows_fwd_kernel<12, 2>), dim3((unsigned)nblk_r), dim3(WH_THREADS), 0, st, (const float2*)A,
                            logn1, logn2, tw, T);
     else
-        hipLaunchKernelGGL(wh_rows_fwd_kernel<12>, dim3((unsigned)n1c), dim3(WH_THREADS), 0, st, (const float2*)A, logn1,
-                           logn2, tw, T);
+        hipLaunchKernelGGL((wh_rows_fwd_kernel<WH_MAXLOG, 1>), dim3((unsigned)nblk_r), dim3(WH_THREADS), 0, st,
+                           (const float2*)A, logn1, logn2, tw, T);
     const unsigned sblocks = (unsigned)std::min<int64_t>((L + 255) / 256, 16384);
     hipLaunchKernelGGL(wh_spectrum_kernel, dim3(sblocks), dim3(256), 0, st, T, logn1, logn2, psd, logn, fs);
     if (logn2 > 12)
@@ -453,14 +528,14 @@ gwd_status gwd_whiten(const gwd_stream* src, const double* psd, int32_t nperseg,
     else
         hipLaunchKernelGGL(wh_rows_inv_kernel<12>, dim3((unsigned)n1c), dim3(WH_THREADS), 0, st, (const float2*)T, logn1,
                            logn2, tw, A);
-    if (big)
-        hipLaunchKernelGGL(wh_cols_inv_kernel<WH_MAXLOG>, dim3((unsigned)n2c), dim3(WH_THREADS), 0, st, (const float2*)A,
-                           logn1, logn2, tw, dst, part);
+    if (cpb_c == 2)
+        hipLaunchKernelGGL((wh_cols_inv_kernel<12, 2>), dim3((unsigned)nblk_c), dim3(WH_THREADS), 0, st, (const float2*)A,
+                           logn1, logn2, vec_out, tw, dst, part);
     else
-        hipLaunchKernelGGL(wh_cols_inv_kernel<12>, dim3((unsigned)n2c), dim3(WH_THREADS), 0, st, (const float2*)A, logn1,
-                           logn2, tw, dst, part);
+        hipLaunchKernelGGL((wh_cols_inv_kernel<WH_MAXLOG, 1>), dim3((unsigned)nblk_c), dim3(WH_THREADS), 0, st,
+                           (const float2*)A, logn1, logn2, vec_out, tw, dst, part);
     if (normalize) {
-        hipLaunchKernelGGL(wh_sigma_kernel, dim3(1), dim3(256), 0, st, (const double*)part, n2c, logl, inv_sigma);
+        hipLaunchKernelGGL(wh_sigma_kernel, dim3(1), dim3(256), 0, st, (const double*)part, nblk_c, logl, inv_sigma);
         hipLaunchKernelGGL(wh_scale_kernel, dim3(sblocks), dim3(256), 0, st, (float2*)dst, L, (const float*)inv_sigma);
     }
     const hipError_t e = hipGetLastError();
