@@ -288,12 +288,12 @@ __global__ __launch_bounds__(WH_THREADS) void wh_rows_inv_kernel(const float2* T
 }
 
 // Inverse column pass: workgroup b inverse-transforms C[k1 N2 + n2] over k1 for n2 = CPB b ..
-// CPB b + CPB - 1 into y[n1 N2 + n2] (channel 0 real part, channel 1 imaginary part), written
-// interleaved (one 16-byte store per row for CPB = 2 when vec), and leaves its float64 sums of y and
-// y^2 per channel in part[b * 4 + {0..3}].
+// CPB b + CPB - 1 into column n2 of y (channel 0 real part, channel 1 imaginary part), stored
+// contiguously as yt[n2 N1 + n1] (the interleaved output is written by the transpose below), and
+// leaves its float64 sums of y and y^2 per channel in part[b * 4 + {0..3}].
 template <int LOGMAX, int CPB>
-__global__ __launch_bounds__(WH_THREADS) void wh_cols_inv_kernel(const float2* C, int logn1, int logn2, int vec,
-                                                                const float2* tw, float* out, double* part) {
+__global__ __launch_bounds__(WH_THREADS) void wh_cols_inv_kernel(const float2* C, int logn1, int logn2,
+                                                                const float2* tw, float2* yt, double* part) {
     __shared__ float2 s[CPB << LOGMAX];
     __shared__ double red[4][WH_THREADS];
     const int n1c = 1 << logn1;
@@ -313,23 +313,16 @@ __global__ __launch_bounds__(WH_THREADS) void wh_cols_inv_kernel(const float2* C
 #pragma unroll
     for (int c = 0; c < CPB; ++c) lds_fft(s + (c << LOGMAX), logn1, tw, true);
     double a0 = 0.0, q0 = 0.0, a1 = 0.0, q1 = 0.0;
-    for (int j = threadIdx.x; j < n1c; j += blockDim.x) {
-        const int64_t t = ((int64_t)j << logn2) + n2b;
-        float2 y[CPB];
 #pragma unroll
-        for (int c = 0; c < CPB; ++c) y[c] = s[(c << LOGMAX) + j];
-        if (CPB == 2 && vec) {
-            *reinterpret_cast<float4*>(out + 2 * t) = make_float4(y[0].x, y[0].y, y[CPB - 1].x, y[CPB - 1].y);
-        } else {
-#pragma unroll
-            for (int c = 0; c < CPB; ++c) *reinterpret_cast<float2*>(out + 2 * (t + c)) = y[c];
-        }
-#pragma unroll
-        for (int c = 0; c < CPB; ++c) {
-            a0 += y[c].x;
-            q0 += (double)y[c].x * y[c].x;
-            a1 += y[c].y;
-            q1 += (double)y[c].y * y[c].y;
+    for (int c = 0; c < CPB; ++c) {
+        float2* col = yt + ((n2b + c) << logn1);
+        for (int j = threadIdx.x; j < n1c; j += blockDim.x) {
+            const float2 y = s[(c << LOGMAX) + j];
+            col[j] = y;
+            a0 += y.x;
+            q0 += (double)y.x * y.x;
+            a1 += y.y;
+            q1 += (double)y.y * y.y;
         }
     }
     red[0][threadIdx.x] = a0;
@@ -366,12 +359,28 @@ __global__ void wh_sigma_kernel(const double* part, int64_t nblk, int logl, floa
     }
 }
 
-__global__ void wh_scale_kernel(float2* out, int64_t L, const float* inv_sigma) {
-    const float s0 = inv_sigma[0], s1 = inv_sigma[1];
-    const int64_t step = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < L; t += step) {
-        const float2 y = out[t];
-        out[t] = make_float2(y.x * s0, y.y * s1);
+// out[n1 N2 + n2] = yt[n2 N1 + n1] * (1 / sigma per channel, or 1 without normalisation), through a
+// 32 x 32 LDS tile so that both the reads (along n1) and the writes (along n2) are contiguous.
+constexpr int WH_TT = 32;
+
+__global__ __launch_bounds__(256) void wh_transpose_kernel(const float2* yt, int logn1, int logn2,
+                                                         const float* inv_sigma, float2* out) {
+    __shared__ float2 tile[WH_TT][WH_TT + 1];
+    const int n1c = 1 << logn1, n2c = 1 << logn2;
+    const int b1 = blockIdx.x * WH_TT, b2 = blockIdx.y * WH_TT;
+    const float s0 = inv_sigma ? inv_sigma[0] : 1.0f, s1 = inv_sigma ? inv_sigma[1] : 1.0f;
+    const int tx = threadIdx.x & (WH_TT - 1), ty = threadIdx.x / WH_TT;   // 32 x 8 threads
+    for (int r = ty; r < WH_TT; r += 256 / WH_TT) {
+        const int n2 = b2 + r, n1 = b1 + tx;
+        if (n2 < n2c && n1 < n1c) tile[r][tx] = yt[((int64_t)n2 << logn1) + n1];
+    }
+    __syncthreads();
+    for (int r = ty; r < WH_TT; r += 256 / WH_TT) {
+        const int n1 = b1 + r, n2 = b2 + tx;
+        if (n1 < n1c && n2 < n2c) {
+            const float2 y = tile[tx][r];
+            out[((int64_t)n1 << logn2) + n2] = make_float2(y.x * s0, y.y * s1);
+        }
     }
 }
 
@@ -506,7 +515,6 @@ gwd_status gwd_whiten(const gwd_stream* src, const double* psd, int32_t nperseg,
     // of LDS), one for the 128 KB transforms
     const int cpb_c = logn1 <= 12 ? 2 : 1, cpb_r = logn2 <= 12 ? 2 : 1;
     const int vec_in = src->elem_stride == 2 && src->ch[1] == src->ch[0] + 1 && ((uintptr_t)src->ch[0] & 15) == 0;
-    const int vec_out = ((uintptr_t)dst & 15) == 0;
     const int64_t nblk_c = n2c / cpb_c, nblk_r = n1c / cpb_r;
     if (cpb_c == 2)
         hipLaunchKernelGGL((wh_cols_fwd_kernel<12, 2>), dim3((unsigned)nblk_c), dim3(WH_THREADS), 0, st, src->ch[0],
@@ -528,16 +536,18 @@ gwd_status gwd_whiten(const gwd_stream* src, const double* psd, int32_t nperseg,
     else
         hipLaunchKernelGGL(wh_rows_inv_kernel<12>, dim3((unsigned)n1c), dim3(WH_THREADS), 0, st, (const float2*)T, logn1,
                            logn2, tw, A);
+    // the columns of y go to T (free again), then one transpose writes the interleaved output
     if (cpb_c == 2)
         hipLaunchKernelGGL((wh_cols_inv_kernel<12, 2>), dim3((unsigned)nblk_c), dim3(WH_THREADS), 0, st, (const float2*)A,
-                           logn1, logn2, vec_out, tw, dst, part);
+                           logn1, logn2, tw, T, part);
     else
         hipLaunchKernelGGL((wh_cols_inv_kernel<WH_MAXLOG, 1>), dim3((unsigned)nblk_c), dim3(WH_THREADS), 0, st,
-                           (const float2*)A, logn1, logn2, vec_out, tw, dst, part);
-    if (normalize) {
+                           (const float2*)A, logn1, logn2, tw, T, part);
+    if (normalize)
         hipLaunchKernelGGL(wh_sigma_kernel, dim3(1), dim3(256), 0, st, (const double*)part, nblk_c, logl, inv_sigma);
-        hipLaunchKernelGGL(wh_scale_kernel, dim3(sblocks), dim3(256), 0, st, (float2*)dst, L, (const float*)inv_sigma);
-    }
+    const dim3 tgrid((unsigned)((n1c + WH_TT - 1) / WH_TT), (unsigned)((n2c + WH_TT - 1) / WH_TT));
+    hipLaunchKernelGGL(wh_transpose_kernel, tgrid, dim3(256), 0, st, (const float2*)T, logn1, logn2,
+                       normalize ? (const float*)inv_sigma : (const float*)nullptr, (float2*)dst);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? GWD_OK : hip_fail(e, "whitening kernel launch");
 }
