@@ -4,7 +4,7 @@
 //
 // Both channels travel in one complex sequence z[t] = x0[t] + i x1[t]; the spectra of the two real
 // channels separate as X0[k] = (Z[k] + conj Z[N-k]) / 2 and X1[k] = (Z[k] - conj Z[N-k]) / 2i.
-// Transforms are decimation-in-time in LDS (radix-2 stages taken two at a time), one workgroup per
+// Transforms are decimation-in-time in LDS (radix-2 stages taken three at a time), one workgroup per
 // transform, up to 16384 points. A stream of L = N1 N2 samples takes the four-step route: N2 transforms of length N1 down
 // the columns t = n1 N2 + n2, a twiddle e^(-2 pi i n2 k1 / L), N1 transforms of length N2 along
 // the rows; the spectrum is kept transposed (bin k1 + N1 k2 at k1 N2 + k2), which is the order
@@ -51,9 +51,10 @@ __global__ void wh_twiddle_kernel(float2* tw) {
 }
 
 // In-place radix-2 DIT transform of s[0, 2^logn) (input already in bit-reversed order, output in
-// natural order); the inverse uses the conjugate twiddles and does not scale. Stages go in pairs
-// (radix 2^2): a thread takes four points base + j + {0, 1, 2, 3} * half through both stages in
-// registers, so LDS is read and written once per pair; an odd last stage runs alone.
+// natural order); the inverse uses the conjugate twiddles and does not scale. Stages go in threes
+// (radix 2^3): a thread takes eight points base + j + m half (m = 0..7) through the three stages in
+// registers, so LDS is read and written once per three stages; the last one or two run as a pair or
+// alone.
 __device__ inline float2 tw_at(const float2* __restrict__ tw, int i, bool inverse) {
     float2 w = tw[i];
     if (inverse) w.y = -w.y;
@@ -69,25 +70,50 @@ __device__ inline void bfly(float2& a, float2& b, float2 w) {
 __device__ void lds_fft(float2* s, int logn, const float2* __restrict__ tw, bool inverse) {
     const int n = 1 << logn;
     int lh = 0;
-    for (; lh + 1 < logn; lh += 2) {
+    for (; lh + 2 < logn; lh += 3) {   // three stages per pass: eight points base + j + m half per thread
+        const int half = 1 << lh;
+        __syncthreads();
+        for (int b = threadIdx.x; b < (n >> 3); b += blockDim.x) {
+            const int j = b & (half - 1);
+            const int base = ((b - j) << 3) + j;
+            float2 a[8];
+#pragma unroll
+            for (int m = 0; m < 8; ++m) a[m] = s[base + m * half];
+            const float2 w1 = tw_at(tw, j << (WH_MAXLOG - 1 - lh), inverse);           // W_(2 half)^j
+#pragma unroll
+            for (int m = 0; m < 8; m += 2) bfly(a[m], a[m + 1], w1);
+            const float2 w2 = tw_at(tw, j << (WH_MAXLOG - 2 - lh), inverse);           // W_(4 half)^j
+            const float2 w3 = tw_at(tw, (j + half) << (WH_MAXLOG - 2 - lh), inverse);  // W_(4 half)^(j + half)
+#pragma unroll
+            for (int g = 0; g < 8; g += 4) {
+                bfly(a[g], a[g + 2], w2);
+                bfly(a[g + 1], a[g + 3], w3);
+            }
+#pragma unroll
+            for (int m = 0; m < 4; ++m)                                                 // W_(8 half)^(j + m half)
+                bfly(a[m], a[m + 4], tw_at(tw, (j + m * half) << (WH_MAXLOG - 3 - lh), inverse));
+#pragma unroll
+            for (int m = 0; m < 8; ++m) s[base + m * half] = a[m];
+        }
+    }
+    if (lh + 1 < logn) {   // two stages left
         const int half = 1 << lh;
         __syncthreads();
         for (int b = threadIdx.x; b < (n >> 2); b += blockDim.x) {
             const int j = b & (half - 1);
             const int base = ((b - j) << 2) + j;
             float2 a0 = s[base], a1 = s[base + half], a2 = s[base + 2 * half], a3 = s[base + 3 * half];
-            const float2 w1 = tw_at(tw, j << (WH_MAXLOG - 1 - lh), inverse);           // W_(2 half)^j
+            const float2 w1 = tw_at(tw, j << (WH_MAXLOG - 1 - lh), inverse);
             bfly(a0, a1, w1);
             bfly(a2, a3, w1);
-            bfly(a0, a2, tw_at(tw, j << (WH_MAXLOG - 2 - lh), inverse));               // W_(4 half)^j
-            bfly(a1, a3, tw_at(tw, (j + half) << (WH_MAXLOG - 2 - lh), inverse));      // W_(4 half)^(j + half)
+            bfly(a0, a2, tw_at(tw, j << (WH_MAXLOG - 2 - lh), inverse));
+            bfly(a1, a3, tw_at(tw, (j + half) << (WH_MAXLOG - 2 - lh), inverse));
             s[base] = a0;
             s[base + half] = a1;
             s[base + 2 * half] = a2;
             s[base + 3 * half] = a3;
         }
-    }
-    if (lh < logn) {   // odd number of stages: the last one on its own
+    } else if (lh < logn) {   // one stage left
         const int half = 1 << lh;
         __syncthreads();
         for (int b = threadIdx.x; b < (n >> 1); b += blockDim.x) {
