@@ -436,6 +436,25 @@ gwd_status gwd_debug_layer(gwd_model* model, int32_t member, int32_t layer, cons
                            float* skip_inout, void* hip_stream);
 gwd_status gwd_debug_export_weights(const gwd_model* model, int32_t member, float* out, int64_t n_params);
 
+/* Backward operands of one gated layer (test support for layer-local parity of the hand-written
+ * backward, "AI ensemble construction"). After this call, every gwd_backward on the model copies,
+ * for gated layer `layer` (of the member it is called for), the operands and results of that layer's
+ * backward step into the caller's device fp32 buffers, each [B W][C] with C = 128 unless noted:
+ *   x_in   the layer input as the recompute produced it (bf16 values for BF16 models),
+ *   pre    its pre-activation [B W][2C],
+ *   dskip  dL/dskip (the same for every layer),
+ *   dx_in  dL/d(layer output x'), zero for the last layer,
+ *   dg     dL/dg = dskip W_s + dx_in W_r,
+ *   g      the gate output as the weight-gradient GEMMs read it (bf16 values for BF16 models),
+ *   dpre   dL/dpre [B W][2C] as the GEMMs read it (bf16 values for BF16 models),
+ *   dx_out dL/dx = dx_in + dpre[t] W_tap1 + dpre[t + d] W_tap0.
+ * The buffers must hold B W rows for the batch of the next gwd_backward and stay valid until it
+ * completes. layer = -1 turns the copies off (the pointers may then be NULL). GWD_ERR_UNSUPPORTED
+ * for other than kind-1 gated models; GWD_ERR_ARG for a layer out of range or NULL/misaligned
+ * buffers. No device work; the copies add work to gwd_backward only while enabled. */
+gwd_status gwd_debug_capture_backward(gwd_model* model, int32_t layer, float* x_in, float* pre, float* dskip,
+                                      float* dx_in, float* dg, float* g, float* dpre, float* dx_out);
+
 /* Measurement support: issues the launch that gwd_forward makes at middle gated
  * layer `layer` of member `member` (the single-layer kernel, or the fused
  * kernel when a fused launch starts there; every layer it covers must be a

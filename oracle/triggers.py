@@ -84,3 +84,28 @@ def triggers_brute(e: np.ndarray, offsets: Sequence[int], p_thr: float = 0.9, wc
                all(seg[a] >= seg[b] for b in range(a + 1, min(n, a + wc + 1))):
                 out.append((s, a))
     return out
+
+
+def fragile_decisions(e: np.ndarray, offsets: Sequence[int], p_thr: float = 0.9, wc: int = 4096,
+                      margin: float = 1e-4) -> set:
+    """(stream, sample) pairs whose trigger decision lies within `margin` (in logit) of flipping:
+    the score is within margin of the threshold, or of the largest score among its in-stream
+    neighbours in [a - wc, a) and (a, a + wc].
+
+    If another computation of the scores differs from e by less than margin / 2 everywhere, its
+    trigger list can differ from the one of e only at these samples: each of the three comparisons
+    of the rule moves by less than margin.
+    """
+    thr = logit_threshold(p_thr)
+    out = set()
+    for s in range(len(offsets) - 1):
+        seg = np.asarray(e[offsets[s]:offsets[s + 1]], dtype=np.float64)
+        n = seg.size
+        if n == 0:
+            continue
+        pad = np.concatenate([np.full(wc, -np.inf), seg, np.full(wc, -np.inf)])
+        win_max = forward_max(pad, wc)
+        comp = np.maximum(win_max[0:n], win_max[wc + 1:wc + 1 + n])
+        close = (np.abs(seg - thr) < margin) | (np.abs(seg - comp) < margin)
+        out.update((s, int(a)) for a in np.nonzero(close)[0])
+    return out

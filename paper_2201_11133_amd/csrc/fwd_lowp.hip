@@ -1317,6 +1317,10 @@ hipError_t launch_f32_to_bf16(const float* x, int64_t n, uint16_t* y, hipStream_
     hipLaunchKernelGGL(f32_to_bf16_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, n, y);
     return hipGetLastError();
 }
+hipError_t launch_bf16_to_f32(const uint16_t* x, int64_t n, float* y, hipStream_t st) {
+    hipLaunchKernelGGL(bf16_to_f32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, n, y);
+    return hipGetLastError();
+}
 
 // One launch of layer l exactly as the forward issues it for a middle layer (workspace buffers).
 template <bool FP8>

@@ -104,6 +104,10 @@ struct gwd_model {
     int64_t branch_params = 0;                 // kind 2: parameters of one member in its own (branch) blob
     int64_t* branch_map = nullptr;             // kind 2: device [branch_params], trunk index of each branch parameter
     float* dense_grad = nullptr;               // kind 2: device [n_params], the trunk gradient before read-back
+    // test support (gwd_debug_capture_backward): gated layer whose backward operands and results the
+    // next gwd_backward copies out as fp32 [M][C] ([M][2C] for pre and dpre); -1 = off
+    int32_t cap_layer = -1;
+    float* cap_buf[8] = {};                    // x_in, pre, dskip, dx_in, dg, g, dpre, dx_out
 };
 
 namespace gwd {
@@ -149,6 +153,7 @@ hipError_t launch_layer_debug(gwd_model* m, int member, int layer, const float* 
 hipError_t launch_layer_train_bf16io(gwd_model* m, int member, int l, const uint16_t* x_in, int nb, int T,
                                      float* pre_out, uint16_t* x_out, float* skip, hipStream_t st);
 hipError_t launch_f32_to_bf16(const float* x, int64_t n, uint16_t* y, hipStream_t st);
+hipError_t launch_bf16_to_f32(const uint16_t* x, int64_t n, float* y, hipStream_t st);
 int train_layers_per_launch(const gwd_model* m, int l, int T);
 hipError_t launch_fused_train(gwd_model* m, int member, int l, int nl, const uint16_t* x_in, uint16_t* x_out,
                               float* skip, int nb, int T, hipStream_t st);

@@ -47,6 +47,12 @@ static gwd_status check_train(const gwd_model* m, int member, const void* window
 
 static inline float* fptr(void* base, int64_t off_floats) { return (float*)base + off_floats; }
 
+// Test support: copy n values of a backward buffer (bf16 when `half`) to a caller's fp32 buffer.
+static hipError_t capture(float* dst, const void* src, int64_t n, bool half, hipStream_t st) {
+    if (half) return launch_bf16_to_f32((const uint16_t*)src, n, dst, st);
+    return hipMemcpyAsync(dst, src, n * sizeof(float), hipMemcpyDeviceToDevice, st);
+}
+
 // ---------------------------------------------------------------- gated member
 static gwd_status fwd_train_kind1(gwd_model* m, int member, const float* u, int B, int T, float* logits,
                                   float* saved, hipStream_t st) {
@@ -201,6 +207,13 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
             const bool last = l == L - 1;
             const float* xs_i = fptr(b, f_xs + (int64_t)i * M * kC);
             const float* pre = fptr(b, f_pre + (int64_t)i * M * 2 * kC);
+            float* const* cap = l == m->cap_layer ? m->cap_buf : nullptr;
+            if (cap) {  // the layer's operands as its kernels read them
+                HIPCHK(capture(cap[0], xs_i, M * kC, BT != nullptr, st), "capture x_in");
+                HIPCHK(capture(cap[1], pre, M * 2 * kC, false, st), "capture pre");
+                HIPCHK(capture(cap[2], DS, M * kC, false, st), "capture dskip");
+                HIPCHK(capture(cap[3], DX, M * kC, false, st), "capture dx_in");
+            }
             // dg = dskip W_s + dx' W_r
             GemmRowsArgs g{};
             g.A[0] = APart{DS, kC, 0, kC, DS16};
@@ -219,6 +232,11 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
             uint16_t* DPRE16 = BT ? (uint16_t*)DPRE : nullptr;
             if (BT) HIPCHK(launch_gate_bwd16(pre, DG, M, G16, DPRE16, st), "gate bwd");
             else HIPCHK(launch_gate_bwd(pre, DG, M, G, DPRE, st), "gate bwd");
+            if (cap) {
+                HIPCHK(capture(cap[4], DG, M * kC, false, st), "capture dg");
+                HIPCHK(capture(cap[5], BT ? (const void*)G16 : G, M * kC, BT != nullptr, st), "capture g");
+                HIPCHK(capture(cap[6], BT ? (const void*)DPRE16 : DPRE, M * 2 * kC, BT != nullptr, st), "capture dpre");
+            }
             // skip / residual weight gradients
             {
                 WgradArgs a{};
@@ -263,6 +281,7 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
                 g2.bt = BT;
                 HIPCHK(gemm_rows(g2, st), "dx");
             }
+            if (cap) HIPCHK(capture(cap[7], DX, M * kC, false, st), "capture dx_out");
         }
     }
     // ---- input projection: dW_in[c][i] = sum_rows dx0[row][c] u[row][i]; db_in = sum_rows dx0
@@ -392,6 +411,24 @@ gwd_status gwd_adam_step(gwd_model* m, int32_t member, float* master, const floa
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     return pack_member(m, member, hb);
+}
+
+gwd_status gwd_debug_capture_backward(gwd_model* m, int32_t layer, float* x_in, float* pre, float* dskip, float* dx_in,
+                                      float* dg, float* g, float* dpre, float* dx_out) {
+    if (!m) { set_error("gwd_debug_capture_backward: model is NULL"); return GWD_ERR_ARG; }
+    if (m->arch.kind != 1 || m->two_branch) {
+        set_error("gwd_debug_capture_backward: needs the gated member");
+        return GWD_ERR_UNSUPPORTED;
+    }
+    const int L = m->arch.n_stacks * m->arch.layers_per_stack;
+    if (layer < -1 || layer >= L) { set_error("gwd_debug_capture_backward: layer %d out of range", layer); return GWD_ERR_ARG; }
+    float* p[8] = {x_in, pre, dskip, dx_in, dg, g, dpre, dx_out};
+    if (layer >= 0)
+        for (float* q : p)
+            if (!q || ((uintptr_t)q & 3)) { set_error("gwd_debug_capture_backward: NULL or misaligned buffer"); return GWD_ERR_ARG; }
+    m->cap_layer = layer;
+    for (int i = 0; i < 8; ++i) m->cap_buf[i] = layer >= 0 ? p[i] : nullptr;
+    return GWD_OK;
 }
 
 gwd_status gwd_bce_logits(const float* logits, const float* labels, int64_t n, float* grad, double* loss,

@@ -107,6 +107,7 @@ def _load(path: str = LIB_PATH):
         "gwd_autotune": (I32, [P, ctypes.POINTER(Stream), I32, I32, I32, P, I64, ctypes.POINTER(I32),
                                ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32), P]),
         "gwd_debug_export_weights": (I32, [P, I32, P, I64]),
+        "gwd_debug_capture_backward": (I32, [P, I32, P, P, P, P, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -251,6 +252,14 @@ class Model:
         out = np.zeros(self.export_params, dtype=np.float32)
         check(lib.gwd_debug_export_weights(self.h, member, out.ctypes.data, self.export_params))
         return out
+
+    def capture_backward(self, layer: int, bufs=None):
+        """gwd_debug_capture_backward: the next backward copies gated layer `layer`'s operands and
+        results into bufs (dict of fp32 device tensors x_in, pre, dskip, dx_in, dg, g, dpre, dx_out);
+        layer -1 turns it off."""
+        names = ("x_in", "pre", "dskip", "dx_in", "dg", "g", "dpre", "dx_out")
+        ptrs = [_ptr(bufs[k]) if bufs else 0 for k in names]
+        check(lib.gwd_debug_capture_backward(self.h, layer, *ptrs))
 
     def debug_layer(self, member: int, layer: int, x_in, n_windows: int, window: int, pre_out, x_out, skip,
                     stream=None):

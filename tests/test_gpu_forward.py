@@ -53,7 +53,6 @@ def test_export_tiny(g):
 # ---------------------------------------------------------------- tiny member (64 windows, 8 chirped)
 def test_tiny_member_parity_and_triggers(g):
     from oracle.forward import forward_window
-    from oracle.triggers import triggers as otrig
     from paper_2201_11133_amd import synth
     print("case: tiny member 64 windows", flush=True)
     blob = synth.tiny_weights(0)
@@ -71,10 +70,9 @@ def test_tiny_member_parity_and_triggers(g):
     assert np.array_equal(e0.cpu().numpy(), z2.reshape(-1))              # one member, one window per stream
     offs = np.arange(65) * 4096
     got = g.triggers(e0, offs, 0.9, 4096)
-    # the trigger kernel is exact: same list as the oracle rule applied to the GPU's scores
-    ref = otrig(e0.cpu().numpy().astype(np.float64), offs, 0.9, 4096)
-    assert [(s, a) for s, a, _, _ in got] == [(s, a) for s, a, _, _ in ref]
     assert len(got) <= 64
+    # the trigger list of the oracle's own FP64 scores, fragile decisions exempt
+    _check_triggers_against_oracle(g, e0, z64.reshape(-1), offs, "tiny member")
     m.close()
 
 
@@ -222,3 +220,90 @@ def test_arg_errors_on_device(g, full_model):
     with pytest.raises(g.GwdError) as ei:
         full_model.forward([xd], 4096, 256, out_mode=0, out=out)
     assert ei.value.code == g.ERR_CAPACITY
+
+
+# ---------------------------------------------------------------- FP32 trigger lists vs the FP64 oracle's
+TRIG_MARGIN = 1e-4   # logit distance within which a trigger decision counts as fragile
+
+
+def _oracle_scores(blobs, x):
+    """Ensemble logit of the FP64 oracle (one causal pass per member, members in parallel threads)."""
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle.forward import forward_stream
+    from oracle.stream import ensemble
+    a, _ = oracle_params(blobs[0])
+    x64 = x.astype(np.float64)
+    from oracle.arch import unpack
+    with ThreadPoolExecutor(max_workers=len(blobs)) as ex:
+        zs = list(ex.map(lambda b: forward_stream(a, unpack(a, b.astype(np.float64)), x64), blobs))
+    return ensemble(zs)
+
+
+def _check_triggers_against_oracle(g, e_dev, e64, offs, label):
+    """GPU trigger list (FP32 scores) == the oracle rule on the FP64 oracle's scores, except for
+    decisions that are fragile in the oracle's scores. If every score differs by less than half the
+    margin, a decision can only flip where the oracle's score lies within the margin of the
+    threshold or of its strongest in-window competitor: exactly the fragile set."""
+    from oracle.triggers import triggers as otrig
+    from tests.gpu_common import fragile_keys
+    e = e_dev.cpu().numpy().astype(np.float64)
+    dz = float(np.max(np.abs(e - e64)))
+    got = {(int(s), int(a)) for s, a, _, _ in g.triggers(e_dev, offs, 0.9, 4096)}
+    ref = {(int(s), int(a)) for s, a, _, _ in otrig(e64, offs, 0.9, 4096)}
+    fragile = fragile_keys(e64, offs, 0.9, 4096, TRIG_MARGIN)
+    diff = got ^ ref
+    print(f"{label}: oracle {len(ref)} triggers, gpu {len(got)}, max|dz| = {dz:.3g}, "
+          f"fragile decisions {len(fragile)}, differing {len(diff)} (all fragile: {diff <= fragile})", flush=True)
+    assert dz < TRIG_MARGIN / 2, dz
+    assert diff <= fragile, sorted(diff - fragile)
+    return got, ref
+
+
+@pytest.mark.timeout(900)
+def test_fp32_triggers_match_oracle_64s_slice(g, full_model, full_blob):
+    """The single-member FP32 workload's parity slice: the first 64 s (1,009 windows) of the 4096 s
+    stream with 20 chirps, stitched and clustered on the device, against the trigger list of the
+    oracle's FP64 scores."""
+    from paper_2201_11133_amd import synth
+    print("case: fp32 triggers, 64 s slice of the 4096 s stream", flush=True)
+    x, _ = synth.make_stream(101, 4096.0, 20, spacing=10.0, margin=4.0)
+    x = np.ascontiguousarray(x[:64 * 4096])
+    e_dev = full_model.forward([to_dev(x)], 4096, 256, out_mode=0)
+    e64 = _oracle_scores([full_blob], x)
+    _check_triggers_against_oracle(g, e_dev, e64, [0, len(x)], "64 s slice")
+
+
+@pytest.mark.timeout(900)
+def test_fp32_triggers_match_oracle_injections(g, full_model, full_blob):
+    """16 s around each of the first two injections of the 4096 s stream (chirp near the middle),
+    scored as two streams in one call."""
+    from paper_2201_11133_amd import synth
+    print("case: fp32 triggers, slices around two injections", flush=True)
+    x, injs = synth.make_stream(101, 4096.0, 20, spacing=10.0, margin=4.0)
+    parts = []
+    for inj in injs[:2]:
+        a0 = int(inj.tc * 4096) - 8 * 4096
+        parts.append(np.ascontiguousarray(x[a0:a0 + 16 * 4096]))
+    e_dev = full_model.forward([to_dev(p) for p in parts], 4096, 256, out_mode=0)
+    e64 = np.concatenate([_oracle_scores([full_blob], p) for p in parts])
+    offs = [0, len(parts[0]), len(parts[0]) + len(parts[1])]
+    _check_triggers_against_oracle(g, e_dev, e64, offs, "injection slices")
+
+
+@pytest.mark.timeout(900)
+def test_fp32_ensemble_triggers_match_oracle(g):
+    """A 4-member FP32 ensemble (member seeds 11-14) over 16 s with two chirps: the ensemble minimum
+    and the triggers on the device against the oracle's."""
+    from paper_2201_11133_amd import synth
+    print("case: fp32 4-member ensemble triggers, 16 s", flush=True)
+    blobs = np.stack([synth.full_weights(11 + i) for i in range(4)])
+    x, _ = synth.make_stream(106, 16.0, 2)
+    m = g.Model(g.full_arch(), blobs, "fp32")
+    e_dev = m.forward([to_dev(x)], 4096, 256, out_mode=0)
+    torch.cuda.synchronize()
+    e64 = _oracle_scores(list(blobs), x)
+    m.close()
+    dp = np.abs(sigmoid64(e_dev.cpu().numpy()) - sigmoid64(e64)).max()
+    print(f"4-member fp32 ensemble: max|dp| = {dp:.3g}", flush=True)
+    assert dp <= FP32_P_TOL
+    _check_triggers_against_oracle(g, e_dev, e64, [0, len(x)], "4-member ensemble")

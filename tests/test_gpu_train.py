@@ -267,3 +267,176 @@ def test_full_member_gradient_bf16_stated(g):
     # measured on MI355X: 0.244 and 0.971 (random He-normal weights amplify bf16 rounding)
     assert worst_cos > 0.9 and worst_rel < 0.5
     m.close()
+
+
+# ---------------------------------------------------------------- the benchmarked reduction shape
+def _per_tensor_errors(gg, g_ref, arch):
+    from oracle.arch import layout
+    off, worst_rel, worst_cos = 0, 0.0, 1.0
+    rel = {}
+    for name, shape, _ in layout(arch):
+        n = int(np.prod(shape))
+        a, b = gg[off:off + n], g_ref[off:off + n]
+        nb = np.linalg.norm(b)
+        if nb > 0:
+            rel[name] = float(np.linalg.norm(a - b) / nb)
+            worst_cos = min(worst_cos, float(a @ b / (np.linalg.norm(a) * nb + 1e-300)))
+        off += n
+    return rel, worst_cos
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_full_member_gradient_128_chunks(g, prec):
+    """Gradient of a batch of 128 windows of 512 samples: 128 weight-gradient chunks (one window
+    each) and 128 column-sum chunks, so every reduction takes the two-stage grouped path that the
+    training benchmark (256 windows of 4096) takes. FP32: every tensor within 2e-3 relative of the
+    FP64 oracle gradient. BF16: the error is stated (the layer-local test below is its gate)."""
+    from oracle.arch import FULL
+    from oracle.train import bce_grad, loss_and_grad
+    from paper_2201_11133_amd import synth
+    print(f"case: {prec} full member gradient, B = 128, T = 512", flush=True)
+    B, T = 128, 512
+    blob = synth.full_weights(4)
+    u, _ = synth.make_windows(107, B, B // 2, W=T)
+    y = labels(B, T, 8)
+    m = g.Model(g.full_arch(), blob, prec)
+    u_d = to_dev(u)
+    z, saved = fwd_train(g, m, u_d, B, T, torch.float32)
+    dz = torch.from_numpy(bce_grad(z.cpu().numpy().astype(np.float64), y).astype(np.float32)).cuda()
+    grad, du = backward(g, m, u_d, B, T, saved, dz, torch.float32)
+    gg = grad.cpu().numpy().astype(np.float64)
+    m.close()
+    _, g_ref, du_ref = loss_and_grad(FULL, blob.astype(np.float64), u.astype(np.float64), y)
+    rel, cos = _per_tensor_errors(gg, g_ref, FULL)
+    worst = max(rel.values())
+    rel_u = np.linalg.norm(du.cpu().numpy() - du_ref) / np.linalg.norm(du_ref)
+    print(f"{prec} B=128 gradient: worst per-tensor relative error {worst:.3g} ({max(rel, key=rel.get)}), "
+          f"worst cosine {cos:.4f}, input gradient {rel_u:.3g}", flush=True)
+    assert np.all(np.isfinite(gg))
+    if prec == "fp32":
+        assert worst < 2e-3 and rel_u < 2e-3
+
+
+def _ulp_bf16(v):
+    """Spacing of bfloat16 values at |v| (normal range)."""
+    e = np.floor(np.log2(np.maximum(np.abs(v), 2.0 ** -126)))
+    return 2.0 ** (e - 7)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("layer", [0, 9, 18, 29])
+def test_backward_layer_local_parity(g, prec, layer):
+    """One layer's backward step inside the full backward (128 windows of 1024 samples, the grouped
+    reductions), against the oracle's formulas applied to the operands the kernels read (captured
+    through gwd_debug_capture_backward; BF16 members: bf16-rounded operands, fp32 accumulation).
+    Every GEMM result lies within the forward-error bound of a length-K dot product,
+    |d| <= K u (|A| |B|) (Higham, Accuracy and Stability of Numerical Algorithms, sec. 3.1), with K the
+    contraction length (256 or 512 for the row GEMMs; for the weight gradients the rows of one chunk
+    plus the chunks and groups of the fixed-order reduction); the gate backward within a few fp32
+    ulp of the exact value at the captured inputs, then rounded to bf16 for BF16 members."""
+    from oracle.arch import FULL, layout, unpack
+    from oracle.forward import sigmoid
+    from oracle.quant import to_bf16
+    from oracle.train import bce_grad
+    from paper_2201_11133_amd import synth
+    print(f"case: {prec} backward layer {layer}, B = 128, T = 1024", flush=True)
+    B, T, C = 128, 1024, 128
+    M = B * T
+    u32 = 2.0 ** -24
+    blob = synth.full_weights(4)
+    x_win, _ = synth.make_windows(108, B, B // 2, W=T)
+    y = labels(B, T, 9)
+    m = g.Model(g.full_arch(), blob, prec)
+    names = ("x_in", "pre", "dskip", "dx_in", "dg", "g", "dpre", "dx_out")
+    bufs = {k: torch.empty((M, 2 * C if k in ("pre", "dpre") else C), dtype=torch.float32, device="cuda")
+            for k in names}
+    m.capture_backward(layer, bufs)
+    u_d = to_dev(x_win)
+    z, saved = fwd_train(g, m, u_d, B, T, torch.float32)
+    dz = torch.from_numpy(bce_grad(z.cpu().numpy().astype(np.float64), y).astype(np.float32)).cuda()
+    grad, _ = backward(g, m, u_d, B, T, saved, dz, torch.float32, want_du=False)
+    torch.cuda.synchronize()
+    m.capture_backward(-1)
+    m.close()
+    cap = {k: v.cpu().numpy().astype(np.float64) for k, v in bufs.items()}
+    del bufs
+    gg = grad.cpu().numpy().astype(np.float64)
+    p = unpack(FULL, blob.astype(np.float64))
+    q = to_bf16 if prec == "bf16" else (lambda v: v)
+    last = layer == FULL.n_layers - 1
+    d = FULL.dilation(layer)
+    offs, o = {}, 0
+    for name, shape, _ in layout(FULL):
+        offs[name] = (o, shape)
+        o += int(np.prod(shape))
+
+    def grad_of(name):
+        a, shape = offs[name]
+        return gg[a:a + int(np.prod(shape))].reshape(shape)
+
+    def check(label, got, ref, bound):
+        r = np.abs(got - ref) / (bound + 1e-300)
+        print(f"  {label}: max |d| / bound = {r.max():.3g}", flush=True)
+        assert np.all(np.abs(got - ref) <= bound), (label, float(r.max()))
+
+    ds, dxi, x, pre = cap["dskip"], cap["dx_in"], cap["x_in"], cap["pre"]
+    if prec == "bf16":   # the recompute's layer inputs are bf16 values
+        assert np.array_equal(to_bf16(x), x)
+    # dg = dskip W_s + dx' W_r
+    Ws, qds = q(p[f"skip{layer}.W"]), q(ds)
+    ref, absd = qds @ Ws, np.abs(qds) @ np.abs(Ws)
+    K = C
+    if not last:
+        Wr, qdx = q(p[f"res{layer}.W"]), q(dxi)
+        ref, absd, K = ref + qdx @ Wr, absd + np.abs(qdx) @ np.abs(Wr), 2 * C
+    else:
+        assert not dxi.any()
+    check("dg", cap["dg"], ref, K * u32 * absd * 1.01)
+    # gate backward at the captured pre-activation and dg
+    pf, pg, dg = pre[:, :C], pre[:, C:], cap["dg"]
+    th, sg = np.tanh(pf), sigmoid(pg)
+    g_ref = th * sg
+    df_ref, dgg_ref = dg * sg * (1 - th * th), dg * th * sg * (1 - sg)
+    e_g = 16 * u32 * np.abs(g_ref) + 1e-38
+    e_f = np.abs(dg) * sg * (16 * u32 * (1 - th * th) + 8 * u32)
+    e_gg = np.abs(dg) * np.abs(th) * sg * (16 * u32 * (1 - sg) + 8 * u32)
+    if prec == "bf16":   # then rounded to nearest bf16
+        e_g = e_g + 0.5 * _ulp_bf16(np.abs(g_ref) + e_g)
+        e_f = e_f + 0.5 * _ulp_bf16(np.abs(df_ref) + e_f)
+        e_gg = e_gg + 0.5 * _ulp_bf16(np.abs(dgg_ref) + e_gg)
+    check("g", cap["g"], g_ref, e_g)
+    check("dpre (tanh half)", cap["dpre"][:, :C], df_ref, e_f)
+    check("dpre (sigmoid half)", cap["dpre"][:, C:], dgg_ref, e_gg)
+    gq, dpq = cap["g"], cap["dpre"]
+    # weight gradients: sums over the rows of a window (one chunk), then over 128 chunks in groups
+    Kw = T + B + 64
+
+    def wbound(A, Bm):
+        return Kw * u32 * (np.abs(A).T @ np.abs(Bm)) * 1.01
+
+    check("d skip.W", grad_of(f"skip{layer}.W"), qds.T @ gq, wbound(qds, gq))
+    check("d skip.b", grad_of(f"skip{layer}.b"), ds.sum(axis=0), Kw * u32 * np.abs(ds).sum(axis=0) * 1.01)
+    if not last:
+        check("d res.W", grad_of(f"res{layer}.W"), qdx.T @ gq, wbound(qdx, gq))
+        check("d res.b", grad_of(f"res{layer}.b"), dxi.sum(axis=0), Kw * u32 * np.abs(dxi).sum(axis=0) * 1.01)
+    xw = x.reshape(B, T, C)
+    x_sh = np.zeros_like(xw)
+    x_sh[:, d:] = xw[:, :T - d]
+    x_sh = x_sh.reshape(M, C)
+    dW = grad_of(f"dil{layer}.W")
+    check("d dil.W tap 1", dW[:, :, 1], dpq.T @ x, wbound(dpq, x))
+    check("d dil.W tap 0", dW[:, :, 0], dpq.T @ x_sh, wbound(dpq, x_sh))
+    check("d dil.b", grad_of(f"dil{layer}.b"), dpq.sum(axis=0), Kw * u32 * np.abs(dpq).sum(axis=0) * 1.01)
+    # dx = dx' + dpre[t] W_tap1 + dpre[t + d] W_tap0 (the dilated weights read as [2C out][C in])
+    W = p[f"dil{layer}.W"]
+    W1, W0 = q(W[:, :, 1]), q(W[:, :, 0])
+    dpw = dpq.reshape(B, T, 2 * C)
+    dp_l = np.zeros_like(dpw)
+    dp_l[:, :T - d] = dpw[:, d:]
+    dp_l = dp_l.reshape(M, 2 * C)
+    acc = dpq @ W1 + dp_l @ W0
+    bound = 4 * C * u32 * (np.abs(dpq) @ np.abs(W1) + np.abs(dp_l) @ np.abs(W0)) * 1.01 \
+        + u32 * (np.abs(dxi) + np.abs(acc)) * 1.01
+    check("dx", cap["dx_out"], dxi + acc, bound)

@@ -84,3 +84,48 @@ def test_records_carry_logit_and_probability():
 
 def test_empty_streams():
     assert triggers(np.zeros(0), [0, 0, 0]) == []
+
+
+def _fragile_brute(e, offsets, p_thr, wc, margin):
+    import math
+    thr = math.log(p_thr / (1 - p_thr))
+    out = set()
+    for s in range(len(offsets) - 1):
+        seg = [float(v) for v in e[offsets[s]:offsets[s + 1]]]
+        n = len(seg)
+        for a in range(n):
+            nb = [seg[b] for b in range(max(0, a - wc), min(n, a + wc + 1)) if b != a]
+            comp = max(nb) if nb else -math.inf
+            if abs(seg[a] - thr) < margin or abs(seg[a] - comp) < margin:
+                out.add((s, a))
+    return out
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_fragile_decisions_brute_force(seed):
+    """The fragile set against its definition, loop by loop, on quantised streams (many near ties)."""
+    from oracle.triggers import fragile_decisions
+    rng = np.random.default_rng(seed)
+    lens = [0, 1, 37, 200, 5]
+    e = np.round(rng.normal(2.2, 0.5, sum(lens)) * 200) / 200
+    offs = np.concatenate([[0], np.cumsum(lens)])
+    for wc, m in [(1, 1e-3), (7, 6e-3), (50, 2e-2)]:
+        assert fragile_decisions(e, offs, 0.9, wc, m) == _fragile_brute(e, offs, 0.9, wc, m)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_small_perturbations_flip_only_fragile_decisions(seed):
+    """Scores perturbed by less than margin / 2 give a trigger list that differs from the
+    unperturbed one only at fragile decisions (the property the FP32 parity tests rely on)."""
+    from oracle.triggers import fragile_decisions
+    rng = np.random.default_rng(seed)
+    lens = [300, 1, 450]
+    offs = np.concatenate([[0], np.cumsum(lens)])
+    e = np.round(rng.normal(2.2, 0.3, sum(lens)) * 100) / 100
+    margin = 0.02
+    ref = set(triggers_brute(e, offs, 0.9, 20))
+    fr = fragile_decisions(e, offs, 0.9, 20, margin)
+    for _ in range(20):
+        ep = e + rng.uniform(-0.49, 0.49, e.size) * margin
+        got = set(triggers_brute(ep, offs, 0.9, 20))
+        assert (got ^ ref) <= fr
