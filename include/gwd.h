@@ -436,6 +436,31 @@ gwd_status gwd_debug_layer(gwd_model* model, int32_t member, int32_t layer, cons
                            float* skip_inout, void* hip_stream);
 gwd_status gwd_debug_export_weights(const gwd_model* model, int32_t member, float* out, int64_t n_params);
 
+/* Per-layer outputs of a fused launch (test support for layer-local parity of the timed kernels).
+ * Runs the fused BF16/FP8 launch that gwd_forward issues at gated layer `layer` for windows of
+ * length `window` (three consecutive layers of a stack, or four in a BF16 quad; see
+ * gwd_set_tiling), on n_windows windows of caller-provided input x_in [n_windows][window][C] (device
+ * fp32, rounded to bf16 as the residual stream of these paths is; each window zero-context), with
+ * skip_inout [n_windows window][C] the skip sum before the launch (ignored when `layer` is 0) and
+ * updated in place, and writes, for every layer j of the launch, its pre-activation
+ * pre_out[j][row][2C] (fp32), its residual output x_out[j][row][C] (the bf16 values, as fp32; not
+ * written for the network's last layer) and the running skip sum skip_out[j][row][C]
+ * (row = window index * window + t). The arithmetic is that of the launch gwd_forward makes.
+ * *layers_out receives the number of layers of the launch; with all buffers NULL the call only
+ * reports it. GWD_ERR_ARG if no fused launch starts at `layer` for this window length, for bad
+ * indices or misaligned (16-byte) buffers; GWD_ERR_UNSUPPORTED for FP32 or two-branch models. */
+gwd_status gwd_debug_fused(gwd_model* model, int32_t member, int32_t layer, const float* x_in, int32_t n_windows,
+                           int32_t window, float* skip_inout, float* pre_out, float* x_out, float* skip_out,
+                           int32_t* layers_out, void* hip_stream);
+
+/* One matrix-core instruction on one wave (test support: the accumulation rounding of the
+ * instructions the reduced-precision kernels use). D = A B + C for A [32][K] and B [K][32]
+ * (row-major device arrays of bf16 bit patterns for kind 0, K = 16, v_mfma_f32_32x32x16_bf16; of
+ * E4M3 (OCP) bytes for kind 1, K = 64, v_mfma_scale_f32_32x32x64_f8f6f4 with unit block scales) and
+ * C, D [32][32] fp32 row-major. GWD_ERR_ARG for another kind or NULL/misaligned pointers,
+ * GWD_ERR_NO_DEVICE without a GPU. Asynchronous on hip_stream. */
+gwd_status gwd_debug_mfma(int32_t kind, const void* a, const void* b, const float* c, float* d, void* hip_stream);
+
 /* Backward operands of one gated layer (test support for layer-local parity of the hand-written
  * backward, "AI ensemble construction"). After this call, every gwd_backward on the model copies,
  * for gated layer `layer` (of the member it is called for), the operands and results of that layer's

@@ -358,7 +358,6 @@ gwd_status gwd_load_weights(const gwd_arch* arch, int32_t n_members, const float
     if (n_params != np) { set_error("gwd_load_weights: n_params %lld, architecture needs %lld", (long long)n_params, (long long)np); return GWD_ERR_ARG; }
     if (precision != GWD_FP32 && precision != GWD_BF16 && precision != GWD_FP8_E4M3 && precision != GWD_FP64) { set_error("gwd_load_weights: unknown precision %d", (int)precision); return GWD_ERR_ARG; }
     if (!arch_supported(arch)) { set_error("gwd_load_weights: architecture not supported by the GPU kernels"); return GWD_ERR_UNSUPPORTED; }
-    if (arch->kind == 0 && precision != GWD_FP32 && precision != GWD_FP64) { set_error("gwd_load_weights: the plain member runs in FP32 (or FP64 for training checks) only"); return GWD_ERR_UNSUPPORTED; }
     if (arch->kind >= 1 && precision == GWD_FP64) { set_error("gwd_load_weights: FP64 is for the plain member's gradient checks only"); return GWD_ERR_UNSUPPORTED; }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) { set_error("gwd_load_weights: no HIP device"); return GWD_ERR_NO_DEVICE; }
@@ -515,6 +514,48 @@ gwd_status gwd_debug_layer(gwd_model* m, int32_t member, int32_t layer, const fl
     e = launch_layer_debug(m, member, layer, x_in, n_windows, window, pre_out, x_out, skip, (hipStream_t)hip_stream);
     if (e != hipSuccess) return hip_fail(e, "layer kernel launch");
     return GWD_OK;
+}
+
+gwd_status gwd_debug_fused(gwd_model* m, int32_t member, int32_t layer, const float* x_in, int32_t n_windows,
+                           int32_t window, float* skip_inout, float* pre_out, float* x_out, float* skip_out,
+                           int32_t* layers_out, void* hip_stream) {
+    if (!m || !layers_out) { set_error("gwd_debug_fused: NULL argument"); return GWD_ERR_ARG; }
+    *layers_out = 0;
+    if (m->arch.kind != 1 || m->two_branch || (m->prec != GWD_BF16 && m->prec != GWD_FP8_E4M3)) {
+        set_error("gwd_debug_fused: needs a BF16 or FP8 gated (kind 1) model");
+        return GWD_ERR_UNSUPPORTED;
+    }
+    const int L = m->arch.n_stacks * m->arch.layers_per_stack;
+    if (member < 0 || member >= m->n_members) { set_error("gwd_debug_fused: member %d out of range", member); return GWD_ERR_ARG; }
+    if (layer < 0 || layer >= L) { set_error("gwd_debug_fused: layer %d out of range", layer); return GWD_ERR_ARG; }
+    if (n_windows < 1 || window < 128 || window % 128) { set_error("gwd_debug_fused: window must be a positive multiple of 128"); return GWD_ERR_SHAPE; }
+    const int nl = fused_layers_at(m, layer, window);
+    if (nl == 0) { set_error("gwd_debug_fused: no fused launch starts at layer %d", layer); return GWD_ERR_ARG; }
+    *layers_out = nl;
+    if (!pre_out && !x_out && !skip_out && !x_in && !skip_inout) return GWD_OK;   // query
+    if (!x_in || !skip_inout || !pre_out || !x_out || !skip_out) { set_error("gwd_debug_fused: NULL buffer"); return GWD_ERR_ARG; }
+    const void* ptrs[5] = {x_in, skip_inout, pre_out, x_out, skip_out};
+    for (const void* q : ptrs)
+        if ((uintptr_t)q & 15) { set_error("gwd_debug_fused: buffers must be 16-byte aligned"); return GWD_ERR_ARG; }
+    hipError_t e = hipSetDevice(m->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    e = launch_fused_debug(m, member, layer, x_in, n_windows, window, skip_inout, pre_out, x_out, skip_out,
+                           (hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_fail(e, "fused kernel launch");
+    return GWD_OK;
+}
+
+gwd_status gwd_debug_mfma(int32_t kind, const void* a, const void* b, const float* c, float* d, void* hip_stream) {
+    if (kind != 0 && kind != 1) { set_error("gwd_debug_mfma: kind must be 0 (bf16) or 1 (E4M3)"); return GWD_ERR_ARG; }
+    if (!a || !b || !c || !d) { set_error("gwd_debug_mfma: NULL buffer"); return GWD_ERR_ARG; }
+    if (((uintptr_t)a & 1) || ((uintptr_t)b & 1) || ((uintptr_t)c & 3) || ((uintptr_t)d & 3)) {
+        set_error("gwd_debug_mfma: misaligned buffer");
+        return GWD_ERR_ARG;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) { set_error("gwd_debug_mfma: no HIP device"); return GWD_ERR_NO_DEVICE; }
+    hipError_t e = launch_mfma_probe(kind, a, b, c, d, (hipStream_t)hip_stream);
+    return e == hipSuccess ? GWD_OK : hip_fail(e, "mfma probe launch");
 }
 
 gwd_status gwd_debug_time_layer(gwd_model* m, int32_t member, int32_t layer, int32_t reps, float* ms_per_launch,

@@ -463,6 +463,12 @@ struct FusedArgs {
     int S;
     const float* w_in;
     const float* b_in;
+    // test support (debug instantiations only): per-layer pre-activations [NL][rows][256], residual
+    // outputs [NL][rows][128] and running skip sums [NL][rows][128], rows = windows x T
+    float* dbg_pre;
+    float* dbg_x;
+    float* dbg_skip;
+    int64_t dbg_rows;
 };
 
 __device__ inline uint8_t* fu_buf(uint8_t* lds, int j) { return lds + (j == 0 ? FU_B0 : j == 1 ? FU_B1 : FU_B2); }
@@ -527,7 +533,9 @@ struct ChunkRows {
 // network's last, which writes the skip sum only (its residual projection is not part of the model).
 // G2: the weights are block-diagonal over two 64-channel groups (the two-branch member); each wave
 // then takes only the k-steps of its own group's input channels, since the others multiply zeros.
-template <bool FROM_STREAM, bool SKIP_INIT, int NL, bool LAST, bool G2>
+// DBG: test-support instantiation that also writes every layer's pre-activation, residual output and
+// running skip sum of the stored rows to the dbg_* buffers (the arithmetic is unchanged).
+template <bool FROM_STREAM, bool SKIP_INIT, int NL, bool LAST, bool G2, bool DBG = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void fused_bf16_kernel(FusedArgs p) {
     static_assert(NL == 3 || NL == 4, "three or four layers");
     static_assert(!LAST || NL == 4, "the network's last layer ends a quad");
@@ -708,6 +716,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                     for (int i = 0; i < 2; ++i) acur[i] = anxt[i];
                 }
             }
+            if constexpr (DBG) {  // pre-activations (the accumulators started at the biases)
+#pragma unroll
+                for (int rb = 0; rb < 2; ++rb) {
+                    const int sr = sb + 32 * rb + r;
+                    if (store && sr < n_sub) {
+                        float* po = p.dbg_pre + ((int64_t)j * p.dbg_rows + wrow0 + cls + (int64_t)p.d0 * sr) * (2 * kC);
+                        store_col16(po + cb, af[rb]);
+                        store_col16(po + kC + cb, ag[rb]);
+                    }
+                }
+            }
             // the weight fragments of the second phase, residual and skip columns side by side; the
             // first PF2 pairs are in flight during the gate
             // (the network's last layer packs its skip columns only, as column blocks 0-3; its residual
@@ -819,6 +838,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
 #pragma unroll
                 for (int i = 0; i < 16; ++i) sk[rb][i] = (SKIP_INIT && j == 0) ? as[rb][i] : sk[rb][i] + as[rb][i];
             __syncthreads();  // the next layer's input (or the chunk's output) is complete
+            if constexpr (DBG) {  // this layer's residual output rows and running skip sums
+                if (store) {
+#pragma unroll
+                    for (int it = 0; it < 4 && resid; ++it) {
+                        const int idx = tid + 256 * it, rr = idx >> 4, c8 = 8 * (idx & 15);
+                        const int sr = sb + rr;
+                        if (sr < n_sub) {
+                            const uint4 w = *(const uint4*)(Xo + rr * FU_XROW + 2 * c8);
+                            float* xo = p.dbg_x + ((int64_t)j * p.dbg_rows + wrow0 + cls + (int64_t)p.d0 * sr) * kC + c8;
+                            *(float4*)xo = make_float4(__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xffff0000u),
+                                                       __uint_as_float(w.y << 16), __uint_as_float(w.y & 0xffff0000u));
+                            *(float4*)(xo + 4) = make_float4(__uint_as_float(w.z << 16), __uint_as_float(w.z & 0xffff0000u),
+                                                             __uint_as_float(w.w << 16), __uint_as_float(w.w & 0xffff0000u));
+                        }
+                    }
+#pragma unroll
+                    for (int rb = 0; rb < 2; ++rb) {
+                        const int sr = sb + 32 * rb + r;
+                        if (sr < n_sub)
+                            store_col16(p.dbg_skip + ((int64_t)j * p.dbg_rows + wrow0 + cls + (int64_t)p.d0 * sr) * kC + cb,
+                                        sk[rb]);
+                    }
+                }
+            }
         }
         // ---- chunk output: x rows from the last layer's output buffer (16-byte stores), skip rows
         // from registers
@@ -878,7 +921,8 @@ __device__ inline uint8_t* fe_bbuf(uint8_t* lds, int j) { return lds + 3 * FE_XB
 
 // G2 as in the BF16 kernel: one k-step covers 64 input channels, i.e. one group, so a wave of group
 // q / 2 takes steps q / 2 and 2 + q / 2 of phase 1 and step q / 2 of phase 2.
-template <bool FROM_STREAM, bool SKIP_INIT, bool G2>
+// DBG as in the BF16 kernel.
+template <bool FROM_STREAM, bool SKIP_INIT, bool G2, bool DBG = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void fused3_fp8_kernel(FusedArgs p) {
     using T = LP<true, FE_RB, 4>;  // E4M3 fragments (32 B per lane), 4 waves x FE_RB row blocks
     constexpr int RB = FE_RB;
@@ -1006,6 +1050,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                     }
                 }
             }
+            if constexpr (DBG) {  // pre-activations: column scale, then bias, as the gate takes them
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        const int sr = sb + 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
+                        if (store && sr < n_sub) {
+                            float* po = p.dbg_pre + ((int64_t)j * p.dbg_rows + wrow0 + cls + (int64_t)p.d0 * sr) * (2 * kC);
+                            po[n] = fmaf(af[rb][i], sf, bf);
+                            po[kC + n] = fmaf(ag[rb][i], sg, bg);
+                        }
+                    }
+            }
             const uint8_t* Wr = p.wrs[j] + ((size_t)(q * T::NK2) * 64 + lane) * T::FRAG;
             const uint8_t* Ws = p.wrs[j] + ((size_t)((4 + q) * T::NK2) * 64 + lane) * T::FRAG;
             if constexpr (G2) {
@@ -1100,6 +1157,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                 }
             }
             __syncthreads();
+            if constexpr (DBG) {  // this layer's residual output rows (bf16) and running skip sums
+                if (store) {
+                    const uint8_t* XD = fe_bbuf(lds, (j + 1) & 1);
+#pragma unroll
+                    for (int it = 0; it < SCH; ++it) {
+                        const int idx = tid + 256 * it, rr = idx >> 4, c8 = 8 * (idx & 15);
+                        const int sr = sb + rr;
+                        if (sr < n_sub) {
+                            const uint4 w = *(const uint4*)(XD + rr * FU_XROW + 2 * c8);
+                            float* xo = p.dbg_x + ((int64_t)j * p.dbg_rows + wrow0 + cls + (int64_t)p.d0 * sr) * kC + c8;
+                            *(float4*)xo = make_float4(__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xffff0000u),
+                                                       __uint_as_float(w.y << 16), __uint_as_float(w.y & 0xffff0000u));
+                            *(float4*)(xo + 4) = make_float4(__uint_as_float(w.z << 16), __uint_as_float(w.z & 0xffff0000u),
+                                                             __uint_as_float(w.w << 16), __uint_as_float(w.w & 0xffff0000u));
+                        }
+                    }
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                        for (int i = 0; i < 16; ++i) {
+                            const int sr = sb + 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
+                            if (sr < n_sub)
+                                p.dbg_skip[((int64_t)j * p.dbg_rows + wrow0 + cls + (int64_t)p.d0 * sr) * kC + n] = sk[rb][i];
+                        }
+                }
+            }
         }
         // ---- chunk output: x rows from the last residual buffer, skip from registers
         if (store) {
@@ -1145,7 +1228,8 @@ static void launch_fused_bf16(bool g2, dim3 grid, hipStream_t st, const FusedArg
 
 template <bool FP8>
 static hipError_t launch_fused(gwd_model* m, int member, int l, int nl, const uint16_t* x_in, uint16_t* x_out,
-                               float* skip, int nb, int T, const FwdBatch* fb, hipStream_t st) {
+                               float* skip, int nb, int T, const FwdBatch* fb, hipStream_t st,
+                               const FusedArgs* dbg = nullptr) {
     const int L = m->arch.n_stacks * m->arch.layers_per_stack;
     FusedArgs a{};
     for (int j = 0; j < nl; ++j) {
@@ -1181,6 +1265,26 @@ static hipError_t launch_fused(gwd_model* m, int member, int l, int nl, const ui
         a.S = fb->S;
     }
     const dim3 grid((unsigned)(per * a.n_seg));
+    if (dbg) {  // test support: the same launch with per-layer outputs (buffer input, dense weights)
+        if (stream_in || m->two_branch) return hipErrorInvalidValue;
+        a.dbg_pre = dbg->dbg_pre;
+        a.dbg_x = dbg->dbg_x;
+        a.dbg_skip = dbg->dbg_skip;
+        a.dbg_rows = (int64_t)nb * T;
+        if (FP8) {
+            if (nl != 3) return hipErrorInvalidValue;
+            if (first) hipLaunchKernelGGL((fused3_fp8_kernel<false, true, false, true>), grid, dim3(256), 0, st, a);
+            else hipLaunchKernelGGL((fused3_fp8_kernel<false, false, false, true>), grid, dim3(256), 0, st, a);
+        } else if (nl == 3) {
+            if (first) hipLaunchKernelGGL((fused_bf16_kernel<false, true, 3, false, false, true>), grid, dim3(256), 0, st, a);
+            else hipLaunchKernelGGL((fused_bf16_kernel<false, false, 3, false, false, true>), grid, dim3(256), 0, st, a);
+        } else {
+            if (first) return hipErrorInvalidValue;
+            if (l + 3 == L - 1) hipLaunchKernelGGL((fused_bf16_kernel<false, false, 4, true, false, true>), grid, dim3(256), 0, st, a);
+            else hipLaunchKernelGGL((fused_bf16_kernel<false, false, 4, false, false, true>), grid, dim3(256), 0, st, a);
+        }
+        return hipGetLastError();
+    }
     if (FP8) {
         if (nl != 3) return hipErrorInvalidValue;
         if (m->two_branch) {   // block-diagonal weights: skip the zero blocks
@@ -1276,6 +1380,71 @@ static hipError_t debug_lp(gwd_model* m, int member, int l, const float* x_in, i
         hipLaunchKernelGGL(bf16_to_f32_kernel, dim3(nblk), dim3(256), 0, st, tmp + n, n, x_out);
     hipError_t e2 = hipFreeAsync(tmp, st);
     return e != hipSuccess ? e : (e2 != hipSuccess ? e2 : hipGetLastError());
+}
+
+// Test support: one matrix-core instruction on one wave, D = A B + C with A [32][K] and B [K][32]
+// row-major (kind 0: bf16 bits, K = 16, v_mfma_f32_32x32x16_bf16; kind 1: E4M3 bytes, K = 64,
+// v_mfma_scale_f32_32x32x64_f8f6f4 with unit scales), C and D [32][32] fp32 row-major. Lane (h, r)
+// holds row r of A and column r of B over k in [K/2 h, K/2 h + K/2), and accumulator element i is
+// D[8 (i / 4) + 4 h + i % 4][r], the layouts the layer kernels use.
+__global__ __launch_bounds__(64) void mfma_probe_kernel(int kind, const uint8_t* A, const uint8_t* B, const float* C,
+                                                        float* D) {
+    const int lane = threadIdx.x, r = lane & 31, h = lane >> 5;
+    floatx16 c;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) c[i] = C[(8 * (i >> 2) + 4 * h + (i & 3)) * 32 + r];
+    floatx16 d;
+    if (kind == 0) {
+        const uint16_t* A16 = (const uint16_t*)A;
+        const uint16_t* B16 = (const uint16_t*)B;
+        uint16_t a[8], b[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            a[e] = A16[r * 16 + 8 * h + e];
+            b[e] = B16[(8 * h + e) * 32 + r];
+        }
+        d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                    0, 0, 0);
+    } else {
+        uint8_t a[32], b[32];
+#pragma unroll
+        for (int e = 0; e < 32; ++e) {
+            a[e] = A[r * 64 + 32 * h + e];
+            b[e] = B[(32 * h + e) * 32 + r];
+        }
+        d = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(__builtin_bit_cast(intx8, a), __builtin_bit_cast(intx8, b),
+                                                            c, 0, 0, 0, 127, 0, 127);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) D[(8 * (i >> 2) + 4 * h + (i & 3)) * 32 + r] = d[i];
+}
+hipError_t launch_mfma_probe(int kind, const void* A, const void* B, const float* C, float* D, hipStream_t st) {
+    hipLaunchKernelGGL(mfma_probe_kernel, dim3(1), dim3(64), 0, st, kind, (const uint8_t*)A, (const uint8_t*)B, C, D);
+    return hipGetLastError();
+}
+
+// Test support: the fused launch that starts at layer l, on caller-provided fp32 activations of nb
+// windows (rounded to bf16, the residual format of this path), with every layer's pre-activation,
+// residual output and running skip sum written to pre_out [nl][nb T][256], x_out [nl][nb T][128] and
+// skip_out [nl][nb T][128]; skip [nb T][128] is the skip sum before the launch (updated in place).
+int fused_layers_at(const gwd_model* m, int l, int T) { return fused_layers(m, l, T); }
+hipError_t launch_fused_debug(gwd_model* m, int member, int l, const float* x_in, int nb, int T, float* skip,
+                              float* pre_out, float* x_out, float* skip_out, hipStream_t st) {
+    const int nl = fused_layers(m, l, T);
+    if (nl == 0) return hipErrorInvalidValue;
+    const int64_t n = (int64_t)nb * T * kC;
+    uint16_t* tmp = nullptr;
+    hipError_t e = hipMallocAsync((void**)&tmp, 2 * n * sizeof(uint16_t), st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(f32_to_bf16_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x_in, n, tmp);
+    FusedArgs d{};
+    d.dbg_pre = pre_out;
+    d.dbg_x = x_out;
+    d.dbg_skip = skip_out;
+    e = m->prec == GWD_FP8_E4M3 ? launch_fused<true>(m, member, l, nl, tmp, tmp + n, skip, nb, T, nullptr, st, &d)
+                                : launch_fused<false>(m, member, l, nl, tmp, tmp + n, skip, nb, T, nullptr, st, &d);
+    hipError_t e2 = hipFreeAsync(tmp, st);
+    return e != hipSuccess ? e : e2;
 }
 
 // One gated layer on bf16 activations, for the training forward and its recompute: x_in and x_out

@@ -16,6 +16,10 @@ namespace gwd {
 constexpr int kC = 128;
 // Rows (time steps) of one layer-kernel tile.
 constexpr int kBM = 64;
+// Plain member (kind 0, four 16-channel layers and a 1x1 to one logit): per-output-channel weight
+// scales follow its packed blob, 16 per conv layer then 1 for the output layer (1 unless FP8).
+constexpr int kTinyScales = 4 * 16 + 1;
+__host__ __device__ inline int tiny_scale_index(int layer, int out_channel) { return 16 * layer + out_channel; }
 
 // One stream as the kernels see it; win_begin / sample_begin are prefix sums over streams.
 struct StreamDesc {
@@ -155,6 +159,12 @@ hipError_t launch_layer_train_bf16io(gwd_model* m, int member, int l, const uint
 hipError_t launch_f32_to_bf16(const float* x, int64_t n, uint16_t* y, hipStream_t st);
 hipError_t launch_bf16_to_f32(const uint16_t* x, int64_t n, float* y, hipStream_t st);
 int train_layers_per_launch(const gwd_model* m, int l, int T);
+// Test support: layers of the fused BF16/FP8 launch that starts at layer l (0 if none), and that
+// launch with per-layer outputs.
+int fused_layers_at(const gwd_model* m, int l, int T);
+hipError_t launch_mfma_probe(int kind, const void* A, const void* B, const float* C, float* D, hipStream_t st);
+hipError_t launch_fused_debug(gwd_model* m, int member, int l, const float* x_in, int nb, int T, float* skip,
+                              float* pre_out, float* x_out, float* skip_out, hipStream_t st);
 hipError_t launch_fused_train(gwd_model* m, int member, int l, int nl, const uint16_t* x_in, uint16_t* x_out,
                               float* skip, int nb, int T, hipStream_t st);
 

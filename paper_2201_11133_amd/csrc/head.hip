@@ -174,7 +174,7 @@ constexpr int TINY_HALO = 16;
 constexpr int TINY_C = 16;
 
 struct TinyArgs {
-    const float* blob;  // canonical blob (1,681 floats)
+    const float* blob;  // packed blob (1,681 floats, operand values) + kTinyScales channel scales
     const StreamDesc* streams;
     int n_streams;
     int64_t win_base;
@@ -182,8 +182,25 @@ struct TinyArgs {
     OutDesc o;
 };
 
+// Operand rounding of the reduced-precision forms: P = 0 fp32 (none), 1 bf16 (nearest even),
+// 2 E4M3 (nearest even, saturated at +/-448; NaN stays NaN).
+template <int P>
+__device__ inline float tiny_round(float v) {
+    if constexpr (P == 1) return (float)(__bf16)v;
+    if constexpr (P == 2) {
+        v = fabsf(v) > 448.f ? copysignf(448.f, v) : v;
+        return __builtin_amdgcn_cvt_f32_fp8((int)__builtin_amdgcn_cvt_pk_fp8_f32(v, v, 0, false), 0);
+    }
+    return v;
+}
+
+// P as above. BF16: operands rounded to bf16, products exact in fp32 and accumulated in fp32 from
+// the bias (the arithmetic of the bf16 matrix instruction). FP8: E4M3 operands (weights as codes,
+// activations with unit scale), fp32 accumulation, then the channel scale and the bias. Each layer's
+// output is stored in the operand format; the logit stays fp32.
+template <int P>
 __global__ __launch_bounds__(256) void tiny_forward_kernel(TinyArgs p) {
-    __shared__ float w[1681];
+    __shared__ float w[1681 + kTinyScales];
     __shared__ float u[TINY_ROWS + TINY_HALO][2];
     __shared__ float ya[TINY_ROWS + TINY_HALO][TINY_C + 1];
     __shared__ float yb[TINY_ROWS + TINY_HALO][TINY_C + 1];
@@ -196,7 +213,8 @@ __global__ __launch_bounds__(256) void tiny_forward_kernel(TinyArgs p) {
     int lo, hi;
     owner_rows(p.o, k, sd.length, lo, hi);
     if (t0 + TINY_ROWS <= lo || t0 >= hi) return;
-    for (int i = tid; i < 1681; i += 256) w[i] = p.blob[i];
+    for (int i = tid; i < 1681 + kTinyScales; i += 256) w[i] = p.blob[i];
+    const float* sc = w + 1681;
     // LDS row i holds time t = t0 - TINY_HALO + i
     const int64_t start = k * (int64_t)p.o.S;
     for (int i = tid; i < TINY_ROWS + TINY_HALO; i += 256) {
@@ -206,8 +224,8 @@ __global__ __launch_bounds__(256) void tiny_forward_kernel(TinyArgs p) {
             u0 = sd.ch0[(start + t) * sd.stride];
             u1 = sd.ch1[(start + t) * sd.stride];
         }
-        u[i][0] = u0;
-        u[i][1] = u1;
+        u[i][0] = tiny_round<P>(u0);
+        u[i][1] = tiny_round<P>(u1);
     }
     __syncthreads();
     // blob offsets: conv0 W[16][2][2] b[16] (80), conv1..3 W[16][16][2] b[16] (528 each), out W[16] b[1]
@@ -227,14 +245,15 @@ __global__ __launch_bounds__(256) void tiny_forward_kernel(TinyArgs p) {
             const int t = t0 - TINY_HALO + i;
             float acc = 0.f;
             if (t >= 0) {  // rows before the window start are zero input for the next layer
-                acc = B[o];
+                acc = P == 2 ? 0.f : B[o];
                 for (int c = 0; c < cin; ++c) {
                     const float xo = (layer == 0) ? u[i - d][c] : src[i - d][c];
                     const float xc = (layer == 0) ? u[i][c] : src[i][c];
                     acc = fmaf(W[(o * cin + c) * 2 + 0], (t - d >= 0) ? xo : 0.f, acc);
                     acc = fmaf(W[(o * cin + c) * 2 + 1], xc, acc);
                 }
-                acc = fmaxf(acc, 0.f);
+                if (P == 2) acc = fmaf(acc, sc[tiny_scale_index(layer, o)], B[o]);
+                acc = tiny_round<P>(fmaxf(acc, 0.f));
             }
             dst[i][o] = acc;
         }
@@ -248,7 +267,7 @@ __global__ __launch_bounds__(256) void tiny_forward_kernel(TinyArgs p) {
         if (t < lo || t >= hi) continue;
         float z = 0.f;
         for (int c = 0; c < TINY_C; ++c) z = fmaf(Wo[c], yb[TINY_HALO + rr][c], z);
-        z += Wo[TINY_C];
+        z = P == 2 ? fmaf(z, sc[tiny_scale_index(4, 0)], Wo[TINY_C]) : z + Wo[TINY_C];
         emit_logit(p.o, sd, gw, k, t, z);
     }
 }
@@ -261,7 +280,10 @@ hipError_t launch_tiny_forward(const gwd_model* m, const FwdBatch& fb, hipStream
     a.win_base = fb.win_base;
     a.tiles_per_window = fb.T / TINY_ROWS;
     a.o = out_desc(fb);
-    hipLaunchKernelGGL(tiny_forward_kernel, dim3(fb.nb * a.tiles_per_window), dim3(256), 0, st, a);
+    const dim3 grid(fb.nb * a.tiles_per_window);
+    if (m->prec == GWD_BF16) hipLaunchKernelGGL(tiny_forward_kernel<1>, grid, dim3(256), 0, st, a);
+    else if (m->prec == GWD_FP8_E4M3) hipLaunchKernelGGL(tiny_forward_kernel<2>, grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(tiny_forward_kernel<0>, grid, dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

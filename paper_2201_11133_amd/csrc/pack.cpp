@@ -157,9 +157,34 @@ gwd_status pack_member(gwd_model* m, int member, const float* blob) {
         memcpy(img.data() + byte_off, src, n * 4);
     };
     if (a.kind == 0) {
-        int64_t off = reserve(m->n_params * 4);
-        putf(off, blob, m->n_params);
+        // the blob with its weights replaced by the operands the kernel multiplies: bf16 values (BF16),
+        // or E4M3 code values (FP8) followed by one scale per output channel of every weight matrix
+        // (tiny_scale_table); biases stay fp32
+        int64_t off = reserve((m->n_params + kTinyScales) * 4);
+        float* w = (float*)(img.data() + off);
+        memcpy(w, blob, m->n_params * 4);
         mw.blob = off / 4;
+        int64_t wo = 0;
+        for (int layer = 0; layer <= a.n_stacks * a.layers_per_stack; ++layer) {
+            const bool out_layer = layer == a.n_stacks * a.layers_per_stack;
+            const int cout = out_layer ? 1 : a.channels;
+            const int per = out_layer ? a.channels : (layer == 0 ? a.in_channels : a.channels) * a.kernel_size;
+            for (int o = 0; o < cout; ++o) {
+                float* row = w + wo + (int64_t)o * per;
+                if (m->prec == GWD_BF16) {
+                    for (int i = 0; i < per; ++i) row[i] = bf16_to_f32(f32_to_bf16(row[i]));
+                } else if (m->prec == GWD_FP8_E4M3) {
+                    float amax = 0.f;
+                    for (int i = 0; i < per; ++i) amax = fmaxf(amax, fabsf(row[i]));
+                    const float s = amax > 0.f ? amax / 448.f : 1.f;
+                    for (int i = 0; i < per; ++i) row[i] = e4m3_to_f32(f32_to_e4m3(row[i] / s));
+                    w[m->n_params + tiny_scale_index(layer, o)] = s;
+                } else {
+                    w[m->n_params + tiny_scale_index(layer, o)] = 1.f;
+                }
+            }
+            wo += (int64_t)cout * per + cout;
+        }
     } else {
         BlobView v = view_kind1(a);
         const int L = a.n_stacks * a.layers_per_stack;
@@ -283,6 +308,18 @@ gwd_status export_member(const gwd_model* m, int member, float* out) {
     const float* f = (const float*)img.data();
     if (a.kind == 0) {
         memcpy(out, f + mw.blob, m->n_params * 4);
+        if (m->prec == GWD_FP8_E4M3) {  // code value times its channel's scale
+            int64_t wo = 0;
+            for (int layer = 0; layer <= a.n_stacks * a.layers_per_stack; ++layer) {
+                const bool out_layer = layer == a.n_stacks * a.layers_per_stack;
+                const int cout = out_layer ? 1 : a.channels;
+                const int per = out_layer ? a.channels : (layer == 0 ? a.in_channels : a.channels) * a.kernel_size;
+                for (int o = 0; o < cout; ++o)
+                    for (int i = 0; i < per; ++i)
+                        out[wo + (int64_t)o * per + i] *= f[mw.blob + m->n_params + tiny_scale_index(layer, o)];
+                wo += (int64_t)cout * per + cout;
+            }
+        }
         return GWD_OK;
     }
     BlobView v = view_kind1(a);

@@ -42,6 +42,10 @@ static gwd_status check_train(const gwd_model* m, int member, const void* window
     if (B < 1 || T < 1) { set_error("%s: bad batch shape", who); return GWD_ERR_SHAPE; }
     if (m->arch.kind == 1 && T % 128 != 0) { set_error("%s: window %d must be a multiple of 128", who, T); return GWD_ERR_SHAPE; }
     if (m->arch.kind == 1 && m->prec == GWD_FP8_E4M3) { set_error("%s: FP8 models are inference only", who); return GWD_ERR_UNSUPPORTED; }
+    if (m->arch.kind == 0 && m->prec != GWD_FP32 && m->prec != GWD_FP64) {
+        set_error("%s: the plain member trains in FP32 or FP64 only", who);
+        return GWD_ERR_UNSUPPORTED;
+    }
     return GWD_OK;
 }
 

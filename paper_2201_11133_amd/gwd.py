@@ -108,6 +108,8 @@ def _load(path: str = LIB_PATH):
                                ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32), P]),
         "gwd_debug_export_weights": (I32, [P, I32, P, I64]),
         "gwd_debug_capture_backward": (I32, [P, I32, P, P, P, P, P, P, P, P]),
+        "gwd_debug_fused": (I32, [P, I32, I32, P, I32, I32, P, P, P, P, ctypes.POINTER(I32), P]),
+        "gwd_debug_mfma": (I32, [I32, P, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -253,6 +255,28 @@ class Model:
         check(lib.gwd_debug_export_weights(self.h, member, out.ctypes.data, self.export_params))
         return out
 
+    def fused_layers(self, layer: int, window: int) -> int:
+        """Layers of the fused launch that starts at `layer` for this window length (0 if none)."""
+        nl = ctypes.c_int32(0)
+        code = lib.gwd_debug_fused(self.h, 0, layer, None, 1, window, None, None, None, None, ctypes.byref(nl), None)
+        return int(nl.value) if code == OK else 0
+
+    def debug_fused(self, member: int, layer: int, x_in, n_windows: int, window: int, skip, stream=None):
+        """gwd_debug_fused: (pre [nl][rows][2C], x_out [nl][rows][C], skip_out [nl][rows][C]) fp32 device
+        tensors of the fused launch at `layer`; skip (fp32 [rows][C]) is updated in place."""
+        import torch
+        nl = self.fused_layers(layer, window)
+        if nl == 0:
+            raise GwdError(ERR_ARG, f"no fused launch starts at layer {layer}")
+        rows = n_windows * window
+        pre = torch.empty((nl, rows, 256), dtype=torch.float32, device="cuda")
+        xo = torch.zeros((nl, rows, 128), dtype=torch.float32, device="cuda")
+        so = torch.empty((nl, rows, 128), dtype=torch.float32, device="cuda")
+        n = ctypes.c_int32(0)
+        check(lib.gwd_debug_fused(self.h, member, layer, _ptr(x_in), n_windows, window, _ptr(skip), _ptr(pre),
+                                  _ptr(xo), _ptr(so), ctypes.byref(n), _stream_handle(stream)))
+        return pre, xo, so
+
     def capture_backward(self, layer: int, bufs=None):
         """gwd_debug_capture_backward: the next backward copies gated layer `layer`'s operands and
         results into bufs (dict of fp32 device tensors x_in, pre, dskip, dx_in, dg, g, dpre, dx_out);
@@ -265,6 +289,21 @@ class Model:
                     stream=None):
         check(lib.gwd_debug_layer(self.h, member, layer, _ptr(x_in), n_windows, window, _ptr(pre_out),
                                   _ptr(x_out), _ptr(skip), _stream_handle(stream)))
+
+
+def debug_mfma(kind: int, a, b, c, stream=None):
+    """gwd_debug_mfma: D = A B + C by one matrix-core instruction (kind 0: bf16 [32][16] x [16][32],
+    kind 1: E4M3 [32][64] x [64][32]); a and b are uint8/int16 device tensors of the operand bits,
+    c a [32][32] fp32 device tensor. Returns D."""
+    import torch
+    K = 16 if kind == 0 else 64
+    eb = 2 if kind == 0 else 1
+    assert a.is_contiguous() and a.numel() * a.element_size() == 32 * K * eb
+    assert b.is_contiguous() and b.numel() * b.element_size() == 32 * K * eb
+    assert c.dtype == torch.float32 and c.is_contiguous() and c.numel() == 1024
+    d = torch.empty((32, 32), dtype=torch.float32, device=c.device)
+    check(lib.gwd_debug_mfma(kind, _ptr(a), _ptr(b), _ptr(c), _ptr(d), _stream_handle(stream)))
+    return d
 
 
 def _member_function():

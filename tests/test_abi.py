@@ -90,10 +90,10 @@ def test_load_weights_argument_errors(g):
     unsup = g.full_arch()
     unsup.channels = 64
     assert load(g, unsup, np.zeros(g.num_params(unsup), np.float32), 1, g.num_params(unsup), g.FP32)[0] == g.ERR_UNSUPPORTED
-    t = g.tiny_arch()
-    assert load(g, t, np.zeros(1681, np.float32), 1, 1681, g.BF16)[0] == g.ERR_UNSUPPORTED
-    assert "only" in g.last_error()
     if not host_has_gpu():
+        # the plain member loads in every precision (its BF16/FP8 forms pass the argument checks)
+        for prec in (g.BF16, g.FP8_E4M3):
+            assert load(g, g.tiny_arch(), np.zeros(1681, np.float32), 1, 1681, prec)[0] == g.ERR_NO_DEVICE
         code, h = load(g, a, blob, 1, n, g.FP32)
         assert code == g.ERR_NO_DEVICE and not h.value      # valid arguments, but this host has no GPU
         assert g.last_error() != ""
@@ -271,3 +271,15 @@ def test_two_branch_counts_and_load_errors(g):
     assert g.lib.gwd_load_weights(ctypes.byref(wide), 1, wb.ctypes.data, wb.size, g.FP32, ctypes.byref(h)) == g.ERR_UNSUPPORTED
     if not host_has_gpu():
         assert g.lib.gwd_load_weights(ctypes.byref(a), 1, blob.ctypes.data, blob.size, g.BF16, ctypes.byref(h)) == g.ERR_NO_DEVICE
+
+
+def test_debug_entries_reject_bad_arguments(g):
+    """The test-support entries check their arguments on the host."""
+    assert g.lib.gwd_debug_capture_backward(None, 0, None, None, None, None, None, None, None, None) == g.ERR_ARG
+    nl = ctypes.c_int32(7)
+    assert g.lib.gwd_debug_fused(None, 0, 0, None, 1, 4096, None, None, None, None, ctypes.byref(nl), None) == g.ERR_ARG
+    buf = (ctypes.c_float * 1024)()
+    assert g.lib.gwd_debug_mfma(2, buf, buf, buf, buf, None) == g.ERR_ARG
+    assert g.lib.gwd_debug_mfma(0, None, buf, buf, buf, None) == g.ERR_ARG
+    if not host_has_gpu():
+        assert g.lib.gwd_debug_mfma(1, buf, buf, buf, buf, None) == g.ERR_NO_DEVICE

@@ -5,6 +5,10 @@ import pytest
 
 from tests.gpu_common import U32, sigmoid64, to_dev
 
+# unit roundoff of the fp32 accumulation inside each matrix-core instruction (see
+# test_gpu_mfma.py for the FP8 instruction's)
+U_ACC = {"bf16": U32, "fp8": 2 * U32}
+
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
@@ -63,21 +67,62 @@ def test_exported_operands_match_oracle_quantiser(g, model, blob):
     assert np.array_equal(pe["h1.W"], p["h1.W"]) and np.array_equal(pe["dil3.b"], p["dil3.b"])
 
 
-@pytest.mark.parametrize("layer", [0, 9, 18, 29])
-def test_layer_local_parity(g, model, blob, layer):
-    """GPU pre-activation vs the oracle applied to the same quantised operands: the only difference
-    allowed is fp32 accumulation of exact products (|d| <= K u |A||B| scale, Higham sec. 3.1), with
-    u = 2^-24 for the bf16 instruction and u = 2^-23 for the fp8 one (its internal additions are not
-    guaranteed to round to nearest; measured up to 1.42x the round-to-nearest bound). The gate output
-    is re-quantised before the second GEMM, where a rounding flip moves one operand by one unit in
-    the last place; the residual/skip bound allows for that."""
-    from oracle.arch import FULL, unpack
+def check_layer(prec, p, layer, xb, skip_in, pre_g, xo_g, sk_g, label):
+    """Layer-local parity of one gated layer: GPU pre-activation vs the oracle applied to the same
+    quantised operands (|d| <= K u |A||B| scale, Higham sec. 3.1; u per the instruction, see
+    U_ACC), then the residual and skip outputs from the GPU's own pre-activation, with the gate
+    re-quantised like the kernel does (a rounding flip moves one operand by one unit in the last
+    place; the bound allows for that). xb: the layer input as the kernel holds it (bf16 values,
+    [nw][T][C]); skip_in: the skip sum before the layer (None for layer 0)."""
     from oracle.forward import shift_right, sigmoid
     from oracle.quant import to_bf16, to_e4m3
+    C = 128
+    last = layer == 29
+    quant = to_bf16 if prec == "bf16" else to_e4m3
+    ulp_rel = 2.0 ** -7 if prec == "bf16" else 2.0 ** -3
+    Bc, sc, Brs, srs = quantised_layer_mats(prec, p, layer, last)
+    d = 2 ** (layer % 10)
+    Aq = np.concatenate([quant(shift_right(xb, d)), quant(xb)], axis=-1)        # operands as the kernel rounds them
+    acc = Aq @ Bc
+    pre = acc * sc + p[f"dil{layer}.b"]
+    u_acc = U_ACC[prec]
+    bound = (2 * C) * u_acc * (np.abs(Aq) @ np.abs(Bc)) * sc + 2 * U32 * np.abs(pre) + 1e-30
+    ratio = np.abs(pre_g - pre) / bound
+    print(f"{label}: max |d pre| / bound = {ratio.max():.3g}", flush=True)
+    assert np.all(ratio <= 1.0)
+    # second GEMM on the gate of the GPU's own pre-activation, re-quantised like the kernel does
+    gq = quant(np.tanh(pre_g[..., :C]) * sigmoid(pre_g[..., C:]))
+    out = (gq @ Brs) * srs
+    gabs = np.abs(gq)
+    flip = (gabs * ulp_rel + 1e-7) @ np.abs(Brs * srs)             # one-ulp operand flips + fp32 gate
+    acc_b = C * u_acc * (gabs @ np.abs(Brs)) * srs
+    base = np.zeros_like(pre_g[..., :C]) if skip_in is None else skip_in
+    if last:
+        sko = base + out + p[f"skip{layer}.b"]
+        assert np.all(np.abs(sk_g - sko) <= flip + acc_b + 4 * U32 * (np.abs(sko) + 1))
+        return
+    b_r, b_s = p[f"res{layer}.b"], p[f"skip{layer}.b"]
+    sko = base + out[..., C:] + b_s
+    xo = xb + out[..., :C] + b_r
+    tol_s = flip[..., C:] + acc_b[..., C:] + 4 * U32 * (np.abs(sko) + 1)
+    # plus the final rounding of the residual stream to bf16 (half a unit in the last place)
+    tol_x = flip[..., :C] + acc_b[..., :C] + 4 * U32 * (np.abs(xo) + 1) + 2.0 ** -8 * np.abs(xo)
+    assert np.all(np.abs(sk_g - sko) <= tol_s)
+    assert np.all(np.abs(xo_g - xo) <= tol_x)
+    # the residual stream is stored in bf16
+    assert np.array_equal(to_bf16(xo_g), xo_g)
+
+
+@pytest.mark.parametrize("layer", [0, 9, 18, 19, 29])
+def test_layer_local_parity(g, model, blob, layer):
+    """The single-layer kernel at T = 4096, so that the dilation-512 layers (9, 19, 29) read a
+    nonzero x[t - 512] on 3584 of 4096 rows."""
+    from oracle.arch import FULL, unpack
+    from oracle.quant import to_bf16
     prec, m = model
     print(f"case: {prec} layer {layer}", flush=True)
     p = unpack(FULL, blob.astype(np.float64))
-    T, nw, C = 512, 2, 128
+    T, nw, C = 4096, 2, 128
     rng = np.random.default_rng(100 + layer)
     x = (rng.standard_normal((nw, T, C)) * 3).astype(np.float32)
     sk = (rng.standard_normal((nw, T, C)) * 4).astype(np.float32)
@@ -86,42 +131,44 @@ def test_layer_local_parity(g, model, blob, layer):
     xo_d = torch.zeros((nw, T, C), dtype=torch.float32, device="cuda")
     m.debug_layer(0, layer, x_d, nw, T, pre_d, xo_d, sk_d)
     torch.cuda.synchronize()
-    last = layer == 29
-    quant = to_bf16 if prec == "bf16" else to_e4m3
-    ulp_rel = 2.0 ** -7 if prec == "bf16" else 2.0 ** -3
-    Bc, sc, Brs, srs = quantised_layer_mats(prec, p, layer, last)
-    d = 2 ** (layer % 10)
-    x64 = x.astype(np.float64)
-    # the kernel keeps the residual stream in bf16: its input is bf16(x); FP8 operands are e4m3 of that
-    xb = to_bf16(x64)
-    Aq = np.concatenate([quant(shift_right(xb, d)), quant(xb)], axis=-1)        # operands as the kernel rounds them
-    acc = Aq @ Bc
-    pre = acc * sc + p[f"dil{layer}.b"]
-    pre_g = pre_d.cpu().numpy().astype(np.float64)
-    u_acc = U32 if prec == "bf16" else 2 * U32
-    bound = (2 * C) * u_acc * (np.abs(Aq) @ np.abs(Bc)) * sc + 2 * U32 * np.abs(pre) + 1e-30
-    ratio = np.abs(pre_g - pre) / bound
-    print(f"{prec} layer {layer}: max |d pre| / bound = {ratio.max():.3g}", flush=True)
-    assert np.all(ratio <= 1.0)
-    # second GEMM on the gate of the GPU's own pre-activation, re-quantised like the kernel does
-    gq = quant(np.tanh(pre_g[..., :C]) * sigmoid(pre_g[..., C:]))
-    out = (gq @ Brs) * srs
-    gabs = np.abs(gq)
-    flip = (gabs * ulp_rel + 1e-7) @ np.abs(Brs * srs)             # one-ulp operand flips + fp32 gate
-    acc_b = C * u_acc * (gabs @ np.abs(Brs)) * srs
-    if last:
-        sko = sk.astype(np.float64) + out + p[f"skip{layer}.b"]
-        assert np.all(np.abs(sk_d.cpu().numpy() - sko) <= flip + acc_b + 4 * U32 * (np.abs(sko) + 1))
-    else:
-        b_r, b_s = p[f"res{layer}.b"], p[f"skip{layer}.b"]
-        base = np.zeros_like(sk, dtype=np.float64) if layer == 0 else sk.astype(np.float64)
-        sko = base + out[..., C:] + b_s
-        xo = xb + out[..., :C] + b_r
-        tol_s = flip[..., C:] + acc_b[..., C:] + 4 * U32 * (np.abs(sko) + 1)
-        # plus the final rounding of the residual stream to bf16 (half a unit in the last place)
-        tol_x = flip[..., :C] + acc_b[..., :C] + 4 * U32 * (np.abs(xo) + 1) + 2.0 ** -8 * np.abs(xo)
-        assert np.all(np.abs(sk_d.cpu().numpy() - sko) <= tol_s)
-        assert np.all(np.abs(xo_d.cpu().numpy() - xo) <= tol_x)
+    xb = to_bf16(x.astype(np.float64))     # the kernel keeps the residual stream in bf16
+    check_layer(prec, p, layer, xb, None if layer == 0 else sk.astype(np.float64),
+                pre_d.cpu().numpy().astype(np.float64), xo_d.cpu().numpy().astype(np.float64),
+                sk_d.cpu().numpy().astype(np.float64), f"{prec} layer {layer}")
+
+
+@pytest.mark.parametrize("first", [0, 3, 6, 26])
+def test_fused_launch_layer_local_parity(g, model, blob, first):
+    """Every layer of the fused launches the forward times (triples; BF16 quads at the end of each
+    stack, the last one being the network's last layer), checked layer by layer against the
+    oracle: each layer's input is the previous layer's output as the kernel stored it, at
+    T = 4096 so that every dilation, 512 included, reads history rows. Two windows: the
+    dilation-1 sub-sequences are split into segments that start with a warm-up chunk."""
+    from oracle.arch import FULL, unpack
+    from oracle.quant import to_bf16
+    prec, m = model
+    T, nw, C = 4096, 2, 128
+    nl = m.fused_layers(first, T)
+    print(f"case: {prec} fused launch at layer {first} ({nl} layers)", flush=True)
+    assert nl == (4 if prec == "bf16" and first % 10 == 6 else 3)
+    p = unpack(FULL, blob.astype(np.float64))
+    rng = np.random.default_rng(200 + first)
+    x = (rng.standard_normal((nw, T, C)) * 3).astype(np.float32)
+    sk = (rng.standard_normal((nw, T, C)) * 4).astype(np.float32)
+    sk_d = to_dev(sk.copy())
+    pre_d, xo_d, so_d = m.debug_fused(0, first, to_dev(x), nw, T, sk_d)
+    torch.cuda.synchronize()
+    pre_g = pre_d.cpu().numpy().astype(np.float64).reshape(nl, nw, T, 2 * C)
+    xo_g = xo_d.cpu().numpy().astype(np.float64).reshape(nl, nw, T, C)
+    so_g = so_d.cpu().numpy().astype(np.float64).reshape(nl, nw, T, C)
+    # the launch's own skip output is the last layer's running sum
+    assert np.array_equal(sk_d.cpu().numpy().astype(np.float64).reshape(nw, T, C), so_g[-1])
+    xb = to_bf16(x.astype(np.float64))
+    skip_in = None if first == 0 else sk.astype(np.float64)
+    for j in range(nl):
+        layer = first + j
+        check_layer(prec, p, layer, xb, skip_in, pre_g[j], xo_g[j], so_g[j], f"{prec} fused {first}: layer {layer}")
+        xb, skip_in = xo_g[j], so_g[j]
 
 
 def test_end_to_end_error_stated(g, model, blob):
@@ -181,3 +228,66 @@ def test_trigger_lists_stated(g, model):
     print(f"{prec} triggers vs FP64 oracle: oracle {len(ref_s)} {classify(ref_s, got_s)}, "
           f"gpu {len(got_s)} {classify(got_s, ref_s)}", flush=True)
     assert np.all(np.isfinite(e.cpu().numpy()))
+
+
+# ---------------------------------------------------------------- the small plain member in BF16 / FP8
+def test_tiny_member_reduced_precision(g, model):
+    """The 64 windows of the small member's workload (8 chirped) in BF16 and FP8: the exported
+    operands equal the oracle's quantisers bit for bit (BF16 round to nearest even; FP8 one scale per
+    output channel, computed in float32); the per-timestep probabilities are within 2e-2 of the FP64
+    oracle for BF16 on every window (the stated accuracy target is attainable on this member); the
+    FP8 error is stated. Each window is its own stream; the trigger lists are compared with the
+    oracle's, a decision being exempt when it is fragile at twice the measured logit error."""
+    from oracle.arch import TINY, unpack
+    from oracle.forward import forward_window
+    from oracle.quant import quantise_weight_e4m3_f32, to_bf16
+    from oracle.triggers import fragile_decisions, triggers as otrig
+    from paper_2201_11133_amd import synth
+    prec, _ = model
+    print(f"case: tiny member {prec}", flush=True)
+    blob = synth.tiny_weights(0)
+    m = g.Model(g.tiny_arch(), blob, prec)
+    p = unpack(TINY, blob.astype(np.float64))
+    pe = unpack(TINY, m.export_weights(0).astype(np.float64))
+    for name in ["conv0.W", "conv1.W", "conv2.W", "conv3.W", "out.W"]:
+        W = p[name]
+        if prec == "bf16":
+            ref = to_bf16(W)
+        else:
+            codes, s = quantise_weight_e4m3_f32(W)
+            ref = (codes * s.astype(np.float64).reshape((-1,) + (1,) * (W.ndim - 1))).astype(np.float32).astype(np.float64)
+        assert np.array_equal(pe[name], ref), name
+        assert np.array_equal(pe[name.replace(".W", ".b")], p[name.replace(".W", ".b")])
+    x, _ = synth.make_windows(100, 64, 8)
+    z64 = forward_window(TINY, p, x.astype(np.float64))
+    dev = [to_dev(x[i]) for i in range(64)]
+    z = m.forward(dev, 4096, 256, out_mode=0)
+    torch.cuda.synchronize()
+    zh = z.cpu().numpy().astype(np.float64)
+    dp = np.abs(sigmoid64(zh) - sigmoid64(z64.reshape(-1)))
+    dz = float(np.max(np.abs(zh - z64.reshape(-1))))
+    offs = np.arange(65) * 4096
+    got = {(s, a) for s, a, _, _ in g.triggers(z, offs, 0.9, 4096)}
+    ref_t = {(s, a) for s, a, _, _ in otrig(z64.reshape(-1), offs, 0.9, 4096)}
+    fragile = fragile_decisions(z64.reshape(-1), offs, 0.9, 4096, 2.0 * dz + 1e-12)
+    near = {(s, a) for s, a in got ^ ref_t if abs(sigmoid64(z64.reshape(-1)[offs[s] + a]) - 0.9) <= 0.02}
+    m.close()
+    print(f"tiny {prec}: max|dp| = {dp.max():.3g}, mean {dp.mean():.3g}, max|dz| = {dz:.3g}; triggers oracle "
+          f"{len(ref_t)}, gpu {len(got)}, differing {len(got ^ ref_t)} (within 0.02 of the threshold: {len(near)})",
+          flush=True)
+    assert np.all(np.isfinite(zh))
+    assert (got ^ ref_t) <= fragile
+    if prec == "bf16":
+        assert dp.max() <= 2e-2
+
+
+def test_tiny_member_trains_fp32_only(g, model):
+    from paper_2201_11133_amd import synth
+    prec, _ = model
+    m = g.Model(g.tiny_arch(), synth.tiny_weights(0), prec)
+    u = torch.zeros((1, 512, 2), dtype=torch.float32, device="cuda")
+    z = torch.empty((1, 512), dtype=torch.float32, device="cuda")
+    sv = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    code = g.lib.gwd_forward_train(m.h, 0, u.data_ptr(), 1, 512, z.data_ptr(), sv.data_ptr(), None)
+    m.close()
+    assert code == g.ERR_UNSUPPORTED
