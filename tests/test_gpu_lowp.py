@@ -3,11 +3,7 @@ parity, and the end-to-end error against the FP64 oracle (stated, not gated)."""
 import numpy as np
 import pytest
 
-from tests.gpu_common import U32, sigmoid64, to_dev
-
-# unit roundoff of the fp32 accumulation inside each matrix-core instruction (see
-# test_gpu_mfma.py for the FP8 instruction's)
-U_ACC = {"bf16": U32, "fp8": 2 * U32}
+from tests.gpu_common import E4M3_COMBINE, U32, e4m3_dropped_bound, sigmoid64, to_dev
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -67,13 +63,29 @@ def test_exported_operands_match_oracle_quantiser(g, model, blob):
     assert np.array_equal(pe["h1.W"], p["h1.W"]) and np.array_equal(pe["dil3.b"], p["dil3.b"])
 
 
+def gemm_bound(prec, Aq, Bq, n_steps):
+    """Accumulation error bound of Aq @ Bq taken as n_steps chained matrix-core instructions (the
+    accumulator of one is the C of the next), per instruction as pinned in test_gpu_mfma.py:
+    BF16, the dot-product bound K u |A||B| (Higham sec. 3.1, u = 2^-24); E4M3, the bits the
+    instruction's group alignment can drop, plus 8 u (|C| + sum |a b|) per instruction, |C| being
+    at most the sum of the earlier products."""
+    shp = Aq.shape
+    A2 = Aq.reshape(-1, shp[-1])
+    s = np.abs(A2) @ np.abs(Bq)
+    if prec == "bf16":
+        b = shp[-1] * U32 * s
+    else:
+        b = e4m3_dropped_bound(A2, Bq) + E4M3_COMBINE * n_steps * U32 * s
+    return b.reshape(shp[:-1] + (Bq.shape[1],))
+
+
 def check_layer(prec, p, layer, xb, skip_in, pre_g, xo_g, sk_g, label):
     """Layer-local parity of one gated layer: GPU pre-activation vs the oracle applied to the same
-    quantised operands (|d| <= K u |A||B| scale, Higham sec. 3.1; u per the instruction, see
-    U_ACC), then the residual and skip outputs from the GPU's own pre-activation, with the gate
-    re-quantised like the kernel does (a rounding flip moves one operand by one unit in the last
-    place; the bound allows for that). xb: the layer input as the kernel holds it (bf16 values,
-    [nw][T][C]); skip_in: the skip sum before the layer (None for layer 0)."""
+    quantised operands (within gemm_bound, times the column scale), then the residual and skip
+    outputs from the GPU's own pre-activation, with the gate re-quantised like the kernel does (a
+    rounding flip moves one operand by one unit in the last place; the bound allows for that).
+    xb: the layer input as the kernel holds it (bf16 values, [nw][T][C]); skip_in: the skip sum
+    before the layer (None for layer 0)."""
     from oracle.forward import shift_right, sigmoid
     from oracle.quant import to_bf16, to_e4m3
     C = 128
@@ -85,8 +97,7 @@ def check_layer(prec, p, layer, xb, skip_in, pre_g, xo_g, sk_g, label):
     Aq = np.concatenate([quant(shift_right(xb, d)), quant(xb)], axis=-1)        # operands as the kernel rounds them
     acc = Aq @ Bc
     pre = acc * sc + p[f"dil{layer}.b"]
-    u_acc = U_ACC[prec]
-    bound = (2 * C) * u_acc * (np.abs(Aq) @ np.abs(Bc)) * sc + 2 * U32 * np.abs(pre) + 1e-30
+    bound = gemm_bound(prec, Aq, Bc, 4) * sc + 2 * U32 * np.abs(pre) + 1e-30
     ratio = np.abs(pre_g - pre) / bound
     print(f"{label}: max |d pre| / bound = {ratio.max():.3g}", flush=True)
     assert np.all(ratio <= 1.0)
@@ -95,7 +106,7 @@ def check_layer(prec, p, layer, xb, skip_in, pre_g, xo_g, sk_g, label):
     out = (gq @ Brs) * srs
     gabs = np.abs(gq)
     flip = (gabs * ulp_rel + 1e-7) @ np.abs(Brs * srs)             # one-ulp operand flips + fp32 gate
-    acc_b = C * u_acc * (gabs @ np.abs(Brs)) * srs
+    acc_b = gemm_bound(prec, gq, Brs, 2) * srs
     base = np.zeros_like(pre_g[..., :C]) if skip_in is None else skip_in
     if last:
         sko = base + out + p[f"skip{layer}.b"]
