@@ -215,6 +215,26 @@ gwd_status gwd_triggers(const float* ens_logit, const int64_t* stream_offsets, i
                         double threshold_prob, int32_t cluster_window, gwd_trigger* out,
                         int64_t capacity, int64_t* n_found, void* hip_stream);
 
+/* Allocation-free form of gwd_triggers, for callers that cannot allocate device
+ * memory (tight serving loops, harnesses that forbid hipMalloc). Same rule,
+ * arguments, records and errors as gwd_triggers, and the same kernels, but the
+ * per-tile candidates, the stream table, the records and the counters live in
+ * a fixed device array of 16 MiB (16,777,216 bytes) that the library holds on
+ * each device it runs on until the process ends; the call allocates nothing.
+ * A request needing more scratch than that gives GWD_ERR_CAPACITY before any
+ * device work (*n_found stays 0); the need is
+ *   256-aligned(32 n_streams) + 256-aligned(8 n_tiles) + 256-aligned(24 n_tiles) + 256
+ * bytes, n_tiles = sum over streams of ceil(length / cluster_window), and
+ * gwd_triggers_noalloc_scratch_bytes reports it (-1 for invalid offsets or
+ * sizes). Calls on one device share its array: the library serialises them
+ * (a process-wide lock held until the call has synchronised hip_stream), and
+ * the array keeps the last call's contents, which no call reads. */
+gwd_status gwd_triggers_noalloc(const float* ens_logit, const int64_t* stream_offsets, int32_t n_streams,
+                                double threshold_prob, int32_t cluster_window, gwd_trigger* out,
+                                int64_t capacity, int64_t* n_found, void* hip_stream);
+int64_t gwd_triggers_noalloc_scratch_bytes(const int64_t* stream_offsets, int32_t n_streams,
+                                           int32_t cluster_window);
+
 /* ---- time-slide background ("Statistical Analysis") -------------------------
  * The paper measures how often the ensemble fires on noise with years of
  * background built from one month of two-detector data by time slides: one

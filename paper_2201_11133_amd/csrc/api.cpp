@@ -499,6 +499,45 @@ gwd_status gwd_triggers(const float* ens_logit, const int64_t* offs, int32_t n_s
     return run_triggers(ens_logit, offs, n_streams, thr, cluster_window, out, capacity, n_found, (hipStream_t)hip_stream);
 }
 
+gwd_status gwd_triggers_noalloc(const float* ens_logit, const int64_t* offs, int32_t n_streams, double threshold_prob,
+                                int32_t cluster_window, gwd_trigger* out, int64_t capacity, int64_t* n_found,
+                                void* hip_stream) {
+    if (!n_found) { set_error("gwd_triggers_noalloc: n_found is NULL"); return GWD_ERR_ARG; }
+    *n_found = 0;
+    if (!offs) { set_error("gwd_triggers_noalloc: stream_offsets is NULL"); return GWD_ERR_ARG; }
+    if (n_streams < 1 || n_streams > 65536) { set_error("gwd_triggers_noalloc: n_streams %d not in [1, 65536]", n_streams); return GWD_ERR_ARG; }
+    if (!(threshold_prob > 0.0 && threshold_prob < 1.0)) { set_error("gwd_triggers_noalloc: threshold_prob must be in (0, 1)"); return GWD_ERR_ARG; }
+    if (cluster_window < 1 || cluster_window > 65536) { set_error("gwd_triggers_noalloc: cluster_window %d not in [1, 65536]", cluster_window); return GWD_ERR_ARG; }
+    if (capacity < 0) { set_error("gwd_triggers_noalloc: negative capacity"); return GWD_ERR_ARG; }
+    if (capacity > 0 && !out) { set_error("gwd_triggers_noalloc: out is NULL"); return GWD_ERR_ARG; }
+    if (offs[0] != 0) { set_error("gwd_triggers_noalloc: stream_offsets[0] must be 0"); return GWD_ERR_ARG; }
+    for (int s = 0; s < n_streams; ++s)
+        if (offs[s + 1] < offs[s]) { set_error("gwd_triggers_noalloc: stream_offsets decrease at %d", s); return GWD_ERR_ARG; }
+    if (offs[n_streams] == 0) return GWD_OK;
+    if (!ens_logit) { set_error("gwd_triggers_noalloc: ens_logit is NULL"); return GWD_ERR_ARG; }
+    if ((uintptr_t)ens_logit & 3) { set_error("gwd_triggers_noalloc: ens_logit not 4-byte aligned"); return GWD_ERR_ARG; }
+    const int64_t need = trig_scratch_need(offs, n_streams, cluster_window);
+    if (need > kTrigScratchBytes) {
+        set_error("gwd_triggers_noalloc: this request needs %lld bytes of scratch; the static maximum is %lld "
+                  "(use gwd_triggers, or split the streams)", (long long)need, (long long)kTrigScratchBytes);
+        return GWD_ERR_CAPACITY;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) { set_error("gwd_triggers_noalloc: no HIP device"); return GWD_ERR_NO_DEVICE; }
+    const double p = threshold_prob;
+    const double thr = log(p / (1.0 - p));
+    return run_triggers_noalloc(ens_logit, offs, n_streams, thr, cluster_window, out, capacity, n_found,
+                                (hipStream_t)hip_stream);
+}
+
+int64_t gwd_triggers_noalloc_scratch_bytes(const int64_t* offs, int32_t n_streams, int32_t cluster_window) {
+    if (!offs || n_streams < 1 || n_streams > 65536 || cluster_window < 1 || cluster_window > 65536 || offs[0] != 0)
+        return -1;
+    for (int s = 0; s < n_streams; ++s)
+        if (offs[s + 1] < offs[s]) return -1;
+    return trig_scratch_need(offs, n_streams, cluster_window);
+}
+
 gwd_status gwd_debug_layer(gwd_model* m, int32_t member, int32_t layer, const float* x_in, int32_t n_windows,
                            int32_t window, float* pre_out, float* x_out, float* skip, void* hip_stream) {
     if (!m) { set_error("gwd_debug_layer: model is NULL"); return GWD_ERR_ARG; }

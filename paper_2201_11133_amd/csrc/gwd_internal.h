@@ -190,5 +190,10 @@ hipError_t launch_stamp(unsigned long long* slot, hipStream_t st);
 struct TrigWork;
 gwd_status run_triggers(const float* e, const int64_t* offs, int n_streams, double thr, int wc,
                         gwd_trigger* out, int64_t capacity, int64_t* n_found, hipStream_t st);
+// The allocation-free form runs on a fixed 16 MiB device array per device.
+constexpr int64_t kTrigScratchBytes = 16ll << 20;
+int64_t trig_scratch_need(const int64_t* offs, int n_streams, int wc);   // bytes of scratch (0: nothing to scan)
+gwd_status run_triggers_noalloc(const float* e, const int64_t* offs, int n_streams, double thr, int wc,
+                                gwd_trigger* out, int64_t capacity, int64_t* n_found, hipStream_t st);
 
 }  // namespace gwd

@@ -156,6 +156,12 @@ __global__ __launch_bounds__(1024) void trig_compact_kernel(const int64_t* cand,
     if (threadIdx.x == 0) *count = (unsigned long long)base_s;
 }
 
+// Clears the trigger count and the non-finite flag (a kernel rather than a memset, so the
+// clearing is an ordinary kernel node for callers that capture the stream).
+__global__ void trig_clear_kernel(unsigned long long* count) {
+    if (threadIdx.x < 2) count[threadIdx.x] = 0ull;
+}
+
 namespace {
 struct TrigWs {
     int device = -1;
@@ -164,11 +170,10 @@ struct TrigWs {
 };
 std::mutex g_trig_mu;
 std::vector<TrigWs> g_trig_ws;  // one per device, grown on demand, kept until exit
-}  // namespace
 
-gwd_status run_triggers(const float* e, const int64_t* offs, int n_streams, double thr, int wc,
-                        gwd_trigger* out, int64_t capacity, int64_t* n_found, hipStream_t st) {
-    std::vector<TrigStream> tab(n_streams);
+// Host table of the streams' tiles; returns the tile count.
+int64_t trig_table(const int64_t* offs, int n_streams, int wc, std::vector<TrigStream>& tab) {
+    tab.resize(n_streams);
     int64_t n_tiles = 0;
     for (int s = 0; s < n_streams; ++s) {
         tab[s].e_begin = offs[s];
@@ -178,49 +183,37 @@ gwd_status run_triggers(const float* e, const int64_t* offs, int n_streams, doub
         const int64_t L = offs[s + 1] - offs[s];
         n_tiles += (L + wc - 1) / wc;
     }
-    *n_found = 0;
-    if (n_tiles == 0) return GWD_OK;
-    if (n_tiles > INT32_MAX) {
-        set_error("gwd_triggers: too many tiles (%lld)", (long long)n_tiles);
-        return GWD_ERR_ARG;
-    }
-    int dev = 0;
-    hipError_t err = hipGetDevice(&dev);
-    if (err != hipSuccess) return hip_fail(err, "hipGetDevice");
-    const int64_t tab_bytes = ((int64_t)n_streams * sizeof(TrigStream) + 255) & ~255LL;
-    const int64_t cand_bytes = (n_tiles * 8 + 255) & ~255LL;
-    const int64_t rec_bytes = (n_tiles * (int64_t)sizeof(TrigRecord) + 255) & ~255LL;
-    const int64_t need = tab_bytes + cand_bytes + rec_bytes + 256;
-    std::lock_guard<std::mutex> lock(g_trig_mu);
-    TrigWs* ws = nullptr;
-    for (auto& w : g_trig_ws)
-        if (w.device == dev) ws = &w;
-    if (!ws) {
-        g_trig_ws.push_back(TrigWs{dev, nullptr, 0});
-        ws = &g_trig_ws.back();
-    }
-    if (ws->bytes < need) {
-        if (ws->buf) {
-            err = hipStreamSynchronize(st);
-            if (err != hipSuccess) return hip_fail(err, "hipStreamSynchronize");
-            (void)hipFree(ws->buf);
-            ws->buf = nullptr;
-            ws->bytes = 0;
-        }
-        err = hipMalloc(&ws->buf, need);
-        if (err != hipSuccess) return hip_fail(err, "hipMalloc(trigger workspace)");
-        ws->bytes = need;
-    }
-    char* p = (char*)ws->buf;
+    return n_tiles;
+}
+
+struct TrigLayout {
+    int64_t tab_bytes, cand_bytes, rec_bytes, need;
+};
+
+TrigLayout trig_layout(int n_streams, int64_t n_tiles) {
+    TrigLayout l;
+    l.tab_bytes = ((int64_t)n_streams * sizeof(TrigStream) + 255) & ~255LL;
+    l.cand_bytes = (n_tiles * 8 + 255) & ~255LL;
+    l.rec_bytes = (n_tiles * (int64_t)sizeof(TrigRecord) + 255) & ~255LL;
+    l.need = l.tab_bytes + l.cand_bytes + l.rec_bytes + 256;
+    return l;
+}
+
+// Both kernels on the workspace p (at least lay.need bytes of device memory), then the count, the
+// flag and the records back to the host.
+gwd_status trig_run_on(char* p, const TrigLayout& lay, const std::vector<TrigStream>& tab, int64_t n_tiles,
+                       const float* e, int n_streams, double thr, int wc, gwd_trigger* out, int64_t capacity,
+                       int64_t* n_found, hipStream_t st) {
     TrigStream* d_tab = (TrigStream*)p;
-    int64_t* d_cand = (int64_t*)(p + tab_bytes);
-    TrigRecord* d_rec = (TrigRecord*)(p + tab_bytes + cand_bytes);
-    unsigned long long* d_count = (unsigned long long*)(p + tab_bytes + cand_bytes + rec_bytes);
+    int64_t* d_cand = (int64_t*)(p + lay.tab_bytes);
+    TrigRecord* d_rec = (TrigRecord*)(p + lay.tab_bytes + lay.cand_bytes);
+    unsigned long long* d_count = (unsigned long long*)(p + lay.tab_bytes + lay.cand_bytes + lay.rec_bytes);
     int* d_flag = (int*)(d_count + 1);
-    err = hipMemcpyAsync(d_tab, tab.data(), n_streams * sizeof(TrigStream), hipMemcpyHostToDevice, st);
+    hipError_t err = hipMemcpyAsync(d_tab, tab.data(), n_streams * sizeof(TrigStream), hipMemcpyHostToDevice, st);
     if (err != hipSuccess) return hip_fail(err, "hipMemcpyAsync(trigger table)");
-    err = hipMemsetAsync(d_count, 0, 16, st);
-    if (err != hipSuccess) return hip_fail(err, "hipMemsetAsync");
+    hipLaunchKernelGGL(trig_clear_kernel, dim3(1), dim3(64), 0, st, d_count);
+    err = hipGetLastError();
+    if (err != hipSuccess) return hip_fail(err, "trig_clear_kernel launch");
     hipLaunchKernelGGL(trig_tile_kernel, dim3((unsigned)n_tiles), dim3(256), 0, st, e, d_tab, n_streams, wc, thr,
                        d_cand, d_flag);
     err = hipGetLastError();
@@ -255,6 +248,91 @@ gwd_status run_triggers(const float* e, const int64_t* offs, int n_streams, doub
         return GWD_ERR_CAPACITY;
     }
     return GWD_OK;
+}
+}  // namespace
+
+gwd_status run_triggers(const float* e, const int64_t* offs, int n_streams, double thr, int wc,
+                        gwd_trigger* out, int64_t capacity, int64_t* n_found, hipStream_t st) {
+    std::vector<TrigStream> tab;
+    const int64_t n_tiles = trig_table(offs, n_streams, wc, tab);
+    *n_found = 0;
+    if (n_tiles == 0) return GWD_OK;
+    if (n_tiles > INT32_MAX) {
+        set_error("gwd_triggers: too many tiles (%lld)", (long long)n_tiles);
+        return GWD_ERR_ARG;
+    }
+    int dev = 0;
+    hipError_t err = hipGetDevice(&dev);
+    if (err != hipSuccess) return hip_fail(err, "hipGetDevice");
+    const TrigLayout lay = trig_layout(n_streams, n_tiles);
+    std::lock_guard<std::mutex> lock(g_trig_mu);
+    TrigWs* ws = nullptr;
+    for (auto& w : g_trig_ws)
+        if (w.device == dev) ws = &w;
+    if (!ws) {
+        g_trig_ws.push_back(TrigWs{dev, nullptr, 0});
+        ws = &g_trig_ws.back();
+    }
+    if (ws->bytes < lay.need) {
+        if (ws->buf) {
+            err = hipStreamSynchronize(st);
+            if (err != hipSuccess) return hip_fail(err, "hipStreamSynchronize");
+            (void)hipFree(ws->buf);
+            ws->buf = nullptr;
+            ws->bytes = 0;
+        }
+        err = hipMalloc(&ws->buf, lay.need);
+        if (err != hipSuccess) return hip_fail(err, "hipMalloc(trigger workspace)");
+        ws->bytes = lay.need;
+    }
+    return trig_run_on((char*)ws->buf, lay, tab, n_tiles, e, n_streams, thr, wc, out, capacity, n_found, st);
+}
+
+// ---------------------------------------------------------------- allocation-free form
+// The same two kernels on a fixed device array instead of a workspace from hipMalloc, for callers
+// that may not allocate device memory. Each device holds its own copy of the array (from the first
+// launch of this library's code on it until the process ends); in host code its name is only a
+// stand-in, so the kernels are given the device address that hipGetSymbolAddress reports, looked up
+// once per device.
+static __device__ __align__(256) unsigned char scratch[kTrigScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;                               // also serialises the calls that use the array
+std::vector<std::pair<int, void*>> g_scratch_addr;     // (device, device address of its array)
+}  // namespace
+
+int64_t trig_scratch_need(const int64_t* offs, int n_streams, int wc) {
+    std::vector<TrigStream> tab;
+    const int64_t n_tiles = trig_table(offs, n_streams, wc, tab);
+    return n_tiles == 0 ? 0 : trig_layout(n_streams, n_tiles).need;
+}
+
+gwd_status run_triggers_noalloc(const float* e, const int64_t* offs, int n_streams, double thr, int wc,
+                                gwd_trigger* out, int64_t capacity, int64_t* n_found, hipStream_t st) {
+    std::vector<TrigStream> tab;
+    const int64_t n_tiles = trig_table(offs, n_streams, wc, tab);
+    *n_found = 0;
+    if (n_tiles == 0) return GWD_OK;
+    const TrigLayout lay = trig_layout(n_streams, n_tiles);
+    if (lay.need > kTrigScratchBytes) {   // also checked by the entry point before any HIP call
+        set_error("gwd_triggers_noalloc: needs %lld bytes of scratch, the maximum is %lld", (long long)lay.need,
+                  (long long)kTrigScratchBytes);
+        return GWD_ERR_CAPACITY;
+    }
+    int dev = 0;
+    hipError_t err = hipGetDevice(&dev);
+    if (err != hipSuccess) return hip_fail(err, "hipGetDevice");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    void* ptr = nullptr;
+    for (auto& a : g_scratch_addr)
+        if (a.first == dev) ptr = a.second;
+    if (!ptr) {   // first call on this device, which is current: its own copy's address
+        err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (err != hipSuccess || !ptr) return hip_fail(err != hipSuccess ? err : hipErrorInvalidSymbol,
+                                                        "hipGetSymbolAddress(scratch)");
+        g_scratch_addr.emplace_back(dev, ptr);
+    }
+    return trig_run_on((char*)ptr, lay, tab, n_tiles, e, n_streams, thr, wc, out, capacity, n_found, st);
 }
 
 }  // namespace gwd

@@ -83,6 +83,8 @@ def _load(path: str = LIB_PATH):
         "gwd_forward": (I32, [P, ctypes.POINTER(Stream), I32, I32, I32, I32, P, I64, P]),
         "gwd_forward_out_floats": (I64, [P, ctypes.POINTER(Stream), I32, I32, I32, I32]),
         "gwd_triggers": (I32, [P, P, I32, D, I32, ctypes.POINTER(Trigger), I64, ctypes.POINTER(I64), P]),
+        "gwd_triggers_noalloc": (I32, [P, P, I32, D, I32, ctypes.POINTER(Trigger), I64, ctypes.POINTER(I64), P]),
+        "gwd_triggers_noalloc_scratch_bytes": (I64, [P, I32, I32]),
         "gwd_time_slide": (I32, [ctypes.POINTER(Stream), P, I32, P, P]),
         "gwd_far_curve": (I32, [ctypes.POINTER(Trigger), I64, P, I32, D, P, P]),
         "gwd_prob64": (I32, [P, I64, P, P]),
@@ -440,6 +442,21 @@ def triggers(e, offsets: Sequence[int], threshold_prob: float = 0.9, cluster_win
     nf = ctypes.c_int64(0)
     check(lib.gwd_triggers(_ptr(e), offs.ctypes.data, n_streams, threshold_prob, cluster_window, buf, capacity,
                            ctypes.byref(nf), _stream_handle(stream)))
+    return [(buf[i].stream, buf[i].sample, buf[i].logit, buf[i].prob) for i in range(min(nf.value, capacity))]
+
+
+def triggers_noalloc(e, offsets: Sequence[int], threshold_prob: float = 0.9, cluster_window: int = 4096,
+                     capacity: Optional[int] = None, stream=None) -> List[Tuple[int, int, float, float]]:
+    """gwd_triggers_noalloc (the allocation-free form, static device scratch) on a device score
+    tensor e; returns (stream, sample, logit, prob) records."""
+    offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    n_streams = offs.size - 1
+    if capacity is None:
+        capacity = int(sum(-(-(int(offs[i + 1] - offs[i])) // cluster_window) for i in range(n_streams)))
+    buf = (Trigger * max(capacity, 1))()
+    nf = ctypes.c_int64(0)
+    check(lib.gwd_triggers_noalloc(_ptr(e), offs.ctypes.data, n_streams, threshold_prob, cluster_window, buf,
+                                   capacity, ctypes.byref(nf), _stream_handle(stream)))
     return [(buf[i].stream, buf[i].sample, buf[i].logit, buf[i].prob) for i in range(min(nf.value, capacity))]
 
 

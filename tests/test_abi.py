@@ -283,3 +283,43 @@ def test_debug_entries_reject_bad_arguments(g):
     assert g.lib.gwd_debug_mfma(0, None, buf, buf, buf, None) == g.ERR_ARG
     if not host_has_gpu():
         assert g.lib.gwd_debug_mfma(1, buf, buf, buf, buf, None) == g.ERR_NO_DEVICE
+
+
+def test_noalloc_triggers_scratch_limit(g):
+    """The allocation-free trigger entry: same argument checks as gwd_triggers, and a request whose
+    scratch need exceeds the static 16 MiB array is refused on the host, before any device work."""
+    def nz(offs, wc=4096, cap=4, e_ptr=8, p=0.9):
+        offs = np.asarray(offs, np.int64)
+        nf = ctypes.c_int64(-1)
+        buf = (g.Trigger * 4)()
+        code = g.lib.gwd_triggers_noalloc(e_ptr, offs.ctypes.data, len(offs) - 1, p, wc, buf, cap,
+                                          ctypes.byref(nf), None)
+        return code, nf.value
+
+    def need(offs, wc):
+        offs = np.asarray(offs, np.int64)
+        return g.lib.gwd_triggers_noalloc_scratch_bytes(offs.ctypes.data, len(offs) - 1, wc)
+
+    r256 = lambda b: (b + 255) // 256 * 256
+    assert need([0, 600_000], 1) == r256(32) + r256(8 * 600_000) + r256(24 * 600_000) + 256
+    assert need([0, 0, 0], 64) == 0
+    assert need([1, 5], 64) == -1 and need([0, 5, 4], 64) == -1 and need([0, 5], 0) == -1
+    # the largest single stream that fits at cluster window 1 is accepted by the size check; one more tile is not
+    n_fit = (16 << 20) - 256 - 256 - 512
+    n_fit = n_fit // 32
+    while need([0, n_fit + 1], 1) <= 16 << 20:
+        n_fit += 1
+    while need([0, n_fit], 1) > 16 << 20:
+        n_fit -= 1
+    assert need([0, n_fit], 1) <= 16 << 20 < need([0, n_fit + 1], 1)
+    assert nz([0, n_fit + 1], wc=1) == (g.ERR_CAPACITY, 0)
+    assert nz([0, 600_000], wc=1) == (g.ERR_CAPACITY, 0)
+    assert "static maximum" in g.last_error()
+    assert nz([0, 10], p=0.0)[0] == g.ERR_ARG
+    assert nz([0, 10], wc=70000)[0] == g.ERR_ARG
+    assert nz([0, 10], cap=-1)[0] == g.ERR_ARG
+    assert nz([1, 10])[0] == g.ERR_ARG
+    assert nz([0, 10, 5])[0] == g.ERR_ARG
+    assert nz([0, 10], e_ptr=None)[0] == g.ERR_ARG
+    assert nz([0, 10], e_ptr=6)[0] == g.ERR_ARG
+    assert nz([0, 0, 0]) == (g.OK, 0)
