@@ -120,11 +120,7 @@ __device__ inline Frag<FP8> load_frag(const uint8_t* p) {
 template <bool FP8>
 __device__ inline floatx16 mma(const Frag<FP8>& a, const Frag<FP8>& b, floatx16 c) {
     if constexpr (FP8) {
-        intx8 av, bv;
-        av[0] = a.v[0].x; av[1] = a.v[0].y; av[2] = a.v[0].z; av[3] = a.v[0].w;
-        av[4] = a.v[1].x; av[5] = a.v[1].y; av[6] = a.v[1].z; av[7] = a.v[1].w;
-        bv[0] = b.v[0].x; bv[1] = b.v[0].y; bv[2] = b.v[0].z; bv[3] = b.v[0].w;
-        bv[4] = b.v[1].x; bv[5] = b.v[1].y; bv[6] = b.v[1].z; bv[7] = b.v[1].w;
+        const intx8 av = __builtin_bit_cast(intx8, a), bv = __builtin_bit_cast(intx8, b);
         // formats 0/0 = E4M3 for A and B; scale exponents 127 = 2^0
         return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, c, 0, 0, 0, 127, 0, 127);
     } else {
@@ -674,6 +670,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
             // ---- phase 1: pre = [x[s - dil] | x[s]] Bc, K = 256 (k-steps 0-7: tap s - dil, 8-15: tap s);
             // weight fragments from the register ring, operand fragments one step ahead
             floatx16 af[2], ag[2];
+            // the matrix-core phases run at a raised wave priority, so the SIMD's other wave (in its
+            // gate or epilogue) fills the issue slots around them rather than delaying them
+            __builtin_amdgcn_s_setprio(2);
             {
                 const uint8_t* A0 = Xin + r * FU_XROW + 16 * h;
                 const uint8_t* Bf = p.wc[j] + ((size_t)(q * T::NK1) * 64 + lane) * T::FRAG;
@@ -716,6 +715,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                     for (int i = 0; i < 2; ++i) acur[i] = anxt[i];
                 }
             }
+            __builtin_amdgcn_s_setprio(0);
             if constexpr (DBG) {  // pre-activations (the accumulators started at the biases)
 #pragma unroll
                 for (int rb = 0; rb < 2; ++rb) {
@@ -753,12 +753,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                     if (!SKIP_INIT && store && sr < n_sub) sk[rb] = load_col16(p.skip + (wrow0 + cls + (int64_t)p.d0 * sr) * kC + cb);
                 }
             }
-            __syncthreads();  // every wave is done with this layer's input rows
-            // this input's last dil rows become the history of the next chunk
-            if (c + 1 < c1 && tid < 16 * dil) {
-                const int rr = tid >> 4, cc = tid & 15;
-                *(uint4*)(Xin + (rr - dil) * FU_XROW + 16 * cc) = *(const uint4*)(Xin + (FU_ROWS - dil + rr) * FU_XROW + 16 * cc);
-            }
             // ---- gate -> G: per row block, four 8-byte writes of four channels
 #pragma unroll
             for (int rb = 0; rb < 2; ++rb) {
@@ -791,6 +785,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                 Ng += wsh;
             }
             floatx16 ar[2], as[2];
+            __builtin_amdgcn_s_setprio(2);
             {
                 Frag<false> acur[2], anxt[2];
 #pragma unroll
@@ -823,6 +818,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                     for (int i = 0; i < 2; ++i) acur[i] = anxt[i];
                 }
             }
+            __builtin_amdgcn_s_setprio(0);
             // x_next = x + (g Brs_res + b_res), rounded to bf16; skip += g Brs_skip + b_skip
 #pragma unroll
             for (int rb = 0; rb < 2 && resid; ++rb) {
@@ -838,6 +834,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
 #pragma unroll
                 for (int i = 0; i < 16; ++i) sk[rb][i] = (SKIP_INIT && j == 0) ? as[rb][i] : sk[rb][i] + as[rb][i];
             __syncthreads();  // the next layer's input (or the chunk's output) is complete
+            // this input's last dil rows become the history of the next chunk: every wave has read
+            // them by now, and the buffer is next written two layers on (or by the next chunk)
+            if (c + 1 < c1 && tid < 16 * dil) {
+                const int rr = tid >> 4, cc = tid & 15;
+                *(uint4*)(Xin + (rr - dil) * FU_XROW + 16 * cc) = *(const uint4*)(Xin + (FU_ROWS - dil + rr) * FU_XROW + 16 * cc);
+            }
             if constexpr (DBG) {  // this layer's residual output rows and running skip sums
                 if (store) {
 #pragma unroll
@@ -903,40 +905,50 @@ static LayerArgsLP lp_args(gwd_model* m, int member, int l) {
     return a;
 }
 
-// FP8 form of the fused triple: the MFMA operands are E4M3, so each layer input is kept twice, as
-// E4M3 operand rows with their history (128 B + pad) and, for the rows of the chunk, as the bf16
-// residual base; the gate output is E4M3. Arithmetic as in the single-layer FP8 kernel: column
-// scale then bias on the accumulators, the residual added to the bf16 x, and the next layer's
-// operand converted from the bf16-rounded x. One 32-row block per wave (32-row chunks): E4M3
-// weights are half the bytes of bf16 ones, so the weight traffic per row matches the BF16 triple.
-constexpr int FE_RB = 1;                                         // row blocks per wave
-constexpr int FE_ROWS = 32 * FE_RB;                              // sub-rows per chunk
-constexpr int FE_ROW = kC + 16;                                  // E4M3 row + pad
-constexpr int FE_XBUF = (FE_ROWS + FU_HIST) * FE_ROW;            // one operand buffer with its history
-constexpr int FE_BBUF = FE_ROWS * FU_XROW;                       // one bf16 residual buffer
-constexpr int FE_LDS = 3 * FE_XBUF + 2 * FE_BBUF + FE_ROWS * FE_ROW;
+// FP8 form of the fused launches: the same space-to-batch walk, 64-row chunks, transposed products,
+// register rings and load order as the BF16 kernel, with E4M3 operands on
+// v_mfma_scale_f32_32x32x64_f8f6f4 (K = 64 per instruction: 4 steps in the first phase, 2 in the
+// second). Arithmetic as in the single-layer FP8 kernel: accumulators start at zero, then column
+// scale and bias; the residual stream stays bf16 and each layer's operand is the E4M3 conversion of
+// the bf16-rounded x.
+// The lane that computes output channels c of rows r in one layer computes the same channels of the
+// same rows in the next, so the residual stream of the chunk stays in registers (four bf16 channels
+// per 8-byte word); the LDS holds only the E4M3 operand buffers (with their history rows), the E4M3
+// gate output, a bf16 staging buffer for the chunk's input and output rows, and the biases and
+// scales of the launch's layers.
+constexpr int FX_EROW = kC + 16;                                   // E4M3 row + 16-byte pad
+constexpr int FX_E0 = 8 * FX_EROW;                                 // history rows as in the BF16 kernel: 8, 2, 4
+constexpr int FX_E1 = FX_E0 + (FU_ROWS + 2) * FX_EROW;
+constexpr int FX_E2 = FX_E1 + (FU_ROWS + 4) * FX_EROW;
+constexpr int FX_G = FX_E2 + FU_ROWS * FX_EROW;
+constexpr int FX_XS = FX_G + FU_ROWS * FX_EROW;                    // bf16 staging rows
+constexpr int FX_BI = FX_XS + FU_ROWS * FU_XROW;                   // [layer][conv b | conv s | rs b | rs s]
+constexpr int FX_LDS = FX_BI + 4 * 4 * 2 * kC * 4;                 // 72,672 bytes: two blocks per CU
+static_assert(2 * FX_LDS <= 160 * 1024, "two FP8 fused blocks per CU");
 
-__device__ inline uint8_t* fe_xbuf(uint8_t* lds, int j) { return lds + j * FE_XBUF + FU_HIST * FE_ROW; }
-__device__ inline uint8_t* fe_bbuf(uint8_t* lds, int j) { return lds + 3 * FE_XBUF + j * FE_BBUF; }
+__device__ inline uint8_t* fx_buf(uint8_t* lds, int j) { return lds + (j == 0 ? FX_E0 : j == 1 ? FX_E1 : FX_E2); }
+
+// Four bf16 values (an 8-byte word) -> four E4M3 codes (a 32-bit word), saturated to +/-448.
+__device__ inline uint32_t bf16x4_to_e4m3(uint2 w) { return bf16x2_to_e4m3(w.x) | (bf16x2_to_e4m3(w.y) << 16); }
 
 // G2 as in the BF16 kernel: one k-step covers 64 input channels, i.e. one group, so a wave of group
-// q / 2 takes steps q / 2 and 2 + q / 2 of phase 1 and step q / 2 of phase 2.
+// q / 2 takes steps q / 2 and 2 + q / 2 of the first phase and step q / 2 of the second.
 // DBG as in the BF16 kernel.
-template <bool FROM_STREAM, bool SKIP_INIT, bool G2, bool DBG = false>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void fused3_fp8_kernel(FusedArgs p) {
-    using T = LP<true, FE_RB, 4>;  // E4M3 fragments (32 B per lane), 4 waves x FE_RB row blocks
-    constexpr int RB = FE_RB;
-    constexpr int PF = 2;          // weight-fragment ring depth
-    constexpr int NS1 = G2 ? T::NK1 / 2 : T::NK1, NS2 = G2 ? T::NK2 / 2 : T::NK2;
-    constexpr auto k1 = [](int s) { return G2 ? 2 * s : s; };   // phase-1 step s -> k, after the group shift
-    __shared__ __attribute__((aligned(16))) uint8_t lds[FE_LDS];
-    uint8_t* GE = lds + 3 * FE_XBUF + 2 * FE_BBUF;
+template <bool FROM_STREAM, bool SKIP_INIT, int NL, bool LAST, bool G2, bool DBG = false>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void fused_fp8_kernel(FusedArgs p) {
+    static_assert(NL == 3 || NL == 4, "three or four layers");
+    static_assert(!LAST || NL == 4, "the network's last layer ends a quad");
+    using T = LP<true, 2, 4>;  // E4M3 fragments (32 bytes per lane), 4 waves x 2 row blocks
+    __shared__ __attribute__((aligned(16))) uint8_t lds[FX_LDS];
+    uint8_t* G = lds + FX_G;
+    uint8_t* XS = lds + FX_XS;
+    float* BI = (float*)(lds + FX_BI);
     const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6, h = lane >> 5, r = lane & 31;
     const int seg = blockIdx.x % p.n_seg;
     const int cls = (blockIdx.x / p.n_seg) % p.d0;
     const int b = blockIdx.x / (p.n_seg * p.d0);
-    const int n_sub = (p.T - cls + p.d0 - 1) / p.d0;
-    const int n_ch = (n_sub + FE_ROWS - 1) / FE_ROWS;
+    const int n_sub = (p.T - cls + p.d0 - 1) / p.d0;  // rows of this sub-sequence
+    const int n_ch = (n_sub + FU_ROWS - 1) / FU_ROWS;
     const int c0 = seg * p.seg_chunks;
     if (c0 >= n_ch) return;  // uniform over the block
     const int c1 = min(c0 + p.seg_chunks, n_ch);
@@ -949,273 +961,299 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
         start = (gw - sd.win_begin) * p.S;
     }
     // causal zero padding of the operand histories (E4M3 zero is 0x00)
-    for (int idx = tid; idx < 3 * FU_HIST * 8; idx += 256) {
-        const int j = idx / (FU_HIST * 8), rr = (idx >> 3) % FU_HIST, c = idx & 7;
-        *(uint4*)(fe_xbuf(lds, j) + (rr - FU_HIST) * FE_ROW + 16 * c) = make_uint4(0, 0, 0, 0);
+    for (int idx = tid; idx < (8 + 2 + 4) * 8; idx += 256) {
+        const int rr = idx >> 3, c = idx & 7;  // rows 0-7: buffer 0, 8-9: buffer 1, 10-13: buffer 2
+        uint8_t* row = rr < 8 ? fx_buf(lds, 0) - (8 - rr) * FX_EROW
+                     : rr < 10 ? fx_buf(lds, 1) - (10 - rr) * FX_EROW : fx_buf(lds, 2) - (14 - rr) * FX_EROW;
+        *(uint4*)(row + 16 * c) = make_uint4(0, 0, 0, 0);
     }
-    const int n = 32 * q + r;
-    constexpr int SCH = FE_ROWS * 16 / 256;  // 16-byte chunks staged per thread
-    for (int c = (seg > 0 ? c0 - 1 : c0); c < c1; ++c) {
-        const bool store = c >= c0;
-        const int sb = c * FE_ROWS;
-        // ---- stage rows [0, FE_ROWS): bf16 residual base and E4M3 operand; prefetch the skip rows
-        uint4 v[SCH];
+    // lane (h, r): row r of each 32-row block; channels cb + 8 g + e (g, e = 0..3) of the wave's block
+    const int cb = 32 * q + 4 * h;
+    const int gq = G2 ? (q >> 1) : 0;   // G2: this wave's group (its one k-step in each half of K)
+    constexpr int NS1 = G2 ? 2 : T::NK1, NS2 = G2 ? 1 : T::NK2;
+    constexpr auto k1 = [](int s) { return G2 ? 2 * s : s; };   // step -> k, after the group shift
+    const size_t wsh = (size_t)gq * 64 * T::FRAG;                 // weight-fragment shift
+    // HBM rows are requested right before a gate, as in the BF16 kernel
+    auto fetch_rows = [&](int c, ChunkRows<FROM_STREAM>& cr) {
+        const int sb = c * FU_ROWS;
 #pragma unroll
-        for (int it = 0; it < SCH; ++it) {
+        for (int it = 0; it < 4; ++it) {
             const int idx = tid + 256 * it, rr = idx >> 4, c8 = 8 * (idx & 15);
             const int sr = sb + rr;
             const int t = cls + p.d0 * sr;
-            v[it] = make_uint4(0, 0, 0, 0);
-            if (sr < n_sub) {
-                if (FROM_STREAM) {
-                    float u0 = 0.f, u1 = 0.f;
-                    const int64_t smp = start + t;
-                    if (smp < sd.length) {
-                        u0 = sd.ch0[smp * sd.stride];
-                        u1 = sd.ch1[smp * sd.stride];
-                    }
-                    uint32_t w[4];
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int ch = c8 + 2 * e;
-                        const float x0 = p.b_in[ch] + p.w_in[2 * ch] * u0 + p.w_in[2 * ch + 1] * u1;
-                        const float x1 = p.b_in[ch + 1] + p.w_in[2 * ch + 2] * u0 + p.w_in[2 * ch + 3] * u1;
-                        w[e] = (uint32_t)to_bf16_bits(x0) | ((uint32_t)to_bf16_bits(x1) << 16);
-                    }
-                    v[it] = make_uint4(w[0], w[1], w[2], w[3]);
-                } else {
-                    v[it] = *(const uint4*)&p.x_in[(wrow0 + t) * kC + c8];
+            if (FROM_STREAM) {
+                cr.u[it][0] = 0.f;
+                cr.u[it][1] = 0.f;
+                const int64_t smp = start + t;
+                if (sr < n_sub && smp < sd.length) {
+                    cr.u[it][0] = sd.ch0[smp * sd.stride];
+                    cr.u[it][1] = sd.ch1[smp * sd.stride];
                 }
+            } else {
+                cr.v[it] = sr < n_sub ? *(const uint4*)&p.x_in[(wrow0 + t) * kC + c8] : make_uint4(0, 0, 0, 0);
             }
         }
-        float sk[RB][16];
+    };
+    ChunkRows<FROM_STREAM> nrows;
+    fetch_rows(seg > 0 ? c0 - 1 : c0, nrows);
+    // first-phase weight fragments: a ring of FX_PRE steps, loaded ahead during the previous layer's
+    // second phase and refilled after each step's products
+    constexpr int FX_PRE = 2;
+    Frag<true> rf[FX_PRE], rg[FX_PRE];
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
+    for (int k = 0; k < FX_PRE && k < NS1; ++k) {
+        rf[k] = load_frag<true>(p.wc[0] + ((size_t)(q * T::NK1 + k1(k)) * 64 + lane) * T::FRAG + wsh);
+        rg[k] = load_frag<true>(p.wc[0] + ((size_t)((4 + q) * T::NK1 + k1(k)) * 64 + lane) * T::FRAG + wsh);
+    }
+    // biases and scales of the layers: [layer][conv b 256 | conv s 256 | rs b 256 | rs s 256]
+    for (int idx = tid; idx < NL * 2 * kC; idx += 256) {  // four floats per thread and step
+        const int j = idx / (2 * kC), e = 4 * (idx % (2 * kC));
+        const int part = e / (2 * kC), o = e % (2 * kC);
+        const float* src = part == 0 ? p.bc[j] : part == 1 ? p.sc[j] : part == 2 ? p.brs[j] : p.srs[j];
+        float4 v;
+        if (part >= 2 && LAST && j == NL - 1)  // skip columns only, packed first
+            v = o < kC ? make_float4(0.f, 0.f, 0.f, 0.f) : *(const float4*)(src + o - kC);
+        else v = *(const float4*)(src + o);
+        *(float4*)(BI + 4 * idx) = v;
+    }
+    for (int c = (seg > 0 ? c0 - 1 : c0); c < c1; ++c) {
+        const bool store = c >= c0;
+        const int sb = c * FU_ROWS;
+        floatx16 sk[2];
+        // ---- stage the first layer's input rows [0, 64): bf16 for the residual, E4M3 operands
+        uint8_t* E0 = fx_buf(lds, 0);
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int sr = sb + 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
-                sk[rb][i] = (!SKIP_INIT && store && sr < n_sub) ? p.skip[(wrow0 + cls + p.d0 * sr) * kC + n] : 0.f;
-            }
-#pragma unroll
-        for (int it = 0; it < SCH; ++it) {
+        for (int it = 0; it < 4; ++it) {
             const int idx = tid + 256 * it, rr = idx >> 4, c8 = 8 * (idx & 15);
-            *(uint4*)(fe_bbuf(lds, 0) + rr * FU_XROW + 2 * c8) = v[it];
-            *(uint2*)(fe_xbuf(lds, 0) + rr * FE_ROW + c8) = bf16x8_to_e4m3(v[it]);
+            uint4 v;
+            if (FROM_STREAM) {  // input projection x0 = W_in u[t] + b_in, rounded to bf16 (zero past the sub-sequence end)
+                const float u0 = nrows.u[it][0], u1 = nrows.u[it][1];
+                uint32_t w[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int ch = c8 + 2 * e;
+                    const float x0 = p.b_in[ch] + p.w_in[2 * ch] * u0 + p.w_in[2 * ch + 1] * u1;
+                    const float x1 = p.b_in[ch + 1] + p.w_in[2 * ch + 2] * u0 + p.w_in[2 * ch + 3] * u1;
+                    w[e] = (uint32_t)to_bf16_bits(x0) | ((uint32_t)to_bf16_bits(x1) << 16);
+                }
+                v = sb + rr < n_sub ? make_uint4(w[0], w[1], w[2], w[3]) : make_uint4(0, 0, 0, 0);
+            } else {
+                v = nrows.v[it];
+            }
+            *(uint4*)(XS + rr * FU_XROW + 2 * c8) = v;
+            *(uint2*)(E0 + rr * FX_EROW + c8) = bf16x8_to_e4m3(v);
         }
         __syncthreads();
 
 #pragma unroll 1
-        for (int j = 0; j < 3; ++j) {
-            const int dil = 1 << j;
-            uint8_t* XE = fe_xbuf(lds, j);
-            uint8_t* XEo = fe_xbuf(lds, j + 1 < 3 ? j + 1 : 0);
-            const uint8_t* XB = fe_bbuf(lds, j & 1);
-            uint8_t* XBo = fe_bbuf(lds, (j + 1) & 1);
-            const float bf = p.bc[j][n], bg = p.bc[j][kC + n], br = p.brs[j][n], bs = p.brs[j][kC + n];
-            const float sf = p.sc[j][n], sg = p.sc[j][kC + n], s_r = p.srs[j][n], s_s = p.srs[j][kC + n];
-            // ---- phase 1 (K = 256 in 4 steps: 0-1 tap s - dil, 2-3 tap s)
-            floatx16 af[RB] = {}, ag[RB] = {};
+        for (int j = 0; j < NL; ++j) {
+            const int dil = 1 << j;  // dilation in sub-rows
+            uint8_t* Xin = fx_buf(lds, j % 3);
+            uint8_t* Xo = fx_buf(lds, (j + 1) % 3);
+            const bool resid = !LAST || j < NL - 1;  // the network's last layer has no residual output
+            const bool last_layer = j == NL - 1;
+            const float* bj = BI + j * 4 * 2 * kC;
+            // ---- phase 1: acc = [x[s - dil] | x[s]] Bc, K = 256 (k-steps 0-1: tap s - dil, 2-3: tap s)
+            floatx16 af[2], ag[2];
+            __builtin_amdgcn_s_setprio(2);
             {
-                const uint8_t* A0 = XE + r * FE_ROW + 32 * h;
-                const uint8_t* Bf = p.wc[j] + ((size_t)(q * T::NK1) * 64 + lane) * T::FRAG;
-                const uint8_t* Bg = p.wc[j] + ((size_t)((4 + q) * T::NK1) * 64 + lane) * T::FRAG;
-                if constexpr (G2) {   // this wave's group: input channels [64 (q / 2), + 64)
-                    A0 += 64 * (q >> 1);
-                    Bf += (size_t)(q >> 1) * 64 * T::FRAG;
-                    Bg += (size_t)(q >> 1) * 64 * T::FRAG;
-                }
-                Frag<true> rf[PF], rg[PF];
-#pragma unroll
-                for (int k = 0; k < PF && k < NS1; ++k) {
-                    rf[k] = load_frag<true>(Bf + (size_t)k1(k) * 64 * T::FRAG);
-                    rg[k] = load_frag<true>(Bg + (size_t)k1(k) * 64 * T::FRAG);
-                }
+                const uint8_t* A0 = Xin + r * FX_EROW + 32 * h + 64 * gq;
+                const uint8_t* Bf = p.wc[j] + ((size_t)(q * T::NK1) * 64 + lane) * T::FRAG + wsh;
+                const uint8_t* Bg = p.wc[j] + ((size_t)((4 + q) * T::NK1) * 64 + lane) * T::FRAG + wsh;
 #pragma unroll
                 for (int k = 0; k < NS1; ++k) {
-                    const int slot = k % PF;
-                    const int roff = k1(k) < T::NK1 / 2 ? -dil : 0;
-                    Frag<true> a[RB];
+                    const int kk = k1(k) + gq;
+                    const int roff = kk < T::NK1 / 2 ? -dil : 0;
+                    Frag<true> a[2];
+                    __builtin_amdgcn_sched_barrier(0);   // one step's operands live at a time (registers)
 #pragma unroll
-                    for (int i = 0; i < RB; ++i) a[i] = load_frag<true>(A0 + (32 * i + roff) * FE_ROW + 64 * (k1(k) & 1));
-                    __builtin_amdgcn_sched_barrier(0);
+                    for (int i = 0; i < 2; ++i) a[i] = load_frag<true>(A0 + (32 * i + roff) * FX_EROW + 64 * (k1(k) & 1));
 #pragma unroll
-                    for (int i = 0; i < RB; ++i) {
-                        af[i] = mma<true>(a[i], rf[slot], af[i]);
-                        ag[i] = mma<true>(a[i], rg[slot], ag[i]);
+                    for (int i = 0; i < 2; ++i) {
+                        af[i] = mma<true>(rf[k % FX_PRE], a[i], k == 0 ? splat16(0.f) : af[i]);
+                        ag[i] = mma<true>(rg[k % FX_PRE], a[i], k == 0 ? splat16(0.f) : ag[i]);
                     }
                     __builtin_amdgcn_sched_barrier(0);
-                    if (k + PF < NS1) {
-                        rf[slot] = load_frag<true>(Bf + (size_t)k1(k + PF) * 64 * T::FRAG);
-                        rg[slot] = load_frag<true>(Bg + (size_t)k1(k + PF) * 64 * T::FRAG);
+                    if (k + FX_PRE < NS1) {
+                        rf[k % FX_PRE] = load_frag<true>(Bf + (size_t)k1(k + FX_PRE) * 64 * T::FRAG);
+                        rg[k % FX_PRE] = load_frag<true>(Bg + (size_t)k1(k + FX_PRE) * 64 * T::FRAG);
                     }
                 }
             }
-            if constexpr (DBG) {  // pre-activations: column scale, then bias, as the gate takes them
+            __builtin_amdgcn_s_setprio(0);
+            // the second phase's weight fragments, residual and skip columns side by side (the
+            // network's last layer packs its skip columns only, as column blocks 0-3)
+            const uint8_t* Wr = p.wrs[j] + ((size_t)(q * T::NK2) * 64 + lane) * T::FRAG + wsh;
+            const uint8_t* Ws = p.wrs[j] + ((size_t)((resid ? 4 + q : q) * T::NK2) * 64 + lane) * T::FRAG + wsh;
+            Frag<true> ringr[T::NK2], rings[T::NK2];
+            ringr[0] = load_frag<true>(Wr);
+            rings[0] = load_frag<true>(Ws);
+            const bool more = j < NL - 1 || c + 1 < c1;
+            if (last_layer && c + 1 < c1) fetch_rows(c + 1, nrows);  // next chunk's rows, in flight during the gate
+            if (j == 0) {  // this chunk's skip rows, first needed at the end of this layer
 #pragma unroll
-                for (int rb = 0; rb < RB; ++rb)
+                for (int rb = 0; rb < 2; ++rb) {
+                    const int sr = sb + 32 * rb + r;
+                    sk[rb] = splat16(0.f);
+                    if (!SKIP_INIT && store && sr < n_sub) sk[rb] = load_col16(p.skip + (wrow0 + cls + (int64_t)p.d0 * sr) * kC + cb);
+                }
+            }
+            // ---- gate: pre = acc * scale + bias, g = tanh * sigmoid -> E4M3 codes in G (4 channels per word)
+            {
 #pragma unroll
-                    for (int i = 0; i < 16; ++i) {
-                        const int sr = sb + 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
-                        if (store && sr < n_sub) {
-                            float* po = p.dbg_pre + ((int64_t)j * p.dbg_rows + wrow0 + cls + (int64_t)p.d0 * sr) * (2 * kC);
-                            po[n] = fmaf(af[rb][i], sf, bf);
-                            po[kC + n] = fmaf(ag[rb][i], sg, bg);
+                for (int rb = 0; rb < 2; ++rb) {
+                    uint8_t* gr = G + (32 * rb + r) * FX_EROW + cb;
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) {
+                        const float4 bf = *(const float4*)(bj + cb + 8 * g), bg = *(const float4*)(bj + kC + cb + 8 * g);
+                        const float4 sf = *(const float4*)(bj + 2 * kC + cb + 8 * g), sg = *(const float4*)(bj + 3 * kC + cb + 8 * g);
+                        const float bfa[4] = {bf.x, bf.y, bf.z, bf.w}, bga[4] = {bg.x, bg.y, bg.z, bg.w};
+                        const float sfa[4] = {sf.x, sf.y, sf.z, sf.w}, sga[4] = {sg.x, sg.y, sg.z, sg.w};
+                        float v[4];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int i = 4 * g + e;
+                            const float pf = fmaf(af[rb][i], sfa[e], bfa[e]), pg = fmaf(ag[rb][i], sga[e], bga[e]);
+                            if constexpr (DBG) {
+                                af[rb][i] = pf;
+                                ag[rb][i] = pg;
+                            }
+                            v[e] = gate_fast(pf, pg);
                         }
+                        *(uint32_t*)(gr + 8 * g) = e4m3_pair_in_range(v[0], v[1]) | (e4m3_pair_in_range(v[2], v[3]) << 16);
                     }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
             }
-            const uint8_t* Wr = p.wrs[j] + ((size_t)(q * T::NK2) * 64 + lane) * T::FRAG;
-            const uint8_t* Ws = p.wrs[j] + ((size_t)((4 + q) * T::NK2) * 64 + lane) * T::FRAG;
-            if constexpr (G2) {
-                Wr += (size_t)(q >> 1) * 64 * T::FRAG;
-                Ws += (size_t)(q >> 1) * 64 * T::FRAG;
-            }
-            Frag<true> ring[T::NK2];  // phase 2 has two k-steps: both fragments up front
+            if constexpr (DBG) {  // pre-activations (column scale, then bias)
 #pragma unroll
-            for (int k = 0; k < NS2; ++k) ring[k] = load_frag<true>(Wr + (size_t)k * 64 * T::FRAG);
-            __syncthreads();
-            if (tid < 8 * dil) {  // operand history of the next chunk (128 B per row)
-                const int rr = tid >> 3, cc = tid & 7;
-                *(uint4*)(XE + (rr - dil) * FE_ROW + 16 * cc) = *(const uint4*)(XE + (FE_ROWS - dil + rr) * FE_ROW + 16 * cc);
-            }
-            // ---- gate -> E4M3 operand rows
-            float gprev = 0.f;
-#pragma unroll
-            for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    const int m = 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
-                    const float gv = gate_fast(fmaf(af[rb][i], sf, bf), fmaf(ag[rb][i], sg, bg));
-                    if (i & 1) {  // rows m - 1 and m converted together
-                        const uint32_t c2 = e4m3_pair_in_range(gprev, gv);
-                        GE[(m - 1) * FE_ROW + n] = (uint8_t)(c2 & 0xffu);
-                        GE[m * FE_ROW + n] = (uint8_t)(c2 >> 8);
-                    } else {
-                        gprev = gv;
+                for (int rb = 0; rb < 2; ++rb) {
+                    const int sr = sb + 32 * rb + r;
+                    if (store && sr < n_sub) {
+                        float* po = p.dbg_pre + ((int64_t)j * p.dbg_rows + wrow0 + cls + (int64_t)p.d0 * sr) * (2 * kC);
+                        store_col16(po + cb, af[rb]);
+                        store_col16(po + kC + cb, ag[rb]);
                     }
-                    if (i == 15) __builtin_amdgcn_sched_barrier(0);
                 }
+            }
             __syncthreads();
-            const uint8_t* Ag = GE + r * FE_ROW + 32 * h;
-            if constexpr (G2) Ag += 64 * (q >> 1);
-#pragma unroll
-            for (int pass = 0; pass < 2; ++pass) {
-                if (pass == 1) {
-#pragma unroll
-                    for (int k = 0; k < NS2; ++k) ring[k] = load_frag<true>(Ws + (size_t)k * 64 * T::FRAG);
-                }
-                uint32_t xold[RB][8];
-                if (pass == 0) {
-#pragma unroll
-                    for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-                        for (int i = 0; i < 16; i += 2) {
-                            const int m = 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
-                            const uint32_t lo = *(const uint16_t*)(XB + m * FU_XROW + 2 * n);
-                            const uint32_t hi = *(const uint16_t*)(XB + (m + 1) * FU_XROW + 2 * n);
-                            xold[rb][i >> 1] = lo | (hi << 16);
-                        }
-                }
-                floatx16 acc[RB] = {};
+            // ---- phase 2 over G (K = 128 in two steps): each g fragment feeds the residual and the skip columns
+            const uint8_t* Ag = G + r * FX_EROW + 32 * h + 64 * gq;
+            const int jn = j < NL - 1 ? j + 1 : 0;  // the next layer (the first of the next chunk after the last)
+            const uint8_t* Nf = p.wc[jn] + ((size_t)(q * T::NK1) * 64 + lane) * T::FRAG + wsh;
+            const uint8_t* Ng = p.wc[jn] + ((size_t)((4 + q) * T::NK1) * 64 + lane) * T::FRAG + wsh;
+            floatx16 ar[2], as[2];
+            __builtin_amdgcn_s_setprio(2);
+            {
 #pragma unroll
                 for (int k = 0; k < NS2; ++k) {
-                    Frag<true> a[RB];
-#pragma unroll
-                    for (int i = 0; i < RB; ++i) a[i] = load_frag<true>(Ag + 32 * i * FE_ROW + 64 * k);
-#pragma unroll
-                    for (int i = 0; i < RB; ++i) acc[i] = mma<true>(a[i], ring[k], acc[i]);
-                }
-                if (pass == 0) {  // x_next = x + (scale * acc + b_res) in bf16; E4M3 operand of the next layer
-                    uint32_t xprev = 0;
-#pragma unroll
-                    for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-                        for (int i = 0; i < 16; ++i) {
-                            const int m = 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
-                            const uint32_t w = xold[rb][i >> 1];
-                            const uint16_t xb = (uint16_t)((i & 1) ? (w >> 16) : (w & 0xffffu));
-                            const uint16_t xn = to_bf16_bits(bf16_to_f32(xb) + fmaf(acc[rb][i], s_r, br));
-                            *(uint16_t*)(XBo + m * FU_XROW + 2 * n) = xn;
-                            if (j < 2) {  // rows m - 1 and m of the next layer's operand, converted together
-                                if (i & 1) {
-                                    const uint32_t c2 = bf16x2_to_e4m3(xprev | ((uint32_t)xn << 16));
-                                    XEo[(m - 1) * FE_ROW + n] = (uint8_t)(c2 & 0xffu);
-                                    XEo[m * FE_ROW + n] = (uint8_t)(c2 >> 8);
-                                } else {
-                                    xprev = xn;
-                                }
-                            }
-                        }
+                    Frag<true> a[2];
                     __builtin_amdgcn_sched_barrier(0);
-                } else {
-#pragma unroll
-                    for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-                        for (int i = 0; i < 16; ++i) {
-                            const float sv = fmaf(acc[rb][i], s_s, bs);
-                            sk[rb][i] = (SKIP_INIT && j == 0) ? sv : sk[rb][i] + sv;
-                        }
-                }
-            }
-            __syncthreads();
-            if constexpr (DBG) {  // this layer's residual output rows (bf16) and running skip sums
-                if (store) {
-                    const uint8_t* XD = fe_bbuf(lds, (j + 1) & 1);
-#pragma unroll
-                    for (int it = 0; it < SCH; ++it) {
-                        const int idx = tid + 256 * it, rr = idx >> 4, c8 = 8 * (idx & 15);
-                        const int sr = sb + rr;
-                        if (sr < n_sub) {
-                            const uint4 w = *(const uint4*)(XD + rr * FU_XROW + 2 * c8);
-                            float* xo = p.dbg_x + ((int64_t)j * p.dbg_rows + wrow0 + cls + (int64_t)p.d0 * sr) * kC + c8;
-                            *(float4*)xo = make_float4(__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xffff0000u),
-                                                       __uint_as_float(w.y << 16), __uint_as_float(w.y & 0xffff0000u));
-                            *(float4*)(xo + 4) = make_float4(__uint_as_float(w.z << 16), __uint_as_float(w.z & 0xffff0000u),
-                                                             __uint_as_float(w.w << 16), __uint_as_float(w.w & 0xffff0000u));
-                        }
+                    if (k + 1 < NS2) {
+                        ringr[k + 1] = load_frag<true>(Wr + (size_t)(k + 1) * 64 * T::FRAG);
+                        rings[k + 1] = load_frag<true>(Ws + (size_t)(k + 1) * 64 * T::FRAG);
                     }
 #pragma unroll
-                    for (int rb = 0; rb < RB; ++rb)
+                    for (int i = 0; i < 2; ++i) a[i] = load_frag<true>(Ag + 32 * i * FX_EROW + 64 * k);
+                    if (k == NS2 - 1 && more) {  // the next layer's first first-phase fragments
 #pragma unroll
-                        for (int i = 0; i < 16; ++i) {
-                            const int sr = sb + 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
-                            if (sr < n_sub)
-                                p.dbg_skip[((int64_t)j * p.dbg_rows + wrow0 + cls + (int64_t)p.d0 * sr) * kC + n] = sk[rb][i];
+                        for (int kk = 0; kk < FX_PRE && kk < NS1; ++kk) {
+                            rf[kk] = load_frag<true>(Nf + (size_t)k1(kk) * 64 * T::FRAG);
+                            rg[kk] = load_frag<true>(Ng + (size_t)k1(kk) * 64 * T::FRAG);
                         }
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) {
+                        ar[i] = mma<true>(ringr[k], a[i], k == 0 ? splat16(0.f) : ar[i]);
+                        as[i] = mma<true>(rings[k], a[i], k == 0 ? splat16(0.f) : as[i]);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            __builtin_amdgcn_s_setprio(0);
+            __builtin_amdgcn_sched_barrier(0);
+            // x_next = x + (scale * acc + b_res), rounded to bf16, in place in the staging buffer (only
+            // this lane reads and writes these rows and channels), and as E4M3 operand rows of the next
+            // layer; skip += scale * acc + b_skip
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int i = 4 * g;
+                const float4 br4 = *(const float4*)(bj + 4 * kC + cb + 8 * g), sr4 = *(const float4*)(bj + 6 * kC + cb + 8 * g);
+                const float4 bs4 = *(const float4*)(bj + 5 * kC + cb + 8 * g), ss4 = *(const float4*)(bj + 7 * kC + cb + 8 * g);
+#pragma unroll
+                for (int rb = 0; rb < 2; ++rb) {
+                    if (resid) {
+                        uint2* xp = (uint2*)(XS + (32 * rb + r) * FU_XROW + 2 * (cb + 8 * g));
+                        const uint2 xn = residual4(*xp, fmaf(ar[rb][i], sr4.x, br4.x), fmaf(ar[rb][i + 1], sr4.y, br4.y),
+                                                   fmaf(ar[rb][i + 2], sr4.z, br4.z), fmaf(ar[rb][i + 3], sr4.w, br4.w));
+                        *xp = xn;
+                        if (!last_layer) *(uint32_t*)(Xo + (32 * rb + r) * FX_EROW + cb + 8 * g) = bf16x4_to_e4m3(xn);
+                    }
+                    const float sv[4] = {fmaf(as[rb][i], ss4.x, bs4.x), fmaf(as[rb][i + 1], ss4.y, bs4.y),
+                                         fmaf(as[rb][i + 2], ss4.z, bs4.z), fmaf(as[rb][i + 3], ss4.w, bs4.w)};
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) sk[rb][i + e] = (SKIP_INIT && j == 0) ? sv[e] : sk[rb][i + e] + sv[e];
+                }
+            }
+            __syncthreads();  // the next layer's input (or the chunk's output rows) is complete
+            // this input's last dil rows become the history of the next chunk: every wave has read
+            // them by now, and the buffer is next written two layers on (or by the next chunk)
+            if (c + 1 < c1 && tid < 8 * dil) {
+                const int rr = tid >> 3, cc = tid & 7;
+                *(uint4*)(Xin + (rr - dil) * FX_EROW + 16 * cc) = *(const uint4*)(Xin + (FU_ROWS - dil + rr) * FX_EROW + 16 * cc);
+            }
+            if constexpr (DBG) {  // this layer's residual output and running skip sum of the stored rows
+                if (store) {
+#pragma unroll
+                    for (int rb = 0; rb < 2; ++rb) {
+                        const int sr = sb + 32 * rb + r;
+                        if (sr < n_sub) {
+                            const int64_t row = (int64_t)j * p.dbg_rows + wrow0 + cls + (int64_t)p.d0 * sr;
+                            if (resid) {
+#pragma unroll
+                                for (int g = 0; g < 4; ++g) {
+                                    const uint2 w = *(const uint2*)(XS + (32 * rb + r) * FU_XROW + 2 * (cb + 8 * g));
+                                    *(float4*)(p.dbg_x + row * kC + cb + 8 * g) =
+                                        make_float4(__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xffff0000u),
+                                                    __uint_as_float(w.y << 16), __uint_as_float(w.y & 0xffff0000u));
+                                }
+                            }
+                            store_col16(p.dbg_skip + row * kC + cb, sk[rb]);
+                        }
+                    }
                 }
             }
         }
-        // ---- chunk output: x rows from the last residual buffer, skip from registers
+        // ---- chunk output: x rows from the staging buffer (16-byte stores), skip rows from registers
         if (store) {
-            const uint8_t* XF = fe_bbuf(lds, 1);  // the third layer (j = 2) wrote buffer (2 + 1) & 1
 #pragma unroll
-            for (int it = 0; it < SCH; ++it) {
+            for (int it = 0; it < 4 && !LAST; ++it) {
                 const int idx = tid + 256 * it, rr = idx >> 4, c8 = 8 * (idx & 15);
                 const int sr = sb + rr;
                 if (sr < n_sub)
-                    *(uint4*)&p.x_out[(wrow0 + cls + p.d0 * sr) * kC + c8] = *(const uint4*)(XF + rr * FU_XROW + 2 * c8);
+                    *(uint4*)&p.x_out[(wrow0 + cls + p.d0 * sr) * kC + c8] = *(const uint4*)(XS + rr * FU_XROW + 2 * c8);
             }
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    const int sr = sb + 32 * rb + 8 * (i >> 2) + 4 * h + (i & 3);
-                    if (sr < n_sub) p.skip[(wrow0 + cls + p.d0 * sr) * kC + n] = sk[rb][i];
-                }
+            for (int rb = 0; rb < 2; ++rb) {
+                const int sr = sb + 32 * rb + r;
+                if (sr < n_sub) store_col16(p.skip + (wrow0 + cls + (int64_t)p.d0 * sr) * kC + cb, sk[rb]);
+            }
         }
-        __syncthreads();
+        __syncthreads();  // the staging buffer is read above before the next chunk stages into it
     }
 }
 
 // Layers covered by the fused launch that starts at layer l for windows of length T: 0 (l is not a
 // start), 3, or 4. Triples start at stack positions 0, 3, 6; the triple at 6 also takes the stack's
-// last layer (a quad, BF16) when the sub-sequences at its dilation are one chunk long. A triple never
+// last layer (a quad) when the sub-sequences at its dilation are one chunk long. A triple never
 // includes the network's last layer.
 static int fused_layers(const gwd_model* m, int l, int T) {
     if ((m->prec != GWD_BF16 && m->prec != GWD_FP8_E4M3) || m->lp_fuse != 3) return 0;
     const int lps = m->arch.layers_per_stack, L = m->arch.n_stacks * lps, i = l % lps;
     if (i % 3 != 0 || i + 2 >= lps) return 0;
     const int d0 = 1 << i;
-    if (m->prec == GWD_BF16 && i + 4 == lps && T > 0 && (T + d0 - 1) / d0 <= FU_ROWS) return 4;
+    if (i + 4 == lps && T > 0 && (T + d0 - 1) / d0 <= FU_ROWS) return 4;
     return l + 2 < L - 1 ? 3 : 0;
 }
 
@@ -1224,6 +1262,12 @@ template <bool FROM_STREAM, bool SKIP_INIT, int NL, bool LAST>
 static void launch_fused_bf16(bool g2, dim3 grid, hipStream_t st, const FusedArgs& a) {
     if (g2) hipLaunchKernelGGL((fused_bf16_kernel<FROM_STREAM, SKIP_INIT, NL, LAST, true>), grid, dim3(256), 0, st, a);
     else hipLaunchKernelGGL((fused_bf16_kernel<FROM_STREAM, SKIP_INIT, NL, LAST, false>), grid, dim3(256), 0, st, a);
+}
+
+template <bool FROM_STREAM, bool SKIP_INIT, int NL, bool LAST>
+static void launch_fused_fp8(bool g2, dim3 grid, hipStream_t st, const FusedArgs& a) {
+    if (g2) hipLaunchKernelGGL((fused_fp8_kernel<FROM_STREAM, SKIP_INIT, NL, LAST, true>), grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((fused_fp8_kernel<FROM_STREAM, SKIP_INIT, NL, LAST, false>), grid, dim3(256), 0, st, a);
 }
 
 template <bool FP8>
@@ -1247,7 +1291,7 @@ static hipError_t launch_fused(gwd_model* m, int member, int l, int nl, const ui
     a.skip = skip;
     a.d0 = 1 << (l % m->arch.layers_per_stack);
     a.T = T;
-    const int rows = FP8 ? FE_ROWS : FU_ROWS;                           // sub-rows per chunk
+    const int rows = FU_ROWS;                                           // sub-rows per chunk
     const int n_ch = ((T + a.d0 - 1) / a.d0 + rows - 1) / rows;       // chunks of the longest sub-sequence
     if (nl == 4 && n_ch != 1) return hipErrorInvalidValue;              // a quad needs one-chunk sub-sequences
     // enough blocks for every resident slot (two per CU on 256 CUs); a segment after the first costs
@@ -1272,9 +1316,14 @@ static hipError_t launch_fused(gwd_model* m, int member, int l, int nl, const ui
         a.dbg_skip = dbg->dbg_skip;
         a.dbg_rows = (int64_t)nb * T;
         if (FP8) {
-            if (nl != 3) return hipErrorInvalidValue;
-            if (first) hipLaunchKernelGGL((fused3_fp8_kernel<false, true, false, true>), grid, dim3(256), 0, st, a);
-            else hipLaunchKernelGGL((fused3_fp8_kernel<false, false, false, true>), grid, dim3(256), 0, st, a);
+            if (nl == 3) {
+                if (first) hipLaunchKernelGGL((fused_fp8_kernel<false, true, 3, false, false, true>), grid, dim3(256), 0, st, a);
+                else hipLaunchKernelGGL((fused_fp8_kernel<false, false, 3, false, false, true>), grid, dim3(256), 0, st, a);
+            } else {
+                if (first) return hipErrorInvalidValue;
+                if (l + 3 == L - 1) hipLaunchKernelGGL((fused_fp8_kernel<false, false, 4, true, false, true>), grid, dim3(256), 0, st, a);
+                else hipLaunchKernelGGL((fused_fp8_kernel<false, false, 4, false, false, true>), grid, dim3(256), 0, st, a);
+            }
         } else if (nl == 3) {
             if (first) hipLaunchKernelGGL((fused_bf16_kernel<false, true, 3, false, false, true>), grid, dim3(256), 0, st, a);
             else hipLaunchKernelGGL((fused_bf16_kernel<false, false, 3, false, false, true>), grid, dim3(256), 0, st, a);
@@ -1286,15 +1335,15 @@ static hipError_t launch_fused(gwd_model* m, int member, int l, int nl, const ui
         return hipGetLastError();
     }
     if (FP8) {
-        if (nl != 3) return hipErrorInvalidValue;
-        if (m->two_branch) {   // block-diagonal weights: skip the zero blocks
-            if (stream_in) hipLaunchKernelGGL((fused3_fp8_kernel<true, true, true>), grid, dim3(256), 0, st, a);
-            else if (first) hipLaunchKernelGGL((fused3_fp8_kernel<false, true, true>), grid, dim3(256), 0, st, a);
-            else hipLaunchKernelGGL((fused3_fp8_kernel<false, false, true>), grid, dim3(256), 0, st, a);
+        if (nl == 3) {
+            const bool g2 = m->two_branch;   // block-diagonal weights: skip the zero blocks
+            if (stream_in) launch_fused_fp8<true, true, 3, false>(g2, grid, st, a);
+            else if (first) launch_fused_fp8<false, true, 3, false>(g2, grid, st, a);
+            else launch_fused_fp8<false, false, 3, false>(g2, grid, st, a);
         } else {
-            if (stream_in) hipLaunchKernelGGL((fused3_fp8_kernel<true, true, false>), grid, dim3(256), 0, st, a);
-            else if (first) hipLaunchKernelGGL((fused3_fp8_kernel<false, true, false>), grid, dim3(256), 0, st, a);
-            else hipLaunchKernelGGL((fused3_fp8_kernel<false, false, false>), grid, dim3(256), 0, st, a);
+            if (first) return hipErrorInvalidValue;                      // stacks of at least 10 layers
+            if (l + 3 == L - 1) launch_fused_fp8<false, false, 4, true>(m->two_branch, grid, st, a);
+            else launch_fused_fp8<false, false, 4, false>(m->two_branch, grid, st, a);
         }
     } else if (nl == 3) {
         const bool g2 = m->two_branch;   // block-diagonal weights: skip the zero blocks

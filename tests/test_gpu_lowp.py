@@ -150,7 +150,7 @@ def test_layer_local_parity(g, model, blob, layer):
 
 @pytest.mark.parametrize("first", [0, 3, 6, 26])
 def test_fused_launch_layer_local_parity(g, model, blob, first):
-    """Every layer of the fused launches the forward times (triples; BF16 quads at the end of each
+    """Every layer of the fused launches the forward times (triples; quads at the end of each
     stack, the last one being the network's last layer), checked layer by layer against the
     oracle: each layer's input is the previous layer's output as the kernel stored it, at
     T = 4096 so that every dilation, 512 included, reads history rows. Two windows: the
@@ -161,7 +161,7 @@ def test_fused_launch_layer_local_parity(g, model, blob, first):
     T, nw, C = 4096, 2, 128
     nl = m.fused_layers(first, T)
     print(f"case: {prec} fused launch at layer {first} ({nl} layers)", flush=True)
-    assert nl == (4 if prec == "bf16" and first % 10 == 6 else 3)
+    assert nl == (4 if first % 10 == 6 else 3)
     p = unpack(FULL, blob.astype(np.float64))
     rng = np.random.default_rng(200 + first)
     x = (rng.standard_normal((nw, T, C)) * 3).astype(np.float32)
