@@ -445,6 +445,7 @@ void gwd_free(gwd_model* m) {
     if (m->tws.base) (void)hipFree(m->tws.base);
     if (m->branch_map) (void)hipFree(m->branch_map);
     if (m->dense_grad) (void)hipFree(m->dense_grad);
+    if (m->repack_tab) (void)hipFree(m->repack_tab);
     delete m;
 }
 

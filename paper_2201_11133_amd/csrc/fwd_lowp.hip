@@ -427,7 +427,6 @@ static int lp_tiling(const gwd_model* m, bool fp8) {
 // stored. Every output is computed with the same operations, in the same order, as by three
 // launches of the single-layer kernel.
 constexpr int FU_ROWS = 64;                                // sub-rows per chunk (2 row blocks x 4 waves)
-constexpr int FU_HIST = 4;                                 // history rows in front of each input buffer
 constexpr int FU_XROW = 2 * kC + 16;                       // bf16 row + 16-byte pad
 // BF16 form: layer j reads buffer j % 3 and writes buffer (j + 1) % 3. Each buffer keeps in front of
 // its rows as many history rows as the largest dilation read from it: 8 for buffer 0 (dilation 1,

@@ -91,7 +91,7 @@ struct gwd_model {
     int32_t n_members;
     int64_t n_params;
     int device;
-    std::vector<float> host_blob;              // canonical fp32 weights (kept for export and repacking)
+    std::vector<float> host_blob;              // canonical fp32 weights as loaded (the source of the first packing)
     std::vector<gwd::MemberWeights> members;
     gwd::Workspace ws;
     gwd::Workspace tws;                        // training workspace
@@ -108,6 +108,7 @@ struct gwd_model {
     int64_t branch_params = 0;                 // kind 2: parameters of one member in its own (branch) blob
     int64_t* branch_map = nullptr;             // kind 2: device [branch_params], trunk index of each branch parameter
     float* dense_grad = nullptr;               // kind 2: device [n_params], the trunk gradient before read-back
+    void* repack_tab = nullptr;                // device per-layer offsets of the on-device weight refresh (gwd_adam_step)
     // test support (gwd_debug_capture_backward): gated layer whose backward operands and results the
     // next gwd_backward copies out as fp32 [M][C] ([M][2C] for pre and dpre); -1 = off
     int32_t cap_layer = -1;

@@ -371,6 +371,42 @@ gwd_status gwd_backward(gwd_model* m, int32_t member, const float* windows, int3
                      (float*)grad_input, st);
 }
 
+}  // extern "C"
+
+namespace gwd {
+// The member's device image rebuilt from its device canonical blob (m->canon[member]) by the repack
+// kernel; the per-layer offset table is uploaded once per model.
+static gwd_status refresh_member(gwd_model* m, int member, hipStream_t st) {
+    MemberWeights& mw = m->members[member];
+    const float* canon = (const float*)m->canon[member];
+    hipError_t e;
+    if (m->arch.kind == 0) {   // FP32 small member: the image holds the blob as is (scales stay 1)
+        e = hipMemcpyAsync((float*)mw.base + mw.blob, canon, m->n_params * 4, hipMemcpyDeviceToDevice, st);
+        return e == hipSuccess ? GWD_OK : hip_fail(e, "hipMemcpyAsync(image)");
+    }
+    const int L = m->arch.n_stacks * m->arch.layers_per_stack;
+    const BlobOffsets v = blob_offsets(m->arch);
+    const bool bf16 = m->prec == GWD_BF16;
+    if (!m->repack_tab) {
+        std::vector<RepackLayer> tab(L);
+        for (int l = 0; l < L; ++l) {
+            const LayerOffsets& lo = mw.layers[l];
+            tab[l] = RepackLayer{v.dil_w[l], v.dil_b[l], v.res_w[l], v.res_b[l], v.skip_w[l], v.skip_b[l],
+                                 bf16 ? lo.wc : lo.wc * 4, bf16 ? lo.wrs : lo.wrs * 4, lo.bc * 4, lo.brs * 4};
+        }
+        e = hipMalloc(&m->repack_tab, L * sizeof(RepackLayer));
+        if (e != hipSuccess) { m->repack_tab = nullptr; return hip_fail(e, "hipMalloc(repack table)"); }
+        e = hipMemcpy(m->repack_tab, tab.data(), L * sizeof(RepackLayer), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy(repack table)");
+    }
+    const RepackFixed fx{v.in_w, v.in_b, v.h1w, v.h1b, v.h2w, v.h2b, mw.w_in, mw.b_in, mw.h1w, mw.h1b, mw.h2w, mw.h2b};
+    e = launch_repack(bf16, canon, (uint8_t*)mw.base, (const RepackLayer*)m->repack_tab, L, fx, st);
+    return e == hipSuccess ? GWD_OK : hip_fail(e, "repack kernel");
+}
+}  // namespace gwd
+
+extern "C" {
+
 gwd_status gwd_adam_step(gwd_model* m, int32_t member, float* master, const float* grad, float* mom, float* vel,
                          int64_t step, float lr, float beta1, float beta2, float eps, double* grad_norm_out,
                          void* hip_stream) {
@@ -394,27 +430,13 @@ gwd_status gwd_adam_step(gwd_model* m, int32_t member, float* master, const floa
     e = launch_adam(master, grad, mom, vel, n, lr, beta1, beta2, eps, step, part, grad_norm_out, st);
     if (e != hipSuccess) return hip_fail(e, "adam kernel");
     (void)hipFreeAsync(part, st);
-    // refresh the member's working weights from the new master weights
-    if (m->two_branch) {   // expand to the block-diagonal trunk, then as below
-        std::vector<float> hb2((size_t)n), dense;
-        e = hipMemcpyAsync(hb2.data(), master, n * 4, hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess) return hip_fail(e, "hipMemcpy(master to host)");
-        expand_two_branch(&m->branch_arch, hb2.data(), dense);
-        float* hb = m->host_blob.data() + (size_t)member * m->n_params;
-        std::copy(dense.begin(), dense.end(), hb);
-        e = hipMemcpy(m->canon[member], hb, m->n_params * 4, hipMemcpyHostToDevice);
-        if (e != hipSuccess) return hip_fail(e, "hipMemcpy(trunk weights)");
-        return pack_member(m, member, hb);
-    }
-    e = hipMemcpyAsync(m->canon[member], master, n * 4, hipMemcpyDeviceToDevice, st);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(master)");
-    float* hb = m->host_blob.data() + (size_t)member * n;
-    e = hipMemcpyAsync(hb, master, n * 4, hipMemcpyDeviceToHost, st);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(master to host)");
-    e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    return pack_member(m, member, hb);
+    // refresh the member's working weights from the new master weights, on the device (no host copy,
+    // no synchronisation): the canonical copy first (two-branch members: the branch parameters
+    // scattered into their block-diagonal trunk image, whose zero blocks never change), then the image
+    if (m->two_branch) e = launch_scatter(master, m->branch_map, n, (float*)m->canon[member], st);
+    else e = hipMemcpyAsync(m->canon[member], master, n * 4, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "canonical weights");
+    return refresh_member(m, member, st);
 }
 
 gwd_status gwd_debug_capture_backward(gwd_model* m, int32_t layer, float* x_in, float* pre, float* dskip, float* dx_in,

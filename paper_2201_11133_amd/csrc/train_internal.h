@@ -75,6 +75,22 @@ hipError_t launch_input_grad(const float* dx0, int64_t M, const float* w_in, flo
 hipError_t launch_relu_copy(const float* x, int64_t n, float* y, hipStream_t st);
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t st);
 hipError_t launch_gather(const float* src, const int64_t* idx, int64_t n, float* dst, hipStream_t st);
+// dst[idx[i]] = src[i], i < n
+hipError_t launch_scatter(const float* src, const int64_t* idx, int64_t n, float* dst, hipStream_t st);
+// Offsets of one gated layer for the device repack: tensors in the canonical blob (floats; res_w < 0
+// in the network's last layer) and their places in the member's device image (bytes).
+struct RepackLayer {
+    int64_t dil_w, dil_b, res_w, res_b, skip_w, skip_b;
+    int64_t wc, wrs, bc, brs;
+};
+// The input projection and the head: blob offsets and image offsets (floats).
+struct RepackFixed {
+    int64_t in_w, in_b, h1w, h1b, h2w, h2b;
+    int64_t d_in_w, d_in_b, d_h1w, d_h1b, d_h2w, d_h2b;
+};
+// Rebuild a gated member's BF16 (bf16 = true) or FP32 device image from its fp32 canonical blob.
+hipError_t launch_repack(bool bf16, const float* blob, uint8_t* img, const RepackLayer* tab, int L,
+                         const RepackFixed& fx, hipStream_t st);
 hipError_t launch_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
                        float eps, int64_t step, double* norm_part, double* norm_out, hipStream_t st);
 hipError_t launch_bce(const float* z, const float* y, int64_t n, float* grad, double* part, double* loss,

@@ -780,4 +780,95 @@ hipError_t launch_bce(const float* z, const float* y, int64_t n, float* grad, do
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- working-weight refresh on the device
+// After an optimiser step the member's device image is rebuilt from the new fp32 master weights by
+// one gather kernel, with the fragment orders of pack_member (pack.cpp) written out per element:
+// blockIdx.y = layer (blockIdx.y == L: the input projection and the head, copied as fp32). BF16:
+// each weight rounded to nearest even (the hardware conversion); FP32: copied.
+namespace {
+template <bool BF16>
+__global__ void repack_kernel(const float* __restrict__ blob, uint8_t* __restrict__ img, const RepackLayer* tab, int L,
+                              RepackFixed fx) {
+    const int l = blockIdx.y;
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l == L) {   // fixed tensors: [w_in 256 | b_in 128 | h1w 16384 | h1b 128 | h2w 128 | h2b 1]
+        const int64_t n_fix = 256 + 128 + 16384 + 128 + 128 + 1;
+        for (int64_t e = t0; e < n_fix; e += step) {
+            int64_t src, dst;
+            if (e < 256) { src = fx.in_w + e; dst = fx.d_in_w + e; }
+            else if (e < 384) { src = fx.in_b + e - 256; dst = fx.d_in_b + e - 256; }
+            else if (e < 384 + 16384) { src = fx.h1w + e - 384; dst = fx.d_h1w + e - 384; }
+            else if (e < 384 + 16384 + 128) { src = fx.h1b + e - 16768; dst = fx.d_h1b + e - 16768; }
+            else if (e < 384 + 16384 + 256) { src = fx.h2w + e - 16896; dst = fx.d_h2w + e - 16896; }
+            else { src = fx.h2b; dst = fx.d_h2b; }
+            ((float*)img)[dst] = blob[src];
+        }
+        return;
+    }
+    const RepackLayer t = tab[l];
+    const bool last = t.res_w < 0;
+    const int nrs = last ? 128 : 256;
+    const int64_t n_conv = 65536, n_rs = (int64_t)nrs * 128;
+    const int64_t n_all = n_conv + n_rs + 256 + nrs;
+    for (int64_t e = t0; e < n_all; e += step) {
+        if (e < n_conv) {   // conv: K = 256 (tap 0 multiplies x[t - d]), N = 256
+            int k, n;
+            if (BF16) {
+                const int i = e & 7, ln = (e >> 3) & 63, j = (e >> 9) & 15, cb = (int)(e >> 13);
+                k = 16 * j + 8 * (ln >> 5) + i;
+                n = 32 * cb + (ln & 31);
+            } else {
+                const int i = e & 3, ln = (e >> 2) & 63, j = (e >> 8) & 15, cb = (int)(e >> 12);
+                k = 16 * j + 4 * (ln >> 4) + i;
+                n = 16 * cb + (ln & 15);
+            }
+            const float w = blob[t.dil_w + ((int64_t)n * 128 + (k & 127)) * 2 + (k >> 7)];
+            if (BF16) ((__bf16*)(img + t.wc))[e] = (__bf16)w;
+            else ((float*)(img + t.wc))[e] = w;
+        } else if (e < n_conv + n_rs) {   // res | skip: K = 128, N = 256 (last layer: skip only, N = 128)
+            const int64_t f = e - n_conv;
+            int k, n;
+            if (BF16) {
+                const int i = f & 7, ln = (f >> 3) & 63, j = (f >> 9) & 7, cb = (int)(f >> 12);
+                k = 16 * j + 8 * (ln >> 5) + i;
+                n = 32 * cb + (ln & 31);
+            } else {
+                const int i = f & 3, ln = (f >> 2) & 63, j = (f >> 8) & 15, cb = (int)(f >> 12);
+                k = 8 * j + 4 * (ln >> 5) + i;
+                n = 32 * cb + (ln & 31);
+            }
+            const float w = last ? blob[t.skip_w + (int64_t)n * 128 + k]
+                          : n < 128 ? blob[t.res_w + (int64_t)n * 128 + k] : blob[t.skip_w + (int64_t)(n - 128) * 128 + k];
+            if (BF16) ((__bf16*)(img + t.wrs))[f] = (__bf16)w;
+            else ((float*)(img + t.wrs))[f] = w;
+        } else if (e < n_conv + n_rs + 256) {   // conv bias
+            const int c = (int)(e - n_conv - n_rs);
+            ((float*)(img + t.bc))[c] = blob[t.dil_b + c];
+        } else {   // res | skip bias
+            const int c = (int)(e - n_conv - n_rs - 256);
+            ((float*)(img + t.brs))[c] = last ? blob[t.skip_b + c] : c < 128 ? blob[t.res_b + c] : blob[t.skip_b + c - 128];
+        }
+    }
+}
+
+__global__ void scatter_kernel(const float* src, const int64_t* idx, int64_t n, float* dst) {
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) dst[idx[i]] = src[i];
+}
+}  // namespace
+
+hipError_t launch_repack(bool bf16, const float* blob, uint8_t* img, const RepackLayer* tab, int L,
+                         const RepackFixed& fx, hipStream_t st) {
+    const dim3 grid(96, L + 1);
+    if (bf16) hipLaunchKernelGGL(repack_kernel<true>, grid, dim3(256), 0, st, blob, img, tab, L, fx);
+    else hipLaunchKernelGGL(repack_kernel<false>, grid, dim3(256), 0, st, blob, img, tab, L, fx);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const float* src, const int64_t* idx, int64_t n, float* dst, hipStream_t st) {
+    hipLaunchKernelGGL(scatter_kernel, dim3(nblk(n)), dim3(256), 0, st, src, idx, n, dst);
+    return hipGetLastError();
+}
+
 }  // namespace gwd

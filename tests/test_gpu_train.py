@@ -185,6 +185,37 @@ def test_adam_matches_oracle_and_refreshes_weights(g):
     m.close()
 
 
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_adam_refreshes_image_on_device(g, prec):
+    """The working image rebuilt on the device after Adam steps (member 1 of two) equals the one the
+    loader packs from the same master weights on the host: exported weights bit for bit, and the same
+    scores from a forward pass."""
+    from paper_2201_11133_amd import synth
+    print(f"case: adam refresh {prec}", flush=True)
+    blobs = np.stack([synth.full_weights(5), synth.full_weights(6)])
+    n = blobs.shape[1]
+    m = g.Model(g.full_arch(), blobs, prec)
+    rng = np.random.default_rng(3)
+    w = to_dev(blobs[1].copy())
+    gd = to_dev((rng.standard_normal(n) * 1e-2).astype(np.float32))
+    mo = torch.zeros(n, dtype=torch.float32, device="cuda")
+    ve = torch.zeros(n, dtype=torch.float32, device="cuda")
+    norm = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for step in (1, 2):
+        g.check(g.lib.gwd_adam_step(m.h, 1, w.data_ptr(), gd.data_ptr(), mo.data_ptr(), ve.data_ptr(), step, 1e-3,
+                                    0.9, 0.999, 1e-8, norm.data_ptr(), g._stream_handle(None)))
+    torch.cuda.synchronize()
+    wn = w.cpu().numpy()
+    assert not np.array_equal(wn, blobs[1])
+    m2 = g.Model(g.full_arch(), np.stack([blobs[0], wn]), prec)
+    assert np.array_equal(m.export_weights(1), m2.export_weights(1))
+    assert np.array_equal(m.export_weights(0), m2.export_weights(0))
+    x = torch.randn((4096 + 256 * 5, 2), dtype=torch.float32, device="cuda")
+    assert torch.equal(m.forward([x], 4096, 256, 1), m2.forward([x], 4096, 256, 1))
+    m2.close()
+    m.close()
+
+
 def test_bce_kernel(g):
     from oracle.train import bce_grad, bce_logits
     rng = np.random.default_rng(1)
