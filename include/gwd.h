@@ -48,7 +48,8 @@ typedef struct gwd_model gwd_model; /* opaque, library-owned */
 typedef enum {
     GWD_FP32 = 0,     /* fp32 storage and operands; the dilated-conv GEMM accumulates in fp64,
                          the res/skip GEMM in fp32                                          */
-    GWD_BF16 = 1,     /* bf16 operands (RNE), fp32 accumulation, fp32 residual and skip    */
+    GWD_BF16 = 1,     /* bf16 operands (RNE), fp32 accumulation, bf16 residual stream
+                         between layers, fp32 skip sum                                      */
     GWD_FP8_E4M3 = 2, /* OCP E4M3FN operands, per-output-channel weight scales            */
     GWD_FP64 = 3      /* plain member only, training entry points only: everything in fp64
                          (device finite-difference gradient checks)                         */
@@ -128,7 +129,9 @@ typedef struct {
     float prob;
 } gwd_trigger;
 
-/* Number of float parameters of one member in the canonical flat blob
+/* Number of float parameters of one member in the canonical flat blob (the
+ * paper's members are the gated dilated-convolution networks of "AI
+ * architecture", Fig. 1; their widths and depths are this build's reading)
  * (kind 0 with 16 channels: 1,681; kind 1 with 128 channels, 3x10 layers:
  * 2,964,993; kind 2 with two 64-channel branches and a 128-channel head:
  * 1,498,497), or -1 for an invalid descriptor.
@@ -145,19 +148,24 @@ typedef struct {
  *   Kernel tap 0 multiplies x[t - d], tap 1 multiplies x[t]. */
 int64_t gwd_num_params(const gwd_arch* arch);
 
-/* Input samples that influence one output sample: 1 + (kernel-1) * sum of
+/* Input samples that influence one output sample ("AI architecture": stacks
+ * of causal convolutions with doubling dilations): 1 + (kernel-1) * sum of
  * dilations (16 for the plain member, 3070 for the gated and two-branch
  * members), or -1 if invalid. */
 int32_t gwd_receptive_field(const gwd_arch* arch);
 
-/* Copy, pack and (for BF16 / FP8) quantise the weights of n_members members
+/* Build the inference engine of an ensemble once ("Optimization with
+ * TensorRT": one engine per model, half precision where it can be used):
+ * copy, pack and (for BF16 / FP8) quantise the weights of n_members members
  * onto the current device. host_blob holds n_members consecutive blobs of
  * n_params floats each (host memory, read during the call only). BF16 rounds
  * to nearest even; FP8 E4M3 uses one scale per output channel of every
  * weight matrix (max |w| over the channel / 448) and saturates at +/-448.
+ * precision is one of the gwd_precision values (passed as int32_t, so any
+ * other value is an argument error rather than an invalid enumeration).
  * Synchronous. On success *out owns device memory until gwd_free. */
 gwd_status gwd_load_weights(const gwd_arch* arch, int32_t n_members, const float* host_blob,
-                            int64_t n_params, gwd_precision precision, gwd_model** out);
+                            int64_t n_params, int32_t precision, gwd_model** out);
 
 /* Release a model (waits for the device; NULL is ignored). */
 void gwd_free(gwd_model* model);
@@ -358,8 +366,10 @@ gwd_status gwd_whiten(const gwd_stream* src, const double* psd, int32_t nperseg,
  * gwd_backward takes dL/dlogit [B][W] (T) and the same windows and `saved`,
  * and writes dL/dparams (device T [n_params], overwritten, canonical blob
  * order) and, if grad_input is not NULL, dL/dwindows [B][W][2] (T).
- * The gated member's forward uses the model's precision (FP32 or BF16
- * kernels); its backward runs in fp32 against the fp32 master weights. FP8
+ * The gated member's forward and its per-stack recompute use the model's
+ * precision (FP32 or BF16 kernels). For BF16 members the backward's row and
+ * weight-gradient GEMMs take bf16 operands (fp32 accumulation); the gradient
+ * is fp32, against the fp32 master weights. FP8
  * models are inference only (GWD_ERR_UNSUPPORTED). The gated member needs W a
  * multiple of 128. Calls with one model must not overlap (shared workspace). */
 int64_t gwd_saved_bytes(const gwd_model* model, int32_t B, int32_t W);
@@ -442,7 +452,10 @@ const char* gwd_last_error(void);
 
 /* ---- test support ------------------------------------------------------------
  * gwd_debug_layer runs gated layer `layer` of member `member` (kind 1) with
- * the same kernel the forward pass uses, on M = n_windows * window rows of
+ * the model's single-layer kernel (the one the forward uses with one layer
+ * per launch; the default forward fuses three or four layers per launch, see
+ * gwd_debug_fused, and computes every output with the same operations in the
+ * same order), on M = n_windows * window rows of
  * device input x_in [n_windows][window][C] (each window zero-context), and
  * writes the pre-activation a [M][2C] (may be NULL), x_out [M][C] (ignored in
  * the last layer) and updates skip [M][S] in place (skip_inout; it is

@@ -348,7 +348,7 @@ int32_t gwd_receptive_field(const gwd_arch* a) {
 }
 
 gwd_status gwd_load_weights(const gwd_arch* arch, int32_t n_members, const float* host_blob, int64_t n_params,
-                            gwd_precision precision, gwd_model** out) {
+                            int32_t precision_in, gwd_model** out) {
     if (!out) { set_error("gwd_load_weights: out is NULL"); return GWD_ERR_ARG; }
     *out = nullptr;
     if (!arch_valid(arch)) { set_error("gwd_load_weights: invalid architecture"); return GWD_ERR_ARG; }
@@ -356,7 +356,8 @@ gwd_status gwd_load_weights(const gwd_arch* arch, int32_t n_members, const float
     if (!host_blob) { set_error("gwd_load_weights: host_blob is NULL"); return GWD_ERR_ARG; }
     const int64_t np = gwd_num_params(arch);
     if (n_params != np) { set_error("gwd_load_weights: n_params %lld, architecture needs %lld", (long long)n_params, (long long)np); return GWD_ERR_ARG; }
-    if (precision != GWD_FP32 && precision != GWD_BF16 && precision != GWD_FP8_E4M3 && precision != GWD_FP64) { set_error("gwd_load_weights: unknown precision %d", (int)precision); return GWD_ERR_ARG; }
+    if (precision_in != GWD_FP32 && precision_in != GWD_BF16 && precision_in != GWD_FP8_E4M3 && precision_in != GWD_FP64) { set_error("gwd_load_weights: unknown precision %d", (int)precision_in); return GWD_ERR_ARG; }
+    const gwd_precision precision = (gwd_precision)precision_in;
     if (!arch_supported(arch)) { set_error("gwd_load_weights: architecture not supported by the GPU kernels"); return GWD_ERR_UNSUPPORTED; }
     if (arch->kind >= 1 && precision == GWD_FP64) { set_error("gwd_load_weights: FP64 is for the plain member's gradient checks only"); return GWD_ERR_UNSUPPORTED; }
     int ndev = 0;
