@@ -391,6 +391,40 @@ class Trainer:
                                 self.norm.data_ptr(), s))
         return self.loss, self.norm
 
+    # ---- checkpoint and resume: master weights, Adam moments and the step count
+    def save(self, path: str) -> None:
+        """Write a checkpoint (safetensors): fp32 master weights and Adam moments of this member,
+        the step count, and the architecture, precision and batch shape."""
+        import json
+        import torch
+        from safetensors.torch import save_file
+        torch.cuda.synchronize()
+        arch = {n: int(getattr(self.m.arch, n)) for n, _ in Arch._fields_}
+        meta = {"step": str(self.step_no), "member": str(self.member), "B": str(self.B), "T": str(self.T),
+                "precision": self.m.precision, "arch": json.dumps(arch)}
+        save_file({"master": self.master.cpu(), "mom": self.mom.cpu(), "vel": self.vel.cpu()}, path, metadata=meta)
+
+    @classmethod
+    def resume(cls, path: str) -> "Trainer":
+        """A trainer (and its one-member model, trainer.m) continuing from a checkpoint written by
+        save(): the model's working weights are packed from the saved master weights, and the next
+        step is step_no + 1 with the saved moments, so training continues as if uninterrupted."""
+        import json
+        import torch
+        from safetensors import safe_open
+        with safe_open(path, framework="pt") as f:
+            meta = f.metadata()
+            t = {k: f.get_tensor(k) for k in ("master", "mom", "vel")}
+        arch = Arch(**json.loads(meta["arch"]))
+        master = t["master"].numpy()
+        model = Model(arch, master, meta["precision"])
+        tr = cls(model, master, int(meta["B"]), int(meta["T"]), member=0)
+        tr.mom.copy_(t["mom"].to(tr.mom.device))
+        tr.vel.copy_(t["vel"].to(tr.vel.device))
+        tr.step_no = int(meta["step"])
+        torch.cuda.synchronize()
+        return tr
+
 
 class Plan:
     """A captured forward: one graph launch per call, bound to the given stream buffers and output."""
