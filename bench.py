@@ -198,7 +198,7 @@ def ragged_workload(gwd, blobs, prec: str):
                 x[lo:hi] += torch.from_numpy(synth.injection_signal(inj, lo / FS, hi - lo).astype(np.float32)).cuda()
         bufs.append(x)
     m = gwd.Model(gwd.full_arch(), blobs, prec)
-    rows, waves, fuse, batch = m.autotune([bufs[0][: 64 * FS]])
+    rows, waves, fuse, batch, blocks = m.autotune([bufs[0][: 64 * FS]])
     plan = m.plan(bufs, W, S, out_mode=0)
     plan.launch()
     torch.cuda.synchronize()
@@ -215,7 +215,8 @@ def ragged_workload(gwd, blobs, prec: str):
     return {"streams": 32, "stream_seconds_total": round(total_s, 1), "strain_s_per_s": round(total_s / wall, 2),
             "completion_s_p50": round(float(np.percentile(per, 50)) / 1e6, 3),
             "completion_s_p99": round(float(np.percentile(per, 99)) / 1e6, 3),
-            "graph_total_s": round(tot / 1e6, 3), "autotune": {"tile_rows": rows, "waves": waves, "layers_per_launch": fuse, "batch_windows": batch},
+            "graph_total_s": round(tot / 1e6, 3), "autotune": {"tile_rows": rows, "waves": waves, "layers_per_launch": fuse, "batch_windows": batch,
+                                                           "fused_blocks": blocks},
             "triggers": n_trig, "precision": prec}
 
 

@@ -435,17 +435,30 @@ void gwd_plan_free(gwd_plan* plan);
 gwd_status gwd_set_tiling(gwd_model* model, int32_t tile_rows, int32_t waves, int32_t layers_per_launch,
                           int32_t batch_windows);
 
-/* Autotuner: times gwd_forward (out_mode 0) on the given request for every
- * schedule candidate (BF16/FP8: fused triples with the default tiling, and
- * the three tilings one layer per launch; all: batch 256, 512, 1024 windows),
- * keeps
- * the fastest on the model and reports it. If the environment variable
- * GWD_AUTOTUNE_CACHE names a file, a cached choice for the same (architecture,
- * precision, members, window, stride) is used instead of timing, and new
- * choices are appended to it. Synchronises hip_stream. */
+/* Shape of the fused launches (BF16/FP8 gated models): the number of blocks a
+ * launch aims at. Each interleaved sub-sequence of a window is split into
+ * enough segments (each after the first starting with one warm-up chunk that
+ * rebuilds its history rows) for windows x sub-sequences x segments to reach
+ * `blocks`; 0 restores the default, 512 (two blocks per compute unit). The
+ * profiling-based kernel choice of the paper's engine ("Optimization with
+ * TensorRT") is gwd_autotune's, which tries 512, 1024 and 2048. Results do not
+ * depend on it. GWD_ERR_ARG unless blocks is 0 or in [256, 16384];
+ * GWD_ERR_UNSUPPORTED for other models. */
+gwd_status gwd_set_fused_blocks(gwd_model* model, int32_t blocks);
+
+/* Autotuner (the engine's kernel choice by profiling, "Optimization with
+ * TensorRT"): times gwd_forward (out_mode 0) on the given request for every
+ * schedule candidate (BF16/FP8: fused launches aiming at 512, 1024 and 2048
+ * blocks, and the three tilings one layer per launch; all: batch 256, 512,
+ * 1024 windows), keeps the fastest on the model and reports it (*fused_blocks
+ * is 0 for schedules without fused launches; the pointer may be NULL). If the
+ * environment variable GWD_AUTOTUNE_CACHE names a file, a cached choice for the
+ * same (architecture, precision, members, window, stride) is used instead of
+ * timing, and new choices are appended to it. Synchronises hip_stream. */
 gwd_status gwd_autotune(gwd_model* model, const gwd_stream* streams, int32_t n_streams, int32_t window,
                         int32_t stride, float* out, int64_t out_capacity_floats, int32_t* tile_rows,
-                        int32_t* waves, int32_t* layers_per_launch, int32_t* batch_windows, void* hip_stream);
+                        int32_t* waves, int32_t* layers_per_launch, int32_t* batch_windows,
+                        int32_t* fused_blocks, void* hip_stream);
 
 /* Last error message of the calling thread ("" if none). */
 const char* gwd_last_error(void);

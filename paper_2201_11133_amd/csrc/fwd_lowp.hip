@@ -1293,10 +1293,11 @@ static hipError_t launch_fused(gwd_model* m, int member, int l, int nl, const ui
     const int rows = FU_ROWS;                                           // sub-rows per chunk
     const int n_ch = ((T + a.d0 - 1) / a.d0 + rows - 1) / rows;       // chunks of the longest sub-sequence
     if (nl == 4 && n_ch != 1) return hipErrorInvalidValue;              // a quad needs one-chunk sub-sequences
-    // enough blocks for every resident slot (two per CU on 256 CUs); a segment after the first costs
-    // one warm-up chunk, so no more segments than that (more, shorter blocks measured slower)
+    // by default enough blocks for every resident slot (two per CU on 256 CUs); a segment after the
+    // first costs one warm-up chunk; the autotuner may aim at more blocks (gwd_set_fused_blocks)
     const int64_t per = (int64_t)nb * a.d0;
-    const int want = (int)std::min<int64_t>(n_ch, std::max<int64_t>(1, (512 + per - 1) / per));
+    const int64_t target = m->fused_blocks > 0 ? m->fused_blocks : 512;
+    const int want = (int)std::min<int64_t>(n_ch, std::max<int64_t>(1, (target + per - 1) / per));
     a.seg_chunks = (n_ch + want - 1) / want;
     a.n_seg = (n_ch + a.seg_chunks - 1) / a.seg_chunks;
     // the network's first layers take the stream (inference) or a bf16 x0 (training: fb == nullptr)

@@ -103,6 +103,7 @@ struct gwd_model {
     int32_t lp_rows = 0;                       // BF16/FP8 layer tiling: rows per tile (0 = default per precision)
     int32_t lp_waves = 0;                      // and waves per block
     int32_t lp_fuse = 3;                       // BF16: layers per launch (3 = fused triples, 1 = one per launch)
+    int32_t fused_blocks = 0;                  // blocks a fused launch aims at (segments per sub-sequence); 0 = 512
     bool two_branch = false;                   // loaded as kind 2 and expanded to the block-diagonal kind-1 image
     gwd_arch branch_arch{};                    // kind 2: the architecture as loaded
     int64_t branch_params = 0;                 // kind 2: parameters of one member in its own (branch) blob

@@ -170,41 +170,58 @@ gwd_status gwd_set_tiling(gwd_model* m, int32_t tile_rows, int32_t waves, int32_
     return GWD_OK;
 }
 
+gwd_status gwd_set_fused_blocks(gwd_model* m, int32_t blocks) {
+    if (!m) { set_error("gwd_set_fused_blocks: model is NULL"); return GWD_ERR_ARG; }
+    if (!(m->arch.kind == 1 && (m->prec == GWD_BF16 || m->prec == GWD_FP8_E4M3))) {
+        set_error("gwd_set_fused_blocks: fused launches are for gated BF16/FP8 models");
+        return GWD_ERR_UNSUPPORTED;
+    }
+    if (!(blocks == 0 || (blocks >= 256 && blocks <= 16384))) { set_error("gwd_set_fused_blocks: blocks %d not 0 or in [256, 16384]", blocks); return GWD_ERR_ARG; }
+    m->fused_blocks = blocks;
+    return GWD_OK;
+}
+
 namespace {
 struct Sched {
-    int rows, waves, fuse;
+    int rows, waves, fuse, blocks;
 };
 }  // namespace
 
 gwd_status gwd_autotune(gwd_model* m, const gwd_stream* streams, int32_t n_streams, int32_t window, int32_t stride,
                         float* out, int64_t out_capacity_floats, int32_t* rows_out, int32_t* waves_out,
-                        int32_t* fuse_out, int32_t* batch_out, void* hip_stream) {
+                        int32_t* fuse_out, int32_t* batch_out, int32_t* blocks_out, void* hip_stream) {
     if (!m || !rows_out || !waves_out || !fuse_out || !batch_out) { set_error("gwd_autotune: NULL argument"); return GWD_ERR_ARG; }
     hipStream_t st = (hipStream_t)hip_stream;
     const char* cache = getenv("GWD_AUTOTUNE_CACHE");
     char key[160];
     snprintf(key, sizeof key, "gfx950 kind%d prec%d members%d W%d S%d", m->arch.kind, (int)m->prec, m->n_members,
              window, stride);
-    if (cache) {  // "key rows waves layers_per_launch batch" lines
+    const bool lowp = m->arch.kind == 1 && (m->prec == GWD_BF16 || m->prec == GWD_FP8_E4M3);
+    if (cache) {  // "key rows waves layers_per_launch batch fused_blocks" lines
         if (FILE* f = fopen(cache, "r")) {
             char line[256];
             while (fgets(line, sizeof line, f)) {
-                int rw = 0, w = 0, fu = 0, b = 0;
+                int rw = 0, w = 0, fu = 0, b = 0, fb = 0;
                 const size_t kl = strlen(key);
                 if (strncmp(line, key, kl) == 0 && line[kl] == ' ' &&
-                    sscanf(line + kl, " %d %d %d %d", &rw, &w, &fu, &b) == 4) {
+                    sscanf(line + kl, " %d %d %d %d %d", &rw, &w, &fu, &b, &fb) >= 4) {
                     fclose(f);
                     gwd_status s = gwd_set_tiling(m, rw, w, fu, b);
-                    if (s == GWD_OK) { *rows_out = rw; *waves_out = w; *fuse_out = fu; *batch_out = b; }
+                    if (s == GWD_OK && lowp) s = gwd_set_fused_blocks(m, fb);
+                    if (s == GWD_OK) {
+                        *rows_out = rw; *waves_out = w; *fuse_out = fu; *batch_out = b;
+                        if (blocks_out) *blocks_out = fb;
+                    }
                     return s;
                 }
             }
             fclose(f);
         }
     }
-    std::vector<Sched> cand = {{0, 0, 1}};
-    if (m->arch.kind == 1 && (m->prec == GWD_BF16 || m->prec == GWD_FP8_E4M3))
-        cand = {{64, 4, 3}, {64, 4, 1}, {64, 8, 1}, {128, 4, 1}};
+    // candidates: fused launches (64-row chunks, 4 waves) aiming at 512, 1024 or 2048 blocks, and one
+    // layer per launch in each tiling; each at three batch sizes
+    std::vector<Sched> cand = {{0, 0, 1, 0}};
+    if (lowp) cand = {{64, 4, 3, 512}, {64, 4, 3, 1024}, {64, 4, 3, 2048}, {64, 4, 1, 0}, {64, 8, 1, 0}, {128, 4, 1, 0}};
     const int batch_opts[] = {256, 512, 1024};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipSetDevice(m->device);
@@ -212,7 +229,7 @@ gwd_status gwd_autotune(gwd_model* m, const gwd_stream* streams, int32_t n_strea
     if (e == hipSuccess) e = hipEventCreate(&e1);
     if (e != hipSuccess) return hip_fail(e, "autotune events");
     float best = 1e30f;
-    Sched bs{m->lp_rows, m->lp_waves, m->lp_fuse};
+    Sched bs{m->lp_rows, m->lp_waves, m->lp_fuse, m->fused_blocks};
     int bb = m->batch_windows;
     gwd_status s = GWD_OK;
     for (const Sched& c : cand) {
@@ -220,6 +237,7 @@ gwd_status gwd_autotune(gwd_model* m, const gwd_stream* streams, int32_t n_strea
             m->lp_rows = c.rows;
             m->lp_waves = c.waves;
             m->lp_fuse = c.fuse;
+            m->fused_blocks = c.blocks;
             m->batch_windows = b;
             s = gwd_forward(m, streams, n_streams, window, stride, 0, out, out_capacity_floats, st);  // warm-up
             if (s != GWD_OK) break;
@@ -241,14 +259,16 @@ gwd_status gwd_autotune(gwd_model* m, const gwd_stream* streams, int32_t n_strea
     m->lp_rows = bs.rows;
     m->lp_waves = bs.waves;
     m->lp_fuse = bs.fuse;
+    m->fused_blocks = bs.blocks;
     m->batch_windows = bb;
     *rows_out = bs.rows;
     *waves_out = bs.waves;
     *fuse_out = bs.fuse;
     *batch_out = bb;
+    if (blocks_out) *blocks_out = bs.blocks;
     if (cache) {
         if (FILE* f = fopen(cache, "a")) {
-            fprintf(f, "%s %d %d %d %d\n", key, bs.rows, bs.waves, bs.fuse, bb);
+            fprintf(f, "%s %d %d %d %d %d\n", key, bs.rows, bs.waves, bs.fuse, bb, bs.blocks);
             fclose(f);
         }
     }

@@ -75,6 +75,13 @@ def test_tilings_and_batches_do_not_change_results(g, prec):
                 if ref is None:
                     ref = e
                 assert torch.equal(e, ref), (fuse, rows, waves, nb)
+    # fused launches aiming at more blocks: more segments per sub-sequence, each after a warm-up chunk
+    for blocks in (1024, 2048, 8192):
+        m.set_fused_blocks(blocks)
+        for nb in (64, 512):
+            m.set_tiling(64, 4, nb, 3)
+            assert torch.equal(m.forward(xs, 4096, 256, 1), ref), (blocks, nb)
+    m.set_fused_blocks(0)
     m.close()
 
 
@@ -84,11 +91,13 @@ def test_autotune_picks_a_valid_tiling(g, tmp_path, monkeypatch):
     monkeypatch.setenv("GWD_AUTOTUNE_CACHE", str(cache))
     m = g.Model(g.full_arch(), synth.full_weights(11), "bf16")
     x = to_dev(synth.make_stream(311, 40.0, 1)[0])
-    rw, w, fu, b = m.autotune([x])
+    rw, w, fu, b, fb = m.autotune([x])
     assert (rw, w) in TILINGS and fu in (1, 3) and b in (256, 512, 1024)
-    assert cache.read_text().strip().endswith(f"{rw} {w} {fu} {b}")
+    assert fb in ((512, 1024, 2048) if fu == 3 else (0,))
+    assert cache.read_text().strip().endswith(f"{rw} {w} {fu} {b} {fb}")
+    print(f"autotuned: rows {rw}, waves {w}, layers per launch {fu}, batch {b}, fused blocks {fb}", flush=True)
     # second call reads the cache
-    assert m.autotune([x]) == (rw, w, fu, b)
+    assert m.autotune([x]) == (rw, w, fu, b, fb)
     m.close()
 
 
