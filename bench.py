@@ -39,7 +39,7 @@ PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
 # HBM bytes per launch of the middle BF16 gated layer (512 windows), from two rocprofv3 --pmc runs
 # (FETCH_SIZE, WRITE_SIZE) scaled by a 1 GiB copy; valid only for the kernel source they were taken on
 # (profiles/gated_layer_bf16_hbm_traffic_64s.md).
-MEASURED_TRAFFIC = {"bf16": {"source_sha256_16": "03deb27bd8211f87", "bytes": 3231332745, "windows": 512, "layers": 3}}
+MEASURED_TRAFFIC = {"bf16": {"source_sha256_16": "42a36af860241b4a", "bytes": 3202711959, "windows": 512, "layers": 3}}
 
 
 def kernel_traffic(prec: str, windows: int, layers: int):
