@@ -353,11 +353,12 @@ def whitening_workload(gwd, seconds: float = 4096.0, nperseg: int = 16384, reps:
             "output_std": sd}
 
 
-def train_workload(gwd, steps: int = 2, B: int = 256):
+def train_workload(gwd, steps: int = 2, B: int = 256, curve_steps: int = 60):
     """Training of one full-size member: BF16 forward with per-stack checkpoints, BCE on logits,
     hand-written backward (bf16-operand row and weight-gradient GEMMs, fp32 accumulation), Adam on fp32 master
     weights; batches of 256 windows of 2 x 4096,
-    half of them chirped (SNR 8-20), labels 1 within 0.1 s of the coalescence time."""
+    half of them chirped (SNR 8-20), labels 1 within 0.1 s of the coalescence time. Then the loss
+    curve of a fresh member over curve_steps steps on fresh seeded batches."""
     import torch
     from paper_2201_11133_amd import synth
     blob = synth.full_weights(4)
@@ -376,8 +377,24 @@ def train_workload(gwd, steps: int = 2, B: int = 256):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     m.close()
+    # loss curve: a fresh member trained on fresh batches (seeded), the mean loss of every 10 steps
+    m = gwd.Model(gwd.full_arch(), blob, "bf16")
+    tr = gwd.Trainer(m, blob, B, W)
+    curve, acc = [], []
+    for step in range(curve_steps):
+        xb, ib = synth.make_windows(5000 + step, B, B // 2)
+        yb = np.zeros((B, W), np.float32)
+        for i, inj in ib:
+            yb[i] = synth.box_labels(W, inj.tc)
+        acc.append(float(tr.step(torch.from_numpy(xb).cuda(), torch.from_numpy(yb).cuda())[0].item()))
+        if len(acc) == 10:
+            curve.append(round(float(np.mean(acc)), 4))
+            acc = []
+    m.close()
     return {"train_windows_per_s": round(B / dt, 1), "s_per_step": round(dt, 3), "batch": B,
             "loss": round(float(loss.item()), 5), "grad_norm": round(float(norm.item()), 5),
+            "loss_curve": {"steps": curve_steps, "mean_loss_per_10_steps": curve,
+                           "data": "fresh seeded batches of 256 windows per step, half chirped"},
             "precision": "bf16 forward and recompute, bf16-operand row and weight-gradient GEMMs in the "
                          "backward (fp32 accumulation), fp32 master weights and Adam"}
 
