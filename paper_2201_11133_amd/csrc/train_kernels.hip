@@ -89,7 +89,6 @@ __global__ __launch_bounds__(256) void gemm_rows_kernel(GemmRowsArgs a) {
 // L2; A rows are read from HBM once per 64 x 128 output tile and rounded to bf16 as they are staged.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx8 __attribute__((ext_vector_type(8)));
-constexpr int BR = 64;        // rows per block
 constexpr int BN = 128;       // columns per block
 constexpr int BK = 64;        // k per staged chunk
 constexpr int AROW = BK + 8;  // bf16 per LDS row (144 B: conflict-free 16-byte fragment reads)
@@ -112,63 +111,104 @@ __device__ inline uint4 bf16_pack8(float4 lo, float4 hi) {
     return __builtin_bit_cast(uint4, __builtin_convertvector(f, bf16x8));
 }
 
+// One block: 128 rows x 128 columns; wave (wr, wc) owns rows 64 wr .. + 64 (two row blocks) and columns
+// 64 wc .. + 64 (two column tiles), so each B fragment feeds two products and each A fragment two.
+// The next chunk's A rows are requested before the current chunk's products, and the chunk's B
+// fragments before its staging barrier. Products per output in k order (part by part, chunk by
+// chunk, 16-k steps ascending).
+constexpr int BR2 = 128;      // rows per block
+
+__device__ inline void rows_chunk(const GemmRowsArgs& a, int ci, int& p, int& k0) {
+    const int n0 = a.A[0].K / BK;
+    p = ci < n0 ? 0 : 1;
+    k0 = BK * (ci < n0 ? ci : ci - n0);
+}
+
 __global__ __launch_bounds__(256) void gemm_rows_bf16_kernel(GemmRowsArgs a, int Ktot) {
-    __shared__ __attribute__((aligned(16))) uint16_t As[BR * AROW];
+    __shared__ __attribute__((aligned(16))) uint16_t As[BR2 * AROW];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = wave & 1, wc = wave >> 1;  // wave: rows 32 wr, columns 64 wc (two 32-column tiles)
+    const int wr = wave & 1, wc = wave >> 1;
     const int r = lane & 31, h = lane >> 5;
     const int ntn = a.N / BN;
-    const int64_t row0 = (int64_t)(blockIdx.x / ntn) * BR;
+    const int64_t row0 = (int64_t)(blockIdx.x / ntn) * BR2;
     const int col0 = (blockIdx.x % ntn) * BN;
-    const int rr = tid >> 2, kq = 16 * (tid & 3);  // staging: 16 consecutive k of one row
-    const uint16_t* bcol0 = a.bt + (int64_t)(col0 + 64 * wc + r) * Ktot + 8 * h;
-    floatx16 acc[2] = {};
-    int kbase = 0;
-    for (int p = 0; p < a.nparts; ++p) {
+    const int rr = tid >> 1, kq = 32 * (tid & 1);  // staging: 32 consecutive k of one row per chunk
+    int64_t src[2];
+    for (int p = 0; p < 2; ++p) src[p] = p < a.nparts ? part_row(a.A[p], row0 + rr, a.T) : -1;
+    const int nch = Ktot / BK;
+    auto load_raw = [&](int ci, uint4 (&raw)[8]) {
+        int p, k0;
+        rows_chunk(a, ci, p, k0);
         const APart& ap = a.A[p];
-        const int64_t src = part_row(ap, row0 + rr, a.T);
-        const float* arow = src < 0 || ap.p16 ? nullptr : ap.ptr + src * ap.ld + kq;
-        const uint16_t* arow16 = src < 0 || !ap.p16 ? nullptr : ap.p16 + src * ap.ld + kq;
-        for (int k0 = 0; k0 < ap.K; k0 += BK) {
-            uint4 w0 = make_uint4(0, 0, 0, 0), w1 = w0;
-            if (arow) {
-                const float4* q4 = (const float4*)(arow + k0);
-                w0 = bf16_pack8(q4[0], q4[1]);
-                w1 = bf16_pack8(q4[2], q4[3]);
-            } else if (arow16) {  // already bf16
-                w0 = *(const uint4*)(arow16 + k0);
-                w1 = *(const uint4*)(arow16 + k0 + 8);
-            }
-            __syncthreads();  // the previous chunk's fragments are read
-            *(uint4*)&As[rr * AROW + kq] = w0;
-            *(uint4*)&As[rr * AROW + kq + 8] = w1;
-            __syncthreads();
 #pragma unroll
-            for (int s4 = 0; s4 < BK / 16; ++s4) {
-                const bf16x8 av = *(const bf16x8*)&As[(32 * wr + r) * AROW + 16 * s4 + 8 * h];
+        for (int i = 0; i < 8; ++i) raw[i] = make_uint4(0, 0, 0, 0);
+        if (src[p] < 0) return;
+        if (ap.p16) {
+            const uint4* q = (const uint4*)(ap.p16 + src[p] * ap.ld + k0 + kq);
 #pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    const bf16x8 bv = *(const bf16x8*)(bcol0 + (int64_t)32 * c * Ktot + kbase + k0 + 16 * s4);
-                    acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[c], 0, 0, 0);
-                }
-            }
+            for (int i = 0; i < 4; ++i) raw[i] = q[i];
+        } else {
+            const uint4* q = (const uint4*)(ap.ptr + src[p] * ap.ld + k0 + kq);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) raw[i] = q[i];
         }
-        kbase += ap.K;
+    };
+    const uint16_t* bcol = a.bt + (int64_t)(col0 + 64 * wc + r) * Ktot + 8 * h;
+    floatx16 acc[2][2] = {};
+    uint4 raw[8];
+    load_raw(0, raw);
+    for (int ci = 0; ci < nch; ++ci) {
+        int p, k0;
+        rows_chunk(a, ci, p, k0);
+        const bool is16 = a.A[p].p16 != nullptr;
+        const int kb = BK * ci;   // the chunk's first k in the stacked B
+        bf16x8 bf[4][2];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) bf[s4][c] = *(const bf16x8*)(bcol + (int64_t)32 * c * Ktot + kb + 16 * s4);
+        uint4 w[4];
+        if (is16) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) w[i] = raw[i];
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                w[i] = bf16_pack8(__builtin_bit_cast(float4, raw[2 * i]), __builtin_bit_cast(float4, raw[2 * i + 1]));
+        }
+        __syncthreads();  // the previous chunk's fragments are read
+#pragma unroll
+        for (int i = 0; i < 4; ++i) *(uint4*)&As[rr * AROW + kq + 8 * i] = w[i];
+        __syncthreads();
+        if (ci + 1 < nch) load_raw(ci + 1, raw);   // in flight during this chunk's products
+#pragma unroll
+        for (int s4 = 0; s4 < BK / 16; ++s4) {
+            bf16x8 av[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) av[i] = *(const bf16x8*)&As[(64 * wr + 32 * i + r) * AROW + 16 * s4 + 8 * h];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+                    acc[i][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bf[s4][c], acc[i][c], 0, 0, 0);
+        }
     }
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const int n = col0 + 64 * wc + 32 * c + r;
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int64_t row = row0 + 32 * wr + 8 * (i >> 2) + 4 * h + (i & 3);
-            const int64_t o = row * a.ldc + n;
-            float v = acc[c][i];
-            if (a.bias) v += a.bias[n];
-            if (a.beta != 0.f) v += a.beta * a.C[o];
-            if (a.mask) v = (a.mask[row * a.ldm + n] > 0.f) ? v : 0.f;
-            a.C[o] = v;
+        for (int c = 0; c < 2; ++c) {
+            const int n = col0 + 64 * wc + 32 * c + r;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int64_t row = row0 + 64 * wr + 32 * i + 8 * (e >> 2) + 4 * h + (e & 3);
+                const int64_t o = row * a.ldc + n;
+                float v = acc[i][c][e];
+                if (a.bias) v += a.bias[n];
+                if (a.beta != 0.f) v += a.beta * a.C[o];
+                if (a.mask) v = (a.mask[row * a.ldm + n] > 0.f) ? v : 0.f;
+                a.C[o] = v;
+            }
         }
-    }
 }
 
 // Block -> (output tile, row chunk) of the weight-gradient GEMMs. Blocks are dispatched round-robin
@@ -644,7 +684,7 @@ __global__ __launch_bounds__(256) void mean_final_kernel(const double* part, int
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 hipError_t gemm_rows(const GemmRowsArgs& a, hipStream_t st) {
-    bool bf16 = a.bt != nullptr && a.N % BN == 0 && a.M % BR == 0;
+    bool bf16 = a.bt != nullptr && a.N % BN == 0 && a.M % BR2 == 0 && a.nparts <= 2;
     bool any16 = false;
     int Ktot = 0;
     for (int p = 0; p < a.nparts; ++p) {
@@ -660,7 +700,7 @@ hipError_t gemm_rows(const GemmRowsArgs& a, hipStream_t st) {
                            Ktot);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(gemm_rows_bf16_kernel, dim3((unsigned)((a.M / BR) * (a.N / BN))), dim3(256), 0, st, a,
+        hipLaunchKernelGGL(gemm_rows_bf16_kernel, dim3((unsigned)((a.M / BR2) * (a.N / BN))), dim3(256), 0, st, a,
                            Ktot);
         return hipGetLastError();
     }
