@@ -230,12 +230,16 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
             }
             g.M = M; g.N = kC; g.T = T; g.C = DG; g.ldc = kC;
             g.bt = BT;
-            HIPCHK(gemm_rows(g, st), "dg");
-            // BF16/FP8 members: g and dpre in bf16 (the GEMMs that read them round to bf16 anyway)
+            // BF16/FP8 members: g and dpre in bf16 (the GEMMs that read them round to bf16 anyway),
+            // formed in the dg GEMM's epilogue (dg itself is stored only when captured)
             uint16_t* G16 = BT ? (uint16_t*)G : nullptr;
             uint16_t* DPRE16 = BT ? (uint16_t*)DPRE : nullptr;
-            if (BT) HIPCHK(launch_gate_bwd16(pre, DG, M, G16, DPRE16, st), "gate bwd");
-            else HIPCHK(launch_gate_bwd(pre, DG, M, G, DPRE, st), "gate bwd");
+            if (BT) {
+                g.gpre = pre; g.g16 = G16; g.dpre16 = DPRE16;
+                if (!cap) g.C = nullptr;
+            }
+            HIPCHK(gemm_rows(g, st), "dg");
+            if (!BT) HIPCHK(launch_gate_bwd(pre, DG, M, G, DPRE, st), "gate bwd");
             if (cap) {
                 HIPCHK(capture(cap[4], DG, M * kC, false, st), "capture dg");
                 HIPCHK(capture(cap[5], BT ? (const void*)G16 : G, M * kC, BT != nullptr, st), "capture g");

@@ -33,6 +33,12 @@ struct GemmRowsArgs {
     const float* mask;   // optional: C = 0 where mask <= 0
     int64_t ldm;
     uint16_t* bt;        // optional scratch (N x sum K bf16): set = bf16 operands, fp32 accumulation
+    // optional gate-backward epilogue (bf16-operand kernel, N = 128): C is dg; from the pre-activations
+    // gpre [M][256] it writes g16 = bf16(tanh sigma) [M][128] and dpre16 [M][256] as the gate backward
+    // does; C may then be null (dg not stored)
+    const float* gpre;
+    uint16_t* g16;
+    uint16_t* dpre16;
 };
 
 struct WgradArgs {
@@ -63,7 +69,6 @@ hipError_t launch_input_proj(const float* u, int64_t M, const float* w_in, const
                              hipStream_t st);
 hipError_t launch_gate_bwd(const float* pre, const float* dg, int64_t M, float* g, float* dpre, hipStream_t st);
 // the same with g and dpre rounded to bf16 (round to nearest even), for the bf16-operand backward
-hipError_t launch_gate_bwd16(const float* pre, const float* dg, int64_t M, uint16_t* g, uint16_t* dpre, hipStream_t st);
 // dst[n * dst_stride] += sum_rows X[row][n] for bf16 X (N % 4 == 0, N <= 1024, ldx % 4 == 0)
 hipError_t colsum16(const uint16_t* X, int64_t ldx, int64_t M, int N, float* part, int64_t part_capacity, float* dst,
                     int64_t dst_stride, hipStream_t st);

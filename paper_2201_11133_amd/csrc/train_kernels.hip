@@ -85,30 +85,50 @@ __global__ __launch_bounds__(256) void gemm_rows_kernel(GemmRowsArgs a) {
 }
 
 // ---- the same row GEMM with bf16 operands (fp32 accumulation), for BF16/FP8 models: B is packed
-// once per call into bt[n][k] (parts stacked along k), so a lane's B fragment is one 16-byte load from
-// L2; A rows are read from HBM once per 64 x 128 output tile and rounded to bf16 as they are staged.
+// once per call into bt in MFMA fragment order (parts stacked along k), so a wave's B fragment is one
+// 1 KB load from L2; A rows are read from HBM once per 128 x 128 output tile and rounded to bf16 as
+// they are staged.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx8 __attribute__((ext_vector_type(8)));
 constexpr int BN = 128;       // columns per block
 constexpr int BK = 64;        // k per staged chunk
 constexpr int AROW = BK + 8;  // bf16 per LDS row (144 B: conflict-free 16-byte fragment reads)
 
+// Gate backward of one (row, channel c): from the pre-activations (filter pf, gate pg) and dg, the
+// gate output g = tanh(pf) sigma(pg) and dpre for both halves, in bf16 (the dg GEMM's epilogue).
+__device__ inline void gate_bwd_one(float pf, float pg, float d, uint16_t& g, uint16_t& df, uint16_t& dgt) {
+    const float th = tanhf(pf), sg = 1.f / (1.f + expf(-pg));
+    g = __builtin_bit_cast(uint16_t, (__bf16)(th * sg));
+    df = __builtin_bit_cast(uint16_t, (__bf16)(d * sg * (1.f - th * th)));
+    dgt = __builtin_bit_cast(uint16_t, (__bf16)(d * th * sg * (1.f - sg)));
+}
+
+// bt in MFMA fragment order: the 16-byte fragment of lane (h, r) for column tile nt (32 columns) and
+// k step ks (16 k) sits at fragment index (nt Ktot / 16 + ks) 64 + 32 h + r and holds B(k, 32 nt + r)
+// for k = 16 ks + 8 h .. + 8, so a wave's fragment load is 1 KB of consecutive bytes.
 __global__ __launch_bounds__(256) void pack_bt_kernel(GemmRowsArgs a, int Ktot) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;  // i = n Ktot + k
     if (i >= (int64_t)a.N * Ktot) return;
     const int n = (int)(i / Ktot);
-    int k = (int)(i - (int64_t)n * Ktot), p = 0;
+    const int kk = (int)(i - (int64_t)n * Ktot);
+    int k = kk, p = 0;
     while (p + 1 < a.nparts && k >= a.A[p].K) {
         k -= a.A[p].K;
         ++p;
     }
     const BPart& bp = a.B[p];
-    a.bt[i] = __builtin_bit_cast(uint16_t, (__bf16)bp.ptr[(int64_t)k * bp.ld + (int64_t)n * bp.es]);
+    const int64_t f = ((int64_t)(n >> 5) * (Ktot >> 4) + (kk >> 4)) * 64 + ((kk >> 3) & 1) * 32 + (n & 31);
+    a.bt[f * 8 + (kk & 7)] = __builtin_bit_cast(uint16_t, (__bf16)bp.ptr[(int64_t)k * bp.ld + (int64_t)n * bp.es]);
 }
 
 __device__ inline uint4 bf16_pack8(float4 lo, float4 hi) {
     const floatx8 f = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
     return __builtin_bit_cast(uint4, __builtin_convertvector(f, bf16x8));
+}
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+__device__ inline uint2 bf16_pack4(float4 v) {
+    return __builtin_bit_cast(uint2, __builtin_convertvector(__builtin_bit_cast(floatx4, v), bf16x4));
 }
 
 // One block: 128 rows x 128 columns; wave (wr, wc) owns rows 64 wr .. + 64 (two row blocks) and columns
@@ -124,36 +144,63 @@ __device__ inline void rows_chunk(const GemmRowsArgs& a, int ci, int& p, int& k0
     k0 = BK * (ci < n0 ? ci : ci - n0);
 }
 
+constexpr int EP = BN + 4;     // floats per row of the epilogue's LDS stage
+constexpr int ROWS_LDS = (64 * EP * 4 > BR2 * AROW * 2) ? 64 * EP * 4 : BR2 * AROW * 2;
+
 __global__ __launch_bounds__(256) void gemm_rows_bf16_kernel(GemmRowsArgs a, int Ktot) {
-    __shared__ __attribute__((aligned(16))) uint16_t As[BR2 * AROW];
+    __shared__ __attribute__((aligned(16))) uint8_t smem[ROWS_LDS];
+    uint16_t* As = (uint16_t*)smem;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave & 1, wc = wave >> 1;
     const int r = lane & 31, h = lane >> 5;
     const int ntn = a.N / BN;
     const int64_t row0 = (int64_t)(blockIdx.x / ntn) * BR2;
     const int col0 = (blockIdx.x % ntn) * BN;
-    const int rr = tid >> 1, kq = 32 * (tid & 1);  // staging: 32 consecutive k of one row per chunk
-    int64_t src[2];
-    for (int p = 0; p < 2; ++p) src[p] = p < a.nparts ? part_row(a.A[p], row0 + rr, a.T) : -1;
+    // staging of one chunk (64 k) of the block's 128 rows: thread tid stages block rows tid / 8 + 32 i
+    // (i < 4), 16 bytes at column group tid % 8 of every 128 bytes of the row, so each load instruction
+    // covers whole 128-byte lines (bf16 parts one load per row, fp32 parts two). tw[i]: the row's time
+    // step in its window, for the shifted parts' zero rows.
+    const int64_t b0 = row0 / a.T;
+    const int t0 = (int)(row0 - b0 * a.T);
+    const int sr = tid >> 3, sc = tid & 7;
+    int tw[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        int t = t0 + sr + 32 * i;
+        while (t >= a.T) t -= a.T;
+        tw[i] = t;
+    }
     const int nch = Ktot / BK;
+    // rows whose shifted source leaves the window read the (valid) unshifted row and are set to zero
     auto load_raw = [&](int ci, uint4 (&raw)[8]) {
         int p, k0;
         rows_chunk(a, ci, p, k0);
         const APart& ap = a.A[p];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) raw[i] = make_uint4(0, 0, 0, 0);
-        if (src[p] < 0) return;
+        const int sh = ap.shift;
         if (ap.p16) {
-            const uint4* q = (const uint4*)(ap.p16 + src[p] * ap.ld + k0 + kq);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) raw[i] = q[i];
+            for (int i = 0; i < 4; ++i) {
+                const bool ok = (unsigned)(tw[i] + sh) < (unsigned)a.T;
+                const int64_t row = row0 + sr + 32 * i + (ok ? sh : 0);
+                const uint4 v = *(const uint4*)(ap.p16 + row * ap.ld + k0 + 8 * sc);
+                raw[i] = ok ? v : make_uint4(0, 0, 0, 0);
+            }
         } else {
-            const uint4* q = (const uint4*)(ap.ptr + src[p] * ap.ld + k0 + kq);
 #pragma unroll
-            for (int i = 0; i < 8; ++i) raw[i] = q[i];
+            for (int i = 0; i < 4; ++i) {
+                const bool ok = (unsigned)(tw[i] + sh) < (unsigned)a.T;
+                const int64_t row = row0 + sr + 32 * i + (ok ? sh : 0);
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const uint4 v = *(const uint4*)(ap.ptr + row * ap.ld + k0 + 4 * sc + 32 * j);
+                    raw[2 * i + j] = ok ? v : make_uint4(0, 0, 0, 0);
+                }
+            }
         }
     };
-    const uint16_t* bcol = a.bt + (int64_t)(col0 + 64 * wc + r) * Ktot + 8 * h;
+    // this wave's B fragments: column tile (col0 + 64 wc) / 32 + c, k step ks at + ks 64 fragments
+    const uint16_t* bfr = a.bt + ((int64_t)((col0 + 64 * wc) >> 5) * (Ktot >> 4) * 64 + lane) * 8;
+    const int64_t ctile = (int64_t)(Ktot >> 4) * 64 * 8;   // elements per column tile
     floatx16 acc[2][2] = {};
     uint4 raw[8];
     load_raw(0, raw);
@@ -161,24 +208,23 @@ __global__ __launch_bounds__(256) void gemm_rows_bf16_kernel(GemmRowsArgs a, int
         int p, k0;
         rows_chunk(a, ci, p, k0);
         const bool is16 = a.A[p].p16 != nullptr;
-        const int kb = BK * ci;   // the chunk's first k in the stacked B
         bf16x8 bf[4][2];
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
-            for (int c = 0; c < 2; ++c) bf[s4][c] = *(const bf16x8*)(bcol + (int64_t)32 * c * Ktot + kb + 16 * s4);
-        uint4 w[4];
+            for (int c = 0; c < 2; ++c) bf[s4][c] = *(const bf16x8*)(bfr + c * ctile + (int64_t)(4 * ci + s4) * 64 * 8);
+        __syncthreads();  // the previous chunk's fragments are read
         if (is16) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) w[i] = raw[i];
+            for (int i = 0; i < 4; ++i) *(uint4*)&As[(sr + 32 * i) * AROW + 8 * sc] = raw[i];
         } else {
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                w[i] = bf16_pack8(__builtin_bit_cast(float4, raw[2 * i]), __builtin_bit_cast(float4, raw[2 * i + 1]));
-        }
-        __syncthreads();  // the previous chunk's fragments are read
 #pragma unroll
-        for (int i = 0; i < 4; ++i) *(uint4*)&As[rr * AROW + kq + 8 * i] = w[i];
+                for (int j = 0; j < 2; ++j)
+                    *(uint2*)&As[(sr + 32 * i) * AROW + 4 * sc + 32 * j] =
+                        bf16_pack4(__builtin_bit_cast(float4, raw[2 * i + j]));
+        }
         __syncthreads();
         if (ci + 1 < nch) load_raw(ci + 1, raw);   // in flight during this chunk's products
 #pragma unroll
@@ -192,6 +238,52 @@ __global__ __launch_bounds__(256) void gemm_rows_bf16_kernel(GemmRowsArgs a, int
                 for (int c = 0; c < 2; ++c)
                     acc[i][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bf[s4][c], acc[i][c], 0, 0, 0);
         }
+    }
+    if (a.gpre) {
+        // gate-backward epilogue (N = 128, one column block): dg staged through LDS 64 rows at a time,
+        // then each thread takes 4 consecutive channels of a row with 16-byte loads of the
+        // pre-activations
+        float* Ep = (float*)smem;
+        for (int pass = 0; pass < 2; ++pass) {
+            __syncthreads();  // the products' (or the previous pass's) LDS reads are done
+            if (wr == pass) {
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c)
+#pragma unroll
+                        for (int e = 0; e < 16; ++e)
+                            Ep[(32 * i + 8 * (e >> 2) + 4 * h + (e & 3)) * EP + 64 * wc + 32 * c + r] = acc[i][c][e];
+            }
+            __syncthreads();
+            const int cq = 4 * (tid & 31);
+            float4 pf[8], pg[8];
+#pragma unroll
+            for (int it = 0; it < 8; ++it) {
+                const int64_t row = row0 + 64 * pass + 8 * it + (tid >> 5);
+                pf[it] = *(const float4*)(a.gpre + row * 2 * kC + cq);
+                pg[it] = *(const float4*)(a.gpre + row * 2 * kC + kC + cq);
+            }
+#pragma unroll
+            for (int it = 0; it < 8; ++it) {
+                const int rl = 8 * it + (tid >> 5);
+                const int64_t row = row0 + 64 * pass + rl;
+                const float4 d = *(const float4*)&Ep[rl * EP + cq];
+                const float fv[4] = {pf[it].x, pf[it].y, pf[it].z, pf[it].w};
+                const float gv[4] = {pg[it].x, pg[it].y, pg[it].z, pg[it].w};
+                const float dv[4] = {d.x, d.y, d.z, d.w};
+                uint16_t go[4], fo[4], so[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) gate_bwd_one(fv[j], gv[j], dv[j], go[j], fo[j], so[j]);
+                *(uint2*)(a.g16 + row * kC + cq) = make_uint2(go[0] | ((uint32_t)go[1] << 16), go[2] | ((uint32_t)go[3] << 16));
+                *(uint2*)(a.dpre16 + row * 2 * kC + cq) =
+                    make_uint2(fo[0] | ((uint32_t)fo[1] << 16), fo[2] | ((uint32_t)fo[3] << 16));
+                *(uint2*)(a.dpre16 + row * 2 * kC + kC + cq) =
+                    make_uint2(so[0] | ((uint32_t)so[1] << 16), so[2] | ((uint32_t)so[3] << 16));
+                if (a.C) *(float4*)(a.C + row * a.ldc + cq) = d;
+            }
+        }
+        return;
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -547,20 +639,6 @@ __global__ __launch_bounds__(256) void gate_bwd_kernel(const float* pre, const f
     dpre[row * 2 * kC + kC + c] = d * th * sg * (1.f - sg);
 }
 
-__global__ __launch_bounds__(256) void gate_bwd16_kernel(const float* pre, const float* dg, int64_t M, uint16_t* g,
-                                                         uint16_t* dpre) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= M * kC) return;
-    const int64_t row = i / kC;
-    const int c = (int)(i % kC);
-    const float pf = pre[row * 2 * kC + c], pg = pre[row * 2 * kC + kC + c];
-    const float th = tanhf(pf), sg = 1.f / (1.f + expf(-pg));
-    const float d = dg[i];
-    g[i] = __builtin_bit_cast(uint16_t, (__bf16)(th * sg));
-    dpre[row * 2 * kC + c] = __builtin_bit_cast(uint16_t, (__bf16)(d * sg * (1.f - th * th)));
-    dpre[row * 2 * kC + kC + c] = __builtin_bit_cast(uint16_t, (__bf16)(d * th * sg * (1.f - sg)));
-}
-
 // Head backward, elementwise part: dh[row][j] = dz[row] * w2[j] * act'(h[row][j]);
 // ah[row][j] = act(h[row][j]) (used for d w2).
 __global__ __launch_bounds__(256) void head_bwd_elem_kernel(const float* h, const float* dz, int64_t M,
@@ -695,6 +773,10 @@ hipError_t gemm_rows(const GemmRowsArgs& a, hipStream_t st) {
                (q.p16 ? q.ld % 8 == 0 && ((uintptr_t)q.p16 & 15) == 0 : q.ld % 4 == 0 && ((uintptr_t)q.ptr & 15) == 0);
     }
     if (any16 && !bf16) return hipErrorInvalidValue;  // bf16 parts need the bf16-operand kernel
+    if (a.gpre && (!bf16 || a.N != kC || !a.g16 || !a.dpre16 || a.bias || a.beta != 0.f || a.mask ||
+                   (a.C && a.ldc % 4) || ((uintptr_t)a.gpre & 15)))
+        return hipErrorInvalidValue;
+    if (!a.C && !a.gpre) return hipErrorInvalidValue;
     if (bf16) {
         hipLaunchKernelGGL(pack_bt_kernel, dim3((unsigned)(((int64_t)a.N * Ktot + 255) / 256)), dim3(256), 0, st, a,
                            Ktot);
@@ -745,11 +827,6 @@ hipError_t launch_input_proj(const float* u, int64_t M, const float* w_in, const
     hipLaunchKernelGGL(input_proj_kernel, dim3(nblk(M * kC)), dim3(256), 0, st, u, M, w_in, b_in, x0);
     return hipGetLastError();
 }
-hipError_t launch_gate_bwd16(const float* pre, const float* dg, int64_t M, uint16_t* g, uint16_t* dpre, hipStream_t st) {
-    hipLaunchKernelGGL(gate_bwd16_kernel, dim3((unsigned)((M * kC + 255) / 256)), dim3(256), 0, st, pre, dg, M, g, dpre);
-    return hipGetLastError();
-}
-
 hipError_t colsum16(const uint16_t* X, int64_t ldx, int64_t M, int N, float* part, int64_t part_capacity, float* dst,
                     int64_t dst_stride, hipStream_t st) {
     if (N < 4 || N % 4 || N > 1024 || ldx % 4 || ((uintptr_t)X & 7) || part_capacity < N) return hipErrorInvalidValue;
