@@ -127,8 +127,11 @@ __device__ inline uint4 bf16_pack8(float4 lo, float4 hi) {
 }
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-__device__ inline uint2 bf16_pack4(float4 v) {
-    return __builtin_bit_cast(uint2, __builtin_convertvector(__builtin_bit_cast(floatx4, v), bf16x4));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+// four fp32 (as raw bits) -> four bf16, rounded to nearest even
+__device__ inline u32x2 bf16_pack4(u32x4 v) {
+    return __builtin_bit_cast(u32x2, __builtin_convertvector(__builtin_bit_cast(floatx4, v), bf16x4));
 }
 
 // One block: 128 rows x 128 columns; wave (wr, wc) owns rows 64 wr .. + 64 (two row blocks) and columns
@@ -172,7 +175,9 @@ __global__ __launch_bounds__(256) void gemm_rows_bf16_kernel(GemmRowsArgs a, int
     }
     const int nch = Ktot / BK;
     // rows whose shifted source leaves the window read the (valid) unshifted row and are set to zero
-    auto load_raw = [&](int ci, uint4 (&raw)[8]) {
+    // as they are staged (masking at the load would let the compiler turn it into a conditional load)
+    auto row_ok = [&](int sh, int i) { return (unsigned)(tw[i] + sh) < (unsigned)a.T; };
+    auto load_raw = [&](int ci, u32x4 (&raw)[8]) __attribute__((always_inline)) {
         int p, k0;
         rows_chunk(a, ci, p, k0);
         const APart& ap = a.A[p];
@@ -180,21 +185,16 @@ __global__ __launch_bounds__(256) void gemm_rows_bf16_kernel(GemmRowsArgs a, int
         if (ap.p16) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const bool ok = (unsigned)(tw[i] + sh) < (unsigned)a.T;
-                const int64_t row = row0 + sr + 32 * i + (ok ? sh : 0);
-                const uint4 v = *(const uint4*)(ap.p16 + row * ap.ld + k0 + 8 * sc);
-                raw[i] = ok ? v : make_uint4(0, 0, 0, 0);
+                const int64_t row = row0 + sr + 32 * i + (row_ok(sh, i) ? sh : 0);
+                raw[2 * i] = *(const u32x4*)(ap.p16 + row * ap.ld + k0 + 8 * sc);
+                raw[2 * i + 1] = u32x4{0, 0, 0, 0};  // (both paths write raw[0..7] in one order)
             }
         } else {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const bool ok = (unsigned)(tw[i] + sh) < (unsigned)a.T;
-                const int64_t row = row0 + sr + 32 * i + (ok ? sh : 0);
+                const int64_t row = row0 + sr + 32 * i + (row_ok(sh, i) ? sh : 0);
 #pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    const uint4 v = *(const uint4*)(ap.ptr + row * ap.ld + k0 + 4 * sc + 32 * j);
-                    raw[2 * i + j] = ok ? v : make_uint4(0, 0, 0, 0);
-                }
+                for (int j = 0; j < 2; ++j) raw[2 * i + j] = *(const u32x4*)(ap.ptr + row * ap.ld + k0 + 4 * sc + 32 * j);
             }
         }
     };
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(256) void gemm_rows_bf16_kernel(GemmRowsArgs a, int
     const uint16_t* bfr = a.bt + ((int64_t)((col0 + 64 * wc) >> 5) * (Ktot >> 4) * 64 + lane) * 8;
     const int64_t ctile = (int64_t)(Ktot >> 4) * 64 * 8;   // elements per column tile
     floatx16 acc[2][2] = {};
-    uint4 raw[8];
+    u32x4 raw[8];
     load_raw(0, raw);
     for (int ci = 0; ci < nch; ++ci) {
         int p, k0;
@@ -214,16 +214,18 @@ __global__ __launch_bounds__(256) void gemm_rows_bf16_kernel(GemmRowsArgs a, int
 #pragma unroll
             for (int c = 0; c < 2; ++c) bf[s4][c] = *(const bf16x8*)(bfr + c * ctile + (int64_t)(4 * ci + s4) * 64 * 8);
         __syncthreads();  // the previous chunk's fragments are read
+        const int sh = a.A[p].shift;
         if (is16) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) *(uint4*)&As[(sr + 32 * i) * AROW + 8 * sc] = raw[i];
+            for (int i = 0; i < 4; ++i)
+                *(u32x4*)&As[(sr + 32 * i) * AROW + 8 * sc] = row_ok(sh, i) ? raw[2 * i] : u32x4{0, 0, 0, 0};
         } else {
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
-                    *(uint2*)&As[(sr + 32 * i) * AROW + 4 * sc + 32 * j] =
-                        bf16_pack4(__builtin_bit_cast(float4, raw[2 * i + j]));
+                    *(u32x2*)&As[(sr + 32 * i) * AROW + 4 * sc + 32 * j] =
+                        row_ok(sh, i) ? bf16_pack4(raw[2 * i + j]) : u32x2{0, 0};
         }
         __syncthreads();
         if (ci + 1 < nch) load_raw(ci + 1, raw);   // in flight during this chunk's products
@@ -239,36 +241,38 @@ __global__ __launch_bounds__(256) void gemm_rows_bf16_kernel(GemmRowsArgs a, int
                     acc[i][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bf[s4][c], acc[i][c], 0, 0, 0);
         }
     }
-    if (a.gpre) {
-        // gate-backward epilogue (N = 128, one column block): dg staged through LDS 64 rows at a time,
-        // then each thread takes 4 consecutive channels of a row with 16-byte loads of the
-        // pre-activations
-        float* Ep = (float*)smem;
-        for (int pass = 0; pass < 2; ++pass) {
-            __syncthreads();  // the products' (or the previous pass's) LDS reads are done
-            if (wr == pass) {
+    // epilogue: the 128 x 128 tile staged through LDS 64 rows at a time; each thread then takes 4
+    // consecutive columns (cq) of 8 rows, all its loads (C for beta, the mask, or the gate's
+    // pre-activations) issued before the first store
+    float* Ep = (float*)smem;
+    const int cq = 4 * (tid & 31);
+    const int n4 = col0 + cq;
+    for (int pass = 0; pass < 2; ++pass) {
+        __syncthreads();  // the products' (or the previous pass's) LDS reads are done
+        if (wr == pass) {
 #pragma unroll
-                for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
-                    for (int c = 0; c < 2; ++c)
+                for (int c = 0; c < 2; ++c)
 #pragma unroll
-                        for (int e = 0; e < 16; ++e)
-                            Ep[(32 * i + 8 * (e >> 2) + 4 * h + (e & 3)) * EP + 64 * wc + 32 * c + r] = acc[i][c][e];
-            }
-            __syncthreads();
-            const int cq = 4 * (tid & 31);
+                    for (int e = 0; e < 16; ++e)
+                        Ep[(32 * i + 8 * (e >> 2) + 4 * h + (e & 3)) * EP + 64 * wc + 32 * c + r] = acc[i][c][e];
+        }
+        __syncthreads();
+        const int64_t rbase = row0 + 64 * pass + (tid >> 5);   // + 8 it
+        if (a.gpre) {
+            // gate backward (N = 128, one column block): g, dpre from the pre-activations and dg
             float4 pf[8], pg[8];
 #pragma unroll
             for (int it = 0; it < 8; ++it) {
-                const int64_t row = row0 + 64 * pass + 8 * it + (tid >> 5);
+                const int64_t row = rbase + 8 * it;
                 pf[it] = *(const float4*)(a.gpre + row * 2 * kC + cq);
                 pg[it] = *(const float4*)(a.gpre + row * 2 * kC + kC + cq);
             }
 #pragma unroll
             for (int it = 0; it < 8; ++it) {
-                const int rl = 8 * it + (tid >> 5);
-                const int64_t row = row0 + 64 * pass + rl;
-                const float4 d = *(const float4*)&Ep[rl * EP + cq];
+                const int64_t row = rbase + 8 * it;
+                const float4 d = *(const float4*)&Ep[(8 * it + (tid >> 5)) * EP + cq];
                 const float fv[4] = {pf[it].x, pf[it].y, pf[it].z, pf[it].w};
                 const float gv[4] = {pg[it].x, pg[it].y, pg[it].z, pg[it].w};
                 const float dv[4] = {d.x, d.y, d.z, d.w};
@@ -282,25 +286,34 @@ __global__ __launch_bounds__(256) void gemm_rows_bf16_kernel(GemmRowsArgs a, int
                     make_uint2(so[0] | ((uint32_t)so[1] << 16), so[2] | ((uint32_t)so[3] << 16));
                 if (a.C) *(float4*)(a.C + row * a.ldc + cq) = d;
             }
+            continue;
         }
-        return;
-    }
+        float4 cv[8], mv[8];
+        if (a.beta != 0.f) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+            for (int it = 0; it < 8; ++it) cv[it] = *(const float4*)(a.C + (rbase + 8 * it) * a.ldc + n4);
+        }
+        if (a.mask) {
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const int n = col0 + 64 * wc + 32 * c + r;
+            for (int it = 0; it < 8; ++it) mv[it] = *(const float4*)(a.mask + (rbase + 8 * it) * a.ldm + n4);
+        }
+        const float4 bv = a.bias ? *(const float4*)(a.bias + n4) : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const int64_t row = row0 + 64 * wr + 32 * i + 8 * (e >> 2) + 4 * h + (e & 3);
-                const int64_t o = row * a.ldc + n;
-                float v = acc[i][c][e];
-                if (a.bias) v += a.bias[n];
-                if (a.beta != 0.f) v += a.beta * a.C[o];
-                if (a.mask) v = (a.mask[row * a.ldm + n] > 0.f) ? v : 0.f;
-                a.C[o] = v;
+        for (int it = 0; it < 8; ++it) {
+            const float4 d = *(const float4*)&Ep[(8 * it + (tid >> 5)) * EP + cq];
+            float v[4] = {d.x, d.y, d.z, d.w};
+            const float b4[4] = {bv.x, bv.y, bv.z, bv.w};
+            const float c4[4] = {cv[it].x, cv[it].y, cv[it].z, cv[it].w};
+            const float m4[4] = {mv[it].x, mv[it].y, mv[it].z, mv[it].w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (a.bias) v[j] += b4[j];
+                if (a.beta != 0.f) v[j] += a.beta * c4[j];
+                if (a.mask) v[j] = (m4[j] > 0.f) ? v[j] : 0.f;
             }
+            *(float4*)(a.C + (rbase + 8 * it) * a.ldc + n4) = make_float4(v[0], v[1], v[2], v[3]);
         }
+    }
 }
 
 // Block -> (output tile, row chunk) of the weight-gradient GEMMs. Blocks are dispatched round-robin
@@ -772,6 +785,9 @@ hipError_t gemm_rows(const GemmRowsArgs& a, hipStream_t st) {
         bf16 = bf16 && q.K % BK == 0 &&
                (q.p16 ? q.ld % 8 == 0 && ((uintptr_t)q.p16 & 15) == 0 : q.ld % 4 == 0 && ((uintptr_t)q.ptr & 15) == 0);
     }
+    // the bf16 kernel's epilogue moves 4 columns at a time
+    bf16 = bf16 && (!a.C || (a.ldc % 4 == 0 && ((uintptr_t)a.C & 15) == 0)) &&
+           (!a.mask || (a.ldm % 4 == 0 && ((uintptr_t)a.mask & 15) == 0)) && (!a.bias || ((uintptr_t)a.bias & 15) == 0);
     if (any16 && !bf16) return hipErrorInvalidValue;  // bf16 parts need the bf16-operand kernel
     if (a.gpre && (!bf16 || a.N != kC || !a.g16 || !a.dpre16 || a.bias || a.beta != 0.f || a.mask ||
                    (a.C && a.ldc % 4) || ((uintptr_t)a.gpre & 15)))
