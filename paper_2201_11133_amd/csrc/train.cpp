@@ -137,7 +137,9 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
     const int64_t f_dg = f_g + M * kC, f_dx = f_dg + M * kC, f_ds = f_dx + M * kC, f_sks = f_ds + M * kC;
     const int64_t f_r = f_sks + M * kC, f_h = f_r + M * kC, f_dh = f_h + M * kC, f_ah = f_dh + M * kC;
     const int64_t f_dpre = f_ah + M * kC, f_bt = f_dpre + M * 2 * kC, f_part = f_bt + 2 * kC * 2 * kC;
-    const int64_t total = f_part + nch * 2 * kC * 2 * kC;
+    // partials of the largest weight-gradient product (2C x 2C per chunk), then the group sums of
+    // its two-stage reduction (at most 64 groups)
+    const int64_t total = f_part + (nch + 64) * 2 * kC * 2 * kC;
     gwd_status s = ensure_tws(m, total * 4, st);
     if (s != GWD_OK) return s;
     void* b = m->tws.base;
@@ -245,13 +247,19 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
                 HIPCHK(capture(cap[5], BT ? (const void*)G16 : G, M * kC, BT != nullptr, st), "capture g");
                 HIPCHK(capture(cap[6], BT ? (const void*)DPRE16 : DPRE, M * 2 * kC, BT != nullptr, st), "capture dpre");
             }
-            // skip / residual weight gradients
+            // skip / residual weight gradients, one product: A = [dskip | dx'] stacked along k (the
+            // two weights' output channels), B = g, read once
             {
                 WgradArgs a{};
                 a.A[0] = APart{DS, kC, 0, kC, DS16}; a.nparts = 1; a.Ktot = kC;
+                if (!last) {
+                    a.A[1] = APart{DX, kC, 0, kC};
+                    a.nparts = 2; a.Ktot = 2 * kC;
+                }
                 a.B = G; a.ldb = kC; a.N = kC; a.M = M; a.T = T; a.rows_per_chunk = RPC; a.part = PART; a.part_capacity = PART_CAP; a.bf16 = BT != nullptr;
                 a.B16 = G16;
-                HIPCHK(gemm_wgrad(a, grad + v.skip_w[l], 0, st), "d skip.W");
+                HIPCHK(gemm_wgrad(a, WgradDst{grad + v.skip_w[l], last ? nullptr : grad + v.res_w[l], (int64_t)kC * kC, 1,
+                                              false}, st), "d skip.W, d res.W");
                 // dskip is the same for every layer, and so is its column sum: computed once (for the
                 // last layer, the first one here), then copied (the gradient starts at zero)
                 if (l == L - 1)
@@ -259,22 +267,24 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
                 else
                     HIPCHK(hipMemcpyAsync(grad + v.skip_b[l], grad + v.skip_b[L - 1], kC * sizeof(float),
                                           hipMemcpyDeviceToDevice, st), "d skip.b");
-                if (!last) {
-                    a.A[0] = APart{DX, kC, 0, kC};
-                    HIPCHK(gemm_wgrad(a, grad + v.res_w[l], 0, st), "d res.W");
+                if (!last)
                     HIPCHK(colsum(DX, kC, M, kC, nullptr, 0, 0, PART, PART_CAP, grad + v.res_b[l], 1, st), "d res.b");
-                }
             }
             // conv weight gradient: dW[n][c][tap] = sum_t dpre[t][n] x[t - d (1 - tap)][c]
             {
                 WgradArgs a{};
                 a.A[0] = APart{DPRE, 2 * kC, 0, 2 * kC, DPRE16}; a.nparts = 1; a.Ktot = 2 * kC;
                 a.B = xs_i; a.ldb = kC; a.N = kC; a.M = M; a.T = T; a.rows_per_chunk = RPC; a.part = PART; a.part_capacity = PART_CAP; a.bf16 = BT != nullptr;
-                if (BT) a.B16 = (const uint16_t*)xs_i;
                 a.bshift = 0;
-                HIPCHK(gemm_wgrad(a, grad + v.dil_w[l] + 1, 2, st), "d dil.W tap1");
-                a.bshift = -d;
-                HIPCHK(gemm_wgrad(a, grad + v.dil_w[l], 2, st), "d dil.W tap0");
+                if (BT) {  // both taps in one product: B = [x(t) | x(t - d)] stacked along n, dpre read once
+                    a.B16 = (const uint16_t*)xs_i;
+                    a.N = 2 * kC; a.nbparts = 2; a.bshift1 = -d;
+                    HIPCHK(gemm_wgrad(a, WgradDst{grad + v.dil_w[l], nullptr, 0, 1, true}, st), "d dil.W");
+                } else {
+                    HIPCHK(gemm_wgrad(a, grad + v.dil_w[l] + 1, 2, st), "d dil.W tap1");
+                    a.bshift = -d;
+                    HIPCHK(gemm_wgrad(a, grad + v.dil_w[l], 2, st), "d dil.W tap0");
+                }
                 if (BT) HIPCHK(colsum16(DPRE16, 2 * kC, M, 2 * kC, PART, PART_CAP, grad + v.dil_b[l], 1, st), "d dil.b");
                 else HIPCHK(colsum(DPRE, 2 * kC, M, 2 * kC, nullptr, 0, 0, PART, PART_CAP, grad + v.dil_b[l], 1, st), "d dil.b");
             }

@@ -56,19 +56,35 @@ struct WgradArgs {
     int64_t part_capacity;  // floats available at part (partials, then the reduction's scratch)
     bool bf16 = false;      // operands rounded to bf16 (fp32 accumulation): BF16/FP8 members
     const uint16_t* B16 = nullptr;  // with bf16: B already in bf16 (same layout as B, which is unused)
+    // B parts stacked along n (bf16 operands only): N / nbparts columns each, all from the same B
+    // rows, part 0 shifted by bshift and part 1 by bshift1
+    int nbparts = 1;
+    int bshift1 = 0;
+};
+
+// Where the reduced K x N weight gradient goes (accumulated with +=): element i = k N + n at
+// d0[i * stride] for i < split, else at d1[(i - split) * stride]; with taps (N = 2 C, B parts = the
+// two conv taps, part 0 the unshifted one): (k, n) at d0[(k C + n % C) 2 + (n < C)], the layout
+// [n_out][c][tap] of a dilated conv weight.
+struct WgradDst {
+    float* d0;
+    float* d1;
+    int64_t split;
+    int64_t stride;
+    bool taps;
 };
 
 hipError_t gemm_rows(const GemmRowsArgs& a, hipStream_t st);
 // dst (+)= reduced partials: out_mode 0 row-major [K][N]; 2: element (k, n) at dst[(k N + n) * 2]
 // (one tap of a conv weight [n_out][c][2])
 hipError_t gemm_wgrad(const WgradArgs& a, float* dst, int out_mode, hipStream_t st);
+hipError_t gemm_wgrad(const WgradArgs& a, const WgradDst& dst, hipStream_t st);
 // dst[n * dst_stride] += sum_rows f(X[row][n]) * w[row * wstride]   (w optional, f = id or ReLU)
 hipError_t colsum(const float* X, int64_t ldx, int64_t M, int N, const float* w, int64_t wstride, int relu,
                   float* part, int64_t part_capacity, float* dst, int64_t dst_stride, hipStream_t st);
 hipError_t launch_input_proj(const float* u, int64_t M, const float* w_in, const float* b_in, float* x0,
                              hipStream_t st);
 hipError_t launch_gate_bwd(const float* pre, const float* dg, int64_t M, float* g, float* dpre, hipStream_t st);
-// the same with g and dpre rounded to bf16 (round to nearest even), for the bf16-operand backward
 // dst[n * dst_stride] += sum_rows X[row][n] for bf16 X (N % 4 == 0, N <= 1024, ldx % 4 == 0)
 hipError_t colsum16(const uint16_t* X, int64_t ldx, int64_t M, int N, float* part, int64_t part_capacity, float* dst,
                     int64_t dst_stride, hipStream_t st);

@@ -498,6 +498,136 @@ __global__ __launch_bounds__(256) void gemm_wgrad_bf16_kernel(WgradArgs a) {
     }
 }
 
+// The weight-gradient GEMM with bf16 operands on 128 x 128 output tiles, for chunks of one window
+// (T % 64 == 0): partials identical to gemm_wgrad_bf16_kernel's (every output takes the same MFMAs in
+// the same order: 64-row steps, then 16-row groups, ascending), with four times the products per
+// staged byte. Waves 0-1 stage the A tile, waves 2-3 the B tile: a thread loads 8 rows x 8 columns
+// (one 16-byte load per row for bf16, two for fp32), transposes them in registers and writes 8
+// columns of 8 rows as 16-byte words into LDS ([column][row], 144-byte columns: conflict-free
+// writes and fragment reads). Two LDS buffers, one barrier per step; the next step's rows are
+// loaded during the products. Wave (wk, wn) owns output rows 64 wk .. + 64 and columns 64 wn .. + 64.
+constexpr int W2T = 128;                 // tile (k and n)
+constexpr int W2R = 64;                  // rows per step
+constexpr int W2LD = W2R * 2 + 16;       // bytes per LDS column
+constexpr int W2OP = W2T * W2LD;         // bytes per operand tile
+struct W2Operand {
+    const uint16_t* p16;   // bf16 rows, or
+    const float* p32;      // fp32 rows
+    int64_t ld;
+    int shift;             // row shift within the window (zero outside)
+};
+
+__device__ inline u32x4 w2_bf16x8(u32x4 lo, u32x4 hi) {  // 8 fp32 (raw bits) -> 8 bf16
+    return __builtin_bit_cast(u32x4, bf16_pack8(__builtin_bit_cast(float4, lo), __builtin_bit_cast(float4, hi)));
+}
+
+__global__ __launch_bounds__(256) void gemm_wgrad_t128_kernel(WgradArgs a) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * 2 * W2OP];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wk = wave & 1, wn = wave >> 1, h = lane >> 5, r = lane & 31;
+    const int ntn = a.N / W2T, ntk = a.Ktot / W2T;
+    int tile, chunk;
+    wgrad_block(ntn * ntk, tile, chunk);
+    if ((int64_t)chunk * a.T >= a.M) return;  // padding of the grid (uniform per block)
+    const int k0 = (tile / ntn) * W2T, n0 = (tile % ntn) * W2T;
+    // this thread's operand: waves 0-1 the A tile (columns k0 ..), waves 2-3 the B tile (n0 ..)
+    W2Operand op;
+    int col;
+    const bool isA = wave < 2;
+    if (isA) {
+        int p = 0, kb = 0;
+        while (kb + a.A[p].K <= k0) {
+            kb += a.A[p].K;
+            ++p;
+        }
+        op = W2Operand{a.A[p].p16, a.A[p].ptr, a.A[p].ld, a.A[p].shift};
+        col = k0 - kb;
+    } else {
+        const int nb = a.N / a.nbparts, q = n0 / nb;
+        op = W2Operand{a.B16, a.B, a.ldb, q ? a.bshift1 : a.bshift};
+        col = n0 - q * nb;
+    }
+    const int t2 = tid & 127, rg = t2 & 7, cm = t2 >> 3;   // rows 8 rg .. + 8, columns 8 cm .. + 8
+    col += 8 * cm;
+    const int64_t wrow0 = (int64_t)chunk * a.T;           // the chunk's window
+    const bool is16 = op.p16 != nullptr;
+    // rows whose shifted source leaves the window read the unshifted row and are zeroed when staged
+    auto load = [&](int step, u32x4 (&raw)[16]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int t = step * W2R + 8 * rg + j;
+            const bool ok = (unsigned)(t + op.shift) < (unsigned)a.T;
+            const int64_t row = wrow0 + t + (ok ? op.shift : 0);
+            if (is16) {
+                raw[2 * j] = *(const u32x4*)(op.p16 + row * op.ld + col);
+                raw[2 * j + 1] = u32x4{0, 0, 0, 0};
+            } else {
+                raw[2 * j] = *(const u32x4*)(op.p32 + row * op.ld + col);
+                raw[2 * j + 1] = *(const u32x4*)(op.p32 + row * op.ld + col + 4);
+            }
+        }
+    };
+    auto stage = [&](int step, const u32x4 (&raw)[16], uint8_t* dst) __attribute__((always_inline)) {
+        u32x4 w[8];  // row j: columns 8 cm .. + 8 in bf16
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int t = step * W2R + 8 * rg + j;
+            const bool ok = (unsigned)(t + op.shift) < (unsigned)a.T;
+            const u32x4 v = is16 ? raw[2 * j] : w2_bf16x8(raw[2 * j], raw[2 * j + 1]);
+            w[j] = ok ? v : u32x4{0, 0, 0, 0};
+        }
+        // column c: rows (2q, 2q + 1) as one bf16 pair, q < 4
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            u32x4 o;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t lo = w[2 * q][c >> 1], hi = w[2 * q + 1][c >> 1];
+                o[q] = (c & 1) ? ((lo >> 16) | (hi & 0xffff0000u)) : ((lo & 0xffffu) | (hi << 16));
+            }
+            *(u32x4*)(dst + (8 * cm + c) * W2LD + 16 * rg) = o;
+        }
+    };
+    floatx16 acc[2][2] = {};
+    u32x4 raw[16];
+    const int nsteps = a.T / W2R;
+    load(0, raw);
+    for (int s = 0; s < nsteps; ++s) {
+        uint8_t* buf = lds + (s & 1) * 2 * W2OP;
+        stage(s, raw, buf + (isA ? 0 : W2OP));
+        __syncthreads();
+        if (s + 1 < nsteps) load(s + 1, raw);   // in flight during the products
+        const uint8_t* At = buf;
+        const uint8_t* Bt = buf + W2OP;
+#pragma unroll
+        for (int s16 = 0; s16 < W2R / 16; ++s16) {
+            bf16x8 av[2], bv[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                av[i] = *(const bf16x8*)(At + (64 * wk + 32 * i + r) * W2LD + 2 * (16 * s16 + 8 * h));
+                bv[i] = *(const bf16x8*)(Bt + (64 * wn + 32 * i + r) * W2LD + 2 * (16 * s16 + 8 * h));
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+                    acc[i][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bv[c], acc[i][c], 0, 0, 0);
+        }
+    }
+    float* out = a.part + (int64_t)chunk * a.Ktot * a.N;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int n = n0 + 64 * wn + 32 * c + r;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int k = k0 + 64 * wk + 32 * i + 8 * (e >> 2) + 4 * h + (e & 3);
+                out[(int64_t)k * a.N + n] = acc[i][c][e];
+            }
+        }
+}
+
 // dst[i * stride] += sum over chunks of part[chunk][i], i = k N + n, in two fixed-order stages:
 // stage 1 adds the chunks of each of G consecutive groups (in order) into tmp[g][i], stage 2 adds
 // the G group sums (in order) into dst. The result does not depend on scheduling.
@@ -510,19 +640,27 @@ __global__ __launch_bounds__(256) void reduce_groups_kernel(const float* part, i
     for (int c = c0; c < c1; ++c) s += part[(int64_t)c * KN + i];
     tmp[(int64_t)blockIdx.y * KN + i] = s;
 }
-__global__ __launch_bounds__(256) void reduce_parts_kernel(const float* part, int nchunks, int K, int N,
-                                                           float* dst, int64_t stride) {
+__global__ __launch_bounds__(256) void reduce_parts_kernel(const float* part, int nchunks, int64_t KN, int N,
+                                                           WgradDst d) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= (int64_t)K * N) return;
+    if (i >= KN) return;
     float s = 0.f;
-    for (int c = 0; c < nchunks; ++c) s += part[(int64_t)c * K * N + i];
-    dst[i * stride] += s;
+    for (int c = 0; c < nchunks; ++c) s += part[(int64_t)c * KN + i];
+    float* dst;
+    if (d.taps) {
+        const int64_t k = i / N;
+        const int n = (int)(i - k * N), C = N / 2;
+        dst = d.d0 + (k * C + n % C) * 2 + (n < C ? 1 : 0);
+    } else {
+        dst = i < d.split ? d.d0 + i * d.stride : d.d1 + (i - d.split) * d.stride;
+    }
+    *dst += s;
 }
 
 // Launch the reduction of nchunks partial sums of KN values each (part holds them; scratch for the
 // group sums follows them within part_capacity floats).
-static hipError_t reduce_parts(float* part, int64_t part_capacity, int nchunks, int64_t KN, float* dst,
-                               int64_t stride, hipStream_t st) {
+static hipError_t reduce_parts(float* part, int64_t part_capacity, int nchunks, int64_t KN, int N,
+                               const WgradDst& d, hipStream_t st) {
     int G = nchunks >= 128 ? 64 : 1;
     while (G > 1 && (int64_t)(nchunks + G) * KN > part_capacity) G >>= 1;
     if (G > 1) {
@@ -537,8 +675,12 @@ static hipError_t reduce_parts(float* part, int64_t part_capacity, int nchunks, 
         nchunks = G;
     }
     hipLaunchKernelGGL(reduce_parts_kernel, dim3((unsigned)((KN + 255) / 256)), dim3(256), 0, st, (const float*)part,
-                       nchunks, 1, (int)KN, dst, stride);
+                       nchunks, KN, N, d);
     return hipGetLastError();
+}
+static hipError_t reduce_parts(float* part, int64_t part_capacity, int nchunks, int64_t KN, float* dst,
+                               int64_t stride, hipStream_t st) {
+    return reduce_parts(part, part_capacity, nchunks, KN, (int)KN, WgradDst{dst, nullptr, KN, stride, false}, st);
 }
 
 // part[chunk][n] = sum over the chunk's rows of f(X[row][n]) * w(row); f = identity or ReLU
@@ -807,17 +949,36 @@ hipError_t gemm_rows(const GemmRowsArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t gemm_wgrad(const WgradArgs& a0, float* dst, int out_mode, hipStream_t st) {
+hipError_t gemm_wgrad(const WgradArgs& a0, const WgradDst& d, hipStream_t st) {
     WgradArgs a = a0;
-    const int nchunks = (int)((a.M + a.rows_per_chunk - 1) / a.rows_per_chunk);
-    const int64_t blocks = (int64_t)((nchunks + 7) / 8) * 8 * (a.Ktot / GT) * (a.N / GT);
     if ((a.B16 || a.A[0].p16 || (a.nparts > 1 && a.A[1].p16)) && !a.bf16) return hipErrorInvalidValue;
-    if (a.bf16) hipLaunchKernelGGL(gemm_wgrad_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL(gemm_wgrad_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
+    if (a.nbparts < 1 || a.nbparts > 2 || a.N % a.nbparts) return hipErrorInvalidValue;
+    // the 128 x 128 tile kernel: bf16 operands, chunks of one window, parts in whole tiles, 16-byte rows
+    bool t128 = a.bf16 && a.rows_per_chunk == a.T && a.T % W2R == 0 && a.M % a.T == 0 && a.Ktot % W2T == 0 &&
+                (a.N / a.nbparts) % W2T == 0;
+    for (int p = 0; p < a.nparts; ++p) {
+        const APart& q = a.A[p];
+        t128 = t128 && q.K % W2T == 0 && q.ld % 8 == 0 && ((uintptr_t)(q.p16 ? (const void*)q.p16 : q.ptr) & 15) == 0;
+    }
+    t128 = t128 && a.ldb % 8 == 0 && ((uintptr_t)(a.B16 ? (const void*)a.B16 : a.B) & 15) == 0;
+    if (a.nbparts > 1 && !t128) return hipErrorInvalidValue;  // B parts: the tile kernel only
+    const int nchunks = (int)((a.M + a.rows_per_chunk - 1) / a.rows_per_chunk);
+    if (t128) {
+        const int64_t blocks = (int64_t)((nchunks + 7) / 8) * 8 * (a.Ktot / W2T) * (a.N / W2T);
+        hipLaunchKernelGGL(gemm_wgrad_t128_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
+    } else {
+        const int64_t blocks = (int64_t)((nchunks + 7) / 8) * 8 * (a.Ktot / GT) * (a.N / GT);
+        if (a.bf16) hipLaunchKernelGGL(gemm_wgrad_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
+        else hipLaunchKernelGGL(gemm_wgrad_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return reduce_parts(a.part, a.part_capacity, nchunks, (int64_t)a.Ktot * a.N, dst, (int64_t)(out_mode == 2 ? 2 : 1),
-                        st);
+    return reduce_parts(a.part, a.part_capacity, nchunks, (int64_t)a.Ktot * a.N, a.N, d, st);
+}
+
+hipError_t gemm_wgrad(const WgradArgs& a, float* dst, int out_mode, hipStream_t st) {
+    const int64_t KN = (int64_t)a.Ktot * a.N;
+    return gemm_wgrad(a, WgradDst{dst, nullptr, KN, (int64_t)(out_mode == 2 ? 2 : 1), false}, st);
 }
 
 hipError_t colsum(const float* X, int64_t ldx, int64_t M, int N, const float* w, int64_t wstride, int relu,
