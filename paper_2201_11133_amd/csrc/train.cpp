@@ -139,7 +139,8 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
     const int64_t f_dpre = f_ah + M * kC, f_bt = f_dpre + M * 2 * kC, f_part = f_bt + 2 * kC * 2 * kC;
     // partials of the largest weight-gradient product (2C x 2C per chunk), then the group sums of
     // its two-stage reduction (at most 64 groups)
-    const int64_t total = f_part + (nch + 64) * 2 * kC * 2 * kC;
+    const int64_t f_cpart = f_part + (nch + 64) * 2 * kC * 2 * kC;   // column sums fused into them
+    const int64_t total = f_cpart + (nch + 64) * 2 * kC;
     gwd_status s = ensure_tws(m, total * 4, st);
     if (s != GWD_OK) return s;
     void* b = m->tws.base;
@@ -149,7 +150,9 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
     // BF16/FP8 members: the row and weight-gradient GEMMs of the backward take bf16 operands (fp32
     // accumulation)
     uint16_t* BT = (m->prec == GWD_BF16 || m->prec == GWD_FP8_E4M3) ? (uint16_t*)fptr(b, f_bt) : nullptr;
-    const int64_t PART_CAP = total - f_part;  // floats
+    const int64_t PART_CAP = f_cpart - f_part;  // floats
+    float* CPART = fptr(b, f_cpart);
+    const int64_t CPART_CAP = total - f_cpart;
     hipError_t e;
 #define HIPCHK(x, what) do { e = (x); if (e != hipSuccess) return hip_fail(e, what); } while (0)
     HIPCHK(launch_fill(grad, m->n_params, 0.f, st), "zero grad");
@@ -171,9 +174,10 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
         WgradArgs a{};
         a.A[0] = APart{DH, kC, 0, kC}; a.nparts = 1; a.Ktot = kC;
         a.B = R; a.ldb = kC; a.N = kC; a.M = M; a.T = T; a.rows_per_chunk = RPC; a.part = PART; a.part_capacity = PART_CAP; a.bf16 = BT != nullptr;
-        HIPCHK(gemm_wgrad(a, grad + v.h1w, 0, st), "d h1.W");
+        a.cpart = CPART; a.cpart_capacity = CPART_CAP;
+        const WgradDst cd{grad + v.h1b, nullptr, kC, 1, false};
+        HIPCHK(gemm_wgrad(a, WgradDst{grad + v.h1w, nullptr, (int64_t)kC * kC, 1, false}, st, &cd), "d h1.W, d h1.b");
     }
-    HIPCHK(colsum(DH, kC, M, kC, nullptr, 0, 0, PART, PART_CAP, grad + v.h1b, 1, st), "d h1.b");
     {
         GemmRowsArgs g{};
         g.A[0] = APart{DH, kC, 0, kC};
@@ -258,17 +262,21 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
                 }
                 a.B = G; a.ldb = kC; a.N = kC; a.M = M; a.T = T; a.rows_per_chunk = RPC; a.part = PART; a.part_capacity = PART_CAP; a.bf16 = BT != nullptr;
                 a.B16 = G16;
+                // with the residual bias gradient (column sums of dx'; those of the bf16 dskip operand
+                // are dropped)
+                if (!last) {
+                    a.cpart = CPART; a.cpart_capacity = CPART_CAP;
+                }
+                const WgradDst cd{nullptr, grad + v.res_b[l], kC, 1, false};
                 HIPCHK(gemm_wgrad(a, WgradDst{grad + v.skip_w[l], last ? nullptr : grad + v.res_w[l], (int64_t)kC * kC, 1,
-                                              false}, st), "d skip.W, d res.W");
-                // dskip is the same for every layer, and so is its column sum: computed once (for the
-                // last layer, the first one here), then copied (the gradient starts at zero)
+                                              false}, st, last ? nullptr : &cd), "d skip.W, d res");
+                // dskip is the same for every layer, and so is its column sum (fp32): computed once (for
+                // the last layer, the first one here), then copied (the gradient starts at zero)
                 if (l == L - 1)
                     HIPCHK(colsum(DS, kC, M, kC, nullptr, 0, 0, PART, PART_CAP, grad + v.skip_b[l], 1, st), "d skip.b");
                 else
                     HIPCHK(hipMemcpyAsync(grad + v.skip_b[l], grad + v.skip_b[L - 1], kC * sizeof(float),
                                           hipMemcpyDeviceToDevice, st), "d skip.b");
-                if (!last)
-                    HIPCHK(colsum(DX, kC, M, kC, nullptr, 0, 0, PART, PART_CAP, grad + v.res_b[l], 1, st), "d res.b");
             }
             // conv weight gradient: dW[n][c][tap] = sum_t dpre[t][n] x[t - d (1 - tap)][c]
             {
@@ -276,17 +284,19 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
                 a.A[0] = APart{DPRE, 2 * kC, 0, 2 * kC, DPRE16}; a.nparts = 1; a.Ktot = 2 * kC;
                 a.B = xs_i; a.ldb = kC; a.N = kC; a.M = M; a.T = T; a.rows_per_chunk = RPC; a.part = PART; a.part_capacity = PART_CAP; a.bf16 = BT != nullptr;
                 a.bshift = 0;
-                if (BT) {  // both taps in one product: B = [x(t) | x(t - d)] stacked along n, dpre read once
+                if (BT) {  // both taps in one product: B = [x(t) | x(t - d)] stacked along n, dpre read once,
+                           // with the bias gradient (column sums of dpre)
                     a.B16 = (const uint16_t*)xs_i;
                     a.N = 2 * kC; a.nbparts = 2; a.bshift1 = -d;
-                    HIPCHK(gemm_wgrad(a, WgradDst{grad + v.dil_w[l], nullptr, 0, 1, true}, st), "d dil.W");
+                    a.cpart = CPART; a.cpart_capacity = CPART_CAP;
+                    const WgradDst cd{grad + v.dil_b[l], nullptr, 2 * kC, 1, false};
+                    HIPCHK(gemm_wgrad(a, WgradDst{grad + v.dil_w[l], nullptr, 0, 1, true}, st, &cd), "d dil");
                 } else {
                     HIPCHK(gemm_wgrad(a, grad + v.dil_w[l] + 1, 2, st), "d dil.W tap1");
                     a.bshift = -d;
                     HIPCHK(gemm_wgrad(a, grad + v.dil_w[l], 2, st), "d dil.W tap0");
+                    HIPCHK(colsum(DPRE, 2 * kC, M, 2 * kC, nullptr, 0, 0, PART, PART_CAP, grad + v.dil_b[l], 1, st), "d dil.b");
                 }
-                if (BT) HIPCHK(colsum16(DPRE16, 2 * kC, M, 2 * kC, PART, PART_CAP, grad + v.dil_b[l], 1, st), "d dil.b");
-                else HIPCHK(colsum(DPRE, 2 * kC, M, 2 * kC, nullptr, 0, 0, PART, PART_CAP, grad + v.dil_b[l], 1, st), "d dil.b");
             }
             // dx = dx' + dpre[t] W1 + dpre[t+d] W0   (W_tap as [n][c]: dil.W[(n C + c) 2 + tap])
             {

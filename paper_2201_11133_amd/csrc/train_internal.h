@@ -60,10 +60,16 @@ struct WgradArgs {
     // rows, part 0 shifted by bshift and part 1 by bshift1
     int nbparts = 1;
     int bshift1 = 0;
+    // optional: also the column sums of A over the rows (the bias gradient of the layer whose
+    // weight gradient this is), per chunk in cpart [nchunks][Ktot] (cpart_capacity floats, room for
+    // the reduction's group sums included); A parts unshifted
+    float* cpart = nullptr;
+    int64_t cpart_capacity = 0;
 };
 
 // Where the reduced K x N weight gradient goes (accumulated with +=): element i = k N + n at
-// d0[i * stride] for i < split, else at d1[(i - split) * stride]; with taps (N = 2 C, B parts = the
+// d0[i * stride] for i < split, else at d1[(i - split) * stride] (a null d0 or d1 drops those
+// elements); with taps (N = 2 C, B parts = the
 // two conv taps, part 0 the unshifted one): (k, n) at d0[(k C + n % C) 2 + (n < C)], the layout
 // [n_out][c][tap] of a dilated conv weight.
 struct WgradDst {
@@ -78,7 +84,8 @@ hipError_t gemm_rows(const GemmRowsArgs& a, hipStream_t st);
 // dst (+)= reduced partials: out_mode 0 row-major [K][N]; 2: element (k, n) at dst[(k N + n) * 2]
 // (one tap of a conv weight [n_out][c][2])
 hipError_t gemm_wgrad(const WgradArgs& a, float* dst, int out_mode, hipStream_t st);
-hipError_t gemm_wgrad(const WgradArgs& a, const WgradDst& dst, hipStream_t st);
+// With a.cpart set, cdst receives the column sums of A (element k of the Ktot sums, mapped like dst).
+hipError_t gemm_wgrad(const WgradArgs& a, const WgradDst& dst, hipStream_t st, const WgradDst* cdst = nullptr);
 // dst[n * dst_stride] += sum_rows f(X[row][n]) * w[row * wstride]   (w optional, f = id or ReLU)
 hipError_t colsum(const float* X, int64_t ldx, int64_t M, int N, const float* w, int64_t wstride, int relu,
                   float* part, int64_t part_capacity, float* dst, int64_t dst_stride, hipStream_t st);

@@ -506,6 +506,9 @@ __global__ __launch_bounds__(256) void gemm_wgrad_bf16_kernel(WgradArgs a) {
 // columns of 8 rows as 16-byte words into LDS ([column][row], 144-byte columns: conflict-free
 // writes and fragment reads). Two LDS buffers, one barrier per step; the next step's rows are
 // loaded during the products. Wave (wk, wn) owns output rows 64 wk .. + 64 and columns 64 wn .. + 64.
+// With a.cpart, the blocks of the first column tile also sum their A tile's columns over the chunk's
+// rows (fp32 sums of the operand values as stored: fp32 rows before their rounding, bf16 rows
+// exactly): each staging thread over its rows in order, then over the 8 threads of a column group.
 constexpr int W2T = 128;                 // tile (k and n)
 constexpr int W2R = 64;                  // rows per step
 constexpr int W2LD = W2R * 2 + 16;       // bytes per LDS column
@@ -549,6 +552,8 @@ __global__ __launch_bounds__(256) void gemm_wgrad_t128_kernel(WgradArgs a) {
     }
     const int t2 = tid & 127, rg = t2 & 7, cm = t2 >> 3;   // rows 8 rg .. + 8, columns 8 cm .. + 8
     col += 8 * cm;
+    const bool csum = a.cpart != nullptr && isA && tile % ntn == 0;   // uniform per wave
+    float cs[8] = {};
     const int64_t wrow0 = (int64_t)chunk * a.T;           // the chunk's window
     const bool is16 = op.p16 != nullptr;
     // rows whose shifted source leaves the window read the unshifted row and are zeroed when staged
@@ -575,6 +580,12 @@ __global__ __launch_bounds__(256) void gemm_wgrad_t128_kernel(WgradArgs a) {
             const bool ok = (unsigned)(t + op.shift) < (unsigned)a.T;
             const u32x4 v = is16 ? raw[2 * j] : w2_bf16x8(raw[2 * j], raw[2 * j + 1]);
             w[j] = ok ? v : u32x4{0, 0, 0, 0};
+            if (csum && ok) {
+#pragma unroll
+                for (int c = 0; c < 8; ++c)
+                    cs[c] += is16 ? __uint_as_float((c & 1) ? (raw[2 * j][c >> 1] & 0xffff0000u) : (raw[2 * j][c >> 1] << 16))
+                                  : __uint_as_float(raw[2 * j + (c >> 2)][c & 3]);
+            }
         }
         // column c: rows (2q, 2q + 1) as one bf16 pair, q < 4
 #pragma unroll
@@ -626,6 +637,19 @@ __global__ __launch_bounds__(256) void gemm_wgrad_t128_kernel(WgradArgs a) {
                 out[(int64_t)k * a.N + n] = acc[i][c][e];
             }
         }
+    if (csum) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            cs[c] += __shfl_xor(cs[c], 1);
+            cs[c] += __shfl_xor(cs[c], 2);
+            cs[c] += __shfl_xor(cs[c], 4);
+        }
+        if (rg == 0) {
+            float* o = a.cpart + (int64_t)chunk * a.Ktot + k0 + 8 * cm;
+            *(float4*)o = make_float4(cs[0], cs[1], cs[2], cs[3]);
+            *(float4*)(o + 4) = make_float4(cs[4], cs[5], cs[6], cs[7]);
+        }
+    }
 }
 
 // dst[i * stride] += sum over chunks of part[chunk][i], i = k N + n, in two fixed-order stages:
@@ -652,7 +676,9 @@ __global__ __launch_bounds__(256) void reduce_parts_kernel(const float* part, in
         const int n = (int)(i - k * N), C = N / 2;
         dst = d.d0 + (k * C + n % C) * 2 + (n < C ? 1 : 0);
     } else {
-        dst = i < d.split ? d.d0 + i * d.stride : d.d1 + (i - d.split) * d.stride;
+        float* base = i < d.split ? d.d0 : d.d1;
+        if (!base) return;  // (a null destination drops these sums)
+        dst = i < d.split ? base + i * d.stride : base + (i - d.split) * d.stride;
     }
     *dst += s;
 }
@@ -949,7 +975,7 @@ hipError_t gemm_rows(const GemmRowsArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t gemm_wgrad(const WgradArgs& a0, const WgradDst& d, hipStream_t st) {
+hipError_t gemm_wgrad(const WgradArgs& a0, const WgradDst& d, hipStream_t st, const WgradDst* cdst) {
     WgradArgs a = a0;
     if ((a.B16 || a.A[0].p16 || (a.nparts > 1 && a.A[1].p16)) && !a.bf16) return hipErrorInvalidValue;
     if (a.nbparts < 1 || a.nbparts > 2 || a.N % a.nbparts) return hipErrorInvalidValue;
@@ -962,7 +988,10 @@ hipError_t gemm_wgrad(const WgradArgs& a0, const WgradDst& d, hipStream_t st) {
     }
     t128 = t128 && a.ldb % 8 == 0 && ((uintptr_t)(a.B16 ? (const void*)a.B16 : a.B) & 15) == 0;
     if (a.nbparts > 1 && !t128) return hipErrorInvalidValue;  // B parts: the tile kernel only
+    if (a.cpart && (!cdst || a.A[0].shift != 0 || (a.nparts > 1 && a.A[1].shift != 0))) return hipErrorInvalidValue;
+    if (!t128) a.cpart = nullptr;  // column sums by the separate kernels below
     const int nchunks = (int)((a.M + a.rows_per_chunk - 1) / a.rows_per_chunk);
+    if (a.cpart && (int64_t)nchunks * a.Ktot > a.cpart_capacity) return hipErrorInvalidValue;
     if (t128) {
         const int64_t blocks = (int64_t)((nchunks + 7) / 8) * 8 * (a.Ktot / W2T) * (a.N / W2T);
         hipLaunchKernelGGL(gemm_wgrad_t128_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
@@ -973,7 +1002,20 @@ hipError_t gemm_wgrad(const WgradArgs& a0, const WgradDst& d, hipStream_t st) {
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return reduce_parts(a.part, a.part_capacity, nchunks, (int64_t)a.Ktot * a.N, a.N, d, st);
+    e = reduce_parts(a.part, a.part_capacity, nchunks, (int64_t)a.Ktot * a.N, a.N, d, st);
+    if (e != hipSuccess || !cdst) return e;
+    if (a.cpart) return reduce_parts(a.cpart, a.cpart_capacity, nchunks, a.Ktot, a.Ktot, *cdst, st);
+    // column sums part by part (each part's first column maps below or above the split as a whole)
+    for (int p = 0, kb = 0; p < a.nparts; kb += a.A[p].K, ++p) {
+        const APart& q = a.A[p];
+        float* base = kb < cdst->split ? cdst->d0 : cdst->d1;
+        if (!base) continue;
+        float* dst = kb < cdst->split ? base + kb * cdst->stride : base + (kb - cdst->split) * cdst->stride;
+        e = q.p16 ? colsum16(q.p16, q.ld, a.M, q.K, a.part, a.part_capacity, dst, cdst->stride, st)
+                  : colsum(q.ptr, q.ld, a.M, q.K, nullptr, 0, 0, a.part, a.part_capacity, dst, cdst->stride, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t gemm_wgrad(const WgradArgs& a, float* dst, int out_mode, hipStream_t st) {
