@@ -206,26 +206,46 @@ def ragged_workload(gwd, blobs, prec: str):
                 x[lo:hi] += torch.from_numpy(synth.injection_signal(inj, lo / FS, hi - lo).astype(np.float32)).cuda()
         bufs.append(x)
     m = gwd.Model(gwd.full_arch(), blobs, prec)
-    rows, waves, fuse, batch, blocks = m.autotune([bufs[0][: 64 * FS]])
-    plan = m.plan(bufs, W, S, out_mode=0)
-    plan.launch()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    out = plan.launch()
+    rows, waves, fuse, batch, blocks, persistent = m.autotune([bufs[0][: 64 * FS]])
     offs = np.concatenate([[0], np.cumsum(lens)])
-    n_trig = len(gwd.triggers(out, offs, 0.9, 4096))
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    per, tot = plan.completion_us()
-    plan.close()
-    m.close()
     total_s = sum(lens) / FS
-    return {"streams": 32, "stream_seconds_total": round(total_s, 1), "strain_s_per_s": round(total_s / wall, 2),
-            "completion_s_p50": round(float(np.percentile(per, 50)) / 1e6, 3),
-            "completion_s_p99": round(float(np.percentile(per, 99)) / 1e6, 3),
-            "graph_total_s": round(tot / 1e6, 3), "autotune": {"tile_rows": rows, "waves": waves, "layers_per_launch": fuse, "batch_windows": batch,
-                                                           "fused_blocks": blocks},
-            "triggers": n_trig, "precision": prec}
+
+    def timed_plan():
+        plan = m.plan(bufs, W, S, out_mode=0)
+        plan.launch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = plan.launch()
+        n_trig = len(gwd.triggers(out, offs, 0.9, 4096))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        per, tot = plan.completion_us()
+        plan.close()
+        return wall, per, tot, n_trig, out.clone()
+
+    wall, per, tot, n_trig, out_a = timed_plan()
+    res = {"streams": 32, "stream_seconds_total": round(total_s, 1), "strain_s_per_s": round(total_s / wall, 2),
+           "completion_s_p50": round(float(np.percentile(per, 50)) / 1e6, 3),
+           "completion_s_p99": round(float(np.percentile(per, 99)) / 1e6, 3),
+           "graph_total_s": round(tot / 1e6, 3), "autotune": {"tile_rows": rows, "waves": waves, "layers_per_launch": fuse,
+                                                          "batch_windows": batch, "fused_blocks": blocks,
+                                                          "persistent": persistent},
+           "triggers": n_trig, "precision": prec}
+    # the other form of the same request: the persistent launch if the autotuner chose the launch
+    # sequence (fused launches, its fastest shape), else the launch sequence
+    m.set_persistent(not persistent)
+    if not persistent:
+        m.set_tiling(64, 4, 512, 3)
+        m.set_fused_blocks(0)
+    wall2, per2, tot2, n_trig2, out_b = timed_plan()
+    res["persistent_launch" if not persistent else "launch_sequence"] = {
+        "strain_s_per_s": round(total_s / wall2, 2),
+        "completion_s_p50": round(float(np.percentile(per2, 50)) / 1e6, 3),
+        "completion_s_p99": round(float(np.percentile(per2, 99)) / 1e6, 3),
+        "graph_total_s": round(tot2 / 1e6, 3), "triggers": n_trig2,
+        "scores_identical": bool(torch.equal(out_a, out_b))}
+    m.close()
+    return res
 
 
 def background_workload(gwd, blobs, x, prec: str, seconds: float = 900.0, n_slides: int = 4,

@@ -409,7 +409,8 @@ gwd_status gwd_adam_step(gwd_model* model, int32_t member, float* master, const 
  * it, "Optimization with TensorRT".)
  * gwd_plan_completion_us (after a launch; synchronises the device) gives, per
  * stream, the time from the plan's start to the end of the batch holding the
- * stream's last window, and the total, in microseconds. */
+ * stream's last window (persistent forward: to the end of the stream's last
+ * window to finish), and the total, in microseconds. */
 typedef struct gwd_plan gwd_plan;
 gwd_status gwd_plan_create(gwd_model* model, const gwd_stream* streams, int32_t n_streams, int32_t window,
                            int32_t stride, int32_t out_mode, float* out, int64_t out_capacity_floats,
@@ -446,19 +447,38 @@ gwd_status gwd_set_tiling(gwd_model* model, int32_t tile_rows, int32_t waves, in
  * GWD_ERR_UNSUPPORTED for other models. */
 gwd_status gwd_set_fused_blocks(gwd_model* model, int32_t blocks);
 
+/* Persistent forward (BF16/FP8 gated models, on = 1; 0 restores the launch
+ * sequence): gwd_forward and plans created afterwards run the whole request as
+ * one kernel launch over all members and all windows of all streams. Each
+ * block owns a window at a time (windows b, b + grid, ..., grid = two blocks
+ * per compute unit, at most one per window) and runs every member's layers
+ * (the fused launches' arithmetic over each whole interleaved sub-sequence, in
+ * buffers of the block's own) and head on it, the members in order; no block
+ * waits for another. Results are bit for bit those of the launch sequence.
+ * (The paper's engine is built once and replayed for every batch,
+ * "Optimization with TensorRT"; here the whole ragged request is one launch.)
+ * Needs every layer in a fused launch at the request's window (three layers
+ * per launch, windows up to 4096); gwd_forward returns GWD_ERR_UNSUPPORTED
+ * otherwise. It leaves the workspace without the batch layout that
+ * gwd_debug_time_layer reads. GWD_ERR_ARG unless on is 0 or 1;
+ * GWD_ERR_UNSUPPORTED for other models (FP32, small member, two-branch). */
+gwd_status gwd_set_persistent(gwd_model* model, int32_t on);
+
 /* Autotuner (the engine's kernel choice by profiling, "Optimization with
  * TensorRT"): times gwd_forward (out_mode 0) on the given request for every
  * schedule candidate (BF16/FP8: fused launches aiming at 512, 1024 and 2048
  * blocks, and the three tilings one layer per launch; all: batch 256, 512,
- * 1024 windows), keeps the fastest on the model and reports it (*fused_blocks
- * is 0 for schedules without fused launches; the pointer may be NULL). If the
- * environment variable GWD_AUTOTUNE_CACHE names a file, a cached choice for the
- * same (architecture, precision, members, window, stride) is used instead of
+ * 1024 windows; BF16/FP8 gated models where the window allows it: the
+ * persistent forward), keeps the fastest on the model and reports it
+ * (*fused_blocks is 0 for schedules without fused launches, *persistent 1 for
+ * the persistent forward; either pointer may be NULL). If the environment
+ * variable GWD_AUTOTUNE_CACHE names a file, a cached choice for the same
+ * (architecture, precision, members, window, stride) is used instead of
  * timing, and new choices are appended to it. Synchronises hip_stream. */
 gwd_status gwd_autotune(gwd_model* model, const gwd_stream* streams, int32_t n_streams, int32_t window,
                         int32_t stride, float* out, int64_t out_capacity_floats, int32_t* tile_rows,
                         int32_t* waves, int32_t* layers_per_launch, int32_t* batch_windows,
-                        int32_t* fused_blocks, void* hip_stream);
+                        int32_t* fused_blocks, int32_t* persistent, void* hip_stream);
 
 /* Last error message of the calling thread ("" if none). */
 const char* gwd_last_error(void);

@@ -213,6 +213,12 @@ gwd_status forward_prepare(gwd_model* m, const gwd_stream* streams, int32_t n_st
     if (nwin_out) *nwin_out = nwin;
     nb_max = 0;
     if (total_win == 0) return GWD_OK;
+    const bool persist = m->persistent;
+    if (persist && !persistent_supported(m, window)) {
+        set_error("gwd_forward: the persistent forward needs every layer in a fused launch (a gated BF16/FP8 model, "
+                  "three layers per launch, windows up to 4096); window %d", window);
+        return GWD_ERR_UNSUPPORTED;
+    }
     hipError_t e = hipSetDevice(m->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     // device table: one StreamDesc per stream, then the global index of every stream's first window
@@ -246,18 +252,43 @@ gwd_status forward_prepare(gwd_model* m, const gwd_stream* streams, int32_t n_st
             }
         }
     }
-    // workspace: stream table (sized for the largest table so far), then x ping-pong and skip
+    // workspace: stream table (sized for the largest table so far; then the persistent launch's
+    // tables), then x ping-pong and skip (persistent: the blocks' own buffers)
     const int64_t desc_bytes = (int64_t)n_streams * (int64_t)sizeof(StreamDesc);
     const int64_t first_bytes = (int64_t)firsts.size() * (int64_t)sizeof(int64_t);
-    const int64_t tab_bytes = std::max<int64_t>(m->ws_tab_bytes, (desc_bytes + first_bytes + 255) & ~255LL);
-    const int64_t act = m->arch.kind == 1 ? (int64_t)nb_max * window * kC * 4 : 0;
-    s = ensure_workspace(m, tab_bytes + 3 * act, st);
+    const int64_t stream_bytes = (desc_bytes + first_bytes + 255) & ~255LL;
+    const int64_t persist_bytes = persist ? persistent_table_bytes(m, window) : 0;
+    const int64_t tab_bytes = std::max<int64_t>(m->ws_tab_bytes, stream_bytes + persist_bytes);
+    int64_t act_bytes = m->arch.kind == 1 ? 3 * (int64_t)nb_max * window * kC * 4 : 0;
+    if (persist) {  // two blocks per compute unit, at most one per window
+        int n_cu = 0;
+        e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, m->device);
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+        m->persist_grid = (int)std::min<int64_t>(total_win, 2 * (int64_t)std::max(n_cu, 1));
+        act_bytes = m->persist_grid * persistent_block_bytes(window);
+    }
+    s = ensure_workspace(m, tab_bytes + act_bytes, st);
     if (s != GWD_OK) return s;
     m->ws_tab_bytes = tab_bytes;
-    std::vector<char> host_tab(desc_bytes + first_bytes);
+    std::vector<char> host_tab(persist ? stream_bytes + persist_bytes : desc_bytes + first_bytes);
     memcpy(host_tab.data(), tab.data(), desc_bytes);
     memcpy(host_tab.data() + desc_bytes, firsts.data(), first_bytes);
     StreamDesc* d_tab = (StreamDesc*)m->ws.base;
+    if (persist) {  // the launch tables point at the stream table and the request's output
+        FwdBatch pf{};
+        pf.streams = d_tab;
+        pf.n_streams = n_streams;
+        pf.T = window;
+        pf.S = stride;
+        pf.out_mode = out_mode;
+        pf.out = out;
+        pf.sum_L = sum_L;
+        pf.total_win = total_win;
+        std::vector<char> pt;
+        persistent_tables(m, pf, pt);
+        memcpy(host_tab.data() + stream_bytes, pt.data(), pt.size());
+        m->persist_tab_off = stream_bytes;
+    }
     if (sync_table) {
         e = hipStreamSynchronize(st);
         if (e == hipSuccess) e = hipMemcpy(d_tab, host_tab.data(), host_tab.size(), hipMemcpyHostToDevice);
@@ -266,7 +297,7 @@ gwd_status forward_prepare(gwd_model* m, const gwd_stream* streams, int32_t n_st
         e = hipMemcpyAsync(d_tab, host_tab.data(), host_tab.size(), hipMemcpyHostToDevice, st);
     }
     if (e != hipSuccess) return hip_fail(e, "stream table upload");
-    m->last_nb = nb_max;
+    m->last_nb = persist ? 0 : nb_max;   // (the persistent buffers are not the batch layout)
     m->last_T = window;
     fb.streams = d_tab;
     fb.firsts = (const int64_t*)((const char*)d_tab + desc_bytes);
@@ -284,8 +315,13 @@ gwd_status forward_prepare(gwd_model* m, const gwd_stream* streams, int32_t n_st
 hipError_t forward_enqueue(gwd_model* m, FwdBatch fb, int64_t total_win, int nb_max, hipStream_t st,
                            hipError_t (*after_batch)(void*, int64_t, hipStream_t), void* ctx) {
     const int64_t tab_bytes = m->ws_tab_bytes;
-    const int64_t act = m->arch.kind == 1 ? (int64_t)nb_max * fb.T * kC * 4 : 0;
     char* base = (char*)m->ws.base;
+    if (m->persistent) {  // one launch for every window and member
+        hipError_t e = launch_persistent(m, fb, base + m->persist_tab_off, base + tab_bytes, m->persist_grid, fb.done, st);
+        if (e == hipSuccess && after_batch) e = after_batch(ctx, 0, st);
+        return e;
+    }
+    const int64_t act = m->arch.kind == 1 ? (int64_t)nb_max * fb.T * kC * 4 : 0;
     float* x_a = (float*)(base + tab_bytes);
     float* x_b = (float*)(base + tab_bytes + act);
     float* skip = (float*)(base + tab_bytes + 2 * act);

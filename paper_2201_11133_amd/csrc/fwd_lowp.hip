@@ -21,7 +21,11 @@
 //   64 x 4 (RB 2, 4 waves/SIMD, phase 2 in two passes: residual columns, then skip columns)
 //   64 x 8 (RB 1, 4 waves/SIMD, two passes)
 //   128 x 4 (RB 4, 2 waves/SIMD, one pass: each operand fragment feeds both column blocks)
+#include <algorithm>
+#include <vector>
+
 #include "gwd_internal.h"
+#include "head_common.h"
 #include "layer_common.h"
 
 namespace gwd {
@@ -468,6 +472,20 @@ struct FusedArgs {
 
 __device__ inline uint8_t* fu_buf(uint8_t* lds, int j) { return lds + (j == 0 ? FU_B0 : j == 1 ? FU_B1 : FU_B2); }
 
+// What one block of a fused launch reads and writes besides the launch's arguments: the residual
+// stream and skip sum of its windows, the global index of the first of them, and the block's
+// index within the launch. A fused kernel takes its own launch's (read where they are used, as
+// kernel arguments); the persistent kernel passes its per-block buffers and the window it owns.
+struct LaunchIO {
+    const FusedArgs& p;
+    __device__ const uint16_t* x_in() const { return p.x_in; }
+    __device__ uint16_t* x_out() const { return p.x_out; }
+    __device__ float* skip() const { return p.skip; }
+    __device__ int64_t win_base() const { return p.win_base; }
+    __device__ unsigned bid() const { return blockIdx.x; }
+};
+
+
 // Sixteen fp32 values of one 32-channel block in the transposed accumulator layout (see
 // fused_bf16_kernel): element 4 g + e is channel 8 g + e of b, where b already points at the
 // block's first channel + 4 h.
@@ -530,18 +548,17 @@ struct ChunkRows {
 // then takes only the k-steps of its own group's input channels, since the others multiply zeros.
 // DBG: test-support instantiation that also writes every layer's pre-activation, residual output and
 // running skip sum of the stored rows to the dbg_* buffers (the arithmetic is unchanged).
-template <bool FROM_STREAM, bool SKIP_INIT, int NL, bool LAST, bool G2, bool DBG = false>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void fused_bf16_kernel(FusedArgs p) {
+template <bool FROM_STREAM, bool SKIP_INIT, int NL, bool LAST, bool G2, bool DBG, class IO, class FA>
+__device__ __forceinline__ void fused_bf16_body(const FA& p, const IO& io, uint8_t* lds) {
     static_assert(NL == 3 || NL == 4, "three or four layers");
     static_assert(!LAST || NL == 4, "the network's last layer ends a quad");
     using T = LP<false, 2, 4>;  // bf16 fragments, 4 waves x 2 row blocks
-    __shared__ __attribute__((aligned(16))) uint8_t lds[FU_LDS];
     uint8_t* G = lds + FU_GB;
     float* BI = (float*)(lds + FU_BI);
     const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6, h = lane >> 5, r = lane & 31;
-    const int seg = blockIdx.x % p.n_seg;
-    const int cls = (blockIdx.x / p.n_seg) % p.d0;
-    const int b = blockIdx.x / (p.n_seg * p.d0);
+    const int seg = io.bid() % p.n_seg;
+    const int cls = (io.bid() / p.n_seg) % p.d0;
+    const int b = io.bid() / (p.n_seg * p.d0);
     const int n_sub = (p.T - cls + p.d0 - 1) / p.d0;  // rows of this sub-sequence
     const int n_ch = (n_sub + FU_ROWS - 1) / FU_ROWS;
     const int c0 = seg * p.seg_chunks;
@@ -551,7 +568,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
     StreamDesc sd{};
     int64_t start = 0;
     if (FROM_STREAM) {
-        const int64_t gw = p.win_base + b;
+        const int64_t gw = io.win_base() + b;
         sd = p.streams[find_stream(p.streams, p.n_streams, gw)];
         start = (gw - sd.win_begin) * p.S;
     }
@@ -598,7 +615,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                     cr.u[it][1] = sd.ch1[smp * sd.stride];
                 }
             } else {
-                cr.v[it] = sr < n_sub ? *(const uint4*)&p.x_in[(wrow0 + t) * kC + c8] : make_uint4(0, 0, 0, 0);
+                cr.v[it] = sr < n_sub ? *(const uint4*)&io.x_in()[(wrow0 + t) * kC + c8] : make_uint4(0, 0, 0, 0);
             }
         }
     };
@@ -749,7 +766,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                 for (int rb = 0; rb < 2; ++rb) {
                     const int sr = sb + 32 * rb + r;
                     sk[rb] = splat16(0.f);
-                    if (!SKIP_INIT && store && sr < n_sub) sk[rb] = load_col16(p.skip + (wrow0 + cls + (int64_t)p.d0 * sr) * kC + cb);
+                    if (!SKIP_INIT && store && sr < n_sub) sk[rb] = load_col16(io.skip() + (wrow0 + cls + (int64_t)p.d0 * sr) * kC + cb);
                 }
             }
             // ---- gate -> G: per row block, four 8-byte writes of four channels
@@ -873,17 +890,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                 const int idx = tid + 256 * it, rr = idx >> 4, c8 = 8 * (idx & 15);
                 const int sr = sb + rr;
                 if (sr < n_sub)
-                    *(uint4*)&p.x_out[(wrow0 + cls + p.d0 * sr) * kC + c8] = *(const uint4*)(XL + rr * FU_XROW + 2 * c8);
+                    *(uint4*)&io.x_out()[(wrow0 + cls + p.d0 * sr) * kC + c8] = *(const uint4*)(XL + rr * FU_XROW + 2 * c8);
             }
 #pragma unroll
             for (int rb = 0; rb < 2; ++rb) {
                 const int sr = sb + 32 * rb + r;
-                if (sr < n_sub) store_col16(p.skip + (wrow0 + cls + (int64_t)p.d0 * sr) * kC + cb, sk[rb]);
+                if (sr < n_sub) store_col16(io.skip() + (wrow0 + cls + (int64_t)p.d0 * sr) * kC + cb, sk[rb]);
             }
         }
         __syncthreads();  // the output buffer is read above before the next chunk stages into buffer 0
     }
 }
+
+template <bool FROM_STREAM, bool SKIP_INIT, int NL, bool LAST, bool G2, bool DBG = false>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void fused_bf16_kernel(FusedArgs p) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds[FU_LDS];
+    fused_bf16_body<FROM_STREAM, SKIP_INIT, NL, LAST, G2, DBG>(p, LaunchIO{p}, lds);
+}
+
 
 template <bool FP8>
 static LayerArgsLP lp_args(gwd_model* m, int member, int l) {
@@ -933,19 +957,18 @@ __device__ inline uint32_t bf16x4_to_e4m3(uint2 w) { return bf16x2_to_e4m3(w.x) 
 // G2 as in the BF16 kernel: one k-step covers 64 input channels, i.e. one group, so a wave of group
 // q / 2 takes steps q / 2 and 2 + q / 2 of the first phase and step q / 2 of the second.
 // DBG as in the BF16 kernel.
-template <bool FROM_STREAM, bool SKIP_INIT, int NL, bool LAST, bool G2, bool DBG = false>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void fused_fp8_kernel(FusedArgs p) {
+template <bool FROM_STREAM, bool SKIP_INIT, int NL, bool LAST, bool G2, bool DBG, class IO, class FA>
+__device__ __forceinline__ void fused_fp8_body(const FA& p, const IO& io, uint8_t* lds) {
     static_assert(NL == 3 || NL == 4, "three or four layers");
     static_assert(!LAST || NL == 4, "the network's last layer ends a quad");
     using T = LP<true, 2, 4>;  // E4M3 fragments (32 bytes per lane), 4 waves x 2 row blocks
-    __shared__ __attribute__((aligned(16))) uint8_t lds[FX_LDS];
     uint8_t* G = lds + FX_G;
     uint8_t* XS = lds + FX_XS;
     float* BI = (float*)(lds + FX_BI);
     const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6, h = lane >> 5, r = lane & 31;
-    const int seg = blockIdx.x % p.n_seg;
-    const int cls = (blockIdx.x / p.n_seg) % p.d0;
-    const int b = blockIdx.x / (p.n_seg * p.d0);
+    const int seg = io.bid() % p.n_seg;
+    const int cls = (io.bid() / p.n_seg) % p.d0;
+    const int b = io.bid() / (p.n_seg * p.d0);
     const int n_sub = (p.T - cls + p.d0 - 1) / p.d0;  // rows of this sub-sequence
     const int n_ch = (n_sub + FU_ROWS - 1) / FU_ROWS;
     const int c0 = seg * p.seg_chunks;
@@ -955,7 +978,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
     StreamDesc sd{};
     int64_t start = 0;
     if (FROM_STREAM) {
-        const int64_t gw = p.win_base + b;
+        const int64_t gw = io.win_base() + b;
         sd = p.streams[find_stream(p.streams, p.n_streams, gw)];
         start = (gw - sd.win_begin) * p.S;
     }
@@ -989,7 +1012,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                     cr.u[it][1] = sd.ch1[smp * sd.stride];
                 }
             } else {
-                cr.v[it] = sr < n_sub ? *(const uint4*)&p.x_in[(wrow0 + t) * kC + c8] : make_uint4(0, 0, 0, 0);
+                cr.v[it] = sr < n_sub ? *(const uint4*)&io.x_in()[(wrow0 + t) * kC + c8] : make_uint4(0, 0, 0, 0);
             }
         }
     };
@@ -1094,7 +1117,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                 for (int rb = 0; rb < 2; ++rb) {
                     const int sr = sb + 32 * rb + r;
                     sk[rb] = splat16(0.f);
-                    if (!SKIP_INIT && store && sr < n_sub) sk[rb] = load_col16(p.skip + (wrow0 + cls + (int64_t)p.d0 * sr) * kC + cb);
+                    if (!SKIP_INIT && store && sr < n_sub) sk[rb] = load_col16(io.skip() + (wrow0 + cls + (int64_t)p.d0 * sr) * kC + cb);
                 }
             }
             // ---- gate: pre = acc * scale + bias, g = tanh * sigmoid -> E4M3 codes in G (4 channels per word)
@@ -1231,17 +1254,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
                 const int idx = tid + 256 * it, rr = idx >> 4, c8 = 8 * (idx & 15);
                 const int sr = sb + rr;
                 if (sr < n_sub)
-                    *(uint4*)&p.x_out[(wrow0 + cls + p.d0 * sr) * kC + c8] = *(const uint4*)(XS + rr * FU_XROW + 2 * c8);
+                    *(uint4*)&io.x_out()[(wrow0 + cls + p.d0 * sr) * kC + c8] = *(const uint4*)(XS + rr * FU_XROW + 2 * c8);
             }
 #pragma unroll
             for (int rb = 0; rb < 2; ++rb) {
                 const int sr = sb + 32 * rb + r;
-                if (sr < n_sub) store_col16(p.skip + (wrow0 + cls + (int64_t)p.d0 * sr) * kC + cb, sk[rb]);
+                if (sr < n_sub) store_col16(io.skip() + (wrow0 + cls + (int64_t)p.d0 * sr) * kC + cb, sk[rb]);
             }
         }
         __syncthreads();  // the staging buffer is read above before the next chunk stages into it
     }
 }
+
+template <bool FROM_STREAM, bool SKIP_INIT, int NL, bool LAST, bool G2, bool DBG = false>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void fused_fp8_kernel(FusedArgs p) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds[FX_LDS];
+    fused_fp8_body<FROM_STREAM, SKIP_INIT, NL, LAST, G2, DBG>(p, LaunchIO{p}, lds);
+}
+
 
 // Layers covered by the fused launch that starts at layer l for windows of length T: 0 (l is not a
 // start), 3, or 4. Triples start at stack positions 0, 3, 6; the triple at 6 also takes the stack's
@@ -1581,6 +1611,229 @@ hipError_t layer_debug_bf16(gwd_model* m, int member, int l, const float* x_in, 
 hipError_t layer_debug_fp8(gwd_model* m, int member, int l, const float* x_in, int nb, int T, float* pre_out,
                            float* x_out, float* skip, hipStream_t st) {
     return debug_lp<true>(m, member, l, x_in, nb, T, pre_out, x_out, skip, st);
+}
+
+// ---------------------------------------------------------------- persistent forward
+// One launch for every member and every window of every stream (per-block window ownership): block
+// b takes windows b, b + grid, ... and runs the whole network of each member on its window, the
+// members in order, then the head over the rows the window owns. The fused launches become loops
+// over the window's sub-sequences (each whole, so no warm-up chunks), with the window's residual
+// stream (two bf16 buffers) and skip sum (fp32) in global buffers of the block's own; a barrier
+// separates consecutive pieces, since they share the LDS and read what the block wrote before. The
+// arithmetic of every row is that of the fused launches (same bodies, same order), so the results
+// are bit for bit those of the ordinary forward. Each window is finished by one block and every
+// stitched sample belongs to one window, so the ensemble minimum over members needs no
+// synchronisation between blocks. With done set, lane 0 records the wall clock after each window
+// as a running maximum per stream (the stream's completion time).
+struct PersistArgs {
+    const FusedArgs* launches;   // [members][n_launch]: one window's launch (n_seg = 1)
+    const HeadArgs* heads;       // [members]
+    const int32_t* kinds;        // [n_launch]: 0 first (stream input), 1 triple, 2 quad, 3 the network's last quad
+    int n_members, n_launch;
+    int64_t total_win;
+    const StreamDesc* streams;
+    int n_streams;
+    int T;
+    uint16_t* xbuf;              // per block: two bf16 [T][128]
+    float* skbuf;                // per block: fp32 [T][128]
+    unsigned long long* done;    // optional, [n_streams]
+};
+
+// The persistent kernel's view for piece `b` of launch `l` on window `w`: launch l writes the
+// block's buffer l % 2 and reads the other (the first launch reads the stream). The buffers are
+// formed from the kernel arguments where they are used, so that nothing but the indices stays live
+// across a piece.
+struct OwnedIO {
+    const PersistArgs& a;
+    int64_t w;
+    unsigned b;
+    int l;
+    __device__ uint16_t* buf(int i) const { return a.xbuf + ((int64_t)blockIdx.x * 2 + i) * a.T * kC; }
+    __device__ const uint16_t* x_in() const { return l == 0 ? nullptr : buf((l & 1) ^ 1); }
+    __device__ uint16_t* x_out() const { return buf(l & 1); }
+    __device__ float* skip() const { return a.skbuf + (int64_t)blockIdx.x * a.T * kC; }
+    __device__ int64_t win_base() const { return w; }
+    __device__ unsigned bid() const { return b; }
+};
+
+// The launch tables are read through the constant address space: the compiler may then load a
+// field again wherever it is used instead of holding it in a register across the piece (as it
+// does with kernel arguments), which keeps the bodies within their register budget.
+typedef __attribute__((address_space(4))) const FusedArgs ConstFusedArgs;
+
+template <bool FP8>
+__device__ __forceinline__ void persistent_piece(int kind, const ConstFusedArgs& p, const OwnedIO& io, uint8_t* lds) {
+    if constexpr (FP8) {
+        switch (kind) {
+            case 0: fused_fp8_body<true, true, 3, false, false, false>(p, io, lds); break;
+            case 1: fused_fp8_body<false, false, 3, false, false, false>(p, io, lds); break;
+            case 2: fused_fp8_body<false, false, 4, false, false, false>(p, io, lds); break;
+            default: fused_fp8_body<false, false, 4, true, false, false>(p, io, lds); break;
+        }
+    } else {
+        switch (kind) {
+            case 0: fused_bf16_body<true, true, 3, false, false, false>(p, io, lds); break;
+            case 1: fused_bf16_body<false, false, 3, false, false, false>(p, io, lds); break;
+            case 2: fused_bf16_body<false, false, 4, false, false, false>(p, io, lds); break;
+            default: fused_bf16_body<false, false, 4, true, false, false>(p, io, lds); break;
+        }
+    }
+}
+
+// Little stays live across a piece (the bodies need nearly every register): the window, member,
+// launch and piece indices; the buffers follow from the block index and the launch's parity, and
+// the window's stream is looked up again for the head.
+template <bool FP8>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void persistent_forward_kernel(PersistArgs a) {
+    constexpr int LDS = FP8 ? FX_LDS : FU_LDS;
+    static_assert(LDS >= (kBM * kHS + 4 * kBM) * 4, "the head's tile fits the fused launches' LDS");
+    __shared__ __attribute__((aligned(16))) uint8_t lds[LDS];
+    for (int64_t w = blockIdx.x; w < a.total_win; w += gridDim.x) {
+        for (int m = 0; m < a.n_members; ++m) {
+            for (int l = 0; l < a.n_launch; ++l) {
+                const ConstFusedArgs& p = ((const ConstFusedArgs*)a.launches)[m * a.n_launch + l];
+                const unsigned pieces = (unsigned)(p.d0 * p.n_seg);
+                for (unsigned bid = 0; bid < pieces; ++bid) {
+                    persistent_piece<FP8>(a.kinds[l], p, OwnedIO{a, w, bid, l}, lds);
+                    __syncthreads();
+                }
+            }
+            const int si = find_stream(a.streams, a.n_streams, w);
+            const StreamDesc sd = a.streams[si];
+            const int64_t k = w - sd.win_begin;
+            const HeadArgs& hp = a.heads[m];
+            int lo, hi;
+            owner_rows(hp.o, k, sd.length, lo, hi);
+            const float* sk = a.skbuf + (int64_t)blockIdx.x * a.T * kC;
+            for (int t0 = (lo / kBM) * kBM; t0 < hi; t0 += kBM)
+                head_tile(hp, sd, w, k, t0, lo, hi, sk, (float*)lds, (float(*)[kBM])(lds + kBM * kHS * 4));
+            __syncthreads();
+        }
+        if (a.done && threadIdx.x == 0)
+            atomicMax(a.done + find_stream(a.streams, a.n_streams, w), (unsigned long long)wall_clock64());
+    }
+}
+
+// The network's launches for windows of length T: true when every layer lies in a fused launch
+// (windows up to 4096: the quads need one-chunk sub-sequences), the only form the persistent
+// kernel runs.
+bool persistent_supported(const gwd_model* m, int T) {
+    if (m->arch.kind != 1 || m->two_branch || (m->prec != GWD_BF16 && m->prec != GWD_FP8_E4M3) || m->lp_fuse != 3)
+        return false;
+    const int L = m->arch.n_stacks * m->arch.layers_per_stack;
+    for (int l = 0; l < L;) {
+        const int nl = fused_layers(m, l, T);
+        if (nl == 0) return false;
+        l += nl;
+    }
+    return true;
+}
+
+int64_t persistent_table_bytes(const gwd_model* m, int T) {
+    const int L = m->arch.n_stacks * m->arch.layers_per_stack;
+    int n_launch = 0;
+    for (int l = 0; l < L; ++n_launch) l += std::max(1, fused_layers(m, l, T));
+    const int64_t bytes = (int64_t)m->n_members * n_launch * sizeof(FusedArgs) + (int64_t)m->n_members * sizeof(HeadArgs) +
+                          (int64_t)n_launch * sizeof(int32_t);
+    return (bytes + 255) & ~255LL;
+}
+
+// Per-block buffers of the persistent kernel (bytes per block).
+int64_t persistent_block_bytes(int T) { return (int64_t)T * kC * (2 * 2 + 4); }
+
+// The launch and head tables of a request, as host bytes to be uploaded to d_tables (their device
+// address): every member's fused launches over one window, and its head with the request's output
+// descriptor.
+void persistent_tables(gwd_model* m, const FwdBatch& fb, std::vector<char>& host) {
+    const int L = m->arch.n_stacks * m->arch.layers_per_stack;
+    std::vector<int> starts;
+    for (int l = 0; l < L;) {
+        starts.push_back(l);
+        l += fused_layers(m, l, fb.T);
+    }
+    const int n_launch = (int)starts.size();
+    host.assign(persistent_table_bytes(m, fb.T), 0);
+    FusedArgs* la = (FusedArgs*)host.data();
+    HeadArgs* ha = (HeadArgs*)(la + m->n_members * n_launch);
+    int32_t* kinds = (int32_t*)(ha + m->n_members);
+    const bool fp8 = m->prec == GWD_FP8_E4M3;
+    for (int mem = 0; mem < m->n_members; ++mem) {
+        for (int i = 0; i < n_launch; ++i) {
+            const int l = starts[i], nl = fused_layers(m, l, fb.T);
+            FusedArgs a{};
+            for (int j = 0; j < nl; ++j) {
+                const LayerArgsLP lp = fp8 ? lp_args<true>(m, mem, l + j) : lp_args<false>(m, mem, l + j);
+                a.wc[j] = lp.wc;
+                a.bc[j] = lp.bc;
+                a.wrs[j] = lp.wrs;
+                a.brs[j] = lp.brs;
+                a.sc[j] = lp.sc;
+                a.srs[j] = lp.srs;
+                if (j == 0) { a.w_in = lp.w_in; a.b_in = lp.b_in; }
+            }
+            a.d0 = 1 << (l % m->arch.layers_per_stack);
+            a.T = fb.T;
+            a.seg_chunks = ((fb.T + a.d0 - 1) / a.d0 + FU_ROWS - 1) / FU_ROWS;
+            a.n_seg = 1;
+            a.streams = fb.streams;
+            a.n_streams = fb.n_streams;
+            a.S = fb.S;
+            la[mem * n_launch + i] = a;
+            if (mem == 0) kinds[i] = l == 0 ? 0 : nl == 3 ? 1 : (l + 3 == L - 1 ? 3 : 2);
+        }
+        const MemberWeights& mw = m->members[mem];
+        const float* base = (const float*)mw.base;
+        HeadArgs h{};
+        h.h1w = base + mw.h1w;
+        h.h1b = base + mw.h1b;
+        h.h2w = base + mw.h2w;
+        h.h2b = base + mw.h2b;
+        h.mid_relu = m->arch.head_mid_relu;
+        h.streams = fb.streams;
+        h.n_streams = fb.n_streams;
+        h.o.out_mode = fb.out_mode;
+        h.o.member = mem;
+        h.o.T = fb.T;
+        h.o.S = fb.S;
+        h.o.out = fb.out;
+        h.o.sum_L = fb.sum_L;
+        h.o.total_win = fb.total_win;
+        ha[mem] = h;
+    }
+}
+
+__global__ void fill_u64_kernel(unsigned long long* p, int n) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+hipError_t launch_persistent(gwd_model* m, const FwdBatch& fb, const void* d_tables, void* act, int grid,
+                             unsigned long long* done, hipStream_t st) {
+    const int L = m->arch.n_stacks * m->arch.layers_per_stack;
+    int n_launch = 0;
+    for (int l = 0; l < L; ++n_launch) l += std::max(1, fused_layers(m, l, fb.T));
+    PersistArgs a{};
+    a.launches = (const FusedArgs*)d_tables;
+    a.heads = (const HeadArgs*)(a.launches + m->n_members * n_launch);
+    a.kinds = (const int32_t*)(a.heads + m->n_members);
+    a.n_members = m->n_members;
+    a.n_launch = n_launch;
+    a.total_win = fb.total_win;
+    a.streams = fb.streams;
+    a.n_streams = fb.n_streams;
+    a.T = fb.T;
+    a.xbuf = (uint16_t*)act;
+    a.skbuf = (float*)((char*)act + (int64_t)grid * fb.T * kC * 2 * 2);
+    a.done = done;
+    if (done) {  // a fill kernel, not a memset: plans capture this into a graph
+        hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)((fb.n_streams + 255) / 256)), dim3(256), 0, st, done,
+                           fb.n_streams);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (m->prec == GWD_FP8_E4M3) hipLaunchKernelGGL(persistent_forward_kernel<true>, dim3(grid), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(persistent_forward_kernel<false>, dim3(grid), dim3(256), 0, st, a);
+    return hipGetLastError();
 }
 
 }  // namespace gwd

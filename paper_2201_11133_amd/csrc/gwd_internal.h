@@ -110,6 +110,9 @@ struct gwd_model {
     int64_t* branch_map = nullptr;             // kind 2: device [branch_params], trunk index of each branch parameter
     float* dense_grad = nullptr;               // kind 2: device [n_params], the trunk gradient before read-back
     void* repack_tab = nullptr;                // device per-layer offsets of the on-device weight refresh (gwd_adam_step)
+    bool persistent = false;                   // BF16/FP8: the forward as one persistent launch (gwd_set_persistent)
+    int32_t persist_grid = 0;                  // its blocks, and its tables' offset in the workspace (forward_prepare)
+    int64_t persist_tab_off = 0;
     // test support (gwd_debug_capture_backward): gated layer whose backward operands and results the
     // next gwd_backward copies out as fp32 [M][C] ([M][2C] for pre and dpre); -1 = off
     int32_t cap_layer = -1;
@@ -147,6 +150,7 @@ struct FwdBatch {
     const int64_t* firsts;  // device: global index of each stream's first window (streams with windows)
     int64_t first_idx;      // first entry of `firsts` inside this batch
     int n_first;            // entries of `firsts` inside this batch
+    unsigned long long* done;  // persistent forward (optional): per stream, the wall clock at completion
 };
 
 hipError_t launch_tiny_forward(const gwd_model* m, const FwdBatch& fb, hipStream_t st);
@@ -187,6 +191,16 @@ gwd_status forward_prepare(gwd_model* m, const gwd_stream* streams, int32_t n_st
 hipError_t forward_enqueue(gwd_model* m, FwdBatch fb, int64_t total_win, int nb_max, hipStream_t st,
                            hipError_t (*after_batch)(void*, int64_t, hipStream_t), void* ctx);
 hipError_t launch_stamp(unsigned long long* slot, hipStream_t st);
+
+// Persistent forward (fwd_lowp.hip): whether a model runs it at window length T, the size of its
+// launch tables and per-block buffers, the tables of a request (host bytes for the device address
+// they are uploaded to), and the launch.
+bool persistent_supported(const gwd_model* m, int T);
+int64_t persistent_table_bytes(const gwd_model* m, int T);
+int64_t persistent_block_bytes(int T);
+void persistent_tables(gwd_model* m, const FwdBatch& fb, std::vector<char>& host);
+hipError_t launch_persistent(gwd_model* m, const FwdBatch& fb, const void* d_tables, void* act, int grid,
+                             unsigned long long* done, hipStream_t st);
 
 // Triggers (triggers.hip)
 struct TrigWork;

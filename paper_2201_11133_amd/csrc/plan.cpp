@@ -23,6 +23,7 @@ struct gwd_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     unsigned long long* stamps = nullptr;  // device [n_batches + 1]: start, then after each batch
+    unsigned long long* done = nullptr;    // persistent plans: device [n_streams], completion per stream
     gwd::Workspace ws;                     // the plan's own activations and stream table (the graph points into it)
     int64_t n_batches = 0;
     std::vector<int64_t> last_batch;       // per stream: batch holding its last window (-1: no windows)
@@ -81,14 +82,19 @@ gwd_status gwd_plan_create(gwd_model* m, const gwd_stream* streams, int32_t n_st
         return s;
     }
     p->model = m;
-    p->n_batches = (total_win + nb_max - 1) / nb_max;
+    // a persistent plan is one batch; its streams' completion times come from the kernel itself
+    p->n_batches = m->persistent ? 1 : (total_win + nb_max - 1) / nb_max;
     int64_t wb = 0;
     p->last_batch.assign(n_streams, -1);
     for (int i = 0; i < n_streams; ++i) {
-        if (nwin[i] > 0) p->last_batch[i] = (wb + nwin[i] - 1) / nb_max;
+        if (nwin[i] > 0) p->last_batch[i] = m->persistent ? 0 : (wb + nwin[i] - 1) / nb_max;
         wb += nwin[i];
     }
     e = hipMalloc((void**)&p->stamps, (p->n_batches + 1) * sizeof(unsigned long long));
+    if (e == hipSuccess && m->persistent) {
+        e = hipMalloc((void**)&p->done, n_streams * sizeof(unsigned long long));
+        fb.done = p->done;
+    }
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
@@ -120,10 +126,12 @@ gwd_status gwd_plan_launch(gwd_plan* p, void* hip_stream) {
 gwd_status gwd_plan_completion_us(gwd_plan* p, double* per_stream_us, int32_t n_streams, double* total_us) {
     if (!p || !per_stream_us || !total_us) { set_error("gwd_plan_completion_us: NULL argument"); return GWD_ERR_ARG; }
     if (n_streams != (int32_t)p->last_batch.size()) { set_error("gwd_plan_completion_us: n_streams mismatch"); return GWD_ERR_ARG; }
-    std::vector<unsigned long long> st(p->n_batches + 1);
+    std::vector<unsigned long long> st(p->n_batches + 1), done(p->done ? n_streams : 0);
     hipError_t e = hipSetDevice(p->model->device);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e == hipSuccess) e = hipMemcpy(st.data(), p->stamps, st.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && p->done)
+        e = hipMemcpy(done.data(), p->done, done.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost);
     int khz = 0;
     if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, p->model->device);
     if (e != hipSuccess) return hip_fail(e, "plan stamps");
@@ -131,7 +139,8 @@ gwd_status gwd_plan_completion_us(gwd_plan* p, double* per_stream_us, int32_t n_
     const double us_per_tick = 1e3 / (double)khz;
     for (int i = 0; i < n_streams; ++i) {
         const int64_t b = p->last_batch[i];
-        per_stream_us[i] = b < 0 ? 0.0 : (double)(st[b + 1] - st[0]) * us_per_tick;
+        const unsigned long long end = p->done ? done[i] : (b < 0 ? st[0] : st[b + 1]);
+        per_stream_us[i] = b < 0 ? 0.0 : (double)(end - st[0]) * us_per_tick;
     }
     *total_us = (double)(st[p->n_batches] - st[0]) * us_per_tick;
     return GWD_OK;
@@ -143,6 +152,7 @@ void gwd_plan_free(gwd_plan* p) {
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->stamps) (void)hipFree(p->stamps);
+    if (p->done) (void)hipFree(p->done);
     if (p->ws.base) (void)hipFree(p->ws.base);
     delete p;
 }
@@ -181,15 +191,27 @@ gwd_status gwd_set_fused_blocks(gwd_model* m, int32_t blocks) {
     return GWD_OK;
 }
 
+gwd_status gwd_set_persistent(gwd_model* m, int32_t on) {
+    if (!m) { set_error("gwd_set_persistent: model is NULL"); return GWD_ERR_ARG; }
+    if (on != 0 && on != 1) { set_error("gwd_set_persistent: on must be 0 or 1"); return GWD_ERR_ARG; }
+    if (on && !(m->arch.kind == 1 && !m->two_branch && (m->prec == GWD_BF16 || m->prec == GWD_FP8_E4M3))) {
+        set_error("gwd_set_persistent: the persistent forward is for gated (kind 1) BF16/FP8 models");
+        return GWD_ERR_UNSUPPORTED;
+    }
+    m->persistent = on != 0;
+    return GWD_OK;
+}
+
 namespace {
 struct Sched {
-    int rows, waves, fuse, blocks;
+    int rows, waves, fuse, blocks, persist;
 };
 }  // namespace
 
 gwd_status gwd_autotune(gwd_model* m, const gwd_stream* streams, int32_t n_streams, int32_t window, int32_t stride,
                         float* out, int64_t out_capacity_floats, int32_t* rows_out, int32_t* waves_out,
-                        int32_t* fuse_out, int32_t* batch_out, int32_t* blocks_out, void* hip_stream) {
+                        int32_t* fuse_out, int32_t* batch_out, int32_t* blocks_out, int32_t* persistent_out,
+                        void* hip_stream) {
     if (!m || !rows_out || !waves_out || !fuse_out || !batch_out) { set_error("gwd_autotune: NULL argument"); return GWD_ERR_ARG; }
     hipStream_t st = (hipStream_t)hip_stream;
     const char* cache = getenv("GWD_AUTOTUNE_CACHE");
@@ -197,20 +219,22 @@ gwd_status gwd_autotune(gwd_model* m, const gwd_stream* streams, int32_t n_strea
     snprintf(key, sizeof key, "gfx950 kind%d prec%d members%d W%d S%d", m->arch.kind, (int)m->prec, m->n_members,
              window, stride);
     const bool lowp = m->arch.kind == 1 && (m->prec == GWD_BF16 || m->prec == GWD_FP8_E4M3);
-    if (cache) {  // "key rows waves layers_per_launch batch fused_blocks" lines
+    if (cache) {  // "key rows waves layers_per_launch batch fused_blocks persistent" lines
         if (FILE* f = fopen(cache, "r")) {
             char line[256];
             while (fgets(line, sizeof line, f)) {
-                int rw = 0, w = 0, fu = 0, b = 0, fb = 0;
+                int rw = 0, w = 0, fu = 0, b = 0, fb = 0, pe = 0;
                 const size_t kl = strlen(key);
                 if (strncmp(line, key, kl) == 0 && line[kl] == ' ' &&
-                    sscanf(line + kl, " %d %d %d %d %d", &rw, &w, &fu, &b, &fb) >= 4) {
+                    sscanf(line + kl, " %d %d %d %d %d %d", &rw, &w, &fu, &b, &fb, &pe) >= 4) {
                     fclose(f);
                     gwd_status s = gwd_set_tiling(m, rw, w, fu, b);
                     if (s == GWD_OK && lowp) s = gwd_set_fused_blocks(m, fb);
+                    if (s == GWD_OK && lowp) s = gwd_set_persistent(m, pe);
                     if (s == GWD_OK) {
                         *rows_out = rw; *waves_out = w; *fuse_out = fu; *batch_out = b;
                         if (blocks_out) *blocks_out = fb;
+                        if (persistent_out) *persistent_out = pe;
                     }
                     return s;
                 }
@@ -218,10 +242,18 @@ gwd_status gwd_autotune(gwd_model* m, const gwd_stream* streams, int32_t n_strea
             fclose(f);
         }
     }
-    // candidates: fused launches (64-row chunks, 4 waves) aiming at 512, 1024 or 2048 blocks, and one
-    // layer per launch in each tiling; each at three batch sizes
-    std::vector<Sched> cand = {{0, 0, 1, 0}};
-    if (lowp) cand = {{64, 4, 3, 512}, {64, 4, 3, 1024}, {64, 4, 3, 2048}, {64, 4, 1, 0}, {64, 8, 1, 0}, {128, 4, 1, 0}};
+    // candidates: fused launches (64-row chunks, 4 waves) aiming at 512, 1024 or 2048 blocks, one
+    // layer per launch in each tiling, each at three batch sizes; and the persistent forward (one
+    // launch, where every layer is in a fused launch at this window; its batch size is moot)
+    std::vector<Sched> cand = {{0, 0, 1, 0, 0}};
+    if (lowp) cand = {{64, 4, 3, 512, 0}, {64, 4, 3, 1024, 0}, {64, 4, 3, 2048, 0}, {64, 4, 1, 0, 0}, {64, 8, 1, 0, 0},
+                      {128, 4, 1, 0, 0}};
+    if (lowp && !m->two_branch) {
+        const int32_t fuse0 = m->lp_fuse;
+        m->lp_fuse = 3;
+        if (persistent_supported(m, window)) cand.push_back({64, 4, 3, 0, 1});
+        m->lp_fuse = fuse0;
+    }
     const int batch_opts[] = {256, 512, 1024};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipSetDevice(m->device);
@@ -229,15 +261,17 @@ gwd_status gwd_autotune(gwd_model* m, const gwd_stream* streams, int32_t n_strea
     if (e == hipSuccess) e = hipEventCreate(&e1);
     if (e != hipSuccess) return hip_fail(e, "autotune events");
     float best = 1e30f;
-    Sched bs{m->lp_rows, m->lp_waves, m->lp_fuse, m->fused_blocks};
+    Sched bs{m->lp_rows, m->lp_waves, m->lp_fuse, m->fused_blocks, m->persistent ? 1 : 0};
     int bb = m->batch_windows;
     gwd_status s = GWD_OK;
     for (const Sched& c : cand) {
         for (int b : batch_opts) {
+            if (c.persist && b != 512) continue;
             m->lp_rows = c.rows;
             m->lp_waves = c.waves;
             m->lp_fuse = c.fuse;
             m->fused_blocks = c.blocks;
+            m->persistent = c.persist != 0;
             m->batch_windows = b;
             s = gwd_forward(m, streams, n_streams, window, stride, 0, out, out_capacity_floats, st);  // warm-up
             if (s != GWD_OK) break;
@@ -260,15 +294,17 @@ gwd_status gwd_autotune(gwd_model* m, const gwd_stream* streams, int32_t n_strea
     m->lp_waves = bs.waves;
     m->lp_fuse = bs.fuse;
     m->fused_blocks = bs.blocks;
+    m->persistent = bs.persist != 0;
     m->batch_windows = bb;
     *rows_out = bs.rows;
     *waves_out = bs.waves;
     *fuse_out = bs.fuse;
     *batch_out = bb;
     if (blocks_out) *blocks_out = bs.blocks;
+    if (persistent_out) *persistent_out = bs.persist;
     if (cache) {
         if (FILE* f = fopen(cache, "a")) {
-            fprintf(f, "%s %d %d %d %d %d\n", key, bs.rows, bs.waves, bs.fuse, bb, bs.blocks);
+            fprintf(f, "%s %d %d %d %d %d %d\n", key, bs.rows, bs.waves, bs.fuse, bb, bs.blocks, bs.persist);
             fclose(f);
         }
     }

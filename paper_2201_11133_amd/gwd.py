@@ -107,8 +107,10 @@ def _load(path: str = LIB_PATH):
         "gwd_plan_free": (None, [P]),
         "gwd_set_tiling": (I32, [P, I32, I32, I32, I32]),
         "gwd_set_fused_blocks": (I32, [P, I32]),
+        "gwd_set_persistent": (I32, [P, I32]),
         "gwd_autotune": (I32, [P, ctypes.POINTER(Stream), I32, I32, I32, P, I64, ctypes.POINTER(I32),
-                               ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32), P]),
+                               ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32),
+                               ctypes.POINTER(I32), P]),
         "gwd_debug_export_weights": (I32, [P, I32, P, I64]),
         "gwd_debug_capture_backward": (I32, [P, I32, P, P, P, P, P, P, P, P]),
         "gwd_debug_fused": (I32, [P, I32, I32, P, I32, I32, P, P, P, P, ctypes.POINTER(I32), P]),
@@ -240,19 +242,23 @@ class Model:
         """gwd_set_fused_blocks: the number of blocks a fused launch aims at (0 = the default, 512)."""
         check(lib.gwd_set_fused_blocks(self.h, blocks))
 
+    def set_persistent(self, on: bool = True):
+        """gwd_set_persistent: run the forward (and plans created afterwards) as one persistent launch."""
+        check(lib.gwd_set_persistent(self.h, 1 if on else 0))
+
     def autotune(self, streams, window: int = 4096, stride: int = 256, out=None, stream=None):
         """Pick the fastest schedule for this request; returns (tile_rows, waves, layers_per_launch,
-        batch_windows, fused_blocks)."""
+        batch_windows, fused_blocks, persistent)."""
         import torch
         arr, _ = make_streams(streams)
         n = self.out_floats(streams, window, stride, 0)
         if out is None:
             out = torch.empty(max(n, 1), dtype=torch.float32, device="cuda")
-        rw, w, fu, b, fb = (ctypes.c_int32(0) for _ in range(5))
+        rw, w, fu, b, fb, pe = (ctypes.c_int32(0) for _ in range(6))
         check(lib.gwd_autotune(self.h, arr, len(streams), window, stride, _ptr(out), out.numel(), ctypes.byref(rw),
                                ctypes.byref(w), ctypes.byref(fu), ctypes.byref(b), ctypes.byref(fb),
-                               _stream_handle(stream)))
-        return int(rw.value), int(w.value), int(fu.value), int(b.value), int(fb.value)
+                               ctypes.byref(pe), _stream_handle(stream)))
+        return int(rw.value), int(w.value), int(fu.value), int(b.value), int(fb.value), int(pe.value)
 
     def plan(self, streams, window: int = 4096, stride: int = 256, out_mode: int = 0, out=None):
         """Capture the whole forward for this request into a replayable graph (see Plan)."""

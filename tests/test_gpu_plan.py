@@ -91,13 +91,17 @@ def test_autotune_picks_a_valid_tiling(g, tmp_path, monkeypatch):
     monkeypatch.setenv("GWD_AUTOTUNE_CACHE", str(cache))
     m = g.Model(g.full_arch(), synth.full_weights(11), "bf16")
     x = to_dev(synth.make_stream(311, 40.0, 1)[0])
-    rw, w, fu, b, fb = m.autotune([x])
-    assert (rw, w) in TILINGS and fu in (1, 3) and b in (256, 512, 1024)
-    assert fb in ((512, 1024, 2048) if fu == 3 else (0,))
-    assert cache.read_text().strip().endswith(f"{rw} {w} {fu} {b} {fb}")
-    print(f"autotuned: rows {rw}, waves {w}, layers per launch {fu}, batch {b}, fused blocks {fb}", flush=True)
+    rw, w, fu, b, fb, pe = m.autotune([x])
+    assert (rw, w) in TILINGS and fu in (1, 3) and b in (256, 512, 1024) and pe in (0, 1)
+    if pe:    # the persistent forward: fused layers, one launch
+        assert fu == 3 and fb == 0 and b == 512
+    else:
+        assert fb in ((512, 1024, 2048) if fu == 3 else (0,))
+    assert cache.read_text().strip().endswith(f"{rw} {w} {fu} {b} {fb} {pe}")
+    print(f"autotuned: rows {rw}, waves {w}, layers per launch {fu}, batch {b}, fused blocks {fb}, "
+          f"persistent {pe}", flush=True)
     # second call reads the cache
-    assert m.autotune([x]) == (rw, w, fu, b, fb)
+    assert m.autotune([x]) == (rw, w, fu, b, fb, pe)
     m.close()
 
 
