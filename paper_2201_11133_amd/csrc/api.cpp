@@ -260,12 +260,15 @@ gwd_status forward_prepare(gwd_model* m, const gwd_stream* streams, int32_t n_st
     const int64_t persist_bytes = persist ? persistent_table_bytes(m, window) : 0;
     const int64_t tab_bytes = std::max<int64_t>(m->ws_tab_bytes, stream_bytes + persist_bytes);
     int64_t act_bytes = m->arch.kind == 1 ? 3 * (int64_t)nb_max * window * kC * 4 : 0;
-    if (persist) {  // two blocks per compute unit, at most one per window
+    if (persist) {  // two blocks per compute unit (at most one per window), each holding up to
+                    // kPersistWindows of its windows at a time
         int n_cu = 0;
         e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, m->device);
         if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
         m->persist_grid = (int)std::min<int64_t>(total_win, 2 * (int64_t)std::max(n_cu, 1));
-        act_bytes = m->persist_grid * persistent_block_bytes(window);
+        const int64_t per_block = (total_win + m->persist_grid - 1) / m->persist_grid;
+        m->persist_R = (int)std::min<int64_t>(kPersistWindows, per_block);
+        act_bytes = (int64_t)m->persist_grid * m->persist_R * persistent_block_bytes(window);
     }
     s = ensure_workspace(m, tab_bytes + act_bytes, st);
     if (s != GWD_OK) return s;
@@ -317,7 +320,8 @@ hipError_t forward_enqueue(gwd_model* m, FwdBatch fb, int64_t total_win, int nb_
     const int64_t tab_bytes = m->ws_tab_bytes;
     char* base = (char*)m->ws.base;
     if (m->persistent) {  // one launch for every window and member
-        hipError_t e = launch_persistent(m, fb, base + m->persist_tab_off, base + tab_bytes, m->persist_grid, fb.done, st);
+        hipError_t e = launch_persistent(m, fb, base + m->persist_tab_off, base + tab_bytes, m->persist_grid,
+                                         m->persist_R, fb.done, st);
         if (e == hipSuccess && after_batch) e = after_batch(ctx, 0, st);
         return e;
     }

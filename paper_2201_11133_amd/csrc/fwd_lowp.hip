@@ -1634,31 +1634,32 @@ struct PersistArgs {
     const StreamDesc* streams;
     int n_streams;
     int T;
-    uint16_t* xbuf;              // per block: two bf16 [T][128]
-    float* skbuf;                // per block: fp32 [T][128]
+    int R;                       // windows a block holds at a time
+    uint16_t* xbuf;              // per block: R x two bf16 [T][128]
+    float* skbuf;                // per block: R x fp32 [T][128]
     unsigned long long* done;    // optional, [n_streams]
 };
 
-// The persistent kernel's view for piece `b` of launch `l` on window `w`: launch l writes the
-// block's buffer l % 2 and reads the other (the first launch reads the stream). The buffers are
-// formed from the kernel arguments where they are used, so that nothing but the indices stays live
-// across a piece.
+// The persistent kernel's view for piece `b` of launch `l` on window `w`, held in the block's slot
+// `i`: launch l writes the slot's buffer l % 2 and reads the other (the first launch reads the
+// stream). The buffers are formed from the kernel arguments where they are used, so that nothing
+// but the indices stays live across a piece.
 struct OwnedIO {
     const PersistArgs& a;
     int64_t w;
     unsigned b;
-    int l;
-    __device__ uint16_t* buf(int i) const { return a.xbuf + ((int64_t)blockIdx.x * 2 + i) * a.T * kC; }
+    int l, i;
+    __device__ int64_t slot() const { return (int64_t)blockIdx.x * a.R + i; }
+    __device__ uint16_t* buf(int j) const { return a.xbuf + (slot() * 2 + j) * a.T * kC; }
     __device__ const uint16_t* x_in() const { return l == 0 ? nullptr : buf((l & 1) ^ 1); }
     __device__ uint16_t* x_out() const { return buf(l & 1); }
-    __device__ float* skip() const { return a.skbuf + (int64_t)blockIdx.x * a.T * kC; }
+    __device__ float* skip() const { return a.skbuf + slot() * a.T * kC; }
     __device__ int64_t win_base() const { return w; }
     __device__ unsigned bid() const { return b; }
 };
 
-// The launch tables are read through the constant address space: the compiler may then load a
-// field again wherever it is used instead of holding it in a register across the piece (as it
-// does with kernel arguments), which keeps the bodies within their register budget.
+// The launch tables are read through the constant address space, as kernel arguments are (the
+// tables do not change during the launch).
 typedef __attribute__((address_space(4))) const FusedArgs ConstFusedArgs;
 
 template <bool FP8>
@@ -1681,36 +1682,46 @@ __device__ __forceinline__ void persistent_piece(int kind, const ConstFusedArgs&
 }
 
 // Little stays live across a piece (the bodies need nearly every register): the window, member,
-// launch and piece indices; the buffers follow from the block index and the launch's parity, and
-// the window's stream is looked up again for the head.
+// launch, slot and piece indices; the buffers follow from them and the block index, and a window's
+// stream is looked up again for the head. Block b owns the b-th of grid equal ranges of consecutive
+// windows (their sizes differ by at most one) and walks it R windows at a time, running each launch
+// over all R before the next, so that the weights a launch reads serve R windows per fetch (and
+// the blocks, all at the same depth of equal work, share them in the L2).
 template <bool FP8>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void persistent_forward_kernel(PersistArgs a) {
     constexpr int LDS = FP8 ? FX_LDS : FU_LDS;
     static_assert(LDS >= (kBM * kHS + 4 * kBM) * 4, "the head's tile fits the fused launches' LDS");
     __shared__ __attribute__((aligned(16))) uint8_t lds[LDS];
-    for (int64_t w = blockIdx.x; w < a.total_win; w += gridDim.x) {
+    const int64_t q = a.total_win / gridDim.x, rem = a.total_win % gridDim.x;
+    const int64_t first = (int64_t)blockIdx.x * q + min((int64_t)blockIdx.x, rem);
+    const int64_t end = first + q + ((int64_t)blockIdx.x < rem ? 1 : 0);
+    for (int64_t w0 = first; w0 < end; w0 += a.R) {
+        const int nr = (int)min((int64_t)a.R, end - w0);
         for (int m = 0; m < a.n_members; ++m) {
             for (int l = 0; l < a.n_launch; ++l) {
                 const ConstFusedArgs& p = ((const ConstFusedArgs*)a.launches)[m * a.n_launch + l];
                 const unsigned pieces = (unsigned)(p.d0 * p.n_seg);
-                for (unsigned bid = 0; bid < pieces; ++bid) {
-                    persistent_piece<FP8>(a.kinds[l], p, OwnedIO{a, w, bid, l}, lds);
-                    __syncthreads();
-                }
+                for (int i = 0; i < nr; ++i)
+                    for (unsigned bid = 0; bid < pieces; ++bid) {
+                        persistent_piece<FP8>(a.kinds[l], p, OwnedIO{a, w0 + i, bid, l, i}, lds);
+                        __syncthreads();
+                    }
             }
-            const int si = find_stream(a.streams, a.n_streams, w);
-            const StreamDesc sd = a.streams[si];
-            const int64_t k = w - sd.win_begin;
             const HeadArgs& hp = a.heads[m];
-            int lo, hi;
-            owner_rows(hp.o, k, sd.length, lo, hi);
-            const float* sk = a.skbuf + (int64_t)blockIdx.x * a.T * kC;
-            for (int t0 = (lo / kBM) * kBM; t0 < hi; t0 += kBM)
-                head_tile(hp, sd, w, k, t0, lo, hi, sk, (float*)lds, (float(*)[kBM])(lds + kBM * kHS * 4));
+            for (int i = 0; i < nr; ++i) {
+                const int64_t w = w0 + i;
+                const StreamDesc sd = a.streams[find_stream(a.streams, a.n_streams, w)];
+                const int64_t k = w - sd.win_begin;
+                int lo, hi;
+                owner_rows(hp.o, k, sd.length, lo, hi);
+                const float* sk = a.skbuf + ((int64_t)blockIdx.x * a.R + i) * a.T * kC;
+                for (int t0 = (lo / kBM) * kBM; t0 < hi; t0 += kBM)
+                    head_tile(hp, sd, w, k, t0, lo, hi, sk, (float*)lds, (float(*)[kBM])(lds + kBM * kHS * 4));
+            }
             __syncthreads();
         }
-        if (a.done && threadIdx.x == 0)
-            atomicMax(a.done + find_stream(a.streams, a.n_streams, w), (unsigned long long)wall_clock64());
+        if (a.done && threadIdx.x < nr)
+            atomicMax(a.done + find_stream(a.streams, a.n_streams, w0 + threadIdx.x), (unsigned long long)wall_clock64());
     }
 }
 
@@ -1738,7 +1749,7 @@ int64_t persistent_table_bytes(const gwd_model* m, int T) {
     return (bytes + 255) & ~255LL;
 }
 
-// Per-block buffers of the persistent kernel (bytes per block).
+// Buffers of the persistent kernel for one window a block holds (bytes).
 int64_t persistent_block_bytes(int T) { return (int64_t)T * kC * (2 * 2 + 4); }
 
 // The launch and head tables of a request, as host bytes to be uploaded to d_tables (their device
@@ -1807,7 +1818,7 @@ __global__ void fill_u64_kernel(unsigned long long* p, int n) {
     if (i < n) p[i] = 0;
 }
 
-hipError_t launch_persistent(gwd_model* m, const FwdBatch& fb, const void* d_tables, void* act, int grid,
+hipError_t launch_persistent(gwd_model* m, const FwdBatch& fb, const void* d_tables, void* act, int grid, int R,
                              unsigned long long* done, hipStream_t st) {
     const int L = m->arch.n_stacks * m->arch.layers_per_stack;
     int n_launch = 0;
@@ -1822,8 +1833,9 @@ hipError_t launch_persistent(gwd_model* m, const FwdBatch& fb, const void* d_tab
     a.streams = fb.streams;
     a.n_streams = fb.n_streams;
     a.T = fb.T;
+    a.R = R;
     a.xbuf = (uint16_t*)act;
-    a.skbuf = (float*)((char*)act + (int64_t)grid * fb.T * kC * 2 * 2);
+    a.skbuf = (float*)((char*)act + (int64_t)grid * R * fb.T * kC * 2 * 2);
     a.done = done;
     if (done) {  // a fill kernel, not a memset: plans capture this into a graph
         hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)((fb.n_streams + 255) / 256)), dim3(256), 0, st, done,

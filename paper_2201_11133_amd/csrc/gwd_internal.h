@@ -111,7 +111,8 @@ struct gwd_model {
     float* dense_grad = nullptr;               // kind 2: device [n_params], the trunk gradient before read-back
     void* repack_tab = nullptr;                // device per-layer offsets of the on-device weight refresh (gwd_adam_step)
     bool persistent = false;                   // BF16/FP8: the forward as one persistent launch (gwd_set_persistent)
-    int32_t persist_grid = 0;                  // its blocks, and its tables' offset in the workspace (forward_prepare)
+    int32_t persist_grid = 0, persist_R = 1;   // its blocks and windows per block at a time, and its tables'
+                                               // offset in the workspace (forward_prepare)
     int64_t persist_tab_off = 0;
     // test support (gwd_debug_capture_backward): gated layer whose backward operands and results the
     // next gwd_backward copies out as fp32 [M][C] ([M][2C] for pre and dpre); -1 = off
@@ -195,11 +196,12 @@ hipError_t launch_stamp(unsigned long long* slot, hipStream_t st);
 // Persistent forward (fwd_lowp.hip): whether a model runs it at window length T, the size of its
 // launch tables and per-block buffers, the tables of a request (host bytes for the device address
 // they are uploaded to), and the launch.
+constexpr int kPersistWindows = 16;  // at most this many windows a persistent block holds at a time
 bool persistent_supported(const gwd_model* m, int T);
 int64_t persistent_table_bytes(const gwd_model* m, int T);
 int64_t persistent_block_bytes(int T);
 void persistent_tables(gwd_model* m, const FwdBatch& fb, std::vector<char>& host);
-hipError_t launch_persistent(gwd_model* m, const FwdBatch& fb, const void* d_tables, void* act, int grid,
+hipError_t launch_persistent(gwd_model* m, const FwdBatch& fb, const void* d_tables, void* act, int grid, int R,
                              unsigned long long* done, hipStream_t st);
 
 // Triggers (triggers.hip)
