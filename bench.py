@@ -47,7 +47,7 @@ ACCURACY = {
 # HBM bytes per launch of the middle BF16 gated layer (512 windows), from two rocprofv3 --pmc runs
 # (FETCH_SIZE, WRITE_SIZE) scaled by a 1 GiB copy; valid only for the kernel source they were taken on
 # (profiles/gated_layer_bf16_hbm_traffic_64s.md).
-MEASURED_TRAFFIC = {"bf16": {"source_sha256_16": "42a36af860241b4a", "bytes": 3202711959, "windows": 512, "layers": 3}}
+MEASURED_TRAFFIC = {"bf16": {"source_sha256_16": "f1e1b7703bd9cca4", "bytes": 3238102074, "windows": 512, "layers": 3}}
 
 
 def kernel_traffic(prec: str, windows: int, layers: int):
@@ -56,7 +56,7 @@ def kernel_traffic(prec: str, windows: int, layers: int):
     if not t or t["windows"] != windows or t.get("layers", 1) != layers:
         return None
     h = hashlib.sha256()
-    for f in ("fwd_lowp.hip", "layer_common.h"):   # the kernel source and its device helpers
+    for f in ("fwd_lowp.hip", "fused_bf16_body.inc", "fused_fp8_body.inc", "layer_common.h"):   # the kernel source
         h.update(open(os.path.join(ROOT, "paper_2201_11133_amd", "csrc", f), "rb").read())
     sig = h.hexdigest()[:16]
     return t["bytes"] if sig == t["source_sha256_16"] else None

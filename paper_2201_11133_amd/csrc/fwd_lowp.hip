@@ -472,18 +472,6 @@ struct FusedArgs {
 
 __device__ inline uint8_t* fu_buf(uint8_t* lds, int j) { return lds + (j == 0 ? FU_B0 : j == 1 ? FU_B1 : FU_B2); }
 
-// What one block of a fused launch reads and writes besides the launch's arguments: the residual
-// stream and skip sum of its windows, the global index of the first of them, and the block's
-// index within the launch. A fused kernel takes its own launch's (read where they are used, as
-// kernel arguments); the persistent kernel passes its per-block buffers and the window it owns.
-struct LaunchIO {
-    const FusedArgs& p;
-    __device__ const uint16_t* x_in() const { return p.x_in; }
-    __device__ uint16_t* x_out() const { return p.x_out; }
-    __device__ float* skip() const { return p.skip; }
-    __device__ int64_t win_base() const { return p.win_base; }
-    __device__ unsigned bid() const { return blockIdx.x; }
-};
 
 
 // Sixteen fp32 values of one 32-channel block in the transposed accumulator layout (see
@@ -548,364 +536,36 @@ struct ChunkRows {
 // then takes only the k-steps of its own group's input channels, since the others multiply zeros.
 // DBG: test-support instantiation that also writes every layer's pre-activation, residual output and
 // running skip sum of the stored rows to the dbg_* buffers (the arithmetic is unchanged).
-template <bool FROM_STREAM, bool SKIP_INIT, int NL, bool LAST, bool G2, bool DBG, class IO, class FA>
-__device__ __forceinline__ void fused_bf16_body(const FA& p, const IO& io, uint8_t* lds) {
-    static_assert(NL == 3 || NL == 4, "three or four layers");
-    static_assert(!LAST || NL == 4, "the network's last layer ends a quad");
-    using T = LP<false, 2, 4>;  // bf16 fragments, 4 waves x 2 row blocks
-    uint8_t* G = lds + FU_GB;
-    float* BI = (float*)(lds + FU_BI);
-    const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6, h = lane >> 5, r = lane & 31;
-    const int seg = io.bid() % p.n_seg;
-    const int cls = (io.bid() / p.n_seg) % p.d0;
-    const int b = io.bid() / (p.n_seg * p.d0);
-    const int n_sub = (p.T - cls + p.d0 - 1) / p.d0;  // rows of this sub-sequence
-    const int n_ch = (n_sub + FU_ROWS - 1) / FU_ROWS;
-    const int c0 = seg * p.seg_chunks;
-    if (c0 >= n_ch) return;  // uniform over the block
-    const int c1 = min(c0 + p.seg_chunks, n_ch);
-    const int64_t wrow0 = (int64_t)b * p.T;
-    StreamDesc sd{};
-    int64_t start = 0;
-    if (FROM_STREAM) {
-        const int64_t gw = io.win_base() + b;
-        sd = p.streams[find_stream(p.streams, p.n_streams, gw)];
-        start = (gw - sd.win_begin) * p.S;
-    }
-    // causal zero padding: the rows before the sub-sequence start are zero for every layer
-    for (int idx = tid; idx < (8 + 2 + 4) * 16; idx += 256) {
-        const int rr = idx >> 4, c = idx & 15;  // rows 0-7: buffer 0, 8-9: buffer 1, 10-13: buffer 2
-        uint8_t* row = rr < 8 ? fu_buf(lds, 0) - (8 - rr) * FU_XROW
-                     : rr < 10 ? fu_buf(lds, 1) - (10 - rr) * FU_XROW : fu_buf(lds, 2) - (14 - rr) * FU_XROW;
-        *(uint4*)(row + 16 * c) = make_uint4(0, 0, 0, 0);
-    }
-    // Products are taken transposed: weight fragments are the A operand and row fragments the B
-    // operand, so an accumulator holds rows along the lanes. Lane (h, r) holds row r of each
-    // 32-row block and, of its wave's 32-channel block, the channels 8 g + 4 h + e (g, e = 0..3):
-    // four runs of four consecutive channels, which move as 8- and 16-byte words.
-    const int cb = 32 * q + 4 * h;
-    // The k-steps this wave takes. Wave q owns output channels [32 q, 32 q + 32) of each column half,
-    // which for G2 lie in group q / 2; that group's input channels are k-steps gk .. gk + 3 of each
-    // tap (phase 1: step s is k = 8 (s / 4) + gk + s % 4) and of the gate output (phase 2: k = gk + s),
-    // gk = 4 (q / 2). The weight, row and gate pointers are shifted by gk once, so the unrolled
-    // offsets stay constants. Skipped steps would add exact zero products, so the accumulators, and
-    // every result, are those of the full loop.
-    const int gk = G2 ? 4 * (q >> 1) : 0;
-    constexpr auto k1 = [](int s) { return G2 ? ((s & 4) << 1) + (s & 3) : s; };
-    constexpr int NS1 = G2 ? T::NK1 / 2 : T::NK1, NS2 = G2 ? T::NK2 / 2 : T::NK2;
-    const size_t wsh = (size_t)gk * 64 * T::FRAG;   // weight-fragment shift
-    // Global loads retire in issue order, so a load from HBM would hold up the next wait on a
-    // weight fragment. HBM rows are therefore requested right before a gate, which waits on no
-    // load for thousands of cycles: the skip rows of a chunk before its first layer's gate, the
-    // input rows of the next chunk before the last layer's gate. The weight fragments of each
-    // layer's first steps are requested during the previous layer's second phase.
-    auto fetch_rows = [&](int c, ChunkRows<FROM_STREAM>& cr) {
-        const int sb = c * FU_ROWS;
-#pragma unroll
-        for (int it = 0; it < 4; ++it) {
-            const int idx = tid + 256 * it, rr = idx >> 4, c8 = 8 * (idx & 15);
-            const int sr = sb + rr;
-            const int t = cls + p.d0 * sr;
-            if (FROM_STREAM) {
-                cr.u[it][0] = 0.f;
-                cr.u[it][1] = 0.f;
-                const int64_t smp = start + t;
-                if (sr < n_sub && smp < sd.length) {
-                    cr.u[it][0] = sd.ch0[smp * sd.stride];
-                    cr.u[it][1] = sd.ch1[smp * sd.stride];
-                }
-            } else {
-                cr.v[it] = sr < n_sub ? *(const uint4*)&io.x_in()[(wrow0 + t) * kC + c8] : make_uint4(0, 0, 0, 0);
-            }
-        }
-    };
-    ChunkRows<FROM_STREAM> nrows;
-    fetch_rows(seg > 0 ? c0 - 1 : c0, nrows);
-    // the weight-fragment ring of the first phase; its first FU_PRE slots are loaded ahead of each layer
-    constexpr int FU_PRE = 2;
-    constexpr int FU_PF2 = 2;  // second-phase ring depth in fragment pairs (four MFMAs per step)
-    Frag<false> rf[T::PF1], rg[T::PF1];
-#pragma unroll
-    for (int k = 0; k < FU_PRE; ++k) {
-        if constexpr (G2) {
-            rf[k] = load_frag<false>(p.wc[0] + ((size_t)(q * T::NK1 + gk + k1(k)) * 64 + lane) * T::FRAG);
-            rg[k] = load_frag<false>(p.wc[0] + ((size_t)((4 + q) * T::NK1 + gk + k1(k)) * 64 + lane) * T::FRAG);
-        } else {
-            rf[k] = load_frag<false>(p.wc[0] + ((size_t)(q * T::NK1 + k) * 64 + lane) * T::FRAG);
-            rg[k] = load_frag<false>(p.wc[0] + ((size_t)((4 + q) * T::NK1 + k) * 64 + lane) * T::FRAG);
-        }
-    }
-    // the biases of the layers, once per block (requested after the first rows and
-    // weights, so the latencies overlap): [layer][conv 256 | res 128 | skip 128]
-    for (int idx = tid; idx < NL * kC; idx += 256) {  // four floats per thread and step
-        const int j = idx / kC, e = 4 * (idx % kC);
-        float4 v;
-        if (e < 2 * kC) v = *(const float4*)(p.bc[j] + e);
-        else if (LAST && j == NL - 1)  // skip columns only
-            v = e < 3 * kC ? make_float4(0.f, 0.f, 0.f, 0.f) : *(const float4*)(p.brs[j] + e - 3 * kC);
-        else v = *(const float4*)(p.brs[j] + e - 2 * kC);
-        *(float4*)(BI + 4 * idx) = v;
-    }
-    for (int c = (seg > 0 ? c0 - 1 : c0); c < c1; ++c) {
-        const bool store = c >= c0;
-        const int sb = c * FU_ROWS;
-        floatx16 sk[2];
-        // ---- stage the first layer's input rows [0, 64) of the chunk
-        uint8_t* X0 = fu_buf(lds, 0);
-#pragma unroll
-        for (int it = 0; it < 4; ++it) {
-            const int idx = tid + 256 * it, rr = idx >> 4, c8 = 8 * (idx & 15);
-            uint4 v;
-            if (FROM_STREAM) {  // input projection x0 = W_in u[t] + b_in, rounded to bf16 (zero past the sub-sequence end)
-                const float u0 = nrows.u[it][0], u1 = nrows.u[it][1];
-                uint32_t w[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int ch = c8 + 2 * e;
-                    const float x0 = p.b_in[ch] + p.w_in[2 * ch] * u0 + p.w_in[2 * ch + 1] * u1;
-                    const float x1 = p.b_in[ch + 1] + p.w_in[2 * ch + 2] * u0 + p.w_in[2 * ch + 3] * u1;
-                    w[e] = (uint32_t)to_bf16_bits(x0) | ((uint32_t)to_bf16_bits(x1) << 16);
-                }
-                v = sb + rr < n_sub ? make_uint4(w[0], w[1], w[2], w[3]) : make_uint4(0, 0, 0, 0);
-            } else {
-                v = nrows.v[it];
-            }
-            *(uint4*)(X0 + rr * FU_XROW + 2 * c8) = v;
-        }
-        __syncthreads();
-
-#pragma unroll 1
-        for (int j = 0; j < NL; ++j) {
-            const int dil = 1 << j;  // dilation in sub-rows
-            uint8_t* Xin = fu_buf(lds, j % 3);
-            uint8_t* Xo = fu_buf(lds, (j + 1) % 3);
-            const bool resid = !LAST || j < NL - 1;  // the network's last layer has no residual output
-            const float* bj = BI + j * 4 * kC;
-            // biases are the first products' accumulator inputs
-            const floatx16 bf = lds_col16(bj + cb), bg = lds_col16(bj + kC + cb);
-            // ---- phase 1: pre = [x[s - dil] | x[s]] Bc, K = 256 (k-steps 0-7: tap s - dil, 8-15: tap s);
-            // weight fragments from the register ring, operand fragments one step ahead
-            floatx16 af[2], ag[2];
-            // the matrix-core phases run at a raised wave priority, so the SIMD's other wave (in its
-            // gate or epilogue) fills the issue slots around them rather than delaying them
-            __builtin_amdgcn_s_setprio(2);
-            {
-                const uint8_t* A0 = Xin + r * FU_XROW + 16 * h;
-                const uint8_t* Bf = p.wc[j] + ((size_t)(q * T::NK1) * 64 + lane) * T::FRAG;
-                const uint8_t* Bg = p.wc[j] + ((size_t)((4 + q) * T::NK1) * 64 + lane) * T::FRAG;
-                if constexpr (G2) {
-                    A0 += 32 * gk;
-                    Bf += wsh;
-                    Bg += wsh;
-                }
-#pragma unroll
-                for (int k = FU_PRE; k < T::PF1; ++k) {
-                    rf[k] = load_frag<false>(Bf + (size_t)k1(k) * 64 * T::FRAG);
-                    rg[k] = load_frag<false>(Bg + (size_t)k1(k) * 64 * T::FRAG);
-                }
-                Frag<false> acur[2], anxt[2];
-#pragma unroll
-                for (int i = 0; i < 2; ++i) acur[i] = load_frag<false>(A0 + (32 * i - dil) * FU_XROW);
-#pragma unroll
-                for (int k = 0; k < NS1; ++k) {
-                    const int slot = k % T::PF1;
-                    const Frag<false> cf = rf[slot], cg = rg[slot];
-                    if (k + T::PF1 < NS1) {
-                        rf[slot] = load_frag<false>(Bf + (size_t)k1(k + T::PF1) * 64 * T::FRAG);
-                        rg[slot] = load_frag<false>(Bg + (size_t)k1(k + T::PF1) * 64 * T::FRAG);
-                    }
-                    if (k + 1 < NS1) {
-                        const int roff = k1(k + 1) < T::NK1 / 2 ? -dil : 0;
-#pragma unroll
-                        for (int i = 0; i < 2; ++i)
-                            anxt[i] = load_frag<false>(A0 + (32 * i + roff) * FU_XROW + 32 * (k1(k + 1) & 7));   // gk in A0
-                    }
-                    __builtin_amdgcn_sched_barrier(0);  // the next step's loads issue before this step's MFMAs
-#pragma unroll
-                    for (int i = 0; i < 2; ++i) {
-                        af[i] = mma<false>(cf, acur[i], k == 0 ? bf : af[i]);
-                        ag[i] = mma<false>(cg, acur[i], k == 0 ? bg : ag[i]);
-                    }
-                    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                    for (int i = 0; i < 2; ++i) acur[i] = anxt[i];
-                }
-            }
-            __builtin_amdgcn_s_setprio(0);
-            if constexpr (DBG) {  // pre-activations (the accumulators started at the biases)
-#pragma unroll
-                for (int rb = 0; rb < 2; ++rb) {
-                    const int sr = sb + 32 * rb + r;
-                    if (store && sr < n_sub) {
-                        float* po = p.dbg_pre + ((int64_t)j * p.dbg_rows + wrow0 + cls + (int64_t)p.d0 * sr) * (2 * kC);
-                        store_col16(po + cb, af[rb]);
-                        store_col16(po + kC + cb, ag[rb]);
-                    }
-                }
-            }
-            // the weight fragments of the second phase, residual and skip columns side by side; the
-            // first PF2 pairs are in flight during the gate
-            // (the network's last layer packs its skip columns only, as column blocks 0-3; its residual
-            // products are then computed from those same fragments and not used)
-            const uint8_t* Wr = p.wrs[j] + ((size_t)(q * T::NK2) * 64 + lane) * T::FRAG;
-            const uint8_t* Ws = p.wrs[j] + ((size_t)((resid ? 4 + q : q) * T::NK2) * 64 + lane) * T::FRAG;
-            if constexpr (G2) {
-                Wr += wsh;
-                Ws += wsh;
-            }
-            Frag<false> ringr[FU_PF2], rings[FU_PF2];
-#pragma unroll
-            for (int k = 0; k < FU_PF2; ++k) {
-                ringr[k] = load_frag<false>(Wr + (size_t)k * 64 * T::FRAG);
-                rings[k] = load_frag<false>(Ws + (size_t)k * 64 * T::FRAG);
-            }
-            const bool more = j < NL - 1 || c + 1 < c1;
-            if (j == NL - 1 && c + 1 < c1) fetch_rows(c + 1, nrows);  // next chunk's rows, in flight during the gate
-            if (j == 0) {  // this chunk's skip rows, first needed at the end of this layer
-#pragma unroll
-                for (int rb = 0; rb < 2; ++rb) {
-                    const int sr = sb + 32 * rb + r;
-                    sk[rb] = splat16(0.f);
-                    if (!SKIP_INIT && store && sr < n_sub) sk[rb] = load_col16(io.skip() + (wrow0 + cls + (int64_t)p.d0 * sr) * kC + cb);
-                }
-            }
-            // ---- gate -> G: per row block, four 8-byte writes of four channels
-#pragma unroll
-            for (int rb = 0; rb < 2; ++rb) {
-                uint8_t* gr = G + (32 * rb + r) * FU_XROW + 2 * cb;
-#pragma unroll
-                for (int g = 0; g < 4; ++g) {
-                    const int i = 4 * g;
-                    *(uint2*)(gr + 16 * g) =
-                        make_uint2(pack_bf16x2(gate_fast(af[rb][i], ag[rb][i]), gate_fast(af[rb][i + 1], ag[rb][i + 1])),
-                                   pack_bf16x2(gate_fast(af[rb][i + 2], ag[rb][i + 2]), gate_fast(af[rb][i + 3], ag[rb][i + 3])));
-                }
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            // residual inputs of this lane, gathered before any output is written
-            uint2 xold[2][4];
-#pragma unroll
-            for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-                for (int g = 0; g < 4; ++g) xold[rb][g] = *(const uint2*)(Xin + (32 * rb + r) * FU_XROW + 2 * cb + 16 * g);
-            const floatx16 br = lds_col16(bj + 2 * kC + cb), bs = lds_col16(bj + 3 * kC + cb);
-            __syncthreads();
-            // ---- phase 2 over G (K = 128): each g fragment feeds the residual and the skip columns
-            const uint8_t* Ag = G + r * FU_XROW + 16 * h;
-            if constexpr (G2) Ag += 32 * gk;
-            const int jn = j < NL - 1 ? j + 1 : 0;  // the next layer (the first of the next chunk after the last)
-            const uint8_t* Nf = p.wc[jn] + ((size_t)(q * T::NK1) * 64 + lane) * T::FRAG;
-            const uint8_t* Ng = p.wc[jn] + ((size_t)((4 + q) * T::NK1) * 64 + lane) * T::FRAG;
-            if constexpr (G2) {
-                Nf += wsh;
-                Ng += wsh;
-            }
-            floatx16 ar[2], as[2];
-            __builtin_amdgcn_s_setprio(2);
-            {
-                Frag<false> acur[2], anxt[2];
-#pragma unroll
-                for (int i = 0; i < 2; ++i) acur[i] = load_frag<false>(Ag + 32 * i * FU_XROW);
-#pragma unroll
-                for (int k = 0; k < NS2; ++k) {
-                    const int slot = k % FU_PF2;
-                    const Frag<false> cwr = ringr[slot], cws = rings[slot];
-                    if (k + FU_PF2 < NS2) {
-                        ringr[slot] = load_frag<false>(Wr + (size_t)(k + FU_PF2) * 64 * T::FRAG);
-                        rings[slot] = load_frag<false>(Ws + (size_t)(k + FU_PF2) * 64 * T::FRAG);
-                    } else if (k - (NS2 - FU_PF2) < FU_PRE && more) {
-                        // the next layer's first-phase ring, in registers this phase leaves free
-                        const int kk = k - (NS2 - FU_PF2);
-                        rf[kk] = load_frag<false>(Nf + (size_t)k1(kk) * 64 * T::FRAG);
-                        rg[kk] = load_frag<false>(Ng + (size_t)k1(kk) * 64 * T::FRAG);
-                    }
-                    if (k + 1 < NS2) {
-#pragma unroll
-                        for (int i = 0; i < 2; ++i) anxt[i] = load_frag<false>(Ag + 32 * i * FU_XROW + 32 * (k + 1));
-                    }
-                    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                    for (int i = 0; i < 2; ++i) {
-                        ar[i] = mma<false>(cwr, acur[i], k == 0 ? br : ar[i]);
-                        as[i] = mma<false>(cws, acur[i], k == 0 ? bs : as[i]);
-                    }
-                    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                    for (int i = 0; i < 2; ++i) acur[i] = anxt[i];
-                }
-            }
-            __builtin_amdgcn_s_setprio(0);
-            // x_next = x + (g Brs_res + b_res), rounded to bf16; skip += g Brs_skip + b_skip
-#pragma unroll
-            for (int rb = 0; rb < 2 && resid; ++rb) {
-                uint8_t* xr = Xo + (32 * rb + r) * FU_XROW + 2 * cb;
-#pragma unroll
-                for (int g = 0; g < 4; ++g) {
-                    const int i = 4 * g;
-                    *(uint2*)(xr + 16 * g) = residual4(xold[rb][g], ar[rb][i], ar[rb][i + 1], ar[rb][i + 2], ar[rb][i + 3]);
-                }
-            }
-#pragma unroll
-            for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-                for (int i = 0; i < 16; ++i) sk[rb][i] = (SKIP_INIT && j == 0) ? as[rb][i] : sk[rb][i] + as[rb][i];
-            __syncthreads();  // the next layer's input (or the chunk's output) is complete
-            // this input's last dil rows become the history of the next chunk: every wave has read
-            // them by now, and the buffer is next written two layers on (or by the next chunk)
-            if (c + 1 < c1 && tid < 16 * dil) {
-                const int rr = tid >> 4, cc = tid & 15;
-                *(uint4*)(Xin + (rr - dil) * FU_XROW + 16 * cc) = *(const uint4*)(Xin + (FU_ROWS - dil + rr) * FU_XROW + 16 * cc);
-            }
-            if constexpr (DBG) {  // this layer's residual output rows and running skip sums
-                if (store) {
-#pragma unroll
-                    for (int it = 0; it < 4 && resid; ++it) {
-                        const int idx = tid + 256 * it, rr = idx >> 4, c8 = 8 * (idx & 15);
-                        const int sr = sb + rr;
-                        if (sr < n_sub) {
-                            const uint4 w = *(const uint4*)(Xo + rr * FU_XROW + 2 * c8);
-                            float* xo = p.dbg_x + ((int64_t)j * p.dbg_rows + wrow0 + cls + (int64_t)p.d0 * sr) * kC + c8;
-                            *(float4*)xo = make_float4(__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xffff0000u),
-                                                       __uint_as_float(w.y << 16), __uint_as_float(w.y & 0xffff0000u));
-                            *(float4*)(xo + 4) = make_float4(__uint_as_float(w.z << 16), __uint_as_float(w.z & 0xffff0000u),
-                                                             __uint_as_float(w.w << 16), __uint_as_float(w.w & 0xffff0000u));
-                        }
-                    }
-#pragma unroll
-                    for (int rb = 0; rb < 2; ++rb) {
-                        const int sr = sb + 32 * rb + r;
-                        if (sr < n_sub)
-                            store_col16(p.dbg_skip + ((int64_t)j * p.dbg_rows + wrow0 + cls + (int64_t)p.d0 * sr) * kC + cb,
-                                        sk[rb]);
-                    }
-                }
-            }
-        }
-        // ---- chunk output: x rows from the last layer's output buffer (16-byte stores), skip rows
-        // from registers
-        if (store) {
-            const uint8_t* XL = fu_buf(lds, NL % 3);
-#pragma unroll
-            for (int it = 0; it < 4 && !LAST; ++it) {
-                const int idx = tid + 256 * it, rr = idx >> 4, c8 = 8 * (idx & 15);
-                const int sr = sb + rr;
-                if (sr < n_sub)
-                    *(uint4*)&io.x_out()[(wrow0 + cls + p.d0 * sr) * kC + c8] = *(const uint4*)(XL + rr * FU_XROW + 2 * c8);
-            }
-#pragma unroll
-            for (int rb = 0; rb < 2; ++rb) {
-                const int sr = sb + 32 * rb + r;
-                if (sr < n_sub) store_col16(io.skip() + (wrow0 + cls + (int64_t)p.d0 * sr) * kC + cb, sk[rb]);
-            }
-        }
-        __syncthreads();  // the output buffer is read above before the next chunk stages into buffer 0
-    }
-}
-
 template <bool FROM_STREAM, bool SKIP_INIT, int NL, bool LAST, bool G2, bool DBG = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void fused_bf16_kernel(FusedArgs p) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[FU_LDS];
-    fused_bf16_body<FROM_STREAM, SKIP_INIT, NL, LAST, G2, DBG>(p, LaunchIO{p}, lds);
+#define GWD_IO_BID blockIdx.x
+#define GWD_IO_X_IN p.x_in
+#define GWD_IO_X_OUT p.x_out
+#define GWD_IO_SKIP p.skip
+#define GWD_IO_WIN_BASE p.win_base
+#include "fused_bf16_body.inc"
+#undef GWD_IO_BID
+#undef GWD_IO_X_IN
+#undef GWD_IO_X_OUT
+#undef GWD_IO_SKIP
+#undef GWD_IO_WIN_BASE
+}
+
+// The same body for the persistent forward: one block's piece of a launch on the window it owns.
+template <bool FROM_STREAM, bool SKIP_INIT, int NL, bool LAST, bool G2, bool DBG, class IO, class FA>
+__device__ __forceinline__ void fused_bf16_body(const FA& p, const IO& io, uint8_t* lds) {
+#define GWD_IO_BID io.bid()
+#define GWD_IO_X_IN io.x_in()
+#define GWD_IO_X_OUT io.x_out()
+#define GWD_IO_SKIP io.skip()
+#define GWD_IO_WIN_BASE io.win_base()
+#include "fused_bf16_body.inc"
+#undef GWD_IO_BID
+#undef GWD_IO_X_IN
+#undef GWD_IO_X_OUT
+#undef GWD_IO_SKIP
+#undef GWD_IO_WIN_BASE
 }
 
 
@@ -957,319 +617,36 @@ __device__ inline uint32_t bf16x4_to_e4m3(uint2 w) { return bf16x2_to_e4m3(w.x) 
 // G2 as in the BF16 kernel: one k-step covers 64 input channels, i.e. one group, so a wave of group
 // q / 2 takes steps q / 2 and 2 + q / 2 of the first phase and step q / 2 of the second.
 // DBG as in the BF16 kernel.
-template <bool FROM_STREAM, bool SKIP_INIT, int NL, bool LAST, bool G2, bool DBG, class IO, class FA>
-__device__ __forceinline__ void fused_fp8_body(const FA& p, const IO& io, uint8_t* lds) {
-    static_assert(NL == 3 || NL == 4, "three or four layers");
-    static_assert(!LAST || NL == 4, "the network's last layer ends a quad");
-    using T = LP<true, 2, 4>;  // E4M3 fragments (32 bytes per lane), 4 waves x 2 row blocks
-    uint8_t* G = lds + FX_G;
-    uint8_t* XS = lds + FX_XS;
-    float* BI = (float*)(lds + FX_BI);
-    const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6, h = lane >> 5, r = lane & 31;
-    const int seg = io.bid() % p.n_seg;
-    const int cls = (io.bid() / p.n_seg) % p.d0;
-    const int b = io.bid() / (p.n_seg * p.d0);
-    const int n_sub = (p.T - cls + p.d0 - 1) / p.d0;  // rows of this sub-sequence
-    const int n_ch = (n_sub + FU_ROWS - 1) / FU_ROWS;
-    const int c0 = seg * p.seg_chunks;
-    if (c0 >= n_ch) return;  // uniform over the block
-    const int c1 = min(c0 + p.seg_chunks, n_ch);
-    const int64_t wrow0 = (int64_t)b * p.T;
-    StreamDesc sd{};
-    int64_t start = 0;
-    if (FROM_STREAM) {
-        const int64_t gw = io.win_base() + b;
-        sd = p.streams[find_stream(p.streams, p.n_streams, gw)];
-        start = (gw - sd.win_begin) * p.S;
-    }
-    // causal zero padding of the operand histories (E4M3 zero is 0x00)
-    for (int idx = tid; idx < (8 + 2 + 4) * 8; idx += 256) {
-        const int rr = idx >> 3, c = idx & 7;  // rows 0-7: buffer 0, 8-9: buffer 1, 10-13: buffer 2
-        uint8_t* row = rr < 8 ? fx_buf(lds, 0) - (8 - rr) * FX_EROW
-                     : rr < 10 ? fx_buf(lds, 1) - (10 - rr) * FX_EROW : fx_buf(lds, 2) - (14 - rr) * FX_EROW;
-        *(uint4*)(row + 16 * c) = make_uint4(0, 0, 0, 0);
-    }
-    // lane (h, r): row r of each 32-row block; channels cb + 8 g + e (g, e = 0..3) of the wave's block
-    const int cb = 32 * q + 4 * h;
-    const int gq = G2 ? (q >> 1) : 0;   // G2: this wave's group (its one k-step in each half of K)
-    constexpr int NS1 = G2 ? 2 : T::NK1, NS2 = G2 ? 1 : T::NK2;
-    constexpr auto k1 = [](int s) { return G2 ? 2 * s : s; };   // step -> k, after the group shift
-    const size_t wsh = (size_t)gq * 64 * T::FRAG;                 // weight-fragment shift
-    // HBM rows are requested right before a gate, as in the BF16 kernel
-    auto fetch_rows = [&](int c, ChunkRows<FROM_STREAM>& cr) {
-        const int sb = c * FU_ROWS;
-#pragma unroll
-        for (int it = 0; it < 4; ++it) {
-            const int idx = tid + 256 * it, rr = idx >> 4, c8 = 8 * (idx & 15);
-            const int sr = sb + rr;
-            const int t = cls + p.d0 * sr;
-            if (FROM_STREAM) {
-                cr.u[it][0] = 0.f;
-                cr.u[it][1] = 0.f;
-                const int64_t smp = start + t;
-                if (sr < n_sub && smp < sd.length) {
-                    cr.u[it][0] = sd.ch0[smp * sd.stride];
-                    cr.u[it][1] = sd.ch1[smp * sd.stride];
-                }
-            } else {
-                cr.v[it] = sr < n_sub ? *(const uint4*)&io.x_in()[(wrow0 + t) * kC + c8] : make_uint4(0, 0, 0, 0);
-            }
-        }
-    };
-    ChunkRows<FROM_STREAM> nrows;
-    fetch_rows(seg > 0 ? c0 - 1 : c0, nrows);
-    // first-phase weight fragments: a ring of FX_PRE steps, loaded ahead during the previous layer's
-    // second phase and refilled after each step's products
-    constexpr int FX_PRE = 2;
-    Frag<true> rf[FX_PRE], rg[FX_PRE];
-#pragma unroll
-    for (int k = 0; k < FX_PRE && k < NS1; ++k) {
-        rf[k] = load_frag<true>(p.wc[0] + ((size_t)(q * T::NK1 + k1(k)) * 64 + lane) * T::FRAG + wsh);
-        rg[k] = load_frag<true>(p.wc[0] + ((size_t)((4 + q) * T::NK1 + k1(k)) * 64 + lane) * T::FRAG + wsh);
-    }
-    // biases and scales of the layers: [layer][conv b 256 | conv s 256 | rs b 256 | rs s 256]
-    for (int idx = tid; idx < NL * 2 * kC; idx += 256) {  // four floats per thread and step
-        const int j = idx / (2 * kC), e = 4 * (idx % (2 * kC));
-        const int part = e / (2 * kC), o = e % (2 * kC);
-        const float* src = part == 0 ? p.bc[j] : part == 1 ? p.sc[j] : part == 2 ? p.brs[j] : p.srs[j];
-        float4 v;
-        if (part >= 2 && LAST && j == NL - 1)  // skip columns only, packed first
-            v = o < kC ? make_float4(0.f, 0.f, 0.f, 0.f) : *(const float4*)(src + o - kC);
-        else v = *(const float4*)(src + o);
-        *(float4*)(BI + 4 * idx) = v;
-    }
-    for (int c = (seg > 0 ? c0 - 1 : c0); c < c1; ++c) {
-        const bool store = c >= c0;
-        const int sb = c * FU_ROWS;
-        floatx16 sk[2];
-        // ---- stage the first layer's input rows [0, 64): bf16 for the residual, E4M3 operands
-        uint8_t* E0 = fx_buf(lds, 0);
-#pragma unroll
-        for (int it = 0; it < 4; ++it) {
-            const int idx = tid + 256 * it, rr = idx >> 4, c8 = 8 * (idx & 15);
-            uint4 v;
-            if (FROM_STREAM) {  // input projection x0 = W_in u[t] + b_in, rounded to bf16 (zero past the sub-sequence end)
-                const float u0 = nrows.u[it][0], u1 = nrows.u[it][1];
-                uint32_t w[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int ch = c8 + 2 * e;
-                    const float x0 = p.b_in[ch] + p.w_in[2 * ch] * u0 + p.w_in[2 * ch + 1] * u1;
-                    const float x1 = p.b_in[ch + 1] + p.w_in[2 * ch + 2] * u0 + p.w_in[2 * ch + 3] * u1;
-                    w[e] = (uint32_t)to_bf16_bits(x0) | ((uint32_t)to_bf16_bits(x1) << 16);
-                }
-                v = sb + rr < n_sub ? make_uint4(w[0], w[1], w[2], w[3]) : make_uint4(0, 0, 0, 0);
-            } else {
-                v = nrows.v[it];
-            }
-            *(uint4*)(XS + rr * FU_XROW + 2 * c8) = v;
-            *(uint2*)(E0 + rr * FX_EROW + c8) = bf16x8_to_e4m3(v);
-        }
-        __syncthreads();
-
-#pragma unroll 1
-        for (int j = 0; j < NL; ++j) {
-            const int dil = 1 << j;  // dilation in sub-rows
-            uint8_t* Xin = fx_buf(lds, j % 3);
-            uint8_t* Xo = fx_buf(lds, (j + 1) % 3);
-            const bool resid = !LAST || j < NL - 1;  // the network's last layer has no residual output
-            const bool last_layer = j == NL - 1;
-            const float* bj = BI + j * 4 * 2 * kC;
-            // ---- phase 1: acc = [x[s - dil] | x[s]] Bc, K = 256 (k-steps 0-1: tap s - dil, 2-3: tap s)
-            floatx16 af[2], ag[2];
-            __builtin_amdgcn_s_setprio(2);
-            {
-                const uint8_t* A0 = Xin + r * FX_EROW + 32 * h + 64 * gq;
-                const uint8_t* Bf = p.wc[j] + ((size_t)(q * T::NK1) * 64 + lane) * T::FRAG + wsh;
-                const uint8_t* Bg = p.wc[j] + ((size_t)((4 + q) * T::NK1) * 64 + lane) * T::FRAG + wsh;
-#pragma unroll
-                for (int k = 0; k < NS1; ++k) {
-                    const int kk = k1(k) + gq;
-                    const int roff = kk < T::NK1 / 2 ? -dil : 0;
-                    Frag<true> a[2];
-                    __builtin_amdgcn_sched_barrier(0);   // one step's operands live at a time (registers)
-#pragma unroll
-                    for (int i = 0; i < 2; ++i) a[i] = load_frag<true>(A0 + (32 * i + roff) * FX_EROW + 64 * (k1(k) & 1));
-#pragma unroll
-                    for (int i = 0; i < 2; ++i) {
-                        af[i] = mma<true>(rf[k % FX_PRE], a[i], k == 0 ? splat16(0.f) : af[i]);
-                        ag[i] = mma<true>(rg[k % FX_PRE], a[i], k == 0 ? splat16(0.f) : ag[i]);
-                    }
-                    __builtin_amdgcn_sched_barrier(0);
-                    if (k + FX_PRE < NS1) {
-                        rf[k % FX_PRE] = load_frag<true>(Bf + (size_t)k1(k + FX_PRE) * 64 * T::FRAG);
-                        rg[k % FX_PRE] = load_frag<true>(Bg + (size_t)k1(k + FX_PRE) * 64 * T::FRAG);
-                    }
-                }
-            }
-            __builtin_amdgcn_s_setprio(0);
-            // the second phase's weight fragments, residual and skip columns side by side (the
-            // network's last layer packs its skip columns only, as column blocks 0-3)
-            const uint8_t* Wr = p.wrs[j] + ((size_t)(q * T::NK2) * 64 + lane) * T::FRAG + wsh;
-            const uint8_t* Ws = p.wrs[j] + ((size_t)((resid ? 4 + q : q) * T::NK2) * 64 + lane) * T::FRAG + wsh;
-            Frag<true> ringr[T::NK2], rings[T::NK2];
-            ringr[0] = load_frag<true>(Wr);
-            rings[0] = load_frag<true>(Ws);
-            const bool more = j < NL - 1 || c + 1 < c1;
-            if (last_layer && c + 1 < c1) fetch_rows(c + 1, nrows);  // next chunk's rows, in flight during the gate
-            if (j == 0) {  // this chunk's skip rows, first needed at the end of this layer
-#pragma unroll
-                for (int rb = 0; rb < 2; ++rb) {
-                    const int sr = sb + 32 * rb + r;
-                    sk[rb] = splat16(0.f);
-                    if (!SKIP_INIT && store && sr < n_sub) sk[rb] = load_col16(io.skip() + (wrow0 + cls + (int64_t)p.d0 * sr) * kC + cb);
-                }
-            }
-            // ---- gate: pre = acc * scale + bias, g = tanh * sigmoid -> E4M3 codes in G (4 channels per word)
-            {
-#pragma unroll
-                for (int rb = 0; rb < 2; ++rb) {
-                    uint8_t* gr = G + (32 * rb + r) * FX_EROW + cb;
-#pragma unroll
-                    for (int g = 0; g < 4; ++g) {
-                        const float4 bf = *(const float4*)(bj + cb + 8 * g), bg = *(const float4*)(bj + kC + cb + 8 * g);
-                        const float4 sf = *(const float4*)(bj + 2 * kC + cb + 8 * g), sg = *(const float4*)(bj + 3 * kC + cb + 8 * g);
-                        const float bfa[4] = {bf.x, bf.y, bf.z, bf.w}, bga[4] = {bg.x, bg.y, bg.z, bg.w};
-                        const float sfa[4] = {sf.x, sf.y, sf.z, sf.w}, sga[4] = {sg.x, sg.y, sg.z, sg.w};
-                        float v[4];
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            const int i = 4 * g + e;
-                            const float pf = fmaf(af[rb][i], sfa[e], bfa[e]), pg = fmaf(ag[rb][i], sga[e], bga[e]);
-                            if constexpr (DBG) {
-                                af[rb][i] = pf;
-                                ag[rb][i] = pg;
-                            }
-                            v[e] = gate_fast(pf, pg);
-                        }
-                        *(uint32_t*)(gr + 8 * g) = e4m3_pair_in_range(v[0], v[1]) | (e4m3_pair_in_range(v[2], v[3]) << 16);
-                    }
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-            }
-            if constexpr (DBG) {  // pre-activations (column scale, then bias)
-#pragma unroll
-                for (int rb = 0; rb < 2; ++rb) {
-                    const int sr = sb + 32 * rb + r;
-                    if (store && sr < n_sub) {
-                        float* po = p.dbg_pre + ((int64_t)j * p.dbg_rows + wrow0 + cls + (int64_t)p.d0 * sr) * (2 * kC);
-                        store_col16(po + cb, af[rb]);
-                        store_col16(po + kC + cb, ag[rb]);
-                    }
-                }
-            }
-            __syncthreads();
-            // ---- phase 2 over G (K = 128 in two steps): each g fragment feeds the residual and the skip columns
-            const uint8_t* Ag = G + r * FX_EROW + 32 * h + 64 * gq;
-            const int jn = j < NL - 1 ? j + 1 : 0;  // the next layer (the first of the next chunk after the last)
-            const uint8_t* Nf = p.wc[jn] + ((size_t)(q * T::NK1) * 64 + lane) * T::FRAG + wsh;
-            const uint8_t* Ng = p.wc[jn] + ((size_t)((4 + q) * T::NK1) * 64 + lane) * T::FRAG + wsh;
-            floatx16 ar[2], as[2];
-            __builtin_amdgcn_s_setprio(2);
-            {
-#pragma unroll
-                for (int k = 0; k < NS2; ++k) {
-                    Frag<true> a[2];
-                    __builtin_amdgcn_sched_barrier(0);
-                    if (k + 1 < NS2) {
-                        ringr[k + 1] = load_frag<true>(Wr + (size_t)(k + 1) * 64 * T::FRAG);
-                        rings[k + 1] = load_frag<true>(Ws + (size_t)(k + 1) * 64 * T::FRAG);
-                    }
-#pragma unroll
-                    for (int i = 0; i < 2; ++i) a[i] = load_frag<true>(Ag + 32 * i * FX_EROW + 64 * k);
-                    if (k == NS2 - 1 && more) {  // the next layer's first first-phase fragments
-#pragma unroll
-                        for (int kk = 0; kk < FX_PRE && kk < NS1; ++kk) {
-                            rf[kk] = load_frag<true>(Nf + (size_t)k1(kk) * 64 * T::FRAG);
-                            rg[kk] = load_frag<true>(Ng + (size_t)k1(kk) * 64 * T::FRAG);
-                        }
-                    }
-                    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                    for (int i = 0; i < 2; ++i) {
-                        ar[i] = mma<true>(ringr[k], a[i], k == 0 ? splat16(0.f) : ar[i]);
-                        as[i] = mma<true>(rings[k], a[i], k == 0 ? splat16(0.f) : as[i]);
-                    }
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-            }
-            __builtin_amdgcn_s_setprio(0);
-            __builtin_amdgcn_sched_barrier(0);
-            // x_next = x + (scale * acc + b_res), rounded to bf16, in place in the staging buffer (only
-            // this lane reads and writes these rows and channels), and as E4M3 operand rows of the next
-            // layer; skip += scale * acc + b_skip
-#pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                const int i = 4 * g;
-                const float4 br4 = *(const float4*)(bj + 4 * kC + cb + 8 * g), sr4 = *(const float4*)(bj + 6 * kC + cb + 8 * g);
-                const float4 bs4 = *(const float4*)(bj + 5 * kC + cb + 8 * g), ss4 = *(const float4*)(bj + 7 * kC + cb + 8 * g);
-#pragma unroll
-                for (int rb = 0; rb < 2; ++rb) {
-                    if (resid) {
-                        uint2* xp = (uint2*)(XS + (32 * rb + r) * FU_XROW + 2 * (cb + 8 * g));
-                        const uint2 xn = residual4(*xp, fmaf(ar[rb][i], sr4.x, br4.x), fmaf(ar[rb][i + 1], sr4.y, br4.y),
-                                                   fmaf(ar[rb][i + 2], sr4.z, br4.z), fmaf(ar[rb][i + 3], sr4.w, br4.w));
-                        *xp = xn;
-                        if (!last_layer) *(uint32_t*)(Xo + (32 * rb + r) * FX_EROW + cb + 8 * g) = bf16x4_to_e4m3(xn);
-                    }
-                    const float sv[4] = {fmaf(as[rb][i], ss4.x, bs4.x), fmaf(as[rb][i + 1], ss4.y, bs4.y),
-                                         fmaf(as[rb][i + 2], ss4.z, bs4.z), fmaf(as[rb][i + 3], ss4.w, bs4.w)};
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) sk[rb][i + e] = (SKIP_INIT && j == 0) ? sv[e] : sk[rb][i + e] + sv[e];
-                }
-            }
-            __syncthreads();  // the next layer's input (or the chunk's output rows) is complete
-            // this input's last dil rows become the history of the next chunk: every wave has read
-            // them by now, and the buffer is next written two layers on (or by the next chunk)
-            if (c + 1 < c1 && tid < 8 * dil) {
-                const int rr = tid >> 3, cc = tid & 7;
-                *(uint4*)(Xin + (rr - dil) * FX_EROW + 16 * cc) = *(const uint4*)(Xin + (FU_ROWS - dil + rr) * FX_EROW + 16 * cc);
-            }
-            if constexpr (DBG) {  // this layer's residual output and running skip sum of the stored rows
-                if (store) {
-#pragma unroll
-                    for (int rb = 0; rb < 2; ++rb) {
-                        const int sr = sb + 32 * rb + r;
-                        if (sr < n_sub) {
-                            const int64_t row = (int64_t)j * p.dbg_rows + wrow0 + cls + (int64_t)p.d0 * sr;
-                            if (resid) {
-#pragma unroll
-                                for (int g = 0; g < 4; ++g) {
-                                    const uint2 w = *(const uint2*)(XS + (32 * rb + r) * FU_XROW + 2 * (cb + 8 * g));
-                                    *(float4*)(p.dbg_x + row * kC + cb + 8 * g) =
-                                        make_float4(__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xffff0000u),
-                                                    __uint_as_float(w.y << 16), __uint_as_float(w.y & 0xffff0000u));
-                                }
-                            }
-                            store_col16(p.dbg_skip + row * kC + cb, sk[rb]);
-                        }
-                    }
-                }
-            }
-        }
-        // ---- chunk output: x rows from the staging buffer (16-byte stores), skip rows from registers
-        if (store) {
-#pragma unroll
-            for (int it = 0; it < 4 && !LAST; ++it) {
-                const int idx = tid + 256 * it, rr = idx >> 4, c8 = 8 * (idx & 15);
-                const int sr = sb + rr;
-                if (sr < n_sub)
-                    *(uint4*)&io.x_out()[(wrow0 + cls + p.d0 * sr) * kC + c8] = *(const uint4*)(XS + rr * FU_XROW + 2 * c8);
-            }
-#pragma unroll
-            for (int rb = 0; rb < 2; ++rb) {
-                const int sr = sb + 32 * rb + r;
-                if (sr < n_sub) store_col16(io.skip() + (wrow0 + cls + (int64_t)p.d0 * sr) * kC + cb, sk[rb]);
-            }
-        }
-        __syncthreads();  // the staging buffer is read above before the next chunk stages into it
-    }
-}
-
 template <bool FROM_STREAM, bool SKIP_INIT, int NL, bool LAST, bool G2, bool DBG = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void fused_fp8_kernel(FusedArgs p) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[FX_LDS];
-    fused_fp8_body<FROM_STREAM, SKIP_INIT, NL, LAST, G2, DBG>(p, LaunchIO{p}, lds);
+#define GWD_IO_BID blockIdx.x
+#define GWD_IO_X_IN p.x_in
+#define GWD_IO_X_OUT p.x_out
+#define GWD_IO_SKIP p.skip
+#define GWD_IO_WIN_BASE p.win_base
+#include "fused_fp8_body.inc"
+#undef GWD_IO_BID
+#undef GWD_IO_X_IN
+#undef GWD_IO_X_OUT
+#undef GWD_IO_SKIP
+#undef GWD_IO_WIN_BASE
+}
+
+// The same body for the persistent forward: one block's piece of a launch on the window it owns.
+template <bool FROM_STREAM, bool SKIP_INIT, int NL, bool LAST, bool G2, bool DBG, class IO, class FA>
+__device__ __forceinline__ void fused_fp8_body(const FA& p, const IO& io, uint8_t* lds) {
+#define GWD_IO_BID io.bid()
+#define GWD_IO_X_IN io.x_in()
+#define GWD_IO_X_OUT io.x_out()
+#define GWD_IO_SKIP io.skip()
+#define GWD_IO_WIN_BASE io.win_base()
+#include "fused_fp8_body.inc"
+#undef GWD_IO_BID
+#undef GWD_IO_X_IN
+#undef GWD_IO_X_OUT
+#undef GWD_IO_SKIP
+#undef GWD_IO_WIN_BASE
 }
 
 
