@@ -39,6 +39,7 @@ struct LayerArgsLP {
     uint16_t* x_out;
     float* skip;
     float* pre_out;
+    uint16_t* pre16;     // or the pre-activations rounded to bf16 (training recompute of BF16 members)
     const uint8_t* wc;   // packed conv operands
     const float* bc;
     const uint8_t* wrs;  // packed res|skip operands
@@ -319,6 +320,11 @@ void layer_lp_kernel(LayerArgsLP p) {
                     float* po = p.pre_out + (row0 + m) * (2 * kC);
                     po[n] = vf;
                     po[kC + n] = vg;
+                }
+                if (p.pre16) {
+                    uint16_t* po = p.pre16 + (row0 + m) * (2 * kC);
+                    po[n] = to_bf16_bits(vf);
+                    po[kC + n] = to_bf16_bits(vg);
                 }
                 const float gv = gate_fast(vf, vg);
                 if (FP8) {  // rows m (i even) and m + 1 (i odd) converted together
@@ -908,13 +914,14 @@ hipError_t launch_fused_debug(gwd_model* m, int member, int l, const float* x_in
 // when pre_out is set. The same launches as the debug path without its fp32 <-> bf16 conversions.
 template <bool FP8>
 static hipError_t train_lp(gwd_model* m, int member, int l, const uint16_t* x_in, int nb, int T, float* pre_out,
-                           uint16_t* x_out, float* skip, hipStream_t st) {
+                           uint16_t* pre16, uint16_t* x_out, float* skip, hipStream_t st) {
     const int L = m->arch.n_stacks * m->arch.layers_per_stack;
     LayerArgsLP a = lp_args<FP8>(m, member, l);
     a.x_in = x_in;
     a.x_out = x_out;
     a.skip = skip;
     a.pre_out = pre_out;
+    a.pre16 = pre16;
     a.T = T;
     const int tiling = lp_tiling(m, FP8);
     if (l == 0) return (L == 1) ? launch_lp<FP8, false, true, true>(a, nb, tiling, st)
@@ -923,9 +930,9 @@ static hipError_t train_lp(gwd_model* m, int member, int l, const uint16_t* x_in
     return launch_lp<FP8, false, false, true>(a, nb, tiling, st);
 }
 hipError_t launch_layer_train_bf16io(gwd_model* m, int member, int l, const uint16_t* x_in, int nb, int T,
-                                     float* pre_out, uint16_t* x_out, float* skip, hipStream_t st) {
-    return m->prec == GWD_FP8_E4M3 ? train_lp<true>(m, member, l, x_in, nb, T, pre_out, x_out, skip, st)
-                                   : train_lp<false>(m, member, l, x_in, nb, T, pre_out, x_out, skip, st);
+                                     uint16_t* pre16, uint16_t* x_out, float* skip, hipStream_t st) {
+    return m->prec == GWD_FP8_E4M3 ? train_lp<true>(m, member, l, x_in, nb, T, nullptr, pre16, x_out, skip, st)
+                                   : train_lp<false>(m, member, l, x_in, nb, T, nullptr, pre16, x_out, skip, st);
 }
 // Training forward of BF16/FP8 members (no pre-activations kept): the fused launches of the
 // inference forward where they apply. Layers covered by the launch at layer l (1 = a single layer).

@@ -159,10 +159,10 @@ hipError_t launch_wavenet_forward(gwd_model* m, const FwdBatch& fb, float* x_a, 
                                   hipStream_t st);
 hipError_t launch_layer_debug(gwd_model* m, int member, int layer, const float* x_in, int nb, int T,
                               float* pre_out, float* x_out, float* skip, hipStream_t st);
-// BF16/FP8 members: one layer on bf16 activations (training; skip may be null: no skip sum), and an
-// fp32 -> bf16 rounding copy.
+// BF16/FP8 members: one layer on bf16 activations (training; skip may be null: no skip sum; pre16, if
+// set, receives the pre-activations rounded to bf16 [nb T][256]), and an fp32 -> bf16 rounding copy.
 hipError_t launch_layer_train_bf16io(gwd_model* m, int member, int l, const uint16_t* x_in, int nb, int T,
-                                     float* pre_out, uint16_t* x_out, float* skip, hipStream_t st);
+                                     uint16_t* pre16, uint16_t* x_out, float* skip, hipStream_t st);
 hipError_t launch_f32_to_bf16(const float* x, int64_t n, uint16_t* y, hipStream_t st);
 hipError_t launch_bf16_to_f32(const uint16_t* x, int64_t n, float* y, hipStream_t st);
 int train_layers_per_launch(const gwd_model* m, int l, int T);

@@ -204,8 +204,9 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
             // the stack's last output and the recomputed skip sum are not needed: scratch buffers
             float* xnext = (i + 1 < LPS) ? fptr(b, f_xs + (int64_t)(i + 1) * M * kC) : G;
             float* pre_i = fptr(b, f_pre + (int64_t)i * M * 2 * kC);
-            if (BT)  // (no skip sum: the recompute needs layer inputs and pre-activations only)
-                HIPCHK(launch_layer_train_bf16io(m, member, l, (const uint16_t*)xs_i, B, T, pre_i,
+            if (BT)  // (no skip sum: the recompute needs layer inputs and pre-activations only; the
+                     // pre-activations in bf16, in the first half of each slot)
+                HIPCHK(launch_layer_train_bf16io(m, member, l, (const uint16_t*)xs_i, B, T, (uint16_t*)pre_i,
                                                  (l < L - 1) ? (uint16_t*)xnext : nullptr, nullptr, st), "recompute");
             else
                 HIPCHK(launch_layer_debug(m, member, l, xs_i, B, T, pre_i, (l < L - 1) ? xnext : nullptr, SKS, st),
@@ -220,7 +221,7 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
             float* const* cap = l == m->cap_layer ? m->cap_buf : nullptr;
             if (cap) {  // the layer's operands as its kernels read them
                 HIPCHK(capture(cap[0], xs_i, M * kC, BT != nullptr, st), "capture x_in");
-                HIPCHK(capture(cap[1], pre, M * 2 * kC, false, st), "capture pre");
+                HIPCHK(capture(cap[1], pre, M * 2 * kC, BT != nullptr, st), "capture pre");
                 HIPCHK(capture(cap[2], DS, M * kC, false, st), "capture dskip");
                 HIPCHK(capture(cap[3], DX, M * kC, false, st), "capture dx_in");
             }
@@ -241,7 +242,7 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
             uint16_t* G16 = BT ? (uint16_t*)G : nullptr;
             uint16_t* DPRE16 = BT ? (uint16_t*)DPRE : nullptr;
             if (BT) {
-                g.gpre = pre; g.g16 = G16; g.dpre16 = DPRE16;
+                g.gpre = (const uint16_t*)pre; g.g16 = G16; g.dpre16 = DPRE16;
                 if (!cap) g.C = nullptr;
             }
             HIPCHK(gemm_rows(g, st), "dg");

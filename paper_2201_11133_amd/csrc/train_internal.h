@@ -34,9 +34,9 @@ struct GemmRowsArgs {
     int64_t ldm;
     uint16_t* bt;        // optional scratch (N x sum K bf16): set = bf16 operands, fp32 accumulation
     // optional gate-backward epilogue (bf16-operand kernel, N = 128): C is dg; from the pre-activations
-    // gpre [M][256] it writes g16 = bf16(tanh sigma) [M][128] and dpre16 [M][256] as the gate backward
-    // does; C may then be null (dg not stored)
-    const float* gpre;
+    // gpre [M][256] (bf16, as the recompute stores them) it writes g16 = bf16(tanh sigma) [M][128] and
+    // dpre16 [M][256]; C may then be null (dg not stored)
+    const uint16_t* gpre;
     uint16_t* g16;
     uint16_t* dpre16;
 };

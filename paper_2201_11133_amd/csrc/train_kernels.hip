@@ -261,20 +261,22 @@ __global__ __launch_bounds__(256) void gemm_rows_bf16_kernel(GemmRowsArgs a, int
         __syncthreads();
         const int64_t rbase = row0 + 64 * pass + (tid >> 5);   // + 8 it
         if (a.gpre) {
-            // gate backward (N = 128, one column block): g, dpre from the pre-activations and dg
-            float4 pf[8], pg[8];
+            // gate backward (N = 128, one column block): g, dpre from the bf16 pre-activations and dg
+            u32x2 pf[8], pg[8];
 #pragma unroll
             for (int it = 0; it < 8; ++it) {
                 const int64_t row = rbase + 8 * it;
-                pf[it] = *(const float4*)(a.gpre + row * 2 * kC + cq);
-                pg[it] = *(const float4*)(a.gpre + row * 2 * kC + kC + cq);
+                pf[it] = *(const u32x2*)(a.gpre + row * 2 * kC + cq);
+                pg[it] = *(const u32x2*)(a.gpre + row * 2 * kC + kC + cq);
             }
 #pragma unroll
             for (int it = 0; it < 8; ++it) {
                 const int64_t row = rbase + 8 * it;
                 const float4 d = *(const float4*)&Ep[(8 * it + (tid >> 5)) * EP + cq];
-                const float fv[4] = {pf[it].x, pf[it].y, pf[it].z, pf[it].w};
-                const float gv[4] = {pg[it].x, pg[it].y, pg[it].z, pg[it].w};
+                const float fv[4] = {__uint_as_float(pf[it][0] << 16), __uint_as_float(pf[it][0] & 0xffff0000u),
+                                     __uint_as_float(pf[it][1] << 16), __uint_as_float(pf[it][1] & 0xffff0000u)};
+                const float gv[4] = {__uint_as_float(pg[it][0] << 16), __uint_as_float(pg[it][0] & 0xffff0000u),
+                                     __uint_as_float(pg[it][1] << 16), __uint_as_float(pg[it][1] & 0xffff0000u)};
                 const float dv[4] = {d.x, d.y, d.z, d.w};
                 uint16_t go[4], fo[4], so[4];
 #pragma unroll
@@ -958,7 +960,7 @@ hipError_t gemm_rows(const GemmRowsArgs& a, hipStream_t st) {
            (!a.mask || (a.ldm % 4 == 0 && ((uintptr_t)a.mask & 15) == 0)) && (!a.bias || ((uintptr_t)a.bias & 15) == 0);
     if (any16 && !bf16) return hipErrorInvalidValue;  // bf16 parts need the bf16-operand kernel
     if (a.gpre && (!bf16 || a.N != kC || !a.g16 || !a.dpre16 || a.bias || a.beta != 0.f || a.mask ||
-                   (a.C && a.ldc % 4) || ((uintptr_t)a.gpre & 15)))
+                   (a.C && a.ldc % 4) || ((uintptr_t)a.gpre & 7)))
         return hipErrorInvalidValue;
     if (!a.C && !a.gpre) return hipErrorInvalidValue;
     if (bf16) {
