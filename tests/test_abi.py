@@ -106,6 +106,8 @@ def test_forward_and_debug_argument_errors(g):
     assert g.lib.gwd_debug_layer(None, 0, 0, None, 1, 4096, None, None, None, None) == g.ERR_ARG
     out = np.zeros(10, np.float32)
     assert g.lib.gwd_debug_export_weights(None, 0, out.ctypes.data, 10) == g.ERR_ARG
+    assert g.lib.gwd_set_persistent(None, 1) == g.ERR_ARG
+    assert g.lib.gwd_set_fused_blocks(None, 0) == g.ERR_ARG
     g.lib.gwd_free(None)    # ignored
 
 

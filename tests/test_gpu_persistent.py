@@ -84,6 +84,7 @@ def test_persistent_needs_fused_layers(g):
         m.set_persistent(True)
     m.close()
     m = g.Model(g.full_arch(), synth.full_weights(72)[None], "bf16")
+    assert g.lib.gwd_set_persistent(m.h, 2) == g.ERR_ARG
     m.set_persistent(True)
     x = to_dev(synth.make_stream(711, 6.0, 0)[0])
     with pytest.raises(RuntimeError):   # windows of 8192: the last layer of a stack is a single launch
