@@ -3,7 +3,8 @@
   ensemble score before p, and every per-window logit before it, bit for bit unchanged, in every
   precision and through every fused launch (history rows, chunk edges, sub-sequence interleaving);
 - guard bands: the kernels write inside their output buffers only (NaN-patterned bands around each
-  output are bit for bit intact afterwards, and the output holds no NaN);
+  output are bit for bit intact afterwards, and the output holds no NaN), the persistent forward
+  included;
 - checkpoint and resume of training: two steps, a checkpoint, a fresh model and trainer from it and
   one more step give the same master weights, moments and loss, bit for bit, as three steps without
   interruption."""
@@ -84,13 +85,17 @@ def test_causality_small_member(g):
     m.close()
 
 
-@pytest.mark.parametrize("prec,mode", [("bf16", 0), ("bf16", 1), ("bf16", 2), ("fp8", 2), ("fp32", 0)])
-def test_forward_writes_inside_its_output(g, prec, mode):
+@pytest.mark.parametrize("prec,mode,persistent", [("bf16", 0, False), ("bf16", 1, False), ("bf16", 2, False),
+                                                  ("fp8", 2, False), ("fp32", 0, False), ("bf16", 1, True),
+                                                  ("fp8", 2, True)])
+def test_forward_writes_inside_its_output(g, prec, mode, persistent):
     from paper_2201_11133_amd import synth
-    print(f"case: guard bands forward {prec} mode {mode}", flush=True)
+    print(f"case: guard bands forward {prec} mode {mode}{' persistent' if persistent else ''}", flush=True)
     W, S = 4096, 256
     blobs = np.stack([synth.full_weights(33), synth.full_weights(34)])
     m = g.Model(g.full_arch(), blobs, prec)
+    if persistent:
+        m.set_persistent(True)
     xs = [to_dev(synth.make_stream(403, 5.3, 1)[0]), to_dev(synth.make_stream(404, 0.7, 0)[0])]
     n = m.out_floats(xs, W, S, mode)
     buf, out = guarded(n)
