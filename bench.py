@@ -47,7 +47,7 @@ ACCURACY = {
 # HBM bytes per launch of the middle BF16 gated layer (512 windows), from two rocprofv3 --pmc runs
 # (FETCH_SIZE, WRITE_SIZE) scaled by a 1 GiB copy; valid only for the kernel source they were taken on
 # (profiles/gated_layer_bf16_hbm_traffic_64s.md).
-MEASURED_TRAFFIC = {"bf16": {"source_sha256_16": "f1e1b7703bd9cca4", "bytes": 3238102074, "windows": 512, "layers": 3}}
+MEASURED_TRAFFIC = {"bf16": {"source_sha256_16": "cf52ec1247609588", "bytes": 3238478907, "windows": 512, "layers": 3}}
 
 
 def kernel_traffic(prec: str, windows: int, layers: int):
