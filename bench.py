@@ -110,34 +110,46 @@ def time_steps(fn, steps: int, warmup: int, label: str = "", warm_fn=None):
 
 def layer_kernel_timing(model, prec: str, reps: int = 10):
     """Average duration of the dominant kernel in the forward's own launch configuration, timed by
-    the library with HIP events on the stream it launches on. With fused launches that is the
-    three-layer kernel, timed at the triples of the middle stack (dilations 1-4, 8-32, and 64-256
-    where that one is a triple); a launch at layer 16 that also takes the stack's last layer (a
-    quad, dilations 64-512) is reported beside it. Otherwise the single-layer kernel at a middle
-    layer."""
-    timed = [model.time_layer(0, l, reps) for l in (10, 13, 16)]
-    launches = [t for t in timed if t[2] == 3]
-    quads = [t for t in timed if t[2] == 4]
-    if not launches:
-        launches, quads = [model.time_layer(0, 15, reps)], []
+    the library with HIP events on the stream it launches on. The middle stack's launches are timed
+    one by one (BF16 by default: a sextet, dilations 1-32, and a quad, 64-512; triples and a quad
+    with three layers per launch); the kernel with the most time per stack is the dominant one, and
+    the others are reported beside it. With one layer per launch: the single-layer kernel at a
+    middle layer."""
+    timed, l = [], 10
+    while l < 20:
+        t = model.time_layer(0, l, reps)
+        if t[2] == 1:
+            timed = [model.time_layer(0, 15, reps)]
+            break
+        timed.append(t)
+        l += t[2]
+    groups = {}
+    for t in timed:
+        groups.setdefault(t[2], []).append(t)
+    nl = max(groups, key=lambda k: sum(x[0] for x in groups[k]))
+    launches = groups[nl]
     ms = sum(x[0] for x in launches) / len(launches)
-    nb, nl = launches[0][1], launches[0][2]
+    nb = launches[0][1]
     flop = nb * W * FLOP_PER_LAYER_T * nl
     achieved = flop / (ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[prec]
     traffic = kernel_traffic(prec, nb, nl)
-    kernel = f"fused gated layer triple ({prec})" if nl == 3 else f"gated layer ({prec})"
+    names = {1: "gated layer", 3: "fused gated layer triple", 4: "fused gated layer quad", 6: "fused gated layer sextet"}
+    kernel = f"{names.get(nl, f'fused {nl}-layer launch')} ({prec})"
     out = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
            "frac": round(achieved / peak, 4), "traffic": traffic, "kernel": kernel,
            "ms_per_launch": round(ms, 4), "ms_per_launch_each": [round(x[0], 4) for x in launches],
            "windows_per_launch": nb, "layers_per_launch": nl, "flop_per_launch": flop}
     if traffic:
         out["hbm_GBps"] = round(traffic / (ms * 1e-3) / 1e9, 1)
-    if quads:
-        qms, qnb = quads[0][0], quads[0][1]
-        qflop = qnb * W * FLOP_PER_LAYER_T * 4
-        out["quad"] = {"ms_per_launch": round(qms, 4), "layers_per_launch": 4, "flop_per_launch": qflop,
-                       "achieved": round(qflop / (qms * 1e-3) / 1e12, 2)}
+    for k in sorted(groups):
+        if k == nl:
+            continue
+        kms = sum(x[0] for x in groups[k]) / len(groups[k])
+        kflop = groups[k][0][1] * W * FLOP_PER_LAYER_T * k
+        out[names.get(k, f"{k}-layer").split()[-1]] = {
+            "ms_per_launch": round(kms, 4), "layers_per_launch": k, "flop_per_launch": kflop,
+            "achieved": round(kflop / (kms * 1e-3) / 1e12, 2)}
     return out
 
 

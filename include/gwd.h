@@ -423,12 +423,14 @@ void gwd_plan_free(gwd_plan* plan);
  *   tile_rows, waves: tiling of the single-layer BF16/FP8 kernel, (64, 4),
  *     (64, 8) or (128, 4); (0, 0) = default per precision (BF16 (64, 4), FP8
  *     (64, 8)); FP32 models have one tiling and accept only (0, 0);
- *   layers_per_launch: BF16 and FP8, 3 = fused launches (the default): the
- *     layers with dilations d, 2d, 4d of a stack run as one launch, and in
- *     BF16 the triple at stack position 6 also takes the stack's last layer
- *     (four layers) when the sub-sequences at its dilation fit one 64-row
- *     chunk (window <= 64 x that dilation, e.g. 4096 at 64); 1 = one launch
- *     per layer; 0 = default; FP32 models accept 0 or 1;
+ *   layers_per_launch: BF16 and FP8, 3 = fused launches: the layers with
+ *     dilations d, 2d, 4d of a stack run as one launch, and the triple at
+ *     stack position 6 also takes the stack's last layer (four layers) when
+ *     the sub-sequences at its dilation fit one 64-row chunk (window <= 64 x
+ *     that dilation, e.g. 4096 at 64); 6 (BF16 models with stacks of ten
+ *     layers) = sextets: stack positions 0-5 (dilations 1-32) in one launch,
+ *     then 6-9 in another at any window length; 1 = one launch per layer;
+ *     0 = default (6 where sextets apply, else 3); FP32 models accept 0 or 1;
  *   batch_windows: windows per batch of layer launches (1..8192, default 512;
  *     gwd_forward lowers it for a call whose activations would not fit in 60 %
  *     of the free device memory, e.g. windows of 2^20 samples).
@@ -457,9 +459,10 @@ gwd_status gwd_set_fused_blocks(gwd_model* model, int32_t blocks);
  * waits for another. Results are bit for bit those of the launch sequence.
  * (The paper's engine is built once and replayed for every batch,
  * "Optimization with TensorRT"; here the whole ragged request is one launch.)
- * Needs every layer in a fused launch at the request's window (three layers
- * per launch, windows up to 4096); gwd_forward returns GWD_ERR_UNSUPPORTED
- * otherwise. It leaves the workspace without the batch layout that
+ * It runs the triples-and-quads grouping (whatever the fused schedule set by
+ * gwd_set_tiling, 3 or 6 layers per launch) and needs every layer in one of
+ * those launches at the request's window (windows up to 4096) and a fused
+ * schedule; gwd_forward returns GWD_ERR_UNSUPPORTED otherwise. It leaves the workspace without the batch layout that
  * gwd_debug_time_layer reads. GWD_ERR_ARG unless on is 0 or 1;
  * GWD_ERR_UNSUPPORTED for other models (FP32, small member, two-branch). */
 gwd_status gwd_set_persistent(gwd_model* model, int32_t on);
@@ -467,7 +470,8 @@ gwd_status gwd_set_persistent(gwd_model* model, int32_t on);
 /* Autotuner (the engine's kernel choice by profiling, "Optimization with
  * TensorRT"): times gwd_forward (out_mode 0) on the given request for every
  * schedule candidate (BF16/FP8: fused launches aiming at 512, 1024 and 2048
- * blocks, and the three tilings one layer per launch; all: batch 256, 512,
+ * blocks, BF16 with stacks of ten layers also sextets aiming at 512 and 1024,
+ * and the three tilings one layer per launch; all: batch 256, 512,
  * 1024 windows; BF16/FP8 gated models where the window allows it: the
  * persistent forward), keeps the fastest on the model and reports it
  * (*fused_blocks is 0 for schedules without fused launches, *persistent 1 for
@@ -553,7 +557,7 @@ gwd_status gwd_debug_capture_backward(gwd_model* model, int32_t layer, float* x_
  * of windows, on the activations the last gwd_forward left in the model's
  * workspace, and times the last `reps` launches between two HIP events
  * recorded on hip_stream. Writes the average milliseconds per launch, the
- * windows per launch and the layers per launch (1, 3 or 4). Requires a prior
+ * windows per launch and the layers per launch (1, 3, 4 or 6). Requires a prior
  * gwd_forward on the model; synchronises hip_stream. The workspace contents
  * are overwritten. */
 gwd_status gwd_debug_time_layer(gwd_model* model, int32_t member, int32_t layer, int32_t reps,

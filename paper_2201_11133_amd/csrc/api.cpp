@@ -450,6 +450,7 @@ gwd_status gwd_load_weights(const gwd_arch* arch, int32_t n_members, const float
     } else {
         m->host_blob.assign(host_blob, host_blob + (size_t)np * n_members);
     }
+    m->lp_fuse = default_layers_per_launch(m);
     const int64_t npk = m->n_params;
     m->members.resize(n_members);
     m->canon.assign(n_members, nullptr);

@@ -424,42 +424,45 @@ static int lp_tiling(const gwd_model* m, bool fp8) {
     return LP_64x4;
 }
 
-// ---------------------------------------------------------------- fused layer triples (BF16)
-// Three consecutive layers of a stack, with dilations d0, 2 d0 and 4 d0, in one launch. Split a
-// window's rows by t mod d0 into d0 interleaved sub-sequences (t = p + d0 s): on each of them the
-// three layers are causal convolutions with dilations 1, 2 and 4 (the space-to-batch form of a
-// dilated convolution). A block walks 64-row chunks of one sub-sequence in time order and runs
-// the three layers on each chunk in LDS. Each layer's input buffer keeps the last 1 / 2 / 4 rows
-// of the previous chunk in front of the current one, so nothing is recomputed, and the skip sum of
-// the chunk stays in registers across the three layers: x and skip cross HBM once per three
-// layers instead of once per layer. Long sub-sequences (d0 = 1) are split into segments that
-// start with one warm-up chunk, computed only to rebuild those history rows; its outputs are not
-// stored. Every output is computed with the same operations, in the same order, as by three
-// launches of the single-layer kernel.
+// ---------------------------------------------------------------- fused layer launches (BF16)
+// NL consecutive layers of a stack, with dilations d0, 2 d0, ..., 2^(NL-1) d0, in one launch. Split
+// a window's rows by t mod d0 into d0 interleaved sub-sequences (t = p + d0 s): on each of them the
+// layers are causal convolutions with dilations 1, 2, 4, ... (the space-to-batch form of a dilated
+// convolution). A block walks 64-row chunks of one sub-sequence in time order and runs the layers
+// on each chunk in LDS. Each layer keeps the last 1 / 2 / 4 / ... rows of its input from the
+// previous chunk, so nothing is recomputed, and the skip sum of the chunk stays in registers
+// across the layers: x and skip cross HBM once per launch instead of once per layer. Long
+// sub-sequences (d0 = 1) are split into segments that start with one warm-up chunk, computed only
+// to rebuild those history rows; its outputs are not stored. (After j layers the first 2^j - 1
+// rows of the warm-up chunk are off, and the next chunk takes its last 2^j rows: one warm-up
+// chunk serves up to six layers.) Every output is computed with the same operations, in the same
+// order, as by NL launches of the single-layer kernel.
 constexpr int FU_ROWS = 64;                                // sub-rows per chunk (2 row blocks x 4 waves)
 constexpr int FU_XROW = 2 * kC + 16;                       // bf16 row + 16-byte pad
-// BF16 form: layer j reads buffer j % 3 and writes buffer (j + 1) % 3. Each buffer keeps in front of
-// its rows as many history rows as the largest dilation read from it: 8 for buffer 0 (dilation 1,
-// and 8 for the fourth layer of a quad), 2 for buffer 1, 4 for buffer 2. Then the gate buffer and
-// the biases of up to four layers.
-constexpr int FU_B0 = 8 * FU_XROW;
-constexpr int FU_B1 = FU_B0 + (FU_ROWS + 2) * FU_XROW;
-constexpr int FU_B2 = FU_B1 + (FU_ROWS + 4) * FU_XROW;
-constexpr int FU_GB = FU_B2 + FU_ROWS * FU_XROW;
-constexpr int FU_BI = FU_GB + FU_ROWS * FU_XROW;
-constexpr int FU_LDS = FU_BI + 4 * 4 * kC * 4;             // 81,632 bytes: two blocks per CU
+constexpr int FU_MAXL = 6;                                 // most layers in one fused launch
+// BF16 form: layer j reads buffer j % 3, writes buffer (j + 1) % 3 and puts its gate output in
+// buffer (j + 2) % 3, whose rows (the previous layer's input) nobody reads any more. Layer j's
+// history rows (its input's last 2^j rows of the previous chunk) are a region of their own, H_j,
+// at row 2^j - 1 of the history area, so layers that share a buffer keep theirs apart. Then the
+// biases of up to six layers.
+constexpr int FU_B0 = 0;
+constexpr int FU_B1 = FU_ROWS * FU_XROW;
+constexpr int FU_B2 = 2 * FU_ROWS * FU_XROW;
+constexpr int FU_H = 3 * FU_ROWS * FU_XROW;
+constexpr int FU_BI = FU_H + ((1 << FU_MAXL) - 1) * FU_XROW;
+constexpr int FU_LDS = FU_BI + FU_MAXL * 4 * kC * 4;       // 81,648 bytes: two blocks per CU
 static_assert(2 * FU_LDS <= 160 * 1024, "two fused blocks per CU");
 
 struct FusedArgs {
     const uint16_t* x_in;  // residual stream, bf16 [rows][128]
     uint16_t* x_out;
     float* skip;
-    const uint8_t* wc[4];  // layers of the launch (three, or four for a quad)
-    const float* bc[4];
-    const uint8_t* wrs[4];
-    const float* brs[4];
-    const float* sc[4];    // FP8: conv column scales [256]
-    const float* srs[4];   // FP8: res|skip column scales [256]
+    const uint8_t* wc[FU_MAXL];  // layers of the launch (three, four for a quad, six for a BF16 sextet)
+    const float* bc[FU_MAXL];
+    const uint8_t* wrs[FU_MAXL];
+    const float* brs[FU_MAXL];
+    const float* sc[FU_MAXL];    // FP8: conv column scales [256]
+    const float* srs[FU_MAXL];   // FP8: res|skip column scales [256]
     int d0, T;             // dilation of the first layer; window length
     int n_seg, seg_chunks; // segments per sub-sequence, chunks per segment
     const StreamDesc* streams;
@@ -657,17 +660,27 @@ __device__ __forceinline__ void fused_fp8_body(const FA& p, const IO& io, uint8_
 
 
 // Layers covered by the fused launch that starts at layer l for windows of length T: 0 (l is not a
-// start), 3, or 4. Triples start at stack positions 0, 3, 6; the triple at 6 also takes the stack's
-// last layer (a quad) when the sub-sequences at its dilation are one chunk long. A triple never
-// includes the network's last layer.
-static int fused_layers(const gwd_model* m, int l, int T) {
-    if ((m->prec != GWD_BF16 && m->prec != GWD_FP8_E4M3) || m->lp_fuse != 3) return 0;
+// start), 3, 4 or 6.
+// - Triples (lp_fuse 3) start at stack positions 0, 3, 6; the triple at 6 also takes the stack's
+//   last layer (a quad) when the sub-sequences at its dilation are one chunk long. A triple never
+//   includes the network's last layer.
+// - Sextets (lp_fuse 6, BF16 stacks of ten layers): positions 0-5 in one launch, then 6-9 as a
+//   quad at any window length (each BF16 layer keeps history rows of its own).
+static int fused_layers_in(const gwd_model* m, int l, int T, int mode) {
+    if (m->prec == GWD_BF16 && mode == 6 && m->arch.layers_per_stack == 10 && T > 0) {
+        const int i = l % 10;
+        return i == 0 ? 6 : i == 6 ? 4 : 0;
+    }
+    if ((m->prec != GWD_BF16 && m->prec != GWD_FP8_E4M3) || mode != 3) return 0;
     const int lps = m->arch.layers_per_stack, L = m->arch.n_stacks * lps, i = l % lps;
     if (i % 3 != 0 || i + 2 >= lps) return 0;
     const int d0 = 1 << i;
     if (i + 4 == lps && T > 0 && (T + d0 - 1) / d0 <= FU_ROWS) return 4;
     return l + 2 < L - 1 ? 3 : 0;
 }
+static int fused_layers(const gwd_model* m, int l, int T) { return fused_layers_in(m, l, T, m->lp_fuse); }
+// The persistent kernel's grouping, whatever the model's schedule: triples and quads.
+static int persist_layers(const gwd_model* m, int l, int T) { return fused_layers_in(m, l, T, 3); }
 
 // One fused launch of layers l .. l + nl - 1 over nb windows of length T.
 template <bool FROM_STREAM, bool SKIP_INIT, int NL, bool LAST>
@@ -705,7 +718,8 @@ static hipError_t launch_fused(gwd_model* m, int member, int l, int nl, const ui
     a.T = T;
     const int rows = FU_ROWS;                                           // sub-rows per chunk
     const int n_ch = ((T + a.d0 - 1) / a.d0 + rows - 1) / rows;       // chunks of the longest sub-sequence
-    if (nl == 4 && n_ch != 1) return hipErrorInvalidValue;              // a quad needs one-chunk sub-sequences
+    if (FP8 && nl == 4 && n_ch != 1) return hipErrorInvalidValue;       // an FP8 quad needs one-chunk sub-sequences
+    if (FP8 && nl == 6) return hipErrorInvalidValue;                    // sextets are BF16 only
     // by default enough blocks for every resident slot (two per CU on 256 CUs); a segment after the
     // first costs one warm-up chunk; the autotuner may aim at more blocks (gwd_set_fused_blocks)
     const int64_t per = (int64_t)nb * a.d0;
@@ -740,6 +754,9 @@ static hipError_t launch_fused(gwd_model* m, int member, int l, int nl, const ui
         } else if (nl == 3) {
             if (first) hipLaunchKernelGGL((fused_bf16_kernel<false, true, 3, false, false, true>), grid, dim3(256), 0, st, a);
             else hipLaunchKernelGGL((fused_bf16_kernel<false, false, 3, false, false, true>), grid, dim3(256), 0, st, a);
+        } else if (nl == 6) {
+            if (first) hipLaunchKernelGGL((fused_bf16_kernel<false, true, 6, false, false, true>), grid, dim3(256), 0, st, a);
+            else hipLaunchKernelGGL((fused_bf16_kernel<false, false, 6, false, false, true>), grid, dim3(256), 0, st, a);
         } else {
             if (first) return hipErrorInvalidValue;
             if (l + 3 == L - 1) hipLaunchKernelGGL((fused_bf16_kernel<false, false, 4, true, false, true>), grid, dim3(256), 0, st, a);
@@ -763,6 +780,11 @@ static hipError_t launch_fused(gwd_model* m, int member, int l, int nl, const ui
         if (stream_in) launch_fused_bf16<true, true, 3, false>(g2, grid, st, a);
         else if (first) launch_fused_bf16<false, true, 3, false>(g2, grid, st, a);
         else launch_fused_bf16<false, false, 3, false>(g2, grid, st, a);
+    } else if (nl == 6) {
+        const bool g2 = m->two_branch;
+        if (stream_in) launch_fused_bf16<true, true, 6, false>(g2, grid, st, a);
+        else if (first) launch_fused_bf16<false, true, 6, false>(g2, grid, st, a);
+        else launch_fused_bf16<false, false, 6, false>(g2, grid, st, a);
     } else {
         if (first) return hipErrorInvalidValue;                          // stacks of at least 10 layers
         if (l + 3 == L - 1) launch_fused_bf16<false, false, 4, true>(m->two_branch, grid, st, a);
@@ -1109,15 +1131,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void p
     }
 }
 
-// The network's launches for windows of length T: true when every layer lies in a fused launch
-// (windows up to 4096: the quads need one-chunk sub-sequences), the only form the persistent
-// kernel runs.
+// The network's launches for windows of length T in the triples-and-quads grouping: true when every
+// layer lies in a fused launch (windows up to 4096: the FP8 quads need one-chunk sub-sequences, and
+// so does this grouping's quad), the only form the persistent kernel runs. The model's schedule must
+// be a fused one (not one layer per launch).
 bool persistent_supported(const gwd_model* m, int T) {
-    if (m->arch.kind != 1 || m->two_branch || (m->prec != GWD_BF16 && m->prec != GWD_FP8_E4M3) || m->lp_fuse != 3)
+    if (m->arch.kind != 1 || m->two_branch || (m->prec != GWD_BF16 && m->prec != GWD_FP8_E4M3) || m->lp_fuse == 1)
         return false;
     const int L = m->arch.n_stacks * m->arch.layers_per_stack;
     for (int l = 0; l < L;) {
-        const int nl = fused_layers(m, l, T);
+        const int nl = persist_layers(m, l, T);
         if (nl == 0) return false;
         l += nl;
     }
@@ -1127,7 +1150,7 @@ bool persistent_supported(const gwd_model* m, int T) {
 int64_t persistent_table_bytes(const gwd_model* m, int T) {
     const int L = m->arch.n_stacks * m->arch.layers_per_stack;
     int n_launch = 0;
-    for (int l = 0; l < L; ++n_launch) l += std::max(1, fused_layers(m, l, T));
+    for (int l = 0; l < L; ++n_launch) l += std::max(1, persist_layers(m, l, T));
     const int64_t bytes = (int64_t)m->n_members * n_launch * sizeof(FusedArgs) + (int64_t)m->n_members * sizeof(HeadArgs) +
                           (int64_t)n_launch * sizeof(int32_t);
     return (bytes + 255) & ~255LL;
@@ -1144,7 +1167,7 @@ void persistent_tables(gwd_model* m, const FwdBatch& fb, std::vector<char>& host
     std::vector<int> starts;
     for (int l = 0; l < L;) {
         starts.push_back(l);
-        l += fused_layers(m, l, fb.T);
+        l += persist_layers(m, l, fb.T);
     }
     const int n_launch = (int)starts.size();
     host.assign(persistent_table_bytes(m, fb.T), 0);
@@ -1154,7 +1177,7 @@ void persistent_tables(gwd_model* m, const FwdBatch& fb, std::vector<char>& host
     const bool fp8 = m->prec == GWD_FP8_E4M3;
     for (int mem = 0; mem < m->n_members; ++mem) {
         for (int i = 0; i < n_launch; ++i) {
-            const int l = starts[i], nl = fused_layers(m, l, fb.T);
+            const int l = starts[i], nl = persist_layers(m, l, fb.T);
             FusedArgs a{};
             for (int j = 0; j < nl; ++j) {
                 const LayerArgsLP lp = fp8 ? lp_args<true>(m, mem, l + j) : lp_args<false>(m, mem, l + j);
@@ -1206,7 +1229,7 @@ hipError_t launch_persistent(gwd_model* m, const FwdBatch& fb, const void* d_tab
                              unsigned long long* done, hipStream_t st) {
     const int L = m->arch.n_stacks * m->arch.layers_per_stack;
     int n_launch = 0;
-    for (int l = 0; l < L; ++n_launch) l += std::max(1, fused_layers(m, l, fb.T));
+    for (int l = 0; l < L; ++n_launch) l += std::max(1, persist_layers(m, l, fb.T));
     PersistArgs a{};
     a.launches = (const FusedArgs*)d_tables;
     a.heads = (const HeadArgs*)(a.launches + m->n_members * n_launch);

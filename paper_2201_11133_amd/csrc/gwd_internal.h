@@ -102,7 +102,7 @@ struct gwd_model {
     std::vector<int64_t> host_firsts;          // host copy of FwdBatch::firsts for the current request
     int32_t lp_rows = 0;                       // BF16/FP8 layer tiling: rows per tile (0 = default per precision)
     int32_t lp_waves = 0;                      // and waves per block
-    int32_t lp_fuse = 3;                       // BF16: layers per launch (3 = fused triples, 1 = one per launch)
+    int32_t lp_fuse = 3;                       // BF16/FP8: layers per launch (3 = fused triples and quads, 6 = BF16 sextets and quads, 1 = one per launch)
     int32_t fused_blocks = 0;                  // blocks a fused launch aims at (segments per sub-sequence); 0 = 512
     bool two_branch = false;                   // loaded as kind 2 and expanded to the block-diagonal kind-1 image
     gwd_arch branch_arch{};                    // kind 2: the architecture as loaded
@@ -169,6 +169,7 @@ int train_layers_per_launch(const gwd_model* m, int l, int T);
 // Test support: layers of the fused BF16/FP8 launch that starts at layer l (0 if none), and that
 // launch with per-layer outputs.
 int fused_layers_at(const gwd_model* m, int l, int T);
+int default_layers_per_launch(const gwd_model* m);
 hipError_t launch_mfma_probe(int kind, const void* A, const void* B, const float* C, float* D, hipStream_t st);
 hipError_t launch_fused_debug(gwd_model* m, int member, int l, const float* x_in, int nb, int T, float* skip,
                               float* pre_out, float* x_out, float* skip_out, hipStream_t st);

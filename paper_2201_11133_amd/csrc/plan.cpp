@@ -39,6 +39,12 @@ static hipError_t stamp_after_batch(void* ctx, int64_t bi, hipStream_t st) {
     return launch_stamp(((StampCtx*)ctx)->stamps + bi + 1, st);
 }
 
+// BF16 gated models with stacks of ten layers run sextets and quads (fewer launches, so fewer
+// round trips of the residual and skip streams through HBM); other BF16/FP8 models triples and quads.
+int default_layers_per_launch(const gwd_model* m) {
+    return (m->arch.kind == 1 && m->prec == GWD_BF16 && m->arch.layers_per_stack == 10) ? 6 : 3;
+}
+
 }  // namespace gwd
 
 using namespace gwd;
@@ -168,14 +174,16 @@ gwd_status gwd_set_tiling(gwd_model* m, int32_t tile_rows, int32_t waves, int32_
         return GWD_ERR_ARG;
     }
     const bool fusable = lowp;
-    if (!(layers_per_launch == 0 || layers_per_launch == 1 || (layers_per_launch == 3 && fusable))) {
+    const bool sextets = m->arch.kind == 1 && m->prec == GWD_BF16 && m->arch.layers_per_stack == 10;
+    if (!(layers_per_launch == 0 || layers_per_launch == 1 || (layers_per_launch == 3 && fusable) ||
+          (layers_per_launch == 6 && sextets))) {
         set_error("gwd_set_tiling: %d layers per launch not available for this model", layers_per_launch);
         return GWD_ERR_ARG;
     }
     if (batch_windows < 1 || batch_windows > 8192) { set_error("gwd_set_tiling: batch_windows not in [1, 8192]"); return GWD_ERR_ARG; }
     m->lp_rows = tile_rows;
     m->lp_waves = waves;
-    m->lp_fuse = layers_per_launch == 0 ? 3 : layers_per_launch;
+    m->lp_fuse = layers_per_launch == 0 ? default_layers_per_launch(m) : layers_per_launch;
     m->batch_windows = batch_windows;
     return GWD_OK;
 }
@@ -242,12 +250,17 @@ gwd_status gwd_autotune(gwd_model* m, const gwd_stream* streams, int32_t n_strea
             fclose(f);
         }
     }
-    // candidates: fused launches (64-row chunks, 4 waves) aiming at 512, 1024 or 2048 blocks, one
-    // layer per launch in each tiling, each at three batch sizes; and the persistent forward (one
-    // launch, where every layer is in a fused launch at this window; its batch size is moot)
+    // candidates: fused launches (64-row chunks, 4 waves) aiming at 512, 1024 or 2048 blocks, BF16
+    // sextets (stacks of ten layers) aiming at 512 or 1024, one layer per launch in each tiling,
+    // each at three batch sizes; and the persistent forward (one launch, where every layer is in a
+    // fused launch at this window; its batch size is moot)
     std::vector<Sched> cand = {{0, 0, 1, 0, 0}};
     if (lowp) cand = {{64, 4, 3, 512, 0}, {64, 4, 3, 1024, 0}, {64, 4, 3, 2048, 0}, {64, 4, 1, 0, 0}, {64, 8, 1, 0, 0},
                       {128, 4, 1, 0, 0}};
+    if (lowp && m->prec == GWD_BF16 && m->arch.layers_per_stack == 10) {
+        cand.push_back({64, 4, 6, 512, 0});
+        cand.push_back({64, 4, 6, 1024, 0});
+    }
     if (lowp && !m->two_branch) {
         const int32_t fuse0 = m->lp_fuse;
         m->lp_fuse = 3;

@@ -159,7 +159,9 @@ def test_fused_launch_layer_local_parity(g, model, blob, first):
     from oracle.quant import to_bf16
     prec, m = model
     T, nw, C = 4096, 2, 128
+    m.set_tiling(0, 0, 512, 3)     # triples and quads (BF16 runs sextets by default)
     nl = m.fused_layers(first, T)
+    m.set_tiling()
     print(f"case: {prec} fused launch at layer {first} ({nl} layers)", flush=True)
     assert nl == (4 if first % 10 == 6 else 3)
     p = unpack(FULL, blob.astype(np.float64))
@@ -167,8 +169,10 @@ def test_fused_launch_layer_local_parity(g, model, blob, first):
     x = (rng.standard_normal((nw, T, C)) * 3).astype(np.float32)
     sk = (rng.standard_normal((nw, T, C)) * 4).astype(np.float32)
     sk_d = to_dev(sk.copy())
+    m.set_tiling(0, 0, 512, 3)
     pre_d, xo_d, so_d = m.debug_fused(0, first, to_dev(x), nw, T, sk_d)
     torch.cuda.synchronize()
+    m.set_tiling()
     pre_g = pre_d.cpu().numpy().astype(np.float64).reshape(nl, nw, T, 2 * C)
     xo_g = xo_d.cpu().numpy().astype(np.float64).reshape(nl, nw, T, C)
     so_g = so_d.cpu().numpy().astype(np.float64).reshape(nl, nw, T, C)
@@ -180,6 +184,41 @@ def test_fused_launch_layer_local_parity(g, model, blob, first):
         layer = first + j
         check_layer(prec, p, layer, xb, skip_in, pre_g[j], xo_g[j], so_g[j], f"{prec} fused {first}: layer {layer}")
         xb, skip_in = xo_g[j], so_g[j]
+
+
+@pytest.mark.parametrize("first,T", [(0, 4096), (10, 4096), (16, 4096), (6, 8192), (20, 2048), (26, 8192)])
+def test_sextet_layer_local_parity(g, blob, first, T):
+    """BF16 sextets (six layers per launch, dilations d0 .. 32 d0, each layer with history rows of
+    its own) and the quads after them, layer by layer against the oracle as above. At T = 8192
+    the quads' sub-sequences are two chunks long, so their history rows cross a chunk edge; two
+    windows split the dilation-1 sub-sequences into one-chunk segments, each after a warm-up
+    chunk that must rebuild the history of all six layers."""
+    from oracle.arch import FULL, unpack
+    from oracle.quant import to_bf16
+    m = g.Model(g.full_arch(), blob, "bf16")
+    m.set_tiling(0, 0, 512, 6)
+    nw, C = 2, 128
+    nl = m.fused_layers(first, T)
+    print(f"case: bf16 sextet form, launch at layer {first} ({nl} layers), T = {T}", flush=True)
+    assert nl == (4 if first % 10 == 6 else 6)
+    p = unpack(FULL, blob.astype(np.float64))
+    rng = np.random.default_rng(300 + first)
+    x = (rng.standard_normal((nw, T, C)) * 3).astype(np.float32)
+    sk = (rng.standard_normal((nw, T, C)) * 4).astype(np.float32)
+    sk_d = to_dev(sk.copy())
+    pre_d, xo_d, so_d = m.debug_fused(0, first, to_dev(x), nw, T, sk_d)
+    torch.cuda.synchronize()
+    pre_g = pre_d.cpu().numpy().astype(np.float64).reshape(nl, nw, T, 2 * C)
+    xo_g = xo_d.cpu().numpy().astype(np.float64).reshape(nl, nw, T, C)
+    so_g = so_d.cpu().numpy().astype(np.float64).reshape(nl, nw, T, C)
+    assert np.array_equal(sk_d.cpu().numpy().astype(np.float64).reshape(nw, T, C), so_g[-1])
+    xb = to_bf16(x.astype(np.float64))
+    skip_in = None if first == 0 else sk.astype(np.float64)
+    for j in range(nl):
+        layer = first + j
+        check_layer("bf16", p, layer, xb, skip_in, pre_g[j], xo_g[j], so_g[j], f"bf16 sextet form {first}: layer {layer}")
+        xb, skip_in = xo_g[j], so_g[j]
+    m.close()
 
 
 def test_end_to_end_error_stated(g, model, blob):

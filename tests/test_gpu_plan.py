@@ -67,7 +67,8 @@ def test_tilings_and_batches_do_not_change_results(g, prec):
     xs = [to_dev(synth.make_stream(310, 20.0, 1)[0]), to_dev(synth.make_stream(311, 0.6, 0)[0]),
           to_dev(synth.make_stream(312, 3.3, 0)[0][: 3 * 4096 + 1234])]
     ref = None
-    for fuse in (1, 3):
+    fuses = (1, 3, 6) if prec == "bf16" else (1, 3)   # six layers per launch: BF16 sextets
+    for fuse in fuses:
         for rows, waves in TILINGS:
             for nb in (7, 64, 300, 512):
                 m.set_tiling(rows, waves, nb, fuse)
@@ -79,8 +80,9 @@ def test_tilings_and_batches_do_not_change_results(g, prec):
     for blocks in (1024, 2048, 8192):
         m.set_fused_blocks(blocks)
         for nb in (64, 512):
-            m.set_tiling(64, 4, nb, 3)
-            assert torch.equal(m.forward(xs, 4096, 256, 1), ref), (blocks, nb)
+            for fuse in fuses[1:]:
+                m.set_tiling(64, 4, nb, fuse)
+                assert torch.equal(m.forward(xs, 4096, 256, 1), ref), (blocks, nb, fuse)
     m.set_fused_blocks(0)
     m.close()
 
@@ -92,11 +94,11 @@ def test_autotune_picks_a_valid_tiling(g, tmp_path, monkeypatch):
     m = g.Model(g.full_arch(), synth.full_weights(11), "bf16")
     x = to_dev(synth.make_stream(311, 40.0, 1)[0])
     rw, w, fu, b, fb, pe = m.autotune([x])
-    assert (rw, w) in TILINGS and fu in (1, 3) and b in (256, 512, 1024) and pe in (0, 1)
+    assert (rw, w) in TILINGS and fu in (1, 3, 6) and b in (256, 512, 1024) and pe in (0, 1)
     if pe:    # the persistent forward: fused layers, one launch
         assert fu == 3 and fb == 0 and b == 512
     else:
-        assert fb in ((512, 1024, 2048) if fu == 3 else (0,))
+        assert fb in ((512, 1024, 2048) if fu == 3 else (512, 1024) if fu == 6 else (0,))
     assert cache.read_text().strip().endswith(f"{rw} {w} {fu} {b} {fb} {pe}")
     print(f"autotuned: rows {rw}, waves {w}, layers per launch {fu}, batch {b}, fused blocks {fb}, "
           f"persistent {pe}", flush=True)
@@ -133,9 +135,11 @@ def test_fused_triples_with_partial_chunks(g, prec, W, S):
     m = g.Model(g.full_arch(), synth.full_weights(12), prec)
     xs = [to_dev(synth.make_stream(330, 6.0, 1)[0]), to_dev(synth.make_stream(331, 1.1, 0)[0][:4321])]
     res = {}
-    for fuse in (1, 3):
+    fuses = (1, 3, 6) if prec == "bf16" else (1, 3)
+    for fuse in fuses:
         m.set_tiling(0, 0, 64, fuse)
         res[fuse] = (m.forward(xs, W, S, 2).clone(), m.forward(xs, W, S, 1).clone())
-    assert torch.equal(res[1][0], res[3][0])
-    assert torch.equal(res[1][1], res[3][1])
+    for fuse in fuses[1:]:
+        assert torch.equal(res[1][0], res[fuse][0]), fuse
+        assert torch.equal(res[1][1], res[fuse][1]), fuse
     m.close()

@@ -158,6 +158,31 @@ def test_backward_is_deterministic(g):
     m.close()
 
 
+def test_bf16_training_with_sextets_equals_triples(g):
+    """The training forward takes the inference forward's fused launches: with six layers per launch
+    (BF16 sextets, then quads) two steps give the same loss, gradient and weights, bit for bit, as
+    with triples and quads."""
+    from paper_2201_11133_amd import synth
+    print("case: bf16 training, sextets against triples", flush=True)
+    B, T = 4, 4096
+    blob = synth.full_weights(36)
+    x, injs = synth.make_windows(407, B, B // 2)
+    y = np.zeros((B, T), np.float32)
+    for i, inj in injs:
+        y[i] = synth.box_labels(T, inj.tc)
+    xd, yd = to_dev(x), to_dev(y)
+    res = []
+    for fuse in (3, 6):
+        m = g.Model(g.full_arch(), blob, "bf16")
+        m.set_tiling(0, 0, 512, fuse)
+        tr = g.Trainer(m, blob, B, T)
+        losses = [float(tr.step(xd, yd)[0].item()) for _ in range(2)]
+        res.append((losses, tr.grad.clone(), tr.master.clone()))
+        m.close()
+    assert res[0][0] == res[1][0]
+    assert torch.equal(res[0][1], res[1][1]) and torch.equal(res[0][2], res[1][2])
+
+
 # ---------------------------------------------------------------- Adam, BCE
 def test_adam_matches_oracle_and_refreshes_weights(g):
     from oracle.train import adam_step
