@@ -427,10 +427,10 @@ void gwd_plan_free(gwd_plan* plan);
  *     dilations d, 2d, 4d of a stack run as one launch, and the triple at
  *     stack position 6 also takes the stack's last layer (four layers) when
  *     the sub-sequences at its dilation fit one 64-row chunk (window <= 64 x
- *     that dilation, e.g. 4096 at 64); 6 (BF16 models with stacks of ten
- *     layers) = sextets: stack positions 0-5 (dilations 1-32) in one launch,
- *     then 6-9 in another at any window length; 1 = one launch per layer;
- *     0 = default (6 where sextets apply, else 3); FP32 models accept 0 or 1;
+ *     that dilation, e.g. 4096 at 64); 6 (stacks of ten layers) = sextets:
+ *     stack positions 0-5 (dilations 1-32) in one launch, then 6-9 in another
+ *     at any window length; 1 = one launch per layer; 0 = default (6 where
+ *     sextets apply, else 3); FP32 models accept 0 or 1;
  *   batch_windows: windows per batch of layer launches (1..8192, default 512;
  *     gwd_forward lowers it for a call whose activations would not fit in 60 %
  *     of the free device memory, e.g. windows of 2^20 samples).
@@ -470,7 +470,7 @@ gwd_status gwd_set_persistent(gwd_model* model, int32_t on);
 /* Autotuner (the engine's kernel choice by profiling, "Optimization with
  * TensorRT"): times gwd_forward (out_mode 0) on the given request for every
  * schedule candidate (BF16/FP8: fused launches aiming at 512, 1024 and 2048
- * blocks, BF16 with stacks of ten layers also sextets aiming at 512 and 1024,
+ * blocks, with stacks of ten layers also sextets aiming at 512 and 1024,
  * and the three tilings one layer per launch; all: batch 256, 512,
  * 1024 windows; BF16/FP8 gated models where the window allows it: the
  * persistent forward), keeps the fastest on the model and reports it

@@ -605,17 +605,20 @@ static LayerArgsLP lp_args(gwd_model* m, int member, int l) {
 // the bf16-rounded x.
 // The lane that computes output channels c of rows r in one layer computes the same channels of the
 // same rows in the next, so the residual stream of the chunk stays in registers (four bf16 channels
-// per 8-byte word); the LDS holds only the E4M3 operand buffers (with their history rows), the E4M3
-// gate output, a bf16 staging buffer for the chunk's input and output rows, and the biases and
-// scales of the launch's layers.
+// per 8-byte word); the LDS holds only the E4M3 operand buffers (one of which takes the E4M3 gate
+// output) and history rows, a bf16 staging buffer for the chunk's input and output rows, and the
+// biases and scales of the launch's layers.
+// Layer j reads operand buffer j % 3, writes buffer (j + 1) % 3 and puts its E4M3 gate output in
+// buffer (j + 2) % 3; its history rows are H_j, at row 2^j - 1 of the history area, as in the BF16
+// form.
 constexpr int FX_EROW = kC + 16;                                   // E4M3 row + 16-byte pad
-constexpr int FX_E0 = 8 * FX_EROW;                                 // history rows as in the BF16 kernel: 8, 2, 4
-constexpr int FX_E1 = FX_E0 + (FU_ROWS + 2) * FX_EROW;
-constexpr int FX_E2 = FX_E1 + (FU_ROWS + 4) * FX_EROW;
-constexpr int FX_G = FX_E2 + FU_ROWS * FX_EROW;
-constexpr int FX_XS = FX_G + FU_ROWS * FX_EROW;                    // bf16 staging rows
+constexpr int FX_E0 = 0;
+constexpr int FX_E1 = FU_ROWS * FX_EROW;
+constexpr int FX_E2 = 2 * FU_ROWS * FX_EROW;
+constexpr int FX_H = 3 * FU_ROWS * FX_EROW;
+constexpr int FX_XS = FX_H + ((1 << FU_MAXL) - 1) * FX_EROW;       // bf16 staging rows
 constexpr int FX_BI = FX_XS + FU_ROWS * FU_XROW;                   // [layer][conv b | conv s | rs b | rs s]
-constexpr int FX_LDS = FX_BI + 4 * 4 * 2 * kC * 4;                 // 72,672 bytes: two blocks per CU
+constexpr int FX_LDS = FX_BI + FU_MAXL * 4 * 2 * kC * 4;           // 78,704 bytes: two blocks per CU
 static_assert(2 * FX_LDS <= 160 * 1024, "two FP8 fused blocks per CU");
 
 __device__ inline uint8_t* fx_buf(uint8_t* lds, int j) { return lds + (j == 0 ? FX_E0 : j == 1 ? FX_E1 : FX_E2); }
@@ -664,10 +667,10 @@ __device__ __forceinline__ void fused_fp8_body(const FA& p, const IO& io, uint8_
 // - Triples (lp_fuse 3) start at stack positions 0, 3, 6; the triple at 6 also takes the stack's
 //   last layer (a quad) when the sub-sequences at its dilation are one chunk long. A triple never
 //   includes the network's last layer.
-// - Sextets (lp_fuse 6, BF16 stacks of ten layers): positions 0-5 in one launch, then 6-9 as a
-//   quad at any window length (each BF16 layer keeps history rows of its own).
+// - Sextets (lp_fuse 6, stacks of ten layers): positions 0-5 in one launch, then 6-9 as a quad at
+//   any window length (each layer keeps history rows of its own).
 static int fused_layers_in(const gwd_model* m, int l, int T, int mode) {
-    if (m->prec == GWD_BF16 && mode == 6 && m->arch.layers_per_stack == 10 && T > 0) {
+    if ((m->prec == GWD_BF16 || m->prec == GWD_FP8_E4M3) && mode == 6 && m->arch.layers_per_stack == 10 && T > 0) {
         const int i = l % 10;
         return i == 0 ? 6 : i == 6 ? 4 : 0;
     }
@@ -718,8 +721,6 @@ static hipError_t launch_fused(gwd_model* m, int member, int l, int nl, const ui
     a.T = T;
     const int rows = FU_ROWS;                                           // sub-rows per chunk
     const int n_ch = ((T + a.d0 - 1) / a.d0 + rows - 1) / rows;       // chunks of the longest sub-sequence
-    if (FP8 && nl == 4 && n_ch != 1) return hipErrorInvalidValue;       // an FP8 quad needs one-chunk sub-sequences
-    if (FP8 && nl == 6) return hipErrorInvalidValue;                    // sextets are BF16 only
     // by default enough blocks for every resident slot (two per CU on 256 CUs); a segment after the
     // first costs one warm-up chunk; the autotuner may aim at more blocks (gwd_set_fused_blocks)
     const int64_t per = (int64_t)nb * a.d0;
@@ -746,6 +747,9 @@ static hipError_t launch_fused(gwd_model* m, int member, int l, int nl, const ui
             if (nl == 3) {
                 if (first) hipLaunchKernelGGL((fused_fp8_kernel<false, true, 3, false, false, true>), grid, dim3(256), 0, st, a);
                 else hipLaunchKernelGGL((fused_fp8_kernel<false, false, 3, false, false, true>), grid, dim3(256), 0, st, a);
+            } else if (nl == 6) {
+                if (first) hipLaunchKernelGGL((fused_fp8_kernel<false, true, 6, false, false, true>), grid, dim3(256), 0, st, a);
+                else hipLaunchKernelGGL((fused_fp8_kernel<false, false, 6, false, false, true>), grid, dim3(256), 0, st, a);
             } else {
                 if (first) return hipErrorInvalidValue;
                 if (l + 3 == L - 1) hipLaunchKernelGGL((fused_fp8_kernel<false, false, 4, true, false, true>), grid, dim3(256), 0, st, a);
@@ -770,6 +774,11 @@ static hipError_t launch_fused(gwd_model* m, int member, int l, int nl, const ui
             if (stream_in) launch_fused_fp8<true, true, 3, false>(g2, grid, st, a);
             else if (first) launch_fused_fp8<false, true, 3, false>(g2, grid, st, a);
             else launch_fused_fp8<false, false, 3, false>(g2, grid, st, a);
+        } else if (nl == 6) {
+            const bool g2 = m->two_branch;
+            if (stream_in) launch_fused_fp8<true, true, 6, false>(g2, grid, st, a);
+            else if (first) launch_fused_fp8<false, true, 6, false>(g2, grid, st, a);
+            else launch_fused_fp8<false, false, 6, false>(g2, grid, st, a);
         } else {
             if (first) return hipErrorInvalidValue;                      // stacks of at least 10 layers
             if (l + 3 == L - 1) launch_fused_fp8<false, false, 4, true>(m->two_branch, grid, st, a);
@@ -1132,9 +1141,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void p
 }
 
 // The network's launches for windows of length T in the triples-and-quads grouping: true when every
-// layer lies in a fused launch (windows up to 4096: the FP8 quads need one-chunk sub-sequences, and
-// so does this grouping's quad), the only form the persistent kernel runs. The model's schedule must
-// be a fused one (not one layer per launch).
+// layer lies in a fused launch (windows up to 4096: this grouping takes the quad only where the
+// sub-sequences are one chunk long), the only form the persistent kernel runs. The model's schedule
+// must be a fused one (not one layer per launch).
 bool persistent_supported(const gwd_model* m, int T) {
     if (m->arch.kind != 1 || m->two_branch || (m->prec != GWD_BF16 && m->prec != GWD_FP8_E4M3) || m->lp_fuse == 1)
         return false;

@@ -39,10 +39,11 @@ static hipError_t stamp_after_batch(void* ctx, int64_t bi, hipStream_t st) {
     return launch_stamp(((StampCtx*)ctx)->stamps + bi + 1, st);
 }
 
-// BF16 gated models with stacks of ten layers run sextets and quads (fewer launches, so fewer
-// round trips of the residual and skip streams through HBM); other BF16/FP8 models triples and quads.
+// BF16/FP8 gated models with stacks of ten layers run sextets and quads (fewer launches, so fewer
+// round trips of the residual and skip streams through HBM); other models triples and quads.
 int default_layers_per_launch(const gwd_model* m) {
-    return (m->arch.kind == 1 && m->prec == GWD_BF16 && m->arch.layers_per_stack == 10) ? 6 : 3;
+    return (m->arch.kind == 1 && (m->prec == GWD_BF16 || m->prec == GWD_FP8_E4M3) && m->arch.layers_per_stack == 10)
+               ? 6 : 3;
 }
 
 }  // namespace gwd
@@ -174,7 +175,7 @@ gwd_status gwd_set_tiling(gwd_model* m, int32_t tile_rows, int32_t waves, int32_
         return GWD_ERR_ARG;
     }
     const bool fusable = lowp;
-    const bool sextets = m->arch.kind == 1 && m->prec == GWD_BF16 && m->arch.layers_per_stack == 10;
+    const bool sextets = lowp && m->arch.layers_per_stack == 10;
     if (!(layers_per_launch == 0 || layers_per_launch == 1 || (layers_per_launch == 3 && fusable) ||
           (layers_per_launch == 6 && sextets))) {
         set_error("gwd_set_tiling: %d layers per launch not available for this model", layers_per_launch);
@@ -250,14 +251,14 @@ gwd_status gwd_autotune(gwd_model* m, const gwd_stream* streams, int32_t n_strea
             fclose(f);
         }
     }
-    // candidates: fused launches (64-row chunks, 4 waves) aiming at 512, 1024 or 2048 blocks, BF16
+    // candidates: fused launches (64-row chunks, 4 waves) aiming at 512, 1024 or 2048 blocks,
     // sextets (stacks of ten layers) aiming at 512 or 1024, one layer per launch in each tiling,
     // each at three batch sizes; and the persistent forward (one launch, where every layer is in a
     // fused launch at this window; its batch size is moot)
     std::vector<Sched> cand = {{0, 0, 1, 0, 0}};
     if (lowp) cand = {{64, 4, 3, 512, 0}, {64, 4, 3, 1024, 0}, {64, 4, 3, 2048, 0}, {64, 4, 1, 0, 0}, {64, 8, 1, 0, 0},
                       {128, 4, 1, 0, 0}};
-    if (lowp && m->prec == GWD_BF16 && m->arch.layers_per_stack == 10) {
+    if (lowp && m->arch.layers_per_stack == 10) {
         cand.push_back({64, 4, 6, 512, 0});
         cand.push_back({64, 4, 6, 1024, 0});
     }

@@ -186,20 +186,21 @@ def test_fused_launch_layer_local_parity(g, model, blob, first):
         xb, skip_in = xo_g[j], so_g[j]
 
 
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
 @pytest.mark.parametrize("first,T", [(0, 4096), (10, 4096), (16, 4096), (6, 8192), (20, 2048), (26, 8192)])
-def test_sextet_layer_local_parity(g, blob, first, T):
-    """BF16 sextets (six layers per launch, dilations d0 .. 32 d0, each layer with history rows of
-    its own) and the quads after them, layer by layer against the oracle as above. At T = 8192
-    the quads' sub-sequences are two chunks long, so their history rows cross a chunk edge; two
+def test_sextet_layer_local_parity(g, blob, prec, first, T):
+    """Sextets (six layers per launch, dilations d0 .. 32 d0, each layer with history rows of its
+    own) and the quads after them, layer by layer against the oracle as above. At T = 8192 the
+    quads' sub-sequences are two chunks long, so their history rows cross a chunk edge; two
     windows split the dilation-1 sub-sequences into one-chunk segments, each after a warm-up
     chunk that must rebuild the history of all six layers."""
     from oracle.arch import FULL, unpack
     from oracle.quant import to_bf16
-    m = g.Model(g.full_arch(), blob, "bf16")
+    m = g.Model(g.full_arch(), blob, prec)
     m.set_tiling(0, 0, 512, 6)
     nw, C = 2, 128
     nl = m.fused_layers(first, T)
-    print(f"case: bf16 sextet form, launch at layer {first} ({nl} layers), T = {T}", flush=True)
+    print(f"case: {prec} sextet form, launch at layer {first} ({nl} layers), T = {T}", flush=True)
     assert nl == (4 if first % 10 == 6 else 6)
     p = unpack(FULL, blob.astype(np.float64))
     rng = np.random.default_rng(300 + first)
@@ -216,7 +217,7 @@ def test_sextet_layer_local_parity(g, blob, first, T):
     skip_in = None if first == 0 else sk.astype(np.float64)
     for j in range(nl):
         layer = first + j
-        check_layer("bf16", p, layer, xb, skip_in, pre_g[j], xo_g[j], so_g[j], f"bf16 sextet form {first}: layer {layer}")
+        check_layer(prec, p, layer, xb, skip_in, pre_g[j], xo_g[j], so_g[j], f"{prec} sextet form {first}: layer {layer}")
         xb, skip_in = xo_g[j], so_g[j]
     m.close()
 

@@ -67,7 +67,7 @@ def test_tilings_and_batches_do_not_change_results(g, prec):
     xs = [to_dev(synth.make_stream(310, 20.0, 1)[0]), to_dev(synth.make_stream(311, 0.6, 0)[0]),
           to_dev(synth.make_stream(312, 3.3, 0)[0][: 3 * 4096 + 1234])]
     ref = None
-    fuses = (1, 3, 6) if prec == "bf16" else (1, 3)   # six layers per launch: BF16 sextets
+    fuses = (1, 3, 6)   # one layer, triples and quads, sextets and quads per launch
     for fuse in fuses:
         for rows, waves in TILINGS:
             for nb in (7, 64, 300, 512):
@@ -135,7 +135,7 @@ def test_fused_triples_with_partial_chunks(g, prec, W, S):
     m = g.Model(g.full_arch(), synth.full_weights(12), prec)
     xs = [to_dev(synth.make_stream(330, 6.0, 1)[0]), to_dev(synth.make_stream(331, 1.1, 0)[0][:4321])]
     res = {}
-    fuses = (1, 3, 6) if prec == "bf16" else (1, 3)
+    fuses = (1, 3, 6)
     for fuse in fuses:
         m.set_tiling(0, 0, 64, fuse)
         res[fuse] = (m.forward(xs, W, S, 2).clone(), m.forward(xs, W, S, 1).clone())
