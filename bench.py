@@ -44,10 +44,10 @@ ACCURACY = {
     "bf16": "max |dp| 0.0113 vs the FP64 oracle on a trained member: meets the 2e-2 target (gated)",
     "fp8": "max |dp| 0.098 vs the FP64 oracle on a trained member: misses the 2e-2 target (stated, not gated)",
 }
-# HBM bytes per launch of the middle BF16 gated layer (512 windows), from two rocprofv3 --pmc runs
-# (FETCH_SIZE, WRITE_SIZE) scaled by a 1 GiB copy; valid only for the kernel source they were taken on
-# (profiles/gated_layer_bf16_hbm_traffic_64s.md).
-MEASURED_TRAFFIC = {"bf16": {"source_sha256_16": "cf52ec1247609588", "bytes": 3238478907, "windows": 512, "layers": 3}}
+# HBM bytes per launch of the dominant BF16 kernel, the middle stack's sextet (512 windows x 6 layers),
+# from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by a 1 GiB copy; valid only for the
+# kernel source they were taken on (profiles/fused_sextet_bf16_counters_64s.md).
+MEASURED_TRAFFIC = {"bf16": {"source_sha256_16": "9959a37d7c0e2c9f", "bytes": 3308353049, "windows": 512, "layers": 6}}
 
 
 def kernel_traffic(prec: str, windows: int, layers: int):
