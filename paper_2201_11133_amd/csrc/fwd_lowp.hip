@@ -477,6 +477,12 @@ struct FusedArgs {
     float* dbg_x;
     float* dbg_skip;
     int64_t dbg_rows;
+    // training recompute (BF16, DBG = 2): layer j's pre-activations at rec_pre + j rec_pre_stride
+    // ([rows][256] bf16) and, for j < NL - 1, its output at rec_x + j rec_x_stride ([rows][128] bf16)
+    uint16_t* rec_pre;
+    int64_t rec_pre_stride;
+    uint16_t* rec_x;
+    int64_t rec_x_stride;
 };
 
 __device__ inline uint8_t* fu_buf(uint8_t* lds, int j) { return lds + (j == 0 ? FU_B0 : j == 1 ? FU_B1 : FU_B2); }
@@ -543,9 +549,12 @@ struct ChunkRows {
 // network's last, which writes the skip sum only (its residual projection is not part of the model).
 // G2: the weights are block-diagonal over two 64-channel groups (the two-branch member); each wave
 // then takes only the k-steps of its own group's input channels, since the others multiply zeros.
-// DBG: test-support instantiation that also writes every layer's pre-activation, residual output and
-// running skip sum of the stored rows to the dbg_* buffers (the arithmetic is unchanged).
-template <bool FROM_STREAM, bool SKIP_INIT, int NL, bool LAST, bool G2, bool DBG = false>
+// DBG: 1, test-support instantiation that also writes every layer's pre-activation, residual output
+// and running skip sum of the stored rows to the dbg_* buffers; 2, the training recompute, which
+// writes every layer's pre-activation and (but for the last layer's, the chunk output) its output
+// in bf16 to the rec_* buffers and neither reads nor writes the skip sum. The arithmetic is
+// unchanged.
+template <bool FROM_STREAM, bool SKIP_INIT, int NL, bool LAST, bool G2, int DBG = 0>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void fused_bf16_kernel(FusedArgs p) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[FU_LDS];
 #define GWD_IO_BID blockIdx.x
@@ -562,7 +571,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
 }
 
 // The same body for the persistent forward: one block's piece of a launch on the window it owns.
-template <bool FROM_STREAM, bool SKIP_INIT, int NL, bool LAST, bool G2, bool DBG, class IO, class FA>
+template <bool FROM_STREAM, bool SKIP_INIT, int NL, bool LAST, bool G2, int DBG, class IO, class FA>
 __device__ __forceinline__ void fused_bf16_body(const FA& p, const IO& io, uint8_t* lds) {
 #define GWD_IO_BID io.bid()
 #define GWD_IO_X_IN io.x_in()
@@ -737,6 +746,19 @@ static hipError_t launch_fused(gwd_model* m, int member, int l, int nl, const ui
         a.S = fb->S;
     }
     const dim3 grid((unsigned)(per * a.n_seg));
+    if (dbg && dbg->rec_pre) {  // the training recompute (BF16): per-layer bf16 outputs, no skip sum
+        if (FP8 || stream_in || m->two_branch) return hipErrorInvalidValue;
+        a.rec_pre = dbg->rec_pre;
+        a.rec_pre_stride = dbg->rec_pre_stride;
+        a.rec_x = dbg->rec_x;
+        a.rec_x_stride = dbg->rec_x_stride;
+        a.skip = nullptr;
+        if (nl == 3) hipLaunchKernelGGL((fused_bf16_kernel<false, false, 3, false, false, 2>), grid, dim3(256), 0, st, a);
+        else if (nl == 6) hipLaunchKernelGGL((fused_bf16_kernel<false, false, 6, false, false, 2>), grid, dim3(256), 0, st, a);
+        else if (l + 3 == L - 1) hipLaunchKernelGGL((fused_bf16_kernel<false, false, 4, true, false, 2>), grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((fused_bf16_kernel<false, false, 4, false, false, 2>), grid, dim3(256), 0, st, a);
+        return hipGetLastError();
+    }
     if (dbg) {  // test support: the same launch with per-layer outputs (buffer input, dense weights)
         if (stream_in || m->two_branch) return hipErrorInvalidValue;
         a.dbg_pre = dbg->dbg_pre;
@@ -975,6 +997,21 @@ hipError_t launch_fused_train(gwd_model* m, int member, int l, int nl, const uin
                               float* skip, int nb, int T, hipStream_t st) {
     return m->prec == GWD_FP8_E4M3 ? launch_fused<true>(m, member, l, nl, x_in, x_out, skip, nb, T, nullptr, st)
                                    : launch_fused<false>(m, member, l, nl, x_in, x_out, skip, nb, T, nullptr, st);
+}
+// The training recompute of the fused launch at layer l (BF16 members): from the bf16 input x_in
+// [nb][T][128], layer j's pre-activations go to pre + j pre_stride ([nb T][256] bf16), its output to
+// xs + j xs_stride ([nb T][128] bf16) for j < nl - 1, and the last layer's output to x_out (unused
+// for the network's last layer). The skip sum is neither read nor written.
+hipError_t launch_fused_recompute(gwd_model* m, int member, int l, int nl, const uint16_t* x_in, uint16_t* x_out,
+                                  uint16_t* pre, int64_t pre_stride, uint16_t* xs, int64_t xs_stride, int nb, int T,
+                                  hipStream_t st) {
+    if (m->prec != GWD_BF16 || !pre || (nl > 1 && !xs)) return hipErrorInvalidValue;
+    FusedArgs r{};
+    r.rec_pre = pre;
+    r.rec_pre_stride = pre_stride;
+    r.rec_x = xs;
+    r.rec_x_stride = xs_stride;
+    return launch_fused<false>(m, member, l, nl, x_in, x_out, nullptr, nb, T, nullptr, st, &r);
 }
 hipError_t launch_f32_to_bf16(const float* x, int64_t n, uint16_t* y, hipStream_t st) {
     hipLaunchKernelGGL(f32_to_bf16_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, n, y);

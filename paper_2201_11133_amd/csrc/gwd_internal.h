@@ -175,6 +175,9 @@ hipError_t launch_fused_debug(gwd_model* m, int member, int l, const float* x_in
                               float* pre_out, float* x_out, float* skip_out, hipStream_t st);
 hipError_t launch_fused_train(gwd_model* m, int member, int l, int nl, const uint16_t* x_in, uint16_t* x_out,
                               float* skip, int nb, int T, hipStream_t st);
+hipError_t launch_fused_recompute(gwd_model* m, int member, int l, int nl, const uint16_t* x_in, uint16_t* x_out,
+                                  uint16_t* pre, int64_t pre_stride, uint16_t* xs, int64_t xs_stride, int nb, int T,
+                                  hipStream_t st);
 
 // Layers covered by the launch that starts at layer l (3 for a fused BF16 triple, else 1).
 int layers_per_launch(const gwd_model* m, int l);

@@ -196,14 +196,26 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
         // recompute the stack, keeping each layer's input and pre-activation
         // (BF16/FP8 members: the layer inputs XS are bf16, in the first half of each slot)
         const float* xin = saved + (int64_t)sidx * M * kC;
-        for (int i = 0; i < LPS; ++i) {
+        for (int i = 0; i < LPS;) {
             const int l = sidx * LPS + i;
             float* xs_i = fptr(b, f_xs + (int64_t)i * M * kC);
             if (i == 0)
                 HIPCHK(hipMemcpyAsync(xs_i, xin, M * kC * (BT ? 2 : 4), hipMemcpyDeviceToDevice, st), "copy stack input");
+            float* pre_i = fptr(b, f_pre + (int64_t)i * M * 2 * kC);
+            // BF16 members: the forward's fused launches, writing each layer's pre-activations and
+            // output in bf16 (the same arithmetic as one layer per launch)
+            const int nl = (m->prec == GWD_BF16) ? train_layers_per_launch(m, l, T) : 1;
+            if (nl > 1) {
+                float* xlast = (i + nl < LPS) ? fptr(b, f_xs + (int64_t)(i + nl) * M * kC) : G;
+                HIPCHK(launch_fused_recompute(m, member, l, nl, (const uint16_t*)xs_i, (uint16_t*)xlast,
+                                              (uint16_t*)pre_i, 4 * M * kC,
+                                              (uint16_t*)fptr(b, f_xs + (int64_t)(i + 1) * M * kC), 2 * M * kC, B, T, st),
+                       "recompute");
+                i += nl;
+                continue;
+            }
             // the stack's last output and the recomputed skip sum are not needed: scratch buffers
             float* xnext = (i + 1 < LPS) ? fptr(b, f_xs + (int64_t)(i + 1) * M * kC) : G;
-            float* pre_i = fptr(b, f_pre + (int64_t)i * M * 2 * kC);
             if (BT)  // (no skip sum: the recompute needs layer inputs and pre-activations only; the
                      // pre-activations in bf16, in the first half of each slot)
                 HIPCHK(launch_layer_train_bf16io(m, member, l, (const uint16_t*)xs_i, B, T, (uint16_t*)pre_i,
@@ -211,6 +223,7 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
             else
                 HIPCHK(launch_layer_debug(m, member, l, xs_i, B, T, pre_i, (l < L - 1) ? xnext : nullptr, SKS, st),
                        "recompute");
+            ++i;
         }
         for (int i = LPS - 1; i >= 0; --i) {
             const int l = sidx * LPS + i;

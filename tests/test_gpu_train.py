@@ -159,11 +159,12 @@ def test_backward_is_deterministic(g):
 
 
 def test_bf16_training_with_sextets_equals_triples(g):
-    """The training forward takes the inference forward's fused launches: with six layers per launch
-    (BF16 sextets, then quads) two steps give the same loss, gradient and weights, bit for bit, as
-    with triples and quads."""
+    """The training forward and the backward's recompute take the inference forward's fused
+    launches (the recompute's also write each layer's bf16 pre-activations and outputs): with six
+    layers per launch (sextets, then quads) and with triples and quads, two steps give the same
+    loss, gradient and weights, bit for bit, as with one layer per launch."""
     from paper_2201_11133_amd import synth
-    print("case: bf16 training, sextets against triples", flush=True)
+    print("case: bf16 training, sextets and triples against one layer per launch", flush=True)
     B, T = 4, 4096
     blob = synth.full_weights(36)
     x, injs = synth.make_windows(407, B, B // 2)
@@ -172,15 +173,16 @@ def test_bf16_training_with_sextets_equals_triples(g):
         y[i] = synth.box_labels(T, inj.tc)
     xd, yd = to_dev(x), to_dev(y)
     res = []
-    for fuse in (3, 6):
+    for fuse in (1, 3, 6):
         m = g.Model(g.full_arch(), blob, "bf16")
         m.set_tiling(0, 0, 512, fuse)
         tr = g.Trainer(m, blob, B, T)
         losses = [float(tr.step(xd, yd)[0].item()) for _ in range(2)]
         res.append((losses, tr.grad.clone(), tr.master.clone()))
         m.close()
-    assert res[0][0] == res[1][0]
-    assert torch.equal(res[0][1], res[1][1]) and torch.equal(res[0][2], res[1][2])
+    for k in (1, 2):
+        assert res[0][0] == res[k][0], k
+        assert torch.equal(res[0][1], res[k][1]) and torch.equal(res[0][2], res[k][2]), k
 
 
 # ---------------------------------------------------------------- Adam, BCE
