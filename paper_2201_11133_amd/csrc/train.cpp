@@ -202,9 +202,9 @@ static gwd_status bwd_kind1(gwd_model* m, int member, const float* u, int B, int
             if (i == 0)
                 HIPCHK(hipMemcpyAsync(xs_i, xin, M * kC * (BT ? 2 : 4), hipMemcpyDeviceToDevice, st), "copy stack input");
             float* pre_i = fptr(b, f_pre + (int64_t)i * M * 2 * kC);
-            // BF16 members: the forward's fused launches, writing each layer's pre-activations and
-            // output in bf16 (the same arithmetic as one layer per launch)
-            const int nl = (m->prec == GWD_BF16) ? train_layers_per_launch(m, l, T) : 1;
+            // BF16 members (not the two-branch image): the forward's fused launches, writing each
+            // layer's pre-activations and output in bf16 (the same arithmetic as one layer per launch)
+            const int nl = (m->prec == GWD_BF16 && !m->two_branch) ? train_layers_per_launch(m, l, T) : 1;
             if (nl > 1) {
                 float* xlast = (i + nl < LPS) ? fptr(b, f_xs + (int64_t)(i + nl) * M * kC) : G;
                 HIPCHK(launch_fused_recompute(m, member, l, nl, (const uint16_t*)xs_i, (uint16_t*)xlast,

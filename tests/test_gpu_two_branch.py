@@ -125,6 +125,31 @@ def test_fp8_training_is_refused(g, blob):
     m.close()
 
 
+def test_bf16_training_fused_equals_one_layer_per_launch(g, blob):
+    """BF16 training pass of the two-branch member: the forward through the fused sextets and quads
+    (zero blocks skipped) gives the same logits and gradient, bit for bit, as one layer per launch."""
+    from oracle.train import bce_grad
+    from paper_2201_11133_amd import synth
+    from tests.test_gpu_train import backward, fwd_train, labels
+    print("case: two-branch bf16 training, fused against one layer per launch", flush=True)
+    B, T = 2, 4096
+    u, _ = synth.make_windows(311, B, 1, W=T)
+    y = labels(B, T, 9)
+    u_d = to_dev(u)
+    res = []
+    for fuse in (0, 1):
+        m = g.Model(g.two_branch_arch(), blob, "bf16")
+        m.set_tiling(0, 0, 512, fuse)
+        z, saved = fwd_train(g, m, u_d, B, T, torch.float32)
+        dz = torch.from_numpy(bce_grad(z.cpu().numpy().astype(np.float64), y).astype(np.float32)).cuda()
+        grad, du = backward(g, m, u_d, B, T, saved, dz, torch.float32)
+        res.append((z.clone(), grad.clone(), du.clone()))
+        m.close()
+    assert bool(torch.isfinite(res[0][1]).all())
+    for a, b in zip(res[0], res[1]):
+        assert torch.equal(a, b)
+
+
 def test_gradient_fp32(g, blob):
     """FP32 training pass of the two-branch member: the gradient in its own blob layout (read back from
     the trunk image's) and the input gradient, per tensor against the oracle."""
