@@ -216,7 +216,7 @@ gwd_status forward_prepare(gwd_model* m, const gwd_stream* streams, int32_t n_st
     const bool persist = m->persistent;
     if (persist && !persistent_supported(m, window)) {
         set_error("gwd_forward: the persistent forward needs every layer in a fused launch (a gated BF16/FP8 model, "
-                  "three layers per launch, windows up to 4096); window %d", window);
+                  "a fused schedule, windows up to 4096); window %d", window);
         return GWD_ERR_UNSUPPORTED;
     }
     hipError_t e = hipSetDevice(m->device);

@@ -102,7 +102,7 @@ struct gwd_model {
     std::vector<int64_t> host_firsts;          // host copy of FwdBatch::firsts for the current request
     int32_t lp_rows = 0;                       // BF16/FP8 layer tiling: rows per tile (0 = default per precision)
     int32_t lp_waves = 0;                      // and waves per block
-    int32_t lp_fuse = 3;                       // BF16/FP8: layers per launch (3 = fused triples and quads, 6 = BF16 sextets and quads, 1 = one per launch)
+    int32_t lp_fuse = 3;                       // BF16/FP8: layers per launch (3 = fused triples and quads, 6 = sextets and quads, 1 = one per launch)
     int32_t fused_blocks = 0;                  // blocks a fused launch aims at (segments per sub-sequence); 0 = 512
     bool two_branch = false;                   // loaded as kind 2 and expanded to the block-diagonal kind-1 image
     gwd_arch branch_arch{};                    // kind 2: the architecture as loaded
@@ -179,7 +179,7 @@ hipError_t launch_fused_recompute(gwd_model* m, int member, int l, int nl, const
                                   uint16_t* pre, int64_t pre_stride, uint16_t* xs, int64_t xs_stride, int nb, int T,
                                   hipStream_t st);
 
-// Layers covered by the launch that starts at layer l (3 for a fused BF16 triple, else 1).
+// Layers covered by the launch that starts at layer l (3, 4 or 6 for a fused launch, else 1).
 int layers_per_launch(const gwd_model* m, int l);
 // One production launch of a middle layer on the workspace buffers (timing support).
 hipError_t launch_layer_production(gwd_model* m, int member, int layer, void* x_in, void* x_out, float* skip, int nb,

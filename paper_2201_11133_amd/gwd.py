@@ -229,7 +229,7 @@ class Model:
 
     def time_layer(self, member: int = 0, layer: int = 15, reps: int = 10, stream=None):
         """(ms per launch, windows per launch, layers per launch) of the forward's launch at a middle
-        layer (a fused triple covers three layers, a BF16 sextet six)."""
+        layer (a fused triple covers three layers, a sextet six)."""
         ms, nw, nl = ctypes.c_float(0), ctypes.c_int32(0), ctypes.c_int32(0)
         check(lib.gwd_debug_time_layer(self.h, member, layer, reps, ctypes.byref(ms), ctypes.byref(nw),
                                        ctypes.byref(nl), _stream_handle(stream)))
