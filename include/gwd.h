@@ -459,10 +459,9 @@ gwd_status gwd_set_fused_blocks(gwd_model* model, int32_t blocks);
  * waits for another. Results are bit for bit those of the launch sequence.
  * (The paper's engine is built once and replayed for every batch,
  * "Optimization with TensorRT"; here the whole ragged request is one launch.)
- * It runs the triples-and-quads grouping (whatever the fused schedule set by
- * gwd_set_tiling, 3 or 6 layers per launch) and needs every layer in one of
- * those launches at the request's window (windows up to 4096) and a fused
- * schedule; gwd_forward returns GWD_ERR_UNSUPPORTED otherwise. It leaves the workspace without the batch layout that
+ * It runs the fused grouping set by gwd_set_tiling (sextets and quads, or
+ * triples and quads) and needs a fused schedule and windows of up to 4096
+ * samples; gwd_forward returns GWD_ERR_UNSUPPORTED otherwise. It leaves the workspace without the batch layout that
  * gwd_debug_time_layer reads. GWD_ERR_ARG unless on is 0 or 1;
  * GWD_ERR_UNSUPPORTED for other models (FP32, small member, two-branch). */
 gwd_status gwd_set_persistent(gwd_model* model, int32_t on);

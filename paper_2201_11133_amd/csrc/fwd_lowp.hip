@@ -691,8 +691,8 @@ static int fused_layers_in(const gwd_model* m, int l, int T, int mode) {
     return l + 2 < L - 1 ? 3 : 0;
 }
 static int fused_layers(const gwd_model* m, int l, int T) { return fused_layers_in(m, l, T, m->lp_fuse); }
-// The persistent kernel's grouping, whatever the model's schedule: triples and quads.
-static int persist_layers(const gwd_model* m, int l, int T) { return fused_layers_in(m, l, T, 3); }
+// The persistent kernel's grouping: the model's sextets and quads, else triples and quads.
+static int persist_layers(const gwd_model* m, int l, int T) { return fused_layers_in(m, l, T, m->lp_fuse == 6 ? 6 : 3); }
 
 // One fused launch of layers l .. l + nl - 1 over nb windows of length T.
 template <bool FROM_STREAM, bool SKIP_INIT, int NL, bool LAST>
@@ -1121,14 +1121,18 @@ __device__ __forceinline__ void persistent_piece(int kind, const ConstFusedArgs&
             case 0: fused_fp8_body<true, true, 3, false, false, false>(p, io, lds); break;
             case 1: fused_fp8_body<false, false, 3, false, false, false>(p, io, lds); break;
             case 2: fused_fp8_body<false, false, 4, false, false, false>(p, io, lds); break;
+            case 4: fused_fp8_body<true, true, 6, false, false, false>(p, io, lds); break;
+            case 5: fused_fp8_body<false, false, 6, false, false, false>(p, io, lds); break;
             default: fused_fp8_body<false, false, 4, true, false, false>(p, io, lds); break;
         }
     } else {
         switch (kind) {
-            case 0: fused_bf16_body<true, true, 3, false, false, false>(p, io, lds); break;
-            case 1: fused_bf16_body<false, false, 3, false, false, false>(p, io, lds); break;
-            case 2: fused_bf16_body<false, false, 4, false, false, false>(p, io, lds); break;
-            default: fused_bf16_body<false, false, 4, true, false, false>(p, io, lds); break;
+            case 0: fused_bf16_body<true, true, 3, false, false, 0>(p, io, lds); break;
+            case 1: fused_bf16_body<false, false, 3, false, false, 0>(p, io, lds); break;
+            case 2: fused_bf16_body<false, false, 4, false, false, 0>(p, io, lds); break;
+            case 4: fused_bf16_body<true, true, 6, false, false, 0>(p, io, lds); break;
+            case 5: fused_bf16_body<false, false, 6, false, false, 0>(p, io, lds); break;
+            default: fused_bf16_body<false, false, 4, true, false, 0>(p, io, lds); break;
         }
     }
 }
@@ -1177,12 +1181,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void p
     }
 }
 
-// The network's launches for windows of length T in the triples-and-quads grouping: true when every
-// layer lies in a fused launch (windows up to 4096: this grouping takes the quad only where the
-// sub-sequences are one chunk long), the only form the persistent kernel runs. The model's schedule
-// must be a fused one (not one layer per launch).
+// The network's launches for windows of length T in the model's fused grouping (sextets and quads,
+// else triples and quads): true when every layer lies in a fused launch, the only form the
+// persistent kernel runs, for windows of up to 4096 samples (where the triples-and-quads grouping
+// also ends each stack on a quad). The model's schedule must be a fused one.
 bool persistent_supported(const gwd_model* m, int T) {
-    if (m->arch.kind != 1 || m->two_branch || (m->prec != GWD_BF16 && m->prec != GWD_FP8_E4M3) || m->lp_fuse == 1)
+    if (m->arch.kind != 1 || m->two_branch || (m->prec != GWD_BF16 && m->prec != GWD_FP8_E4M3) || m->lp_fuse == 1 ||
+        T > 4096)
         return false;
     const int L = m->arch.n_stacks * m->arch.layers_per_stack;
     for (int l = 0; l < L;) {
@@ -1243,7 +1248,8 @@ void persistent_tables(gwd_model* m, const FwdBatch& fb, std::vector<char>& host
             a.n_streams = fb.n_streams;
             a.S = fb.S;
             la[mem * n_launch + i] = a;
-            if (mem == 0) kinds[i] = l == 0 ? 0 : nl == 3 ? 1 : (l + 3 == L - 1 ? 3 : 2);
+            // kinds: 0 first triple, 1 triple, 2 quad, 3 the network's last quad, 4 first sextet, 5 sextet
+            if (mem == 0) kinds[i] = l == 0 ? (nl == 6 ? 4 : 0) : nl == 3 ? 1 : nl == 6 ? 5 : (l + 3 == L - 1 ? 3 : 2);
         }
         const MemberWeights& mw = m->members[mem];
         const float* base = (const float*)mw.base;
