@@ -262,10 +262,10 @@ gwd_status gwd_autotune(gwd_model* m, const gwd_stream* streams, int32_t n_strea
         cand.push_back({64, 4, 6, 512, 0});
         cand.push_back({64, 4, 6, 1024, 0});
     }
-    if (lowp && !m->two_branch) {
-        const int32_t fuse0 = m->lp_fuse;
-        m->lp_fuse = 3;
-        if (persistent_supported(m, window)) cand.push_back({64, 4, 3, 0, 1});
+    if (lowp && !m->two_branch) {   // the persistent forward in the model's default fused grouping
+        const int32_t fuse0 = m->lp_fuse, fuse = default_layers_per_launch(m);
+        m->lp_fuse = fuse;
+        if (persistent_supported(m, window)) cand.push_back({64, 4, fuse, 0, 1});
         m->lp_fuse = fuse0;
     }
     const int batch_opts[] = {256, 512, 1024};

@@ -95,8 +95,8 @@ def test_autotune_picks_a_valid_tiling(g, tmp_path, monkeypatch):
     x = to_dev(synth.make_stream(311, 40.0, 1)[0])
     rw, w, fu, b, fb, pe = m.autotune([x])
     assert (rw, w) in TILINGS and fu in (1, 3, 6) and b in (256, 512, 1024) and pe in (0, 1)
-    if pe:    # the persistent forward: fused layers, one launch
-        assert fu == 3 and fb == 0 and b == 512
+    if pe:    # the persistent forward: fused layers (sextets and quads here), one launch
+        assert fu == 6 and fb == 0 and b == 512
     else:
         assert fb in ((512, 1024, 2048) if fu == 3 else (512, 1024) if fu == 6 else (0,))
     assert cache.read_text().strip().endswith(f"{rw} {w} {fu} {b} {fb} {pe}")
