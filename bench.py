@@ -47,7 +47,7 @@ ACCURACY = {
 # HBM bytes per launch of the dominant BF16 kernel, the middle stack's sextet (512 windows x 6 layers),
 # from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by a 1 GiB copy; valid only for the
 # kernel source they were taken on (profiles/fused_sextet_bf16_counters_64s.md).
-MEASURED_TRAFFIC = {"bf16": {"source_sha256_16": "0b82a9b3ba87289a", "bytes": 3306692126, "windows": 512, "layers": 6}}
+MEASURED_TRAFFIC = {"bf16": {"source_sha256_16": "6f025f4101bb5838", "bytes": 3306783521, "windows": 512, "layers": 6}}
 
 
 def kernel_traffic(prec: str, windows: int, layers: int):
