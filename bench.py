@@ -243,11 +243,11 @@ def ragged_workload(gwd, blobs, prec: str):
                                                           "batch_windows": batch, "fused_blocks": blocks,
                                                           "persistent": persistent},
            "triggers": n_trig, "precision": prec}
-    # the other form of the same request: the persistent launch if the autotuner chose the launch
-    # sequence (fused launches, its fastest shape), else the launch sequence
+    # the other form of the same request: the persistent launch (in the default fused grouping) if the
+    # autotuner chose the launch sequence, else the launch sequence
     m.set_persistent(not persistent)
     if not persistent:
-        m.set_tiling(64, 4, 512, 3)
+        m.set_tiling(64, 4, 512, 0)
         m.set_fused_blocks(0)
     wall2, per2, tot2, n_trig2, out_b = timed_plan()
     res["persistent_launch" if not persistent else "launch_sequence"] = {
