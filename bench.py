@@ -511,7 +511,7 @@ def main():
                     help="also run one plain 1 GiB device-to-device copy (counter calibration for profiles)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(windows shard by time with no exchange; see the design notes)", file=sys.stderr)
         sys.exit(2)
 

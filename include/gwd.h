@@ -131,7 +131,7 @@ typedef struct {
 
 /* Number of float parameters of one member in the canonical flat blob (the
  * paper's members are the gated dilated-convolution networks of "AI
- * architecture", Fig. 1; their widths and depths are this build's reading)
+ * architecture", Fig. 1; their widths and depths are this library's reading)
  * (kind 0 with 16 channels: 1,681; kind 1 with 128 channels, 3x10 layers:
  * 2,964,993; kind 2 with two 64-channel branches and a 128-channel head:
  * 1,498,497), or -1 for an invalid descriptor.

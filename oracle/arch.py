@@ -5,7 +5,7 @@ Test infrastructure only (see the package docstring).
 The paper describes its classifier as a modified WaveNet that reads the two
 detector strains sampled at 4096 Hz and emits a classification probability per
 time step (Materials and Methods, "AI architecture"; Fig. 1). It gives no
-widths, depths or kernel sizes, so this build fixes two concrete members:
+widths, depths or kernel sizes, so this package fixes two concrete members:
 
 kind 0, "plain stack": four causal convolutions, kernel 2, dilations 1, 2, 4, 8,
     16 channels, ReLU after each, then a 1x1 convolution to one channel; the
